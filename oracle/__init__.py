@@ -1,0 +1,18 @@
+"""CPU FP64 oracle for the block Wilson-Dirac path.
+
+TEST INFRASTRUCTURE ONLY.  Only the tests, the smoke check and the
+CPU-baseline leg of the benchmark may import this package.  It shares no code
+with the HIP library (no kernels, headers, helpers, tables or constant
+generators) and imports nothing from it; both consume the seeded inputs of
+the separate ``synth`` module.
+
+Contents (each module cites the part of the paper it follows):
+  wilson     Wilson-Dirac operator D, box restrictions D_Lambda, block solves (C, FP64)
+  geometry   tilings and the domains of Section 2 (box reading)
+  dense      dense-matrix determinant identities of Section 3 on tiny lattices
+  roots      polynomial P_N, remainder R_{N+1} and roots u_k of Section 4
+  mb         block-local multi-boson action S_MB^a of Section 4
+  precision  FP64 -> FP32 -> BF16 rounding rules
+"""
+from . import dense, geometry, mb, precision, roots, wilson  # noqa: F401
+from ._clib import build  # noqa: F401
