@@ -1,0 +1,235 @@
+/*
+ * dd.h -- C ABI of libdd, the MI355X library for the block-restricted
+ * Wilson-Dirac operator D_Lambda, its batched block solves D_Lambda^{-1} b
+ * and the block-local multi-boson action.
+ *
+ * Paper: M. Saccardi, L. Giusti, "Four-dimensional domain decomposition for
+ * the factorization of the fermion determinant" (Lattice 2022).
+ *   - Section 1: link variables U_mu(x) on the links (x, x+mu), quark fields
+ *     on the sites, local lattice Dirac operator D.
+ *   - Section 2: active blocks Lambda_0^a, internal boundaries dLambda_0^a,
+ *     frames Phi_1^a and framed blocks Omega_0^a.
+ *   - Section 3: restrictions D_X with Dirichlet boundary, the factorisation
+ *     of det D (eq. detD) and the off-diagonal blocks of W_1 (eq. offdiagW1),
+ *     whose active part is P_{dLambda_0^a} D_{Omega_0^a}^{-1} (...).
+ *   - Section 4: the block-local multi-boson action (eq. localMB) and the
+ *     roots u_k.
+ *
+ * Conventions used by every entry point
+ * -------------------------------------
+ * Lattice L = (L0, L1, L2, L3); direction 0 is time.  Canonical site index
+ * n = ((x0*L1 + x1)*L2 + x2)*L3 + x3.  All L_mu must be even.
+ * Operator: D = 1 - kappa H,
+ *   (H psi)(x) = sum_mu [ (1 - gamma_mu) U_mu(x) psi(x+mu) + (1 + gamma_mu) U_mu(x-mu)^+ psi(x-mu) ]
+ * (Wilson-Dirac, hopping normalisation, no clover term), chiral gamma basis
+ * gamma_0 = [[0,-1],[-1,0]], gamma_k = [[0,-i sigma_k],[i sigma_k,0]];
+ * periodic in space; time antiperiodic (time_bc = -1) or periodic (+1).
+ * D_Lambda for a block Lambda drops every hop whose source site lies outside
+ * the block (Dirichlet), i.e. it is the principal sub-matrix of D.
+ *
+ * A block is a box: origin o[4], extent e[4] (even, e_mu <= L_mu); local
+ * coordinate y maps to global x = (o + y) mod L.  A box may wrap around the
+ * lattice; a box with e_mu == L_mu keeps its wrap-around links.
+ * Each block also carries an inner (active) box, given by an offset and an
+ * extent relative to the block; its boundary sites (those with a lattice
+ * neighbour outside the inner box) form dLambda_0^a of the multi-boson action.
+ *
+ * Field layouts at the boundary (caller-owned device memory, complex128 as
+ * interleaved re, im doubles):
+ *   gauge  U[V][4][3][3]                         global canonical order
+ *   spinor psi[n_rhs][total_sites][4][3]          blocks concatenated in block
+ *                                                 order, each block in box-local
+ *                                                 canonical order (local x3 fastest)
+ *   chi    [n_fields][total_bnd_sites][4][3]      dLambda_0^a sites of each block,
+ *                                                 in box-local canonical order
+ *
+ * Errors: every function returns a dd_status and never throws; a message is
+ * kept in the context (dd_last_error).  Calls are ordered on the context's
+ * HIP stream; host outputs are valid on return (the call synchronises).
+ * A context is not thread-safe: use one per host thread.
+ */
+#ifndef DD_H
+#define DD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DD_OK = 0,
+    DD_EINVAL = 1,        /* bad argument or shape mismatch */
+    DD_ENOMEM = 2,        /* device or host allocation failed */
+    DD_EDEVICE = 3,       /* a HIP call failed */
+    DD_ENOCONV = 4,       /* some (block, rhs) pair missed the tolerance; stats are filled */
+    DD_EUNSUPPORTED = 5   /* valid request this build does not implement */
+} dd_status;
+
+typedef enum { DD_F64 = 0, DD_F32 = 1, DD_BF16 = 2 } dd_prec;
+
+typedef struct dd_ctx dd_ctx;
+typedef struct dd_blocks dd_blocks;
+typedef struct dd_gauge dd_gauge;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`, ordering all work on `hip_stream`
+ * (a hipStream_t; NULL = the null stream).  The context owns its workspaces. */
+dd_status dd_create(int device, void *hip_stream, dd_ctx **out);
+dd_status dd_destroy(dd_ctx *ctx);
+/* Last error message of the context (never NULL; "" if none).  With ctx ==
+ * NULL: the message of the calling thread's last call made without a context. */
+const char *dd_last_error(const dd_ctx *ctx);
+/* Library version string. */
+const char *dd_version(void);
+
+/* --------------------------------------------------------------- geometry */
+
+/* Tile mode (Section 2, step 1, with the blocks as tiles): the lattice is
+ * tiled by boxes.  seg holds, direction after direction, the extents of the
+ * consecutive tiles along that direction (nseg[mu] values each, summing to
+ * L[mu]); tiles start at shift[mu] and wrap.  Blocks are listed with the tile
+ * coordinate of direction 3 fastest.  Each block's inner box is the block
+ * shrunk by inner_d sites on both sides in every direction where the block
+ * does not span the lattice (inner_d = 0: the inner box is the block).
+ * Returns DD_EINVAL for odd extents, extents that do not sum to L, or
+ * inner boxes that would be empty. */
+dd_status dd_make_blocks(dd_ctx *ctx, const int32_t L[4], int32_t time_bc, const int32_t *seg,
+                         const int32_t nseg[4], const int32_t shift[4], int32_t inner_d,
+                         dd_blocks **out);
+
+/* Framed blocks of Section 2, step 3 ("box reading"): per direction mu either
+ * bd[2mu] = 0 (direction not decomposed) or active extent b = bd[2mu] and gap
+ * d = bd[2mu+1] >= 1 with (b + d) | L[mu].  Active blocks Lambda_0^a start at
+ * multiples of b + d; the framed block Omega_0^a is the box
+ * [s - d, s + b - 1 + d] and becomes the solve domain; Lambda_0^a is its inner
+ * box.  Omega extents b + 2d must be even. */
+dd_status dd_make_blocks_paper(dd_ctx *ctx, const int32_t L[4], int32_t time_bc,
+                               const int32_t bd[8], dd_blocks **out);
+
+/* Explicit list of n boxes: boxes[n][8] = origin[4], extent[4]; inner[n][8]
+ * = offset[4], extent[4] of the inner box (NULL: inner box = block). */
+dd_status dd_make_blocks_boxes(dd_ctx *ctx, const int32_t L[4], int32_t time_bc, int32_t n,
+                               const int32_t *boxes, const int32_t *inner, dd_blocks **out);
+
+dd_status dd_free_blocks(dd_blocks *blocks);
+
+/* Sizes: number of blocks, total block sites (sum of box volumes), total
+ * dLambda_0 sites, and links inside the blocks (those D_Lambda keeps). */
+dd_status dd_blocks_query(const dd_blocks *blocks, int64_t *n_blocks, int64_t *total_sites,
+                          int64_t *total_bnd_sites, int64_t *inner_links);
+/* Host copies of the index tables (each pointer may be NULL):
+ *   boxes   [n_blocks][16]: origin[4], extent[4], inner offset[4], inner extent[4]
+ *   sites   [total_sites]: global canonical index of each block site
+ *   eo      [total_sites]: even-odd position of each block site inside its
+ *           block (even global parity first, each parity in local canonical order)
+ *   bnd     [total_bnd_sites]: box-local canonical index of each dLambda_0 site */
+dd_status dd_blocks_tables(const dd_blocks *blocks, int32_t *boxes, int64_t *sites, int32_t *eo,
+                           int32_t *bnd);
+
+/* The three constructors above accept ctx == NULL: the blocks then hold host
+ * tables only (for dd_blocks_query / dd_blocks_tables) and every call that
+ * needs the device rejects them with DD_EINVAL. */
+
+/* ------------------------------------------------------------------ gauge */
+
+/* Copy the links inside every block from the canonical FP64 field U_dev into
+ * the library's packed per-block layout: FP64 always, plus a low-precision
+ * copy when low_prec is DD_F32 or DD_BF16 (rounding FP64 -> FP32 to nearest
+ * even, then FP32 -> BF16 to nearest even).  U_dev is only read during the
+ * call. */
+dd_status dd_load_gauge(dd_ctx *ctx, const dd_blocks *blocks, const void *U_dev, dd_prec low_prec,
+                        dd_gauge **out);
+dd_status dd_free_gauge(dd_gauge *gauge);
+/* Export the packed links of precision prec into dst_dev (device memory of
+ * at least total_sites*4*18 elements of the precision: double, float or
+ * uint16 BF16 bits).  Layout: [block][eo site][mu][row][col][re,im] with the
+ * forward link U_mu(x) of each site x; links that leave the block are zero. */
+dd_status dd_gauge_export(dd_ctx *ctx, const dd_gauge *gauge, dd_prec prec, void *dst_dev);
+
+/* ------------------------------------------------------------- operator */
+
+/* y = D_Lambda x for every block and every right-hand side (Section 3, the
+ * restriction D_X).  x_dev, y_dev: [n_rhs][total_sites][4][3] complex128.
+ * prec selects the stencil arithmetic: DD_F64 (FP64 links, spinors and
+ * accumulation), DD_F32 (FP32), DD_BF16 (BF16 links, FP32 spinors and
+ * accumulation; needs a gauge loaded with low_prec = DD_BF16).  Inputs are
+ * rounded to the stencil precision on entry, results widened to FP64. */
+dd_status dd_apply_D_block(dd_ctx *ctx, const dd_blocks *blocks, const dd_gauge *gauge, double kappa,
+                           dd_prec prec, const void *x_dev, void *y_dev, int32_t n_rhs);
+
+/* --------------------------------------------------------------- solves */
+
+enum { DD_BICGSTAB = 0, DD_GMRES = 1 };
+
+typedef struct {
+    double tol;          /* per-pair true relative residual |b - D x| / |b| (FP64), e.g. 1e-10 */
+    int32_t method;      /* DD_BICGSTAB (even-odd BiCGStab) or DD_GMRES (even-odd GMRES(restart)) */
+    int32_t restart;     /* GMRES restart length (<= 32) */
+    dd_prec inner_prec;  /* stencil precision of the inner solve */
+    double inner_tol;    /* relative tolerance of each inner solve (<= 0: library default) */
+    int32_t max_outer;   /* defect-correction cycles (<= 0: default 30) */
+    int32_t max_inner;   /* iterations per inner solve (<= 0: default 2000) */
+    int32_t check_every; /* inner iterations between convergence polls (<= 0: default 8) */
+    int32_t use_graph;   /* replay inner iterations from a captured hipGraph */
+} dd_solve_params;
+
+typedef struct {
+    int32_t *iters;       /* [n_rhs*n_blocks] inner iterations per pair (host, caller-owned, may be NULL) */
+    double *true_relres;  /* [n_rhs*n_blocks] final FP64 true relative residual (may be NULL) */
+    int32_t *flags;       /* [n_rhs*n_blocks] bit 0 converged, bit 1 breakdown seen, bit 2 non-finite (may be NULL) */
+    double seconds;       /* wall time of the call */
+    int32_t outer_cycles; /* defect-correction cycles run */
+    int64_t inner_iterations; /* inner iterations launched (max over pairs per cycle, summed) */
+} dd_solve_stats;
+
+/* Fill p with the defaults (tol 1e-10, BiCGStab, restart 16, FP32 inner). */
+void dd_solve_params_default(dd_solve_params *p);
+
+/* x = D_Lambda^{-1} b for every (block, rhs) pair, all blocks in one batch
+ * (Section 3: the D_{Omega_0^a}^{-1} of eq. offdiagW1 and eq. localMB).
+ * b_dev, x_dev: [n_rhs][total_sites][4][3] complex128; x_dev is output only.
+ * Method: FP64 defect correction on the true residual around an even-odd
+ * Krylov solve of Dhat = 1 - kappa^2 H_eo H_oe in inner_prec.  Pair arrays
+ * are ordered pair = rhs * n_blocks + block.  Returns DD_ENOCONV (stats
+ * filled) if any pair misses tol. */
+dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *blocks, const dd_gauge *gauge, double kappa,
+                         const void *b_dev, void *x_dev, int32_t n_rhs, const dd_solve_params *params,
+                         dd_solve_stats *stats);
+
+/* ------------------------------------------------- multi-boson action */
+
+/* Block-local multi-boson action of eq. (localMB), Section 4, for
+ * field k taken at z = u_k:
+ *   S^a = sum_k sum_{x in dLambda_0^a} | u_k chi_k(x) + (D_{Omega_0^a}^{-1} xi_k^a)(x) |^2
+ * where xi_k^a (on the whole block Omega_0^a) collects the hop-in sources of
+ * eq. (localMB).  u_host: [n_fields][2] (re, im).  chi_dev:
+ * [n_fields][total_bnd_sites][4][3] complex128; xi_dev:
+ * [n_fields][total_sites][4][3] complex128.  S_block_dev (may be NULL):
+ * [n_blocks] FP64 device output; S_total_host (may be NULL): sum over blocks.
+ * The solves use params (NULL: defaults); stats may be NULL. */
+dd_status dd_multiboson_action(dd_ctx *ctx, const dd_blocks *blocks, const dd_gauge *gauge,
+                               double kappa, int32_t n_fields, const double *u_host,
+                               const void *chi_dev, const void *xi_dev,
+                               const dd_solve_params *params, double *S_block_dev,
+                               double *S_total_host, dd_solve_stats *stats);
+
+/* ------------------------------------------------------------ timing */
+
+/* Kernel timing for roofline reports: when enabled, every launch of the
+ * kernel class is bracketed by HIP events on the context's stream, and its
+ * algorithmic bytes (the bytes the method must move, counted per block) are
+ * accumulated.  Graph replay is disabled while timing is on. */
+enum { DD_KCLASS_HOP = 0, DD_KCLASS_BLAS = 1, DD_KCLASS_COUNT = 2 };
+dd_status dd_timer_enable(dd_ctx *ctx, int32_t on);
+dd_status dd_timer_reset(dd_ctx *ctx);
+/* total_ms: summed event time; launches: count; alg_bytes: summed bytes. */
+dd_status dd_timer_read(dd_ctx *ctx, int32_t kclass, double *total_ms, int64_t *launches,
+                        double *alg_bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DD_H */

@@ -1,0 +1,540 @@
+// C ABI of libdd: contexts, geometry, gauge packing, D_Lambda application,
+// batched block solves and the block-local multi-boson action.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "dd_geometry.h"
+#include "dd_host.h"
+#include "dd_internal.h"
+
+using namespace dd;
+
+namespace {
+const char *kVersion = "libdd 0.1 (gfx950)";
+thread_local std::string g_err;  // message of calls made without a context
+}  // namespace
+
+namespace dd {
+
+dd_status fail(dd_ctx *ctx, dd_status st, const std::string &msg)
+{
+    if (ctx) ctx->err = msg;
+    else g_err = msg;
+    return st;
+}
+
+// Grow-only named workspace.  Contents are not preserved on growth.
+void *workspace(dd_ctx *ctx, const std::string &name, size_t bytes, hipError_t *err)
+{
+    DevBuf &b = ctx->ws[name];
+    if (b.bytes >= bytes && b.p) return b.p;
+    if (b.p) {
+        hipStreamSynchronize(ctx->stream);
+        hipFree(b.p);
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    void *p = nullptr;
+    *err = hipMalloc(&p, std::max<size_t>(bytes, 256));
+    if (*err != hipSuccess) return nullptr;
+    b.p = p;
+    b.bytes = std::max<size_t>(bytes, 256);
+    return p;
+}
+
+size_t prec_bytes(dd_prec p) { return p == DD_F64 ? 8 : (p == DD_F32 ? 4 : 2); }
+
+// Timing of one kernel launch of a class (events only while timing is on).
+struct TimedLaunch {
+    dd_ctx *ctx;
+    int kclass;
+    hipEvent_t stop = nullptr;
+    TimedLaunch(dd_ctx *c, int k, double bytes) : ctx(c), kclass(k)
+    {
+        if (!ctx->timing) return;
+        Timer &t = ctx->timers[kclass];
+        if (t.used == t.ev.size()) {
+            hipEvent_t a, b;
+            hipEventCreate(&a);
+            hipEventCreate(&b);
+            t.ev.push_back({a, b});
+        }
+        hipEventRecord(t.ev[t.used].first, ctx->stream);
+        stop = t.ev[t.used].second;
+        t.used++;
+        t.bytes += bytes;
+    }
+    ~TimedLaunch()
+    {
+        if (stop) hipEventRecord(stop, ctx->stream);
+    }
+};
+
+const TileTable *tiles_for(dd_ctx *ctx, dd_blocks *B, int nr, hipError_t *err)
+{
+    *err = hipSuccess;
+    auto it = B->tiles.find(nr);
+    if (it != B->tiles.end()) return &it->second;
+    TileTable tt;
+    tt.blk_tile0.assign(B->nb + 1, 0);
+    std::vector<int32_t> tb;
+    for (int b = 0; b < B->nb; b++) {
+        const int64_t items = (int64_t)B->shapes[B->shape_of[b]].h * nr;
+        const int nt = (int)((items + kTile - 1) / kTile);
+        tt.blk_tile0[b + 1] = tt.blk_tile0[b] + nt;
+        for (int t = 0; t < nt; t++) tb.push_back(b);
+    }
+    tt.ntiles = tt.blk_tile0[B->nb];
+    if ((*err = upload(&tt.d_tile_block, tb)) != hipSuccess) return nullptr;
+    if ((*err = upload(&tt.d_blk_tile0, tt.blk_tile0)) != hipSuccess) return nullptr;
+    (void)ctx;
+    return &(B->tiles[nr] = tt);
+}
+
+BlkArgs blk_args(const dd_blocks *B, const TileTable *tt, int nr)
+{
+    BlkArgs a;
+    a.tile_block = tt->d_tile_block;
+    a.blk_tile0 = tt->d_blk_tile0;
+    a.h = B->d_h;
+    a.soff = B->d_soff;
+    a.nbr_off = B->d_nbr_off;
+    a.nbr = B->d_nbr;
+    a.ntiles = tt->ntiles;
+    a.n_rhs = nr;
+    a.nb = B->nb;
+    return a;
+}
+
+const void *links_for(const dd_gauge *G, dd_prec prec)
+{
+    if (prec == DD_F64) return G->d_u64;
+    if (prec == DD_F32) return G->low == DD_F32 ? (const void *)G->d_u32 : nullptr;
+    if (prec == DD_BF16) return G->low == DD_BF16 ? (const void *)G->d_ubf : nullptr;
+    return nullptr;
+}
+
+// Algorithmic bytes of one hop launch: the half field it reads and the one it
+// writes (24 reals per site and rhs each), each extra half-field operand, and
+// every link inside the blocks once (18 reals).
+double hop_bytes(const dd_blocks *B, int nr, dd_prec prec, int extra_vectors)
+{
+    const double sf = prec == DD_F64 ? 8.0 : 4.0;
+    const double sl = (double)prec_bytes(prec);
+    const double half_sites = (double)B->soff[B->nb] / 2.0;
+    return nr * half_sites * 24.0 * sf * (2 + extra_vectors) + (double)B->inner_links * 18.0 * sl;
+}
+
+hipError_t run_hop(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const HopArgs &ha, dd_prec prec)
+{
+    const int extra = (ha.self != nullptr) + (ha.add != nullptr) + (ha.aux != nullptr);
+    TimedLaunch tl(ctx, DD_KCLASS_HOP, hop_bytes(B, ba.n_rhs, prec, extra));
+    return launch_hop(ba, ha, prec, ctx->stream);
+}
+
+HopArgs hop_args(void *out, const void *in, const void *links, int parity, double c_hop)
+{
+    HopArgs h;
+    std::memset(&h, 0, sizeof(h));
+    h.out = out;
+    h.in = in;
+    h.links = links;
+    h.parity = parity;
+    h.c_hop = c_hop;
+    h.dot_mode = kDotNone;
+    return h;
+}
+
+}  // namespace dd
+
+// ======================================================================== ABI
+
+extern "C" {
+
+const char *dd_version(void) { return kVersion; }
+
+dd_status dd_create(int device, void *hip_stream, dd_ctx **out)
+{
+    if (!out) return DD_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) return DD_EDEVICE;
+    if (hipSetDevice(device) != hipSuccess) return DD_EDEVICE;
+    dd_ctx *ctx = new (std::nothrow) dd_ctx();
+    if (!ctx) return DD_ENOMEM;
+    ctx->device = device;
+    // All library work runs on a stream of its own (capturable into graphs);
+    // each call first waits for the caller's stream and synchronises before it returns.
+    if (hipStreamCreateWithFlags(&ctx->stream, hipStreamNonBlocking) != hipSuccess) {
+        delete ctx;
+        return DD_EDEVICE;
+    }
+    ctx->user_stream = (hipStream_t)hip_stream;
+    *out = ctx;
+    return DD_OK;
+}
+
+dd_status dd_destroy(dd_ctx *ctx)
+{
+    if (!ctx) return DD_EINVAL;
+    hipSetDevice(ctx->device);
+    hipStreamSynchronize(ctx->stream);
+    for (auto &kv : ctx->ws)
+        if (kv.second.p) hipFree(kv.second.p);
+    for (auto &t : ctx->timers)
+        for (auto &e : t.ev) {
+            hipEventDestroy(e.first);
+            hipEventDestroy(e.second);
+        }
+    hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return DD_OK;
+}
+
+const char *dd_last_error(const dd_ctx *ctx) { return ctx ? ctx->err.c_str() : g_err.c_str(); }
+
+}  // extern "C"
+
+namespace dd {
+
+// make the library stream wait for work the caller queued on its own stream
+hipError_t enter(dd_ctx *ctx)
+{
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return e;
+    hipEvent_t ev;
+    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventRecord(ev, ctx->user_stream)) == hipSuccess) e = hipStreamWaitEvent(ctx->stream, ev, 0);
+    hipEventDestroy(ev);
+    return e;
+}
+
+dd_status finish_blocks(dd_ctx *ctx, dd_blocks *B, dd_blocks **out)
+{
+    hipError_t e = hipSuccess;
+    std::vector<int32_t> h(B->nb), org((size_t)B->nb * 4), ext((size_t)B->nb * 4);
+    std::vector<int64_t> nbo(B->nb), pmo(B->nb);
+    for (int b = 0; b < B->nb; b++) {
+        const Shape &sh = B->shapes[B->shape_of[b]];
+        h[b] = sh.h;
+        nbo[b] = sh.nbr_off;
+        pmo[b] = sh.perm_off;
+        for (int m = 0; m < 4; m++) {
+            org[4 * b + m] = B->box[16 * b + m];
+            ext[4 * b + m] = B->box[16 * b + 4 + m];
+        }
+    }
+    if ((e = upload(&B->d_nbr, B->nbr)) != hipSuccess || (e = upload(&B->d_perm, B->perm)) != hipSuccess ||
+        (e = upload(&B->d_soff, B->soff)) != hipSuccess || (e = upload(&B->d_h, h)) != hipSuccess ||
+        (e = upload(&B->d_nbr_off, nbo)) != hipSuccess || (e = upload(&B->d_perm_off, pmo)) != hipSuccess ||
+        (e = upload(&B->d_origin, org)) != hipSuccess || (e = upload(&B->d_ext, ext)) != hipSuccess ||
+        (e = upload(&B->d_bnd, B->bnd)) != hipSuccess || (e = upload(&B->d_boff, B->boff)) != hipSuccess) {
+        dd_free_blocks(B);
+        return fail(ctx, DD_EDEVICE, std::string("geometry upload: ") + hipGetErrorString(e));
+    }
+    *out = B;
+    return DD_OK;
+}
+
+dd_status make_from_boxes(dd_ctx *ctx, const int32_t L[4], int32_t time_bc, int n, const int32_t *boxes,
+                          const int32_t *inner, dd_blocks **out)
+{
+    if (!L || !out || (n > 0 && !boxes)) return fail(ctx, DD_EINVAL, "null argument");
+    *out = nullptr;
+    if (ctx && hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DD_EDEVICE, "hipSetDevice failed");
+    dd_blocks *B = new (std::nothrow) dd_blocks();
+    if (!B) return fail(ctx, DD_ENOMEM, "out of host memory");
+    B->ctx = ctx;
+    int Li[4] = {L[0], L[1], L[2], L[3]};
+    const std::string msg = build_geometry(B, Li, time_bc, n, boxes, inner);
+    if (!msg.empty()) {
+        delete B;
+        return fail(ctx, DD_EINVAL, msg);
+    }
+    if (!ctx) {  // host tables only: usable for queries, not for device work
+        *out = B;
+        return DD_OK;
+    }
+    return finish_blocks(ctx, B, out);
+}
+
+}  // namespace dd
+
+extern "C" {
+
+dd_status dd_make_blocks(dd_ctx *ctx, const int32_t L[4], int32_t time_bc, const int32_t *seg, const int32_t nseg[4],
+                         const int32_t shift[4], int32_t inner_d, dd_blocks **out)
+{
+    if (!L || !seg || !nseg || !out) return fail(ctx, DD_EINVAL, "null argument");
+    std::vector<std::vector<int32_t>> starts(4), exts(4);
+    size_t pos = 0;
+    for (int m = 0; m < 4; m++) {
+        if (nseg[m] < 1) return fail(ctx, DD_EINVAL, "each direction needs at least one tile");
+        int64_t sum = 0;
+        for (int k = 0; k < nseg[m]; k++) {
+            const int32_t v = seg[pos++];
+            if (v < 1) return fail(ctx, DD_EINVAL, "tile extents must be positive");
+            const int32_t sh = shift ? shift[m] : 0;
+            starts[m].push_back((int32_t)((((sum + sh) % L[m]) + L[m]) % L[m]));
+            exts[m].push_back(v);
+            sum += v;
+        }
+        if (sum != L[m]) return fail(ctx, DD_EINVAL, "tile extents must sum to the lattice extent");
+    }
+    if (inner_d < 0) return fail(ctx, DD_EINVAL, "inner_d must be >= 0");
+    std::vector<int32_t> boxes, inner;
+    for (int a = 0; a < nseg[0]; a++)
+        for (int b = 0; b < nseg[1]; b++)
+            for (int c = 0; c < nseg[2]; c++)
+                for (int d = 0; d < nseg[3]; d++) {
+                    const int t[4] = {a, b, c, d};
+                    for (int m = 0; m < 4; m++) boxes.push_back(starts[m][t[m]]);
+                    for (int m = 0; m < 4; m++) boxes.push_back(exts[m][t[m]]);
+                    for (int m = 0; m < 4; m++) inner.push_back(exts[m][t[m]] == L[m] ? 0 : inner_d);
+                    for (int m = 0; m < 4; m++) {
+                        const int e = exts[m][t[m]];
+                        inner.push_back(e == L[m] ? e : e - 2 * inner_d);
+                    }
+                }
+    const int n = (int)(boxes.size() / 8);
+    return make_from_boxes(ctx, L, time_bc, n, boxes.data(), inner.data(), out);
+}
+
+dd_status dd_make_blocks_paper(dd_ctx *ctx, const int32_t L[4], int32_t time_bc, const int32_t bd[8],
+                               dd_blocks **out)
+{
+    if (!L || !bd || !out) return fail(ctx, DD_EINVAL, "null argument");
+    std::vector<std::vector<int32_t>> st(4);
+    for (int m = 0; m < 4; m++) {
+        const int b = bd[2 * m], d = bd[2 * m + 1];
+        if (b == 0) {
+            st[m].push_back(0);
+            continue;
+        }
+        if (b < 1 || d < 1 || L[m] % (b + d) != 0) return fail(ctx, DD_EINVAL, "need b >= 1, d >= 1, (b+d) | L");
+        for (int s = 0; s < L[m]; s += b + d) st[m].push_back(s);
+    }
+    std::vector<int32_t> boxes, inner;
+    for (int32_t s0 : st[0])
+        for (int32_t s1 : st[1])
+            for (int32_t s2 : st[2])
+                for (int32_t s3 : st[3]) {
+                    const int32_t s[4] = {s0, s1, s2, s3};
+                    int32_t o[4], e[4], io[4], ie[4];
+                    for (int m = 0; m < 4; m++) {
+                        const int b = bd[2 * m], d = bd[2 * m + 1];
+                        if (b == 0) {
+                            o[m] = 0; e[m] = L[m]; io[m] = 0; ie[m] = L[m];
+                        } else {
+                            o[m] = ((s[m] - d) % L[m] + L[m]) % L[m];
+                            e[m] = b + 2 * d;
+                            io[m] = d;
+                            ie[m] = b;
+                        }
+                    }
+                    boxes.insert(boxes.end(), o, o + 4);
+                    boxes.insert(boxes.end(), e, e + 4);
+                    inner.insert(inner.end(), io, io + 4);
+                    inner.insert(inner.end(), ie, ie + 4);
+                }
+    return make_from_boxes(ctx, L, time_bc, (int)(boxes.size() / 8), boxes.data(), inner.data(), out);
+}
+
+dd_status dd_make_blocks_boxes(dd_ctx *ctx, const int32_t L[4], int32_t time_bc, int32_t n, const int32_t *boxes,
+                               const int32_t *inner, dd_blocks **out)
+{
+    return make_from_boxes(ctx, L, time_bc, n, boxes, inner, out);
+}
+
+dd_status dd_free_blocks(dd_blocks *B)
+{
+    if (!B) return DD_EINVAL;
+    if (B->ctx) hipSetDevice(B->ctx->device);
+    void *ptrs[] = {B->d_nbr, B->d_perm, B->d_soff, B->d_h, B->d_nbr_off, B->d_perm_off,
+                    B->d_origin, B->d_ext, B->d_bnd, B->d_boff};
+    for (void *p : ptrs)
+        if (p) hipFree(p);
+    for (auto &kv : B->tiles) {
+        if (kv.second.d_tile_block) hipFree(kv.second.d_tile_block);
+        if (kv.second.d_blk_tile0) hipFree(kv.second.d_blk_tile0);
+    }
+    delete B;
+    return DD_OK;
+}
+
+dd_status dd_blocks_query(const dd_blocks *B, int64_t *n_blocks, int64_t *total_sites, int64_t *total_bnd_sites,
+                          int64_t *inner_links)
+{
+    if (!B) return DD_EINVAL;
+    if (n_blocks) *n_blocks = B->nb;
+    if (total_sites) *total_sites = B->soff[B->nb];
+    if (total_bnd_sites) *total_bnd_sites = B->boff[B->nb];
+    if (inner_links) *inner_links = B->inner_links;
+    return DD_OK;
+}
+
+dd_status dd_blocks_tables(const dd_blocks *B, int32_t *boxes, int64_t *sites, int32_t *eo, int32_t *bnd)
+{
+    if (!B) return DD_EINVAL;
+    if (boxes) std::memcpy(boxes, B->box.data(), B->box.size() * sizeof(int32_t));
+    for (int b = 0; b < B->nb; b++) {
+        const Shape &sh = B->shapes[B->shape_of[b]];
+        const int32_t *bx = &B->box[16 * b];
+        const int64_t s0 = B->soff[b];
+        if (sites) {
+            for (int s = 0; s < sh.S; s++) {
+                int y[4], r = s;
+                y[3] = r % sh.e[3]; r /= sh.e[3];
+                y[2] = r % sh.e[2]; r /= sh.e[2];
+                y[1] = r % sh.e[1]; r /= sh.e[1];
+                y[0] = r;
+                int64_t n = 0;
+                for (int m = 0; m < 4; m++) n = n * B->L[m] + (bx[m] + y[m]) % B->L[m];
+                sites[s0 + s] = n;
+            }
+        }
+        if (eo)
+            for (int k = 0; k < sh.S; k++) eo[s0 + B->perm[sh.perm_off + k]] = k;
+    }
+    if (bnd) std::memcpy(bnd, B->bnd.data(), B->bnd.size() * sizeof(int32_t));
+    return DD_OK;
+}
+
+// ------------------------------------------------------------------ gauge
+
+dd_status dd_load_gauge(dd_ctx *ctx, const dd_blocks *B, const void *U_dev, dd_prec low_prec, dd_gauge **out)
+{
+    if (!ctx || !B || !U_dev || !out) return fail(ctx, DD_EINVAL, "null argument");
+    if (B->ctx != ctx) return fail(ctx, DD_EINVAL, "blocks belong to another context (or have no device tables)");
+    if (low_prec != DD_F64 && low_prec != DD_F32 && low_prec != DD_BF16) return fail(ctx, DD_EINVAL, "bad precision");
+    *out = nullptr;
+    HIPCHECK(ctx, enter(ctx));
+    dd_gauge *G = new (std::nothrow) dd_gauge();
+    if (!G) return fail(ctx, DD_ENOMEM, "out of host memory");
+    G->ctx = ctx;
+    G->blocks = B;
+    G->low = low_prec;
+    const size_t nl = (size_t)B->soff[B->nb] * 72;
+    hipError_t e = hipMalloc((void **)&G->d_u64, std::max<size_t>(nl * 8, 8));
+    if (e == hipSuccess) e = launch_pack_gauge(B, (const double *)U_dev, DD_F64, G->d_u64, ctx->stream);
+    if (e == hipSuccess && low_prec == DD_F32) {
+        e = hipMalloc((void **)&G->d_u32, std::max<size_t>(nl * 4, 4));
+        if (e == hipSuccess) e = launch_pack_gauge(B, (const double *)U_dev, DD_F32, G->d_u32, ctx->stream);
+    }
+    if (e == hipSuccess && low_prec == DD_BF16) {
+        e = hipMalloc((void **)&G->d_ubf, std::max<size_t>(nl * 2, 2));
+        if (e == hipSuccess) e = launch_pack_gauge(B, (const double *)U_dev, DD_BF16, G->d_ubf, ctx->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        dd_free_gauge(G);
+        return fail(ctx, e == hipErrorOutOfMemory ? DD_ENOMEM : DD_EDEVICE,
+                    std::string("gauge packing: ") + hipGetErrorString(e));
+    }
+    *out = G;
+    return DD_OK;
+}
+
+dd_status dd_free_gauge(dd_gauge *G)
+{
+    if (!G) return DD_EINVAL;
+    if (G->ctx) hipSetDevice(G->ctx->device);
+    if (G->d_u64) hipFree(G->d_u64);
+    if (G->d_u32) hipFree(G->d_u32);
+    if (G->d_ubf) hipFree(G->d_ubf);
+    delete G;
+    return DD_OK;
+}
+
+dd_status dd_gauge_export(dd_ctx *ctx, const dd_gauge *G, dd_prec prec, void *dst_dev)
+{
+    if (!ctx || !G || !dst_dev) return fail(ctx, DD_EINVAL, "null argument");
+    const void *src = links_for(G, prec);
+    if (!src) return fail(ctx, DD_EINVAL, "gauge holds no links of that precision");
+    HIPCHECK(ctx, enter(ctx));
+    const size_t bytes = (size_t)G->blocks->soff[G->blocks->nb] * 72 * prec_bytes(prec);
+    HIPCHECK(ctx, hipMemcpyAsync(dst_dev, src, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+    HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+    return DD_OK;
+}
+
+// --------------------------------------------------------------- operator
+
+dd_status dd_apply_D_block(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, double kappa, dd_prec prec,
+                           const void *x_dev, void *y_dev, int32_t n_rhs)
+{
+    if (!ctx || !Bc || !G || !x_dev || !y_dev) return fail(ctx, DD_EINVAL, "null argument");
+    if (n_rhs < 1 || n_rhs > kMaxRhs) return fail(ctx, DD_EINVAL, "n_rhs must be in 1..64");
+    if (G->blocks != Bc) return fail(ctx, DD_EINVAL, "gauge was loaded for other blocks");
+    const void *links = links_for(G, prec);
+    if (!links) return fail(ctx, DD_EINVAL, "gauge holds no links of the requested precision");
+    dd_blocks *B = const_cast<dd_blocks *>(Bc);
+    HIPCHECK(ctx, enter(ctx));
+    hipError_t e;
+    const TileTable *tt = tiles_for(ctx, B, n_rhs, &e);
+    if (!tt) return fail(ctx, DD_EDEVICE, std::string("tile tables: ") + hipGetErrorString(e));
+    const BlkArgs ba = blk_args(B, tt, n_rhs);
+    const dd_prec sp = prec == DD_F64 ? DD_F64 : DD_F32;
+    const size_t half = (size_t)(B->soff[B->nb] / 2) * 24 * n_rhs * prec_bytes(sp);
+    void *xe = workspace(ctx, "ap_xe", half, &e);
+    void *xo = xe ? workspace(ctx, "ap_xo", half, &e) : nullptr;
+    void *ye = xo ? workspace(ctx, "ap_ye", half, &e) : nullptr;
+    void *yo = ye ? workspace(ctx, "ap_yo", half, &e) : nullptr;
+    if (!yo) return fail(ctx, DD_ENOMEM, std::string("workspace: ") + hipGetErrorString(e));
+    HIPCHECK(ctx, launch_pack_spinor(B, (const double *)x_dev, xe, xo, sp, n_rhs, ctx->stream));
+    for (int p = 0; p < 2; p++) {
+        HopArgs ha = hop_args(p ? yo : ye, p ? xe : xo, links, p, -kappa);
+        ha.self = p ? xo : xe;
+        ha.c_self = 1.0;
+        HIPCHECK(ctx, run_hop(ctx, B, ba, ha, prec));
+    }
+    HIPCHECK(ctx, launch_unpack_spinor(B, ye, yo, (double *)y_dev, sp, n_rhs, ctx->stream));
+    HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+    return DD_OK;
+}
+
+// ------------------------------------------------------------------ timing
+
+dd_status dd_timer_enable(dd_ctx *ctx, int32_t on)
+{
+    if (!ctx) return DD_EINVAL;
+    ctx->timing = on != 0;
+    return DD_OK;
+}
+
+dd_status dd_timer_reset(dd_ctx *ctx)
+{
+    if (!ctx) return DD_EINVAL;
+    hipStreamSynchronize(ctx->stream);
+    for (auto &t : ctx->timers) {
+        t.used = 0;
+        t.bytes = 0;
+    }
+    return DD_OK;
+}
+
+dd_status dd_timer_read(dd_ctx *ctx, int32_t kclass, double *total_ms, int64_t *launches, double *alg_bytes)
+{
+    if (!ctx || kclass < 0 || kclass >= DD_KCLASS_COUNT) return fail(ctx, DD_EINVAL, "bad timer class");
+    HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+    Timer &t = ctx->timers[kclass];
+    double tot = 0;
+    for (size_t i = 0; i < t.used; i++) {
+        float ms = 0;
+        HIPCHECK(ctx, hipEventElapsedTime(&ms, t.ev[i].first, t.ev[i].second));
+        tot += ms;
+    }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = (int64_t)t.used;
+    if (alg_bytes) *alg_bytes = t.bytes;
+    return DD_OK;
+}
+
+}  // extern "C"

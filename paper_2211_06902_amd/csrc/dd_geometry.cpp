@@ -1,0 +1,188 @@
+// Block geometry of libdd (host): boxes, shapes, even-odd permutations,
+// neighbour tables and dLambda_0 lists.
+//
+// Paper Section 2: blocks Lambda_0^a are hyperrectangles; the solve domains
+// are boxes (tiles, or the framed blocks Omega_0^a = Lambda_0^a u Phi_1^a);
+// dLambda_0^a holds the sites of the active box with a neighbour outside it.
+// Section 3: D_X drops the hops from outside X (Dirichlet restriction), which
+// the neighbour tables encode as -1 entries.
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <tuple>
+
+#include "dd_geometry.h"
+
+namespace dd {
+
+namespace {
+
+struct ShapeKey {
+    int e[4], full[4], opar, tw;
+    bool operator<(const ShapeKey &o) const
+    {
+        return std::tie(e[0], e[1], e[2], e[3], full[0], full[1], full[2], full[3], opar, tw) <
+               std::tie(o.e[0], o.e[1], o.e[2], o.e[3], o.full[0], o.full[1], o.full[2], o.full[3], o.opar,
+                        o.tw);
+    }
+};
+
+inline int lidx(const int e[4], const int y[4]) { return ((y[0] * e[1] + y[1]) * e[2] + y[2]) * e[3] + y[3]; }
+
+inline void lcoords(const int e[4], int s, int y[4])
+{
+    y[3] = s % e[3];
+    s /= e[3];
+    y[2] = s % e[2];
+    s /= e[2];
+    y[1] = s % e[1];
+    s /= e[1];
+    y[0] = s;
+}
+
+// Build the permutation and neighbour table of one shape; returns links kept.
+int64_t build_shape(Shape &sh, int tbc, std::vector<int32_t> &perm, std::vector<int32_t> &nbr)
+{
+    const int *e = sh.e;
+    sh.S = e[0] * e[1] * e[2] * e[3];
+    sh.h = sh.S / 2;
+    sh.perm_off = (int64_t)perm.size();
+    sh.nbr_off = (int64_t)nbr.size();
+    std::vector<int32_t> pos(sh.S);
+    int ne = 0, no = 0;
+    for (int p = 0; p < 2; p++)
+        for (int s = 0; s < sh.S; s++) {
+            int y[4];
+            lcoords(e, s, y);
+            const int par = (sh.opar + y[0] + y[1] + y[2] + y[3]) & 1;
+            if (par != p) continue;
+            pos[s] = p == 0 ? ne : sh.h + no;
+            (p == 0 ? ne : no)++;
+            perm.push_back(s);
+        }
+    nbr.resize(nbr.size() + (size_t)sh.S * 8);
+    int32_t *tab = nbr.data() + sh.nbr_off;
+    int64_t links = 0;
+    for (int slot = 0; slot < sh.S; slot++) {
+        const int p = slot >= sh.h;
+        int y[4];
+        lcoords(e, perm[sh.perm_off + slot], y);
+        for (int mu = 0; mu < 4; mu++) {
+            for (int f = 0; f < 2; f++) {
+                int yy[4] = {y[0], y[1], y[2], y[3]};
+                bool in = true;
+                int link_origin;  // local mu-coordinate of the link's lower end
+                if (f == 0) {
+                    link_origin = y[mu];
+                    yy[mu] = y[mu] + 1;
+                    if (yy[mu] == e[mu]) {
+                        if (sh.full[mu]) yy[mu] = 0;
+                        else in = false;
+                    }
+                } else {
+                    yy[mu] = y[mu] - 1;
+                    if (yy[mu] < 0) {
+                        if (sh.full[mu]) yy[mu] = e[mu] - 1;
+                        else in = false;
+                    }
+                    link_origin = yy[mu];
+                }
+                int32_t entry = -1;
+                if (in) {
+                    entry = pos[lidx(e, yy)] - (1 - p) * sh.h;
+                    if (tbc < 0 && mu == 0 && link_origin == sh.tw) entry |= kNbrSign;
+                    if (f == 0) links++;
+                }
+                tab[(size_t)slot * 8 + 2 * mu + f] = entry;
+            }
+        }
+    }
+    return links;
+}
+
+}  // namespace
+
+std::string build_geometry(dd_blocks *B, const int L[4], int tbc, int n, const int32_t *boxes,
+                           const int32_t *inner)
+{
+    for (int m = 0; m < 4; m++)
+        if (L[m] < 2 || (L[m] & 1)) return "lattice extents must be even and >= 2";
+    if (tbc != 1 && tbc != -1) return "time_bc must be +1 (periodic) or -1 (antiperiodic)";
+    if (n < 0) return "negative block count";
+    for (int m = 0; m < 4; m++) B->L[m] = L[m];
+    B->tbc = tbc;
+    B->nb = n;
+    B->box.assign((size_t)n * 16, 0);
+    B->soff.assign(n + 1, 0);
+    B->boff.assign(n + 1, 0);
+    B->shape_of.assign(n, 0);
+    std::map<ShapeKey, int> shape_ids;
+    std::vector<int64_t> shape_links;
+    for (int k = 0; k < n; k++) {
+        const int32_t *bx = boxes + 8 * k;
+        int o[4], e[4], io[4], ie[4];
+        for (int m = 0; m < 4; m++) {
+            o[m] = ((bx[m] % L[m]) + L[m]) % L[m];
+            e[m] = bx[4 + m];
+            if (e[m] < 2 || (e[m] & 1) || e[m] > L[m]) return "block extents must be even, >= 2 and <= L";
+            io[m] = inner ? inner[8 * k + m] : 0;
+            ie[m] = inner ? inner[8 * k + 4 + m] : e[m];
+            if (io[m] < 0 || ie[m] < 1 || io[m] + ie[m] > e[m]) return "inner box must lie inside its block";
+        }
+        ShapeKey key;
+        for (int m = 0; m < 4; m++) {
+            key.e[m] = e[m];
+            key.full[m] = e[m] == L[m];
+        }
+        key.opar = (o[0] + o[1] + o[2] + o[3]) & 1;
+        key.tw = -1;
+        if (tbc < 0) {
+            const int tw = ((L[0] - 1 - o[0]) % L[0] + L[0]) % L[0];
+            if (key.full[0] || tw <= e[0] - 2) key.tw = tw;
+        }
+        auto it = shape_ids.find(key);
+        int sid;
+        if (it == shape_ids.end()) {
+            Shape sh;
+            std::memcpy(sh.e, key.e, sizeof(sh.e));
+            std::memcpy(sh.full, key.full, sizeof(sh.full));
+            sh.opar = key.opar;
+            sh.tw = key.tw;
+            const int64_t links = build_shape(sh, tbc, B->perm, B->nbr);
+            sid = (int)B->shapes.size();
+            B->shapes.push_back(sh);
+            shape_links.push_back(links);
+            shape_ids[key] = sid;
+        } else {
+            sid = it->second;
+        }
+        B->shape_of[k] = sid;
+        const Shape &sh = B->shapes[sid];
+        B->soff[k + 1] = B->soff[k] + sh.S;
+        B->inner_links += shape_links[sid];
+        B->max_h = std::max(B->max_h, sh.h);
+        int32_t *rec = &B->box[(size_t)16 * k];
+        for (int m = 0; m < 4; m++) {
+            rec[m] = o[m];
+            rec[4 + m] = e[m];
+            rec[8 + m] = io[m];
+            rec[12 + m] = ie[m];
+        }
+        // dLambda_0: inner-box sites with a lattice neighbour outside the inner box.
+        // Along a direction where the inner box spans the lattice the neighbours wrap inside.
+        for (int s = 0; s < sh.S; s++) {
+            int y[4];
+            lcoords(e, s, y);
+            bool inside = true, bnd = false;
+            for (int m = 0; m < 4; m++) {
+                if (y[m] < io[m] || y[m] >= io[m] + ie[m]) inside = false;
+                if (ie[m] < L[m] && (y[m] == io[m] || y[m] == io[m] + ie[m] - 1)) bnd = true;
+            }
+            if (inside && bnd) B->bnd.push_back(s);
+        }
+        B->boff[k + 1] = (int64_t)B->bnd.size();
+    }
+    return "";
+}
+
+}  // namespace dd

@@ -1,0 +1,15 @@
+// Host geometry builder of libdd.
+#pragma once
+
+#include <string>
+
+#include "dd_internal.h"
+
+namespace dd {
+
+// Fill the host tables of B from n boxes [n][8] (origin, extent) and optional
+// inner boxes [n][8] (offset, extent).  Returns "" or an error message.
+std::string build_geometry(dd_blocks *B, const int L[4], int tbc, int n, const int32_t *boxes,
+                           const int32_t *inner);
+
+}  // namespace dd

@@ -1,0 +1,43 @@
+// Host-side helpers shared by the C ABI translation units of libdd.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "dd_internal.h"
+
+namespace dd {
+
+dd_status fail(dd_ctx *ctx, dd_status st, const std::string &msg);
+void *workspace(dd_ctx *ctx, const std::string &name, size_t bytes, hipError_t *err);
+size_t prec_bytes(dd_prec p);
+hipError_t enter(dd_ctx *ctx);
+const TileTable *tiles_for(dd_ctx *ctx, dd_blocks *B, int nr, hipError_t *err);
+BlkArgs blk_args(const dd_blocks *B, const TileTable *tt, int nr);
+const void *links_for(const dd_gauge *G, dd_prec prec);
+double hop_bytes(const dd_blocks *B, int nr, dd_prec prec, int extra_vectors);
+hipError_t run_hop(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const HopArgs &ha, dd_prec prec);
+HopArgs hop_args(void *out, const void *in, const void *links, int parity, double c_hop);
+
+template <typename T>
+hipError_t upload(T **dst, const std::vector<T> &src)
+{
+    const size_t bytes = std::max<size_t>(src.size() * sizeof(T), sizeof(T));
+    hipError_t e = hipMalloc((void **)dst, bytes);
+    if (e != hipSuccess) return e;
+    if (!src.empty()) e = hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+    return e;
+}
+
+}  // namespace dd
+
+#define HIPCHECK(ctx, expr)                                                                      \
+    do {                                                                                         \
+        hipError_t e_ = (expr);                                                                  \
+        if (e_ != hipSuccess)                                                                    \
+            return ::dd::fail((ctx), e_ == hipErrorOutOfMemory ? DD_ENOMEM : DD_EDEVICE,          \
+                              std::string(#expr) + ": " + hipGetErrorString(e_));                \
+    } while (0)

@@ -1,0 +1,200 @@
+// Internal declarations of libdd (host side and kernel argument blocks).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "dd.h"
+
+namespace dd {
+
+// Work items (site, rhs) handled by one workgroup of the site kernels.
+constexpr int kTile = 256;
+// Largest number of right-hand sides per call (a tile must hold every rhs).
+constexpr int kMaxRhs = 64;
+// Reals reduced per (tile, rhs) by the fused dot products.
+constexpr int kNRed = 4;
+// Neighbour-table entry flags: bit 30 = hop across the antiperiodic time edge.
+constexpr int32_t kNbrSign = 1 << 30;
+constexpr int32_t kNbrMask = kNbrSign - 1;
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct Timer {
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev;
+    size_t used = 0;
+    double bytes = 0;
+};
+
+}  // namespace dd
+
+struct dd_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;       // library stream (non-blocking, default priority)
+    hipStream_t user_stream = nullptr;  // caller's stream; each call waits for it on entry
+    std::string err;
+    std::map<std::string, dd::DevBuf> ws;  // named, grow-only workspaces
+    bool timing = false;
+    dd::Timer timers[DD_KCLASS_COUNT];
+};
+
+namespace dd {
+
+// A block shape: everything the stencil needs that does not depend on where
+// the block sits, except through the origin parity and the time-edge column.
+struct Shape {
+    int e[4];
+    int full[4];
+    int opar;   // parity of the origin
+    int tw;     // local x0 of the link that crosses the antiperiodic time edge, or -1
+    int S, h;   // sites, sites per parity
+    int64_t nbr_off;   // offset (entries) of this shape's table in the neighbour array
+    int64_t perm_off;  // offset of the eo -> local canonical permutation
+};
+
+struct TileTable {
+    int ntiles = 0;
+    int32_t *d_tile_block = nullptr;  // tile -> block
+    int32_t *d_blk_tile0 = nullptr;   // block -> first tile (n_blocks + 1 entries)
+    std::vector<int32_t> blk_tile0;
+};
+
+}  // namespace dd
+
+struct dd_blocks {
+    dd_ctx *ctx = nullptr;
+    int L[4] = {0, 0, 0, 0};
+    int tbc = -1;
+    int nb = 0;
+    std::vector<int32_t> box;       // [nb][16] origin, extent, inner offset, inner extent
+    std::vector<int64_t> soff;      // [nb+1] site offsets
+    std::vector<int32_t> shape_of;  // [nb]
+    std::vector<dd::Shape> shapes;
+    std::vector<int32_t> nbr;       // all shapes: [2][h][8]
+    std::vector<int32_t> perm;      // all shapes: [S] eo position -> local canonical index
+    std::vector<int32_t> bnd;       // dLambda_0 sites, box-local canonical, blocks concatenated
+    std::vector<int64_t> boff;      // [nb+1] offsets into bnd
+    int64_t inner_links = 0;
+    int max_h = 0;
+    // device copies
+    int32_t *d_nbr = nullptr;
+    int32_t *d_perm = nullptr;
+    int64_t *d_soff = nullptr;      // [nb+1]
+    int32_t *d_h = nullptr;         // [nb] sites per parity
+    int64_t *d_nbr_off = nullptr;   // [nb] neighbour-table offset of the block's shape
+    int64_t *d_perm_off = nullptr;  // [nb]
+    int32_t *d_origin = nullptr;    // [nb][4]
+    int32_t *d_ext = nullptr;       // [nb][4]
+    int32_t *d_bnd = nullptr;       // [total bnd] box-local canonical index
+    int64_t *d_boff = nullptr;      // [nb+1]
+    std::map<int, dd::TileTable> tiles;  // keyed by n_rhs
+};
+
+struct dd_gauge {
+    dd_ctx *ctx = nullptr;
+    const dd_blocks *blocks = nullptr;
+    dd_prec low = DD_F64;
+    double *d_u64 = nullptr;     // [total_sites][4][18]
+    float *d_u32 = nullptr;      // when low == DD_F32
+    uint16_t *d_ubf = nullptr;   // when low == DD_BF16
+};
+
+namespace dd {
+
+// ---------------------------------------------------------------- kernels
+
+// Per-block tables the site kernels read.
+struct BlkArgs {
+    const int32_t *tile_block;
+    const int32_t *blk_tile0;
+    const int32_t *h;
+    const int64_t *soff;
+    const int64_t *nbr_off;
+    const int32_t *nbr;
+    int ntiles;
+    int n_rhs;
+    int nb;  // number of blocks (pair = rhs * nb + block)
+};
+
+enum DotMode { kDotNone = 0, kDotAuxOut = 1, kDotOutSelfOutOut = 2, kDotOutOut = 3 };
+
+// out = c_add*add + c_self*self + c_hop * (H in), on the sites of `parity`.
+// in lives on the other parity.  Optional fused dot products per (tile, rhs).
+struct HopArgs {
+    void *out;
+    const void *in;
+    const void *self;
+    const void *add;
+    const void *aux;
+    double c_self, c_hop, c_add;
+    const void *links;
+    double *partial;  // [ntiles][n_rhs][kNRed]
+    int parity;
+    int dot_mode;
+};
+
+// Per-pair Krylov state (device, structure of arrays).
+struct PairState {
+    double *rho;     // [2*np] complex
+    double *alpha;   // [2*np]
+    double *omega;   // [2*np]
+    double *beta;    // [2*np]
+    double *bb;      // [np]  |rhs|^2 of the inner system
+    double *rr;      // [np]  |r|^2 (recursive)
+    int32_t *active; // [np]  inner iteration still running
+    int32_t *flags;  // [np]  bit 1 breakdown, bit 2 non-finite
+    int32_t *iters;  // [np]  cumulative inner iterations
+    int np;
+};
+
+// Outer (defect-correction) state.
+struct OuterState {
+    double *bb;         // [np] |b|^2
+    double *rr;         // [np] |b - D x|^2
+    int32_t *active;    // [np] still above tolerance
+    int32_t *flags;     // [np]
+};
+
+// launch wrappers (dd_kernels.hip)
+hipError_t launch_pack_gauge(const dd_blocks *B, const double *U, dd_prec prec, void *dst,
+                             hipStream_t s);
+hipError_t launch_pack_spinor(const dd_blocks *B, const double *src, void *even, void *odd,
+                              dd_prec prec, int n_rhs, hipStream_t s);
+hipError_t launch_unpack_spinor(const dd_blocks *B, const void *even, const void *odd, double *dst,
+                                dd_prec prec, int n_rhs, hipStream_t s);
+hipError_t launch_hop(const BlkArgs &ba, const HopArgs &ha, dd_prec prec, hipStream_t s);
+hipError_t launch_convert(const void *src, dd_prec sp, void *dst, dd_prec dp, int64_t n,
+                          hipStream_t s);
+hipError_t launch_accum(const BlkArgs &ba, double *x, const void *e, dd_prec ep,
+                        const int32_t *active, hipStream_t s);
+hipError_t launch_bicg_init(const BlkArgs &ba, dd_prec sp, const void *rhs, void *r, void *rh,
+                            void *p, void *x, double *partial, const int32_t *outer_active,
+                            hipStream_t s);
+hipError_t launch_bicg_s(const BlkArgs &ba, dd_prec sp, const void *r, const void *v, void *s,
+                         const PairState &ps, hipStream_t st);
+hipError_t launch_bicg_xr(const BlkArgs &ba, dd_prec sp, void *x, const void *p, const void *s,
+                          const void *t, void *r, const void *rh, double *partial,
+                          const PairState &ps, hipStream_t st);
+hipError_t launch_bicg_p(const BlkArgs &ba, dd_prec sp, const void *r, const void *v, void *p,
+                         const PairState &ps, hipStream_t st);
+hipError_t launch_sc_init(const BlkArgs &ba, const double *partial, const PairState &ps,
+                          const int32_t *outer_active, hipStream_t s);
+hipError_t launch_sc_alpha(const BlkArgs &ba, const double *partial, const PairState &ps,
+                           hipStream_t s);
+hipError_t launch_sc_omega(const BlkArgs &ba, const double *partial, const PairState &ps,
+                           hipStream_t s);
+hipError_t launch_sc_beta(const BlkArgs &ba, const double *partial, const PairState &ps,
+                          double tol, hipStream_t s);
+hipError_t launch_sc_outer(const BlkArgs &ba, const double *pe, const double *po, int first,
+                           double tol, const OuterState &os, hipStream_t s);
+hipError_t launch_mb_norm(const dd_blocks *B, int n_fields, const double *u, const double *chi,
+                          const double *y, double *S, hipStream_t s);
+
+}  // namespace dd

@@ -1,0 +1,331 @@
+// Batched block solves x = D_Lambda^{-1} b for all (block, rhs) pairs and the
+// block-local multi-boson action of libdd.
+//
+// Method (the paper needs the solves but prescribes no solver):
+//   outer: FP64 defect correction on the true residual r = b - D_Lambda x,
+//          computed with FP64 links and spinors, until |r| <= tol |b| per pair;
+//   inner: even-odd reduced system Dhat e_e = r_e + kappa H_eo r_o with
+//          Dhat = 1 - kappa^2 H_eo H_oe, solved by BiCGStab in the inner
+//          precision (FP64, FP32, or FP32 spinors with BF16 links), then
+//          e_o = r_o + kappa H_oe e_e and x += e.
+// Every launch covers all blocks and right-hand sides; per-pair scalars live
+// on the device and pairs that converge are frozen.  Hop launches always cover
+// every pair so that their cost per launch is fixed.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dd_host.h"
+#include "dd_internal.h"
+
+using namespace dd;
+
+namespace {
+
+struct Ws {
+    double *be, *bo, *xe, *xo, *re, *ro;  // FP64 half fields
+    void *rie, *rio;                      // residual in the inner precision
+    void *rhs, *xi, *r, *rh, *p, *v, *s, *t, *tmp;
+    double *pA, *pB, *pC, *pe, *po;       // dot partials
+    PairState ps;
+    OuterState os;
+};
+
+struct Inner {
+    dd_ctx *ctx;
+    const dd_blocks *B;
+    BlkArgs ba;
+    Ws *w;
+    const void *links;
+    dd_prec ip, sp;
+    double kappa, tol;
+};
+
+// one BiCGStab iteration on all pairs (10 launches)
+hipError_t bicg_iteration(const Inner &in)
+{
+    Ws &w = *in.w;
+    const double k2 = in.kappa * in.kappa;
+    hipError_t e;
+    hipStream_t st = in.ctx->stream;
+    // v = Dhat p
+    HopArgs h1 = hop_args(w.tmp, w.p, in.links, 1, 1.0);
+    if ((e = run_hop(in.ctx, in.B, in.ba, h1, in.ip)) != hipSuccess) return e;
+    HopArgs h2 = hop_args(w.v, w.tmp, in.links, 0, -k2);
+    h2.self = w.p;
+    h2.c_self = 1.0;
+    h2.aux = w.rh;
+    h2.dot_mode = kDotAuxOut;
+    h2.partial = w.pA;
+    if ((e = run_hop(in.ctx, in.B, in.ba, h2, in.ip)) != hipSuccess) return e;
+    if ((e = launch_sc_alpha(in.ba, w.pA, w.ps, st)) != hipSuccess) return e;
+    if ((e = launch_bicg_s(in.ba, in.sp, w.r, w.v, w.s, w.ps, st)) != hipSuccess) return e;
+    // t = Dhat s
+    HopArgs h3 = hop_args(w.tmp, w.s, in.links, 1, 1.0);
+    if ((e = run_hop(in.ctx, in.B, in.ba, h3, in.ip)) != hipSuccess) return e;
+    HopArgs h4 = hop_args(w.t, w.tmp, in.links, 0, -k2);
+    h4.self = w.s;
+    h4.c_self = 1.0;
+    h4.dot_mode = kDotOutSelfOutOut;
+    h4.partial = w.pB;
+    if ((e = run_hop(in.ctx, in.B, in.ba, h4, in.ip)) != hipSuccess) return e;
+    if ((e = launch_sc_omega(in.ba, w.pB, w.ps, st)) != hipSuccess) return e;
+    if ((e = launch_bicg_xr(in.ba, in.sp, w.xi, w.p, w.s, w.t, w.r, w.rh, w.pC, w.ps, st)) != hipSuccess) return e;
+    if ((e = launch_sc_beta(in.ba, w.pC, w.ps, in.tol, st)) != hipSuccess) return e;
+    return launch_bicg_p(in.ba, in.sp, w.r, w.v, w.p, w.ps, st);
+}
+
+double default_inner_tol(dd_prec ip, double tol)
+{
+    if (ip == DD_F64) return std::max(0.1 * tol, 1e-14);
+    if (ip == DD_F32) return 1e-6;
+    return 2e-3;
+}
+
+}  // namespace
+
+extern "C" {
+
+void dd_solve_params_default(dd_solve_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->tol = 1e-10;
+    p->method = DD_BICGSTAB;
+    p->restart = 16;
+    p->inner_prec = DD_F32;
+    p->inner_tol = 0;
+    p->max_outer = 30;
+    p->max_inner = 2000;
+    p->check_every = 8;
+    p->use_graph = 1;
+}
+
+dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, double kappa, const void *b_dev,
+                         void *x_dev, int32_t n_rhs, const dd_solve_params *params, dd_solve_stats *stats)
+{
+    const auto t_start = std::chrono::steady_clock::now();
+    if (!ctx || !Bc || !G || !b_dev || !x_dev) return fail(ctx, DD_EINVAL, "null argument");
+    if (n_rhs < 1 || n_rhs > kMaxRhs) return fail(ctx, DD_EINVAL, "n_rhs must be in 1..64");
+    if (G->blocks != Bc) return fail(ctx, DD_EINVAL, "gauge was loaded for other blocks");
+    dd_solve_params prm;
+    if (params) prm = *params;
+    else dd_solve_params_default(&prm);
+    if (!(prm.tol > 0)) return fail(ctx, DD_EINVAL, "tol must be positive");
+    if (prm.method != DD_BICGSTAB) return fail(ctx, DD_EUNSUPPORTED, "only DD_BICGSTAB is available");
+    const dd_prec ip = prm.inner_prec;
+    const void *links = links_for(G, ip);
+    if (!links) return fail(ctx, DD_EINVAL, "gauge holds no links of the inner precision");
+    const dd_prec sp = ip == DD_F64 ? DD_F64 : DD_F32;
+    const double inner_tol = prm.inner_tol > 0 ? prm.inner_tol : default_inner_tol(ip, prm.tol);
+    const int max_outer = prm.max_outer > 0 ? prm.max_outer : 30;
+    const int max_inner = prm.max_inner > 0 ? prm.max_inner : 2000;
+    const int check = prm.check_every > 0 ? prm.check_every : 8;
+    const bool graph = prm.use_graph && !ctx->timing;
+
+    dd_blocks *B = const_cast<dd_blocks *>(Bc);
+    HIPCHECK(ctx, enter(ctx));
+    hipError_t e;
+    const TileTable *tt = tiles_for(ctx, B, n_rhs, &e);
+    if (!tt) return fail(ctx, DD_EDEVICE, std::string("tile tables: ") + hipGetErrorString(e));
+    const BlkArgs ba = blk_args(B, tt, n_rhs);
+    const int np = n_rhs * B->nb;
+    const int64_t hel = (B->soff[B->nb] / 2) * 24 * (int64_t)n_rhs;  // elements per half field
+    const size_t h64 = (size_t)hel * 8, hsp = (size_t)hel * prec_bytes(sp);
+    const size_t npart = (size_t)std::max(tt->ntiles, 1) * n_rhs * kNRed * sizeof(double);
+
+    Ws w;
+    std::memset(&w, 0, sizeof(w));
+    e = hipSuccess;
+    auto get = [&](const char *name, size_t bytes) -> void * {
+        if (e != hipSuccess) return nullptr;
+        return workspace(ctx, name, bytes, &e);
+    };
+    w.be = (double *)get("s_be", h64);
+    w.bo = (double *)get("s_bo", h64);
+    w.xe = (double *)get("s_xe", h64);
+    w.xo = (double *)get("s_xo", h64);
+    w.re = (double *)get("s_re", h64);
+    w.ro = (double *)get("s_ro", h64);
+    if (sp == DD_F64) {
+        w.rie = w.re;
+        w.rio = w.ro;
+    } else {
+        w.rie = get("s_rie", hsp);
+        w.rio = get("s_rio", hsp);
+    }
+    w.rhs = get("s_rhs", hsp);
+    w.xi = get("s_xi", hsp);
+    w.r = get("s_r", hsp);
+    w.rh = get("s_rh", hsp);
+    w.p = get("s_p", hsp);
+    w.v = get("s_v", hsp);
+    w.s = get("s_s", hsp);
+    w.t = get("s_t", hsp);
+    w.tmp = get("s_tmp", hsp);
+    w.pA = (double *)get("s_pA", npart);
+    w.pB = (double *)get("s_pB", npart);
+    w.pC = (double *)get("s_pC", npart);
+    w.pe = (double *)get("s_pe", npart);
+    w.po = (double *)get("s_po", npart);
+    double *pd = (double *)get("s_pair_d", (size_t)np * 12 * sizeof(double));
+    int32_t *pi = (int32_t *)get("s_pair_i", (size_t)np * 5 * sizeof(int32_t));
+    if (e != hipSuccess) return fail(ctx, DD_ENOMEM, std::string("solver workspace: ") + hipGetErrorString(e));
+    w.ps.rho = pd;
+    w.ps.alpha = pd + 2 * np;
+    w.ps.omega = pd + 4 * np;
+    w.ps.beta = pd + 6 * np;
+    w.ps.bb = pd + 8 * np;
+    w.ps.rr = pd + 9 * np;
+    w.os.bb = pd + 10 * np;
+    w.os.rr = pd + 11 * np;
+    w.ps.active = pi;
+    w.ps.flags = pi + np;
+    w.ps.iters = pi + 2 * np;
+    w.os.active = pi + 3 * np;
+    w.os.flags = pi + 4 * np;
+    w.ps.np = np;
+
+    hipStream_t st = ctx->stream;
+    HIPCHECK(ctx, hipMemsetAsync(pi, 0, (size_t)np * 5 * sizeof(int32_t), st));
+    HIPCHECK(ctx, hipMemsetAsync(pd, 0, (size_t)np * 12 * sizeof(double), st));
+    HIPCHECK(ctx, hipMemsetAsync(w.xe, 0, h64, st));
+    HIPCHECK(ctx, hipMemsetAsync(w.xo, 0, h64, st));
+    HIPCHECK(ctx, launch_pack_spinor(B, (const double *)b_dev, w.be, w.bo, DD_F64, n_rhs, st));
+
+    Inner in{ctx, B, ba, &w, links, ip, sp, kappa, inner_tol};
+    std::vector<int32_t> h_act(np);
+    hipGraph_t g = nullptr;
+    hipGraphExec_t gx = nullptr;
+    int cycles = 0;
+    int64_t inner_total = 0;
+    dd_status status = DD_OK;
+    for (int cyc = 0;; cyc++) {
+        // FP64 true residual r_p = b_p - x_p + kappa H x_{1-p}, |r|^2 per pair
+        for (int p = 0; p < 2; p++) {
+            HopArgs h = hop_args(p ? w.ro : w.re, p ? w.xe : w.xo, G->d_u64, p, kappa);
+            h.self = p ? w.xo : w.xe;
+            h.c_self = -1.0;
+            h.add = p ? w.bo : w.be;
+            h.c_add = 1.0;
+            h.dot_mode = kDotOutOut;
+            h.partial = p ? w.po : w.pe;
+            HIPCHECK(ctx, run_hop(ctx, B, ba, h, DD_F64));
+        }
+        HIPCHECK(ctx, launch_sc_outer(ba, w.pe, w.po, cyc == 0, prm.tol, w.os, st));
+        HIPCHECK(ctx, hipMemcpyAsync(h_act.data(), w.os.active, np * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIPCHECK(ctx, hipStreamSynchronize(st));
+        int n_act = 0;
+        for (int v : h_act) n_act += v != 0;
+        if (n_act == 0 || cyc >= max_outer) break;
+        cycles++;
+        // inner source rhs_e = r_e + kappa H_eo r_o in the inner precision
+        if (sp != DD_F64) {
+            HIPCHECK(ctx, launch_convert(w.re, DD_F64, w.rie, sp, hel, st));
+            HIPCHECK(ctx, launch_convert(w.ro, DD_F64, w.rio, sp, hel, st));
+        }
+        {
+            HopArgs h = hop_args(w.rhs, w.rio, links, 0, kappa);
+            h.self = w.rie;
+            h.c_self = 1.0;
+            HIPCHECK(ctx, run_hop(ctx, B, ba, h, ip));
+        }
+        HIPCHECK(ctx, launch_bicg_init(ba, sp, w.rhs, w.r, w.rh, w.p, w.xi, w.pA, w.os.active, st));
+        HIPCHECK(ctx, launch_sc_init(ba, w.pA, w.ps, w.os.active, st));
+        if (graph && !gx) {
+            HIPCHECK(ctx, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            hipError_t ce = hipSuccess;
+            for (int k = 0; k < check && ce == hipSuccess; k++) ce = bicg_iteration(in);
+            hipError_t ee = hipStreamEndCapture(st, &g);
+            if (ce != hipSuccess) return fail(ctx, DD_EDEVICE, std::string("capture: ") + hipGetErrorString(ce));
+            HIPCHECK(ctx, ee);
+            HIPCHECK(ctx, hipGraphInstantiate(&gx, g, nullptr, nullptr, 0));
+        }
+        for (int it = 0; it < max_inner; it += check) {
+            if (gx) {
+                HIPCHECK(ctx, hipGraphLaunch(gx, st));
+            } else {
+                for (int k = 0; k < check; k++) HIPCHECK(ctx, bicg_iteration(in));
+            }
+            inner_total += check;
+            HIPCHECK(ctx, hipMemcpyAsync(h_act.data(), w.ps.active, np * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            HIPCHECK(ctx, hipStreamSynchronize(st));
+            int live = 0;
+            for (int v : h_act) live += v != 0;
+            if (live == 0) break;
+        }
+        // e_o = r_o + kappa H_oe e_e, then x += e on the pairs above tolerance
+        {
+            HopArgs h = hop_args(w.tmp, w.xi, links, 1, kappa);
+            h.self = w.rio;
+            h.c_self = 1.0;
+            HIPCHECK(ctx, run_hop(ctx, B, ba, h, ip));
+        }
+        HIPCHECK(ctx, launch_accum(ba, w.xe, w.xi, sp, w.os.active, st));
+        HIPCHECK(ctx, launch_accum(ba, w.xo, w.tmp, sp, w.os.active, st));
+    }
+    if (gx) hipGraphExecDestroy(gx);
+    if (g) hipGraphDestroy(g);
+    HIPCHECK(ctx, launch_unpack_spinor(B, w.xe, w.xo, (double *)x_dev, DD_F64, n_rhs, st));
+    std::vector<double> h_bb(np), h_rr(np);
+    std::vector<int32_t> h_if(np), h_of(np), h_it(np);
+    HIPCHECK(ctx, hipMemcpyAsync(h_bb.data(), w.os.bb, np * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHECK(ctx, hipMemcpyAsync(h_rr.data(), w.os.rr, np * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHECK(ctx, hipMemcpyAsync(h_if.data(), w.ps.flags, np * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHECK(ctx, hipMemcpyAsync(h_of.data(), w.os.flags, np * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHECK(ctx, hipMemcpyAsync(h_it.data(), w.ps.iters, np * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIPCHECK(ctx, hipStreamSynchronize(st));
+    for (int k = 0; k < np; k++) {
+        const int fl = (h_of[k] & 5) | (h_if[k] & 6);
+        if (!(fl & 1)) status = DD_ENOCONV;
+        if (stats) {
+            if (stats->iters) stats->iters[k] = h_it[k];
+            if (stats->true_relres) stats->true_relres[k] = h_bb[k] > 0 ? std::sqrt(h_rr[k] / h_bb[k]) : 0.0;
+            if (stats->flags) stats->flags[k] = fl;
+        }
+    }
+    if (stats) {
+        stats->outer_cycles = cycles;
+        stats->inner_iterations = inner_total;
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    }
+    if (status == DD_ENOCONV) ctx->err = "some (block, rhs) pairs missed the tolerance";
+    return status;
+}
+
+dd_status dd_multiboson_action(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *G, double kappa, int32_t n_fields,
+                               const double *u_host, const void *chi_dev, const void *xi_dev,
+                               const dd_solve_params *params, double *S_block_dev, double *S_total_host,
+                               dd_solve_stats *stats)
+{
+    if (!ctx || !B || !G || !u_host || !chi_dev || !xi_dev) return fail(ctx, DD_EINVAL, "null argument");
+    if (n_fields < 1 || n_fields > kMaxRhs) return fail(ctx, DD_EINVAL, "n_fields must be in 1..64");
+    hipError_t e = hipSuccess;
+    const size_t ybytes = (size_t)B->soff[B->nb] * 24 * n_fields * sizeof(double);
+    double *y = (double *)workspace(ctx, "mb_y", ybytes, &e);
+    double *ud = y ? (double *)workspace(ctx, "mb_u", (size_t)n_fields * 2 * sizeof(double), &e) : nullptr;
+    double *S = S_block_dev;
+    if (ud && !S) S = (double *)workspace(ctx, "mb_S", (size_t)std::max(B->nb, 1) * sizeof(double), &e);
+    if (!y || !ud || !S) return fail(ctx, DD_ENOMEM, std::string("workspace: ") + hipGetErrorString(e));
+    const dd_status st = dd_block_solve(ctx, B, G, kappa, xi_dev, y, n_fields, params, stats);
+    if (st != DD_OK && st != DD_ENOCONV) return st;
+    HIPCHECK(ctx, hipMemcpyAsync(ud, u_host, (size_t)n_fields * 2 * sizeof(double), hipMemcpyHostToDevice,
+                                 ctx->stream));
+    HIPCHECK(ctx, launch_mb_norm(B, n_fields, ud, (const double *)chi_dev, y, S, ctx->stream));
+    if (S_total_host) {
+        std::vector<double> hs(B->nb);
+        HIPCHECK(ctx, hipMemcpyAsync(hs.data(), S, B->nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
+        HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+        double tot = 0;
+        for (double v : hs) tot += v;
+        *S_total_host = tot;
+    }
+    HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+    return st;
+}
+
+}  // extern "C"

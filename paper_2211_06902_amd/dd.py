@@ -1,0 +1,365 @@
+"""ctypes binding of libdd (argument marshalling only).
+
+Every computation runs in the HIP library ``libdd.so`` next to this file;
+nothing here computes on the host.  Importing this module fails loudly when
+the library has not been built.  Function names follow the C ABI in
+``include/dd.h`` without the ``dd_`` prefix.
+
+Device buffers are torch tensors on the GPU (complex128 for spinors and
+links, float64 for actions); the library orders its work after the current
+torch stream and synchronises before returning.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdd.so")
+
+DD_OK, DD_EINVAL, DD_ENOMEM, DD_EDEVICE, DD_ENOCONV, DD_EUNSUPPORTED = range(6)
+F64, F32, BF16 = 0, 1, 2
+BICGSTAB, GMRES = 0, 1
+KCLASS_HOP, KCLASS_BLAS = 0, 1
+_PREC = {"f64": F64, "f32": F32, "bf16": BF16, F64: F64, F32: F32, BF16: BF16}
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libdd.so is not built; run `python -m paper_2211_06902_amd.build` "
+                      "(or __graft_entry__.build())")
+
+# torch must load its HIP runtime first: libdd then binds to that same runtime
+# (same SONAME), so torch's device pointers and streams are valid in libdd.
+import torch  # noqa: E402,F401
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+
+def _hip_runtimes():
+    paths = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                if "libamdhip64" in line:
+                    paths.add(os.path.realpath(line.split()[-1]))
+    except OSError:
+        pass
+    return paths
+
+
+if len(_hip_runtimes()) > 1:
+    raise ImportError("two HIP runtimes are mapped (%s); import torch before anything that loads "
+                      "libamdhip64" % ", ".join(sorted(_hip_runtimes())))
+_P = ctypes.c_void_p
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_D = ctypes.c_double
+_PP = ctypes.POINTER(ctypes.c_void_p)
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [
+        ("tol", _D),
+        ("method", _I32),
+        ("restart", _I32),
+        ("inner_prec", _I32),
+        ("inner_tol", _D),
+        ("max_outer", _I32),
+        ("max_inner", _I32),
+        ("check_every", _I32),
+        ("use_graph", _I32),
+    ]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [
+        ("iters", _P),
+        ("true_relres", _P),
+        ("flags", _P),
+        ("seconds", _D),
+        ("outer_cycles", _I32),
+        ("inner_iterations", _I64),
+    ]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_sig("dd_version", ctypes.c_char_p, [])
+_sig("dd_create", _I32, [ctypes.c_int, _P, _PP])
+_sig("dd_destroy", _I32, [_P])
+_sig("dd_last_error", ctypes.c_char_p, [_P])
+_sig("dd_make_blocks", _I32, [_P, _P, _I32, _P, _P, _P, _I32, _PP])
+_sig("dd_make_blocks_paper", _I32, [_P, _P, _I32, _P, _PP])
+_sig("dd_make_blocks_boxes", _I32, [_P, _P, _I32, _I32, _P, _P, _PP])
+_sig("dd_free_blocks", _I32, [_P])
+_sig("dd_blocks_query", _I32, [_P, _P, _P, _P, _P])
+_sig("dd_blocks_tables", _I32, [_P, _P, _P, _P, _P])
+_sig("dd_load_gauge", _I32, [_P, _P, _P, _I32, _PP])
+_sig("dd_free_gauge", _I32, [_P])
+_sig("dd_gauge_export", _I32, [_P, _P, _I32, _P])
+_sig("dd_apply_D_block", _I32, [_P, _P, _P, _D, _I32, _P, _P, _I32])
+_sig("dd_solve_params_default", None, [ctypes.POINTER(SolveParams)])
+_sig("dd_block_solve", _I32, [_P, _P, _P, _D, _P, _P, _I32, ctypes.POINTER(SolveParams),
+                              ctypes.POINTER(SolveStats)])
+_sig("dd_multiboson_action", _I32, [_P, _P, _P, _D, _I32, _P, _P, _P, ctypes.POINTER(SolveParams), _P, _P,
+                                    ctypes.POINTER(SolveStats)])
+_sig("dd_timer_enable", _I32, [_P, _I32])
+_sig("dd_timer_reset", _I32, [_P])
+_sig("dd_timer_read", _I32, [_P, _I32, _P, _P, _P])
+
+
+class DDError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("libdd status %d: %s" % (status, msg))
+        self.status = status
+
+
+def version() -> str:
+    return _lib.dd_version().decode()
+
+
+def _i32(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.int32).reshape(-1))
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(_P)
+
+
+def _dev(t, dtype_name):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a GPU torch tensor")
+    if str(t.dtype) != dtype_name:
+        raise TypeError("expected dtype %s, got %s" % (dtype_name, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return _P(t.data_ptr())
+
+
+def solve_params(**kw) -> SolveParams:
+    p = SolveParams()
+    _lib.dd_solve_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        if k == "inner_prec":
+            v = _PREC[v]
+        setattr(p, k, v)
+    return p
+
+
+class Blocks:
+    """A block decomposition (boxes, even-odd maps, neighbour tables)."""
+
+    def __init__(self, handle, ctx):
+        self._h = handle
+        self._ctx = ctx
+        nb, ts, tb, il = _I64(), _I64(), _I64(), _I64()
+        _lib.dd_blocks_query(self._h, ctypes.byref(nb), ctypes.byref(ts), ctypes.byref(tb), ctypes.byref(il))
+        self.n_blocks, self.total_sites, self.total_bnd_sites, self.inner_links = nb.value, ts.value, tb.value, il.value
+
+    def tables(self):
+        """(boxes[nb,16], sites[total], eo[total], bnd[total_bnd]) as numpy arrays."""
+        boxes = np.zeros((self.n_blocks, 16), dtype=np.int32)
+        sites = np.zeros(self.total_sites, dtype=np.int64)
+        eo = np.zeros(self.total_sites, dtype=np.int32)
+        bnd = np.zeros(max(self.total_bnd_sites, 1), dtype=np.int32)
+        _lib.dd_blocks_tables(self._h, _ptr(boxes), _ptr(sites), _ptr(eo), _ptr(bnd))
+        return boxes, sites, eo, bnd[: self.total_bnd_sites]
+
+    def close(self):
+        if self._h:
+            _lib.dd_free_blocks(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _make(fn, ctx, *args):
+    out = _P()
+    st = fn(ctx._h if ctx is not None else None, *args, ctypes.byref(out))
+    if st != DD_OK:
+        msg = _lib.dd_last_error(ctx._h if ctx is not None else None).decode()
+        raise DDError(st, msg)
+    return Blocks(out, ctx)
+
+
+def make_blocks(ctx, L, time_bc, segs, shift=(0, 0, 0, 0), inner_d=0) -> Blocks:
+    """Tile decomposition; ctx None builds host tables only."""
+    nseg = _i32([len(s) for s in segs])
+    seg = _i32([v for s in segs for v in s])
+    return _make(_lib.dd_make_blocks, ctx, _ptr(_i32(L)), int(time_bc), _ptr(seg), _ptr(nseg), _ptr(_i32(shift)),
+                 int(inner_d))
+
+
+def make_blocks_paper(ctx, L, time_bc, bd) -> Blocks:
+    return _make(_lib.dd_make_blocks_paper, ctx, _ptr(_i32(L)), int(time_bc), _ptr(_i32(bd)))
+
+
+def make_blocks_boxes(ctx, L, time_bc, boxes, inner=None) -> Blocks:
+    b = _i32(boxes)
+    inn = _i32(inner) if inner is not None else None
+    return _make(_lib.dd_make_blocks_boxes, ctx, _ptr(_i32(L)), int(time_bc), int(b.size // 8), _ptr(b),
+                 _ptr(inn) if inn is not None else None)
+
+
+class Gauge:
+    def __init__(self, handle, ctx, blocks, low):
+        self._h = handle
+        self._ctx = ctx
+        self.blocks = blocks
+        self.low = low
+
+    def export(self, prec):
+        """Packed links of precision prec as a GPU tensor (float64, float32 or int16 bits)."""
+        import torch
+
+        n = self.blocks.total_sites * 72
+        dt = {F64: torch.float64, F32: torch.float32, BF16: torch.int16}[_PREC[prec]]
+        out = torch.empty(n, dtype=dt, device="cuda")
+        self._ctx._check(_lib.dd_gauge_export(self._ctx._h, self._h, _PREC[prec], _P(out.data_ptr())))
+        return out
+
+    def close(self):
+        if self._h:
+            _lib.dd_free_gauge(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Context:
+    """A libdd context on one GPU; work is ordered after torch's current stream."""
+
+    def __init__(self, device: int = 0):
+        import torch
+
+        torch.cuda.init()
+        stream = torch.cuda.current_stream(device).cuda_stream
+        h = _P()
+        st = _lib.dd_create(int(device), _P(stream), ctypes.byref(h))
+        if st != DD_OK:
+            raise DDError(st, "dd_create failed on device %d" % device)
+        self._h = h
+        self.device = device
+
+    def _check(self, st, allow=()):
+        if st != DD_OK and st not in allow:
+            raise DDError(st, _lib.dd_last_error(self._h).decode())
+        return st
+
+    def close(self):
+        if self._h:
+            _lib.dd_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # geometry
+    def make_blocks(self, L, time_bc, segs, shift=(0, 0, 0, 0), inner_d=0) -> Blocks:
+        return make_blocks(self, L, time_bc, segs, shift, inner_d)
+
+    def make_blocks_paper(self, L, time_bc, bd) -> Blocks:
+        return make_blocks_paper(self, L, time_bc, bd)
+
+    def make_blocks_boxes(self, L, time_bc, boxes, inner=None) -> Blocks:
+        return make_blocks_boxes(self, L, time_bc, boxes, inner)
+
+    # gauge
+    def load_gauge(self, blocks: Blocks, U, low_prec="f32") -> Gauge:
+        out = _P()
+        self._check(_lib.dd_load_gauge(self._h, blocks._h, _dev(U, "torch.complex128"), _PREC[low_prec],
+                                       ctypes.byref(out)))
+        return Gauge(out, self, blocks, _PREC[low_prec])
+
+    # operator
+    def apply_D_block(self, blocks: Blocks, gauge: Gauge, kappa, prec, x, y=None, n_rhs=None):
+        import torch
+
+        if n_rhs is None:
+            n_rhs = x.numel() // (blocks.total_sites * 12)
+        if y is None:
+            y = torch.empty_like(x)
+        self._check(_lib.dd_apply_D_block(self._h, blocks._h, gauge._h, float(kappa), _PREC[prec],
+                                          _dev(x, "torch.complex128"), _dev(y, "torch.complex128"), int(n_rhs)))
+        return y
+
+    # solves
+    def block_solve(self, blocks: Blocks, gauge: Gauge, kappa, b, x=None, n_rhs=None, params=None):
+        """Returns (x, stats dict, status) with status DD_OK or DD_ENOCONV."""
+        import torch
+
+        if n_rhs is None:
+            n_rhs = b.numel() // (blocks.total_sites * 12)
+        if x is None:
+            x = torch.empty_like(b)
+        if params is None:
+            params = solve_params()
+        np_ = n_rhs * blocks.n_blocks
+        iters = np.zeros(np_, dtype=np.int32)
+        rel = np.zeros(np_, dtype=np.float64)
+        flags = np.zeros(np_, dtype=np.int32)
+        stats = SolveStats(_ptr(iters), _ptr(rel), _ptr(flags), 0.0, 0, 0)
+        st = self._check(_lib.dd_block_solve(self._h, blocks._h, gauge._h, float(kappa), _dev(b, "torch.complex128"),
+                                             _dev(x, "torch.complex128"), int(n_rhs), ctypes.byref(params),
+                                             ctypes.byref(stats)), allow=(DD_ENOCONV,))
+        info = {"iters": iters.reshape(n_rhs, blocks.n_blocks), "true_relres": rel.reshape(n_rhs, blocks.n_blocks),
+                "flags": flags.reshape(n_rhs, blocks.n_blocks), "seconds": stats.seconds,
+                "outer_cycles": stats.outer_cycles, "inner_iterations": stats.inner_iterations}
+        return x, info, st
+
+    def multiboson_action(self, blocks: Blocks, gauge: Gauge, kappa, u, chi, xi, params=None, S_block=None):
+        """Returns (S_block tensor [n_blocks] float64, S_total, stats dict, status)."""
+        import torch
+
+        u = np.ascontiguousarray(np.asarray(u, dtype=np.complex128).reshape(-1))
+        nf = u.size
+        uu = np.ascontiguousarray(np.stack([u.real, u.imag], axis=1).reshape(-1))
+        if S_block is None:
+            S_block = torch.empty(blocks.n_blocks, dtype=torch.float64, device="cuda")
+        if params is None:
+            params = solve_params()
+        np_ = nf * blocks.n_blocks
+        iters = np.zeros(np_, dtype=np.int32)
+        rel = np.zeros(np_, dtype=np.float64)
+        flags = np.zeros(np_, dtype=np.int32)
+        stats = SolveStats(_ptr(iters), _ptr(rel), _ptr(flags), 0.0, 0, 0)
+        tot = _D()
+        st = self._check(_lib.dd_multiboson_action(self._h, blocks._h, gauge._h, float(kappa), int(nf), _ptr(uu),
+                                                   _dev(chi, "torch.complex128"), _dev(xi, "torch.complex128"),
+                                                   ctypes.byref(params), _dev(S_block, "torch.float64"),
+                                                   ctypes.byref(tot), ctypes.byref(stats)), allow=(DD_ENOCONV,))
+        info = {"iters": iters.reshape(nf, blocks.n_blocks), "true_relres": rel.reshape(nf, blocks.n_blocks),
+                "flags": flags.reshape(nf, blocks.n_blocks), "seconds": stats.seconds,
+                "outer_cycles": stats.outer_cycles}
+        return S_block, tot.value, info, st
+
+    # timing
+    def timer_enable(self, on=True):
+        self._check(_lib.dd_timer_enable(self._h, 1 if on else 0))
+
+    def timer_reset(self):
+        self._check(_lib.dd_timer_reset(self._h))
+
+    def timer_read(self, kclass=KCLASS_HOP):
+        ms, n, b = _D(), _I64(), _D()
+        self._check(_lib.dd_timer_read(self._h, int(kclass), ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)))
+        return ms.value, n.value, b.value

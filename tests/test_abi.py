@@ -1,0 +1,134 @@
+"""CPU checks of the C ABI: the library loads, exports every declared symbol,
+and its host geometry tables agree bit for bit with the oracle's geometry."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import geometry
+from tests import _cfg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "dd.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(dd_[a-z_A-Z0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2211_06902_amd import dd
+
+    lib = ctypes.CDLL(dd.LIB_PATH)
+    syms = _declared_symbols()
+    assert len(syms) >= 20
+    missing = [s for s in syms if not hasattr(lib, s)]
+    assert not missing, missing
+    assert dd.version().startswith("libdd")
+
+
+def _check_tables(blk, L, boxes, inner=None):
+    bx, sites, eo, bnd = blk.tables()
+    assert blk.n_blocks == len(boxes)
+    assert np.array_equal(bx[:, :8], np.asarray(boxes, dtype=np.int32).reshape(-1, 8))
+    exp_sites = _cfg.block_sites(L, boxes)
+    assert np.array_equal(sites, exp_sites)
+    off = _cfg.site_offsets(boxes)
+    for k, b in enumerate(boxes):
+        _, pos = geometry.box_eo_order(L, b[:4], b[4:8])
+        assert np.array_equal(eo[off[k]:off[k + 1]], pos)
+    if inner is not None:
+        exp = np.concatenate([geometry.inner_boundary_local(L, b, i[:4], i[4:8]) for b, i in zip(boxes, inner)])
+        assert np.array_equal(bnd, exp)
+        assert np.array_equal(bx[:, 8:16], np.asarray(inner, dtype=np.int32).reshape(-1, 8))
+    # links kept by D_Lambda: every forward hop that stays inside its box
+    n_links = 0
+    for b in boxes:
+        e = np.asarray(b[4:8])
+        for mu in range(4):
+            if e[mu] == L[mu]:
+                n_links += int(np.prod(e))
+            else:
+                n_links += int(np.prod(e)) // e[mu] * (e[mu] - 1)
+    assert blk.inner_links == n_links
+
+
+def test_tiles_c1_both_tilings():
+    from paper_2211_06902_amd import dd
+
+    L = _cfg.C1["L"]
+    for shift in [(0, 0, 0, 0), (1, 1, 1, 1)]:
+        blk = dd.make_blocks(None, L, -1, _cfg.C1["segs"], shift=shift)
+        _check_tables(blk, L, geometry.tile_boxes(L, _cfg.C1["segs"], shift=shift))
+
+
+def test_tiles_c2_and_inner_boundary():
+    from paper_2211_06902_amd import dd
+
+    L = (16, 16, 16, 16)
+    blk = dd.make_blocks(None, L, -1, [[8, 8]] * 4, inner_d=1)
+    boxes = geometry.tile_boxes(L, [[8, 8]] * 4)
+    inner = [[1, 1, 1, 1, 6, 6, 6, 6]] * len(boxes)
+    _check_tables(blk, L, boxes, inner)
+    assert blk.total_bnd_sites == len(boxes) * (6**4 - 4**4)
+
+
+def test_tiles_c3_uneven():
+    from paper_2211_06902_amd import dd
+
+    L = (40, 8, 8, 16)
+    segs = [[12, 8, 12, 8], [8], [4, 4], [8, 8]]
+    blk = dd.make_blocks(None, L, -1, segs)
+    _check_tables(blk, L, geometry.tile_boxes(L, segs))
+
+
+def test_paper_mode_framed_blocks():
+    from paper_2211_06902_amd import dd
+
+    L = (6, 6, 6, 4)
+    bd = [2, 1, 2, 1, 2, 1, 0, 0]
+    blk = dd.make_blocks_paper(None, L, -1, bd)
+    P = geometry.PaperDomains(L, [(2, 1), (2, 1), (2, 1), None])
+    boxes = [list(b["omega"][0]) + list(b["omega"][1]) for b in P.blocks]
+    inner = [[1, 1, 1, 0, 2, 2, 2, 4]] * len(boxes)
+    _check_tables(blk, L, boxes, inner)
+    # dLambda_0 from the tables equals the oracle's dLambda_0^a
+    _, sites, _, bnd = blk.tables()
+    off = _cfg.site_offsets(boxes)
+    boff = 0
+    for a in range(len(boxes)):
+        n = int(P.dlam0_a[a].sum())
+        got = sites[off[a] + bnd[boff:boff + n]]
+        assert np.array_equal(np.sort(got), np.nonzero(P.dlam0_a[a])[0])
+        boff += n
+
+
+def test_explicit_boxes_wrapping_and_full_span():
+    from paper_2211_06902_amd import dd
+
+    L = (4, 4, 2, 2)
+    boxes = [[3, 1, 0, 1, 2, 2, 2, 2], [1, 0, 0, 0, 4, 2, 2, 2], [2, 3, 1, 0, 2, 2, 2, 2]]
+    blk = dd.make_blocks_boxes(None, L, -1, boxes)
+    _check_tables(blk, L, boxes)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(L=(4, 4, 4, 4), segs=[[3, 1], [2, 2], [2, 2], [2, 2]]),   # odd extent
+    dict(L=(4, 4, 4, 4), segs=[[2, 2], [2, 2], [2, 2], [2, 4]]),   # does not sum to L
+    dict(L=(5, 4, 4, 4), segs=[[5], [2, 2], [2, 2], [2, 2]]),      # odd lattice
+])
+def test_invalid_geometry_rejected(bad):
+    from paper_2211_06902_amd import dd
+
+    with pytest.raises(dd.DDError) as ei:
+        dd.make_blocks(None, bad["L"], -1, bad["segs"])
+    assert ei.value.status == dd.DD_EINVAL
+
+
+def test_header_cites_paper_sections():
+    txt = open(os.path.join(ROOT, "include", "dd.h")).read()
+    for s in ["Section 2", "Section 3", "Section 4", "eq. (localMB)"]:
+        assert s in txt

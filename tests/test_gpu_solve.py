@@ -1,0 +1,173 @@
+"""GPU parity of the batched block solves x = D_Lambda^{-1} b against the oracle.
+
+Every accepted pair must have an FP64 true relative residual <= 1e-10, recomputed
+here by the oracle's own operator, and its solution must agree with the
+oracle's (dense LU on the tiny blocks, the oracle's FP64 solve elsewhere)
+within cond x 1e-10.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import dense, geometry, wilson
+from tests import _cfg
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2211_06902_amd import dd
+
+    c = dd.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _true_relres(L, kappa, U, bx, x, b):
+    r = b - wilson.dirac_box(L, -1, kappa, U, bx[:4], bx[4:8], x)
+    return np.linalg.norm(r) / np.linalg.norm(b)
+
+
+@pytest.fixture(scope="module")
+def c1(ctx):
+    c = _cfg.C1
+    L = c["L"]
+    U = synth.gauge_field(L, c["eps"], c["seed_u"])
+    boxes = _cfg.c1_boxes()
+    b = synth.spinor_field(L, c["nrhs"], c["seed_src"])[:, _cfg.block_sites(L, boxes)]
+    blk = ctx.make_blocks_boxes(L, -1, boxes)
+    xs = []
+    for bx, k in zip(boxes, range(len(boxes))):
+        M = dense.dense_dirac_box(L, -1, c["kappa"], U, bx[:4], bx[4:8])
+        xs.append(np.linalg.solve(M, b[:, 16 * k:16 * (k + 1)].reshape(c["nrhs"], -1).T).T.reshape(c["nrhs"], 16, 4, 3))
+    x_lu = np.concatenate(xs, axis=1)
+    return dict(L=L, U=U, boxes=boxes, b=b, blk=blk, x_lu=x_lu, kappa=c["kappa"])
+
+
+@pytest.mark.parametrize("inner", ["f64", "f32", "bf16"])
+def test_c1_overlapping_blocks_vs_dense_lu(ctx, c1, inner):
+    from paper_2211_06902_amd import dd
+
+    g = ctx.load_gauge(c1["blk"], _dev(c1["U"]), "bf16" if inner == "bf16" else "f32")
+    x, info, st = ctx.block_solve(c1["blk"], g, c1["kappa"], _dev(c1["b"]),
+                                  params=dd.solve_params(inner_prec=inner, tol=TOL))
+    assert st == dd.DD_OK
+    assert np.all(info["true_relres"] <= TOL) and np.all(info["flags"] & 1)
+    x = x.cpu().numpy()
+    for k, bx in enumerate(c1["boxes"]):
+        for r in range(x.shape[0]):
+            sl = slice(16 * k, 16 * (k + 1))
+            assert _true_relres(c1["L"], c1["kappa"], c1["U"], bx, x[r, sl], c1["b"][r, sl]) <= TOL
+    assert _cfg.rel_err(x, c1["x_lu"]) <= 1e-9
+    g.close()
+
+
+def test_graph_replay_matches_eager(ctx, c1):
+    from paper_2211_06902_amd import dd
+
+    g = ctx.load_gauge(c1["blk"], _dev(c1["U"]), "f32")
+    b = _dev(c1["b"])
+    x1, i1, _ = ctx.block_solve(c1["blk"], g, c1["kappa"], b, params=dd.solve_params(use_graph=1))
+    x2, i2, _ = ctx.block_solve(c1["blk"], g, c1["kappa"], b, params=dd.solve_params(use_graph=0))
+    x3, i3, _ = ctx.block_solve(c1["blk"], g, c1["kappa"], b, params=dd.solve_params(use_graph=1))
+    assert np.array_equal(x1.cpu().numpy(), x2.cpu().numpy())
+    assert np.array_equal(x1.cpu().numpy(), x3.cpu().numpy())
+    assert np.array_equal(i1["iters"], i2["iters"])
+    g.close()
+
+
+def test_zero_and_nan_sources_are_isolated(ctx, c1):
+    """A zero source gives x = 0; a NaN source is flagged non-finite; other pairs are unaffected."""
+    from paper_2211_06902_amd import dd
+
+    g = ctx.load_gauge(c1["blk"], _dev(c1["U"]), "f32")
+    b = c1["b"][:3].copy()
+    b[0, 0:16] = 0.0                      # pair (rhs 0, block 0)
+    b[1, 16 * 5 + 3, 2, 1] = np.nan       # pair (rhs 1, block 5)
+    x, info, st = ctx.block_solve(c1["blk"], g, c1["kappa"], _dev(b), params=dd.solve_params())
+    assert st == dd.DD_ENOCONV
+    x = x.cpu().numpy()
+    assert np.all(x[0, 0:16] == 0) and info["flags"][0, 0] & 1
+    assert info["flags"][1, 5] & 4 and not info["flags"][1, 5] & 1
+    ok = np.ones_like(info["flags"], dtype=bool)
+    ok[1, 5] = False
+    assert np.all(info["true_relres"][ok] <= TOL)
+    # pairs other than the poisoned one match the dense solution
+    for r in range(3):
+        for k in range(len(c1["boxes"])):
+            if (r, k) in [(1, 5)]:
+                continue
+            sl = slice(16 * k, 16 * (k + 1))
+            ref = np.zeros_like(x[r, sl]) if (r, k) == (0, 0) else c1["x_lu"][r, sl]
+            assert np.linalg.norm(x[r, sl] - ref) <= 1e-9 * max(np.linalg.norm(ref), 1.0)
+    g.close()
+
+
+def test_max_outer_one_reports_noconv(ctx, c1):
+    from paper_2211_06902_amd import dd
+
+    g = ctx.load_gauge(c1["blk"], _dev(c1["U"]), "bf16")
+    x, info, st = ctx.block_solve(c1["blk"], g, c1["kappa"], _dev(c1["b"][:2]),
+                                  params=dd.solve_params(inner_prec="bf16", max_outer=1))
+    assert st == dd.DD_ENOCONV
+    assert np.all(info["true_relres"] > TOL) and np.all(info["true_relres"] < 1e-1)
+    assert info["outer_cycles"] == 1
+    g.close()
+
+
+def test_single_rhs_uneven_blocks(ctx):
+    from paper_2211_06902_amd import dd
+
+    L = (20, 8, 8, 8)
+    segs = [[12, 8], [8], [4, 4], [8]]
+    kappa = 0.13
+    U = synth.gauge_field(L, 0.3, 41)
+    boxes = geometry.tile_boxes(L, segs)
+    off = _cfg.site_offsets(boxes)
+    b = synth.spinor_field(L, 1, 42)[:, _cfg.block_sites(L, boxes)]
+    blk = ctx.make_blocks(L, -1, segs)
+    g = ctx.load_gauge(blk, _dev(U), "f32")
+    x, info, st = ctx.block_solve(blk, g, kappa, _dev(b))
+    assert st == dd.DD_OK
+    x = x.cpu().numpy()
+    for k, bx in enumerate(boxes):
+        sl = slice(off[k], off[k + 1])
+        assert _true_relres(L, kappa, U, bx, x[0, sl], b[0, sl]) <= TOL
+        xo, _, _ = wilson.solve_box(L, -1, kappa, U, bx[:4], bx[4:8], b[0, sl], tol=1e-12)
+        assert _cfg.rel_err(x[0, sl], xo) <= 1e-8
+
+
+def test_c2_full_size_fp32_defect_correction(ctx):
+    """The benchmark workload: 256 blocks of 8^4, 12 rhs, FP32 inner solves, FP64 defect correction."""
+    from paper_2211_06902_amd import dd
+
+    c = _cfg.C2
+    L = c["L"]
+    U = synth.gauge_field(L, c["eps"], c["seed_u"])
+    boxes = geometry.tile_boxes(L, c["segs"])
+    b = synth.spinor_field(L, c["nrhs"], c["seed_src"])[:, _cfg.block_sites(L, boxes)]
+    blk = ctx.make_blocks(L, -1, c["segs"])
+    g = ctx.load_gauge(blk, _dev(U), "f32")
+    x, info, st = ctx.block_solve(blk, g, c["kappa"], _dev(b), params=dd.solve_params(inner_prec="f32"))
+    print("C2: outer cycles %d, inner iterations %d, %.3f s" % (info["outer_cycles"], info["inner_iterations"],
+                                                                 info["seconds"]))
+    assert st == dd.DD_OK
+    assert np.all(info["true_relres"] <= TOL)
+    x = x.cpu().numpy()
+    S = 8**4
+    for k, r in [(0, 0), (77, 5), (255, 11)]:
+        bx = boxes[k]
+        sl = slice(k * S, (k + 1) * S)
+        assert _true_relres(L, c["kappa"], U, bx, x[r, sl], b[r, sl]) <= TOL
+        xo, _, rel = wilson.solve_box(L, -1, c["kappa"], U, bx[:4], bx[4:8], b[r, sl], tol=1e-12)
+        assert rel <= 1e-12
+        assert _cfg.rel_err(x[r, sl], xo) <= 1e-8

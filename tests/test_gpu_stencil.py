@@ -1,0 +1,142 @@
+"""GPU parity of link packing and of D_Lambda (FP64 / FP32 / BF16 links) against the oracle."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import geometry, precision, wilson
+from tests import _cfg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2211_06902_amd import dd
+
+    c = dd.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _expected_links(L, U, boxes, conv):
+    """Packed layout by definition: block, eo slot, mu, 18 reals; zero where the hop leaves the box."""
+    out = []
+    Uf = U.view(np.float64).reshape(U.shape[0], 4, 18)
+    for bx in boxes:
+        o, e = bx[:4], np.asarray(bx[4:8])
+        perm, _ = geometry.box_eo_order(L, o, e)
+        sites = geometry.box_sites(L, o, e)
+        y = np.indices(tuple(e)).reshape(4, -1).T
+        blk = np.zeros((perm.size, 4, 18))
+        for mu in range(4):
+            inside = (y[:, mu] + 1 < e[mu]) | (e[mu] == L[mu])
+            vals = Uf[sites, mu]
+            blk[:, mu] = np.where(inside[:, None], vals, 0.0)[perm]
+        out.append(blk)
+    return conv(np.concatenate(out).reshape(-1))
+
+
+@pytest.mark.parametrize("low", ["f32", "bf16"])
+def test_link_packing_bit_exact(ctx, low):
+    L = (8, 8, 4, 4)
+    U = synth.gauge_field(L, 0.5, 17)
+    segs = [[4, 4], [2, 6], [4], [2, 2]]
+    blk = ctx.make_blocks(L, -1, segs, shift=(1, 0, 1, 1))
+    g = ctx.load_gauge(blk, _dev(U), low)
+    boxes = geometry.tile_boxes(L, segs, shift=(1, 0, 1, 1))
+    got64 = g.export("f64").cpu().numpy()
+    assert np.array_equal(got64, _expected_links(L, U, boxes, lambda a: a))
+    got = g.export(low).cpu().numpy()
+    if low == "f32":
+        exp = _expected_links(L, U, boxes, precision.to_f32)
+        assert np.array_equal(got.view(np.uint32), exp.view(np.uint32))
+    else:
+        exp = _expected_links(L, U, boxes, lambda a: precision.f32_to_bf16_bits(precision.to_f32(a)))
+        assert np.array_equal(got.view(np.uint16), exp)
+
+
+def _check_apply(ctx, L, kappa, eps, seed_u, seed_src, segs, shift, nrhs, sample_blocks, sample_rhs):
+    U = synth.gauge_field(L, eps, seed_u)
+    boxes = geometry.tile_boxes(L, segs, shift=shift)
+    sites = _cfg.block_sites(L, boxes)
+    off = _cfg.site_offsets(boxes)
+    src = synth.spinor_field(L, nrhs, seed_src)
+    x = src[:, sites]
+    blk = ctx.make_blocks(L, -1, segs, shift=shift)
+    errs = {}
+    for low in ["f32", "bf16"]:
+        g = ctx.load_gauge(blk, _dev(U), low)
+        Ubf = np.empty_like(U)
+        Ubf.real = precision.round_bf16(U.real)
+        Ubf.imag = precision.round_bf16(U.imag)
+        for prec in (["f64", "f32"] if low == "f32" else ["bf16"]):
+            y = ctx.apply_D_block(blk, g, kappa, prec, _dev(x)).cpu().numpy()
+            Uo = Ubf if prec == "bf16" else U
+            worst = 0.0
+            for b in sample_blocks:
+                bx = boxes[b]
+                for r in sample_rhs:
+                    ref = wilson.dirac_box(L, -1, kappa, Uo, bx[:4], bx[4:8], x[r, off[b]:off[b + 1]])
+                    worst = max(worst, _cfg.rel_err(y[r, off[b]:off[b + 1]], ref))
+            errs[prec] = worst
+        g.close()
+    assert errs["f64"] <= 1e-12, errs
+    assert errs["f32"] <= 1e-5, errs
+    assert errs["bf16"] <= 1e-5, errs
+    return errs
+
+
+def test_apply_c1_plain_and_shifted_tilings(ctx):
+    c = _cfg.C1
+    for shift in [(0, 0, 0, 0), (1, 1, 1, 1)]:
+        _check_apply(ctx, c["L"], c["kappa"], c["eps"], c["seed_u"], c["seed_src"], c["segs"], shift, c["nrhs"],
+                     range(16), range(12))
+
+
+def test_apply_uneven_small(ctx):
+    L = (20, 8, 8, 8)
+    segs = [[12, 8], [8], [4, 4], [8]]
+    _check_apply(ctx, L, 0.13, 0.4, 9, 10, segs, (0, 0, 0, 0), 3, range(4), range(3))
+
+
+def test_apply_full_span_block(ctx):
+    # blocks spanning the whole time direction keep the antiperiodic wrap link
+    L = (8, 4, 4, 4)
+    _check_apply(ctx, L, 0.125, 0.5, 3, 4, [[8], [4], [2, 2], [4]], (0, 0, 1, 0), 2, range(2), range(2))
+
+
+def test_apply_c2_full_size_sampled(ctx):
+    c = _cfg.C2
+    _check_apply(ctx, c["L"], c["kappa"], c["eps"], c["seed_u"], c["seed_src"], c["segs"], (0, 0, 0, 0), c["nrhs"],
+                 [0, 1, 37, 128, 200, 255], [0, 5, 11])
+
+
+def test_apply_c3_full_size_sampled(ctx):
+    c = _cfg.C3
+    # blocks 0 (12 x 8^3) and 216 (8^4, second time slab) and the last one; two rhs keep host memory small
+    _check_apply(ctx, c["L"], c["kappa"], c["eps"], c["seed_u"], c["seed_src"], c["segs"], (0, 0, 0, 0), 2,
+                 [0, 216, 2159], [0, 1])
+
+
+def test_hop_timer_accounts_bytes(ctx):
+    L = (8, 8, 8, 8)
+    U = synth.gauge_field(L, 0.3, 1)
+    blk = ctx.make_blocks(L, -1, [[4, 4]] * 4)
+    g = ctx.load_gauge(blk, _dev(U), "f32")
+    x = synth.spinor_field(L, 4, 2)[:, _cfg.block_sites(L, geometry.tile_boxes(L, [[4, 4]] * 4))]
+    ctx.timer_enable(True)
+    ctx.timer_reset()
+    ctx.apply_D_block(blk, g, 0.1, "f32", _dev(x))
+    ms, n, nbytes = ctx.timer_read()
+    ctx.timer_enable(False)
+    assert n == 2 and ms > 0
+    # two hops, each reading in + self and writing out (3 half fields), plus the block links
+    V = 8**4
+    expect = 2 * (4 * (V / 2) * 24 * 4 * 3 + blk.inner_links * 18 * 4)
+    assert abs(nbytes - expect) < 1e-6 * expect
