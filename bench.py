@@ -65,7 +65,7 @@ def cpu_baseline(U, src):
     from oracle import wilson
 
     nthr = wilson.num_threads()
-    npairs = max(1, min(nthr, 16))
+    npairs = max(1, min(8 * nthr, 3072))  # about 10-20 s of CPU work
     S = 8**4
     boxes = []
     b = np.zeros((1, npairs * S, 4, 3), dtype=np.complex128)
@@ -78,7 +78,7 @@ def cpu_baseline(U, src):
     _, iters, rel, fails = wilson.solve_many(L, -1, KAPPA, U, np.asarray(boxes), b, tol=TOL, nthreads=nthr)
     dt = time.perf_counter() - t0
     return {"value": npairs / dt, "unit": "solves/s", "cores": nthr, "kind": "oracle",
-            "sample": "%d (block, rhs) pairs of the same workload, one per thread, FP64 eo-BiCGStab with FP64 "
+            "sample": "%d (block, rhs) pairs of the same workload (8 per thread), FP64 eo-BiCGStab with FP64 "
                       "defect correction to 1e-10 (%.1f s wall, %d failed)" % (npairs, dt, fails)}
 
 
@@ -89,7 +89,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--inner", default="f32", choices=["f32", "bf16", "f64"])
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (4 times), to calibrate HBM byte counters")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4, "copies": 4}))
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: the block solves need no communication and this build has no "
               "multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
@@ -131,7 +143,8 @@ def main():
         iters.append(info["inner_iterations"])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    hop_ms, hop_n, hop_bytes = ctx.timer_read(dd.KCLASS_HOP)
+    kclass = {"f64": dd.KCLASS_HOP_F64, "f32": dd.KCLASS_HOP_F32, "bf16": dd.KCLASS_HOP_BF16}[args.inner]
+    hop_ms, hop_n, hop_bytes = ctx.timer_read(kclass)
     ctx.timer_enable(False)
 
     n_solves = blk.n_blocks * NRHS

@@ -215,13 +215,25 @@ dd_status dd_multiboson_action(dd_ctx *ctx, const dd_blocks *blocks, const dd_ga
                                const dd_solve_params *params, double *S_block_dev,
                                double *S_total_host, dd_solve_stats *stats);
 
+/* ------------------------------------------------------------ tuning */
+
+/* Launch-shape overrides (0 = automatic).  DD_TUNE_RHS_GROUP_F64 / _F32: the
+ * number of right-hand sides one thread of the site kernels handles for
+ * FP64 / FP32 spinors (1, 2 or 4; ignored when it does not divide n_rhs).
+ * Results do not depend on it beyond rounding of the fused dot products'
+ * summation order, which is fixed for a given setting. */
+enum { DD_TUNE_RHS_GROUP_F64 = 0, DD_TUNE_RHS_GROUP_F32 = 1 };
+dd_status dd_tune_set(dd_ctx *ctx, int32_t what, int32_t value);
+
 /* ------------------------------------------------------------ timing */
 
 /* Kernel timing for roofline reports: when enabled, every launch of the
  * kernel class is bracketed by HIP events on the context's stream, and its
  * algorithmic bytes (the bytes the method must move, counted per block) are
- * accumulated.  Graph replay is disabled while timing is on. */
-enum { DD_KCLASS_HOP = 0, DD_KCLASS_BLAS = 1, DD_KCLASS_COUNT = 2 };
+ * accumulated.  The hop classes are the stencil kernel in each precision
+ * (FP64; FP32; FP32 spinors with BF16 links).  Graph replay is disabled
+ * while timing is on. */
+enum { DD_KCLASS_HOP_F64 = 0, DD_KCLASS_HOP_F32 = 1, DD_KCLASS_HOP_BF16 = 2, DD_KCLASS_COUNT = 3 };
 dd_status dd_timer_enable(dd_ctx *ctx, int32_t on);
 dd_status dd_timer_reset(dd_ctx *ctx);
 /* total_ms: summed event time; launches: count; alg_bytes: summed bytes. */

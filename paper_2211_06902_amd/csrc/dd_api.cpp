@@ -77,16 +77,17 @@ struct TimedLaunch {
     }
 };
 
-const TileTable *tiles_for(dd_ctx *ctx, dd_blocks *B, int nr, hipError_t *err)
+const TileTable *tiles_for(dd_ctx *ctx, dd_blocks *B, int nr, int g, hipError_t *err)
 {
     *err = hipSuccess;
-    auto it = B->tiles.find(nr);
+    const int key = 8 * nr + g;
+    auto it = B->tiles.find(key);
     if (it != B->tiles.end()) return &it->second;
     TileTable tt;
     tt.blk_tile0.assign(B->nb + 1, 0);
     std::vector<int32_t> tb;
     for (int b = 0; b < B->nb; b++) {
-        const int64_t items = (int64_t)B->shapes[B->shape_of[b]].h * nr;
+        const int64_t items = (int64_t)B->shapes[B->shape_of[b]].h * (nr / g);
         const int nt = (int)((items + kTile - 1) / kTile);
         tt.blk_tile0[b + 1] = tt.blk_tile0[b] + nt;
         for (int t = 0; t < nt; t++) tb.push_back(b);
@@ -95,10 +96,25 @@ const TileTable *tiles_for(dd_ctx *ctx, dd_blocks *B, int nr, hipError_t *err)
     if ((*err = upload(&tt.d_tile_block, tb)) != hipSuccess) return nullptr;
     if ((*err = upload(&tt.d_blk_tile0, tt.blk_tile0)) != hipSuccess) return nullptr;
     (void)ctx;
-    return &(B->tiles[nr] = tt);
+    return &(B->tiles[key] = tt);
 }
 
-BlkArgs blk_args(const dd_blocks *B, const TileTable *tt, int nr)
+// Right-hand sides per thread for a spinor precision (the largest power of
+// two up to the default below that divides n_rhs).  A context override
+// (dd_tune_set) takes precedence when it divides n_rhs.
+int rhs_group(const dd_ctx *ctx, int nr, dd_prec sp)
+{
+    const int forced = ctx ? ctx->rhs_group[sp == DD_F64 ? 0 : 1] : 0;
+    if (forced > 0 && nr % forced == 0) return forced;
+    // FP32: two rhs per thread halve the link loads and keep 3 waves per SIMD
+    // (four need more than 256 VGPRs); FP64: one rhs per thread (two need 224).
+    const int want = sp == DD_F64 ? 1 : 2;
+    for (int g = want; g > 1; g >>= 1)
+        if (nr % g == 0) return g;
+    return 1;
+}
+
+BlkArgs blk_args(const dd_blocks *B, const TileTable *tt, int nr, int g)
 {
     BlkArgs a;
     a.tile_block = tt->d_tile_block;
@@ -110,6 +126,7 @@ BlkArgs blk_args(const dd_blocks *B, const TileTable *tt, int nr)
     a.ntiles = tt->ntiles;
     a.n_rhs = nr;
     a.nb = B->nb;
+    a.g = g;
     return a;
 }
 
@@ -135,7 +152,7 @@ double hop_bytes(const dd_blocks *B, int nr, dd_prec prec, int extra_vectors)
 hipError_t run_hop(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const HopArgs &ha, dd_prec prec)
 {
     const int extra = (ha.self != nullptr) + (ha.add != nullptr) + (ha.aux != nullptr);
-    TimedLaunch tl(ctx, DD_KCLASS_HOP, hop_bytes(B, ba.n_rhs, prec, extra));
+    TimedLaunch tl(ctx, DD_KCLASS_HOP_F64 + (int)prec, hop_bytes(B, ba.n_rhs, prec, extra));
     return launch_hop(ba, ha, prec, ctx->stream);
 }
 
@@ -209,6 +226,7 @@ hipError_t enter(dd_ctx *ctx)
 {
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return e;
+    (void)hipGetLastError();  // drop a stale error left by unrelated runtime calls
     hipEvent_t ev;
     if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
     if ((e = hipEventRecord(ev, ctx->user_stream)) == hipSuccess) e = hipStreamWaitEvent(ctx->stream, ev, 0);
@@ -248,10 +266,11 @@ dd_status make_from_boxes(dd_ctx *ctx, const int32_t L[4], int32_t time_bc, int 
 {
     if (!L || !out || (n > 0 && !boxes)) return fail(ctx, DD_EINVAL, "null argument");
     *out = nullptr;
-    if (ctx && hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, DD_EDEVICE, "hipSetDevice failed");
+    if (ctx && enter(ctx) != hipSuccess) return fail(ctx, DD_EDEVICE, "hipSetDevice failed");
     dd_blocks *B = new (std::nothrow) dd_blocks();
     if (!B) return fail(ctx, DD_ENOMEM, "out of host memory");
     B->ctx = ctx;
+    B->device = ctx ? ctx->device : -1;
     int Li[4] = {L[0], L[1], L[2], L[3]};
     const std::string msg = build_geometry(B, Li, time_bc, n, boxes, inner);
     if (!msg.empty()) {
@@ -356,7 +375,7 @@ dd_status dd_make_blocks_boxes(dd_ctx *ctx, const int32_t L[4], int32_t time_bc,
 dd_status dd_free_blocks(dd_blocks *B)
 {
     if (!B) return DD_EINVAL;
-    if (B->ctx) hipSetDevice(B->ctx->device);
+    if (B->device >= 0) hipSetDevice(B->device);
     void *ptrs[] = {B->d_nbr, B->d_perm, B->d_soff, B->d_h, B->d_nbr_off, B->d_perm_off,
                     B->d_origin, B->d_ext, B->d_bnd, B->d_boff};
     for (void *p : ptrs)
@@ -419,6 +438,7 @@ dd_status dd_load_gauge(dd_ctx *ctx, const dd_blocks *B, const void *U_dev, dd_p
     dd_gauge *G = new (std::nothrow) dd_gauge();
     if (!G) return fail(ctx, DD_ENOMEM, "out of host memory");
     G->ctx = ctx;
+    G->device = ctx->device;
     G->blocks = B;
     G->low = low_prec;
     const size_t nl = (size_t)B->soff[B->nb] * 72;
@@ -445,7 +465,7 @@ dd_status dd_load_gauge(dd_ctx *ctx, const dd_blocks *B, const void *U_dev, dd_p
 dd_status dd_free_gauge(dd_gauge *G)
 {
     if (!G) return DD_EINVAL;
-    if (G->ctx) hipSetDevice(G->ctx->device);
+    hipSetDevice(G->device);
     if (G->d_u64) hipFree(G->d_u64);
     if (G->d_u32) hipFree(G->d_u32);
     if (G->d_ubf) hipFree(G->d_ubf);
@@ -478,10 +498,11 @@ dd_status dd_apply_D_block(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, 
     dd_blocks *B = const_cast<dd_blocks *>(Bc);
     HIPCHECK(ctx, enter(ctx));
     hipError_t e;
-    const TileTable *tt = tiles_for(ctx, B, n_rhs, &e);
-    if (!tt) return fail(ctx, DD_EDEVICE, std::string("tile tables: ") + hipGetErrorString(e));
-    const BlkArgs ba = blk_args(B, tt, n_rhs);
     const dd_prec sp = prec == DD_F64 ? DD_F64 : DD_F32;
+    const int g = rhs_group(ctx, n_rhs, sp);
+    const TileTable *tt = tiles_for(ctx, B, n_rhs, g, &e);
+    if (!tt) return fail(ctx, DD_EDEVICE, std::string("tile tables: ") + hipGetErrorString(e));
+    const BlkArgs ba = blk_args(B, tt, n_rhs, g);
     const size_t half = (size_t)(B->soff[B->nb] / 2) * 24 * n_rhs * prec_bytes(sp);
     void *xe = workspace(ctx, "ap_xe", half, &e);
     void *xo = xe ? workspace(ctx, "ap_xo", half, &e) : nullptr;
@@ -501,6 +522,17 @@ dd_status dd_apply_D_block(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, 
 }
 
 // ------------------------------------------------------------------ timing
+
+dd_status dd_tune_set(dd_ctx *ctx, int32_t what, int32_t value)
+{
+    if (!ctx) return DD_EINVAL;
+    if (what != DD_TUNE_RHS_GROUP_F64 && what != DD_TUNE_RHS_GROUP_F32)
+        return fail(ctx, DD_EINVAL, "unknown tuning knob");
+    if (value != 0 && value != 1 && value != 2 && value != 4)
+        return fail(ctx, DD_EINVAL, "rhs group must be 0 (automatic), 1, 2 or 4");
+    ctx->rhs_group[what] = value;
+    return DD_OK;
+}
 
 dd_status dd_timer_enable(dd_ctx *ctx, int32_t on)
 {

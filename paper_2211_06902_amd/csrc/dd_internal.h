@@ -12,7 +12,8 @@
 
 namespace dd {
 
-// Work items (site, rhs) handled by one workgroup of the site kernels.
+// Threads per workgroup of the site kernels; each thread handles one site and
+// a group of right-hand sides, so a tile covers kTile (site, rhs group) items.
 constexpr int kTile = 256;
 // Largest number of right-hand sides per call (a tile must hold every rhs).
 constexpr int kMaxRhs = 64;
@@ -43,6 +44,7 @@ struct dd_ctx {
     std::map<std::string, dd::DevBuf> ws;  // named, grow-only workspaces
     bool timing = false;
     dd::Timer timers[DD_KCLASS_COUNT];
+    int rhs_group[2] = {0, 0};  // forced rhs per thread for FP64 / FP32 spinors (0 = automatic)
 };
 
 namespace dd {
@@ -69,7 +71,8 @@ struct TileTable {
 }  // namespace dd
 
 struct dd_blocks {
-    dd_ctx *ctx = nullptr;
+    dd_ctx *ctx = nullptr;  // creating context (identity only; may be destroyed first)
+    int device = -1;        // device holding the tables (-1: host tables only)
     int L[4] = {0, 0, 0, 0};
     int tbc = -1;
     int nb = 0;
@@ -94,11 +97,12 @@ struct dd_blocks {
     int32_t *d_ext = nullptr;       // [nb][4]
     int32_t *d_bnd = nullptr;       // [total bnd] box-local canonical index
     int64_t *d_boff = nullptr;      // [nb+1]
-    std::map<int, dd::TileTable> tiles;  // keyed by n_rhs
+    std::map<int, dd::TileTable> tiles;  // keyed by 8 * n_rhs + rhs per thread
 };
 
 struct dd_gauge {
-    dd_ctx *ctx = nullptr;
+    dd_ctx *ctx = nullptr;  // creating context (identity only; may be destroyed first)
+    int device = 0;
     const dd_blocks *blocks = nullptr;
     dd_prec low = DD_F64;
     double *d_u64 = nullptr;     // [total_sites][4][18]
@@ -121,6 +125,7 @@ struct BlkArgs {
     int ntiles;
     int n_rhs;
     int nb;  // number of blocks (pair = rhs * nb + block)
+    int g;   // right-hand sides per thread (1, 2 or 4; divides n_rhs)
 };
 
 enum DotMode { kDotNone = 0, kDotAuxOut = 1, kDotOutSelfOutOut = 2, kDotOutOut = 3 };

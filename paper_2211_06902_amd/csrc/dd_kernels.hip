@@ -159,148 +159,291 @@ __device__ __forceinline__ void hop_term(AC acc[24], const AC psi[24], const AC 
     }
 }
 
-template <typename SP, typename AC>
-__device__ __forceinline__ void load_spinor(const SP *p, int64_t cs, AC psi[24])
+// ------------------------------------------------- G right-hand sides per thread
+//
+// A thread owns one site and G consecutive right-hand sides (G | n_rhs), so
+// each link it loads serves G spinors and every component is one vector load
+// of G contiguous values (16 bytes for 4 floats or 2 doubles).
+
+template <typename T, int G>
+__device__ __forceinline__ void ldv(const T *p, T (&v)[G])
 {
+    constexpr int B = (int)sizeof(T) * G;
+    if constexpr (B % 16 == 0) {
 #pragma unroll
-    for (int c = 0; c < 24; c++) psi[c] = (AC)p[c * cs];
+        for (int k = 0; k < B / 16; k++) {
+            const uint4 q = reinterpret_cast<const uint4 *>(p)[k];
+            __builtin_memcpy(reinterpret_cast<char *>(v) + 16 * k, &q, 16);
+        }
+    } else if constexpr (B == 8) {
+        const uint2 q = *reinterpret_cast<const uint2 *>(p);
+        __builtin_memcpy(v, &q, 8);
+    } else {
+#pragma unroll
+        for (int j = 0; j < G; j++) v[j] = p[j];
+    }
 }
 
-template <int MU, typename SP, typename LK, typename AC>
-__device__ __forceinline__ void hop_dir(AC acc[24], const int32_t *nb, const SP *in, int64_t cs, int nr,
+template <typename T, int G>
+__device__ __forceinline__ void stv(T *p, const T (&v)[G])
+{
+    constexpr int B = (int)sizeof(T) * G;
+    if constexpr (B % 16 == 0) {
+#pragma unroll
+        for (int k = 0; k < B / 16; k++) {
+            uint4 q;
+            __builtin_memcpy(&q, reinterpret_cast<const char *>(v) + 16 * k, 16);
+            reinterpret_cast<uint4 *>(p)[k] = q;
+        }
+    } else if constexpr (B == 8) {
+        uint2 q;
+        __builtin_memcpy(&q, v, 8);
+        *reinterpret_cast<uint2 *>(p) = q;
+    } else {
+#pragma unroll
+        for (int j = 0; j < G; j++) p[j] = v[j];
+    }
+}
+
+// (tile, thread) -> block, site, rhs group
+struct Item {
+    int b, site, rg, tile, titem0, ng;
+    int64_t off, cs;
+    bool live;
+};
+
+__device__ __forceinline__ Item item_of(const BlkArgs &ba)
+{
+    Item it;
+    it.tile = xcd_tile(blockIdx.x, ba.ntiles);
+    it.b = ba.tile_block[it.tile];
+    const int nr = ba.n_rhs;
+    it.ng = nr / ba.g;
+    const int hb = ba.h[it.b];
+    const int titems = hb * it.ng;
+    it.titem0 = (it.tile - ba.blk_tile0[it.b]) * kTile;
+    const int titem = it.titem0 + (int)threadIdx.x;
+    it.live = titem < titems;
+    it.site = it.live ? titem / it.ng : 0;
+    it.rg = it.live ? titem - it.site * it.ng : 0;
+    it.off = (ba.soff[it.b] >> 1) * 24 * nr + (int64_t)it.site * nr + (int64_t)it.rg * ba.g;
+    it.cs = (int64_t)hb * nr;
+    return it;
+}
+
+// Per-(tile, rhs) sums of up to kNRed values; every thread of the tile calls it.
+template <int G>
+__device__ __forceinline__ void tile_reduce(double (*red)[kTile], const double (&dv)[G][kNRed], int nred,
+                                            double *partial, const Item &it, int nr)
+{
+    for (int k = 0; k < nred; k++) {
+#pragma unroll
+        for (int j = 0; j < G; j++) red[j][threadIdx.x] = dv[j][k];
+        __syncthreads();
+        const int t = threadIdx.x;
+        if (t < nr) {
+            const int q = t / G, jj = t - (t / G) * G;
+            const int start = ((q - it.titem0 % it.ng) % it.ng + it.ng) % it.ng;
+            double s = 0;
+            for (int m = start; m < kTile; m += it.ng) s += red[jj][m];
+            partial[((int64_t)it.tile * nr + t) * kNRed + k] = s;
+        }
+        __syncthreads();
+    }
+}
+
+// acc[j] += sg * (1 -/+ gamma_mu) W psi_j(idx) for the G rhs, accumulating the
+// colour contributions of the projected half spinor straight into acc.
+template <int MU, bool FWD, typename SP, typename AC, int G>
+__device__ __forceinline__ void hop_term_g(AC (&acc)[G][24], const SP *in, int64_t cs, int64_t site_off,
+                                           const AC (&u)[18], AC sg)
+{
+    using P = Proj<MU, FWD>;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        SP v[4][2][G];
+#pragma unroll
+        for (int sp = 0; sp < 4; sp++)
+#pragma unroll
+            for (int ri = 0; ri < 2; ri++) ldv<SP, G>(in + (2 * (3 * sp + c) + ri) * cs + site_off, v[sp][ri]);
+#pragma unroll
+        for (int j = 0; j < G; j++) {
+            AC h[2][2];
+            AC re, im;
+            cmul_code<P::a0>((AC)v[P::pi0][0][j], (AC)v[P::pi0][1][j], re, im);
+            h[0][0] = sg * ((AC)v[0][0][j] + re);
+            h[0][1] = sg * ((AC)v[0][1][j] + im);
+            cmul_code<P::a1>((AC)v[P::pi1][0][j], (AC)v[P::pi1][1][j], re, im);
+            h[1][0] = sg * ((AC)v[1][0][j] + re);
+            h[1][1] = sg * ((AC)v[1][1][j] + im);
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                AC ur, ui;
+                if constexpr (FWD) {  // U[a][c]
+                    ur = u[2 * (3 * a + c)];
+                    ui = u[2 * (3 * a + c) + 1];
+                } else {              // conj(U[c][a])
+                    ur = u[2 * (3 * c + a)];
+                    ui = -u[2 * (3 * c + a) + 1];
+                }
+                AC d[2][2];
+#pragma unroll
+                for (int s = 0; s < 2; s++) {
+                    d[s][0] = ur * h[s][0] - ui * h[s][1];
+                    d[s][1] = ur * h[s][1] + ui * h[s][0];
+                }
+                acc[j][2 * a] += d[0][0];
+                acc[j][2 * a + 1] += d[0][1];
+                acc[j][2 * (3 + a)] += d[1][0];
+                acc[j][2 * (3 + a) + 1] += d[1][1];
+                cmul_code<P::b0>(d[P::s0][0], d[P::s0][1], re, im);
+                acc[j][2 * (6 + a)] += re;
+                acc[j][2 * (6 + a) + 1] += im;
+                cmul_code<P::b1>(d[P::s1][0], d[P::s1][1], re, im);
+                acc[j][2 * (9 + a)] += re;
+                acc[j][2 * (9 + a) + 1] += im;
+            }
+        }
+    }
+}
+
+template <int MU, typename SP, typename LK, typename AC, int G>
+__device__ __forceinline__ void hop_dir(AC (&acc)[G][24], const int32_t (&nb)[8], const SP *in, int64_t cs, int nr,
                                         const LK *lk, int slot_self, int other0)
 {
     const int32_t ef = nb[2 * MU];
     if (ef >= 0) {
         const int idx = ef & kNbrMask;
         const AC sg = (ef & kNbrSign) ? (AC)-1 : (AC)1;
-        AC psi[24], u[18];
-        load_spinor(in + (int64_t)idx * nr, cs, psi);
+        AC u[18];
         load_link(lk + ((int64_t)slot_self * 4 + MU) * 18, u);
-        hop_term<MU, true>(acc, psi, u, sg);
+        hop_term_g<MU, true, SP, AC, G>(acc, in, cs, (int64_t)idx * nr, u, sg);
     }
     const int32_t eb = nb[2 * MU + 1];
     if (eb >= 0) {
         const int idx = eb & kNbrMask;
         const AC sg = (eb & kNbrSign) ? (AC)-1 : (AC)1;
-        AC psi[24], u[18];
-        load_spinor(in + (int64_t)idx * nr, cs, psi);
+        AC u[18];
         load_link(lk + ((int64_t)(other0 + idx) * 4 + MU) * 18, u);
-        hop_term<MU, false>(acc, psi, u, sg);
-    }
-}
-
-// per-(tile, rhs) reduction of up to kNRed values; every thread must call it
-__device__ __forceinline__ void tile_reduce(double (*red)[kTile], const double v[kNRed], int nred,
-                                            double *partial, int tile, int64_t item0, int nr)
-{
-    for (int k = 0; k < nred; k++) red[k][threadIdx.x] = v[k];
-    __syncthreads();
-    const int j = threadIdx.x;
-    if (j < nr) {
-        const int rj = (int)((item0 + j) % nr);
-        for (int k = 0; k < nred; k++) {
-            double s = 0;
-            for (int m = j; m < kTile; m += nr) s += red[k][m];
-            partial[((int64_t)tile * nr + rj) * kNRed + k] = s;
-        }
+        hop_term_g<MU, false, SP, AC, G>(acc, in, cs, (int64_t)idx * nr, u, sg);
     }
 }
 
 // --------------------------------------------------------------- hop
 
-template <typename SP, typename LK, typename AC>
+template <typename SP, typename LK, typename AC, int G>
 __global__ void __launch_bounds__(kTile) k_hop(BlkArgs ba, HopArgs ha)
 {
-    __shared__ double red[kNRed][kTile];
-    const int tile = xcd_tile(blockIdx.x, ba.ntiles);
-    const int b = ba.tile_block[tile];
+    __shared__ double red[G][kTile];
+    const Item it = item_of(ba);
     const int nr = ba.n_rhs;
-    const int hb = ba.h[b];
-    const int64_t items = (int64_t)hb * nr;
-    const int64_t item0 = (int64_t)(tile - ba.blk_tile0[b]) * kTile;
-    const int64_t item = item0 + threadIdx.x;
-    const bool live = item < items;
-    const int64_t base = (ba.soff[b] >> 1) * 24 * nr;
     const int p = ha.parity;
-    double dv[kNRed] = {0, 0, 0, 0};
-    if (live) {
-        const int site = (int)(item / nr);
-        const int r = (int)(item - (int64_t)site * nr);
-        const int32_t *nb = ba.nbr + ba.nbr_off[b] + (int64_t)(p * hb + site) * 8;
-        const LK *lk = reinterpret_cast<const LK *>(ha.links) + ba.soff[b] * 72;
-        const SP *in = reinterpret_cast<const SP *>(ha.in) + base + r;
-        int32_t nbl[8];
-        {
-            const int4 *q = reinterpret_cast<const int4 *>(nb);
-            const int4 a0 = q[0], a1 = q[1];
-            nbl[0] = a0.x; nbl[1] = a0.y; nbl[2] = a0.z; nbl[3] = a0.w;
-            nbl[4] = a1.x; nbl[5] = a1.y; nbl[6] = a1.z; nbl[7] = a1.w;
-        }
-        AC acc[24];
+    double dv[G][kNRed];
 #pragma unroll
-        for (int c = 0; c < 24; c++) acc[c] = 0;
-        const int slot = p * hb + site;
+    for (int j = 0; j < G; j++)
+#pragma unroll
+        for (int k = 0; k < kNRed; k++) dv[j][k] = 0;
+    if (it.live) {
+        const int hb = ba.h[it.b];
+        const int32_t *nbp = ba.nbr + ba.nbr_off[it.b] + (int64_t)(p * hb + it.site) * 8;
+        int32_t nb[8];
+        {
+            const int4 *q = reinterpret_cast<const int4 *>(nbp);
+            const int4 a0 = q[0], a1 = q[1];
+            nb[0] = a0.x; nb[1] = a0.y; nb[2] = a0.z; nb[3] = a0.w;
+            nb[4] = a1.x; nb[5] = a1.y; nb[6] = a1.z; nb[7] = a1.w;
+        }
+        const LK *lk = reinterpret_cast<const LK *>(ha.links) + ba.soff[it.b] * 72;
+        // input pointer at this block and rhs group; neighbour sites add idx * nr
+        const SP *in = reinterpret_cast<const SP *>(ha.in) + (ba.soff[it.b] >> 1) * 24 * nr + (int64_t)it.rg * G;
+        AC acc[G][24];
+#pragma unroll
+        for (int j = 0; j < G; j++)
+#pragma unroll
+            for (int c = 0; c < 24; c++) acc[j][c] = 0;
+        const int slot = p * hb + it.site;
         const int other0 = (1 - p) * hb;
-        hop_dir<0>(acc, nbl, in, items, nr, lk, slot, other0);
-        hop_dir<1>(acc, nbl, in, items, nr, lk, slot, other0);
-        hop_dir<2>(acc, nbl, in, items, nr, lk, slot, other0);
-        hop_dir<3>(acc, nbl, in, items, nr, lk, slot, other0);
+        hop_dir<0, SP, LK, AC, G>(acc, nb, in, it.cs, nr, lk, slot, other0);
+        hop_dir<1, SP, LK, AC, G>(acc, nb, in, it.cs, nr, lk, slot, other0);
+        hop_dir<2, SP, LK, AC, G>(acc, nb, in, it.cs, nr, lk, slot, other0);
+        hop_dir<3, SP, LK, AC, G>(acc, nb, in, it.cs, nr, lk, slot, other0);
 
-        const int64_t off = base + item;
-        SP *out = reinterpret_cast<SP *>(ha.out) + off;
-        const SP *self = ha.self ? reinterpret_cast<const SP *>(ha.self) + off : nullptr;
-        const SP *add = ha.add ? reinterpret_cast<const SP *>(ha.add) + off : nullptr;
-        const SP *aux = ha.aux ? reinterpret_cast<const SP *>(ha.aux) + off : nullptr;
+        SP *out = reinterpret_cast<SP *>(ha.out) + it.off;
+        const SP *self = ha.self ? reinterpret_cast<const SP *>(ha.self) + it.off : nullptr;
+        const SP *add = ha.add ? reinterpret_cast<const SP *>(ha.add) + it.off : nullptr;
+        const SP *aux = ha.aux ? reinterpret_cast<const SP *>(ha.aux) + it.off : nullptr;
         const AC ch = (AC)ha.c_hop, cself = (AC)ha.c_self, cadd = (AC)ha.c_add;
 #pragma unroll
         for (int k = 0; k < 12; k++) {
-            SP o[2];
-            double sv[2] = {0, 0};
+            SP o[2][G], sv[2][G], av[2][G];
 #pragma unroll
             for (int ri = 0; ri < 2; ri++) {
                 const int c = 2 * k + ri;
-                AC v = ch * acc[c];
+                AC v[G];
+#pragma unroll
+                for (int j = 0; j < G; j++) v[j] = ch * acc[j][c];
                 if (self) {
-                    const SP s = self[c * items];
-                    sv[ri] = (double)s;
-                    v += cself * (AC)s;
+                    ldv<SP, G>(self + c * it.cs, sv[ri]);
+#pragma unroll
+                    for (int j = 0; j < G; j++) v[j] += cself * (AC)sv[ri][j];
                 }
-                if (add) v += cadd * (AC)add[c * items];
-                o[ri] = (SP)v;
-                out[c * items] = o[ri];
+                if (add) {
+                    SP w[G];
+                    ldv<SP, G>(add + c * it.cs, w);
+#pragma unroll
+                    for (int j = 0; j < G; j++) v[j] += cadd * (AC)w[j];
+                }
+#pragma unroll
+                for (int j = 0; j < G; j++) o[ri][j] = (SP)v[j];
+                stv<SP, G>(out + c * it.cs, o[ri]);
+                if (ha.dot_mode == kDotAuxOut) ldv<SP, G>(aux + c * it.cs, av[ri]);
             }
-            const double ore = (double)o[0], oim = (double)o[1];
-            if (ha.dot_mode == kDotAuxOut) {
-                const double are = (double)aux[(2 * k) * items], aim = (double)aux[(2 * k + 1) * items];
-                dv[0] += are * ore + aim * oim;
-                dv[1] += are * oim - aim * ore;
-            } else if (ha.dot_mode == kDotOutSelfOutOut) {
-                dv[0] += ore * sv[0] + oim * sv[1];
-                dv[1] += ore * sv[1] - oim * sv[0];
-                dv[2] += ore * ore + oim * oim;
-            } else if (ha.dot_mode == kDotOutOut) {
-                dv[0] += ore * ore + oim * oim;
+#pragma unroll
+            for (int j = 0; j < G; j++) {
+                const double ore = (double)o[0][j], oim = (double)o[1][j];
+                if (ha.dot_mode == kDotAuxOut) {
+                    const double are = (double)av[0][j], aim = (double)av[1][j];
+                    dv[j][0] += are * ore + aim * oim;
+                    dv[j][1] += are * oim - aim * ore;
+                } else if (ha.dot_mode == kDotOutSelfOutOut) {
+                    const double sre = (double)sv[0][j], sim = (double)sv[1][j];
+                    dv[j][0] += ore * sre + oim * sim;
+                    dv[j][1] += ore * sim - oim * sre;
+                    dv[j][2] += ore * ore + oim * oim;
+                } else if (ha.dot_mode == kDotOutOut) {
+                    dv[j][0] += ore * ore + oim * oim;
+                }
             }
         }
     }
     if (ha.dot_mode != kDotNone) {
         const int nred = ha.dot_mode == kDotAuxOut ? 2 : (ha.dot_mode == kDotOutSelfOutOut ? 3 : 1);
-        tile_reduce(red, dv, nred, ha.partial, tile, item0, nr);
+        tile_reduce<G>(red, dv, nred, ha.partial, it, nr);
     }
+}
+
+template <int G>
+static hipError_t launch_hop_g(const BlkArgs &ba, const HopArgs &ha, dd_prec prec, hipStream_t s)
+{
+    dim3 g(ba.ntiles), t(kTile);
+    switch (prec) {
+    case DD_F64: hipLaunchKernelGGL((k_hop<double, double, double, G>), g, t, 0, s, ba, ha); break;
+    case DD_F32: hipLaunchKernelGGL((k_hop<float, float, float, G>), g, t, 0, s, ba, ha); break;
+    case DD_BF16: hipLaunchKernelGGL((k_hop<float, uint16_t, float, G>), g, t, 0, s, ba, ha); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_hop(const BlkArgs &ba, const HopArgs &ha, dd_prec prec, hipStream_t s)
 {
     if (ba.ntiles <= 0) return hipSuccess;
-    dim3 g(ba.ntiles), t(kTile);
-    switch (prec) {
-    case DD_F64: hipLaunchKernelGGL((k_hop<double, double, double>), g, t, 0, s, ba, ha); break;
-    case DD_F32: hipLaunchKernelGGL((k_hop<float, float, float>), g, t, 0, s, ba, ha); break;
-    case DD_BF16: hipLaunchKernelGGL((k_hop<float, uint16_t, float>), g, t, 0, s, ba, ha); break;
+    switch (ba.g) {
+    case 1: return launch_hop_g<1>(ba, ha, prec, s);
+    case 2: return launch_hop_g<2>(ba, ha, prec, s);
+    case 4: return launch_hop_g<4>(ba, ha, prec, s);
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- packing
@@ -400,27 +543,36 @@ hipError_t launch_pack_gauge(const dd_blocks *B, const double *U, dd_prec prec, 
     return hipGetLastError();
 }
 
-// boundary layout [r][q][24] (q = block site, box-local canonical) <-> half fields
+// boundary layout [r][q][24] (q = block site, box-local canonical) <-> half fields.
+// Thread t -> (eo block site q = t / n_rhs, rhs r = t % n_rhs): consecutive
+// threads write consecutive half-field addresses; each thread moves one
+// 192-byte spinor record of the boundary layout with 16-byte accesses.
 template <typename SP, bool PACK>
 __global__ void __launch_bounds__(256) k_spinor_xfer(PackGeom g, double *ext_f, SP *even, SP *odd,
                                                     int nr, int64_t total)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total * nr) return;
-    const int r = (int)(t / total);
-    const int64_t q = t - (int64_t)r * total;  // block site in eo order
+    const int64_t q = t / nr;  // block site in eo order
+    const int r = (int)(t - q * nr);
     const int b = find_block(g.soff, g.nb, q);
     const int s = (int)(q - g.soff[b]);
     const int hb = g.h[b];
     const int p = s >= hb;
     const int site = s - p * hb;
     const int y = g.perm[g.perm_off[b] + s];
-    double *e = ext_f + ((int64_t)r * total + g.soff[b] + y) * 24;
+    double2 *e = reinterpret_cast<double2 *>(ext_f + ((int64_t)r * total + g.soff[b] + y) * 24);
     SP *hf = (p ? odd : even) + (g.soff[b] >> 1) * 24 * nr + (int64_t)site * nr + r;
     const int64_t cs = (int64_t)hb * nr;
-    for (int c = 0; c < 24; c++) {
-        if constexpr (PACK) hf[c * cs] = (SP)e[c];
-        else e[c] = (double)hf[c * cs];
+#pragma unroll
+    for (int k = 0; k < 12; k++) {
+        if constexpr (PACK) {
+            const double2 v = e[k];
+            hf[(2 * k) * cs] = (SP)v.x;
+            hf[(2 * k + 1) * cs] = (SP)v.y;
+        } else {
+            e[k] = make_double2((double)hf[(2 * k) * cs], (double)hf[(2 * k + 1) * cs]);
+        }
     }
 }
 
@@ -484,240 +636,351 @@ hipError_t launch_convert(const void *src, dd_prec sp, void *dst, dd_prec dp, in
 
 
 // ------------------------------------------------------ Krylov site kernels
+//
+// Same (site, G rhs) decomposition as the hop.  Pairs that are no longer
+// active keep their x (the update is selected away), everything else is
+// computed unconditionally: pairs never mix, so values of frozen pairs do
+// not reach active ones.
 
-// common prologue of the per-item kernels: tile -> (block, site, rhs, pair)
-struct Item {
-    int b, r, pair, tile;
-    int64_t off, cs, item0;
-    bool live;
-};
-
-__device__ __forceinline__ Item item_of(const BlkArgs &ba)
+template <int G>
+__device__ __forceinline__ void pair_flags(const BlkArgs &ba, const Item &it, const int32_t *active, bool (&act)[G],
+                                           bool &any)
 {
-    Item it;
-    it.tile = xcd_tile(blockIdx.x, ba.ntiles);
-    it.b = ba.tile_block[it.tile];
-    const int nr = ba.n_rhs;
-    const int64_t items = (int64_t)ba.h[it.b] * nr;
-    it.item0 = (int64_t)(it.tile - ba.blk_tile0[it.b]) * kTile;
-    const int64_t item = it.item0 + threadIdx.x;
-    it.live = item < items;
-    const int site = it.live ? (int)(item / nr) : 0;
-    it.r = it.live ? (int)(item - (int64_t)site * nr) : 0;
-    it.pair = it.r * ba.nb + it.b;
-    it.off = (ba.soff[it.b] >> 1) * 24 * nr + item;
-    it.cs = items;
-    return it;
+    any = false;
+#pragma unroll
+    for (int j = 0; j < G; j++) {
+        act[j] = it.live && active[(it.rg * G + j) * ba.nb + it.b] != 0;
+        any = any || act[j];
+    }
 }
 
 // x_p += e_p for the pairs still above tolerance (FP64 accumulator)
-template <typename SE>
+template <typename SE, int G>
 __global__ void __launch_bounds__(kTile) k_accum(BlkArgs ba, double *x, const SE *e, const int32_t *active)
 {
     const Item it = item_of(ba);
-    if (!it.live || !active[it.pair]) return;
-#pragma unroll 4
-    for (int c = 0; c < 24; c++) x[it.off + c * it.cs] += (double)e[it.off + c * it.cs];
-}
-
-hipError_t launch_accum(const BlkArgs &ba, double *x, const void *e, dd_prec ep, const int32_t *active,
-                        hipStream_t s)
-{
-    if (ba.ntiles <= 0) return hipSuccess;
-    dim3 g(ba.ntiles), t(kTile);
-    if (ep == DD_F64)
-        hipLaunchKernelGGL(k_accum<double>, g, t, 0, s, ba, x, (const double *)e, active);
-    else
-        hipLaunchKernelGGL(k_accum<float>, g, t, 0, s, ba, x, (const float *)e, active);
-    return hipGetLastError();
+    bool act[G], any;
+    pair_flags<G>(ba, it, active, act, any);
+    if (!any) return;
+    for (int c = 0; c < 24; c++) {
+        double xv[G];
+        SE ev[G];
+        ldv<double, G>(x + it.off + c * it.cs, xv);
+        ldv<SE, G>(e + it.off + c * it.cs, ev);
+#pragma unroll
+        for (int j = 0; j < G; j++)
+            if (act[j]) xv[j] += (double)ev[j];
+        stv<double, G>(x + it.off + c * it.cs, xv);
+    }
 }
 
 // BiCGStab start: r = rh = p = rhs, x = 0; |rhs|^2 per (tile, rhs)
-template <typename SP>
+template <typename SP, int G>
 __global__ void __launch_bounds__(kTile) k_bicg_init(BlkArgs ba, const SP *rhs, SP *r, SP *rh, SP *p, SP *x,
                                                      double *partial, const int32_t *outer_active)
 {
-    __shared__ double red[kNRed][kTile];
+    __shared__ double red[G][kTile];
     const Item it = item_of(ba);
-    double dv[kNRed] = {0, 0, 0, 0};
-    if (it.live && outer_active[it.pair]) {
+    double dv[G][kNRed] = {};
+    bool act[G], any;
+    pair_flags<G>(ba, it, outer_active, act, any);
+    if (any) {
         for (int c = 0; c < 24; c++) {
             const int64_t i = it.off + c * it.cs;
-            const SP v = rhs[i];
-            r[i] = v;
-            rh[i] = v;
-            p[i] = v;
-            x[i] = (SP)0;
-            dv[0] += (double)v * (double)v;
+            SP v[G], z[G];
+            ldv<SP, G>(rhs + i, v);
+#pragma unroll
+            for (int j = 0; j < G; j++) {
+                z[j] = (SP)0;
+                dv[j][0] += act[j] ? (double)v[j] * (double)v[j] : 0.0;
+            }
+            stv<SP, G>(r + i, v);
+            stv<SP, G>(rh + i, v);
+            stv<SP, G>(p + i, v);
+            stv<SP, G>(x + i, z);
         }
     }
-    tile_reduce(red, dv, 1, partial, it.tile, it.item0, ba.n_rhs);
+    tile_reduce<G>(red, dv, 1, partial, it, ba.n_rhs);
+}
+
+template <int G>
+__device__ __forceinline__ void load_coef(const double *arr, const BlkArgs &ba, const Item &it, double (&re)[G],
+                                          double (&im)[G])
+{
+#pragma unroll
+    for (int j = 0; j < G; j++) {
+        const int pr = (it.rg * G + j) * ba.nb + it.b;
+        re[j] = arr[2 * pr];
+        im[j] = arr[2 * pr + 1];
+    }
 }
 
 // s = r - alpha v
-template <typename SP>
+template <typename SP, int G>
 __global__ void __launch_bounds__(kTile) k_bicg_s(BlkArgs ba, const SP *r, const SP *v, SP *s, PairState ps)
 {
     const Item it = item_of(ba);
-    if (!it.live || !ps.active[it.pair]) return;
-    const double ar = ps.alpha[2 * it.pair], ai = ps.alpha[2 * it.pair + 1];
-    using AC = SP;
-    const AC a_r = (AC)ar, a_i = (AC)ai;
-#pragma unroll 4
+    bool act[G], any;
+    pair_flags<G>(ba, it, ps.active, act, any);
+    if (!any) return;
+    double ar[G], ai[G];
+    load_coef<G>(ps.alpha, ba, it, ar, ai);
+#pragma unroll 2
     for (int k = 0; k < 12; k++) {
         const int64_t i0 = it.off + (2 * k) * it.cs, i1 = i0 + it.cs;
-        const AC vr = (AC)v[i0], vi = (AC)v[i1];
-        s[i0] = (SP)((AC)r[i0] - (a_r * vr - a_i * vi));
-        s[i1] = (SP)((AC)r[i1] - (a_r * vi + a_i * vr));
+        SP vr[G], vi[G], rr[G], ri[G], sr[G], si[G];
+        ldv<SP, G>(v + i0, vr);
+        ldv<SP, G>(v + i1, vi);
+        ldv<SP, G>(r + i0, rr);
+        ldv<SP, G>(r + i1, ri);
+#pragma unroll
+        for (int j = 0; j < G; j++) {
+            const SP a_r = (SP)ar[j], a_i = (SP)ai[j];
+            sr[j] = rr[j] - (a_r * vr[j] - a_i * vi[j]);
+            si[j] = ri[j] - (a_r * vi[j] + a_i * vr[j]);
+        }
+        stv<SP, G>(s + i0, sr);
+        stv<SP, G>(s + i1, si);
     }
 }
 
-// x += alpha p + omega s;  r = s - omega t;  <rh, r> and |r|^2 per (tile, rhs)
-template <typename SP>
-__global__ void __launch_bounds__(kTile) k_bicg_xr(BlkArgs ba, SP *x, const SP *p, const SP *s, const SP *t,
-                                                   SP *r, const SP *rh, double *partial, PairState ps)
+// x += alpha p + omega s (active pairs);  r = s - omega t;  <rh, r>, |r|^2 per (tile, rhs)
+template <typename SP, int G>
+__global__ void __launch_bounds__(kTile) k_bicg_xr(BlkArgs ba, SP *x, const SP *p, const SP *s, const SP *t, SP *r,
+                                                   const SP *rh, double *partial, PairState ps)
 {
-    __shared__ double red[kNRed][kTile];
+    __shared__ double red[G][kTile];
     const Item it = item_of(ba);
-    double dv[kNRed] = {0, 0, 0, 0};
-    if (it.live && ps.active[it.pair]) {
-        using AC = SP;
-        const AC a_r = (AC)ps.alpha[2 * it.pair], a_i = (AC)ps.alpha[2 * it.pair + 1];
-        const AC w_r = (AC)ps.omega[2 * it.pair], w_i = (AC)ps.omega[2 * it.pair + 1];
-#pragma unroll 2
+    double dv[G][kNRed] = {};
+    bool act[G], any;
+    pair_flags<G>(ba, it, ps.active, act, any);
+    if (any) {
+        double ar[G], ai[G], wr[G], wi[G];
+        load_coef<G>(ps.alpha, ba, it, ar, ai);
+        load_coef<G>(ps.omega, ba, it, wr, wi);
         for (int k = 0; k < 12; k++) {
             const int64_t i0 = it.off + (2 * k) * it.cs, i1 = i0 + it.cs;
-            const AC pr = (AC)p[i0], pi = (AC)p[i1];
-            const AC sr = (AC)s[i0], si = (AC)s[i1];
-            const AC tr = (AC)t[i0], ti = (AC)t[i1];
-            x[i0] = (SP)((AC)x[i0] + (a_r * pr - a_i * pi) + (w_r * sr - w_i * si));
-            x[i1] = (SP)((AC)x[i1] + (a_r * pi + a_i * pr) + (w_r * si + w_i * sr));
-            const SP nr_ = (SP)(sr - (w_r * tr - w_i * ti));
-            const SP ni_ = (SP)(si - (w_r * ti + w_i * tr));
-            r[i0] = nr_;
-            r[i1] = ni_;
-            const double hr = (double)rh[i0], hi = (double)rh[i1];
-            const double rr_ = (double)nr_, ri_ = (double)ni_;
-            dv[0] += hr * rr_ + hi * ri_;
-            dv[1] += hr * ri_ - hi * rr_;
-            dv[2] += rr_ * rr_ + ri_ * ri_;
+            SP pr[G], pi[G], sr[G], si[G], tr[G], ti[G], xr[G], xi[G], nr_[G], ni_[G], hr[G], hi[G];
+            ldv<SP, G>(p + i0, pr);
+            ldv<SP, G>(p + i1, pi);
+            ldv<SP, G>(s + i0, sr);
+            ldv<SP, G>(s + i1, si);
+            ldv<SP, G>(t + i0, tr);
+            ldv<SP, G>(t + i1, ti);
+            ldv<SP, G>(x + i0, xr);
+            ldv<SP, G>(x + i1, xi);
+            ldv<SP, G>(rh + i0, hr);
+            ldv<SP, G>(rh + i1, hi);
+#pragma unroll
+            for (int j = 0; j < G; j++) {
+                const SP a_r = (SP)ar[j], a_i = (SP)ai[j], w_r = (SP)wr[j], w_i = (SP)wi[j];
+                const SP nxr = xr[j] + (a_r * pr[j] - a_i * pi[j]) + (w_r * sr[j] - w_i * si[j]);
+                const SP nxi = xi[j] + (a_r * pi[j] + a_i * pr[j]) + (w_r * si[j] + w_i * sr[j]);
+                xr[j] = act[j] ? nxr : xr[j];
+                xi[j] = act[j] ? nxi : xi[j];
+                nr_[j] = sr[j] - (w_r * tr[j] - w_i * ti[j]);
+                ni_[j] = si[j] - (w_r * ti[j] + w_i * tr[j]);
+                const double a = (double)hr[j], b = (double)hi[j], c = (double)nr_[j], d = (double)ni_[j];
+                dv[j][0] += a * c + b * d;
+                dv[j][1] += a * d - b * c;
+                dv[j][2] += c * c + d * d;
+            }
+            stv<SP, G>(x + i0, xr);
+            stv<SP, G>(x + i1, xi);
+            stv<SP, G>(r + i0, nr_);
+            stv<SP, G>(r + i1, ni_);
         }
     }
-    tile_reduce(red, dv, 3, partial, it.tile, it.item0, ba.n_rhs);
+    tile_reduce<G>(red, dv, 3, partial, it, ba.n_rhs);
 }
 
 // p = r + beta (p - omega v)
-template <typename SP>
+template <typename SP, int G>
 __global__ void __launch_bounds__(kTile) k_bicg_p(BlkArgs ba, const SP *r, const SP *v, SP *p, PairState ps)
 {
     const Item it = item_of(ba);
-    if (!it.live || !ps.active[it.pair]) return;
-    using AC = SP;
-    const AC b_r = (AC)ps.beta[2 * it.pair], b_i = (AC)ps.beta[2 * it.pair + 1];
-    const AC w_r = (AC)ps.omega[2 * it.pair], w_i = (AC)ps.omega[2 * it.pair + 1];
-#pragma unroll 4
+    bool act[G], any;
+    pair_flags<G>(ba, it, ps.active, act, any);
+    if (!any) return;
+    double br[G], bi[G], wr[G], wi[G];
+    load_coef<G>(ps.beta, ba, it, br, bi);
+    load_coef<G>(ps.omega, ba, it, wr, wi);
+#pragma unroll 2
     for (int k = 0; k < 12; k++) {
         const int64_t i0 = it.off + (2 * k) * it.cs, i1 = i0 + it.cs;
-        const AC vr = (AC)v[i0], vi = (AC)v[i1];
-        const AC qr = (AC)p[i0] - (w_r * vr - w_i * vi);
-        const AC qi = (AC)p[i1] - (w_r * vi + w_i * vr);
-        p[i0] = (SP)((AC)r[i0] + (b_r * qr - b_i * qi));
-        p[i1] = (SP)((AC)r[i1] + (b_r * qi + b_i * qr));
+        SP vr[G], vi[G], pr[G], pi[G], rr[G], ri[G];
+        ldv<SP, G>(v + i0, vr);
+        ldv<SP, G>(v + i1, vi);
+        ldv<SP, G>(p + i0, pr);
+        ldv<SP, G>(p + i1, pi);
+        ldv<SP, G>(r + i0, rr);
+        ldv<SP, G>(r + i1, ri);
+#pragma unroll
+        for (int j = 0; j < G; j++) {
+            const SP b_r = (SP)br[j], b_i = (SP)bi[j], w_r = (SP)wr[j], w_i = (SP)wi[j];
+            const SP qr = pr[j] - (w_r * vr[j] - w_i * vi[j]);
+            const SP qi = pi[j] - (w_r * vi[j] + w_i * vr[j]);
+            pr[j] = rr[j] + (b_r * qr - b_i * qi);
+            pi[j] = ri[j] + (b_r * qi + b_i * qr);
+        }
+        stv<SP, G>(p + i0, pr);
+        stv<SP, G>(p + i1, pi);
     }
 }
 
-hipError_t launch_bicg_init(const BlkArgs &ba, dd_prec sp, const void *rhs, void *r, void *rh, void *p,
-                            void *x, double *partial, const int32_t *outer_active, hipStream_t st)
+hipError_t launch_accum(const BlkArgs &ba, double *x, const void *e, dd_prec ep, const int32_t *active,
+                        hipStream_t st)
 {
     if (ba.ntiles <= 0) return hipSuccess;
     dim3 g(ba.ntiles), t(kTile);
-    if (sp == DD_F64)
-        hipLaunchKernelGGL(k_bicg_init<double>, g, t, 0, st, ba, (const double *)rhs, (double *)r, (double *)rh,
-                           (double *)p, (double *)x, partial, outer_active);
-    else
-        hipLaunchKernelGGL(k_bicg_init<float>, g, t, 0, st, ba, (const float *)rhs, (float *)r, (float *)rh,
-                           (float *)p, (float *)x, partial, outer_active);
+    const bool d = ep == DD_F64;
+    switch (ba.g) {
+    case 1:
+        if (d) hipLaunchKernelGGL((k_accum<double, 1>), g, t, 0, st, ba, x, (const double *)e, active);
+        else hipLaunchKernelGGL((k_accum<float, 1>), g, t, 0, st, ba, x, (const float *)e, active);
+        break;
+    case 2:
+        if (d) hipLaunchKernelGGL((k_accum<double, 2>), g, t, 0, st, ba, x, (const double *)e, active);
+        else hipLaunchKernelGGL((k_accum<float, 2>), g, t, 0, st, ba, x, (const float *)e, active);
+        break;
+    case 4:
+        if (d) hipLaunchKernelGGL((k_accum<double, 4>), g, t, 0, st, ba, x, (const double *)e, active);
+        else hipLaunchKernelGGL((k_accum<float, 4>), g, t, 0, st, ba, x, (const float *)e, active);
+        break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_bicg_s(const BlkArgs &ba, dd_prec sp, const void *r, const void *v, void *s,
-                         const PairState &ps, hipStream_t st)
+template <typename SP, int G>
+static void launch_init_t(const BlkArgs &ba, const void *rhs, void *r, void *rh, void *p, void *x, double *partial,
+                          const int32_t *oa, hipStream_t st)
 {
-    if (ba.ntiles <= 0) return hipSuccess;
-    dim3 g(ba.ntiles), t(kTile);
-    if (sp == DD_F64)
-        hipLaunchKernelGGL(k_bicg_s<double>, g, t, 0, st, ba, (const double *)r, (const double *)v, (double *)s, ps);
-    else
-        hipLaunchKernelGGL(k_bicg_s<float>, g, t, 0, st, ba, (const float *)r, (const float *)v, (float *)s, ps);
-    return hipGetLastError();
+    hipLaunchKernelGGL((k_bicg_init<SP, G>), dim3(ba.ntiles), dim3(kTile), 0, st, ba, (const SP *)rhs, (SP *)r,
+                       (SP *)rh, (SP *)p, (SP *)x, partial, oa);
+}
+template <typename SP, int G>
+static void launch_s_t(const BlkArgs &ba, const void *r, const void *v, void *s, const PairState &ps, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_bicg_s<SP, G>), dim3(ba.ntiles), dim3(kTile), 0, st, ba, (const SP *)r, (const SP *)v,
+                       (SP *)s, ps);
+}
+template <typename SP, int G>
+static void launch_xr_t(const BlkArgs &ba, void *x, const void *p, const void *s, const void *t, void *r,
+                        const void *rh, double *partial, const PairState &ps, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_bicg_xr<SP, G>), dim3(ba.ntiles), dim3(kTile), 0, st, ba, (SP *)x, (const SP *)p,
+                       (const SP *)s, (const SP *)t, (SP *)r, (const SP *)rh, partial, ps);
+}
+template <typename SP, int G>
+static void launch_p_t(const BlkArgs &ba, const void *r, const void *v, void *p, const PairState &ps, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_bicg_p<SP, G>), dim3(ba.ntiles), dim3(kTile), 0, st, ba, (const SP *)r, (const SP *)v,
+                       (SP *)p, ps);
+}
+
+#define DD_DISPATCH(FN, SPREC, ...)                                                   \
+    do {                                                                              \
+        if (ba.ntiles <= 0) return hipSuccess;                                        \
+        const bool d_ = (SPREC) == DD_F64;                                            \
+        switch (ba.g) {                                                               \
+        case 1: if (d_) FN<double, 1>(__VA_ARGS__); else FN<float, 1>(__VA_ARGS__); break; \
+        case 2: if (d_) FN<double, 2>(__VA_ARGS__); else FN<float, 2>(__VA_ARGS__); break; \
+        case 4: if (d_) FN<double, 4>(__VA_ARGS__); else FN<float, 4>(__VA_ARGS__); break; \
+        default: return hipErrorInvalidValue;                                         \
+        }                                                                             \
+        return hipGetLastError();                                                     \
+    } while (0)
+
+hipError_t launch_bicg_init(const BlkArgs &ba, dd_prec sp, const void *rhs, void *r, void *rh, void *p, void *x,
+                            double *partial, const int32_t *outer_active, hipStream_t st)
+{
+    DD_DISPATCH(launch_init_t, sp, ba, rhs, r, rh, p, x, partial, outer_active, st);
+}
+
+hipError_t launch_bicg_s(const BlkArgs &ba, dd_prec sp, const void *r, const void *v, void *s, const PairState &ps,
+                         hipStream_t st)
+{
+    DD_DISPATCH(launch_s_t, sp, ba, r, v, s, ps, st);
 }
 
 hipError_t launch_bicg_xr(const BlkArgs &ba, dd_prec sp, void *x, const void *p, const void *s, const void *tv,
                           void *r, const void *rh, double *partial, const PairState &ps, hipStream_t st)
 {
-    if (ba.ntiles <= 0) return hipSuccess;
-    dim3 g(ba.ntiles), t(kTile);
-    if (sp == DD_F64)
-        hipLaunchKernelGGL(k_bicg_xr<double>, g, t, 0, st, ba, (double *)x, (const double *)p, (const double *)s,
-                           (const double *)tv, (double *)r, (const double *)rh, partial, ps);
-    else
-        hipLaunchKernelGGL(k_bicg_xr<float>, g, t, 0, st, ba, (float *)x, (const float *)p, (const float *)s,
-                           (const float *)tv, (float *)r, (const float *)rh, partial, ps);
-    return hipGetLastError();
+    DD_DISPATCH(launch_xr_t, sp, ba, x, p, s, tv, r, rh, partial, ps, st);
 }
 
-hipError_t launch_bicg_p(const BlkArgs &ba, dd_prec sp, const void *r, const void *v, void *p,
-                         const PairState &ps, hipStream_t st)
+hipError_t launch_bicg_p(const BlkArgs &ba, dd_prec sp, const void *r, const void *v, void *p, const PairState &ps,
+                         hipStream_t st)
 {
-    if (ba.ntiles <= 0) return hipSuccess;
-    dim3 g(ba.ntiles), t(kTile);
-    if (sp == DD_F64)
-        hipLaunchKernelGGL(k_bicg_p<double>, g, t, 0, st, ba, (const double *)r, (const double *)v, (double *)p, ps);
-    else
-        hipLaunchKernelGGL(k_bicg_p<float>, g, t, 0, st, ba, (const float *)r, (const float *)v, (float *)p, ps);
-    return hipGetLastError();
+    DD_DISPATCH(launch_p_t, sp, ba, r, v, p, ps, st);
 }
 
 // ------------------------------------------------------ per-pair scalars
+//
+// One wavefront per (block, rhs) pair: the lanes stride over the block's
+// tiles, a fixed butterfly sums them (the same order on every run), and lane
+// 0 updates the pair's recurrence scalars in FP64.
 
-// sum over the tiles of the pair's block of partial[.][r][k]
-__device__ __forceinline__ double pair_sum(const BlkArgs &ba, const double *partial, int b, int r, int k)
+__device__ __forceinline__ double wave_sum(double v)
 {
-    double s = 0;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+template <int NK>
+__device__ __forceinline__ void pair_sums(const BlkArgs &ba, const double *partial, int b, int r, int lane,
+                                          double (&s)[NK])
+{
+#pragma unroll
+    for (int k = 0; k < NK; k++) s[k] = 0;
     const int t1 = ba.blk_tile0[b + 1];
-    for (int t = ba.blk_tile0[b]; t < t1; t++) s += partial[((int64_t)t * ba.n_rhs + r) * kNRed + k];
-    return s;
+    for (int t = ba.blk_tile0[b] + lane; t < t1; t += 64)
+#pragma unroll
+        for (int k = 0; k < NK; k++) s[k] += partial[((int64_t)t * ba.n_rhs + r) * kNRed + k];
+#pragma unroll
+    for (int k = 0; k < NK; k++) s[k] = wave_sum(s[k]);
 }
 
 __device__ __forceinline__ bool finite(double v) { return isfinite(v); }
 
-__global__ void k_sc_init(BlkArgs ba, const double *partial, PairState ps, const int32_t *outer_active)
-{
-    const int pair = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pair >= ps.np) return;
+#define DD_PAIR_PROLOGUE(NP)                                                   \
+    const int lane = threadIdx.x & 63;                                         \
+    const int pair = (int)((blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6); \
+    if (pair >= (NP)) return;                                                  \
     const int b = pair % ba.nb, r = pair / ba.nb;
+
+__global__ void __launch_bounds__(256) k_sc_init(BlkArgs ba, const double *partial, PairState ps,
+                                                 const int32_t *outer_active)
+{
+    DD_PAIR_PROLOGUE(ps.np)
+    double s[1];
+    pair_sums<1>(ba, partial, b, r, lane, s);
+    if (lane != 0) return;
     if (!outer_active[pair]) {
         ps.active[pair] = 0;
         return;
     }
-    const double bb = pair_sum(ba, partial, b, r, 0);
+    const double bb = s[0];
     ps.bb[pair] = bb;
     ps.rr[pair] = bb;
     ps.rho[2 * pair] = bb;
     ps.rho[2 * pair + 1] = 0;
     ps.omega[2 * pair] = 1;
     ps.omega[2 * pair + 1] = 0;
-    const bool ok = finite(bb) && bb > 0;
-    ps.active[pair] = ok ? 1 : 0;
+    ps.active[pair] = (finite(bb) && bb > 0) ? 1 : 0;
     if (!finite(bb)) ps.flags[pair] |= 4;
 }
 
-__global__ void k_sc_alpha(BlkArgs ba, const double *partial, PairState ps)
+__global__ void __launch_bounds__(256) k_sc_alpha(BlkArgs ba, const double *partial, PairState ps)
 {
-    const int pair = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pair >= ps.np || !ps.active[pair]) return;
-    const int b = pair % ba.nb, r = pair / ba.nb;
-    const double vr = pair_sum(ba, partial, b, r, 0), vi = pair_sum(ba, partial, b, r, 1);
+    DD_PAIR_PROLOGUE(ps.np)
+    if (!ps.active[pair]) return;
+    double s[2];
+    pair_sums<2>(ba, partial, b, r, lane, s);
+    if (lane != 0) return;
+    const double vr = s[0], vi = s[1];
     const double rr = ps.rho[2 * pair], ri = ps.rho[2 * pair + 1];
     const double den = vr * vr + vi * vi;
     const double ar = (rr * vr + ri * vi) / den, ai = (ri * vr - rr * vi) / den;
@@ -730,14 +993,15 @@ __global__ void k_sc_alpha(BlkArgs ba, const double *partial, PairState ps)
     ps.alpha[2 * pair + 1] = ai;
 }
 
-__global__ void k_sc_omega(BlkArgs ba, const double *partial, PairState ps)
+__global__ void __launch_bounds__(256) k_sc_omega(BlkArgs ba, const double *partial, PairState ps)
 {
-    const int pair = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pair >= ps.np || !ps.active[pair]) return;
-    const int b = pair % ba.nb, r = pair / ba.nb;
-    const double tsr = pair_sum(ba, partial, b, r, 0), tsi = pair_sum(ba, partial, b, r, 1);
-    const double tt = pair_sum(ba, partial, b, r, 2);
-    const double wr = tsr / tt, wi = tsi / tt;
+    DD_PAIR_PROLOGUE(ps.np)
+    if (!ps.active[pair]) return;
+    double s[3];
+    pair_sums<3>(ba, partial, b, r, lane, s);
+    if (lane != 0) return;
+    const double tt = s[2];
+    const double wr = s[0] / tt, wi = s[1] / tt;
     if (!(tt > 0) || !finite(wr) || !finite(wi)) {
         ps.active[pair] = 0;
         ps.flags[pair] |= 2;
@@ -747,13 +1011,14 @@ __global__ void k_sc_omega(BlkArgs ba, const double *partial, PairState ps)
     ps.omega[2 * pair + 1] = wi;
 }
 
-__global__ void k_sc_beta(BlkArgs ba, const double *partial, PairState ps, double tol2)
+__global__ void __launch_bounds__(256) k_sc_beta(BlkArgs ba, const double *partial, PairState ps, double tol2)
 {
-    const int pair = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pair >= ps.np || !ps.active[pair]) return;
-    const int b = pair % ba.nb, r = pair / ba.nb;
-    const double nr_ = pair_sum(ba, partial, b, r, 0), ni_ = pair_sum(ba, partial, b, r, 1);
-    const double rr = pair_sum(ba, partial, b, r, 2);
+    DD_PAIR_PROLOGUE(ps.np)
+    if (!ps.active[pair]) return;
+    double s[3];
+    pair_sums<3>(ba, partial, b, r, lane, s);
+    if (lane != 0) return;
+    const double nr_ = s[0], ni_ = s[1], rr = s[2];
     ps.iters[pair] += 1;
     ps.rr[pair] = rr;
     if (!finite(rr)) {
@@ -786,13 +1051,15 @@ __global__ void k_sc_beta(BlkArgs ba, const double *partial, PairState ps, doubl
 }
 
 // true residual |b - D x|^2 = even + odd partials; first call also sets |b|^2
-__global__ void k_sc_outer(BlkArgs ba, const double *pe, const double *po, int first, double tol2, OuterState os,
-                           int np)
+__global__ void __launch_bounds__(256) k_sc_outer(BlkArgs ba, const double *pe, const double *po, int first,
+                                                  double tol2, OuterState os, int np)
 {
-    const int pair = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pair >= np) return;
-    const int b = pair % ba.nb, r = pair / ba.nb;
-    const double rr = pair_sum(ba, pe, b, r, 0) + pair_sum(ba, po, b, r, 0);
+    DD_PAIR_PROLOGUE(np)
+    double se[1], so[1];
+    pair_sums<1>(ba, pe, b, r, lane, se);
+    pair_sums<1>(ba, po, b, r, lane, so);
+    if (lane != 0) return;
+    const double rr = se[0] + so[0];
     if (first) {
         os.bb[pair] = rr;
         os.flags[pair] = 0;
@@ -809,7 +1076,7 @@ __global__ void k_sc_outer(BlkArgs ba, const double *pe, const double *po, int f
     else os.flags[pair] &= ~1;
 }
 
-static inline dim3 pair_grid(int np) { return dim3((unsigned)((np + 255) / 256)); }
+static inline dim3 pair_grid(int np) { return dim3((unsigned)((np + 3) / 4)); }
 
 hipError_t launch_sc_init(const BlkArgs &ba, const double *partial, const PairState &ps, const int32_t *outer_active,
                           hipStream_t s)
@@ -827,8 +1094,7 @@ hipError_t launch_sc_omega(const BlkArgs &ba, const double *partial, const PairS
     hipLaunchKernelGGL(k_sc_omega, pair_grid(ps.np), dim3(256), 0, s, ba, partial, ps);
     return hipGetLastError();
 }
-hipError_t launch_sc_beta(const BlkArgs &ba, const double *partial, const PairState &ps, double tol,
-                          hipStream_t s)
+hipError_t launch_sc_beta(const BlkArgs &ba, const double *partial, const PairState &ps, double tol, hipStream_t s)
 {
     hipLaunchKernelGGL(k_sc_beta, pair_grid(ps.np), dim3(256), 0, s, ba, partial, ps, tol * tol);
     return hipGetLastError();

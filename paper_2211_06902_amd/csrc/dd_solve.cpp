@@ -13,6 +13,7 @@
 // every pair so that their cost per launch is fixed.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -130,13 +131,17 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
     dd_blocks *B = const_cast<dd_blocks *>(Bc);
     HIPCHECK(ctx, enter(ctx));
     hipError_t e;
-    const TileTable *tt = tiles_for(ctx, B, n_rhs, &e);
-    if (!tt) return fail(ctx, DD_EDEVICE, std::string("tile tables: ") + hipGetErrorString(e));
-    const BlkArgs ba = blk_args(B, tt, n_rhs);
+    // FP64 residual kernels and inner-precision kernels may group rhs differently
+    const int g64 = rhs_group(ctx, n_rhs, DD_F64), gsp = rhs_group(ctx, n_rhs, sp);
+    const TileTable *tt64 = tiles_for(ctx, B, n_rhs, g64, &e);
+    const TileTable *ttsp = tt64 ? tiles_for(ctx, B, n_rhs, gsp, &e) : nullptr;
+    if (!ttsp) return fail(ctx, DD_EDEVICE, std::string("tile tables: ") + hipGetErrorString(e));
+    const BlkArgs ba64 = blk_args(B, tt64, n_rhs, g64);
+    const BlkArgs ba = blk_args(B, ttsp, n_rhs, gsp);
     const int np = n_rhs * B->nb;
     const int64_t hel = (B->soff[B->nb] / 2) * 24 * (int64_t)n_rhs;  // elements per half field
     const size_t h64 = (size_t)hel * 8, hsp = (size_t)hel * prec_bytes(sp);
-    const size_t npart = (size_t)std::max(tt->ntiles, 1) * n_rhs * kNRed * sizeof(double);
+    const size_t npart = (size_t)std::max({tt64->ntiles, ttsp->ntiles, 1}) * n_rhs * kNRed * sizeof(double);
 
     Ws w;
     std::memset(&w, 0, sizeof(w));
@@ -214,9 +219,9 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
             h.c_add = 1.0;
             h.dot_mode = kDotOutOut;
             h.partial = p ? w.po : w.pe;
-            HIPCHECK(ctx, run_hop(ctx, B, ba, h, DD_F64));
+            HIPCHECK(ctx, run_hop(ctx, B, ba64, h, DD_F64));
         }
-        HIPCHECK(ctx, launch_sc_outer(ba, w.pe, w.po, cyc == 0, prm.tol, w.os, st));
+        HIPCHECK(ctx, launch_sc_outer(ba64, w.pe, w.po, cyc == 0, prm.tol, w.os, st));
         HIPCHECK(ctx, hipMemcpyAsync(h_act.data(), w.os.active, np * sizeof(int32_t), hipMemcpyDeviceToHost, st));
         HIPCHECK(ctx, hipStreamSynchronize(st));
         int n_act = 0;

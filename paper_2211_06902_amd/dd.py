@@ -22,7 +22,8 @@ LIB_PATH = os.path.join(_HERE, "libdd.so")
 DD_OK, DD_EINVAL, DD_ENOMEM, DD_EDEVICE, DD_ENOCONV, DD_EUNSUPPORTED = range(6)
 F64, F32, BF16 = 0, 1, 2
 BICGSTAB, GMRES = 0, 1
-KCLASS_HOP, KCLASS_BLAS = 0, 1
+KCLASS_HOP_F64, KCLASS_HOP_F32, KCLASS_HOP_BF16 = 0, 1, 2
+TUNE_RHS_GROUP_F64, TUNE_RHS_GROUP_F32 = 0, 1
 _PREC = {"f64": F64, "f32": F32, "bf16": BF16, F64: F64, F32: F32, BF16: BF16}
 
 if not os.path.exists(LIB_PATH):
@@ -109,6 +110,7 @@ _sig("dd_block_solve", _I32, [_P, _P, _P, _D, _P, _P, _I32, ctypes.POINTER(Solve
                               ctypes.POINTER(SolveStats)])
 _sig("dd_multiboson_action", _I32, [_P, _P, _P, _D, _I32, _P, _P, _P, ctypes.POINTER(SolveParams), _P, _P,
                                     ctypes.POINTER(SolveStats)])
+_sig("dd_tune_set", _I32, [_P, _I32, _I32])
 _sig("dd_timer_enable", _I32, [_P, _I32])
 _sig("dd_timer_reset", _I32, [_P])
 _sig("dd_timer_read", _I32, [_P, _I32, _P, _P, _P])
@@ -352,6 +354,11 @@ class Context:
                 "outer_cycles": stats.outer_cycles}
         return S_block, tot.value, info, st
 
+    # tuning
+    def tune_set(self, what, value):
+        """what: TUNE_RHS_GROUP_F64 / TUNE_RHS_GROUP_F32; value 0 (auto), 1, 2 or 4."""
+        self._check(_lib.dd_tune_set(self._h, int(what), int(value)))
+
     # timing
     def timer_enable(self, on=True):
         self._check(_lib.dd_timer_enable(self._h, 1 if on else 0))
@@ -359,7 +366,7 @@ class Context:
     def timer_reset(self):
         self._check(_lib.dd_timer_reset(self._h))
 
-    def timer_read(self, kclass=KCLASS_HOP):
+    def timer_read(self, kclass=KCLASS_HOP_F32):
         ms, n, b = _D(), _I64(), _D()
         self._check(_lib.dd_timer_read(self._h, int(kclass), ctypes.byref(ms), ctypes.byref(n), ctypes.byref(b)))
         return ms.value, n.value, b.value

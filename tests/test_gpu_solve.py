@@ -171,3 +171,20 @@ def test_c2_full_size_fp32_defect_correction(ctx):
         xo, _, rel = wilson.solve_box(L, -1, c["kappa"], U, bx[:4], bx[4:8], b[r, sl], tol=1e-12)
         assert rel <= 1e-12
         assert _cfg.rel_err(x[r, sl], xo) <= 1e-8
+
+
+@pytest.mark.parametrize("grp", [1, 4])
+def test_solve_with_other_rhs_groups(ctx, c1, grp):
+    from paper_2211_06902_amd import dd
+
+    g = ctx.load_gauge(c1["blk"], _dev(c1["U"]), "f32")
+    try:
+        ctx.tune_set(dd.TUNE_RHS_GROUP_F32, grp)
+        ctx.tune_set(dd.TUNE_RHS_GROUP_F64, grp)
+        x, info, st = ctx.block_solve(c1["blk"], g, c1["kappa"], _dev(c1["b"]), params=dd.solve_params())
+    finally:
+        ctx.tune_set(dd.TUNE_RHS_GROUP_F32, 0)
+        ctx.tune_set(dd.TUNE_RHS_GROUP_F64, 0)
+    assert st == dd.DD_OK and np.all(info["true_relres"] <= TOL)
+    assert _cfg.rel_err(x.cpu().numpy(), c1["x_lu"]) <= 1e-9
+    g.close()

@@ -140,3 +140,30 @@ def test_hop_timer_accounts_bytes(ctx):
     V = 8**4
     expect = 2 * (4 * (V / 2) * 24 * 4 * 3 + blk.inner_links * 18 * 4)
     assert abs(nbytes - expect) < 1e-6 * expect
+
+
+def test_rhs_group_variants_identical(ctx):
+    """The stencil result does not depend on how many rhs a thread handles."""
+    from paper_2211_06902_amd import dd
+
+    L = (8, 8, 8, 8)
+    segs = [[4, 4]] * 4
+    U = synth.gauge_field(L, 0.3, 5)
+    blk = ctx.make_blocks(L, -1, segs)
+    g = ctx.load_gauge(blk, _dev(U), "bf16")
+    g32 = ctx.load_gauge(blk, _dev(U), "f32")
+    x = _dev(synth.spinor_field(L, 12, 6)[:, _cfg.block_sites(L, geometry.tile_boxes(L, segs))])
+    outs = {}
+    try:
+        for grp in [1, 2, 4]:
+            ctx.tune_set(dd.TUNE_RHS_GROUP_F32, grp)
+            ctx.tune_set(dd.TUNE_RHS_GROUP_F64, grp)
+            outs[grp] = [ctx.apply_D_block(blk, g32, 0.13, "f32", x).cpu().numpy(),
+                         ctx.apply_D_block(blk, g, 0.13, "bf16", x).cpu().numpy(),
+                         ctx.apply_D_block(blk, g32, 0.13, "f64", x).cpu().numpy()]
+    finally:
+        ctx.tune_set(dd.TUNE_RHS_GROUP_F32, 0)
+        ctx.tune_set(dd.TUNE_RHS_GROUP_F64, 0)
+    for grp in [2, 4]:
+        for a, b in zip(outs[1], outs[grp]):
+            assert np.array_equal(a, b)
