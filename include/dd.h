@@ -144,8 +144,11 @@ dd_status dd_load_gauge(dd_ctx *ctx, const dd_blocks *blocks, const void *U_dev,
 dd_status dd_free_gauge(dd_gauge *gauge);
 /* Export the packed links of precision prec into dst_dev (device memory of
  * at least total_sites*4*18 elements of the precision: double, float or
- * uint16 BF16 bits).  Layout: [block][eo site][mu][row][col][re,im] with the
- * forward link U_mu(x) of each site x; links that leave the block are zero. */
+ * uint16 BF16 bits).  Layout per block b (S_b sites, starting at element
+ * 72 * site_offset(b)): [mu][k = 3*row + col][eo site][re,im] holding the
+ * forward link U_mu(x) of each block site x (even sites first), multiplied
+ * by -1 when it crosses the antiperiodic time edge; links that leave the
+ * block are zero.  Rounding to FP32/BF16 follows the sign change (exact). */
 dd_status dd_gauge_export(dd_ctx *ctx, const dd_gauge *gauge, dd_prec prec, void *dst_dev);
 
 /* ------------------------------------------------------------- operator */
@@ -222,7 +225,9 @@ dd_status dd_multiboson_action(dd_ctx *ctx, const dd_blocks *blocks, const dd_ga
  * FP64 / FP32 spinors (1, 2 or 4; ignored when it does not divide n_rhs).
  * Results do not depend on it beyond rounding of the fused dot products'
  * summation order, which is fixed for a given setting. */
-enum { DD_TUNE_RHS_GROUP_F64 = 0, DD_TUNE_RHS_GROUP_F32 = 1 };
+/* DD_TUNE_HOP_LDS: 1 (default) stages each hop tile's chunk of the input
+ * field in LDS, 0 reads every neighbour from global memory. */
+enum { DD_TUNE_RHS_GROUP_F64 = 0, DD_TUNE_RHS_GROUP_F32 = 1, DD_TUNE_HOP_LDS = 2 };
 dd_status dd_tune_set(dd_ctx *ctx, int32_t what, int32_t value);
 
 /* ------------------------------------------------------------ timing */

@@ -80,21 +80,27 @@ struct TimedLaunch {
 const TileTable *tiles_for(dd_ctx *ctx, dd_blocks *B, int nr, int g, hipError_t *err)
 {
     *err = hipSuccess;
-    const int key = 8 * nr + g;
+    const int key = nr * 8 + g;
     auto it = B->tiles.find(key);
     if (it != B->tiles.end()) return &it->second;
     TileTable tt;
     tt.blk_tile0.assign(B->nb + 1, 0);
-    std::vector<int32_t> tb;
+    std::vector<int32_t> tb, chunk(B->nb, 0);
+    const int ng = nr / g;
     for (int b = 0; b < B->nb; b++) {
-        const int64_t items = (int64_t)B->shapes[B->shape_of[b]].h * (nr / g);
-        const int nt = (int)((items + kTile - 1) / kTile);
+        const Shape &sh = B->shapes[B->shape_of[b]];
+        const int hs = sh.e[1] * sh.e[2] * sh.e[3] / 2;  // sites per parity of an x0-slice
+        int T = hs <= kTile ? hs * (kTile / hs) : kTile;
+        T = std::min(T, sh.h);
+        chunk[b] = T;
+        const int nt = ((sh.h + T - 1) / T) * ng;
         tt.blk_tile0[b + 1] = tt.blk_tile0[b] + nt;
         for (int t = 0; t < nt; t++) tb.push_back(b);
     }
     tt.ntiles = tt.blk_tile0[B->nb];
     if ((*err = upload(&tt.d_tile_block, tb)) != hipSuccess) return nullptr;
     if ((*err = upload(&tt.d_blk_tile0, tt.blk_tile0)) != hipSuccess) return nullptr;
+    if ((*err = upload(&tt.d_chunk, chunk)) != hipSuccess) return nullptr;
     (void)ctx;
     return &(B->tiles[key] = tt);
 }
@@ -106,17 +112,27 @@ int rhs_group(const dd_ctx *ctx, int nr, dd_prec sp)
 {
     const int forced = ctx ? ctx->rhs_group[sp == DD_F64 ? 0 : 1] : 0;
     if (forced > 0 && nr % forced == 0) return forced;
-    // FP32: two rhs per thread halve the link loads and keep 3 waves per SIMD
-    // (four need more than 256 VGPRs); FP64: one rhs per thread (two need 224).
-    const int want = sp == DD_F64 ? 1 : 2;
+    // One rhs per thread by default: measured fastest for FP32 and FP64 (more
+    // rhs per thread share link loads but cost occupancy).
+    const int want = 1;
     for (int g = want; g > 1; g >>= 1)
         if (nr % g == 0) return g;
     return 1;
 }
 
+// rhs per thread of the hop kernel: its LDS stage holds 256 sites x G spinors,
+// so G is at most 2 for FP32 spinors and 1 for FP64.
+int hop_group(const dd_ctx *ctx, int nr, dd_prec sp)
+{
+    const int g = rhs_group(ctx, nr, sp);
+    const int cap = sp == DD_F64 ? 1 : 2;
+    return g > cap ? cap : g;
+}
+
 BlkArgs blk_args(const dd_blocks *B, const TileTable *tt, int nr, int g)
 {
     BlkArgs a;
+    a.chunk = tt->d_chunk;
     a.tile_block = tt->d_tile_block;
     a.blk_tile0 = tt->d_blk_tile0;
     a.h = B->d_h;
@@ -149,8 +165,10 @@ double hop_bytes(const dd_blocks *B, int nr, dd_prec prec, int extra_vectors)
     return nr * half_sites * 24.0 * sf * (2 + extra_vectors) + (double)B->inner_links * 18.0 * sl;
 }
 
-hipError_t run_hop(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const HopArgs &ha, dd_prec prec)
+hipError_t run_hop(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const HopArgs &ha_in, dd_prec prec)
 {
+    HopArgs ha = ha_in;
+    ha.use_lds = ctx->hop_lds ? 1 : 0;
     const int extra = (ha.self != nullptr) + (ha.add != nullptr) + (ha.aux != nullptr);
     TimedLaunch tl(ctx, DD_KCLASS_HOP_F64 + (int)prec, hop_bytes(B, ba.n_rhs, prec, extra));
     return launch_hop(ba, ha, prec, ctx->stream);
@@ -383,6 +401,7 @@ dd_status dd_free_blocks(dd_blocks *B)
     for (auto &kv : B->tiles) {
         if (kv.second.d_tile_block) hipFree(kv.second.d_tile_block);
         if (kv.second.d_blk_tile0) hipFree(kv.second.d_blk_tile0);
+        if (kv.second.d_chunk) hipFree(kv.second.d_chunk);
     }
     delete B;
     return DD_OK;
@@ -499,7 +518,7 @@ dd_status dd_apply_D_block(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, 
     HIPCHECK(ctx, enter(ctx));
     hipError_t e;
     const dd_prec sp = prec == DD_F64 ? DD_F64 : DD_F32;
-    const int g = rhs_group(ctx, n_rhs, sp);
+    const int g = hop_group(ctx, n_rhs, sp);
     const TileTable *tt = tiles_for(ctx, B, n_rhs, g, &e);
     if (!tt) return fail(ctx, DD_EDEVICE, std::string("tile tables: ") + hipGetErrorString(e));
     const BlkArgs ba = blk_args(B, tt, n_rhs, g);
@@ -526,6 +545,10 @@ dd_status dd_apply_D_block(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, 
 dd_status dd_tune_set(dd_ctx *ctx, int32_t what, int32_t value)
 {
     if (!ctx) return DD_EINVAL;
+    if (what == DD_TUNE_HOP_LDS) {
+        ctx->hop_lds = value != 0;
+        return DD_OK;
+    }
     if (what != DD_TUNE_RHS_GROUP_F64 && what != DD_TUNE_RHS_GROUP_F32)
         return fail(ctx, DD_EINVAL, "unknown tuning knob");
     if (value != 0 && value != 1 && value != 2 && value != 4)

@@ -17,6 +17,7 @@ size_t prec_bytes(dd_prec p);
 hipError_t enter(dd_ctx *ctx);
 const TileTable *tiles_for(dd_ctx *ctx, dd_blocks *B, int nr, int g, hipError_t *err);
 int rhs_group(const dd_ctx *ctx, int nr, dd_prec sp);
+int hop_group(const dd_ctx *ctx, int nr, dd_prec sp);
 BlkArgs blk_args(const dd_blocks *B, const TileTable *tt, int nr, int g);
 const void *links_for(const dd_gauge *G, dd_prec prec);
 double hop_bytes(const dd_blocks *B, int nr, dd_prec prec, int extra_vectors);

@@ -13,7 +13,7 @@
 namespace dd {
 
 // Threads per workgroup of the site kernels; each thread handles one site and
-// a group of right-hand sides, so a tile covers kTile (site, rhs group) items.
+// a group of right-hand sides.
 constexpr int kTile = 256;
 // Largest number of right-hand sides per call (a tile must hold every rhs).
 constexpr int kMaxRhs = 64;
@@ -45,6 +45,7 @@ struct dd_ctx {
     bool timing = false;
     dd::Timer timers[DD_KCLASS_COUNT];
     int rhs_group[2] = {0, 0};  // forced rhs per thread for FP64 / FP32 spinors (0 = automatic)
+    bool hop_lds = true;        // stage the hop's chunk of the input in LDS
 };
 
 namespace dd {
@@ -61,10 +62,15 @@ struct Shape {
     int64_t perm_off;  // offset of the eo -> local canonical permutation
 };
 
+// Tile decomposition of the site kernels: a tile is one rhs group (g
+// consecutive rhs) on a chunk of chunk[b] consecutive eo sites of block b
+// (whole x0-slices when a slice has at most kTile sites per parity); tiles
+// are ordered block, chunk, group (group fastest).
 struct TileTable {
     int ntiles = 0;
     int32_t *d_tile_block = nullptr;  // tile -> block
     int32_t *d_blk_tile0 = nullptr;   // block -> first tile (n_blocks + 1 entries)
+    int32_t *d_chunk = nullptr;       // sites per chunk of each block
     std::vector<int32_t> blk_tile0;
 };
 
@@ -97,7 +103,7 @@ struct dd_blocks {
     int32_t *d_ext = nullptr;       // [nb][4]
     int32_t *d_bnd = nullptr;       // [total bnd] box-local canonical index
     int64_t *d_boff = nullptr;      // [nb+1]
-    std::map<int, dd::TileTable> tiles;  // keyed by 8 * n_rhs + rhs per thread
+    std::map<int, dd::TileTable> tiles;  // keyed by (n_rhs, rhs per thread)
 };
 
 struct dd_gauge {
@@ -125,7 +131,8 @@ struct BlkArgs {
     int ntiles;
     int n_rhs;
     int nb;  // number of blocks (pair = rhs * nb + block)
-    int g;   // right-hand sides per thread (1, 2 or 4; divides n_rhs)
+    int g;                 // right-hand sides per thread (1, 2 or 4; divides n_rhs)
+    const int32_t *chunk;  // sites per chunk of each block
 };
 
 enum DotMode { kDotNone = 0, kDotAuxOut = 1, kDotOutSelfOutOut = 2, kDotOutOut = 3 };
@@ -143,6 +150,7 @@ struct HopArgs {
     double *partial;  // [ntiles][n_rhs][kNRed]
     int parity;
     int dot_mode;
+    int use_lds;  // 0: every neighbour is read from global memory
 };
 
 // Per-pair Krylov state (device, structure of arrays).

@@ -1,28 +1,29 @@
 // HIP kernels of libdd for gfx950.
 //
 // Data layout (device, library-owned):
-//   half field  (one parity of a spinor field, all blocks, all rhs):
-//       element (block b, component c in 0..23, eo site h, rhs r) at
-//       (soff[b]/2)*24*n_rhs + c*(h_b*n_rhs) + h*n_rhs + r
-//     i.e. per block a component-major structure of arrays whose innermost
-//     index is the right-hand side.  A wavefront reading one component of
-//     consecutive (site, rhs) items touches consecutive addresses, and all
-//     right-hand sides of a site sit next to each other, so one link load
-//     serves every rhs of the site in the same instruction.
+//   half field (one parity of a spinor field, all blocks, all rhs): for block
+//     b with h_b sites per parity, element (rhs r, component c in 0..23, eo
+//     site h) at (soff[b]/2)*24*n_rhs + (r*24 + c)*h_b + h, i.e. per block and
+//     rhs a component-major structure of arrays with the site innermost.
 //     Component c = 2*(3*spin + colour) + {0: re, 1: im}.
-//   links: [block site slot (eo order, even sites first)][mu][3][3][re,im],
-//     the forward link U_mu(x) of every block site; links that leave the
-//     block are stored as zero and never read.
+//   links: per block [mu][k = 3*row + col][eo site][re, im], the forward link
+//     U_mu(x) of every block site; links that leave the block are zero.
 //   neighbour table per block shape: [parity][h][8] int32, entries
 //     2*mu = x+mu, 2*mu+1 = x-mu as the eo index inside the other parity,
 //     -1 if the hop is dropped (Dirichlet), bit 30 set if the hop crosses
 //     the antiperiodic time edge.
 //
-// Work decomposition of every site kernel: one workgroup of kTile threads
-// handles kTile consecutive (site, rhs) items of one block ("tile").  Tiles
-// are numbered block after block; the launch index is remapped so that
-// consecutive tiles go to the same XCD (the hardware deals workgroups to the
-// 8 XCDs round-robin), keeping a block's neighbour reads in one L2.
+// Work decomposition of every site kernel: a workgroup ("tile") of kTile
+// threads handles one rhs group (G consecutive right-hand sides) on a chunk
+// of consecutive eo sites of one block; thread tid owns site h0 + tid and its
+// G rhs.  A chunk is a whole number of x0-slices when a slice has at most
+// kTile sites per parity, so the hops along directions 1..3 of a chunk stay
+// inside the same eo index range of the other parity.  Tiles are numbered
+// block, chunk, group (group fastest) and the launch index is remapped so
+// that consecutive tiles go to the same XCD (workgroups are dealt to the 8
+// XCDs round-robin), keeping a block's shared reads in one L2.
+// Every load or store of one component by a wavefront covers 64 consecutive
+// sites of one rhs: 256 contiguous bytes in FP32.
 #include <hip/hip_runtime.h>
 
 #include "dd_internal.h"
@@ -47,40 +48,88 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
 
 __device__ __forceinline__ float bf16_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
 
-// load the 18 reals of one link into registers of type AC
-template <typename AC>
-__device__ __forceinline__ void load_link(const double *p, AC u[18])
+// Buffer addressing: a descriptor holds a wave-uniform base and size; a load
+// takes a per-lane byte offset (VGPR) plus a wave-uniform byte offset (SGPR),
+// so the 24 components of a spinor (uniform stride) share one VGPR offset and
+// cost no address arithmetic.  Accesses beyond the size read 0 / are dropped.
+struct Buf {
+    __amdgpu_buffer_rsrc_t r;
+};
+__device__ __forceinline__ Buf make_buf(const void *p, uint32_t bytes)
 {
-    const double2 *q = reinterpret_cast<const double2 *>(p);
+    return Buf{__builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000)};
+}
+template <typename T>
+__device__ __forceinline__ T bload(const Buf &b, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ float bload<float>(const Buf &b, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.r, (int)voff, (int)soff, 0));
+}
+template <>
+__device__ __forceinline__ double bload<double>(const Buf &b, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(b.r, (int)voff, (int)soff, 0));
+}
+template <typename T>
+__device__ __forceinline__ void bstore(const Buf &b, T v, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ void bstore<float>(const Buf &b, float v, uint32_t voff, uint32_t soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), b.r, (int)voff, (int)soff, 0);
+}
+template <>
+__device__ __forceinline__ void bstore<double>(const Buf &b, double v, uint32_t voff, uint32_t soff)
+{
+    using u2 = __attribute__((ext_vector_type(2))) uint32_t;
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), b.r, (int)voff, (int)soff, 0);
+}
+
+// Link layout per block: element (site slot s, mu, complex entry k = 3*row + col, re/im)
+// at soff[b]*72 + ((mu*9 + k)*S_b + s)*2 + ri.  Consecutive slots are adjacent, so a
+// wavefront reading entry k of one direction for consecutive sites touches one line.
+// load_link: voff = byte offset of the slot's pair, soff = byte offset of entry 0
+// of direction mu, kstride = bytes between entries.
+template <typename AC>
+__device__ __forceinline__ void load_link(const Buf &b, const double *, uint32_t voff, uint32_t soff,
+                                          uint32_t kstride, AC (&u)[18])
+{
 #pragma unroll
     for (int k = 0; k < 9; k++) {
-        const double2 v = q[k];
-        u[2 * k] = (AC)v.x;
-        u[2 * k + 1] = (AC)v.y;
+        const auto q = __builtin_amdgcn_raw_buffer_load_b128(b.r, (int)voff, (int)(soff + k * kstride), 0);
+        u[2 * k] = (AC)__builtin_bit_cast(double, __builtin_shufflevector(q, q, 0, 1));
+        u[2 * k + 1] = (AC)__builtin_bit_cast(double, __builtin_shufflevector(q, q, 2, 3));
     }
 }
 template <typename AC>
-__device__ __forceinline__ void load_link(const float *p, AC u[18])
+__device__ __forceinline__ void load_link(const Buf &b, const float *, uint32_t voff, uint32_t soff, uint32_t kstride,
+                                          AC (&u)[18])
 {
-    const float2 *q = reinterpret_cast<const float2 *>(p);
 #pragma unroll
     for (int k = 0; k < 9; k++) {
-        const float2 v = q[k];
-        u[2 * k] = (AC)v.x;
-        u[2 * k + 1] = (AC)v.y;
+        // take the 8 bytes as one integer: indexing the returned vector lets
+        // the compiler shrink the load to its first dword
+        const uint64_t q =
+            __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(b.r, (int)voff, (int)(soff + k * kstride), 0));
+        u[2 * k] = (AC)__uint_as_float((uint32_t)q);
+        u[2 * k + 1] = (AC)__uint_as_float((uint32_t)(q >> 32));
     }
 }
 template <typename AC>
-__device__ __forceinline__ void load_link(const uint16_t *p, AC u[18])
+__device__ __forceinline__ void load_link(const Buf &b, const uint16_t *, uint32_t voff, uint32_t soff,
+                                          uint32_t kstride, AC (&u)[18])
 {
-    const uint32_t *q = reinterpret_cast<const uint32_t *>(p);
 #pragma unroll
     for (int k = 0; k < 9; k++) {
-        const uint32_t w = q[k];
+        const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(b.r, (int)voff, (int)(soff + k * kstride), 0);
         u[2 * k] = (AC)bf16_to_f32(w & 0xffffu);
         u[2 * k + 1] = (AC)bf16_to_f32(w >> 16);
     }
 }
+
+// a * b + c in one rounding
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // c * (re, im) for the coefficient codes 0:+1 1:-1 2:+i 3:-i
 template <int CODE, typename AC>
@@ -105,65 +154,7 @@ template <> struct Proj<2, false> { static constexpr int pi0 = 3, pi1 = 2, a0 = 
 template <> struct Proj<3, true>  { static constexpr int pi0 = 2, pi1 = 3, a0 = 2, a1 = 3, s0 = 0, s1 = 1, b0 = 3, b1 = 2; };
 template <> struct Proj<3, false> { static constexpr int pi0 = 2, pi1 = 3, a0 = 3, a1 = 2, s0 = 0, s1 = 1, b0 = 2, b1 = 3; };
 
-// acc += sg * (1 -/+ gamma_mu) W psi, psi given as 24 reals
-template <int MU, bool FWD, typename AC>
-__device__ __forceinline__ void hop_term(AC acc[24], const AC psi[24], const AC u[18], AC sg)
-{
-    using P = Proj<MU, FWD>;
-    AC h[2][3][2];
-#pragma unroll
-    for (int c = 0; c < 3; c++) {
-        AC re, im;
-        cmul_code<P::a0>(psi[2 * (3 * P::pi0 + c)], psi[2 * (3 * P::pi0 + c) + 1], re, im);
-        h[0][c][0] = sg * (psi[2 * c] + re);
-        h[0][c][1] = sg * (psi[2 * c + 1] + im);
-        cmul_code<P::a1>(psi[2 * (3 * P::pi1 + c)], psi[2 * (3 * P::pi1 + c) + 1], re, im);
-        h[1][c][0] = sg * (psi[2 * (3 + c)] + re);
-        h[1][c][1] = sg * (psi[2 * (3 + c) + 1] + im);
-    }
-    AC w[2][3][2];
-#pragma unroll
-    for (int s = 0; s < 2; s++)
-#pragma unroll
-        for (int a = 0; a < 3; a++) {
-            AC re = 0, im = 0;
-#pragma unroll
-            for (int b = 0; b < 3; b++) {
-                AC ur, ui;
-                if constexpr (FWD) {  // U[a][b]
-                    ur = u[2 * (3 * a + b)];
-                    ui = u[2 * (3 * a + b) + 1];
-                } else {              // conj(U[b][a])
-                    ur = u[2 * (3 * b + a)];
-                    ui = -u[2 * (3 * b + a) + 1];
-                }
-                re += ur * h[s][b][0] - ui * h[s][b][1];
-                im += ur * h[s][b][1] + ui * h[s][b][0];
-            }
-            w[s][a][0] = re;
-            w[s][a][1] = im;
-        }
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        acc[2 * a] += w[0][a][0];
-        acc[2 * a + 1] += w[0][a][1];
-        acc[2 * (3 + a)] += w[1][a][0];
-        acc[2 * (3 + a) + 1] += w[1][a][1];
-        AC re, im;
-        cmul_code<P::b0>(w[P::s0][a][0], w[P::s0][a][1], re, im);
-        acc[2 * (6 + a)] += re;
-        acc[2 * (6 + a) + 1] += im;
-        cmul_code<P::b1>(w[P::s1][a][0], w[P::s1][a][1], re, im);
-        acc[2 * (9 + a)] += re;
-        acc[2 * (9 + a) + 1] += im;
-    }
-}
-
-// ------------------------------------------------- G right-hand sides per thread
-//
-// A thread owns one site and G consecutive right-hand sides (G | n_rhs), so
-// each link it loads serves G spinors and every component is one vector load
-// of G contiguous values (16 bytes for 4 floats or 2 doubles).
+// ------------------------------------------------------------- tiles
 
 template <typename T, int G>
 __device__ __forceinline__ void ldv(const T *p, T (&v)[G])
@@ -205,147 +196,234 @@ __device__ __forceinline__ void stv(T *p, const T (&v)[G])
     }
 }
 
-// (tile, thread) -> block, site, rhs group
-struct Item {
-    int b, site, rg, tile, titem0, ng;
-    int64_t off, cs;
+struct Tile {
+    int tile, b, grp, h0, tv, hb, site, tid;
     bool live;
+    int64_t base;  // element of (rhs grp*G, component 0, site) in the half fields
 };
 
-__device__ __forceinline__ Item item_of(const BlkArgs &ba)
+// a value every lane of the wavefront holds: keep it in a scalar register
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni64(int64_t v)
 {
-    Item it;
-    it.tile = xcd_tile(blockIdx.x, ba.ntiles);
-    it.b = ba.tile_block[it.tile];
-    const int nr = ba.n_rhs;
-    it.ng = nr / ba.g;
-    const int hb = ba.h[it.b];
-    const int titems = hb * it.ng;
-    it.titem0 = (it.tile - ba.blk_tile0[it.b]) * kTile;
-    const int titem = it.titem0 + (int)threadIdx.x;
-    it.live = titem < titems;
-    it.site = it.live ? titem / it.ng : 0;
-    it.rg = it.live ? titem - it.site * it.ng : 0;
-    it.off = (ba.soff[it.b] >> 1) * 24 * nr + (int64_t)it.site * nr + (int64_t)it.rg * ba.g;
-    it.cs = (int64_t)hb * nr;
-    return it;
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u), hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// Per-(tile, rhs) sums of up to kNRed values; every thread of the tile calls it.
-template <int G>
-__device__ __forceinline__ void tile_reduce(double (*red)[kTile], const double (&dv)[G][kNRed], int nred,
-                                            double *partial, const Item &it, int nr)
+__device__ __forceinline__ Tile tile_of(const BlkArgs &ba)
 {
+    Tile t;
+    t.tile = uni(xcd_tile(blockIdx.x, ba.ntiles));
+    t.b = uni(ba.tile_block[t.tile]);
+    const int ng = ba.n_rhs / ba.g;
+    const int rel = t.tile - uni(ba.blk_tile0[t.b]);
+    t.grp = rel % ng;
+    const int chunk = rel / ng;
+    t.hb = uni(ba.h[t.b]);
+    const int T = uni(ba.chunk[t.b]);
+    t.h0 = chunk * T;
+    t.tv = min(T, t.hb - t.h0);
+    t.tid = threadIdx.x;
+    t.live = t.tid < t.tv;
+    t.site = t.h0 + t.tid;
+    t.base = (ba.soff[t.b] >> 1) * 24 * ba.n_rhs + (int64_t)t.grp * ba.g * 24 * t.hb + t.site;
+    return t;
+}
+
+// element offset of component c of the thread's j-th rhs, relative to Tile::base
+__device__ __forceinline__ int64_t eoff(const Tile &t, int j, int c) { return ((int64_t)j * 24 + c) * t.hb; }
+
+// Per-(tile, rhs) sums: a fixed tree over the tile's threads for each of the
+// G rhs and each of the nred values; partial[(tile * G + j) * kNRed + k].
+template <int G>
+__device__ __forceinline__ void tile_sum(double (*red)[kTile], const double (&dv)[G][kNRed], int nred,
+                                         double *partial, int tile)
+{
+    const int tid = threadIdx.x;
     for (int k = 0; k < nred; k++) {
 #pragma unroll
-        for (int j = 0; j < G; j++) red[j][threadIdx.x] = dv[j][k];
+        for (int j = 0; j < G; j++) red[j][tid] = dv[j][k];
         __syncthreads();
-        const int t = threadIdx.x;
-        if (t < nr) {
-            const int q = t / G, jj = t - (t / G) * G;
-            const int start = ((q - it.titem0 % it.ng) % it.ng + it.ng) % it.ng;
-            double s = 0;
-            for (int m = start; m < kTile; m += it.ng) s += red[jj][m];
-            partial[((int64_t)it.tile * nr + t) * kNRed + k] = s;
+        for (int w = kTile / 2; w > 0; w >>= 1) {
+            if (tid < w)
+#pragma unroll
+                for (int j = 0; j < G; j++) red[j][tid] += red[j][tid + w];
+            __syncthreads();
         }
+        if (tid < G) partial[((int64_t)tile * G + tid) * kNRed + k] = red[tid][0];
         __syncthreads();
     }
 }
 
-// acc[j] += sg * (1 -/+ gamma_mu) W psi_j(idx) for the G rhs, accumulating the
-// colour contributions of the projected half spinor straight into acc.
-template <int MU, bool FWD, typename SP, typename AC, int G>
-__device__ __forceinline__ void hop_term_g(AC (&acc)[G][24], const SP *in, int64_t cs, int64_t site_off,
-                                           const AC (&u)[18], AC sg)
+// ------------------------------------------------------------- hop
+
+// Sources of a neighbour's spinor for the G rhs of a thread: global memory or
+// the LDS copy of the tile's chunk.  load(comp, v) fills v with component comp.
+// Offsets are 32-bit and relative to wave-uniform block bases.
+template <typename SP, int G>
+struct SrcGlobal {
+    Buf b;          // the block's half field
+    uint32_t voff;  // bytes to (rhs group, component 0, neighbour site)
+    uint32_t cstr;  // bytes between components (h_b elements)
+    __device__ __forceinline__ void load(int comp, SP (&v)[G]) const
+    {
+#pragma unroll
+        for (int j = 0; j < G; j++) v[j] = bload<SP>(b, voff, (uint32_t)(j * 24 + comp) * cstr);
+    }
+};
+template <typename SP, int G>
+struct SrcLds {
+    const SP *p;  // stage + lidx * G
+    __device__ __forceinline__ void load(int comp, SP (&v)[G]) const { ldv<SP, G>(p + comp * kTile * G, v); }
+};
+
+// acc[j] += (1 -/+ gamma_mu) W psi_j for the G rhs: project to the half
+// spinor h (2 spins x 3 colours), multiply by W = U (forward) or U^+
+// (backward), then rebuild the lower spin components from the upper ones.
+// The antiperiodic time sign is part of the stored link.
+template <int MU, bool FWD, typename SP, typename AC, int G, typename SRC>
+__device__ __forceinline__ void hop_term(AC (&acc)[G][24], const SRC &src, const AC (&u)[18])
 {
     using P = Proj<MU, FWD>;
+    AC h[G][2][3][2];
 #pragma unroll
     for (int c = 0; c < 3; c++) {
         SP v[4][2][G];
 #pragma unroll
         for (int sp = 0; sp < 4; sp++)
 #pragma unroll
-            for (int ri = 0; ri < 2; ri++) ldv<SP, G>(in + (2 * (3 * sp + c) + ri) * cs + site_off, v[sp][ri]);
+            for (int ri = 0; ri < 2; ri++) src.load(2 * (3 * sp + c) + ri, v[sp][ri]);
 #pragma unroll
         for (int j = 0; j < G; j++) {
-            AC h[2][2];
             AC re, im;
             cmul_code<P::a0>((AC)v[P::pi0][0][j], (AC)v[P::pi0][1][j], re, im);
-            h[0][0] = sg * ((AC)v[0][0][j] + re);
-            h[0][1] = sg * ((AC)v[0][1][j] + im);
+            h[j][0][c][0] = (AC)v[0][0][j] + re;
+            h[j][0][c][1] = (AC)v[0][1][j] + im;
             cmul_code<P::a1>((AC)v[P::pi1][0][j], (AC)v[P::pi1][1][j], re, im);
-            h[1][0] = sg * ((AC)v[1][0][j] + re);
-            h[1][1] = sg * ((AC)v[1][1][j] + im);
+            h[j][1][c][0] = (AC)v[1][0][j] + re;
+            h[j][1][c][1] = (AC)v[1][1][j] + im;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < G; j++) {
+        // W = U h (or U^+ h) as explicit fused multiply-add chains: one
+        // multiply and five FMAs per real component
+        AC w[2][3][2];
+#pragma unroll
+        for (int s = 0; s < 2; s++)
 #pragma unroll
             for (int a = 0; a < 3; a++) {
-                AC ur, ui;
-                if constexpr (FWD) {  // U[a][c]
-                    ur = u[2 * (3 * a + c)];
-                    ui = u[2 * (3 * a + c) + 1];
-                } else {              // conj(U[c][a])
-                    ur = u[2 * (3 * c + a)];
-                    ui = -u[2 * (3 * c + a) + 1];
-                }
-                AC d[2][2];
+                AC re, im;
 #pragma unroll
-                for (int s = 0; s < 2; s++) {
-                    d[s][0] = ur * h[s][0] - ui * h[s][1];
-                    d[s][1] = ur * h[s][1] + ui * h[s][0];
+                for (int c = 0; c < 3; c++) {
+                    AC ur, ui;
+                    if constexpr (FWD) {  // U[a][c]
+                        ur = u[2 * (3 * a + c)];
+                        ui = u[2 * (3 * a + c) + 1];
+                    } else {              // conj(U[c][a])
+                        ur = u[2 * (3 * c + a)];
+                        ui = -u[2 * (3 * c + a) + 1];
+                    }
+                    const AC hr = h[j][s][c][0], hi = h[j][s][c][1];
+                    if (c == 0) {
+                        re = ur * hr;
+                        im = ur * hi;
+                    } else {
+                        re = fmad(ur, hr, re);
+                        im = fmad(ur, hi, im);
+                    }
+                    re = fmad(-ui, hi, re);
+                    im = fmad(ui, hr, im);
                 }
-                acc[j][2 * a] += d[0][0];
-                acc[j][2 * a + 1] += d[0][1];
-                acc[j][2 * (3 + a)] += d[1][0];
-                acc[j][2 * (3 + a) + 1] += d[1][1];
-                cmul_code<P::b0>(d[P::s0][0], d[P::s0][1], re, im);
-                acc[j][2 * (6 + a)] += re;
-                acc[j][2 * (6 + a) + 1] += im;
-                cmul_code<P::b1>(d[P::s1][0], d[P::s1][1], re, im);
-                acc[j][2 * (9 + a)] += re;
-                acc[j][2 * (9 + a) + 1] += im;
+                w[s][a][0] = re;
+                w[s][a][1] = im;
             }
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            acc[j][2 * a] += w[0][a][0];
+            acc[j][2 * a + 1] += w[0][a][1];
+            acc[j][2 * (3 + a)] += w[1][a][0];
+            acc[j][2 * (3 + a) + 1] += w[1][a][1];
+            AC re, im;
+            cmul_code<P::b0>(w[P::s0][a][0], w[P::s0][a][1], re, im);
+            acc[j][2 * (6 + a)] += re;
+            acc[j][2 * (6 + a) + 1] += im;
+            cmul_code<P::b1>(w[P::s1][a][0], w[P::s1][a][1], re, im);
+            acc[j][2 * (9 + a)] += re;
+            acc[j][2 * (9 + a) + 1] += im;
         }
     }
 }
 
-template <int MU, typename SP, typename LK, typename AC, int G>
-__device__ __forceinline__ void hop_dir(AC (&acc)[G][24], const int32_t (&nb)[8], const SP *in, int64_t cs, int nr,
-                                        const LK *lk, int slot_self, int other0)
+struct HopCtx {
+    int h0, tv;          // staged other-parity sites [h0, h0 + tv)
+    int grp_off;         // element offset of the thread's rhs group in the block's half field
+    int slot_self, other0;
+    uint32_t cstr;       // bytes between spinor components (h_b elements)
+    uint32_t kstr;       // bytes between link entries (S_b pairs)
+    Buf in_b, lk_b;      // the block's input half field and links
+};
+
+template <int MU, bool FWD, typename SP, typename LK, typename AC, int G>
+__device__ __forceinline__ void hop_one(AC (&acc)[G][24], int32_t e, const SP *stage, const HopCtx &hc)
 {
-    const int32_t ef = nb[2 * MU];
-    if (ef >= 0) {
-        const int idx = ef & kNbrMask;
-        const AC sg = (ef & kNbrSign) ? (AC)-1 : (AC)1;
-        AC u[18];
-        load_link(lk + ((int64_t)slot_self * 4 + MU) * 18, u);
-        hop_term_g<MU, true, SP, AC, G>(acc, in, cs, (int64_t)idx * nr, u, sg);
-    }
-    const int32_t eb = nb[2 * MU + 1];
-    if (eb >= 0) {
-        const int idx = eb & kNbrMask;
-        const AC sg = (eb & kNbrSign) ? (AC)-1 : (AC)1;
-        AC u[18];
-        load_link(lk + ((int64_t)(other0 + idx) * 4 + MU) * 18, u);
-        hop_term_g<MU, false, SP, AC, G>(acc, in, cs, (int64_t)idx * nr, u, sg);
+    if (e < 0) return;
+    const int idx = e & kNbrMask;
+    AC u[18];
+    const int slot = FWD ? hc.slot_self : hc.other0 + idx;
+    load_link(hc.lk_b, (const LK *)nullptr, (uint32_t)slot * 2 * (uint32_t)sizeof(LK), MU * 9 * hc.kstr, hc.kstr, u);
+    const int lidx = idx - hc.h0;
+    if ((unsigned)lidx < (unsigned)hc.tv) {
+        const SrcLds<SP, G> src{stage + lidx * G};
+        hop_term<MU, FWD, SP, AC, G>(acc, src, u);
+    } else {
+        const SrcGlobal<SP, G> src{hc.in_b, (uint32_t)(hc.grp_off + idx) * (uint32_t)sizeof(SP), hc.cstr};
+        hop_term<MU, FWD, SP, AC, G>(acc, src, u);
     }
 }
 
-// --------------------------------------------------------------- hop
-
+// out = c_add*add + c_self*self + c_hop * (H in) on the sites of one parity,
+// `in` on the other parity.  The tile first copies its chunk of `in` (its rhs
+// group) into LDS; hops that land inside the chunk read LDS, the others
+// (direction 0 across the chunk edge) read global memory.
 template <typename SP, typename LK, typename AC, int G>
 __global__ void __launch_bounds__(kTile) k_hop(BlkArgs ba, HopArgs ha)
 {
+    __shared__ SP stage[24 * kTile * G];
     __shared__ double red[G][kTile];
-    const Item it = item_of(ba);
-    const int nr = ba.n_rhs;
+    const Tile t = tile_of(ba);
     const int p = ha.parity;
+    // wave-uniform block bases and buffer descriptors; per-thread offsets are 32-bit
+    const int64_t soff = uni64(ba.soff[t.b]);
+    const int64_t hbase = (soff >> 1) * 24 * ba.n_rhs;
+    const uint32_t fbytes = (uint32_t)(ba.n_rhs * 24 * t.hb) * (uint32_t)sizeof(SP);  // block's half field
+    HopCtx hc;
+    hc.h0 = t.h0;
+    hc.tv = ha.use_lds ? t.tv : 0;
+    hc.cstr = (uint32_t)t.hb * (uint32_t)sizeof(SP);
+    hc.kstr = (uint32_t)(4 * t.hb) * (uint32_t)sizeof(LK);  // S_b = 2 h_b slots, (re, im) per slot
+    hc.grp_off = t.grp * G * 24 * t.hb;
+    hc.in_b = make_buf(reinterpret_cast<const SP *>(ha.in) + hbase, fbytes);
+    hc.lk_b = make_buf(reinterpret_cast<const LK *>(ha.links) + soff * 72, (uint32_t)(2 * t.hb * 72) * (uint32_t)sizeof(LK));
+    const uint32_t my = (uint32_t)(hc.grp_off + t.site) * (uint32_t)sizeof(SP);  // bytes to (group, comp 0, own site)
+    if (t.live && ha.use_lds) {
+#pragma unroll 4
+        for (int c = 0; c < 24; c++) {
+            SP v[G];
+#pragma unroll
+            for (int j = 0; j < G; j++) v[j] = bload<SP>(hc.in_b, my, (uint32_t)(j * 24 + c) * hc.cstr);
+            stv<SP, G>(stage + (c * kTile + t.tid) * G, v);
+        }
+    }
+    __syncthreads();
     double dv[G][kNRed];
 #pragma unroll
     for (int j = 0; j < G; j++)
 #pragma unroll
         for (int k = 0; k < kNRed; k++) dv[j][k] = 0;
-    if (it.live) {
-        const int hb = ba.h[it.b];
-        const int32_t *nbp = ba.nbr + ba.nbr_off[it.b] + (int64_t)(p * hb + it.site) * 8;
+    if (t.live) {
+        const int32_t *nbp = ba.nbr + uni64(ba.nbr_off[t.b]) + (unsigned)((p * t.hb + t.site) * 8);
         int32_t nb[8];
         {
             const int4 *q = reinterpret_cast<const int4 *>(nbp);
@@ -353,97 +431,84 @@ __global__ void __launch_bounds__(kTile) k_hop(BlkArgs ba, HopArgs ha)
             nb[0] = a0.x; nb[1] = a0.y; nb[2] = a0.z; nb[3] = a0.w;
             nb[4] = a1.x; nb[5] = a1.y; nb[6] = a1.z; nb[7] = a1.w;
         }
-        const LK *lk = reinterpret_cast<const LK *>(ha.links) + ba.soff[it.b] * 72;
-        // input pointer at this block and rhs group; neighbour sites add idx * nr
-        const SP *in = reinterpret_cast<const SP *>(ha.in) + (ba.soff[it.b] >> 1) * 24 * nr + (int64_t)it.rg * G;
+        hc.slot_self = p * t.hb + t.site;
+        hc.other0 = (1 - p) * t.hb;
         AC acc[G][24];
 #pragma unroll
         for (int j = 0; j < G; j++)
 #pragma unroll
             for (int c = 0; c < 24; c++) acc[j][c] = 0;
-        const int slot = p * hb + it.site;
-        const int other0 = (1 - p) * hb;
-        hop_dir<0, SP, LK, AC, G>(acc, nb, in, it.cs, nr, lk, slot, other0);
-        hop_dir<1, SP, LK, AC, G>(acc, nb, in, it.cs, nr, lk, slot, other0);
-        hop_dir<2, SP, LK, AC, G>(acc, nb, in, it.cs, nr, lk, slot, other0);
-        hop_dir<3, SP, LK, AC, G>(acc, nb, in, it.cs, nr, lk, slot, other0);
+        hop_one<0, true, SP, LK, AC, G>(acc, nb[0], stage, hc);
+        hop_one<0, false, SP, LK, AC, G>(acc, nb[1], stage, hc);
+        hop_one<1, true, SP, LK, AC, G>(acc, nb[2], stage, hc);
+        hop_one<1, false, SP, LK, AC, G>(acc, nb[3], stage, hc);
+        hop_one<2, true, SP, LK, AC, G>(acc, nb[4], stage, hc);
+        hop_one<2, false, SP, LK, AC, G>(acc, nb[5], stage, hc);
+        hop_one<3, true, SP, LK, AC, G>(acc, nb[6], stage, hc);
+        hop_one<3, false, SP, LK, AC, G>(acc, nb[7], stage, hc);
 
-        SP *out = reinterpret_cast<SP *>(ha.out) + it.off;
-        const SP *self = ha.self ? reinterpret_cast<const SP *>(ha.self) + it.off : nullptr;
-        const SP *add = ha.add ? reinterpret_cast<const SP *>(ha.add) + it.off : nullptr;
-        const SP *aux = ha.aux ? reinterpret_cast<const SP *>(ha.aux) + it.off : nullptr;
+        const Buf out_b = make_buf(reinterpret_cast<const SP *>(ha.out) + hbase, fbytes);
+        const Buf self_b = make_buf(ha.self ? reinterpret_cast<const SP *>(ha.self) + hbase : nullptr, ha.self ? fbytes : 0);
+        const Buf add_b = make_buf(ha.add ? reinterpret_cast<const SP *>(ha.add) + hbase : nullptr, ha.add ? fbytes : 0);
+        const Buf aux_b = make_buf(ha.aux ? reinterpret_cast<const SP *>(ha.aux) + hbase : nullptr, ha.aux ? fbytes : 0);
+        const bool has_self = ha.self != nullptr, has_add = ha.add != nullptr;
         const AC ch = (AC)ha.c_hop, cself = (AC)ha.c_self, cadd = (AC)ha.c_add;
 #pragma unroll
-        for (int k = 0; k < 12; k++) {
-            SP o[2][G], sv[2][G], av[2][G];
+        for (int j = 0; j < G; j++) {
+#pragma unroll 4
+            for (int k = 0; k < 12; k++) {
+                double o[2], sv[2] = {0, 0}, av[2] = {0, 0};
 #pragma unroll
-            for (int ri = 0; ri < 2; ri++) {
-                const int c = 2 * k + ri;
-                AC v[G];
-#pragma unroll
-                for (int j = 0; j < G; j++) v[j] = ch * acc[j][c];
-                if (self) {
-                    ldv<SP, G>(self + c * it.cs, sv[ri]);
-#pragma unroll
-                    for (int j = 0; j < G; j++) v[j] += cself * (AC)sv[ri][j];
+                for (int ri = 0; ri < 2; ri++) {
+                    const uint32_t so = (uint32_t)(j * 24 + 2 * k + ri) * hc.cstr;
+                    AC v = ch * acc[j][2 * k + ri];
+                    if (has_self) {
+                        const SP sx = bload<SP>(self_b, my, so);
+                        sv[ri] = (double)sx;
+                        v = fmad(cself, (AC)sx, v);
+                    }
+                    if (has_add) v = fmad(cadd, (AC)bload<SP>(add_b, my, so), v);
+                    const SP ov = (SP)v;
+                    bstore<SP>(out_b, ov, my, so);
+                    o[ri] = (double)ov;
+                    if (ha.dot_mode == kDotAuxOut) av[ri] = (double)bload<SP>(aux_b, my, so);
                 }
-                if (add) {
-                    SP w[G];
-                    ldv<SP, G>(add + c * it.cs, w);
-#pragma unroll
-                    for (int j = 0; j < G; j++) v[j] += cadd * (AC)w[j];
-                }
-#pragma unroll
-                for (int j = 0; j < G; j++) o[ri][j] = (SP)v[j];
-                stv<SP, G>(out + c * it.cs, o[ri]);
-                if (ha.dot_mode == kDotAuxOut) ldv<SP, G>(aux + c * it.cs, av[ri]);
-            }
-#pragma unroll
-            for (int j = 0; j < G; j++) {
-                const double ore = (double)o[0][j], oim = (double)o[1][j];
                 if (ha.dot_mode == kDotAuxOut) {
-                    const double are = (double)av[0][j], aim = (double)av[1][j];
-                    dv[j][0] += are * ore + aim * oim;
-                    dv[j][1] += are * oim - aim * ore;
+                    dv[j][0] += av[0] * o[0] + av[1] * o[1];
+                    dv[j][1] += av[0] * o[1] - av[1] * o[0];
                 } else if (ha.dot_mode == kDotOutSelfOutOut) {
-                    const double sre = (double)sv[0][j], sim = (double)sv[1][j];
-                    dv[j][0] += ore * sre + oim * sim;
-                    dv[j][1] += ore * sim - oim * sre;
-                    dv[j][2] += ore * ore + oim * oim;
+                    dv[j][0] += o[0] * sv[0] + o[1] * sv[1];
+                    dv[j][1] += o[0] * sv[1] - o[1] * sv[0];
+                    dv[j][2] += o[0] * o[0] + o[1] * o[1];
                 } else if (ha.dot_mode == kDotOutOut) {
-                    dv[j][0] += ore * ore + oim * oim;
+                    dv[j][0] += o[0] * o[0] + o[1] * o[1];
                 }
             }
         }
     }
     if (ha.dot_mode != kDotNone) {
         const int nred = ha.dot_mode == kDotAuxOut ? 2 : (ha.dot_mode == kDotOutSelfOutOut ? 3 : 1);
-        tile_reduce<G>(red, dv, nred, ha.partial, it, nr);
+        tile_sum<G>(red, dv, nred, ha.partial, t.tile);
     }
-}
-
-template <int G>
-static hipError_t launch_hop_g(const BlkArgs &ba, const HopArgs &ha, dd_prec prec, hipStream_t s)
-{
-    dim3 g(ba.ntiles), t(kTile);
-    switch (prec) {
-    case DD_F64: hipLaunchKernelGGL((k_hop<double, double, double, G>), g, t, 0, s, ba, ha); break;
-    case DD_F32: hipLaunchKernelGGL((k_hop<float, float, float, G>), g, t, 0, s, ba, ha); break;
-    case DD_BF16: hipLaunchKernelGGL((k_hop<float, uint16_t, float, G>), g, t, 0, s, ba, ha); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
 }
 
 hipError_t launch_hop(const BlkArgs &ba, const HopArgs &ha, dd_prec prec, hipStream_t s)
 {
     if (ba.ntiles <= 0) return hipSuccess;
-    switch (ba.g) {
-    case 1: return launch_hop_g<1>(ba, ha, prec, s);
-    case 2: return launch_hop_g<2>(ba, ha, prec, s);
-    case 4: return launch_hop_g<4>(ba, ha, prec, s);
-    default: return hipErrorInvalidValue;
-    }
+    dim3 g(ba.ntiles), t(kTile);
+    if (prec == DD_F64 && ba.g == 1)
+        hipLaunchKernelGGL((k_hop<double, double, double, 1>), g, t, 0, s, ba, ha);
+    else if (prec == DD_F32 && ba.g == 1)
+        hipLaunchKernelGGL((k_hop<float, float, float, 1>), g, t, 0, s, ba, ha);
+    else if (prec == DD_F32 && ba.g == 2)
+        hipLaunchKernelGGL((k_hop<float, float, float, 2>), g, t, 0, s, ba, ha);
+    else if (prec == DD_BF16 && ba.g == 1)
+        hipLaunchKernelGGL((k_hop<float, uint16_t, float, 1>), g, t, 0, s, ba, ha);
+    else if (prec == DD_BF16 && ba.g == 2)
+        hipLaunchKernelGGL((k_hop<float, uint16_t, float, 2>), g, t, 0, s, ba, ha);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- packing
@@ -492,7 +557,7 @@ __global__ void __launch_bounds__(256) k_pack_gauge(PackGeom g, const double *U,
     if (q >= total) return;
     const int b = find_block(g.soff, g.nb, q);
     const int s = (int)(q - g.soff[b]);
-    const int hb = g.h[b];
+    const int64_t S = 2 * (int64_t)g.h[b];
     const int y = g.perm[g.perm_off[b] + s];
     int c[4];
     local_coords(y, g.ext + 4 * b, c);
@@ -500,14 +565,18 @@ __global__ void __launch_bounds__(256) k_pack_gauge(PackGeom g, const double *U,
     for (int m = 0; m < 4; m++) x[m] = (g.origin[4 * b + m] + c[m]) % g.L[m];
     const int64_t n = (((int64_t)x[0] * g.L[1] + x[1]) * g.L[2] + x[2]) * g.L[3] + x[3];
     const int32_t *nb = g.nbr + g.nbr_off[b] + (int64_t)s * 8;  // slot s = p*h + site
-    (void)hb;
+    LT *blk = dst + g.soff[b] * 72;
     for (int mu = 0; mu < 4; mu++) {
-        LT *o = dst + (q * 4 + mu) * 18;
-        if (nb[2 * mu] >= 0) {
-            const double *u = U + (n * 4 + mu) * 18;
-            for (int k = 0; k < 18; k++) o[k] = cvt_link<LT>(u[k]);
-        } else {
-            for (int k = 0; k < 18; k++) o[k] = (LT)0;
+        const int32_t e = nb[2 * mu];
+        const bool in = e >= 0;
+        // a link across the antiperiodic time edge is stored with the -1 of the
+        // fermion boundary condition, so both hops through it pick it up
+        const double sg = (in && (e & kNbrSign)) ? -1.0 : 1.0;
+        const double *u = U + (n * 4 + mu) * 18;
+        for (int k = 0; k < 9; k++) {
+            LT *o = blk + (((int64_t)mu * 9 + k) * S + s) * 2;
+            o[0] = in ? cvt_link<LT>(sg * u[2 * k]) : (LT)0;
+            o[1] = in ? cvt_link<LT>(sg * u[2 * k + 1]) : (LT)0;
         }
     }
 }
@@ -544,17 +613,17 @@ hipError_t launch_pack_gauge(const dd_blocks *B, const double *U, dd_prec prec, 
 }
 
 // boundary layout [r][q][24] (q = block site, box-local canonical) <-> half fields.
-// Thread t -> (eo block site q = t / n_rhs, rhs r = t % n_rhs): consecutive
-// threads write consecutive half-field addresses; each thread moves one
-// 192-byte spinor record of the boundary layout with 16-byte accesses.
+// Thread t -> (rhs r = t / total, eo block site q = t % total): consecutive
+// threads touch consecutive sites of one rhs in the half fields; each thread
+// moves one 192-byte spinor record of the boundary layout with 16-byte accesses.
 template <typename SP, bool PACK>
 __global__ void __launch_bounds__(256) k_spinor_xfer(PackGeom g, double *ext_f, SP *even, SP *odd,
                                                     int nr, int64_t total)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total * nr) return;
-    const int64_t q = t / nr;  // block site in eo order
-    const int r = (int)(t - q * nr);
+    const int r = (int)(t / total);
+    const int64_t q = t - (int64_t)r * total;  // block site in eo order
     const int b = find_block(g.soff, g.nb, q);
     const int s = (int)(q - g.soff[b]);
     const int hb = g.h[b];
@@ -562,16 +631,15 @@ __global__ void __launch_bounds__(256) k_spinor_xfer(PackGeom g, double *ext_f, 
     const int site = s - p * hb;
     const int y = g.perm[g.perm_off[b] + s];
     double2 *e = reinterpret_cast<double2 *>(ext_f + ((int64_t)r * total + g.soff[b] + y) * 24);
-    SP *hf = (p ? odd : even) + (g.soff[b] >> 1) * 24 * nr + (int64_t)site * nr + r;
-    const int64_t cs = (int64_t)hb * nr;
+    SP *hf = (p ? odd : even) + (g.soff[b] >> 1) * 24 * nr + (int64_t)r * 24 * hb + site;
 #pragma unroll
     for (int k = 0; k < 12; k++) {
         if constexpr (PACK) {
             const double2 v = e[k];
-            hf[(2 * k) * cs] = (SP)v.x;
-            hf[(2 * k + 1) * cs] = (SP)v.y;
+            hf[(int64_t)(2 * k) * hb] = (SP)v.x;
+            hf[(int64_t)(2 * k + 1) * hb] = (SP)v.y;
         } else {
-            e[k] = make_double2((double)hf[(2 * k) * cs], (double)hf[(2 * k + 1) * cs]);
+            e[k] = make_double2((double)hf[(int64_t)(2 * k) * hb], (double)hf[(int64_t)(2 * k + 1) * hb]);
         }
     }
 }
@@ -637,20 +705,31 @@ hipError_t launch_convert(const void *src, dd_prec sp, void *dst, dd_prec dp, in
 
 // ------------------------------------------------------ Krylov site kernels
 //
-// Same (site, G rhs) decomposition as the hop.  Pairs that are no longer
-// active keep their x (the update is selected away), everything else is
-// computed unconditionally: pairs never mix, so values of frozen pairs do
-// not reach active ones.
+// Same tiles as the hop.  Pairs that are no longer active keep their x (the
+// update is selected away); everything else is computed unconditionally:
+// pairs never mix, so values of frozen pairs do not reach active ones.
 
 template <int G>
-__device__ __forceinline__ void pair_flags(const BlkArgs &ba, const Item &it, const int32_t *active, bool (&act)[G],
-                                           bool &any)
+__device__ __forceinline__ bool pair_flags(const BlkArgs &ba, const Tile &t, const int32_t *active, bool (&act)[G])
 {
-    any = false;
+    bool any = false;
 #pragma unroll
     for (int j = 0; j < G; j++) {
-        act[j] = it.live && active[(it.rg * G + j) * ba.nb + it.b] != 0;
+        act[j] = t.live && active[(t.grp * G + j) * ba.nb + t.b] != 0;
         any = any || act[j];
+    }
+    return any;
+}
+
+template <int G>
+__device__ __forceinline__ void load_coef(const double *arr, const BlkArgs &ba, const Tile &t, double (&re)[G],
+                                          double (&im)[G])
+{
+#pragma unroll
+    for (int j = 0; j < G; j++) {
+        const int pr = (t.grp * G + j) * ba.nb + t.b;
+        re[j] = arr[2 * pr];
+        im[j] = arr[2 * pr + 1];
     }
 }
 
@@ -658,19 +737,16 @@ __device__ __forceinline__ void pair_flags(const BlkArgs &ba, const Item &it, co
 template <typename SE, int G>
 __global__ void __launch_bounds__(kTile) k_accum(BlkArgs ba, double *x, const SE *e, const int32_t *active)
 {
-    const Item it = item_of(ba);
-    bool act[G], any;
-    pair_flags<G>(ba, it, active, act, any);
-    if (!any) return;
-    for (int c = 0; c < 24; c++) {
-        double xv[G];
-        SE ev[G];
-        ldv<double, G>(x + it.off + c * it.cs, xv);
-        ldv<SE, G>(e + it.off + c * it.cs, ev);
+    const Tile t = tile_of(ba);
+    bool act[G];
+    if (!pair_flags<G>(ba, t, active, act)) return;
+    x += t.base;
+    e += t.base;
 #pragma unroll
-        for (int j = 0; j < G; j++)
-            if (act[j]) xv[j] += (double)ev[j];
-        stv<double, G>(x + it.off + c * it.cs, xv);
+    for (int j = 0; j < G; j++) {
+        if (!act[j]) continue;
+#pragma unroll 4
+        for (int c = 0; c < 24; c++) x[eoff(t, j, c)] += (double)e[eoff(t, j, c)];
     }
 }
 
@@ -680,178 +756,119 @@ __global__ void __launch_bounds__(kTile) k_bicg_init(BlkArgs ba, const SP *rhs, 
                                                      double *partial, const int32_t *outer_active)
 {
     __shared__ double red[G][kTile];
-    const Item it = item_of(ba);
+    const Tile t = tile_of(ba);
     double dv[G][kNRed] = {};
-    bool act[G], any;
-    pair_flags<G>(ba, it, outer_active, act, any);
-    if (any) {
-        for (int c = 0; c < 24; c++) {
-            const int64_t i = it.off + c * it.cs;
-            SP v[G], z[G];
-            ldv<SP, G>(rhs + i, v);
+    bool act[G];
+    if (pair_flags<G>(ba, t, outer_active, act)) {
 #pragma unroll
-            for (int j = 0; j < G; j++) {
-                z[j] = (SP)0;
-                dv[j][0] += act[j] ? (double)v[j] * (double)v[j] : 0.0;
+        for (int j = 0; j < G; j++) {
+            if (!act[j]) continue;
+#pragma unroll 4
+            for (int c = 0; c < 24; c++) {
+                const int64_t i = t.base + eoff(t, j, c);
+                const SP v = rhs[i];
+                r[i] = v;
+                rh[i] = v;
+                p[i] = v;
+                x[i] = (SP)0;
+                dv[j][0] += (double)v * (double)v;
             }
-            stv<SP, G>(r + i, v);
-            stv<SP, G>(rh + i, v);
-            stv<SP, G>(p + i, v);
-            stv<SP, G>(x + i, z);
         }
     }
-    tile_reduce<G>(red, dv, 1, partial, it, ba.n_rhs);
-}
-
-template <int G>
-__device__ __forceinline__ void load_coef(const double *arr, const BlkArgs &ba, const Item &it, double (&re)[G],
-                                          double (&im)[G])
-{
-#pragma unroll
-    for (int j = 0; j < G; j++) {
-        const int pr = (it.rg * G + j) * ba.nb + it.b;
-        re[j] = arr[2 * pr];
-        im[j] = arr[2 * pr + 1];
-    }
+    tile_sum<G>(red, dv, 1, partial, t.tile);
 }
 
 // s = r - alpha v
 template <typename SP, int G>
 __global__ void __launch_bounds__(kTile) k_bicg_s(BlkArgs ba, const SP *r, const SP *v, SP *s, PairState ps)
 {
-    const Item it = item_of(ba);
-    bool act[G], any;
-    pair_flags<G>(ba, it, ps.active, act, any);
-    if (!any) return;
+    const Tile t = tile_of(ba);
+    bool act[G];
+    if (!pair_flags<G>(ba, t, ps.active, act)) return;
     double ar[G], ai[G];
-    load_coef<G>(ps.alpha, ba, it, ar, ai);
-#pragma unroll 2
-    for (int k = 0; k < 12; k++) {
-        const int64_t i0 = it.off + (2 * k) * it.cs, i1 = i0 + it.cs;
-        SP vr[G], vi[G], rr[G], ri[G], sr[G], si[G];
-        ldv<SP, G>(v + i0, vr);
-        ldv<SP, G>(v + i1, vi);
-        ldv<SP, G>(r + i0, rr);
-        ldv<SP, G>(r + i1, ri);
+    load_coef<G>(ps.alpha, ba, t, ar, ai);
 #pragma unroll
-        for (int j = 0; j < G; j++) {
-            const SP a_r = (SP)ar[j], a_i = (SP)ai[j];
-            sr[j] = rr[j] - (a_r * vr[j] - a_i * vi[j]);
-            si[j] = ri[j] - (a_r * vi[j] + a_i * vr[j]);
+    for (int j = 0; j < G; j++) {
+        if (!act[j]) continue;
+        const SP a_r = (SP)ar[j], a_i = (SP)ai[j];
+#pragma unroll 4
+        for (int k = 0; k < 12; k++) {
+            const int64_t i0 = t.base + eoff(t, j, 2 * k), i1 = i0 + t.hb;
+            const SP vr = v[i0], vi = v[i1];
+            s[i0] = r[i0] - (a_r * vr - a_i * vi);
+            s[i1] = r[i1] - (a_r * vi + a_i * vr);
         }
-        stv<SP, G>(s + i0, sr);
-        stv<SP, G>(s + i1, si);
     }
 }
 
-// x += alpha p + omega s (active pairs);  r = s - omega t;  <rh, r>, |r|^2 per (tile, rhs)
+// x += alpha p + omega s;  r = s - omega t;  <rh, r>, |r|^2 per (tile, rhs)
 template <typename SP, int G>
-__global__ void __launch_bounds__(kTile) k_bicg_xr(BlkArgs ba, SP *x, const SP *p, const SP *s, const SP *t, SP *r,
+__global__ void __launch_bounds__(kTile) k_bicg_xr(BlkArgs ba, SP *x, const SP *p, const SP *s, const SP *tv, SP *r,
                                                    const SP *rh, double *partial, PairState ps)
 {
     __shared__ double red[G][kTile];
-    const Item it = item_of(ba);
+    const Tile t = tile_of(ba);
     double dv[G][kNRed] = {};
-    bool act[G], any;
-    pair_flags<G>(ba, it, ps.active, act, any);
-    if (any) {
+    bool act[G];
+    if (pair_flags<G>(ba, t, ps.active, act)) {
         double ar[G], ai[G], wr[G], wi[G];
-        load_coef<G>(ps.alpha, ba, it, ar, ai);
-        load_coef<G>(ps.omega, ba, it, wr, wi);
-        for (int k = 0; k < 12; k++) {
-            const int64_t i0 = it.off + (2 * k) * it.cs, i1 = i0 + it.cs;
-            SP pr[G], pi[G], sr[G], si[G], tr[G], ti[G], xr[G], xi[G], nr_[G], ni_[G], hr[G], hi[G];
-            ldv<SP, G>(p + i0, pr);
-            ldv<SP, G>(p + i1, pi);
-            ldv<SP, G>(s + i0, sr);
-            ldv<SP, G>(s + i1, si);
-            ldv<SP, G>(t + i0, tr);
-            ldv<SP, G>(t + i1, ti);
-            ldv<SP, G>(x + i0, xr);
-            ldv<SP, G>(x + i1, xi);
-            ldv<SP, G>(rh + i0, hr);
-            ldv<SP, G>(rh + i1, hi);
+        load_coef<G>(ps.alpha, ba, t, ar, ai);
+        load_coef<G>(ps.omega, ba, t, wr, wi);
 #pragma unroll
-            for (int j = 0; j < G; j++) {
-                const SP a_r = (SP)ar[j], a_i = (SP)ai[j], w_r = (SP)wr[j], w_i = (SP)wi[j];
-                const SP nxr = xr[j] + (a_r * pr[j] - a_i * pi[j]) + (w_r * sr[j] - w_i * si[j]);
-                const SP nxi = xi[j] + (a_r * pi[j] + a_i * pr[j]) + (w_r * si[j] + w_i * sr[j]);
-                xr[j] = act[j] ? nxr : xr[j];
-                xi[j] = act[j] ? nxi : xi[j];
-                nr_[j] = sr[j] - (w_r * tr[j] - w_i * ti[j]);
-                ni_[j] = si[j] - (w_r * ti[j] + w_i * tr[j]);
-                const double a = (double)hr[j], b = (double)hi[j], c = (double)nr_[j], d = (double)ni_[j];
-                dv[j][0] += a * c + b * d;
-                dv[j][1] += a * d - b * c;
+        for (int j = 0; j < G; j++) {
+            if (!act[j]) continue;
+            const SP a_r = (SP)ar[j], a_i = (SP)ai[j], w_r = (SP)wr[j], w_i = (SP)wi[j];
+#pragma unroll 2
+            for (int k = 0; k < 12; k++) {
+                const int64_t i0 = t.base + eoff(t, j, 2 * k), i1 = i0 + t.hb;
+                const SP pr = p[i0], pi = p[i1], sr = s[i0], si = s[i1], tr = tv[i0], ti = tv[i1];
+                x[i0] = x[i0] + (a_r * pr - a_i * pi) + (w_r * sr - w_i * si);
+                x[i1] = x[i1] + (a_r * pi + a_i * pr) + (w_r * si + w_i * sr);
+                const SP nr_ = sr - (w_r * tr - w_i * ti);
+                const SP ni_ = si - (w_r * ti + w_i * tr);
+                r[i0] = nr_;
+                r[i1] = ni_;
+                const double a = (double)rh[i0], bq = (double)rh[i1], c = (double)nr_, d = (double)ni_;
+                dv[j][0] += a * c + bq * d;
+                dv[j][1] += a * d - bq * c;
                 dv[j][2] += c * c + d * d;
             }
-            stv<SP, G>(x + i0, xr);
-            stv<SP, G>(x + i1, xi);
-            stv<SP, G>(r + i0, nr_);
-            stv<SP, G>(r + i1, ni_);
         }
     }
-    tile_reduce<G>(red, dv, 3, partial, it, ba.n_rhs);
+    tile_sum<G>(red, dv, 3, partial, t.tile);
 }
 
 // p = r + beta (p - omega v)
 template <typename SP, int G>
 __global__ void __launch_bounds__(kTile) k_bicg_p(BlkArgs ba, const SP *r, const SP *v, SP *p, PairState ps)
 {
-    const Item it = item_of(ba);
-    bool act[G], any;
-    pair_flags<G>(ba, it, ps.active, act, any);
-    if (!any) return;
+    const Tile t = tile_of(ba);
+    bool act[G];
+    if (!pair_flags<G>(ba, t, ps.active, act)) return;
     double br[G], bi[G], wr[G], wi[G];
-    load_coef<G>(ps.beta, ba, it, br, bi);
-    load_coef<G>(ps.omega, ba, it, wr, wi);
-#pragma unroll 2
-    for (int k = 0; k < 12; k++) {
-        const int64_t i0 = it.off + (2 * k) * it.cs, i1 = i0 + it.cs;
-        SP vr[G], vi[G], pr[G], pi[G], rr[G], ri[G];
-        ldv<SP, G>(v + i0, vr);
-        ldv<SP, G>(v + i1, vi);
-        ldv<SP, G>(p + i0, pr);
-        ldv<SP, G>(p + i1, pi);
-        ldv<SP, G>(r + i0, rr);
-        ldv<SP, G>(r + i1, ri);
+    load_coef<G>(ps.beta, ba, t, br, bi);
+    load_coef<G>(ps.omega, ba, t, wr, wi);
 #pragma unroll
-        for (int j = 0; j < G; j++) {
-            const SP b_r = (SP)br[j], b_i = (SP)bi[j], w_r = (SP)wr[j], w_i = (SP)wi[j];
-            const SP qr = pr[j] - (w_r * vr[j] - w_i * vi[j]);
-            const SP qi = pi[j] - (w_r * vi[j] + w_i * vr[j]);
-            pr[j] = rr[j] + (b_r * qr - b_i * qi);
-            pi[j] = ri[j] + (b_r * qi + b_i * qr);
+    for (int j = 0; j < G; j++) {
+        if (!act[j]) continue;
+        const SP b_r = (SP)br[j], b_i = (SP)bi[j], w_r = (SP)wr[j], w_i = (SP)wi[j];
+#pragma unroll 4
+        for (int k = 0; k < 12; k++) {
+            const int64_t i0 = t.base + eoff(t, j, 2 * k), i1 = i0 + t.hb;
+            const SP vr = v[i0], vi = v[i1];
+            const SP qr = p[i0] - (w_r * vr - w_i * vi);
+            const SP qi = p[i1] - (w_r * vi + w_i * vr);
+            p[i0] = r[i0] + (b_r * qr - b_i * qi);
+            p[i1] = r[i1] + (b_r * qi + b_i * qr);
         }
-        stv<SP, G>(p + i0, pr);
-        stv<SP, G>(p + i1, pi);
     }
 }
 
-hipError_t launch_accum(const BlkArgs &ba, double *x, const void *e, dd_prec ep, const int32_t *active,
-                        hipStream_t st)
+template <typename SE, int G>
+static void launch_accum_t(const BlkArgs &ba, double *x, const void *e, const int32_t *active, hipStream_t st)
 {
-    if (ba.ntiles <= 0) return hipSuccess;
-    dim3 g(ba.ntiles), t(kTile);
-    const bool d = ep == DD_F64;
-    switch (ba.g) {
-    case 1:
-        if (d) hipLaunchKernelGGL((k_accum<double, 1>), g, t, 0, st, ba, x, (const double *)e, active);
-        else hipLaunchKernelGGL((k_accum<float, 1>), g, t, 0, st, ba, x, (const float *)e, active);
-        break;
-    case 2:
-        if (d) hipLaunchKernelGGL((k_accum<double, 2>), g, t, 0, st, ba, x, (const double *)e, active);
-        else hipLaunchKernelGGL((k_accum<float, 2>), g, t, 0, st, ba, x, (const float *)e, active);
-        break;
-    case 4:
-        if (d) hipLaunchKernelGGL((k_accum<double, 4>), g, t, 0, st, ba, x, (const double *)e, active);
-        else hipLaunchKernelGGL((k_accum<float, 4>), g, t, 0, st, ba, x, (const float *)e, active);
-        break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    hipLaunchKernelGGL((k_accum<SE, G>), dim3(ba.ntiles), dim3(kTile), 0, st, ba, x, (const SE *)e, active);
 }
-
 template <typename SP, int G>
 static void launch_init_t(const BlkArgs &ba, const void *rhs, void *r, void *rh, void *p, void *x, double *partial,
                           const int32_t *oa, hipStream_t st)
@@ -879,18 +896,25 @@ static void launch_p_t(const BlkArgs &ba, const void *r, const void *v, void *p,
                        (SP *)p, ps);
 }
 
-#define DD_DISPATCH(FN, SPREC, ...)                                                   \
-    do {                                                                              \
-        if (ba.ntiles <= 0) return hipSuccess;                                        \
-        const bool d_ = (SPREC) == DD_F64;                                            \
-        switch (ba.g) {                                                               \
-        case 1: if (d_) FN<double, 1>(__VA_ARGS__); else FN<float, 1>(__VA_ARGS__); break; \
-        case 2: if (d_) FN<double, 2>(__VA_ARGS__); else FN<float, 2>(__VA_ARGS__); break; \
-        case 4: if (d_) FN<double, 4>(__VA_ARGS__); else FN<float, 4>(__VA_ARGS__); break; \
-        default: return hipErrorInvalidValue;                                         \
-        }                                                                             \
-        return hipGetLastError();                                                     \
+// dispatch on the spinor precision and the rhs group (1, 2 or 4)
+#define DD_DISPATCH(FN, SPREC, ...)                                                              \
+    do {                                                                                         \
+        if (ba.ntiles <= 0) return hipSuccess;                                                   \
+        const bool d_ = (SPREC) == DD_F64;                                                       \
+        switch (ba.g) {                                                                          \
+        case 1: if (d_) FN<double, 1>(__VA_ARGS__); else FN<float, 1>(__VA_ARGS__); break;       \
+        case 2: if (d_) FN<double, 2>(__VA_ARGS__); else FN<float, 2>(__VA_ARGS__); break;       \
+        case 4: if (d_) FN<double, 4>(__VA_ARGS__); else FN<float, 4>(__VA_ARGS__); break;       \
+        default: return hipErrorInvalidValue;                                                    \
+        }                                                                                        \
+        return hipGetLastError();                                                                \
     } while (0)
+
+hipError_t launch_accum(const BlkArgs &ba, double *x, const void *e, dd_prec ep, const int32_t *active,
+                        hipStream_t st)
+{
+    DD_DISPATCH(launch_accum_t, ep, ba, x, e, active, st);
+}
 
 hipError_t launch_bicg_init(const BlkArgs &ba, dd_prec sp, const void *rhs, void *r, void *rh, void *p, void *x,
                             double *partial, const int32_t *outer_active, hipStream_t st)
@@ -919,8 +943,8 @@ hipError_t launch_bicg_p(const BlkArgs &ba, dd_prec sp, const void *r, const voi
 // ------------------------------------------------------ per-pair scalars
 //
 // One wavefront per (block, rhs) pair: the lanes stride over the block's
-// tiles, a fixed butterfly sums them (the same order on every run), and lane
-// 0 updates the pair's recurrence scalars in FP64.
+// tiles of the pair's rhs group, a fixed butterfly sums them (the same order
+// on every run), and lane 0 updates the pair's recurrence scalars in FP64.
 
 __device__ __forceinline__ double wave_sum(double v)
 {
@@ -935,10 +959,14 @@ __device__ __forceinline__ void pair_sums(const BlkArgs &ba, const double *parti
 {
 #pragma unroll
     for (int k = 0; k < NK; k++) s[k] = 0;
-    const int t1 = ba.blk_tile0[b + 1];
-    for (int t = ba.blk_tile0[b] + lane; t < t1; t += 64)
+    const int t0 = ba.blk_tile0[b], t1 = ba.blk_tile0[b + 1];
+    const int ng = ba.n_rhs / ba.g, grp = r / ba.g, j = r - grp * ba.g;
+    const int nchunk = (t1 - t0) / ng;
+    for (int ch = lane; ch < nchunk; ch += 64) {
+        const int t = t0 + ch * ng + grp;
 #pragma unroll
-        for (int k = 0; k < NK; k++) s[k] += partial[((int64_t)t * ba.n_rhs + r) * kNRed + k];
+        for (int k = 0; k < NK; k++) s[k] += partial[((int64_t)t * ba.g + j) * kNRed + k];
+    }
 #pragma unroll
     for (int k = 0; k < NK; k++) s[k] = wave_sum(s[k]);
 }

@@ -132,7 +132,10 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
     HIPCHECK(ctx, enter(ctx));
     hipError_t e;
     // FP64 residual kernels and inner-precision kernels may group rhs differently
-    const int g64 = rhs_group(ctx, n_rhs, DD_F64), gsp = rhs_group(ctx, n_rhs, sp);
+    // the FP64 residual kernels and the inner-precision kernels may group rhs
+    // differently; a scalar kernel reads partials with the tiling of the
+    // kernel that wrote them
+    const int g64 = hop_group(ctx, n_rhs, DD_F64), gsp = hop_group(ctx, n_rhs, sp);
     const TileTable *tt64 = tiles_for(ctx, B, n_rhs, g64, &e);
     const TileTable *ttsp = tt64 ? tiles_for(ctx, B, n_rhs, gsp, &e) : nullptr;
     if (!ttsp) return fail(ctx, DD_EDEVICE, std::string("tile tables: ") + hipGetErrorString(e));
@@ -141,7 +144,7 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
     const int np = n_rhs * B->nb;
     const int64_t hel = (B->soff[B->nb] / 2) * 24 * (int64_t)n_rhs;  // elements per half field
     const size_t h64 = (size_t)hel * 8, hsp = (size_t)hel * prec_bytes(sp);
-    const size_t npart = (size_t)std::max({tt64->ntiles, ttsp->ntiles, 1}) * n_rhs * kNRed * sizeof(double);
+    const size_t npart = (size_t)std::max({tt64->ntiles * g64, ttsp->ntiles * gsp, 1}) * kNRed * sizeof(double);
 
     Ws w;
     std::memset(&w, 0, sizeof(w));

