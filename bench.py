@@ -82,6 +82,24 @@ def cpu_baseline(U, src):
                       "defect correction to 1e-10 (%.1f s wall, %d failed)" % (npairs, dt, fails)}
 
 
+PROFILE = os.path.join(ROOT, "profiles", "k_hop_f32_c2_32x4_12rhs.md")
+
+
+def profiled_traffic():
+    """HBM bytes per launch of the hop from the committed rocprofv3 summary, if it
+    was taken on the current kernel source (else None)."""
+    try:
+        from paper_2211_06902_amd.rocprof_summary import kernel_source_hash
+
+        txt = open(PROFILE).read()
+        js = json.loads(txt.split("```json", 1)[1].split("```", 1)[0])
+        if js.get("kernel_source_sha256_16") != kernel_source_hash():
+            return None
+        return js["hbm_traffic_bytes_per_launch"]
+    except (OSError, IndexError, KeyError, ValueError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -180,7 +198,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": profiled_traffic() if args.inner == "f32" else None,
             "launches": hop_n,
             "avg_launch_us": hop_ms * 1e3 / max(hop_n, 1),
             "alg_bytes_per_launch": hop_bytes / max(hop_n, 1),

@@ -1,0 +1,139 @@
+"""Summarise rocprofv3 output of the benchmark into a short text file under profiles/.
+
+    python -m paper_2211_06902_amd.rocprof_summary --stats DIR --fetch DIR --write DIR \
+        --copy-fetch DIR --copy-write DIR --kernel k_hop<float --out profiles/NAME.md \
+        --command "..." [--bench-json FILE]
+
+Inputs are the output directories of
+  rocprofv3 --kernel-trace --stats --output-format csv ...   (per-kernel durations)
+  rocprofv3 --pmc FETCH_SIZE ... / --pmc WRITE_SIZE ...         (per-dispatch KiB)
+of the same benchmark command, and the same two counters on a plain device copy
+of known size (bench.py --copy-calibration: 1 GiB read and written per copy),
+whose ratio to the known bytes scales the counters to bytes.  The summary
+records a hash of the kernel source so that readers can tell whether the
+counters still describe the current kernel.
+"""
+from __future__ import annotations
+
+import argparse
+import collections
+import csv
+import glob
+import hashlib
+import json
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCE = os.path.join(HERE, "csrc", "dd_kernels.hip")
+GIB = float(1 << 30)
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def _one(path_dir: str, pattern: str) -> str:
+    hits = sorted(glob.glob(os.path.join(path_dir, "**", pattern), recursive=True))
+    if not hits:
+        raise FileNotFoundError("%s not found under %s" % (pattern, path_dir))
+    return hits[0]
+
+
+def _counter(path_dir: str, name: str, kernel: str):
+    rows = list(csv.DictReader(open(_one(path_dir, "*counter_collection.csv"))))
+    vals = [float(r["Counter_Value"]) for r in rows if r["Counter_Name"] == name and kernel in r["Kernel_Name"]]
+    return vals
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--stats", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--copy-fetch", required=True)
+    ap.add_argument("--copy-write", required=True)
+    ap.add_argument("--kernel", required=True, help="substring of the kernel name")
+    ap.add_argument("--alg-bytes-per-launch", type=float, required=True)
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--command", required=True)
+    ap.add_argument("--title", default="")
+    args = ap.parse_args()
+
+    stats = list(csv.DictReader(open(_one(args.stats, "*kernel_stats.csv"))))
+    mine = [r for r in stats if args.kernel in r["Name"]]
+    if not mine:
+        raise SystemExit("kernel %r not in stats" % args.kernel)
+    calls = sum(int(r["Calls"]) for r in mine)
+    total_ns = sum(float(r["TotalDurationNs"]) for r in mine)
+    avg_us = total_ns / calls / 1e3
+
+    copy_f = _counter(args.copy_fetch, "FETCH_SIZE", "copyBuffer") or _counter(args.copy_fetch, "FETCH_SIZE", "")
+    copy_w = _counter(args.copy_write, "WRITE_SIZE", "copyBuffer") or _counter(args.copy_write, "WRITE_SIZE", "")
+    big_f = max(copy_f)
+    big_w = max(copy_w)
+    scale_f = GIB / (big_f * 1024.0)  # bytes per reported byte
+    scale_w = GIB / (big_w * 1024.0)
+    fv = _counter(args.fetch, "FETCH_SIZE", args.kernel)
+    wv = _counter(args.write, "WRITE_SIZE", args.kernel)
+    fetch_b = sum(fv) / len(fv) * 1024.0 * scale_f
+    write_b = sum(wv) / len(wv) * 1024.0 * scale_w
+    traffic = fetch_b + write_b
+    achieved = args.alg_bytes_per_launch / (avg_us * 1e-6) / 1e9
+
+    summary = {
+        "kernel": args.kernel,
+        "kernel_source_sha256_16": kernel_source_hash(),
+        "launches": calls,
+        "avg_duration_us": avg_us,
+        "alg_bytes_per_launch": args.alg_bytes_per_launch,
+        "achieved_alg_GBs": achieved,
+        "hbm_fetch_bytes_per_launch": fetch_b,
+        "hbm_write_bytes_per_launch": write_b,
+        "hbm_traffic_bytes_per_launch": traffic,
+        "traffic_over_alg": traffic / args.alg_bytes_per_launch,
+        "fetch_scale": scale_f,
+        "write_scale": scale_w,
+    }
+    top = sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:12]
+    lines = [
+        "# %s" % (args.title or "rocprofv3 summary: " + args.kernel),
+        "",
+        "Command (run from the repository root on one MI355X; `cd /tmp && export TMPDIR=/tmp` first):",
+        "",
+        "```",
+        args.command,
+        "```",
+        "",
+        "## Dominant kernel",
+        "",
+        "| quantity | value |",
+        "|---|---|",
+        "| kernel (name contains) | `%s` |" % args.kernel,
+        "| launches | %d |" % calls,
+        "| average duration | %.1f us |" % avg_us,
+        "| algorithmic bytes per launch | %.4g |" % args.alg_bytes_per_launch,
+        "| achieved algorithmic bandwidth | %.0f GB/s (%.1f %% of 8 TB/s) |" % (achieved, achieved / 80.0),
+        "| HBM fetch per launch (FETCH_SIZE x %.3f) | %.4g B |" % (scale_f, fetch_b),
+        "| HBM write per launch (WRITE_SIZE x %.3f) | %.4g B |" % (scale_w, write_b),
+        "| HBM traffic / algorithmic bytes | %.3f |" % (traffic / args.alg_bytes_per_launch),
+        "| kernel source sha256[:16] | %s |" % summary["kernel_source_sha256_16"],
+        "",
+        "Calibration: a 1 GiB device copy reads FETCH_SIZE = %.0f KiB and WRITE_SIZE = %.0f KiB per copy." % (big_f, big_w),
+        "",
+        "## Kernel time (all kernels of the run, top 12)",
+        "",
+        "| kernel | calls | total ms | avg us | % |",
+        "|---|---|---|---|---|",
+    ]
+    for r in top:
+        lines.append("| `%s` | %s | %.2f | %.1f | %.1f |" % (r["Name"][:70], r["Calls"], float(r["TotalDurationNs"]) / 1e6,
+                                                       float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
+    lines += ["", "```json", json.dumps(summary, indent=1), "```", ""]
+    with open(args.out, "w") as f:
+        f.write("\n".join(lines))
+    print(json.dumps(summary))
+
+
+if __name__ == "__main__":
+    main()
