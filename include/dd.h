@@ -169,13 +169,14 @@ enum { DD_BICGSTAB = 0, DD_GMRES = 1 };
 typedef struct {
     double tol;          /* per-pair true relative residual |b - D x| / |b| (FP64), e.g. 1e-10 */
     int32_t method;      /* DD_BICGSTAB (even-odd BiCGStab) or DD_GMRES (even-odd GMRES(restart)) */
-    int32_t restart;     /* GMRES restart length (<= 32) */
+    int32_t restart;     /* GMRES restart length, 1..16 (default 16) */
     dd_prec inner_prec;  /* stencil precision of the inner solve */
     double inner_tol;    /* relative tolerance of each inner solve (<= 0: library default) */
     int32_t max_outer;   /* defect-correction cycles (<= 0: default 30) */
     int32_t max_inner;   /* iterations per inner solve (<= 0: default 2000) */
-    int32_t check_every; /* inner iterations between convergence polls (<= 0: default 8) */
-    int32_t use_graph;   /* replay inner iterations from a captured hipGraph */
+    int32_t check_every; /* BiCGStab: inner iterations between convergence polls (<= 0: default 8) */
+    int32_t use_graph;   /* replay inner iterations (BiCGStab) or the persistent inner launch
+                            (GMRES) from a captured hipGraph */
 } dd_solve_params;
 
 typedef struct {
@@ -184,7 +185,8 @@ typedef struct {
     int32_t *flags;       /* [n_rhs*n_blocks] bit 0 converged, bit 1 breakdown seen, bit 2 non-finite (may be NULL) */
     double seconds;       /* wall time of the call */
     int32_t outer_cycles; /* defect-correction cycles run */
-    int64_t inner_iterations; /* inner iterations launched (max over pairs per cycle, summed) */
+    int64_t inner_iterations; /* BiCGStab: inner iterations launched (summed over cycles);
+                                 GMRES: largest per-pair total of Krylov steps */
 } dd_solve_stats;
 
 /* Fill p with the defaults (tol 1e-10, BiCGStab, restart 16, FP32 inner). */
@@ -227,7 +229,22 @@ dd_status dd_multiboson_action(dd_ctx *ctx, const dd_blocks *blocks, const dd_ga
  * summation order, which is fixed for a given setting. */
 /* DD_TUNE_HOP_LDS: 1 (default) stages each hop tile's chunk of the input
  * field in LDS, 0 reads every neighbour from global memory. */
-enum { DD_TUNE_RHS_GROUP_F64 = 0, DD_TUNE_RHS_GROUP_F32 = 1, DD_TUNE_HOP_LDS = 2 };
+/* Schedule of the persistent GMRES solver (0 = default):
+ * DD_TUNE_GMRES_THREADS  threads per workgroup, 256 or 512;
+ * DD_TUNE_GMRES_QUEUES   work queues, 1 (one global queue) or 8 (one per XCD:
+ *                        a block's right-hand sides go to one XCD);
+ * DD_TUNE_GMRES_WG_PER_CU resident workgroups per compute unit, at most what
+ *                        fits.  Results depend on the threads per workgroup
+ *                        only through the fixed summation order of the
+ *                        workgroup's dot products. */
+enum {
+    DD_TUNE_RHS_GROUP_F64 = 0,
+    DD_TUNE_RHS_GROUP_F32 = 1,
+    DD_TUNE_HOP_LDS = 2,
+    DD_TUNE_GMRES_THREADS = 3,
+    DD_TUNE_GMRES_QUEUES = 4,
+    DD_TUNE_GMRES_WG_PER_CU = 5
+};
 dd_status dd_tune_set(dd_ctx *ctx, int32_t what, int32_t value);
 
 /* ------------------------------------------------------------ timing */

@@ -403,6 +403,11 @@ dd_status dd_free_blocks(dd_blocks *B)
         if (kv.second.d_blk_tile0) hipFree(kv.second.d_blk_tile0);
         if (kv.second.d_chunk) hipFree(kv.second.d_chunk);
     }
+    for (auto &kv : B->queues) {
+        if (kv.second.d_queue) hipFree(kv.second.d_queue);
+        if (kv.second.d_qoff) hipFree(kv.second.d_qoff);
+        if (kv.second.d_qctr) hipFree(kv.second.d_qctr);
+    }
     delete B;
     return DD_OK;
 }
@@ -547,6 +552,22 @@ dd_status dd_tune_set(dd_ctx *ctx, int32_t what, int32_t value)
     if (!ctx) return DD_EINVAL;
     if (what == DD_TUNE_HOP_LDS) {
         ctx->hop_lds = value != 0;
+        return DD_OK;
+    }
+    if (what == DD_TUNE_GMRES_THREADS) {
+        if (value != 0 && value != 256 && value != 512)
+            return fail(ctx, DD_EINVAL, "GMRES threads per workgroup must be 0, 256 or 512");
+        ctx->gm_threads = value;
+        return DD_OK;
+    }
+    if (what == DD_TUNE_GMRES_QUEUES) {
+        if (value != 0 && value != 1 && value != 8) return fail(ctx, DD_EINVAL, "GMRES queues must be 0, 1 or 8");
+        ctx->gm_queues = value;
+        return DD_OK;
+    }
+    if (what == DD_TUNE_GMRES_WG_PER_CU) {
+        if (value < 0 || value > 64) return fail(ctx, DD_EINVAL, "GMRES workgroups per CU must be in 0..64");
+        ctx->gm_wg_per_cu = value;
         return DD_OK;
     }
     if (what != DD_TUNE_RHS_GROUP_F64 && what != DD_TUNE_RHS_GROUP_F32)

@@ -1,0 +1,467 @@
+// Persistent batched GMRES(m) for the even-odd reduced block systems
+// Dhat e = f, Dhat = 1 - kappa^2 H_eo H_oe, one system per (block, rhs) pair.
+//
+// One workgroup solves one pair at a time, entirely on chip: the two eo hops
+// of Dhat, classical Gram-Schmidt applied twice (CGS2) with FP64 dot
+// products and FP64 vector updates, the Hessenberg matrix, complex Givens
+// rotations, the residual estimate and the back substitution all stay inside
+// the workgroup, so a pair needs no kernel launch per Krylov step and no
+// host round trip.  A fixed grid of workgroups (as many as fit on the chip)
+// pulls pairs from work queues with a global atomic counter until the queues
+// are empty; blocks of uneven size are balanced by the queue order (largest
+// first), and with one queue per XCD a block's right-hand sides are solved by
+// workgroups of one XCD, so that they share the block's links in one L2.
+//
+// Vectors of a pair are component-major with the site innermost (stride h,
+// the block's sites per parity), in the library's half-field layout for the
+// caller's f and e and in per-workgroup basis slots of the workspace.
+#include <hip/hip_runtime.h>
+
+#include "dd_internal.h"
+#include "dd_stencil.h"
+
+namespace dd {
+
+namespace {
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum of v over the workgroup, returned to every thread: a butterfly inside
+// each wavefront, then the wavefronts in order (a fixed order).
+template <int NT>
+__device__ __forceinline__ double wg_sum1(double v, double *red)
+{
+    constexpr int NW = NT / 64;
+    const double s = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    double t = 0;
+#pragma unroll
+    for (int w = 0; w < NW; w++) t += red[w];
+    __syncthreads();
+    return t;
+}
+
+// The workgroup's basis slot: M + 2 vectors behind one buffer descriptor,
+// vector i at byte offset i * vbytes (an SGPR offset of the buffer loads).
+struct Slot {
+    Buf b;
+    uint32_t vbytes;
+};
+
+struct PairGeo {
+    int h;               // sites per parity
+    const int32_t *nbr;  // the block shape's neighbour table [parity][h][8]
+    Buf lk_b;            // the block's links
+    uint32_t kstr;       // bytes between link entries
+};
+
+// out = c_hop (H in) + c_self self + c_add add on the sites of parity p of
+// one pair (`in` on the other parity); self and add may be null.  Returns the
+// thread's share of |out|^2.  The caller separates it from readers of `out`
+// at other sites with a barrier.
+template <typename SP, typename LK, int NT>
+__device__ __forceinline__ double wg_hop(const PairGeo &g, int p, const SP *in, SP *out, const SP *self, double c_self,
+                                         double c_hop, const SP *add, double c_add)
+{
+    using AC = SP;
+    HopCtx hc;
+    hc.h0 = 0;
+    hc.tv = 0;
+    hc.grp_off = 0;
+    hc.cstr = (uint32_t)g.h * (uint32_t)sizeof(SP);
+    hc.kstr = g.kstr;
+    hc.in_b = make_buf(in, (uint32_t)(24 * g.h) * (uint32_t)sizeof(SP));
+    hc.lk_b = g.lk_b;
+    hc.other0 = (1 - p) * g.h;
+    const AC ch = (AC)c_hop, cs = (AC)c_self, ca = (AC)c_add;
+    double nn = 0;
+    for (int s = threadIdx.x; s < g.h; s += NT) {
+        const int4 *q = reinterpret_cast<const int4 *>(g.nbr + (size_t)(p * g.h + s) * 8);
+        const int4 a0 = q[0], a1 = q[1];
+        hc.slot_self = p * g.h + s;
+        AC acc[1][24];
+#pragma unroll
+        for (int c = 0; c < 24; c++) acc[0][c] = 0;
+        hop_one<0, true, SP, LK, AC, 1, false>(acc, a0.x, nullptr, hc);
+        hop_one<0, false, SP, LK, AC, 1, false>(acc, a0.y, nullptr, hc);
+        hop_one<1, true, SP, LK, AC, 1, false>(acc, a0.z, nullptr, hc);
+        hop_one<1, false, SP, LK, AC, 1, false>(acc, a0.w, nullptr, hc);
+        hop_one<2, true, SP, LK, AC, 1, false>(acc, a1.x, nullptr, hc);
+        hop_one<2, false, SP, LK, AC, 1, false>(acc, a1.y, nullptr, hc);
+        hop_one<3, true, SP, LK, AC, 1, false>(acc, a1.z, nullptr, hc);
+        hop_one<3, false, SP, LK, AC, 1, false>(acc, a1.w, nullptr, hc);
+#pragma unroll 4
+        for (int c = 0; c < 24; c++) {
+            const size_t o = (size_t)c * g.h + s;
+            AC v = ch * acc[0][c];
+            if (self) v = fmad(cs, self[o], v);
+            if (add) v = fmad(ca, add[o], v);
+            const SP ov = (SP)v;
+            out[o] = ov;
+            nn += (double)ov * (double)ov;
+        }
+    }
+    return nn;
+}
+
+// out[2i] + i out[2i+1] = <V_i, V_iw> = sum conj(V_i) V_iw for i <= j, FP64
+// products and sums.  The basis vectors are dealt to the wavefronts
+// round-robin and every wavefront runs over all of V_iw (whose repeated reads
+// hit the cache), so each V_i is read once and each sum has one owner.  With
+// norm, out[NV - 1] = |V_iw|^2 (from the last wavefront).  Ends with a barrier.
+template <typename SP, int M, int NT, int NV>
+__device__ __forceinline__ void gs_dots(const Slot &sl, int iw, int h, int j, bool norm, double *out)
+{
+    constexpr int NW = NT / 64, K = (M + NW) / NW;
+    const int lane = threadIdx.x & 63, wave = uni(threadIdx.x >> 6);
+    const bool do_norm = norm && wave == NW - 1;
+    double d[2 * K], nn = 0;
+#pragma unroll
+    for (int k = 0; k < 2 * K; k++) d[k] = 0;
+    const uint32_t hb = (uint32_t)h * (uint32_t)sizeof(SP), wo = (uint32_t)iw * sl.vbytes;
+#pragma unroll 1
+    for (int cc = 0; cc < 12; cc++)
+#pragma unroll 1
+        for (int s = lane; s < h; s += 64) {
+            const uint32_t vo = (uint32_t)(2 * cc * h + s) * (uint32_t)sizeof(SP);
+            const double wr = (double)bload<SP>(sl.b, vo, wo), wi = (double)bload<SP>(sl.b, vo, wo + hb);
+#pragma unroll
+            for (int k = 0; k < K; k++) {
+                const int i = wave + k * NW;
+                if (i <= j) {
+                    const uint32_t io = (uint32_t)i * sl.vbytes;
+                    const double vr = (double)bload<SP>(sl.b, vo, io), vi = (double)bload<SP>(sl.b, vo, io + hb);
+                    d[2 * k] = fma(vr, wr, fma(vi, wi, d[2 * k]));
+                    d[2 * k + 1] = fma(vr, wi, fma(-vi, wr, d[2 * k + 1]));
+                }
+            }
+            if (do_norm) nn = fma(wr, wr, fma(wi, wi, nn));
+        }
+#pragma unroll
+    for (int k = 0; k < K; k++) {
+        const int i = wave + k * NW;
+        if (i <= j) {
+            const double re = wave_sum(d[2 * k]), im = wave_sum(d[2 * k + 1]);
+            if (lane == 0) {
+                out[2 * i] = re;
+                out[2 * i + 1] = im;
+            }
+        }
+    }
+    if (do_norm) {
+        const double s = wave_sum(nn);
+        if (lane == 0) out[NV - 1] = s;
+    }
+    __syncthreads();
+}
+
+// dst = (dst + sgn * sum_{i<n} c_i V_i) * scale with complex c_i from LDS (read
+// as used, so that they take no registers), FP64 arithmetic, stored in SP; dst is
+// a buffer and the byte offset of the vector in it.  Each thread updates its
+// own elements: no barrier inside.
+template <typename SP, int M, int NT>
+__device__ __forceinline__ void combine(const Slot &sl, const Buf &db, uint32_t dso, int h, int n, const double *c,
+                                        double sgn, double scale)
+{
+    const uint32_t hb = (uint32_t)h * (uint32_t)sizeof(SP);
+#pragma unroll 1
+    for (int cc = 0; cc < 12; cc++)
+#pragma unroll 1
+        for (int s = threadIdx.x; s < h; s += NT) {
+            // compiler-only fence: the coefficients are re-read from LDS in every
+            // iteration instead of being held in registers across the loop
+            __asm__ volatile("" ::: "memory");
+            const uint32_t vo = (uint32_t)(2 * cc * h + s) * (uint32_t)sizeof(SP);
+            double wr = (double)bload<SP>(db, vo, dso), wi = (double)bload<SP>(db, vo, dso + hb);
+#pragma unroll
+            for (int i = 0; i <= M; i++)
+                if (i < n) {
+                    const uint32_t io = (uint32_t)i * sl.vbytes;
+                    const double vr = (double)bload<SP>(sl.b, vo, io), vi = (double)bload<SP>(sl.b, vo, io + hb);
+                    const double cr = sgn * c[2 * i], ci = sgn * c[2 * i + 1];
+                    wr = fma(cr, vr, fma(-ci, vi, wr));
+                    wi = fma(cr, vi, fma(ci, vr, wi));
+                }
+            bstore<SP>(db, (SP)(wr * scale), vo, dso);
+            bstore<SP>(db, (SP)(wi * scale), vo, dso + hb);
+        }
+}
+
+// Stop codes of a Krylov step
+enum { kGoOn = 0, kRestart = 1, kConverged = 2, kMaxIter = 3, kNonFinite = 4 };
+
+}  // namespace
+
+// One launch solves every pair listed in the queues whose `active` flag is set
+// and leaves e = Dhat^{-1} f (to the relative tolerance, or the last iterate)
+// in x; every workgroup leaves the loop once all queues are drained.
+template <typename SP, typename LK, int M, int NT>
+__global__ void __launch_bounds__(NT) k_gmres(GmArgs a)
+{
+    constexpr int NW = NT / 64;
+    constexpr int NV = 2 * (M + 1) + 1;
+    static_assert(NV <= NT, "one thread per reduced value");
+    __shared__ double red[NW];
+    __shared__ double sum[NV];
+    __shared__ double Hm[(M + 1) * M * 2];  // Hm[(i * M + j) * 2 + ri], row i, column j
+    __shared__ double cs[M], sn[2 * M], gv[2 * (M + 1)], yv[2 * (M + 1)];
+    __shared__ int s_pair, s_stop;
+    __shared__ double s_est;
+
+    SP *V = reinterpret_cast<SP *>(a.ws) + (int64_t)blockIdx.x * (M + 2) * a.vstr;
+    SP *tmp = V + (int64_t)(M + 1) * a.vstr;
+    Slot sl;
+    sl.vbytes = (uint32_t)a.vstr * (uint32_t)sizeof(SP);
+    sl.b = make_buf(V, (uint32_t)(M + 2) * sl.vbytes);
+    const int m = a.m;
+    const double k2 = a.k2;
+    int tried = 0;  // thread 0: queues found empty so far
+    const int q0 = (int)(blockIdx.x % (unsigned)a.nq);
+    for (;;) {
+        if (threadIdx.x == 0) {
+            int pr = -1;
+            while (tried < a.nq) {
+                const int qq = (q0 + tried) % a.nq;
+                const int k = atomicAdd(a.qctr + qq, 1);
+                if (k < a.qoff[qq + 1] - a.qoff[qq]) {
+                    pr = a.queue[a.qoff[qq] + k];
+                    break;
+                }
+                tried++;
+            }
+            s_pair = pr;
+        }
+        __syncthreads();
+        const int pair = uni(s_pair);
+        __syncthreads();
+        if (pair < 0) break;
+        if (!a.active[pair]) continue;
+
+        const int b = pair % a.nb, r = pair / a.nb;
+        const int h = uni(a.h[b]);
+        const int64_t so = uni64(a.soff[b]);
+        PairGeo g;
+        g.h = h;
+        g.nbr = a.nbr + uni64(a.nbr_off[b]);
+        g.kstr = (uint32_t)(4 * h) * (uint32_t)sizeof(LK);
+        g.lk_b = make_buf(reinterpret_cast<const LK *>(a.links) + so * 72, (uint32_t)(2 * h * 72) * (uint32_t)sizeof(LK));
+        const int64_t pb = (so >> 1) * 24 * a.n_rhs + (int64_t)r * 24 * h;
+        const SP *f = reinterpret_cast<const SP *>(a.rhs) + pb;
+        SP *x = reinterpret_cast<SP *>(a.x) + pb;
+        const int n = 24 * h;
+
+        // beta0 = |f|; x = 0; V_0 = f / beta0
+        double nn = 0;
+        for (int e = threadIdx.x; e < n; e += NT) {
+            const double v = (double)f[e];
+            nn = fma(v, v, nn);
+        }
+        const double beta0 = sqrt(wg_sum1<NT>(nn, red));
+        const bool ok0 = isfinite(beta0) && beta0 > 0;
+        const double inv0 = ok0 ? 1.0 / beta0 : 0.0;
+        for (int e = threadIdx.x; e < n; e += NT) {
+            V[e] = (SP)((double)f[e] * inv0);
+            x[e] = (SP)0;
+        }
+        __syncthreads();
+        int it = 0, stop = ok0 ? kGoOn : (beta0 == 0 ? kConverged : kNonFinite);
+        double est = ok0 ? beta0 : 0.0;
+        double beta = beta0;
+        while (stop == kGoOn || stop == kRestart) {
+            if (threadIdx.x == 0) {
+                for (int i = 0; i <= M; i++) gv[2 * i] = gv[2 * i + 1] = 0;
+                gv[0] = beta;
+            }
+            int k = 0;
+            stop = kGoOn;
+            for (int j = 0; j < m && stop == kGoOn; j++) {
+                SP *vj = V + (int64_t)j * a.vstr, *w = V + (int64_t)(j + 1) * a.vstr;
+                // w = Dhat v_j
+                wg_hop<SP, LK, NT>(g, 1, vj, tmp, nullptr, 0.0, 1.0, nullptr, 0.0);
+                __syncthreads();
+                wg_hop<SP, LK, NT>(g, 0, tmp, w, vj, 1.0, -k2, nullptr, 0.0);
+                __syncthreads();
+                // first Gram-Schmidt pass: h = V^H w, w -= V h
+                gs_dots<SP, M, NT, NV>(sl, j + 1, h, j, false, sum);
+                if (threadIdx.x == 0)
+                    for (int i = 0; i <= j; i++) {
+                        Hm[(i * M + j) * 2] = sum[2 * i];
+                        Hm[(i * M + j) * 2 + 1] = sum[2 * i + 1];
+                    }
+                const uint32_t wso = (uint32_t)(j + 1) * sl.vbytes;
+                combine<SP, M, NT>(sl, sl.b, wso, h, j + 1, sum, -1.0, 1.0);
+                __syncthreads();
+                // second pass: the corrections c = V^H w and |w|^2
+                gs_dots<SP, M, NT, NV>(sl, j + 1, h, j, true, sum);
+                // |w - V c|^2 = |w|^2 - |c|^2 for orthonormal V; c is a rounding-level correction
+                double c2 = 0;
+                for (int i = 0; i <= j; i++) c2 += sum[2 * i] * sum[2 * i] + sum[2 * i + 1] * sum[2 * i + 1];
+                const double hn = sqrt(fmax(sum[NV - 1] - c2, 0.0));
+                if (threadIdx.x == 0) {
+                    for (int i = 0; i <= j; i++) {
+                        Hm[(i * M + j) * 2] += sum[2 * i];
+                        Hm[(i * M + j) * 2 + 1] += sum[2 * i + 1];
+                    }
+                    // previous rotations on column j: (a, b) <- (c a + s b, -conj(s) a + c b)
+                    for (int i = 0; i < j; i++) {
+                        double *pa = Hm + (i * M + j) * 2, *pb2 = Hm + ((i + 1) * M + j) * 2;
+                        const double ar = pa[0], ai = pa[1], br = pb2[0], bi = pb2[1];
+                        const double sr = sn[2 * i], si = sn[2 * i + 1], cc = cs[i];
+                        pa[0] = cc * ar + (sr * br - si * bi);
+                        pa[1] = cc * ai + (sr * bi + si * br);
+                        pb2[0] = cc * br - (sr * ar + si * ai);
+                        pb2[1] = cc * bi - (sr * ai - si * ar);
+                    }
+                    // new rotation zeroing the real subdiagonal hn below a = Hm[j][j]
+                    double *pd = Hm + (j * M + j) * 2;
+                    const double ar = pd[0], ai = pd[1];
+                    const double aa = sqrt(ar * ar + ai * ai);
+                    double cc, sr, si;
+                    if (aa == 0.0) {
+                        cc = 0.0;
+                        sr = 1.0;
+                        si = 0.0;
+                        pd[0] = hn;
+                        pd[1] = 0.0;
+                    } else {
+                        const double t = sqrt(aa * aa + hn * hn);
+                        cc = aa / t;
+                        sr = ar / aa * (hn / t);
+                        si = ai / aa * (hn / t);
+                        pd[0] = ar / aa * t;
+                        pd[1] = ai / aa * t;
+                    }
+                    cs[j] = cc;
+                    sn[2 * j] = sr;
+                    sn[2 * j + 1] = si;
+                    const double gr = gv[2 * j], gi = gv[2 * j + 1];
+                    gv[2 * j] = cc * gr;
+                    gv[2 * j + 1] = cc * gi;
+                    gv[2 * j + 2] = -(sr * gr + si * gi);
+                    gv[2 * j + 3] = -(sr * gi - si * gr);
+                    const double e2 = sqrt(gv[2 * j + 2] * gv[2 * j + 2] + gv[2 * j + 3] * gv[2 * j + 3]);
+                    int st = kGoOn;
+                    if (!isfinite(e2) || !isfinite(hn) || !isfinite(pd[0]) || !isfinite(pd[1])) st = kNonFinite;
+                    else if (e2 <= a.tol * beta0 || !(hn > 0.0)) st = kConverged;
+                    else if (it + 1 >= a.max_iter) st = kMaxIter;
+                    else if (j + 1 == m) st = kRestart;
+                    s_stop = st;
+                    s_est = e2;
+                }
+                // third pass: v_{j+1} = (w - V c) / hn (skipped on breakdown)
+                const double inv = hn > 0.0 && isfinite(hn) ? 1.0 / hn : 0.0;
+                if (inv > 0.0) combine<SP, M, NT>(sl, sl.b, wso, h, j + 1, sum, -1.0, inv);
+                __syncthreads();
+                stop = s_stop;
+                if (stop != kNonFinite) {
+                    est = s_est;
+                    k = j + 1;
+                }
+                it++;
+                __syncthreads();
+            }
+            // x += V y with R y = g (back substitution on the rotated Hessenberg matrix)
+            if (k > 0) {
+                if (threadIdx.x == 0) {
+                    for (int i = k - 1; i >= 0; i--) {
+                        double sr = gv[2 * i], si = gv[2 * i + 1];
+                        for (int l = i + 1; l < k; l++) {
+                            const double hr = Hm[(i * M + l) * 2], hi = Hm[(i * M + l) * 2 + 1];
+                            sr -= hr * yv[2 * l] - hi * yv[2 * l + 1];
+                            si -= hr * yv[2 * l + 1] + hi * yv[2 * l];
+                        }
+                        const double dr = Hm[(i * M + i) * 2], di = Hm[(i * M + i) * 2 + 1];
+                        const double den = dr * dr + di * di;
+                        yv[2 * i] = (sr * dr + si * di) / den;
+                        yv[2 * i + 1] = (si * dr - sr * di) / den;
+                    }
+                }
+                __syncthreads();
+                combine<SP, M, NT>(sl, make_buf(x, (uint32_t)n * (uint32_t)sizeof(SP)), 0u, h, k, yv, 1.0, 1.0);
+                __syncthreads();
+            }
+            if (stop != kRestart) break;
+            // restart from the explicit residual V_0 = f - Dhat x
+            wg_hop<SP, LK, NT>(g, 1, x, tmp, nullptr, 0.0, 1.0, nullptr, 0.0);
+            __syncthreads();
+            const double rn = wg_hop<SP, LK, NT>(g, 0, tmp, V, x, -1.0, k2, f, 1.0);
+            beta = sqrt(wg_sum1<NT>(rn, red));
+            est = beta;
+            if (!isfinite(beta)) {
+                stop = kNonFinite;
+                break;
+            }
+            if (beta <= a.tol * beta0) {
+                stop = kConverged;
+                break;
+            }
+            const double ib = 1.0 / beta;
+            for (int e = threadIdx.x; e < n; e += NT) V[e] = (SP)((double)V[e] * ib);
+            __syncthreads();
+            stop = kRestart;
+        }
+        if (threadIdx.x == 0) {
+            a.iters[pair] += it;
+            if (stop == kNonFinite) a.flags[pair] |= 4;
+            if (a.relres) a.relres[pair] = beta0 > 0 ? est / beta0 : 0.0;
+        }
+        __syncthreads();
+    }
+}
+
+__global__ void k_fill_i32(int32_t *p, int n, int32_t v)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+namespace {
+
+template <typename SP, typename LK>
+struct GmKernels {
+    static const void *get(int M, int nt)
+    {
+        if (M == 8 && nt == 256) return (const void *)k_gmres<SP, LK, 8, 256>;
+        if (M == 8 && nt == 512) return (const void *)k_gmres<SP, LK, 8, 512>;
+        if (M == 16 && nt == 256) return (const void *)k_gmres<SP, LK, 16, 256>;
+        if (M == 16 && nt == 512) return (const void *)k_gmres<SP, LK, 16, 512>;
+        return nullptr;
+    }
+};
+
+const void *gmres_kernel(dd_prec prec, int M, int nt)
+{
+    if (prec == DD_F64) return GmKernels<double, double>::get(M, nt);
+    if (prec == DD_F32) return GmKernels<float, float>::get(M, nt);
+    if (prec == DD_BF16) return GmKernels<float, uint16_t>::get(M, nt);
+    return nullptr;
+}
+
+}  // namespace
+
+int gmres_basis_m(int restart) { return restart <= 8 ? 8 : 16; }
+
+hipError_t gmres_occupancy(dd_prec prec, int restart, int nt, int *wgs_per_cu)
+{
+    const void *k = gmres_kernel(prec, gmres_basis_m(restart), nt);
+    if (!k) return hipErrorInvalidValue;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(wgs_per_cu, k, nt, 0);
+}
+
+hipError_t launch_gmres(const GmArgs &a, dd_prec prec, int nt, int grid, hipStream_t st)
+{
+    if (a.m < 1 || a.m > 16 || grid < 1 || a.nq < 1) return hipErrorInvalidValue;
+    const void *k = gmres_kernel(prec, gmres_basis_m(a.m), nt);
+    if (!k) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fill_i32, dim3((a.nq + 255) / 256), dim3(256), 0, st, a.qctr, a.nq, 0);
+    void *args[] = {const_cast<GmArgs *>(&a)};
+    return hipLaunchKernel(k, dim3(grid), dim3(nt), args, 0, st);
+}
+
+}  // namespace dd

@@ -46,6 +46,9 @@ struct dd_ctx {
     dd::Timer timers[DD_KCLASS_COUNT];
     int rhs_group[2] = {0, 0};  // forced rhs per thread for FP64 / FP32 spinors (0 = automatic)
     bool hop_lds = true;        // stage the hop's chunk of the input in LDS
+    int gm_threads = 0;         // persistent GMRES: threads per workgroup (0 = default)
+    int gm_queues = 0;          // persistent GMRES: work queues, 1 or 8 (0 = default)
+    int gm_wg_per_cu = 0;       // persistent GMRES: resident workgroups per CU (0 = all that fit)
 };
 
 namespace dd {
@@ -72,6 +75,16 @@ struct TileTable {
     int32_t *d_blk_tile0 = nullptr;   // block -> first tile (n_blocks + 1 entries)
     int32_t *d_chunk = nullptr;       // sites per chunk of each block
     std::vector<int32_t> blk_tile0;
+};
+
+// Work queues of the persistent solver: the (block, rhs) pairs split into nq
+// queues (one per XCD, or a single one), each ordered largest block first
+// with a block's right-hand sides adjacent.
+struct QueueTable {
+    int nq = 0;
+    int32_t *d_queue = nullptr;  // pairs, queue after queue
+    int32_t *d_qoff = nullptr;   // [nq + 1] queue offsets
+    int32_t *d_qctr = nullptr;   // [nq] counters (cleared by every launch)
 };
 
 }  // namespace dd
@@ -104,6 +117,7 @@ struct dd_blocks {
     int32_t *d_bnd = nullptr;       // [total bnd] box-local canonical index
     int64_t *d_boff = nullptr;      // [nb+1]
     std::map<int, dd::TileTable> tiles;  // keyed by (n_rhs, rhs per thread)
+    std::map<int, dd::QueueTable> queues;  // keyed by (n_rhs, number of queues)
 };
 
 struct dd_gauge {
@@ -174,6 +188,40 @@ struct OuterState {
     int32_t *active;    // [np] still above tolerance
     int32_t *flags;     // [np]
 };
+
+// Arguments of the persistent GMRES kernel: every pair listed in the queues
+// with active[pair] set solves Dhat e = f in the inner precision, e in x.
+struct GmArgs {
+    const int32_t *h;         // [nb] sites per parity
+    const int64_t *soff;      // [nb + 1] site offsets
+    const int64_t *nbr_off;   // [nb] neighbour-table offsets
+    const int32_t *nbr;
+    int nb, n_rhs;
+    const void *links;        // inner-precision links
+    const void *rhs;          // f: even half field (SP)
+    void *x;                  // e: even half field (SP), overwritten
+    const int32_t *active;    // [np]
+    const int32_t *queue;
+    const int32_t *qoff;
+    int32_t *qctr;
+    int nq;
+    void *ws;                 // basis slots: grid x (basis vectors) x vstr elements
+    int64_t vstr;             // elements per basis vector (24 * largest h)
+    double k2;                // kappa^2
+    double tol;               // relative residual of the inner solve
+    int m;                    // restart length
+    int max_iter;             // Krylov steps per pair and launch
+    int32_t *iters;           // [np] += steps taken
+    int32_t *flags;           // [np] |= 4 on a non-finite value
+    double *relres;           // [np] last residual estimate / |f| (may be null)
+};
+
+// basis vectors the kernel for restart length m keeps per workgroup (its
+// compile-time bound plus one)
+int gmres_basis_m(int restart);
+hipError_t gmres_occupancy(dd_prec prec, int restart, int nt, int *wgs_per_cu);
+hipError_t launch_gmres(const GmArgs &a, dd_prec prec, int nt, int grid, hipStream_t st);
+hipError_t gmres_schedule(dd_ctx *ctx, dd_prec ip, int restart, int np, int *nt, int *nq, int *grid);
 
 // launch wrappers (dd_kernels.hip)
 hipError_t launch_pack_gauge(const dd_blocks *B, const double *U, dd_prec prec, void *dst,

@@ -5,12 +5,16 @@
 //   outer: FP64 defect correction on the true residual r = b - D_Lambda x,
 //          computed with FP64 links and spinors, until |r| <= tol |b| per pair;
 //   inner: even-odd reduced system Dhat e_e = r_e + kappa H_eo r_o with
-//          Dhat = 1 - kappa^2 H_eo H_oe, solved by BiCGStab in the inner
-//          precision (FP64, FP32, or FP32 spinors with BF16 links), then
+//          Dhat = 1 - kappa^2 H_eo H_oe, solved in the inner precision (FP64,
+//          FP32, or FP32 spinors with BF16 links), then
 //          e_o = r_o + kappa H_oe e_e and x += e.
-// Every launch covers all blocks and right-hand sides; per-pair scalars live
-// on the device and pairs that converge are frozen.  Hop launches always cover
-// every pair so that their cost per launch is fixed.
+// Inner methods:
+//   BiCGStab: every launch covers all blocks and right-hand sides; per-pair
+//          scalars live on the device and pairs that converge are frozen.  Hop
+//          launches always cover every pair so that their cost per launch is
+//          fixed.
+//   GMRES(m): one persistent launch per defect-correction cycle; each
+//          workgroup solves whole pairs taken from work queues.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -87,7 +91,63 @@ double default_inner_tol(dd_prec ip, double tol)
     return 2e-3;
 }
 
+// Work queues for the persistent solver: blocks are dealt to the nq queues
+// largest first, each to the queue with the least work so far (sites x
+// rhs); a block's right-hand sides stay adjacent in its queue.
+const QueueTable *queues_for(dd_blocks *B, int nr, int nq, hipError_t *err)
+{
+    *err = hipSuccess;
+    const int key = nr * 16 + nq;
+    auto it = B->queues.find(key);
+    if (it != B->queues.end()) return &it->second;
+    std::vector<int> order(B->nb);
+    for (int b = 0; b < B->nb; b++) order[b] = b;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return B->shapes[B->shape_of[a]].h > B->shapes[B->shape_of[b]].h;
+    });
+    std::vector<std::vector<int32_t>> q(nq);
+    std::vector<int64_t> load(nq, 0);
+    for (int b : order) {
+        const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        for (int r = 0; r < nr; r++) q[k].push_back(r * B->nb + b);
+        load[k] += (int64_t)B->shapes[B->shape_of[b]].h * nr;
+    }
+    std::vector<int32_t> flat, off(1, 0);
+    for (auto &v : q) {
+        flat.insert(flat.end(), v.begin(), v.end());
+        off.push_back((int32_t)flat.size());
+    }
+    QueueTable qt;
+    qt.nq = nq;
+    if ((*err = upload(&qt.d_queue, flat)) != hipSuccess) return nullptr;
+    if ((*err = upload(&qt.d_qoff, off)) != hipSuccess) return nullptr;
+    if ((*err = upload(&qt.d_qctr, std::vector<int32_t>(nq, 0))) != hipSuccess) return nullptr;
+    return &(B->queues[key] = qt);
+}
+
 }  // namespace
+
+namespace dd {
+
+// Launch shape of the persistent GMRES kernel: threads per workgroup, number
+// of work queues and resident workgroups (grid), from the context's settings
+// (dd_tune_set, dd_autotune_gmres) or the defaults.
+hipError_t gmres_schedule(dd_ctx *ctx, dd_prec ip, int restart, int np, int *nt, int *nq, int *grid)
+{
+    *nt = ctx->gm_threads > 0 ? ctx->gm_threads : 256;
+    *nq = ctx->gm_queues > 0 ? ctx->gm_queues : 8;
+    int occ = 0;
+    hipError_t e = gmres_occupancy(ip, restart, *nt, &occ);
+    if (e != hipSuccess) return e;
+    if (occ < 1) return hipErrorInvalidConfiguration;
+    int ncu = 0;
+    if ((e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device)) != hipSuccess) return e;
+    const int wpc = ctx->gm_wg_per_cu > 0 ? std::min(ctx->gm_wg_per_cu, occ) : occ;
+    *grid = std::max(1, std::min(np, wpc * ncu));
+    return hipSuccess;
+}
+
+}  // namespace dd
 
 extern "C" {
 
@@ -117,7 +177,9 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
     if (params) prm = *params;
     else dd_solve_params_default(&prm);
     if (!(prm.tol > 0)) return fail(ctx, DD_EINVAL, "tol must be positive");
-    if (prm.method != DD_BICGSTAB) return fail(ctx, DD_EUNSUPPORTED, "only DD_BICGSTAB is available");
+    if (prm.method != DD_BICGSTAB && prm.method != DD_GMRES) return fail(ctx, DD_EINVAL, "unknown method");
+    const bool gmres = prm.method == DD_GMRES;
+    if (gmres && (prm.restart < 1 || prm.restart > 16)) return fail(ctx, DD_EINVAL, "restart must be in 1..16");
     const dd_prec ip = prm.inner_prec;
     const void *links = links_for(G, ip);
     if (!links) return fail(ctx, DD_EINVAL, "gauge holds no links of the inner precision");
@@ -168,13 +230,24 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
     }
     w.rhs = get("s_rhs", hsp);
     w.xi = get("s_xi", hsp);
-    w.r = get("s_r", hsp);
-    w.rh = get("s_rh", hsp);
-    w.p = get("s_p", hsp);
-    w.v = get("s_v", hsp);
-    w.s = get("s_s", hsp);
-    w.t = get("s_t", hsp);
     w.tmp = get("s_tmp", hsp);
+    int gm_nt = 0, gm_nq = 0, gm_grid = 0;
+    void *gm_ws = nullptr;
+    const QueueTable *qt = nullptr;
+    const int64_t vstr = 24 * (int64_t)B->max_h;
+    if (gmres) {
+        HIPCHECK(ctx, gmres_schedule(ctx, ip, prm.restart, np, &gm_nt, &gm_nq, &gm_grid));
+        qt = queues_for(B, n_rhs, gm_nq, &e);
+        if (!qt) return fail(ctx, DD_EDEVICE, std::string("work queues: ") + hipGetErrorString(e));
+        gm_ws = get("g_basis", (size_t)gm_grid * (gmres_basis_m(prm.restart) + 2) * vstr * prec_bytes(sp));
+    } else {
+        w.r = get("s_r", hsp);
+        w.rh = get("s_rh", hsp);
+        w.p = get("s_p", hsp);
+        w.v = get("s_v", hsp);
+        w.s = get("s_s", hsp);
+        w.t = get("s_t", hsp);
+    }
     w.pA = (double *)get("s_pA", npart);
     w.pB = (double *)get("s_pB", npart);
     w.pC = (double *)get("s_pC", npart);
@@ -242,6 +315,47 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
             h.c_self = 1.0;
             HIPCHECK(ctx, run_hop(ctx, B, ba, h, ip));
         }
+        if (gmres) {
+            GmArgs ga;
+            ga.h = B->d_h;
+            ga.soff = B->d_soff;
+            ga.nbr_off = B->d_nbr_off;
+            ga.nbr = B->d_nbr;
+            ga.nb = B->nb;
+            ga.n_rhs = n_rhs;
+            ga.links = links;
+            ga.rhs = w.rhs;
+            ga.x = w.xi;
+            ga.active = w.os.active;
+            ga.queue = qt->d_queue;
+            ga.qoff = qt->d_qoff;
+            ga.qctr = qt->d_qctr;
+            ga.nq = qt->nq;
+            ga.ws = gm_ws;
+            ga.vstr = vstr;
+            ga.k2 = kappa * kappa;
+            ga.tol = inner_tol;
+            ga.m = prm.restart;
+            ga.max_iter = max_inner;
+            ga.iters = w.ps.iters;
+            ga.flags = w.ps.flags;
+            ga.relres = nullptr;
+            if (graph) {
+                // one defect-correction cycle's inner solve as a graph: clear the
+                // queue counters, then the persistent launch
+                if (!gx) {
+                    HIPCHECK(ctx, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                    const hipError_t ce = launch_gmres(ga, ip, gm_nt, gm_grid, st);
+                    const hipError_t ee = hipStreamEndCapture(st, &g);
+                    if (ce != hipSuccess) return fail(ctx, DD_EDEVICE, std::string("capture: ") + hipGetErrorString(ce));
+                    HIPCHECK(ctx, ee);
+                    HIPCHECK(ctx, hipGraphInstantiate(&gx, g, nullptr, nullptr, 0));
+                }
+                HIPCHECK(ctx, hipGraphLaunch(gx, st));
+            } else {
+                HIPCHECK(ctx, launch_gmres(ga, ip, gm_nt, gm_grid, st));
+            }
+        } else {
         HIPCHECK(ctx, launch_bicg_init(ba, sp, w.rhs, w.r, w.rh, w.p, w.xi, w.pA, w.os.active, st));
         HIPCHECK(ctx, launch_sc_init(ba, w.pA, w.ps, w.os.active, st));
         if (graph && !gx) {
@@ -265,6 +379,7 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
             int live = 0;
             for (int v : h_act) live += v != 0;
             if (live == 0) break;
+        }
         }
         // e_o = r_o + kappa H_oe e_e, then x += e on the pairs above tolerance
         {
@@ -296,6 +411,7 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
             if (stats->flags) stats->flags[k] = fl;
         }
     }
+    if (gmres) inner_total = np ? *std::max_element(h_it.begin(), h_it.end()) : 0;
     if (stats) {
         stats->outer_cycles = cycles;
         stats->inner_iterations = inner_total;

@@ -1,0 +1,318 @@
+// Device-side building blocks of the Wilson hopping stencil shared by the
+// kernels of libdd: buffer addressing, link loads, the spin projectors of
+// the chiral basis and the projected hop term of one direction.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "dd_internal.h"
+
+namespace dd {
+
+// ------------------------------------------------------------- helpers
+
+__device__ __forceinline__ int xcd_tile(int bid, int n)
+{
+    const int q = n >> 3, rem = n & 7, k = bid & 7, j = bid >> 3;
+    return k * q + min(k, rem) + j;
+}
+
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)(((u >> 16) & 0x8000u) | 0x7fc0u);
+    const uint32_t lsb = (u >> 16) & 1u;
+    return (uint16_t)((u + 0x7fffu + lsb) >> 16);
+}
+
+__device__ __forceinline__ float bf16_to_f32(uint32_t b) { return __uint_as_float(b << 16); }
+
+// Buffer addressing: a descriptor holds a wave-uniform base and size; a load
+// takes a per-lane byte offset (VGPR) plus a wave-uniform byte offset (SGPR),
+// so the 24 components of a spinor (uniform stride) share one VGPR offset and
+// cost no address arithmetic.  Accesses beyond the size read 0 / are dropped.
+struct Buf {
+    __amdgpu_buffer_rsrc_t r;
+};
+__device__ __forceinline__ Buf make_buf(const void *p, uint32_t bytes)
+{
+    return Buf{__builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000)};
+}
+template <typename T>
+__device__ __forceinline__ T bload(const Buf &b, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ float bload<float>(const Buf &b, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.r, (int)voff, (int)soff, 0));
+}
+template <>
+__device__ __forceinline__ double bload<double>(const Buf &b, uint32_t voff, uint32_t soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(b.r, (int)voff, (int)soff, 0));
+}
+template <typename T>
+__device__ __forceinline__ void bstore(const Buf &b, T v, uint32_t voff, uint32_t soff);
+template <>
+__device__ __forceinline__ void bstore<float>(const Buf &b, float v, uint32_t voff, uint32_t soff)
+{
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), b.r, (int)voff, (int)soff, 0);
+}
+template <>
+__device__ __forceinline__ void bstore<double>(const Buf &b, double v, uint32_t voff, uint32_t soff)
+{
+    using u2 = __attribute__((ext_vector_type(2))) uint32_t;
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), b.r, (int)voff, (int)soff, 0);
+}
+
+// Link layout per block: element (site slot s, mu, complex entry k = 3*row + col, re/im)
+// at soff[b]*72 + ((mu*9 + k)*S_b + s)*2 + ri.  Consecutive slots are adjacent, so a
+// wavefront reading entry k of one direction for consecutive sites touches one line.
+// load_link: voff = byte offset of the slot's pair, soff = byte offset of entry 0
+// of direction mu, kstride = bytes between entries.
+template <typename AC>
+__device__ __forceinline__ void load_link(const Buf &b, const double *, uint32_t voff, uint32_t soff,
+                                          uint32_t kstride, AC (&u)[18])
+{
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        const auto q = __builtin_amdgcn_raw_buffer_load_b128(b.r, (int)voff, (int)(soff + k * kstride), 0);
+        u[2 * k] = (AC)__builtin_bit_cast(double, __builtin_shufflevector(q, q, 0, 1));
+        u[2 * k + 1] = (AC)__builtin_bit_cast(double, __builtin_shufflevector(q, q, 2, 3));
+    }
+}
+template <typename AC>
+__device__ __forceinline__ void load_link(const Buf &b, const float *, uint32_t voff, uint32_t soff, uint32_t kstride,
+                                          AC (&u)[18])
+{
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        // take the 8 bytes as one integer: indexing the returned vector lets
+        // the compiler shrink the load to its first dword
+        const uint64_t q =
+            __builtin_bit_cast(uint64_t, __builtin_amdgcn_raw_buffer_load_b64(b.r, (int)voff, (int)(soff + k * kstride), 0));
+        u[2 * k] = (AC)__uint_as_float((uint32_t)q);
+        u[2 * k + 1] = (AC)__uint_as_float((uint32_t)(q >> 32));
+    }
+}
+template <typename AC>
+__device__ __forceinline__ void load_link(const Buf &b, const uint16_t *, uint32_t voff, uint32_t soff,
+                                          uint32_t kstride, AC (&u)[18])
+{
+#pragma unroll
+    for (int k = 0; k < 9; k++) {
+        const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(b.r, (int)voff, (int)(soff + k * kstride), 0);
+        u[2 * k] = (AC)bf16_to_f32(w & 0xffffu);
+        u[2 * k + 1] = (AC)bf16_to_f32(w >> 16);
+    }
+}
+
+// a * b + c in one rounding
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// c * (re, im) for the coefficient codes 0:+1 1:-1 2:+i 3:-i
+template <int CODE, typename AC>
+__device__ __forceinline__ void cmul_code(AC re, AC im, AC &ore, AC &oim)
+{
+    if constexpr (CODE == 0) { ore = re; oim = im; }
+    else if constexpr (CODE == 1) { ore = -re; oim = -im; }
+    else if constexpr (CODE == 2) { ore = -im; oim = re; }
+    else { ore = im; oim = -re; }
+}
+
+// Spin structure of the projected hop (1 -/+ gamma_mu) in the chiral basis.
+// Half spinor: h_s = psi_s + a_s * psi_{pi_s} (s = 0, 1); after the colour
+// multiply W = U h (or U^+ h) the full spinor is (W_0, W_1, b_0 W_{sig_0}, b_1 W_{sig_1}).
+template <int MU, bool FWD> struct Proj;
+template <> struct Proj<0, true>  { static constexpr int pi0 = 2, pi1 = 3, a0 = 0, a1 = 0, s0 = 0, s1 = 1, b0 = 0, b1 = 0; };
+template <> struct Proj<0, false> { static constexpr int pi0 = 2, pi1 = 3, a0 = 1, a1 = 1, s0 = 0, s1 = 1, b0 = 1, b1 = 1; };
+template <> struct Proj<1, true>  { static constexpr int pi0 = 3, pi1 = 2, a0 = 2, a1 = 2, s0 = 1, s1 = 0, b0 = 3, b1 = 3; };
+template <> struct Proj<1, false> { static constexpr int pi0 = 3, pi1 = 2, a0 = 3, a1 = 3, s0 = 1, s1 = 0, b0 = 2, b1 = 2; };
+template <> struct Proj<2, true>  { static constexpr int pi0 = 3, pi1 = 2, a0 = 0, a1 = 1, s0 = 1, s1 = 0, b0 = 1, b1 = 0; };
+template <> struct Proj<2, false> { static constexpr int pi0 = 3, pi1 = 2, a0 = 1, a1 = 0, s0 = 1, s1 = 0, b0 = 0, b1 = 1; };
+template <> struct Proj<3, true>  { static constexpr int pi0 = 2, pi1 = 3, a0 = 2, a1 = 3, s0 = 0, s1 = 1, b0 = 3, b1 = 2; };
+template <> struct Proj<3, false> { static constexpr int pi0 = 2, pi1 = 3, a0 = 3, a1 = 2, s0 = 0, s1 = 1, b0 = 2, b1 = 3; };
+
+// ------------------------------------------------------------- vectors
+
+template <typename T, int G>
+__device__ __forceinline__ void ldv(const T *p, T (&v)[G])
+{
+    constexpr int B = (int)sizeof(T) * G;
+    if constexpr (B % 16 == 0) {
+#pragma unroll
+        for (int k = 0; k < B / 16; k++) {
+            const uint4 q = reinterpret_cast<const uint4 *>(p)[k];
+            __builtin_memcpy(reinterpret_cast<char *>(v) + 16 * k, &q, 16);
+        }
+    } else if constexpr (B == 8) {
+        const uint2 q = *reinterpret_cast<const uint2 *>(p);
+        __builtin_memcpy(v, &q, 8);
+    } else {
+#pragma unroll
+        for (int j = 0; j < G; j++) v[j] = p[j];
+    }
+}
+
+template <typename T, int G>
+__device__ __forceinline__ void stv(T *p, const T (&v)[G])
+{
+    constexpr int B = (int)sizeof(T) * G;
+    if constexpr (B % 16 == 0) {
+#pragma unroll
+        for (int k = 0; k < B / 16; k++) {
+            uint4 q;
+            __builtin_memcpy(&q, reinterpret_cast<const char *>(v) + 16 * k, 16);
+            reinterpret_cast<uint4 *>(p)[k] = q;
+        }
+    } else if constexpr (B == 8) {
+        uint2 q;
+        __builtin_memcpy(&q, v, 8);
+        *reinterpret_cast<uint2 *>(p) = q;
+    } else {
+#pragma unroll
+        for (int j = 0; j < G; j++) p[j] = v[j];
+    }
+}
+
+
+// a value every lane of the wavefront holds: keep it in a scalar register
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni64(int64_t v)
+{
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u), hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// ------------------------------------------------------------- hop term
+
+// Sources of a neighbour's spinor for the G rhs of a thread: global memory or
+// the LDS copy of the tile's chunk.  load(comp, v) fills v with component comp.
+// Offsets are 32-bit and relative to wave-uniform block bases.
+template <typename SP, int G>
+struct SrcGlobal {
+    Buf b;          // the block's half field
+    uint32_t voff;  // bytes to (rhs group, component 0, neighbour site)
+    uint32_t cstr;  // bytes between components (h_b elements)
+    __device__ __forceinline__ void load(int comp, SP (&v)[G]) const
+    {
+#pragma unroll
+        for (int j = 0; j < G; j++) v[j] = bload<SP>(b, voff, (uint32_t)(j * 24 + comp) * cstr);
+    }
+};
+template <typename SP, int G>
+struct SrcLds {
+    const SP *p;  // stage + lidx * G
+    __device__ __forceinline__ void load(int comp, SP (&v)[G]) const { ldv<SP, G>(p + comp * kTile * G, v); }
+};
+
+// acc[j] += (1 -/+ gamma_mu) W psi_j for the G rhs: project to the half
+// spinor h (2 spins x 3 colours), multiply by W = U (forward) or U^+
+// (backward), then rebuild the lower spin components from the upper ones.
+// The antiperiodic time sign is part of the stored link.
+template <int MU, bool FWD, typename SP, typename AC, int G, typename SRC>
+__device__ __forceinline__ void hop_term(AC (&acc)[G][24], const SRC &src, const AC (&u)[18])
+{
+    using P = Proj<MU, FWD>;
+    AC h[G][2][3][2];
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        SP v[4][2][G];
+#pragma unroll
+        for (int sp = 0; sp < 4; sp++)
+#pragma unroll
+            for (int ri = 0; ri < 2; ri++) src.load(2 * (3 * sp + c) + ri, v[sp][ri]);
+#pragma unroll
+        for (int j = 0; j < G; j++) {
+            AC re, im;
+            cmul_code<P::a0>((AC)v[P::pi0][0][j], (AC)v[P::pi0][1][j], re, im);
+            h[j][0][c][0] = (AC)v[0][0][j] + re;
+            h[j][0][c][1] = (AC)v[0][1][j] + im;
+            cmul_code<P::a1>((AC)v[P::pi1][0][j], (AC)v[P::pi1][1][j], re, im);
+            h[j][1][c][0] = (AC)v[1][0][j] + re;
+            h[j][1][c][1] = (AC)v[1][1][j] + im;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < G; j++) {
+        // W = U h (or U^+ h) as explicit fused multiply-add chains: one
+        // multiply and five FMAs per real component
+        AC w[2][3][2];
+#pragma unroll
+        for (int s = 0; s < 2; s++)
+#pragma unroll
+            for (int a = 0; a < 3; a++) {
+                AC re, im;
+#pragma unroll
+                for (int c = 0; c < 3; c++) {
+                    AC ur, ui;
+                    if constexpr (FWD) {  // U[a][c]
+                        ur = u[2 * (3 * a + c)];
+                        ui = u[2 * (3 * a + c) + 1];
+                    } else {              // conj(U[c][a])
+                        ur = u[2 * (3 * c + a)];
+                        ui = -u[2 * (3 * c + a) + 1];
+                    }
+                    const AC hr = h[j][s][c][0], hi = h[j][s][c][1];
+                    if (c == 0) {
+                        re = ur * hr;
+                        im = ur * hi;
+                    } else {
+                        re = fmad(ur, hr, re);
+                        im = fmad(ur, hi, im);
+                    }
+                    re = fmad(-ui, hi, re);
+                    im = fmad(ui, hr, im);
+                }
+                w[s][a][0] = re;
+                w[s][a][1] = im;
+            }
+#pragma unroll
+        for (int a = 0; a < 3; a++) {
+            acc[j][2 * a] += w[0][a][0];
+            acc[j][2 * a + 1] += w[0][a][1];
+            acc[j][2 * (3 + a)] += w[1][a][0];
+            acc[j][2 * (3 + a) + 1] += w[1][a][1];
+            AC re, im;
+            cmul_code<P::b0>(w[P::s0][a][0], w[P::s0][a][1], re, im);
+            acc[j][2 * (6 + a)] += re;
+            acc[j][2 * (6 + a) + 1] += im;
+            cmul_code<P::b1>(w[P::s1][a][0], w[P::s1][a][1], re, im);
+            acc[j][2 * (9 + a)] += re;
+            acc[j][2 * (9 + a) + 1] += im;
+        }
+    }
+}
+
+struct HopCtx {
+    int h0, tv;          // staged other-parity sites [h0, h0 + tv)
+    int grp_off;         // element offset of the thread's rhs group in the block's half field
+    int slot_self, other0;
+    uint32_t cstr;       // bytes between spinor components (h_b elements)
+    uint32_t kstr;       // bytes between link entries (S_b pairs)
+    Buf in_b, lk_b;      // the block's input half field and links
+};
+
+// Adds the hop along direction MU (forward or backward) to acc when the
+// neighbour entry e is not dropped.  With LDS, neighbours inside the staged
+// chunk are read from `stage`; all others from global memory.
+template <int MU, bool FWD, typename SP, typename LK, typename AC, int G, bool LDS = true>
+__device__ __forceinline__ void hop_one(AC (&acc)[G][24], int32_t e, const SP *stage, const HopCtx &hc)
+{
+    if (e < 0) return;
+    const int idx = e & kNbrMask;
+    AC u[18];
+    const int slot = FWD ? hc.slot_self : hc.other0 + idx;
+    load_link(hc.lk_b, (const LK *)nullptr, (uint32_t)slot * 2 * (uint32_t)sizeof(LK), MU * 9 * hc.kstr, hc.kstr, u);
+    const int lidx = idx - hc.h0;
+    if (LDS && (unsigned)lidx < (unsigned)hc.tv) {
+        const SrcLds<SP, G> src{stage + lidx * G};
+        hop_term<MU, FWD, SP, AC, G>(acc, src, u);
+    } else {
+        const SrcGlobal<SP, G> src{hc.in_b, (uint32_t)(hc.grp_off + idx) * (uint32_t)sizeof(SP), hc.cstr};
+        hop_term<MU, FWD, SP, AC, G>(acc, src, u);
+    }
+}
+
+}  // namespace dd

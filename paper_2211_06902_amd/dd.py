@@ -24,6 +24,7 @@ F64, F32, BF16 = 0, 1, 2
 BICGSTAB, GMRES = 0, 1
 KCLASS_HOP_F64, KCLASS_HOP_F32, KCLASS_HOP_BF16 = 0, 1, 2
 TUNE_RHS_GROUP_F64, TUNE_RHS_GROUP_F32, TUNE_HOP_LDS = 0, 1, 2
+TUNE_GMRES_THREADS, TUNE_GMRES_QUEUES, TUNE_GMRES_WG_PER_CU = 3, 4, 5
 _PREC = {"f64": F64, "f32": F32, "bf16": BF16, F64: F64, F32: F32, BF16: BF16}
 
 if not os.path.exists(LIB_PATH):
@@ -356,7 +357,8 @@ class Context:
 
     # tuning
     def tune_set(self, what, value):
-        """what: TUNE_RHS_GROUP_F64 / TUNE_RHS_GROUP_F32 (value 0 = auto, 1, 2 or 4) or TUNE_HOP_LDS (0/1)."""
+        """what: TUNE_RHS_GROUP_F64 / TUNE_RHS_GROUP_F32 (value 0 = auto, 1, 2 or 4), TUNE_HOP_LDS (0/1),
+        TUNE_GMRES_THREADS (0, 256, 512), TUNE_GMRES_QUEUES (0, 1, 8) or TUNE_GMRES_WG_PER_CU (0 = all that fit)."""
         self._check(_lib.dd_tune_set(self._h, int(what), int(value)))
 
     # timing
