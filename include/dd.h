@@ -247,6 +247,27 @@ enum {
 };
 dd_status dd_tune_set(dd_ctx *ctx, int32_t what, int32_t value);
 
+/* One timed schedule of the persistent GMRES solver. */
+typedef struct {
+    int32_t threads;    /* threads per workgroup */
+    int32_t queues;     /* work queues */
+    int32_t wg_per_cu;  /* resident workgroups per compute unit */
+    double ms;          /* time of the persistent launch */
+} dd_tune_result;
+
+/* Autotuner of the persistent GMRES schedule for these blocks, n_rhs and
+ * params->inner_prec / params->restart: times one restart cycle (exactly
+ * `restart` Krylov steps for every pair) of the first inner solve of b under
+ * each candidate schedule (threads 256 or 512; 8 queues or 1; all resident
+ * workgroups that fit, or half of them), then keeps the fastest in the
+ * context, as dd_tune_set would.  x_dev (the size of b) is scratch and is
+ * overwritten.  results (may be NULL) receives up to max_results timings in
+ * candidate order, n_results (may be NULL) their number.  The solve itself is
+ * not meant to converge here.  The kernel timers are reset. */
+dd_status dd_autotune_gmres(dd_ctx *ctx, const dd_blocks *blocks, const dd_gauge *gauge, double kappa,
+                            const void *b_dev, void *x_dev, int32_t n_rhs, const dd_solve_params *params,
+                            dd_tune_result *results, int32_t max_results, int32_t *n_results);
+
 /* ------------------------------------------------------------ timing */
 
 /* Kernel timing for roofline reports: when enabled, every launch of the
@@ -255,7 +276,14 @@ dd_status dd_tune_set(dd_ctx *ctx, int32_t what, int32_t value);
  * accumulated.  The hop classes are the stencil kernel in each precision
  * (FP64; FP32; FP32 spinors with BF16 links).  Graph replay is disabled
  * while timing is on. */
-enum { DD_KCLASS_HOP_F64 = 0, DD_KCLASS_HOP_F32 = 1, DD_KCLASS_HOP_BF16 = 2, DD_KCLASS_COUNT = 3 };
+/* DD_KCLASS_GMRES is the persistent GMRES launch (time only, no byte count). */
+enum {
+    DD_KCLASS_HOP_F64 = 0,
+    DD_KCLASS_HOP_F32 = 1,
+    DD_KCLASS_HOP_BF16 = 2,
+    DD_KCLASS_GMRES = 3,
+    DD_KCLASS_COUNT = 4
+};
 dd_status dd_timer_enable(dd_ctx *ctx, int32_t on);
 dd_status dd_timer_reset(dd_ctx *ctx);
 /* total_ms: summed event time; launches: count; alg_bytes: summed bytes. */

@@ -51,32 +51,6 @@ void *workspace(dd_ctx *ctx, const std::string &name, size_t bytes, hipError_t *
 
 size_t prec_bytes(dd_prec p) { return p == DD_F64 ? 8 : (p == DD_F32 ? 4 : 2); }
 
-// Timing of one kernel launch of a class (events only while timing is on).
-struct TimedLaunch {
-    dd_ctx *ctx;
-    int kclass;
-    hipEvent_t stop = nullptr;
-    TimedLaunch(dd_ctx *c, int k, double bytes) : ctx(c), kclass(k)
-    {
-        if (!ctx->timing) return;
-        Timer &t = ctx->timers[kclass];
-        if (t.used == t.ev.size()) {
-            hipEvent_t a, b;
-            hipEventCreate(&a);
-            hipEventCreate(&b);
-            t.ev.push_back({a, b});
-        }
-        hipEventRecord(t.ev[t.used].first, ctx->stream);
-        stop = t.ev[t.used].second;
-        t.used++;
-        t.bytes += bytes;
-    }
-    ~TimedLaunch()
-    {
-        if (stop) hipEventRecord(stop, ctx->stream);
-    }
-};
-
 const TileTable *tiles_for(dd_ctx *ctx, dd_blocks *B, int nr, int g, hipError_t *err)
 {
     *err = hipSuccess;
@@ -255,11 +229,12 @@ hipError_t enter(dd_ctx *ctx)
 dd_status finish_blocks(dd_ctx *ctx, dd_blocks *B, dd_blocks **out)
 {
     hipError_t e = hipSuccess;
-    std::vector<int32_t> h(B->nb), org((size_t)B->nb * 4), ext((size_t)B->nb * 4);
+    std::vector<int32_t> h(B->nb), nl(B->nb), org((size_t)B->nb * 4), ext((size_t)B->nb * 4);
     std::vector<int64_t> nbo(B->nb), pmo(B->nb);
     for (int b = 0; b < B->nb; b++) {
         const Shape &sh = B->shapes[B->shape_of[b]];
         h[b] = sh.h;
+        nl[b] = (int32_t)sh.links;
         nbo[b] = sh.nbr_off;
         pmo[b] = sh.perm_off;
         for (int m = 0; m < 4; m++) {
@@ -269,6 +244,7 @@ dd_status finish_blocks(dd_ctx *ctx, dd_blocks *B, dd_blocks **out)
     }
     if ((e = upload(&B->d_nbr, B->nbr)) != hipSuccess || (e = upload(&B->d_perm, B->perm)) != hipSuccess ||
         (e = upload(&B->d_soff, B->soff)) != hipSuccess || (e = upload(&B->d_h, h)) != hipSuccess ||
+        (e = upload(&B->d_nlinks, nl)) != hipSuccess ||
         (e = upload(&B->d_nbr_off, nbo)) != hipSuccess || (e = upload(&B->d_perm_off, pmo)) != hipSuccess ||
         (e = upload(&B->d_origin, org)) != hipSuccess || (e = upload(&B->d_ext, ext)) != hipSuccess ||
         (e = upload(&B->d_bnd, B->bnd)) != hipSuccess || (e = upload(&B->d_boff, B->boff)) != hipSuccess) {
@@ -394,7 +370,7 @@ dd_status dd_free_blocks(dd_blocks *B)
 {
     if (!B) return DD_EINVAL;
     if (B->device >= 0) hipSetDevice(B->device);
-    void *ptrs[] = {B->d_nbr, B->d_perm, B->d_soff, B->d_h, B->d_nbr_off, B->d_perm_off,
+    void *ptrs[] = {B->d_nbr, B->d_perm, B->d_soff, B->d_h, B->d_nlinks, B->d_nbr_off, B->d_perm_off,
                     B->d_origin, B->d_ext, B->d_bnd, B->d_boff};
     for (void *p : ptrs)
         if (p) hipFree(p);

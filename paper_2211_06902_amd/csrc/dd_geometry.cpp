@@ -149,6 +149,7 @@ std::string build_geometry(dd_blocks *B, const int L[4], int tbc, int n, const i
             sh.opar = key.opar;
             sh.tw = key.tw;
             const int64_t links = build_shape(sh, tbc, B->perm, B->nbr);
+            sh.links = links;
             sid = (int)B->shapes.size();
             B->shapes.push_back(sh);
             shape_links.push_back(links);

@@ -255,6 +255,11 @@ __global__ void __launch_bounds__(NT) k_gmres(GmArgs a)
         const SP *f = reinterpret_cast<const SP *>(a.rhs) + pb;
         SP *x = reinterpret_cast<SP *>(a.x) + pb;
         const int n = 24 * h;
+        // algorithmic bytes (kept by thread 0): a vector of the pair, and one eo
+        // hop's links shared by the block's n_rhs pairs
+        const double vb = (double)n * sizeof(SP);
+        const double lb = (double)a.nlinks[b] * 18.0 * sizeof(LK) / a.n_rhs;
+        double moved = 4.0 * vb;  // |f|, then f -> V_0 and x = 0
 
         // beta0 = |f|; x = 0; V_0 = f / beta0
         double nn = 0;
@@ -364,6 +369,8 @@ __global__ void __launch_bounds__(NT) k_gmres(GmArgs a)
                     k = j + 1;
                 }
                 it++;
+                // two hops (5 vectors, links twice) and four Gram-Schmidt passes
+                moved += (4.0 * (j + 1) + 11.0) * vb + 2.0 * lb;
                 __syncthreads();
             }
             // x += V y with R y = g (back substitution on the rotated Hessenberg matrix)
@@ -384,6 +391,7 @@ __global__ void __launch_bounds__(NT) k_gmres(GmArgs a)
                 }
                 __syncthreads();
                 combine<SP, M, NT>(sl, make_buf(x, (uint32_t)n * (uint32_t)sizeof(SP)), 0u, h, k, yv, 1.0, 1.0);
+                moved += (k + 2.0) * vb;
                 __syncthreads();
             }
             if (stop != kRestart) break;
@@ -393,6 +401,7 @@ __global__ void __launch_bounds__(NT) k_gmres(GmArgs a)
             const double rn = wg_hop<SP, LK, NT>(g, 0, tmp, V, x, -1.0, k2, f, 1.0);
             beta = sqrt(wg_sum1<NT>(rn, red));
             est = beta;
+            moved += 6.0 * vb + 2.0 * lb;
             if (!isfinite(beta)) {
                 stop = kNonFinite;
                 break;
@@ -403,11 +412,13 @@ __global__ void __launch_bounds__(NT) k_gmres(GmArgs a)
             }
             const double ib = 1.0 / beta;
             for (int e = threadIdx.x; e < n; e += NT) V[e] = (SP)((double)V[e] * ib);
+            moved += 2.0 * vb;
             __syncthreads();
             stop = kRestart;
         }
         if (threadIdx.x == 0) {
             a.iters[pair] += it;
+            if (a.bytes) a.bytes[pair] += moved;
             if (stop == kNonFinite) a.flags[pair] |= 4;
             if (a.relres) a.relres[pair] = beta0 > 0 ? est / beta0 : 0.0;
         }

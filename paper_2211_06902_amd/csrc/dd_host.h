@@ -24,6 +24,32 @@ double hop_bytes(const dd_blocks *B, int nr, dd_prec prec, int extra_vectors);
 hipError_t run_hop(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const HopArgs &ha, dd_prec prec);
 HopArgs hop_args(void *out, const void *in, const void *links, int parity, double c_hop);
 
+// Timing of one kernel launch of a class (events only while timing is on).
+struct TimedLaunch {
+    dd_ctx *ctx;
+    int kclass;
+    hipEvent_t stop = nullptr;
+    TimedLaunch(dd_ctx *c, int k, double bytes) : ctx(c), kclass(k)
+    {
+        if (!ctx->timing) return;
+        Timer &t = ctx->timers[kclass];
+        if (t.used == t.ev.size()) {
+            hipEvent_t a, b;
+            hipEventCreate(&a);
+            hipEventCreate(&b);
+            t.ev.push_back({a, b});
+        }
+        hipEventRecord(t.ev[t.used].first, ctx->stream);
+        stop = t.ev[t.used].second;
+        t.used++;
+        t.bytes += bytes;
+    }
+    ~TimedLaunch()
+    {
+        if (stop) hipEventRecord(stop, ctx->stream);
+    }
+};
+
 template <typename T>
 hipError_t upload(T **dst, const std::vector<T> &src)
 {

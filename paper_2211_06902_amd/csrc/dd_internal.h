@@ -61,6 +61,7 @@ struct Shape {
     int opar;   // parity of the origin
     int tw;     // local x0 of the link that crosses the antiperiodic time edge, or -1
     int S, h;   // sites, sites per parity
+    int64_t links;     // links with both ends in the block (the hops D_Lambda keeps)
     int64_t nbr_off;   // offset (entries) of this shape's table in the neighbour array
     int64_t perm_off;  // offset of the eo -> local canonical permutation
 };
@@ -110,6 +111,7 @@ struct dd_blocks {
     int32_t *d_perm = nullptr;
     int64_t *d_soff = nullptr;      // [nb+1]
     int32_t *d_h = nullptr;         // [nb] sites per parity
+    int32_t *d_nlinks = nullptr;    // [nb] links inside the block
     int64_t *d_nbr_off = nullptr;   // [nb] neighbour-table offset of the block's shape
     int64_t *d_perm_off = nullptr;  // [nb]
     int32_t *d_origin = nullptr;    // [nb][4]
@@ -211,6 +213,8 @@ struct GmArgs {
     double tol;               // relative residual of the inner solve
     int m;                    // restart length
     int max_iter;             // Krylov steps per pair and launch
+    const int32_t *nlinks;    // [nb] links inside each block
+    double *bytes;            // [np] += algorithmic bytes moved (may be null)
     int32_t *iters;           // [np] += steps taken
     int32_t *flags;           // [np] |= 4 on a non-finite value
     double *relres;           // [np] last residual estimate / |f| (may be null)

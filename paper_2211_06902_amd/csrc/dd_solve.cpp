@@ -233,6 +233,7 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
     w.tmp = get("s_tmp", hsp);
     int gm_nt = 0, gm_nq = 0, gm_grid = 0;
     void *gm_ws = nullptr;
+    double *gm_bytes = nullptr;
     const QueueTable *qt = nullptr;
     const int64_t vstr = 24 * (int64_t)B->max_h;
     if (gmres) {
@@ -240,6 +241,9 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
         qt = queues_for(B, n_rhs, gm_nq, &e);
         if (!qt) return fail(ctx, DD_EDEVICE, std::string("work queues: ") + hipGetErrorString(e));
         gm_ws = get("g_basis", (size_t)gm_grid * (gmres_basis_m(prm.restart) + 2) * vstr * prec_bytes(sp));
+        gm_bytes = (double *)get("g_bytes", (size_t)np * sizeof(double));
+        if ((gmres_basis_m(prm.restart) + 2) * (double)vstr * prec_bytes(sp) >= 4294967296.0)
+            return fail(ctx, DD_EUNSUPPORTED, "blocks too large for the GMRES basis slots (32-bit offsets)");
     } else {
         w.r = get("s_r", hsp);
         w.rh = get("s_rh", hsp);
@@ -274,6 +278,7 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
     hipStream_t st = ctx->stream;
     HIPCHECK(ctx, hipMemsetAsync(pi, 0, (size_t)np * 5 * sizeof(int32_t), st));
     HIPCHECK(ctx, hipMemsetAsync(pd, 0, (size_t)np * 12 * sizeof(double), st));
+    if (gm_bytes) HIPCHECK(ctx, hipMemsetAsync(gm_bytes, 0, (size_t)np * sizeof(double), st));
     HIPCHECK(ctx, hipMemsetAsync(w.xe, 0, h64, st));
     HIPCHECK(ctx, hipMemsetAsync(w.xo, 0, h64, st));
     HIPCHECK(ctx, launch_pack_spinor(B, (const double *)b_dev, w.be, w.bo, DD_F64, n_rhs, st));
@@ -337,6 +342,8 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
             ga.tol = inner_tol;
             ga.m = prm.restart;
             ga.max_iter = max_inner;
+            ga.nlinks = B->d_nlinks;
+            ga.bytes = ctx->timing ? gm_bytes : nullptr;
             ga.iters = w.ps.iters;
             ga.flags = w.ps.flags;
             ga.relres = nullptr;
@@ -353,6 +360,7 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
                 }
                 HIPCHECK(ctx, hipGraphLaunch(gx, st));
             } else {
+                TimedLaunch tl(ctx, DD_KCLASS_GMRES, 0.0);
                 HIPCHECK(ctx, launch_gmres(ga, ip, gm_nt, gm_grid, st));
             }
         } else {
@@ -401,7 +409,13 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
     HIPCHECK(ctx, hipMemcpyAsync(h_if.data(), w.ps.flags, np * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIPCHECK(ctx, hipMemcpyAsync(h_of.data(), w.os.flags, np * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIPCHECK(ctx, hipMemcpyAsync(h_it.data(), w.ps.iters, np * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    std::vector<double> h_by;
+    if (gmres && ctx->timing) {
+        h_by.resize(np);
+        HIPCHECK(ctx, hipMemcpyAsync(h_by.data(), gm_bytes, np * sizeof(double), hipMemcpyDeviceToHost, st));
+    }
     HIPCHECK(ctx, hipStreamSynchronize(st));
+    for (double v : h_by) ctx->timers[DD_KCLASS_GMRES].bytes += v;
     for (int k = 0; k < np; k++) {
         const int fl = (h_of[k] & 5) | (h_if[k] & 6);
         if (!(fl & 1)) status = DD_ENOCONV;
@@ -419,6 +433,85 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
     }
     if (status == DD_ENOCONV) ctx->err = "some (block, rhs) pairs missed the tolerance";
     return status;
+}
+
+dd_status dd_autotune_gmres(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *G, double kappa, const void *b_dev,
+                            void *x_dev, int32_t n_rhs, const dd_solve_params *params, dd_tune_result *results,
+                            int32_t max_results, int32_t *n_results)
+{
+    if (!ctx || !B || !G || !b_dev || !x_dev) return fail(ctx, DD_EINVAL, "null argument");
+    dd_solve_params p;
+    if (params) p = *params;
+    else dd_solve_params_default(&p);
+    if (p.restart < 1 || p.restart > 16) return fail(ctx, DD_EINVAL, "restart must be in 1..16");
+    // one outer cycle whose inner solve runs exactly `restart` steps per pair
+    p.method = DD_GMRES;
+    p.max_outer = 1;
+    p.inner_tol = 1e-300;
+    p.max_inner = p.restart;
+    p.use_graph = 0;
+    const bool timing0 = ctx->timing;
+    const int nt0 = ctx->gm_threads, nq0 = ctx->gm_queues, w0 = ctx->gm_wg_per_cu;
+    auto restore = [&]() {
+        ctx->timing = timing0;
+        ctx->gm_threads = nt0;
+        ctx->gm_queues = nq0;
+        ctx->gm_wg_per_cu = w0;
+    };
+    struct Cand {
+        int nt, nq, wpc;
+        double ms;
+    };
+    std::vector<Cand> cand;
+    for (int nt : {256, 512}) {
+        int occ = 0;
+        if (gmres_occupancy(p.inner_prec, p.restart, nt, &occ) != hipSuccess || occ < 1) continue;
+        for (int nq : {8, 1}) {
+            cand.push_back({nt, nq, occ, 0.0});
+            if (occ > 1) cand.push_back({nt, nq, (occ + 1) / 2, 0.0});
+        }
+    }
+    if (cand.empty()) return fail(ctx, DD_EDEVICE, "no runnable GMRES schedule");
+    // warm-up with the first candidate (workspaces, tables, code loading)
+    ctx->gm_threads = cand[0].nt;
+    ctx->gm_queues = cand[0].nq;
+    ctx->gm_wg_per_cu = cand[0].wpc;
+    dd_status st = dd_block_solve(ctx, B, G, kappa, b_dev, x_dev, n_rhs, &p, nullptr);
+    if (st != DD_OK && st != DD_ENOCONV) {
+        restore();
+        return st;
+    }
+    ctx->timing = true;
+    for (Cand &c : cand) {
+        ctx->gm_threads = c.nt;
+        ctx->gm_queues = c.nq;
+        ctx->gm_wg_per_cu = c.wpc;
+        dd_timer_reset(ctx);
+        st = dd_block_solve(ctx, B, G, kappa, b_dev, x_dev, n_rhs, &p, nullptr);
+        if (st != DD_OK && st != DD_ENOCONV) {
+            restore();
+            return st;
+        }
+        int64_t n = 0;
+        double bytes = 0;
+        if ((st = dd_timer_read(ctx, DD_KCLASS_GMRES, &c.ms, &n, &bytes)) != DD_OK) {
+            restore();
+            return st;
+        }
+    }
+    dd_timer_reset(ctx);
+    restore();
+    const Cand *best = &cand[0];
+    for (const Cand &c : cand)
+        if (c.ms < best->ms) best = &c;
+    ctx->gm_threads = best->nt;
+    ctx->gm_queues = best->nq;
+    ctx->gm_wg_per_cu = best->wpc;
+    const int nr = std::min<int>((int)cand.size(), std::max(max_results, 0));
+    for (int i = 0; results && i < nr; i++) results[i] = {cand[i].nt, cand[i].nq, cand[i].wpc, cand[i].ms};
+    if (n_results) *n_results = (int32_t)cand.size();
+    ctx->err.clear();
+    return DD_OK;
 }
 
 dd_status dd_multiboson_action(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *G, double kappa, int32_t n_fields,

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libdd.so")
 DD_OK, DD_EINVAL, DD_ENOMEM, DD_EDEVICE, DD_ENOCONV, DD_EUNSUPPORTED = range(6)
 F64, F32, BF16 = 0, 1, 2
 BICGSTAB, GMRES = 0, 1
-KCLASS_HOP_F64, KCLASS_HOP_F32, KCLASS_HOP_BF16 = 0, 1, 2
+KCLASS_HOP_F64, KCLASS_HOP_F32, KCLASS_HOP_BF16, KCLASS_GMRES = 0, 1, 2, 3
 TUNE_RHS_GROUP_F64, TUNE_RHS_GROUP_F32, TUNE_HOP_LDS = 0, 1, 2
 TUNE_GMRES_THREADS, TUNE_GMRES_QUEUES, TUNE_GMRES_WG_PER_CU = 3, 4, 5
 _PREC = {"f64": F64, "f32": F32, "bf16": BF16, F64: F64, F32: F32, BF16: BF16}
@@ -85,6 +85,15 @@ class SolveStats(ctypes.Structure):
     ]
 
 
+class TuneResult(ctypes.Structure):
+    _fields_ = [
+        ("threads", _I32),
+        ("queues", _I32),
+        ("wg_per_cu", _I32),
+        ("ms", _D),
+    ]
+
+
 def _sig(name, res, args):
     f = getattr(_lib, name)
     f.restype = res
@@ -112,6 +121,8 @@ _sig("dd_block_solve", _I32, [_P, _P, _P, _D, _P, _P, _I32, ctypes.POINTER(Solve
 _sig("dd_multiboson_action", _I32, [_P, _P, _P, _D, _I32, _P, _P, _P, ctypes.POINTER(SolveParams), _P, _P,
                                     ctypes.POINTER(SolveStats)])
 _sig("dd_tune_set", _I32, [_P, _I32, _I32])
+_sig("dd_autotune_gmres", _I32, [_P, _P, _P, _D, _P, _P, _I32, ctypes.POINTER(SolveParams),
+                                 ctypes.POINTER(TuneResult), _I32, _P])
 _sig("dd_timer_enable", _I32, [_P, _I32])
 _sig("dd_timer_reset", _I32, [_P])
 _sig("dd_timer_read", _I32, [_P, _I32, _P, _P, _P])
@@ -360,6 +371,23 @@ class Context:
         """what: TUNE_RHS_GROUP_F64 / TUNE_RHS_GROUP_F32 (value 0 = auto, 1, 2 or 4), TUNE_HOP_LDS (0/1),
         TUNE_GMRES_THREADS (0, 256, 512), TUNE_GMRES_QUEUES (0, 1, 8) or TUNE_GMRES_WG_PER_CU (0 = all that fit)."""
         self._check(_lib.dd_tune_set(self._h, int(what), int(value)))
+
+    def autotune_gmres(self, blocks: Blocks, gauge: Gauge, kappa, b, params=None, scratch=None):
+        """Times the persistent GMRES schedules on b's first inner solve and keeps the fastest.
+        Returns (list of (threads, queues, wg_per_cu, ms), the chosen tuple)."""
+        import torch
+
+        n_rhs = b.numel() // (blocks.total_sites * 12)
+        x = scratch if scratch is not None else torch.empty_like(b)
+        if params is None:
+            params = solve_params(method=GMRES)
+        res = (TuneResult * 16)()
+        n = _I32()
+        self._check(_lib.dd_autotune_gmres(self._h, blocks._h, gauge._h, float(kappa), _dev(b, "torch.complex128"),
+                                           _dev(x, "torch.complex128"), int(n_rhs), ctypes.byref(params), res, 16,
+                                           ctypes.byref(n)))
+        out = [(r.threads, r.queues, r.wg_per_cu, r.ms) for r in res[:min(n.value, 16)]]
+        return out, min(out, key=lambda r: r[3])
 
     # timing
     def timer_enable(self, on=True):

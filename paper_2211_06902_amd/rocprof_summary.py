@@ -24,13 +24,17 @@ import json
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCE = os.path.join(HERE, "csrc", "dd_kernels.hip")
+# the hop kernel's source: its kernel file and the shared stencil header
+KERNEL_SOURCES = [os.path.join(HERE, "csrc", "dd_kernels.hip"), os.path.join(HERE, "csrc", "dd_stencil.h")]
 GIB = float(1 << 30)
 
 
 def kernel_source_hash() -> str:
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def _one(path_dir: str, pattern: str) -> str:

@@ -174,6 +174,19 @@ def spinor_field(L, n_rhs: int, seed: int) -> np.ndarray:
     return z[..., 0] + 1j * z[..., 1]
 
 
+def spinor_field_device(n_rhs: int, n_sites: int, seed: int, device="cuda"):
+    """Gaussian complex spinors [n_rhs, n_sites, 4, 3] (complex128) drawn on a
+    torch device by torch's seeded generator for that device (re, im
+    interleaved on a trailing axis).  For workloads whose sources are too large
+    to draw on the host; the values are a function of (seed, device type) only."""
+    import torch
+
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    z = torch.randn((n_rhs, n_sites, 4, 3, 2), generator=g, dtype=torch.float64, device=device)
+    return torch.view_as_complex(z)
+
+
 def gaussian_complex(shape, seed: int) -> np.ndarray:
     """Generic Gaussian complex array (re, im interleaved on a trailing axis)."""
     rng = np.random.default_rng(seed)

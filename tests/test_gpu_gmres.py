@@ -189,3 +189,61 @@ def test_bad_restart_is_rejected(ctx, c1):
             ctx.block_solve(c1["blk"], g, c1["kappa"], _dev(c1["b"][:1]),
                             params=dd.solve_params(method=dd.GMRES, restart=m))
     g.close()
+
+
+def test_autotuner_picks_a_working_schedule(ctx, uneven):
+    from paper_2211_06902_amd import dd
+
+    g = ctx.load_gauge(uneven["blk"], _dev(uneven["U"]), "bf16")
+    b = _dev(uneven["b"])
+    p = dd.solve_params(method=dd.GMRES, inner_prec="bf16")
+    try:
+        tried, best = ctx.autotune_gmres(uneven["blk"], g, uneven["kappa"], b, params=p)
+        assert len(tried) >= 4 and all(r[3] > 0 for r in tried)
+        assert best in tried and best[3] == min(r[3] for r in tried)
+        x, info, st = ctx.block_solve(uneven["blk"], g, uneven["kappa"], b, params=p)
+    finally:
+        for k in (dd.TUNE_GMRES_THREADS, dd.TUNE_GMRES_QUEUES, dd.TUNE_GMRES_WG_PER_CU):
+            ctx.tune_set(k, 0)
+    assert st == dd.DD_OK
+    _check_uneven(uneven, x, info, 3)
+    g.close()
+
+
+def test_c3_full_size_bf16_gmres(ctx):
+    """The 48^3 x 96 workload at full size: 2160 uneven blocks x 12 rhs, BF16 links, GMRES(16).
+    Every pair's FP64 true residual is checked by the library; sampled pairs of both block shapes
+    against the oracle's FP64 solve."""
+    import torch
+
+    from paper_2211_06902_amd import dd
+
+    c = _cfg.C3
+    L = c["L"]
+    U = synth.gauge_field(L, c["eps"], c["seed_u"])
+    boxes = geometry.tile_boxes(L, c["segs"])
+    off = _cfg.site_offsets(boxes)
+    b = synth.spinor_field_device(c["nrhs"], int(off[-1]), c["seed_src"])
+    blk = ctx.make_blocks(L, -1, c["segs"])
+    g = ctx.load_gauge(blk, _dev(U), "bf16")
+    x, info, st = ctx.block_solve(blk, g, c["kappa"], b,
+                                  params=dd.solve_params(method=dd.GMRES, restart=16, inner_prec="bf16"))
+    print("C3: outer cycles %d, max GMRES steps %d, %.3f s" % (info["outer_cycles"], info["inner_iterations"],
+                                                               info["seconds"]))
+    assert st == dd.DD_OK
+    assert np.all(info["true_relres"] <= TOL)
+    shapes = [tuple(bx[4:8]) for bx in boxes]
+    picks = [0, shapes.index((8, 8, 8, 8)), len(boxes) - 1, 1000]
+    for k, r in zip(picks, [0, 5, 11, 7]):
+        bx = boxes[k]
+        sl = slice(int(off[k]), int(off[k + 1]))
+        bk = b[r, sl].cpu().numpy()
+        xk = x[r, sl].cpu().numpy()
+        assert _true_relres(L, c["kappa"], U, bx, xk, bk) <= TOL
+        xo, _, rel = wilson.solve_box(L, -1, c["kappa"], U, bx[:4], bx[4:8], bk, tol=1e-12)
+        assert rel <= 1e-12
+        assert _cfg.rel_err(xk, xo) <= 1e-8
+    del x, b
+    torch.cuda.empty_cache()
+    g.close()
+    blk.close()
