@@ -13,6 +13,8 @@ Contents (each module cites the part of the paper it follows):
   roots      polynomial P_N, remainder R_{N+1} and roots u_k of Section 4
   mb         block-local multi-boson action S_MB^a of Section 4
   precision  FP64 -> FP32 -> BF16 rounding rules
+  convnet    the learned block preconditioner: 4D conv net, gradients, loss, Adam
+             (not in the paper; parity pinned by independent identities)
 """
-from . import dense, geometry, mb, precision, roots, wilson  # noqa: F401
+from . import convnet, dense, geometry, mb, precision, roots, wilson  # noqa: F401
 from ._clib import build  # noqa: F401
