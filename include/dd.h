@@ -268,6 +268,57 @@ dd_status dd_autotune_gmres(dd_ctx *ctx, const dd_blocks *blocks, const dd_gauge
                             const void *b_dev, void *x_dev, int32_t n_rhs, const dd_solve_params *params,
                             dd_tune_result *results, int32_t max_results, int32_t *n_results);
 
+/* ---------------------------------------------- learned preconditioner */
+
+/* A small 4D convolutional network that approximates the block inverse on
+ * blocks of one extent (not part of the paper, which needs only the exact
+ * D_{Omega_0^a}^{-1} of Section 3: the network only speeds up the Krylov
+ * solves that provide it, whose FP64 true residual still decides).
+ *   layers: three 3^4 correlations with zero padding at the block faces and
+ *           no bias, channels 24 -> 32 -> 32 -> 24, activation (identity or
+ *           ReLU) after the first two;
+ *   fields: rows [n][S][24] FP32, one row per block site in box-local
+ *           canonical order (x3 fastest), channel 2 * (3 * spin + colour) +
+ *           (0: real, 1: imaginary part);
+ *   weights: layer after layer, each [81][c_in][c_out] FP32 with tap
+ *           27 (t0 + 1) + 9 (t1 + 1) + 3 (t2 + 1) + (t3 + 1) for the offset
+ *           t in {-1, 0, 1}^4 of the input site; dd_nn_num_weights() of them. */
+typedef struct dd_nn dd_nn;
+enum { DD_NN_LINEAR = 0, DD_NN_RELU = 1 };
+int64_t dd_nn_num_weights(void);
+/* The weights are copied (host FP32); the handle keeps FP32 master weights
+ * and Adam state on the context's device. */
+dd_status dd_nn_create(dd_ctx *ctx, const int32_t extent[4], int32_t act, const float *weights_host, dd_nn **out);
+dd_status dd_nn_free(dd_nn *nn);
+dd_status dd_nn_get_weights(dd_ctx *ctx, const dd_nn *nn, float *weights_host);
+/* y = N(x) on n blocks' rows (device FP32, [n][S][24] each); synchronizes. */
+dd_status dd_nn_apply(dd_ctx *ctx, const dd_nn *nn, const float *x_dev, float *y_dev, int64_t n);
+
+typedef struct {
+    int32_t epochs;     /* passes over the training pairs (default 4) */
+    int32_t batch;      /* pairs per Adam step (default 32) */
+    double lr;          /* Adam step size (default 1e-3) */
+    double beta1, beta2, eps;  /* Adam constants (0.9, 0.999, 1e-8) */
+    uint64_t seed;      /* shuffling: epoch e uses a Mersenne-Twister-64 stream seeded seed + e */
+    int32_t mask_even;  /* 1: the loss counts only sites even in global parity (default) */
+} dd_nn_train_params;
+void dd_nn_train_params_default(dd_nn_train_params *p);
+
+/* Training data are (source, solution) pairs in dd_block_solve's layout:
+ * src_dev / sol_dev [n_rhs][total_sites][4][3] complex128 over blocks that all
+ * have the network's extent, pair p = rhs * n_blocks + block.  Loss of a batch:
+ * mean over its pairs of |M (N(src) - sol)|^2 / |M sol|^2, M the mask above.
+ * dd_nn_loss_grad: the loss and FP32 weight gradients (host, may be NULL) of
+ * the listed pairs without updating anything.  dd_nn_train: Adam over shuffled
+ * batches; per-epoch mean training loss and (with a validation set, else
+ * NULL) validation loss into the host arrays [epochs] (may be NULL). */
+dd_status dd_nn_loss_grad(dd_ctx *ctx, dd_nn *nn, const dd_blocks *blocks, const void *src_dev, const void *sol_dev,
+                          int32_t n_rhs, const int32_t *pairs_host, int32_t n_pairs, int32_t mask_even,
+                          double *loss, float *grad_host);
+dd_status dd_nn_train(dd_ctx *ctx, dd_nn *nn, const dd_blocks *blocks, const void *src_dev, const void *sol_dev,
+                      int32_t n_rhs, const void *val_src_dev, const void *val_sol_dev, int32_t val_n_rhs,
+                      const dd_nn_train_params *params, double *train_loss, double *val_loss);
+
 /* ------------------------------------------------------------ timing */
 
 /* Kernel timing for roofline reports: when enabled, every launch of the

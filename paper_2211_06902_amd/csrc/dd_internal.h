@@ -227,6 +227,27 @@ hipError_t gmres_occupancy(dd_prec prec, int restart, int nt, int *wgs_per_cu);
 hipError_t launch_gmres(const GmArgs &a, dd_prec prec, int nt, int grid, hipStream_t st);
 hipError_t gmres_schedule(dd_ctx *ctx, dd_prec ip, int restart, int np, int *nt, int *nq, int *grid);
 
+// Extent of the block the network works on (all its blocks have one shape).
+struct NnExt {
+    int e[4];
+    int S;
+};
+
+// launch wrappers of the network (dd_nn.hip); activations are rows [row][channel]
+hipError_t launch_conv(const float *X, const float *W, float *Y, int64_t nrows, const NnExt &e, int cin, int cout,
+                       int mode, hipStream_t st);
+hipError_t launch_conv_dw(const float *X, const float *dY, float *part, float *dW, int64_t nrows, int nchunk,
+                          const NnExt &e, int cin, int cout, int mode, hipStream_t st);
+hipError_t launch_relu_grad(const float *dH, const float *Z, float *dZ, int64_t n, hipStream_t st);
+hipError_t launch_flip_weights(const float *W, float *Wf, int cin, int cout, hipStream_t st);
+hipError_t launch_gather_rows(const double *src, const double *sol, const int64_t *base, const int32_t *idx, float *X,
+                              float *T, int n, int S, hipStream_t st);
+hipError_t launch_loss(const float *out, const float *T, const int32_t *opar, const int32_t *idx, double *part,
+                       double *den, double *loss_acc, float *grad, int n, int mask_even, const NnExt &e,
+                       hipStream_t st);
+hipError_t launch_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float eps,
+                       int t, hipStream_t st);
+
 // launch wrappers (dd_kernels.hip)
 hipError_t launch_pack_gauge(const dd_blocks *B, const double *U, dd_prec prec, void *dst,
                              hipStream_t s);

@@ -1,0 +1,32 @@
+// The learned block preconditioner's handle (host side).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "dd_internal.h"
+
+struct dd_nn {
+    dd_ctx *ctx = nullptr;  // creating context (identity only)
+    int device = 0;
+    int act = 0;            // DD_NN_LINEAR or DD_NN_RELU
+    dd::NnExt e{};          // block extent the network works on
+    int64_t off[4] = {0, 0, 0, 0};  // layer offsets in the weight arrays
+    int64_t nw = 0;                 // number of weights
+    float *d_w = nullptr;   // FP32 weights, layers back to back, each [81][c_in][c_out]
+    float *d_g = nullptr;   // gradients
+    float *d_m = nullptr;   // Adam first moments
+    float *d_v = nullptr;   // Adam second moments
+    float *d_wf = nullptr;  // one layer's flipped weights (backward pass)
+    float *d_part = nullptr;  // weight-gradient partials per row chunk
+    int step = 0;             // Adam steps taken
+};
+
+namespace dd {
+
+// the network on nrows rows: X [rows][24] -> O [rows][24], keeping the
+// pre-activations Z1, Z2 [rows][32]
+hipError_t nn_forward(dd_ctx *ctx, const dd_nn *nn, const float *X, float *Z1, float *Z2, float *O, int64_t nrows);
+
+}  // namespace dd

@@ -1,0 +1,363 @@
+// Kernels of the learned block preconditioner: a 4D convolutional network
+// (three 3^4 correlations, 24 -> 32 -> 32 -> 24 channels, zero padding at the
+// block faces, no bias, identity or ReLU between layers) with its training
+// (backward pass, relative squared error, Adam) in FP32.
+//
+// Activations are row-major [row][channel] with one row per (sample, block
+// site), sites in box-local canonical order (x3 fastest): a tap of the
+// correlation reads the neighbour's whole channel vector with vector loads.
+// Weights are [tap][c_in][c_out] with tap = 27 (t0+1) + 9 (t1+1) + 3 (t2+1) +
+// (t3+1); every thread of a kernel reads the same weight at the same time, so
+// those loads are wave-uniform.
+#include <hip/hip_runtime.h>
+
+#include "dd_internal.h"
+
+namespace dd {
+
+namespace {
+
+__device__ __forceinline__ void site_coords(int y, const NnExt &e, int c[4])
+{
+    c[3] = y % e.e[3];
+    y /= e.e[3];
+    c[2] = y % e.e[2];
+    y /= e.e[2];
+    c[1] = y % e.e[1];
+    c[0] = y / e.e[1];
+}
+
+// Input transform applied on load: 0 as stored, 1 max(x, 0) (the activation
+// of the previous layer), 2 x where the mask array is positive (else 0).
+template <int MODE>
+__device__ __forceinline__ float in_tf(float x, float m)
+{
+    if constexpr (MODE == 1) return fmaxf(x, 0.0f);
+    else if constexpr (MODE == 2) return m > 0.0f ? x : 0.0f;
+    else return x;
+}
+
+}  // namespace
+
+// Y[row, o] = sum_t sum_c W[t, c, o] tf(X[row + t, c]); one thread per row.
+template <int CIN, int COUT, int MODE>
+__global__ void __launch_bounds__(256) k_conv(const float *__restrict__ X, const float *__restrict__ Msk,
+                                              const float *__restrict__ W, float *__restrict__ Y, int64_t nrows,
+                                              NnExt e)
+{
+    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (row >= nrows) return;
+    const int64_t n = row / e.S;
+    const int y = (int)(row - n * e.S);
+    int c[4];
+    site_coords(y, e, c);
+    float acc[COUT];
+#pragma unroll
+    for (int o = 0; o < COUT; o++) acc[o] = 0.0f;
+    const int st[4] = {e.e[1] * e.e[2] * e.e[3], e.e[2] * e.e[3], e.e[3], 1};
+    for (int t0 = -1; t0 <= 1; t0++) {
+        if ((unsigned)(c[0] + t0) >= (unsigned)e.e[0]) continue;
+        for (int t1 = -1; t1 <= 1; t1++) {
+            if ((unsigned)(c[1] + t1) >= (unsigned)e.e[1]) continue;
+            for (int t2 = -1; t2 <= 1; t2++) {
+                if ((unsigned)(c[2] + t2) >= (unsigned)e.e[2]) continue;
+#pragma unroll
+                for (int t3 = -1; t3 <= 1; t3++) {
+                    if ((unsigned)(c[3] + t3) >= (unsigned)e.e[3]) continue;
+                    const int tap = ((t0 + 1) * 3 + (t1 + 1)) * 9 + (t2 + 1) * 3 + (t3 + 1);
+                    const int64_t nb = n * e.S + y + t0 * st[0] + t1 * st[1] + t2 * st[2] + t3 * st[3];
+                    const float4 *xr = reinterpret_cast<const float4 *>(X + nb * CIN);
+                    const float4 *mr = reinterpret_cast<const float4 *>(Msk + (MODE == 2 ? nb * CIN : 0));
+                    const float *wr = W + tap * CIN * COUT;
+#pragma unroll
+                    for (int q = 0; q < CIN / 4; q++) {
+                        const float4 xv = xr[q];
+                        float4 mv = make_float4(0, 0, 0, 0);
+                        if constexpr (MODE == 2) mv = mr[q];
+                        const float xs[4] = {in_tf<MODE>(xv.x, mv.x), in_tf<MODE>(xv.y, mv.y), in_tf<MODE>(xv.z, mv.z),
+                                             in_tf<MODE>(xv.w, mv.w)};
+#pragma unroll
+                        for (int j = 0; j < 4; j++)
+#pragma unroll
+                            for (int o = 0; o < COUT; o++) acc[o] = __builtin_fmaf(xs[j], wr[(4 * q + j) * COUT + o], acc[o]);
+                    }
+                }
+            }
+        }
+    }
+    float4 *yr = reinterpret_cast<float4 *>(Y + row * COUT);
+#pragma unroll
+    for (int q = 0; q < COUT / 4; q++) yr[q] = make_float4(acc[4 * q], acc[4 * q + 1], acc[4 * q + 2], acc[4 * q + 3]);
+}
+
+// Partial weight gradients of one tap over one chunk of rows:
+// part[chunk][tap][c][o] = sum_{rows r of the chunk} tf(X[r + tap, c]) dY[r, o].
+template <int CIN, int COUT, int MODE>
+__global__ void __launch_bounds__(256) k_conv_dw(const float *__restrict__ X, const float *__restrict__ Msk,
+                                                 const float *__restrict__ dY, float *__restrict__ part,
+                                                 int64_t nrows, int64_t rows_per_chunk, NnExt e)
+{
+    constexpr int R = 64;                       // rows staged at a time
+    constexpr int KPT = (CIN * COUT + 255) / 256;  // accumulators per thread
+    __shared__ float xs[R][CIN];
+    __shared__ float ds[R][COUT];
+    const int tap = blockIdx.x, chunk = blockIdx.y;
+    const int t[4] = {tap / 27 - 1, (tap / 9) % 3 - 1, (tap / 3) % 3 - 1, tap % 3 - 1};
+    const int st[4] = {e.e[1] * e.e[2] * e.e[3], e.e[2] * e.e[3], e.e[3], 1};
+    const int64_t r0 = (int64_t)chunk * rows_per_chunk;
+    const int64_t r1 = min(nrows, r0 + rows_per_chunk);
+    float acc[KPT];
+#pragma unroll
+    for (int k = 0; k < KPT; k++) acc[k] = 0.0f;
+    for (int64_t rb = r0; rb < r1; rb += R) {
+        // stage R rows of dY and the matching neighbour rows of X (zero outside the block)
+        for (int i = threadIdx.x; i < R * CIN; i += 256) {
+            const int rr = i / CIN, cc = i - rr * CIN;
+            const int64_t row = rb + rr;
+            float v = 0.0f;
+            if (row < r1) {
+                const int64_t n = row / e.S;
+                const int y = (int)(row - n * e.S);
+                int c[4];
+                site_coords(y, e, c);
+                bool in = true;
+#pragma unroll
+                for (int m = 0; m < 4; m++) in = in && (unsigned)(c[m] + t[m]) < (unsigned)e.e[m];
+                if (in) {
+                    const int64_t nb = n * e.S + y + t[0] * st[0] + t[1] * st[1] + t[2] * st[2] + t[3] * st[3];
+                    v = in_tf<MODE>(X[nb * CIN + cc], MODE == 2 ? Msk[nb * CIN + cc] : 0.0f);
+                }
+            }
+            xs[rr][cc] = v;
+        }
+        for (int i = threadIdx.x; i < R * COUT; i += 256) {
+            const int rr = i / COUT, oo = i - rr * COUT;
+            const int64_t row = rb + rr;
+            ds[rr][oo] = row < r1 ? dY[row * COUT + oo] : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < KPT; k++) {
+            const int idx = threadIdx.x + 256 * k;
+            if (idx < CIN * COUT) {
+                const int cc = idx / COUT, oo = idx - cc * COUT;
+                float a = acc[k];
+#pragma unroll 8
+                for (int rr = 0; rr < R; rr++) a = __builtin_fmaf(xs[rr][cc], ds[rr][oo], a);
+                acc[k] = a;
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < KPT; k++) {
+        const int idx = threadIdx.x + 256 * k;
+        if (idx < CIN * COUT) part[((int64_t)chunk * 81 + tap) * CIN * COUT + idx] = acc[k];
+    }
+}
+
+// out[k] = sum_j part[j][k] over nchunk chunks, in chunk order
+__global__ void k_sum_chunks(const float *__restrict__ part, float *__restrict__ out, int64_t n, int nchunk)
+{
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= n) return;
+    float s = 0.0f;
+    for (int j = 0; j < nchunk; j++) s += part[(int64_t)j * n + k];
+    out[k] = s;
+}
+
+// dZ = dH where the pre-activation Z is positive, else 0 (ReLU backward)
+__global__ void k_relu_grad(const float *__restrict__ dH, const float *__restrict__ Z, float *__restrict__ dZ, int64_t n)
+{
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k < n) dZ[k] = Z[k] > 0.0f ? dH[k] : 0.0f;
+}
+
+// W'[t][o][c] = W[80 - t][c][o]: the weights of the transposed correlation
+__global__ void k_flip_weights(const float *__restrict__ W, float *__restrict__ Wf, int cin, int cout)
+{
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= 81 * cin * cout) return;
+    const int t = k / (cin * cout), r = k - t * cin * cout, c = r / cout, o = r - c * cout;
+    Wf[((int64_t)t * cout + o) * cin + c] = W[((int64_t)(80 - t) * cin + c) * cout + o];
+}
+
+// Training batch: X[i][s][:] = src rows of sample idx[i] (FP64 -> FP32), T likewise from sol.
+__global__ void k_gather_rows(const double *__restrict__ src, const double *__restrict__ sol,
+                              const int64_t *__restrict__ base, const int32_t *__restrict__ idx, float *__restrict__ X,
+                              float *__restrict__ T, int n, int S)
+{
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t per = (int64_t)S * 24;
+    if (k >= (int64_t)n * per) return;
+    const int i = (int)(k / per);
+    const int64_t off = base[idx[i]] * 24 + (k - i * per);
+    X[k] = (float)src[off];
+    T[k] = (float)sol[off];
+}
+
+// Per-sample sums over the masked sites (global parity even, or all):
+// part[i][chunk] = (sum |out - T|^2, sum |T|^2); one workgroup per (sample, chunk).
+__global__ void __launch_bounds__(256) k_loss_parts(const float *__restrict__ out, const float *__restrict__ T,
+                                                    const int32_t *__restrict__ opar, const int32_t *__restrict__ idx,
+                                                    double *__restrict__ part, int mask_even, int nchunk, NnExt e)
+{
+    __shared__ double r0[4], r1[4];
+    const int i = blockIdx.y, chunk = blockIdx.x;
+    const int per = (e.S + nchunk - 1) / nchunk;
+    const int s0 = chunk * per, s1 = min(e.S, s0 + per);
+    const int op = opar[idx[i]];
+    double a = 0, b = 0;
+    for (int s = s0 + threadIdx.x; s < s1; s += 256) {
+        int c[4];
+        site_coords(s, e, c);
+        if (mask_even && ((c[0] + c[1] + c[2] + c[3] + op) & 1)) continue;
+        const int64_t o = ((int64_t)i * e.S + s) * 24;
+        for (int ch = 0; ch < 24; ch++) {
+            const double d = (double)out[o + ch] - (double)T[o + ch], tv = (double)T[o + ch];
+            a += d * d;
+            b += tv * tv;
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        a += __shfl_xor(a, off, 64);
+        b += __shfl_xor(b, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        r0[threadIdx.x >> 6] = a;
+        r1[threadIdx.x >> 6] = b;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        part[((int64_t)i * nchunk + chunk) * 2] = ((r0[0] + r0[1]) + r0[2]) + r0[3];
+        part[((int64_t)i * nchunk + chunk) * 2 + 1] = ((r1[0] + r1[1]) + r1[2]) + r1[3];
+    }
+}
+
+// per-sample ratios num/den and the batch loss sum (one thread; n is a batch)
+__global__ void k_loss_fin(const double *__restrict__ part, double *__restrict__ den, double *__restrict__ loss_acc,
+                           int n, int nchunk)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    double tot = 0;
+    for (int i = 0; i < n; i++) {
+        double a = 0, b = 0;
+        for (int j = 0; j < nchunk; j++) {
+            a += part[((int64_t)i * nchunk + j) * 2];
+            b += part[((int64_t)i * nchunk + j) * 2 + 1];
+        }
+        den[i] = b;
+        tot += b > 0 ? a / b : 0.0;
+    }
+    loss_acc[0] += tot / n;
+    loss_acc[1] += 1.0;
+}
+
+// dOut = 2 mask (out - T) / (den_i n)
+__global__ void k_loss_grad(const float *__restrict__ out, const float *__restrict__ T,
+                            const int32_t *__restrict__ opar, const int32_t *__restrict__ idx,
+                            const double *__restrict__ den, float *__restrict__ g, int n, int mask_even, NnExt e)
+{
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t per = (int64_t)e.S * 24;
+    if (k >= (int64_t)n * per) return;
+    const int i = (int)(k / per);
+    const int s = (int)((k - i * per) / 24);
+    int c[4];
+    site_coords(s, e, c);
+    const bool on = !mask_even || !((c[0] + c[1] + c[2] + c[3] + opar[idx[i]]) & 1);
+    g[k] = on && den[i] > 0 ? (float)(2.0 * ((double)out[k] - (double)T[k]) / (den[i] * n)) : 0.0f;
+}
+
+// Adam step t on n parameters
+__global__ void k_adam(float *__restrict__ w, const float *__restrict__ g, float *__restrict__ m, float *__restrict__ v,
+                       int64_t n, float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= n) return;
+    const float gk = g[k];
+    const float mk = b1 * m[k] + (1.0f - b1) * gk;
+    const float vk = b2 * v[k] + (1.0f - b2) * gk * gk;
+    m[k] = mk;
+    v[k] = vk;
+    w[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
+}
+
+// ------------------------------------------------------------ launchers
+
+static inline dim3 g256(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
+
+hipError_t launch_conv(const float *X, const float *W, float *Y, int64_t nrows, const NnExt &e, int cin, int cout,
+                       int mode, hipStream_t st)
+{
+    if (nrows <= 0) return hipSuccess;
+#define CV(CI, CO, M)                                                                                              \
+    if (cin == CI && cout == CO && mode == M) {                                                                  \
+        hipLaunchKernelGGL((k_conv<CI, CO, M>), g256(nrows), dim3(256), 0, st, X, nullptr, W, Y, nrows, e);     \
+        return hipGetLastError();                                                                                \
+    }
+    CV(24, 32, 0) CV(32, 32, 0) CV(32, 32, 1) CV(32, 24, 0) CV(32, 24, 1)
+#undef CV
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_conv_dw(const float *X, const float *dY, float *part, float *dW, int64_t nrows, int nchunk,
+                          const NnExt &e, int cin, int cout, int mode, hipStream_t st)
+{
+    const int64_t per = (nrows + nchunk - 1) / nchunk;
+    dim3 g(81, nchunk);
+    bool ok = false;
+#define DW(CI, CO, M)                                                                                            \
+    if (!ok && cin == CI && cout == CO && mode == M) {                                                         \
+        hipLaunchKernelGGL((k_conv_dw<CI, CO, M>), g, dim3(256), 0, st, X, nullptr, dY, part, nrows, per, e); \
+        ok = true;                                                                                             \
+    }
+    DW(24, 32, 0) DW(32, 32, 0) DW(32, 32, 1) DW(32, 24, 0) DW(32, 24, 1)
+#undef DW
+    if (!ok) return hipErrorInvalidValue;
+    const int64_t n = 81LL * cin * cout;
+    hipLaunchKernelGGL(k_sum_chunks, g256(n), dim3(256), 0, st, part, dW, n, nchunk);
+    return hipGetLastError();
+}
+
+hipError_t launch_relu_grad(const float *dH, const float *Z, float *dZ, int64_t n, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_relu_grad, g256(n), dim3(256), 0, st, dH, Z, dZ, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_flip_weights(const float *W, float *Wf, int cin, int cout, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_flip_weights, g256(81LL * cin * cout), dim3(256), 0, st, W, Wf, cin, cout);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_rows(const double *src, const double *sol, const int64_t *base, const int32_t *idx, float *X,
+                              float *T, int n, int S, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_gather_rows, g256((int64_t)n * S * 24), dim3(256), 0, st, src, sol, base, idx, X, T, n, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_loss(const float *out, const float *T, const int32_t *opar, const int32_t *idx, double *part,
+                       double *den, double *loss_acc, float *grad, int n, int mask_even, const NnExt &e,
+                       hipStream_t st)
+{
+    constexpr int nchunk = 16;
+    hipLaunchKernelGGL(k_loss_parts, dim3(nchunk, n), dim3(256), 0, st, out, T, opar, idx, part, mask_even, nchunk, e);
+    hipLaunchKernelGGL(k_loss_fin, dim3(1), dim3(64), 0, st, part, den, loss_acc, n, nchunk);
+    if (grad)
+        hipLaunchKernelGGL(k_loss_grad, g256((int64_t)n * e.S * 24), dim3(256), 0, st, out, T, opar, idx, den, grad, n,
+                           mask_even, e);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float eps,
+                       int t, hipStream_t st)
+{
+    const float c1 = 1.0f - powf(b1, (float)t), c2 = 1.0f - powf(b2, (float)t);
+    hipLaunchKernelGGL(k_adam, g256(n), dim3(256), 0, st, w, g, m, v, n, lr, b1, b2, eps, c1, c2);
+    return hipGetLastError();
+}
+
+}  // namespace dd

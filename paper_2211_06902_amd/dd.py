@@ -94,6 +94,19 @@ class TuneResult(ctypes.Structure):
     ]
 
 
+class NnTrainParams(ctypes.Structure):
+    _fields_ = [
+        ("epochs", _I32),
+        ("batch", _I32),
+        ("lr", _D),
+        ("beta1", _D),
+        ("beta2", _D),
+        ("eps", _D),
+        ("seed", ctypes.c_uint64),
+        ("mask_even", _I32),
+    ]
+
+
 def _sig(name, res, args):
     f = getattr(_lib, name)
     f.restype = res
@@ -121,6 +134,14 @@ _sig("dd_block_solve", _I32, [_P, _P, _P, _D, _P, _P, _I32, ctypes.POINTER(Solve
 _sig("dd_multiboson_action", _I32, [_P, _P, _P, _D, _I32, _P, _P, _P, ctypes.POINTER(SolveParams), _P, _P,
                                     ctypes.POINTER(SolveStats)])
 _sig("dd_tune_set", _I32, [_P, _I32, _I32])
+_sig("dd_nn_num_weights", _I64, [])
+_sig("dd_nn_create", _I32, [_P, _P, _I32, _P, _PP])
+_sig("dd_nn_free", _I32, [_P])
+_sig("dd_nn_get_weights", _I32, [_P, _P, _P])
+_sig("dd_nn_apply", _I32, [_P, _P, _P, _P, _I64])
+_sig("dd_nn_train_params_default", None, [ctypes.POINTER(NnTrainParams)])
+_sig("dd_nn_loss_grad", _I32, [_P, _P, _P, _P, _P, _I32, _P, _I32, _I32, _P, _P])
+_sig("dd_nn_train", _I32, [_P, _P, _P, _P, _P, _I32, _P, _P, _I32, ctypes.POINTER(NnTrainParams), _P, _P])
 _sig("dd_autotune_gmres", _I32, [_P, _P, _P, _D, _P, _P, _I32, ctypes.POINTER(SolveParams),
                                  ctypes.POINTER(TuneResult), _I32, _P])
 _sig("dd_timer_enable", _I32, [_P, _I32])
@@ -158,6 +179,21 @@ def _dev(t, dtype_name):
     return _P(t.data_ptr())
 
 
+NN_LINEAR, NN_RELU = 0, 1
+
+
+def nn_train_params(**kw) -> NnTrainParams:
+    p = NnTrainParams()
+    _lib.dd_nn_train_params_default(ctypes.byref(p))
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def nn_num_weights() -> int:
+    return int(_lib.dd_nn_num_weights())
+
+
 def solve_params(**kw) -> SolveParams:
     p = SolveParams()
     _lib.dd_solve_params_default(ctypes.byref(p))
@@ -166,6 +202,56 @@ def solve_params(**kw) -> SolveParams:
             v = _PREC[v]
         setattr(p, k, v)
     return p
+
+
+class Net:
+    """The learned block preconditioner (FP32 weights and Adam state on the GPU)."""
+
+    def __init__(self, handle, ctx, extent, act):
+        self._h = handle
+        self._ctx = ctx
+        self.extent = extent
+        self.act = act
+        self.sites = int(np.prod(extent))
+
+    def close(self):
+        if self._h:
+            _lib.dd_nn_free(self._h)
+            self._h = None
+
+    def weights(self):
+        w = np.zeros(nn_num_weights(), dtype=np.float32)
+        self._ctx._check(_lib.dd_nn_get_weights(self._ctx._h, self._h, w.ctypes.data_as(_P)))
+        return w
+
+    def apply(self, x):
+        """x: GPU float32 [n, S, 24] rows -> N(x) of the same shape."""
+        import torch
+
+        y = torch.empty_like(x)
+        n = x.numel() // (self.sites * 24)
+        self._ctx._check(_lib.dd_nn_apply(self._ctx._h, self._h, _dev(x, "torch.float32"), _dev(y, "torch.float32"), n))
+        return y
+
+    def loss_grad(self, blocks, src, sol, n_rhs, pairs, mask_even=1):
+        pr = _i32(pairs)
+        loss = _D()
+        g = np.zeros(nn_num_weights(), dtype=np.float32)
+        self._ctx._check(_lib.dd_nn_loss_grad(self._ctx._h, self._h, blocks._h, _dev(src, "torch.complex128"),
+                                              _dev(sol, "torch.complex128"), int(n_rhs), pr.ctypes.data_as(_P),
+                                              int(pr.size), int(mask_even), ctypes.byref(loss), g.ctypes.data_as(_P)))
+        return loss.value, g
+
+    def train(self, blocks, src, sol, n_rhs, val_src=None, val_sol=None, val_n_rhs=0, params=None):
+        p = params if params is not None else nn_train_params()
+        tl = np.zeros(p.epochs)
+        vl = np.zeros(p.epochs)
+        vs = _dev(val_src, "torch.complex128") if val_src is not None else None
+        vo = _dev(val_sol, "torch.complex128") if val_sol is not None else None
+        self._ctx._check(_lib.dd_nn_train(self._ctx._h, self._h, blocks._h, _dev(src, "torch.complex128"),
+                                          _dev(sol, "torch.complex128"), int(n_rhs), vs, vo, int(val_n_rhs),
+                                          ctypes.byref(p), tl.ctypes.data_as(_P), vl.ctypes.data_as(_P)))
+        return tl, vl
 
 
 class Blocks:
@@ -388,6 +474,16 @@ class Context:
                                            ctypes.byref(n)))
         out = [(r.threads, r.queues, r.wg_per_cu, r.ms) for r in res[:min(n.value, 16)]]
         return out, min(out, key=lambda r: r[3])
+
+    # learned preconditioner
+    def nn_create(self, extent, weights, act=NN_LINEAR):
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32).reshape(-1))
+        if w.size != nn_num_weights():
+            raise ValueError("expected %d weights" % nn_num_weights())
+        h = _P()
+        self._check(_lib.dd_nn_create(self._h, _i32(extent).ctypes.data_as(_P), int(act),
+                                      w.ctypes.data_as(_P), ctypes.byref(h)))
+        return Net(h, self, tuple(int(v) for v in extent), act)
 
     # timing
     def timer_enable(self, on=True):

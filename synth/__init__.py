@@ -187,6 +187,23 @@ def spinor_field_device(n_rhs: int, n_sites: int, seed: int, device="cuda"):
     return torch.view_as_complex(z)
 
 
+def convnet_weights(seed: int, scale: float = 0.1, identity: bool = True) -> np.ndarray:
+    """Initial FP32 weights of the 24 -> 32 -> 32 -> 24 block network, layers
+    back to back, each [81][c_in][c_out]: Gaussian with standard deviation
+    scale / sqrt(81 c_in), plus (identity=True) the identity between the first
+    min(c_in, c_out) channels on the centre tap, so that the untrained linear
+    network is close to the identity map."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for cin, cout in ((24, 32), (32, 32), (32, 24)):
+        w = rng.standard_normal((81, cin, cout)) * (scale / np.sqrt(81 * cin))
+        if identity:
+            k = min(cin, cout)
+            w[40, np.arange(k), np.arange(k)] += 1.0
+        out.append(w.reshape(-1))
+    return np.concatenate(out).astype(np.float32)
+
+
 def gaussian_complex(shape, seed: int) -> np.ndarray:
     """Generic Gaussian complex array (re, im interleaved on a trailing axis)."""
     rng = np.random.default_rng(seed)
