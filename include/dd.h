@@ -71,6 +71,7 @@ typedef enum { DD_F64 = 0, DD_F32 = 1, DD_BF16 = 2 } dd_prec;
 typedef struct dd_ctx dd_ctx;
 typedef struct dd_blocks dd_blocks;
 typedef struct dd_gauge dd_gauge;
+typedef struct dd_nn dd_nn;
 
 /* ---------------------------------------------------------------- context */
 
@@ -177,6 +178,11 @@ typedef struct {
     int32_t check_every; /* BiCGStab: inner iterations between convergence polls (<= 0: default 8) */
     int32_t use_graph;   /* replay inner iterations (BiCGStab) or the persistent inner launch
                             (GMRES) from a captured hipGraph */
+    const dd_nn *precond; /* GMRES only (NULL: none): flexible GMRES whose first direction of
+                             a restart cycle is z = N(r) for the cycle's starting residual r;
+                             needs every block to have the network's extent */
+    int32_t precond_cycles; /* with precond: restart cycles between network applications
+                               (<= 0: the network is applied once per inner solve) */
 } dd_solve_params;
 
 typedef struct {
@@ -283,7 +289,6 @@ dd_status dd_autotune_gmres(dd_ctx *ctx, const dd_blocks *blocks, const dd_gauge
  *   weights: layer after layer, each [81][c_in][c_out] FP32 with tap
  *           27 (t0 + 1) + 9 (t1 + 1) + 3 (t2 + 1) + (t3 + 1) for the offset
  *           t in {-1, 0, 1}^4 of the input site; dd_nn_num_weights() of them. */
-typedef struct dd_nn dd_nn;
 enum { DD_NN_LINEAR = 0, DD_NN_RELU = 1 };
 int64_t dd_nn_num_weights(void);
 /* The weights are copied (host FP32); the handle keeps FP32 master weights

@@ -161,13 +161,13 @@ __device__ __forceinline__ void gs_dots(const Slot &sl, int iw, int h, int j, bo
     __syncthreads();
 }
 
-// dst = (dst + sgn * sum_{i<n} c_i V_i) * scale with complex c_i from LDS (read
+// dst = (dst + sgn * sum_{i0<=i<n} c_i V_i) * scale with complex c_i from LDS (read
 // as used, so that they take no registers), FP64 arithmetic, stored in SP; dst is
 // a buffer and the byte offset of the vector in it.  Each thread updates its
 // own elements: no barrier inside.
 template <typename SP, int M, int NT>
 __device__ __forceinline__ void combine(const Slot &sl, const Buf &db, uint32_t dso, int h, int n, const double *c,
-                                        double sgn, double scale)
+                                        double sgn, double scale, int i0 = 0)
 {
     const uint32_t hb = (uint32_t)h * (uint32_t)sizeof(SP);
 #pragma unroll 1
@@ -181,7 +181,7 @@ __device__ __forceinline__ void combine(const Slot &sl, const Buf &db, uint32_t 
             double wr = (double)bload<SP>(db, vo, dso), wi = (double)bload<SP>(db, vo, dso + hb);
 #pragma unroll
             for (int i = 0; i <= M; i++)
-                if (i < n) {
+                if (i >= i0 && i < n) {
                     const uint32_t io = (uint32_t)i * sl.vbytes;
                     const double vr = (double)bload<SP>(sl.b, vo, io), vi = (double)bload<SP>(sl.b, vo, io + hb);
                     const double cr = sgn * c[2 * i], ci = sgn * c[2 * i + 1];
@@ -194,7 +194,7 @@ __device__ __forceinline__ void combine(const Slot &sl, const Buf &db, uint32_t 
 }
 
 // Stop codes of a Krylov step
-enum { kGoOn = 0, kRestart = 1, kConverged = 2, kMaxIter = 3, kNonFinite = 4 };
+enum { kGoOn = 0, kRestart = 1, kConverged = 2, kMaxIter = 3, kNonFinite = 4, kPaused = 5 };
 
 }  // namespace
 
@@ -254,30 +254,37 @@ __global__ void __launch_bounds__(NT) k_gmres(GmArgs a)
         const int64_t pb = (so >> 1) * 24 * a.n_rhs + (int64_t)r * 24 * h;
         const SP *f = reinterpret_cast<const SP *>(a.rhs) + pb;
         SP *x = reinterpret_cast<SP *>(a.x) + pb;
+        SP *rg = a.r ? reinterpret_cast<SP *>(a.r) + pb : nullptr;  // paused residual
+        const SP *z0 = a.z0 ? reinterpret_cast<const SP *>(a.z0) + pb : nullptr;
         const int n = 24 * h;
         // algorithmic bytes (kept by thread 0): a vector of the pair, and one eo
         // hop's links shared by the block's n_rhs pairs
         const double vb = (double)n * sizeof(SP);
         const double lb = (double)a.nlinks[b] * 18.0 * sizeof(LK) / a.n_rhs;
-        double moved = 4.0 * vb;  // |f|, then f -> V_0 and x = 0
+        double moved;
 
-        // beta0 = |f|; x = 0; V_0 = f / beta0
+        // fresh start: beta0 = |f|, x = 0, V_0 = f / beta0; resumed: V_0 = r / |r|
+        const SP *start = a.resume ? rg : f;
         double nn = 0;
         for (int e = threadIdx.x; e < n; e += NT) {
-            const double v = (double)f[e];
+            const double v = (double)start[e];
             nn = fma(v, v, nn);
         }
-        const double beta0 = sqrt(wg_sum1<NT>(nn, red));
-        const bool ok0 = isfinite(beta0) && beta0 > 0;
-        const double inv0 = ok0 ? 1.0 / beta0 : 0.0;
+        double beta = sqrt(wg_sum1<NT>(nn, red));
+        const double beta0 = a.resume ? a.beta0[pair] : beta;
+        const bool ok0 = isfinite(beta) && beta > 0;
+        const double inv0 = ok0 ? 1.0 / beta : 0.0;
         for (int e = threadIdx.x; e < n; e += NT) {
-            V[e] = (SP)((double)f[e] * inv0);
-            x[e] = (SP)0;
+            V[e] = (SP)((double)start[e] * inv0);
+            if (!a.resume) x[e] = (SP)0;
         }
+        moved = a.resume ? 3.0 * vb : 4.0 * vb;
+        if (threadIdx.x == 0 && !a.resume && a.beta0) a.beta0[pair] = beta0;
         __syncthreads();
-        int it = 0, stop = ok0 ? kGoOn : (beta0 == 0 ? kConverged : kNonFinite);
-        double est = ok0 ? beta0 : 0.0;
-        double beta = beta0;
+        int it = 0, stop = ok0 ? kGoOn : (beta == 0 ? kConverged : kNonFinite);
+        if (ok0 && beta <= a.tol * beta0) stop = kConverged;
+        double est = ok0 ? beta : 0.0;
+        int cycles = 0;
         while (stop == kGoOn || stop == kRestart) {
             if (threadIdx.x == 0) {
                 for (int i = 0; i <= M; i++) gv[2 * i] = gv[2 * i + 1] = 0;
@@ -285,12 +292,20 @@ __global__ void __launch_bounds__(NT) k_gmres(GmArgs a)
             }
             int k = 0;
             stop = kGoOn;
+            const bool use_z = z0 && cycles == 0;
             for (int j = 0; j < m && stop == kGoOn; j++) {
                 SP *vj = V + (int64_t)j * a.vstr, *w = V + (int64_t)(j + 1) * a.vstr;
-                // w = Dhat v_j
-                wg_hop<SP, LK, NT>(g, 1, vj, tmp, nullptr, 0.0, 1.0, nullptr, 0.0);
-                __syncthreads();
-                wg_hop<SP, LK, NT>(g, 0, tmp, w, vj, 1.0, -k2, nullptr, 0.0);
+                if (j == 0 && use_z) {
+                    // flexible first direction z_0 = N(v_0) = N(r) / beta: w = Dhat z_0
+                    wg_hop<SP, LK, NT>(g, 1, z0, tmp, nullptr, 0.0, 1.0, nullptr, 0.0);
+                    __syncthreads();
+                    wg_hop<SP, LK, NT>(g, 0, tmp, w, z0, 1.0 / beta, -k2 / beta, nullptr, 0.0);
+                } else {
+                    // w = Dhat v_j
+                    wg_hop<SP, LK, NT>(g, 1, vj, tmp, nullptr, 0.0, 1.0, nullptr, 0.0);
+                    __syncthreads();
+                    wg_hop<SP, LK, NT>(g, 0, tmp, w, vj, 1.0, -k2, nullptr, 0.0);
+                }
                 __syncthreads();
                 // first Gram-Schmidt pass: h = V^H w, w -= V h
                 gs_dots<SP, M, NT, NV>(sl, j + 1, h, j, false, sum);
@@ -390,7 +405,20 @@ __global__ void __launch_bounds__(NT) k_gmres(GmArgs a)
                     }
                 }
                 __syncthreads();
-                combine<SP, M, NT>(sl, make_buf(x, (uint32_t)n * (uint32_t)sizeof(SP)), 0u, h, k, yv, 1.0, 1.0);
+                combine<SP, M, NT>(sl, make_buf(x, (uint32_t)n * (uint32_t)sizeof(SP)), 0u, h, k, yv, 1.0, 1.0,
+                                   use_z ? 1 : 0);
+                if (use_z) {
+                    // x += (y_0 / beta) z0 on the same elements this thread updated
+                    const double zr = yv[0] / beta, zi = yv[1] / beta;
+                    for (int cc = 0; cc < 12; cc++)
+                        for (int s = threadIdx.x; s < h; s += NT) {
+                            const int o = 2 * cc * h + s;
+                            const double ar = (double)z0[o], ai = (double)z0[o + h];
+                            x[o] = (SP)((double)x[o] + (zr * ar - zi * ai));
+                            x[o + h] = (SP)((double)x[o + h] + (zr * ai + zi * ar));
+                        }
+                    moved += 3.0 * vb;
+                }
                 moved += (k + 2.0) * vb;
                 __syncthreads();
             }
@@ -410,6 +438,14 @@ __global__ void __launch_bounds__(NT) k_gmres(GmArgs a)
                 stop = kConverged;
                 break;
             }
+            cycles++;
+            if (a.max_cycles > 0 && cycles >= a.max_cycles && rg) {
+                // hand the residual back (for a new first direction) and resume later
+                for (int e = threadIdx.x; e < n; e += NT) rg[e] = V[e];
+                moved += 2.0 * vb;
+                stop = kPaused;
+                break;
+            }
             const double ib = 1.0 / beta;
             for (int e = threadIdx.x; e < n; e += NT) V[e] = (SP)((double)V[e] * ib);
             moved += 2.0 * vb;
@@ -421,6 +457,7 @@ __global__ void __launch_bounds__(NT) k_gmres(GmArgs a)
             if (a.bytes) a.bytes[pair] += moved;
             if (stop == kNonFinite) a.flags[pair] |= 4;
             if (a.relres) a.relres[pair] = beta0 > 0 ? est / beta0 : 0.0;
+            if (a.more) a.more[pair] = stop == kPaused ? 1 : 0;
         }
         __syncthreads();
     }
@@ -471,6 +508,8 @@ hipError_t launch_gmres(const GmArgs &a, dd_prec prec, int nt, int grid, hipStre
     const void *k = gmres_kernel(prec, gmres_basis_m(a.m), nt);
     if (!k) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_fill_i32, dim3((a.nq + 255) / 256), dim3(256), 0, st, a.qctr, a.nq, 0);
+    const int np = a.nb * a.n_rhs;
+    if (a.more) hipLaunchKernelGGL(k_fill_i32, dim3((np + 255) / 256), dim3(256), 0, st, a.more, np, 0);
     void *args[] = {const_cast<GmArgs *>(&a)};
     return hipLaunchKernel(k, dim3(grid), dim3(nt), args, 0, st);
 }

@@ -213,6 +213,12 @@ struct GmArgs {
     double tol;               // relative residual of the inner solve
     int m;                    // restart length
     int max_iter;             // Krylov steps per pair and launch
+    int resume;               // 0: start from x = 0; 1: continue from x and the paused residual r
+    void *r;                  // paused residuals (even half field, SP; may be null)
+    const void *z0;           // first flexible direction N(r) (even half field, SP; may be null)
+    int max_cycles;           // restart cycles before a pair pauses (0: never pause)
+    int32_t *more;            // [np] 1 if the pair paused (may be null)
+    double *beta0;            // [np] |f| of each pair (written on a fresh start, read on resume)
     const int32_t *nlinks;    // [nb] links inside each block
     double *bytes;            // [np] += algorithmic bytes moved (may be null)
     int32_t *iters;           // [np] += steps taken
@@ -233,7 +239,19 @@ struct NnExt {
     int S;
 };
 
+// Pairs of a half field seen as network rows (all blocks of one extent).
+struct HalfRows {
+    const int32_t *perm;      // eo position -> box-local canonical site
+    const int64_t *perm_off;  // [nb]
+    const int64_t *soff;      // [nb + 1]
+    const int32_t *h;         // [nb]
+    int nb, n_rhs, pair0, npairs, S;
+};
+
 // launch wrappers of the network (dd_nn.hip); activations are rows [row][channel]
+// dir 0: half -> rows (odd sites zero); dir 1: rows -> half_out (even sites)
+hipError_t launch_half_rows(const void *half, float *rows, void *half_out, dd_prec sp, const HalfRows &hr, int dir,
+                            hipStream_t st);
 hipError_t launch_conv(const float *X, const float *W, float *Y, int64_t nrows, const NnExt &e, int cin, int cout,
                        int mode, hipStream_t st);
 hipError_t launch_conv_dw(const float *X, const float *dY, float *part, float *dW, int64_t nrows, int nchunk,

@@ -52,6 +52,32 @@ hipError_t nn_forward(dd_ctx *ctx, const dd_nn *nn, const float *X, float *Z1, f
     return launch_conv(Z2, nn->d_w + nn->off[2], O, nrows, nn->e, 32, 24, a, st);
 }
 
+bool nn_fits(const dd_nn *nn, const dd_blocks *B) { return same_shape(nn, B); }
+
+hipError_t nn_apply_half(dd_ctx *ctx, const dd_nn *nn, const dd_blocks *B, const void *v, void *z, int n_rhs,
+                         dd_prec sp)
+{
+    const int S = nn->e.S;
+    const int np = n_rhs * B->nb;
+    const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(np, (int64_t(1) << 28) / ((int64_t)S * 32 * 4)));
+    hipError_t e = hipSuccess;
+    const size_t rows = (size_t)chunk * S;
+    float *X = (float *)workspace(ctx, "nn_hX", rows * 24 * 4, &e);
+    float *Z1 = X ? (float *)workspace(ctx, "nn_hZ1", rows * 32 * 4, &e) : nullptr;
+    float *Z2 = Z1 ? (float *)workspace(ctx, "nn_hZ2", rows * 32 * 4, &e) : nullptr;
+    float *O = Z2 ? (float *)workspace(ctx, "nn_hO", rows * 24 * 4, &e) : nullptr;
+    if (!O) return e;
+    HalfRows hr{B->d_perm, B->d_perm_off, B->d_soff, B->d_h, B->nb, n_rhs, 0, 0, S};
+    for (int p0 = 0; p0 < np && e == hipSuccess; p0 += chunk) {
+        hr.pair0 = p0;
+        hr.npairs = std::min(chunk, np - p0);
+        e = launch_half_rows(v, X, nullptr, sp, hr, 0, ctx->stream);
+        if (e == hipSuccess) e = nn_forward(ctx, nn, X, Z1, Z2, O, (int64_t)hr.npairs * S);
+        if (e == hipSuccess) e = launch_half_rows(nullptr, O, z, sp, hr, 1, ctx->stream);
+    }
+    return e;
+}
+
 }  // namespace dd
 
 namespace {

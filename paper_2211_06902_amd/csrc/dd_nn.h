@@ -29,4 +29,11 @@ namespace dd {
 // pre-activations Z1, Z2 [rows][32]
 hipError_t nn_forward(dd_ctx *ctx, const dd_nn *nn, const float *X, float *Z1, float *Z2, float *O, int64_t nrows);
 
+// z = N(v) for every (block, rhs) pair of an even half field in the library
+// layout (inner precision sp); v and z may not alias.  Blocks must all have
+// the network's extent (checked by the caller).
+hipError_t nn_apply_half(dd_ctx *ctx, const dd_nn *nn, const dd_blocks *B, const void *v, void *z, int n_rhs,
+                         dd_prec sp);
+bool nn_fits(const dd_nn *nn, const dd_blocks *B);
+
 }  // namespace dd

@@ -283,6 +283,45 @@ __global__ void k_adam(float *__restrict__ w, const float *__restrict__ g, float
     w[k] -= lr * (mk / c1) / (sqrtf(vk / c2) + eps);
 }
 
+// Network rows of pairs pair0 .. pair0 + npairs - 1 from an even half field in
+// the library layout: the block's even sites carry the field, odd sites zero.
+template <typename SP>
+__global__ void k_half_to_rows(const SP *__restrict__ half, float *__restrict__ rows, HalfRows hr)
+{
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= (int64_t)hr.npairs * hr.S) return;
+    const int pl = (int)(k / hr.S), q = (int)(k - (int64_t)pl * hr.S);
+    const int pair = hr.pair0 + pl, b = pair % hr.nb, r = pair / hr.nb;
+    const int hb = hr.h[b];
+    const int s = hr.perm[hr.perm_off[b] + q];
+    float *row = rows + ((int64_t)pl * hr.S + s) * 24;
+    if (q < hb) {
+        const SP *src = half + (hr.soff[b] >> 1) * 24 * hr.n_rhs + (int64_t)r * 24 * hb + q;
+#pragma unroll
+        for (int c = 0; c < 24; c++) row[c] = (float)src[(int64_t)c * hb];
+    } else {
+#pragma unroll
+        for (int c = 0; c < 24; c++) row[c] = 0.0f;
+    }
+}
+
+// even sites of network rows back into an even half field
+template <typename SP>
+__global__ void k_rows_to_half(const float *__restrict__ rows, SP *__restrict__ half, HalfRows hr)
+{
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= (int64_t)hr.npairs * hr.S) return;
+    const int pl = (int)(k / hr.S), q = (int)(k - (int64_t)pl * hr.S);
+    const int pair = hr.pair0 + pl, b = pair % hr.nb, r = pair / hr.nb;
+    const int hb = hr.h[b];
+    if (q >= hb) return;
+    const int s = hr.perm[hr.perm_off[b] + q];
+    const float *row = rows + ((int64_t)pl * hr.S + s) * 24;
+    SP *dst = half + (hr.soff[b] >> 1) * 24 * hr.n_rhs + (int64_t)r * 24 * hb + q;
+#pragma unroll
+    for (int c = 0; c < 24; c++) dst[(int64_t)c * hb] = (SP)row[c];
+}
+
 // ------------------------------------------------------------ launchers
 
 static inline dim3 g256(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
@@ -349,6 +388,20 @@ hipError_t launch_loss(const float *out, const float *T, const int32_t *opar, co
     if (grad)
         hipLaunchKernelGGL(k_loss_grad, g256((int64_t)n * e.S * 24), dim3(256), 0, st, out, T, opar, idx, den, grad, n,
                            mask_even, e);
+    return hipGetLastError();
+}
+
+hipError_t launch_half_rows(const void *half, float *rows, void *half_out, dd_prec sp, const HalfRows &hr, int dir,
+                            hipStream_t st)
+{
+    const dim3 g = g256((int64_t)hr.npairs * hr.S);
+    if (dir == 0) {
+        if (sp == DD_F64) hipLaunchKernelGGL(k_half_to_rows<double>, g, dim3(256), 0, st, (const double *)half, rows, hr);
+        else hipLaunchKernelGGL(k_half_to_rows<float>, g, dim3(256), 0, st, (const float *)half, rows, hr);
+    } else {
+        if (sp == DD_F64) hipLaunchKernelGGL(k_rows_to_half<double>, g, dim3(256), 0, st, rows, (double *)half_out, hr);
+        else hipLaunchKernelGGL(k_rows_to_half<float>, g, dim3(256), 0, st, rows, (float *)half_out, hr);
+    }
     return hipGetLastError();
 }
 

@@ -26,6 +26,7 @@
 
 #include "dd_host.h"
 #include "dd_internal.h"
+#include "dd_nn.h"
 
 using namespace dd;
 
@@ -180,6 +181,9 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
     if (prm.method != DD_BICGSTAB && prm.method != DD_GMRES) return fail(ctx, DD_EINVAL, "unknown method");
     const bool gmres = prm.method == DD_GMRES;
     if (gmres && (prm.restart < 1 || prm.restart > 16)) return fail(ctx, DD_EINVAL, "restart must be in 1..16");
+    const dd_nn *nn = prm.precond;
+    if (nn && !gmres) return fail(ctx, DD_EINVAL, "a network preconditioner needs method DD_GMRES");
+    if (nn && !nn_fits(nn, Bc)) return fail(ctx, DD_EINVAL, "every block must have the network's extent");
     const dd_prec ip = prm.inner_prec;
     const void *links = links_for(G, ip);
     if (!links) return fail(ctx, DD_EINVAL, "gauge holds no links of the inner precision");
@@ -188,7 +192,7 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
     const int max_outer = prm.max_outer > 0 ? prm.max_outer : 30;
     const int max_inner = prm.max_inner > 0 ? prm.max_inner : 2000;
     const int check = prm.check_every > 0 ? prm.check_every : 8;
-    const bool graph = prm.use_graph && !ctx->timing;
+    const bool graph = prm.use_graph && !ctx->timing && !nn;
 
     dd_blocks *B = const_cast<dd_blocks *>(Bc);
     HIPCHECK(ctx, enter(ctx));
@@ -233,7 +237,9 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
     w.tmp = get("s_tmp", hsp);
     int gm_nt = 0, gm_nq = 0, gm_grid = 0;
     void *gm_ws = nullptr;
-    double *gm_bytes = nullptr;
+    double *gm_bytes = nullptr, *gm_beta0 = nullptr;
+    void *gm_r = nullptr, *gm_z0 = nullptr;
+    int32_t *gm_more[2] = {nullptr, nullptr};
     const QueueTable *qt = nullptr;
     const int64_t vstr = 24 * (int64_t)B->max_h;
     if (gmres) {
@@ -242,6 +248,13 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
         if (!qt) return fail(ctx, DD_EDEVICE, std::string("work queues: ") + hipGetErrorString(e));
         gm_ws = get("g_basis", (size_t)gm_grid * (gmres_basis_m(prm.restart) + 2) * vstr * prec_bytes(sp));
         gm_bytes = (double *)get("g_bytes", (size_t)np * sizeof(double));
+        gm_beta0 = (double *)get("g_beta0", (size_t)np * sizeof(double));
+        if (nn) {
+            gm_r = get("g_r", hsp);
+            gm_z0 = get("g_z0", hsp);
+            gm_more[0] = (int32_t *)get("g_moreA", (size_t)np * sizeof(int32_t));
+            gm_more[1] = (int32_t *)get("g_moreB", (size_t)np * sizeof(int32_t));
+        }
         if ((gmres_basis_m(prm.restart) + 2) * (double)vstr * prec_bytes(sp) >= 4294967296.0)
             return fail(ctx, DD_EUNSUPPORTED, "blocks too large for the GMRES basis slots (32-bit offsets)");
     } else {
@@ -347,7 +360,37 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
             ga.iters = w.ps.iters;
             ga.flags = w.ps.flags;
             ga.relres = nullptr;
-            if (graph) {
+            ga.resume = 0;
+            ga.r = gm_r;
+            ga.z0 = nullptr;
+            ga.max_cycles = 0;
+            ga.more = nullptr;
+            ga.beta0 = gm_beta0;
+            if (nn) {
+                // flexible GMRES: first direction N(f) of the first cycle, then N(r) of every
+                // precond_cycles-th restart, the network applied to all pairs between launches
+                HIPCHECK(ctx, nn_apply_half(ctx, nn, B, w.rhs, gm_z0, n_rhs, sp));
+                ga.z0 = gm_z0;
+                ga.max_cycles = prm.precond_cycles > 0 ? prm.precond_cycles : 0;
+                ga.more = gm_more[0];
+                const int rounds = max_inner / std::max(1, prm.restart * std::max(1, ga.max_cycles)) + 1;
+                for (int rd = 0; rd < rounds; rd++) {
+                    {
+                        TimedLaunch tl(ctx, DD_KCLASS_GMRES, 0.0);
+                        HIPCHECK(ctx, launch_gmres(ga, ip, gm_nt, gm_grid, st));
+                    }
+                    if (ga.max_cycles == 0) break;
+                    HIPCHECK(ctx, hipMemcpyAsync(h_act.data(), ga.more, np * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+                    HIPCHECK(ctx, hipStreamSynchronize(st));
+                    int paused = 0;
+                    for (int v : h_act) paused += v != 0;
+                    if (paused == 0) break;
+                    HIPCHECK(ctx, nn_apply_half(ctx, nn, B, gm_r, gm_z0, n_rhs, sp));
+                    ga.resume = 1;
+                    ga.active = ga.more;
+                    ga.more = ga.more == gm_more[0] ? gm_more[1] : gm_more[0];
+                }
+            } else if (graph) {
                 // one defect-correction cycle's inner solve as a graph: clear the
                 // queue counters, then the persistent launch
                 if (!gx) {

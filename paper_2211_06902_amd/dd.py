@@ -71,6 +71,8 @@ class SolveParams(ctypes.Structure):
         ("max_inner", _I32),
         ("check_every", _I32),
         ("use_graph", _I32),
+        ("precond", _P),
+        ("precond_cycles", _I32),
     ]
 
 
@@ -200,6 +202,8 @@ def solve_params(**kw) -> SolveParams:
     for k, v in kw.items():
         if k == "inner_prec":
             v = _PREC[v]
+        if k == "precond" and isinstance(v, Net):
+            v = v._h
         setattr(p, k, v)
     return p
 

@@ -124,11 +124,10 @@ def test_adam_step_matches_oracle(ctx):
     blk.close()
 
 
-def test_training_on_solver_pairs_lowers_validation_loss(ctx):
-    """Train on (source, D^{-1} source) pairs of 4^4 blocks (sources on even sites) made by the
-    block solver; the held-out loss must fall well below that of the untrained network."""
-    import torch
-
+@pytest.fixture(scope="module")
+def toy(ctx):
+    """8^4 lattice in 16 blocks of 4^4 (kappa 0.12, links exp(0.3 i H)), (source, solution)
+    pairs made by the block solver with sources on even sites, and a network trained on them."""
     from paper_2211_06902_amd import dd
 
     L = (8, 8, 8, 8)
@@ -149,14 +148,67 @@ def test_training_on_solver_pairs_lowers_validation_loss(ctx):
     src, sol = pairs(24, 52)
     vsrc, vsol = pairs(8, 53)
     net = ctx.nn_create((4, 4, 4, 4), synth.convnet_weights(54))
-    p = dd.nn_train_params(epochs=1, batch=16, lr=2e-3)
-    tl0, vl0 = net.train(blk, src, sol, 24, vsrc, vsol, 8, params=dd.nn_train_params(epochs=1, batch=16, lr=1e-9))
-    p = dd.nn_train_params(epochs=25, batch=16, lr=2e-3)
-    tl, vl = net.train(blk, src, sol, 24, vsrc, vsol, 8, params=p)
-    print("val loss untrained %.4f -> %s" % (vl0[0], np.array2string(vl[::6], precision=4)))
-    assert vl[-1] < 0.5 * vl0[0]
-    assert tl[-1] < tl[0]
+    _, vl0 = net.train(blk, src, sol, 24, vsrc, vsol, 8, params=dd.nn_train_params(epochs=1, batch=16, lr=1e-9))
+    tl, vl = net.train(blk, src, sol, 24, vsrc, vsol, 8, params=dd.nn_train_params(epochs=25, batch=16, lr=2e-3))
+    yield dict(L=L, U=U, kappa=kappa, blk=blk, g=g, net=net, vl0=vl0, tl=tl, vl=vl)
     net.close()
     g.close()
     blk.close()
-    torch.cuda.synchronize()
+
+
+def test_training_on_solver_pairs_lowers_validation_loss(toy):
+    """Held-out loss of the trained network well below that of the untrained one."""
+    print("val loss untrained %.4f -> %s" % (toy["vl0"][0], np.array2string(toy["vl"][::6], precision=4)))
+    assert toy["vl"][-1] < 0.5 * toy["vl0"][0]
+    assert toy["tl"][-1] < toy["tl"][0]
+
+
+@pytest.mark.parametrize("cycles", [0, 1])
+def test_fgmres_with_trained_network(ctx, toy, cycles):
+    """Flexible GMRES with the network's first directions: same FP64 1e-10 solutions, fewer Krylov steps."""
+    from oracle import geometry, wilson
+    from tests import _cfg
+
+    from paper_2211_06902_amd import dd
+
+    b = synth.spinor_field(toy["L"], 4, 61)[:, _cfg.block_sites(toy["L"], geometry.tile_boxes(toy["L"], [[4, 4]] * 4))]
+    bd = _dev(b)
+    base = dict(method=dd.GMRES, restart=8, inner_prec="f32")
+    x0, i0, s0 = ctx.block_solve(toy["blk"], toy["g"], toy["kappa"], bd, params=dd.solve_params(**base))
+    x1, i1, s1 = ctx.block_solve(toy["blk"], toy["g"], toy["kappa"], bd,
+                                 params=dd.solve_params(precond=toy["net"], precond_cycles=cycles, **base))
+    print("GMRES(8) steps per pair: plain %.1f, with network (every %d cycles) %.1f" %
+          (i0["iters"].mean(), cycles, i1["iters"].mean()))
+    assert s0 == dd.DD_OK and s1 == dd.DD_OK
+    assert np.all(i1["true_relres"] <= 1e-10)
+    assert _cfg.rel_err(x1.cpu().numpy(), x0.cpu().numpy()) <= 1e-8
+    boxes = geometry.tile_boxes(toy["L"], [[4, 4]] * 4)
+    xh = x1.cpu().numpy()
+    for k in (0, 9):
+        sl = slice(256 * k, 256 * (k + 1))
+        r = b[2, sl] - wilson.dirac_box(toy["L"], -1, toy["kappa"], toy["U"], boxes[k][:4], boxes[k][4:8], xh[2, sl])
+        assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(b[2, sl])
+    assert i1["iters"].mean() < i0["iters"].mean()
+
+
+def test_fgmres_with_an_untrained_network_still_converges(ctx, toy):
+    from paper_2211_06902_amd import dd
+
+    net = ctx.nn_create((4, 4, 4, 4), synth.convnet_weights(71, scale=1.0, identity=False))
+    b = _dev(synth.gaussian_complex((2, 8**4, 4, 3), 72))
+    x, info, st = ctx.block_solve(toy["blk"], toy["g"], toy["kappa"], b,
+                                  params=dd.solve_params(method=dd.GMRES, restart=8, precond=net, precond_cycles=1))
+    assert st == dd.DD_OK and np.all(info["true_relres"] <= 1e-10)
+    net.close()
+
+
+def test_network_on_blocks_of_another_extent_is_rejected(ctx, toy):
+    from paper_2211_06902_amd import dd
+
+    blk = ctx.make_blocks(toy["L"], -1, [[8]] * 4)
+    g = ctx.load_gauge(blk, _dev(toy["U"]), "f32")
+    with pytest.raises(dd.DDError):
+        ctx.block_solve(blk, g, toy["kappa"], _dev(synth.gaussian_complex((1, 8**4, 4, 3), 73)),
+                        params=dd.solve_params(method=dd.GMRES, precond=toy["net"]))
+    g.close()
+    blk.close()
