@@ -296,8 +296,13 @@ int64_t dd_nn_num_weights(void);
 dd_status dd_nn_create(dd_ctx *ctx, const int32_t extent[4], int32_t act, const float *weights_host, dd_nn **out);
 dd_status dd_nn_free(dd_nn *nn);
 dd_status dd_nn_get_weights(dd_ctx *ctx, const dd_nn *nn, float *weights_host);
-/* y = N(x) on n blocks' rows (device FP32, [n][S][24] each); synchronizes. */
-dd_status dd_nn_apply(dd_ctx *ctx, const dd_nn *nn, const float *x_dev, float *y_dev, int64_t n);
+/* y = N(x) on n blocks' rows (device FP32, [n][S][24] each); synchronizes.
+ * prec DD_F32: FP32 arithmetic; DD_BF16: weights, input and hidden activations
+ * rounded to BF16 (nearest even), products on the matrix cores with FP32
+ * accumulation, FP32 output. */
+dd_status dd_nn_apply(dd_ctx *ctx, dd_nn *nn, dd_prec prec, const float *x_dev, float *y_dev, int64_t n);
+/* Precision of the network when a solve applies it (default DD_BF16). */
+dd_status dd_nn_set_inference(dd_ctx *ctx, dd_nn *nn, dd_prec prec);
 
 typedef struct {
     int32_t epochs;     /* passes over the training pairs (default 4) */

@@ -265,6 +265,13 @@ hipError_t launch_loss(const float *out, const float *T, const int32_t *opar, co
                        hipStream_t st);
 hipError_t launch_adam(float *w, const float *g, float *m, float *v, int64_t n, float lr, float b1, float b2, float eps,
                        int t, hipStream_t st);
+// BF16 matrix-core inference: X [rows][32] BF16, Wt [81][32][32] BF16; Y BF16 [rows][32]
+// (act applied) or, with out_f32, FP32 [rows][24]
+hipError_t launch_conv_mfma(const uint16_t *X, const uint16_t *Wt, void *Y, int64_t nrows, const NnExt &e, int act,
+                            bool out_f32, hipStream_t st);
+hipError_t launch_weights_bf16(const float *W, uint16_t *Wt, int cin, int cout, hipStream_t st);
+hipError_t launch_half_rows_bf16(const void *half, uint16_t *rows, dd_prec sp, const HalfRows &hr, hipStream_t st);
+hipError_t launch_rows_f32_to_bf16(const float *X, uint16_t *Xb, int64_t nrows, hipStream_t st);
 
 // launch wrappers (dd_kernels.hip)
 hipError_t launch_pack_gauge(const dd_blocks *B, const double *U, dd_prec prec, void *dst,

@@ -54,25 +54,48 @@ hipError_t nn_forward(dd_ctx *ctx, const dd_nn *nn, const float *X, float *Z1, f
 
 bool nn_fits(const dd_nn *nn, const dd_blocks *B) { return same_shape(nn, B); }
 
-hipError_t nn_apply_half(dd_ctx *ctx, const dd_nn *nn, const dd_blocks *B, const void *v, void *z, int n_rhs,
-                         dd_prec sp)
+hipError_t nn_forward_bf16(dd_ctx *ctx, dd_nn *nn, const uint16_t *Xb, uint16_t *Zb1, uint16_t *Zb2, float *O,
+                           int64_t nrows)
+{
+    hipStream_t st = ctx->stream;
+    hipError_t e = hipSuccess;
+    if (nn->bf16_step != nn->step) {
+        for (int l = 0; l < 3 && e == hipSuccess; l++)
+            e = launch_weights_bf16(nn->d_w + nn->off[l], nn->d_wbf + l * 81 * 1024, kCh[l], kCh[l + 1], st);
+        if (e != hipSuccess) return e;
+        nn->bf16_step = nn->step;
+    }
+    if ((e = launch_conv_mfma(Xb, nn->d_wbf, Zb1, nrows, nn->e, nn->act, false, st)) != hipSuccess) return e;
+    if ((e = launch_conv_mfma(Zb1, nn->d_wbf + 81 * 1024, Zb2, nrows, nn->e, nn->act, false, st)) != hipSuccess) return e;
+    return launch_conv_mfma(Zb2, nn->d_wbf + 2 * 81 * 1024, O, nrows, nn->e, 0, true, st);
+}
+
+hipError_t nn_apply_half(dd_ctx *ctx, dd_nn *nn, const dd_blocks *B, const void *v, void *z, int n_rhs, dd_prec sp)
 {
     const int S = nn->e.S;
     const int np = n_rhs * B->nb;
     const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(np, (int64_t(1) << 28) / ((int64_t)S * 32 * 4)));
     hipError_t e = hipSuccess;
     const size_t rows = (size_t)chunk * S;
-    float *X = (float *)workspace(ctx, "nn_hX", rows * 24 * 4, &e);
-    float *Z1 = X ? (float *)workspace(ctx, "nn_hZ1", rows * 32 * 4, &e) : nullptr;
-    float *Z2 = Z1 ? (float *)workspace(ctx, "nn_hZ2", rows * 32 * 4, &e) : nullptr;
+    const bool bf = nn->infer_prec == DD_BF16;
+    const size_t hb = bf ? 2 : 4;  // bytes per hidden value
+    void *X = workspace(ctx, "nn_hX", rows * (bf ? 32 * 2 : 24 * 4), &e);
+    void *Z1 = X ? workspace(ctx, "nn_hZ1", rows * 32 * hb, &e) : nullptr;
+    void *Z2 = Z1 ? workspace(ctx, "nn_hZ2", rows * 32 * hb, &e) : nullptr;
     float *O = Z2 ? (float *)workspace(ctx, "nn_hO", rows * 24 * 4, &e) : nullptr;
     if (!O) return e;
     HalfRows hr{B->d_perm, B->d_perm_off, B->d_soff, B->d_h, B->nb, n_rhs, 0, 0, S};
     for (int p0 = 0; p0 < np && e == hipSuccess; p0 += chunk) {
         hr.pair0 = p0;
         hr.npairs = std::min(chunk, np - p0);
-        e = launch_half_rows(v, X, nullptr, sp, hr, 0, ctx->stream);
-        if (e == hipSuccess) e = nn_forward(ctx, nn, X, Z1, Z2, O, (int64_t)hr.npairs * S);
+        const int64_t nrows = (int64_t)hr.npairs * S;
+        if (bf) {
+            e = launch_half_rows_bf16(v, (uint16_t *)X, sp, hr, ctx->stream);
+            if (e == hipSuccess) e = nn_forward_bf16(ctx, nn, (uint16_t *)X, (uint16_t *)Z1, (uint16_t *)Z2, O, nrows);
+        } else {
+            e = launch_half_rows(v, (float *)X, nullptr, sp, hr, 0, ctx->stream);
+            if (e == hipSuccess) e = nn_forward(ctx, nn, (float *)X, (float *)Z1, (float *)Z2, O, nrows);
+        }
         if (e == hipSuccess) e = launch_half_rows(nullptr, O, z, sp, hr, 1, ctx->stream);
     }
     return e;
@@ -207,6 +230,7 @@ dd_status dd_nn_create(dd_ctx *ctx, const int32_t extent[4], int32_t act, const 
     for (float **p : bufs)
         if (e == hipSuccess) e = hipMalloc((void **)p, wb);
     if (e == hipSuccess) e = hipMalloc((void **)&nn->d_wf, 81 * 32 * 32 * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc((void **)&nn->d_wbf, 3 * 81 * 32 * 32 * sizeof(uint16_t));
     if (e == hipSuccess) e = hipMalloc((void **)&nn->d_part, (size_t)kChunksDw * 81 * 32 * 32 * sizeof(float));
     if (e == hipSuccess) e = hipMemcpy(nn->d_w, weights_host, wb, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(nn->d_m, 0, wb);
@@ -223,7 +247,7 @@ dd_status dd_nn_free(dd_nn *nn)
 {
     if (!nn) return DD_EINVAL;
     hipSetDevice(nn->device);
-    void *ptrs[] = {nn->d_w, nn->d_g, nn->d_m, nn->d_v, nn->d_wf, nn->d_part};
+    void *ptrs[] = {nn->d_w, nn->d_g, nn->d_m, nn->d_v, nn->d_wf, nn->d_part, nn->d_wbf};
     for (void *p : ptrs)
         if (p) hipFree(p);
     delete nn;
@@ -239,23 +263,38 @@ dd_status dd_nn_get_weights(dd_ctx *ctx, const dd_nn *nn, float *weights_host)
     return DD_OK;
 }
 
-dd_status dd_nn_apply(dd_ctx *ctx, const dd_nn *nn, const float *x_dev, float *y_dev, int64_t n)
+dd_status dd_nn_apply(dd_ctx *ctx, dd_nn *nn, dd_prec prec, const float *x_dev, float *y_dev, int64_t n)
 {
     if (!ctx || !nn || (n > 0 && (!x_dev || !y_dev))) return fail(ctx, DD_EINVAL, "null argument");
     if (n < 0) return fail(ctx, DD_EINVAL, "n must be >= 0");
+    if (prec != DD_F32 && prec != DD_BF16) return fail(ctx, DD_EINVAL, "network precision must be DD_F32 or DD_BF16");
     HIPCHECK(ctx, enter(ctx));
     const int64_t chunk = std::max<int64_t>(1, (int64_t(1) << 28) / ((int64_t)nn->e.S * 32 * 4));  // ~256 MiB per buffer
     hipError_t e = hipSuccess;
-    const int64_t rows = std::min(n, chunk) * nn->e.S;
-    float *Z1 = (float *)workspace(ctx, "nn_aZ1", (size_t)std::max<int64_t>(rows, 1) * 32 * 4, &e);
-    float *Z2 = Z1 ? (float *)workspace(ctx, "nn_aZ2", (size_t)std::max<int64_t>(rows, 1) * 32 * 4, &e) : nullptr;
-    if (!Z2) return fail(ctx, DD_ENOMEM, std::string("network workspace: ") + hipGetErrorString(e));
+    const size_t rows = (size_t)std::max<int64_t>(std::min(n, chunk) * nn->e.S, 1);
+    void *Z1 = workspace(ctx, "nn_aZ1", rows * 32 * 4, &e);
+    void *Z2 = Z1 ? workspace(ctx, "nn_aZ2", rows * 32 * 4, &e) : nullptr;
+    void *Xb = Z2 ? workspace(ctx, "nn_aXb", rows * 32 * 2, &e) : nullptr;
+    if (!Xb) return fail(ctx, DD_ENOMEM, std::string("network workspace: ") + hipGetErrorString(e));
     for (int64_t i0 = 0; i0 < n; i0 += chunk) {
         const int64_t m = std::min(chunk, n - i0);
-        const int64_t off = i0 * nn->e.S * 24;
-        HIPCHECK(ctx, nn_forward(ctx, nn, x_dev + off, Z1, Z2, y_dev + off, m * nn->e.S));
+        const int64_t off = i0 * nn->e.S * 24, nrows = m * nn->e.S;
+        if (prec == DD_F32) {
+            HIPCHECK(ctx, nn_forward(ctx, nn, x_dev + off, (float *)Z1, (float *)Z2, y_dev + off, nrows));
+        } else {
+            HIPCHECK(ctx, launch_rows_f32_to_bf16(x_dev + off, (uint16_t *)Xb, nrows, ctx->stream));
+            HIPCHECK(ctx, nn_forward_bf16(ctx, nn, (uint16_t *)Xb, (uint16_t *)Z1, (uint16_t *)Z2, y_dev + off, nrows));
+        }
     }
     HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+    return DD_OK;
+}
+
+dd_status dd_nn_set_inference(dd_ctx *ctx, dd_nn *nn, dd_prec prec)
+{
+    if (!ctx || !nn) return fail(ctx, DD_EINVAL, "null argument");
+    if (prec != DD_F32 && prec != DD_BF16) return fail(ctx, DD_EINVAL, "network precision must be DD_F32 or DD_BF16");
+    nn->infer_prec = prec;
     return DD_OK;
 }
 

@@ -21,6 +21,9 @@ struct dd_nn {
     float *d_wf = nullptr;  // one layer's flipped weights (backward pass)
     float *d_part = nullptr;  // weight-gradient partials per row chunk
     int step = 0;             // Adam steps taken
+    uint16_t *d_wbf = nullptr;  // BF16 inference weights, per layer [81][32 out][32 in]
+    int bf16_step = -1;         // Adam step the BF16 weights were made at
+    int infer_prec = DD_BF16;   // precision of the network inside solves (DD_BF16 or DD_F32)
 };
 
 namespace dd {
@@ -32,8 +35,11 @@ hipError_t nn_forward(dd_ctx *ctx, const dd_nn *nn, const float *X, float *Z1, f
 // z = N(v) for every (block, rhs) pair of an even half field in the library
 // layout (inner precision sp); v and z may not alias.  Blocks must all have
 // the network's extent (checked by the caller).
-hipError_t nn_apply_half(dd_ctx *ctx, const dd_nn *nn, const dd_blocks *B, const void *v, void *z, int n_rhs,
-                         dd_prec sp);
+hipError_t nn_apply_half(dd_ctx *ctx, dd_nn *nn, const dd_blocks *B, const void *v, void *z, int n_rhs, dd_prec sp);
 bool nn_fits(const dd_nn *nn, const dd_blocks *B);
+
+// the network in BF16 on the matrix cores: Xb [rows][32] BF16 -> O [rows][24] FP32
+hipError_t nn_forward_bf16(dd_ctx *ctx, dd_nn *nn, const uint16_t *Xb, uint16_t *Zb1, uint16_t *Zb2, float *O,
+                           int64_t nrows);
 
 }  // namespace dd

@@ -322,6 +322,137 @@ __global__ void k_rows_to_half(const float *__restrict__ rows, SP *__restrict__ 
     for (int c = 0; c < 24; c++) dst[(int64_t)c * hb] = (SP)row[c];
 }
 
+// ------------------------------------------------- BF16 matrix-core inference
+//
+// Implicit GEMM per tap: for the 81 offsets t, Y[rows, :] += X[rows + t, :] W[t]
+// with K = 32 input channels per tap (zero padded), N = 32 output channels and
+// the rows of a wavefront in tiles of 16; v_mfma_f32_16x16x32_bf16 multiplies a
+// 16 x 32 tile of neighbour rows by the tap's 32 x 16 weight block with FP32
+// accumulation.  Lane l supplies row (l mod 16) of A and column (l mod 16) of B,
+// each with the 8 consecutive channels 8 (l / 16) .. 8 (l / 16) + 7 (16 bytes);
+// it receives rows 4 (l / 16) .. 4 (l / 16) + 3 of column (l mod 16) of the
+// 16 x 16 product.
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+
+__device__ __forceinline__ uint16_t f2bf(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)(((u >> 16) & 0x8000u) | 0x7fc0u);
+    return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+// Y = act(conv(X, W)): X [rows][32] BF16, Wt [81][32 out][32 in] BF16;
+// OUT_F32: Y [rows][24] FP32 (last layer), else [rows][32] BF16 after ACT.
+// A wavefront computes 64 rows x 32 channels; a workgroup 256 rows.
+template <int ACT, bool OUT_F32>
+__global__ void __launch_bounds__(256) k_conv_mfma(const uint16_t *__restrict__ X, const uint16_t *__restrict__ Wt,
+                                                   void *__restrict__ Y, int64_t nrows, NnExt e)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * 64;
+    if (row0 >= nrows) return;
+    const int kg = lane >> 4, li = lane & 15;
+    const int st[4] = {e.e[1] * e.e[2] * e.e[3], e.e[2] * e.e[3], e.e[3], 1};
+    int64_t arow[4];
+    int ac[4][4];
+    bool alive[4];
+#pragma unroll
+    for (int rt = 0; rt < 4; rt++) {
+        arow[rt] = row0 + rt * 16 + li;
+        alive[rt] = arow[rt] < nrows;
+        const int64_t n = arow[rt] / e.S;
+        site_coords((int)(arow[rt] - n * e.S), e, ac[rt]);
+    }
+    f32x4 acc[4][2];
+#pragma unroll
+    for (int rt = 0; rt < 4; rt++)
+#pragma unroll
+        for (int ct = 0; ct < 2; ct++) acc[rt][ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+    const bf16x8 zero = {};
+    for (int tap = 0; tap < 81; tap++) {
+        const int t0 = tap / 27 - 1, t1 = (tap / 9) % 3 - 1, t2 = (tap / 3) % 3 - 1, t3 = tap % 3 - 1;
+        const int off = t0 * st[0] + t1 * st[1] + t2 * st[2] + t3 * st[3];
+        bf16x8 bv[2];
+#pragma unroll
+        for (int ct = 0; ct < 2; ct++)
+            bv[ct] = *reinterpret_cast<const bf16x8 *>(Wt + ((int64_t)(tap * 32 + ct * 16 + li) * 32 + kg * 8));
+        bf16x8 av[4];
+#pragma unroll
+        for (int rt = 0; rt < 4; rt++) {
+            const bool in = alive[rt] && (unsigned)(ac[rt][0] + t0) < (unsigned)e.e[0] &&
+                            (unsigned)(ac[rt][1] + t1) < (unsigned)e.e[1] &&
+                            (unsigned)(ac[rt][2] + t2) < (unsigned)e.e[2] && (unsigned)(ac[rt][3] + t3) < (unsigned)e.e[3];
+            av[rt] = in ? *reinterpret_cast<const bf16x8 *>(X + (arow[rt] + off) * 32 + kg * 8) : zero;
+        }
+#pragma unroll
+        for (int rt = 0; rt < 4; rt++)
+#pragma unroll
+            for (int ct = 0; ct < 2; ct++)
+                acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[rt], bv[ct], acc[rt][ct], 0, 0, 0);
+    }
+#pragma unroll
+    for (int rt = 0; rt < 4; rt++)
+#pragma unroll
+        for (int ct = 0; ct < 2; ct++)
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int64_t r = row0 + rt * 16 + 4 * kg + i;
+                const int col = ct * 16 + li;
+                if (r >= nrows) continue;
+                float v = acc[rt][ct][i];
+                if constexpr (OUT_F32) {
+                    if (col < 24) reinterpret_cast<float *>(Y)[r * 24 + col] = v;
+                } else {
+                    if (ACT) v = fmaxf(v, 0.0f);
+                    reinterpret_cast<uint16_t *>(Y)[r * 32 + col] = f2bf(v);
+                }
+            }
+}
+
+// Wt[t][o][c] = bf16(W[t][c][o]) for o < cout, c < cin; 0 elsewhere (32 x 32 per tap)
+__global__ void k_weights_bf16(const float *__restrict__ W, uint16_t *__restrict__ Wt, int cin, int cout)
+{
+    const int k = blockIdx.x * 256 + threadIdx.x;
+    if (k >= 81 * 32 * 32) return;
+    const int t = k / 1024, o = (k / 32) % 32, c = k % 32;
+    Wt[k] = (o < cout && c < cin) ? f2bf(W[((int64_t)t * cin + c) * cout + o]) : (uint16_t)0;
+}
+
+// network rows in BF16 (32 channels, 24..31 zero) from an even half field
+template <typename SP>
+__global__ void k_half_to_rows_bf16(const SP *__restrict__ half, uint16_t *__restrict__ rows, HalfRows hr)
+{
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= (int64_t)hr.npairs * hr.S) return;
+    const int pl = (int)(k / hr.S), q = (int)(k - (int64_t)pl * hr.S);
+    const int pair = hr.pair0 + pl, b = pair % hr.nb, r = pair / hr.nb;
+    const int hb = hr.h[b];
+    const int s = hr.perm[hr.perm_off[b] + q];
+    uint16_t *row = rows + ((int64_t)pl * hr.S + s) * 32;
+    if (q < hb) {
+        const SP *src = half + (hr.soff[b] >> 1) * 24 * hr.n_rhs + (int64_t)r * 24 * hb + q;
+#pragma unroll
+        for (int c = 0; c < 24; c++) row[c] = f2bf((float)src[(int64_t)c * hb]);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 24; c++) row[c] = 0;
+    }
+#pragma unroll
+    for (int c = 24; c < 32; c++) row[c] = 0;
+}
+
+// FP32 rows [rows][24] -> BF16 rows [rows][32]
+__global__ void k_rows_f32_to_bf16(const float *__restrict__ X, uint16_t *__restrict__ Xb, int64_t nrows)
+{
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k >= nrows * 32) return;
+    const int64_t r = k / 32;
+    const int c = (int)(k - r * 32);
+    Xb[k] = c < 24 ? f2bf(X[r * 24 + c]) : (uint16_t)0;
+}
+
 // ------------------------------------------------------------ launchers
 
 static inline dim3 g256(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
@@ -402,6 +533,37 @@ hipError_t launch_half_rows(const void *half, float *rows, void *half_out, dd_pr
         if (sp == DD_F64) hipLaunchKernelGGL(k_rows_to_half<double>, g, dim3(256), 0, st, rows, (double *)half_out, hr);
         else hipLaunchKernelGGL(k_rows_to_half<float>, g, dim3(256), 0, st, rows, (float *)half_out, hr);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_conv_mfma(const uint16_t *X, const uint16_t *Wt, void *Y, int64_t nrows, const NnExt &e, int act,
+                            bool out_f32, hipStream_t st)
+{
+    if (nrows <= 0) return hipSuccess;
+    const dim3 g((unsigned)((nrows + 255) / 256));
+    if (out_f32) hipLaunchKernelGGL((k_conv_mfma<0, true>), g, dim3(256), 0, st, X, Wt, Y, nrows, e);
+    else if (act) hipLaunchKernelGGL((k_conv_mfma<1, false>), g, dim3(256), 0, st, X, Wt, Y, nrows, e);
+    else hipLaunchKernelGGL((k_conv_mfma<0, false>), g, dim3(256), 0, st, X, Wt, Y, nrows, e);
+    return hipGetLastError();
+}
+
+hipError_t launch_weights_bf16(const float *W, uint16_t *Wt, int cin, int cout, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_weights_bf16, g256(81 * 32 * 32), dim3(256), 0, st, W, Wt, cin, cout);
+    return hipGetLastError();
+}
+
+hipError_t launch_half_rows_bf16(const void *half, uint16_t *rows, dd_prec sp, const HalfRows &hr, hipStream_t st)
+{
+    const dim3 g = g256((int64_t)hr.npairs * hr.S);
+    if (sp == DD_F64) hipLaunchKernelGGL(k_half_to_rows_bf16<double>, g, dim3(256), 0, st, (const double *)half, rows, hr);
+    else hipLaunchKernelGGL(k_half_to_rows_bf16<float>, g, dim3(256), 0, st, (const float *)half, rows, hr);
+    return hipGetLastError();
+}
+
+hipError_t launch_rows_f32_to_bf16(const float *X, uint16_t *Xb, int64_t nrows, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_rows_f32_to_bf16, g256(nrows * 32), dim3(256), 0, st, X, Xb, nrows);
     return hipGetLastError();
 }
 

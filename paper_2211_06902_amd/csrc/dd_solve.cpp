@@ -181,7 +181,8 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
     if (prm.method != DD_BICGSTAB && prm.method != DD_GMRES) return fail(ctx, DD_EINVAL, "unknown method");
     const bool gmres = prm.method == DD_GMRES;
     if (gmres && (prm.restart < 1 || prm.restart > 16)) return fail(ctx, DD_EINVAL, "restart must be in 1..16");
-    const dd_nn *nn = prm.precond;
+    // the network keeps a lazily refreshed BF16 copy of its weights
+    dd_nn *nn = const_cast<dd_nn *>(prm.precond);
     if (nn && !gmres) return fail(ctx, DD_EINVAL, "a network preconditioner needs method DD_GMRES");
     if (nn && !nn_fits(nn, Bc)) return fail(ctx, DD_EINVAL, "every block must have the network's extent");
     const dd_prec ip = prm.inner_prec;

@@ -140,7 +140,8 @@ _sig("dd_nn_num_weights", _I64, [])
 _sig("dd_nn_create", _I32, [_P, _P, _I32, _P, _PP])
 _sig("dd_nn_free", _I32, [_P])
 _sig("dd_nn_get_weights", _I32, [_P, _P, _P])
-_sig("dd_nn_apply", _I32, [_P, _P, _P, _P, _I64])
+_sig("dd_nn_apply", _I32, [_P, _P, _I32, _P, _P, _I64])
+_sig("dd_nn_set_inference", _I32, [_P, _P, _I32])
 _sig("dd_nn_train_params_default", None, [ctypes.POINTER(NnTrainParams)])
 _sig("dd_nn_loss_grad", _I32, [_P, _P, _P, _P, _P, _I32, _P, _I32, _I32, _P, _P])
 _sig("dd_nn_train", _I32, [_P, _P, _P, _P, _P, _I32, _P, _P, _I32, ctypes.POINTER(NnTrainParams), _P, _P])
@@ -228,14 +229,19 @@ class Net:
         self._ctx._check(_lib.dd_nn_get_weights(self._ctx._h, self._h, w.ctypes.data_as(_P)))
         return w
 
-    def apply(self, x):
-        """x: GPU float32 [n, S, 24] rows -> N(x) of the same shape."""
+    def apply(self, x, prec="f32"):
+        """x: GPU float32 [n, S, 24] rows -> N(x) of the same shape (prec "f32" or "bf16")."""
         import torch
 
         y = torch.empty_like(x)
         n = x.numel() // (self.sites * 24)
-        self._ctx._check(_lib.dd_nn_apply(self._ctx._h, self._h, _dev(x, "torch.float32"), _dev(y, "torch.float32"), n))
+        self._ctx._check(_lib.dd_nn_apply(self._ctx._h, self._h, _PREC[prec], _dev(x, "torch.float32"),
+                                          _dev(y, "torch.float32"), n))
         return y
+
+    def set_inference(self, prec):
+        """Precision of the network inside solves: "bf16" (default) or "f32"."""
+        self._ctx._check(_lib.dd_nn_set_inference(self._ctx._h, self._h, _PREC[prec]))
 
     def loss_grad(self, blocks, src, sol, n_rhs, pairs, mask_even=1):
         pr = _i32(pairs)

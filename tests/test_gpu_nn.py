@@ -62,6 +62,39 @@ def test_forward_matches_oracle(ctx, extent, k):
     net.close()
 
 
+def _bf16_forward(X, Ws, act):
+    """The network with BF16 weights, input and hidden activations (FP64 sums)."""
+    from oracle import precision
+
+    r = precision.round_bf16
+    h = r(X)
+    for l, W in enumerate(Ws):
+        z = convnet.conv(h, r(W))
+        if l < 2:
+            h = r(np.maximum(z, 0.0) if act == "relu" else z)
+    return z
+
+
+@pytest.mark.parametrize("k", [0, 1])
+def test_bf16_matrix_core_forward_matches_rounded_oracle(ctx, k):
+    code, act = _acts()[k]
+    extent = (4, 4, 4, 4)
+    w = synth.convnet_weights(23, scale=1.0, identity=(code == 0))
+    net = ctx.nn_create(extent, w, act=code)
+    S = 256
+    rng = np.random.default_rng(24)
+    X = rng.standard_normal((5, S, 24)).astype(np.float32)
+    Y = net.apply(_dev(X), prec="bf16").cpu().numpy()
+    Ws = _layers(w)
+    for i in range(5):
+        xi = X[i].astype(np.float64).reshape(extent + (24,))
+        ref = _bf16_forward(xi, Ws, act).reshape(S, 24)
+        exact = convnet.forward(xi, Ws, act)[0].reshape(S, 24)
+        assert np.linalg.norm(Y[i] - ref) <= 2e-3 * np.linalg.norm(ref)
+        assert np.linalg.norm(Y[i] - exact) <= 3e-2 * np.linalg.norm(exact)
+    net.close()
+
+
 def _toy_pairs(ctx, n_rhs, seed):
     """8^4 lattice in 16 blocks of 4^4; random sources and targets in the solver layout."""
     L = (8, 8, 8, 8)
