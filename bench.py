@@ -109,6 +109,253 @@ def cpu_baseline(w, U, b, boxes):
                       "defect correction to 1e-10 (%.1f s wall, %d failed)" % (npairs, dt, fails)}
 
 
+def run_c4(args):
+    """The learned preconditioner: train the network on ~20k (source, D^{-1} source) pairs of the
+    32^4 lattice's 8^4 blocks (sources on even sites, made by the block solver), then solve fresh
+    sources on a held-out gauge field with FGMRES(16) + network against plain GMRES(16)."""
+    import torch
+
+    import synth
+    from paper_2211_06902_amd import dd
+
+    L, kappa, eps = (32, 32, 32, 32), 0.1355, 0.3
+    V = 32**4
+    n_tr, n_va = 70, 8  # rhs per block: 70 x 256 = 17 920 training and 2048 validation pairs
+    ctx = dd.Context(0)
+    blk = ctx.make_blocks(L, -1, [[8] * 4] * 4)
+    t0 = time.perf_counter()
+    g = ctx.load_gauge(blk, torch.from_numpy(synth.gauge_field(L, eps, 2101)).cuda(), "f32")
+    odd = torch.from_numpy(np.indices((8, 8, 8, 8)).sum(axis=0).reshape(-1) % 2 == 1).cuda()
+    src = synth.spinor_field_device(n_tr + n_va, V, 4100)
+    src.view(n_tr + n_va, 256, 4096, 4, 3)[:, :, odd] = 0
+    sol = torch.empty_like(src)
+    p_gen = dd.solve_params(inner_prec="f32")
+    for c in range(0, n_tr + n_va, 12):
+        _, _, st = ctx.block_solve(blk, g, kappa, src[c:c + 12], sol[c:c + 12], params=p_gen)
+        if st != dd.DD_OK:
+            raise SystemExit("training-pair solve did not converge")
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t0
+    g.close()
+
+    print("c4: %d training + %d validation pairs solved in %.1f s" % (n_tr * 256, n_va * 256, t_pairs),
+          file=sys.stderr, flush=True)
+    net = ctx.nn_create((8, 8, 8, 8), synth.convnet_weights(4100))
+    t0 = time.perf_counter()
+    tl, vl = [], []
+    for ep in range(args.epochs):  # one epoch per call (shuffle stream seed 4100 + epoch)
+        tp = dd.nn_train_params(epochs=1, batch=32, lr=1e-3, seed=4100 + ep)
+        a, v = net.train(blk, src[:n_tr], sol[:n_tr], n_tr, src[n_tr:], sol[n_tr:], n_va, params=tp)
+        tl.append(float(a[0]))
+        vl.append(float(v[0]))
+        print("c4: epoch %d train loss %.5f val loss %.5f (%.1f s)" % (ep, a[0], v[0], time.perf_counter() - t0),
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del src, sol
+    torch.cuda.empty_cache()
+
+    # held-out gauge field, fresh sources
+    g2 = ctx.load_gauge(blk, torch.from_numpy(synth.gauge_field(L, eps, 4201)).cuda(), "f32")
+    b = synth.spinor_field_device(12, V, 4202)
+    x = torch.empty_like(b)
+    runs = {
+        "gmres16": dd.solve_params(method=dd.GMRES, restart=16, inner_prec="f32"),
+        "fgmres16_nn_every_cycle": dd.solve_params(method=dd.GMRES, restart=16, inner_prec="f32", precond=net,
+                                                   precond_cycles=1),
+        "fgmres16_nn_once": dd.solve_params(method=dd.GMRES, restart=16, inner_prec="f32", precond=net,
+                                            precond_cycles=0),
+        "bicgstab": dd.solve_params(inner_prec="f32"),
+        "bicgstab_nn": dd.solve_params(inner_prec="f32", precond=net),
+    }
+    res = {}
+    nn_time = None
+    for name, prm in runs.items():
+        ctx.block_solve(blk, g2, kappa, b, x, params=prm)  # warm-up
+        ctx.timer_enable(True)
+        ctx.timer_reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ok, steps = True, []
+        for _ in range(args.steps):
+            _, info, st = ctx.block_solve(blk, g2, kappa, b, x, params=prm)
+            ok = ok and st == dd.DD_OK and bool(np.all(info["true_relres"] <= TOL))
+            steps.append(float(info["iters"].mean()))
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        if name == "bicgstab_nn":
+            nn_time = ctx.timer_read(dd.KCLASS_NN_BF16)
+        ctx.timer_enable(False)
+        res[name] = {"solves_per_s": 3072 / dt if ok else 0.0, "ms_per_step": dt * 1e3, "all_converged": ok,
+                     "mean_inner_steps_per_pair": steps[-1]}
+        print("c4: %s %s" % (name, res[name]), file=sys.stderr, flush=True)
+    nn_ms, nn_n, nn_flops = nn_time
+    achieved = nn_flops / (nn_ms * 1e-3) / 1e12 if nn_ms > 0 else 0.0
+    best = res["bicgstab_nn"]
+    out = {
+        "metric": METRIC,
+        "value": best["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": 1,
+        "ms_per_step": best["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "learned preconditioner: 24-32-32-24 3^4 conv net (FP32 training, BF16 matrix-core "
+                        "inference) trained on 17 920 (source, D^{-1} source) pairs of the 32^4 lattice's 8^4 blocks "
+                        "(links exp(0.3 i H) seed 2101, kappa 0.1355, sources on even sites), validated on 2048; "
+                        "tested on a held-out gauge field (seed 4201), 12 fresh sources per block, FP32 inner "
+                        "BiCGStab right-preconditioned by the network (value) against plain BiCGStab, and FGMRES(16) "
+                        "+ network against plain GMRES(16), FP64 defect correction to 1e-10",
+            "pairs_generation_s": t_pairs,
+            "training_s": t_train,
+            "epochs": args.epochs,
+            "train_loss": [round(v, 5) for v in tl],
+            "val_loss": [round(v, 5) for v in vl],
+            "solvers": res,
+        },
+        "roofline": {
+            "kernel": "k_conv_mfma (network application: 3 BF16 matrix-core launches, 414 720 flop per site)",
+            "bound": "mfma",
+            "achieved": achieved,
+            "peak": 2500.0,
+            "unit": "TFLOP/s",
+            "frac": achieved / 2500.0,
+            "traffic": None,
+            "launches": nn_n,
+            "avg_launch_us": nn_ms * 1e3 / max(nn_n, 1),
+        },
+    }
+    print(json.dumps(out), flush=True)
+    net.close()
+    g2.close()
+    blk.close()
+    ctx.close()
+
+
+def run_c5(args):
+    """The multi-boson action on the 64^4 lattice: 4096 blocks of 8^4 (Omega, inner Lambda_0 of
+    6^4), 12 boson fields (N = 24, c = 0.5), one D_Omega^{-1} xi_k solve per field and block,
+    evaluated with plain FP64 solves, mixed-precision (FP32 inner) solves, and mixed-precision
+    solves right-preconditioned by a network trained on this lattice's blocks."""
+    import torch
+
+    import synth
+    from paper_2211_06902_amd import dd
+
+    L, kappa, eps, nf = (64, 64, 64, 64), 0.1365, 0.2, 12
+    V = 64**4
+    say = lambda m: print("c5: " + m, file=sys.stderr, flush=True)  # noqa: E731
+    t0 = time.perf_counter()
+    ctx = dd.Context(0)
+    blk = ctx.make_blocks(L, -1, [[8] * 8] * 4, inner_d=1)
+    U = torch.from_numpy(synth.gauge_field(L, eps, 5101)).cuda()
+    g = ctx.load_gauge(blk, U, "f32")
+    del U
+    torch.cuda.empty_cache()
+    chi = synth.spinor_field_device(nf, blk.total_bnd_sites, 5102)
+    xi = synth.spinor_field_device(nf, V, 5103)
+    u = dd.mb_roots(2 * nf, 0.5)
+    say("inputs ready (%.1f s)" % (time.perf_counter() - t0))
+
+    # network for this lattice: (even source, solution) pairs of its blocks, FP32 training
+    t0 = time.perf_counter()
+    n_tr = 4
+    odd = torch.from_numpy(np.indices((8, 8, 8, 8)).sum(axis=0).reshape(-1) % 2 == 1).cuda()
+    src = synth.spinor_field_device(n_tr, V, 5104)
+    src.view(n_tr, 4096, 4096, 4, 3)[:, :, odd] = 0
+    sol = torch.empty_like(src)
+    _, _, st = ctx.block_solve(blk, g, kappa, src, sol, params=dd.solve_params(inner_prec="f32"))
+    if st != dd.DD_OK:
+        raise SystemExit("training-pair solve did not converge")
+    net = ctx.nn_create((8, 8, 8, 8), synth.convnet_weights(5104))
+    tl = []
+    for ep in range(args.epochs):
+        a, _ = net.train(blk, src, sol, n_tr, params=dd.nn_train_params(epochs=1, batch=32, lr=1e-3, seed=5104 + ep))
+        tl.append(float(a[0]))
+        say("epoch %d train loss %.5f" % (ep, a[0]))
+    del src, sol
+    torch.cuda.empty_cache()
+    t_train = time.perf_counter() - t0
+
+    runs = {
+        "fp64": dd.solve_params(inner_prec="f64"),
+        "fp32": dd.solve_params(inner_prec="f32"),
+        "fp32_nn": dd.solve_params(inner_prec="f32", precond=net),
+    }
+    res = {}
+    hop = None
+    for name, prm in runs.items():
+        ctx.multiboson_action(blk, g, kappa, u, chi, xi, params=prm)  # warm-up (workspaces)
+        ctx.timer_enable(True)
+        ctx.timer_reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S, tot, info, st = ctx.multiboson_action(blk, g, kappa, u, chi, xi, params=prm)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if name == "fp32":
+            hop = ctx.timer_read(dd.KCLASS_HOP_F32)
+        ctx.timer_enable(False)
+        ok = st == dd.DD_OK and bool(np.all(info["true_relres"] <= TOL))
+        res[name] = {"solves_per_s": blk.n_blocks * nf / dt if ok else 0.0, "seconds": dt, "all_converged": ok,
+                     "S_total": tot, "mean_inner_iterations_per_pair": float(info["iters"].mean())}
+        say("%s %s" % (name, res[name]))
+    ref = res["fp64"]["S_total"]
+    for r in res.values():
+        r["S_rel_diff_vs_fp64"] = abs(r["S_total"] - ref) / abs(ref)
+    hop_ms, hop_n, hop_bytes = hop
+    achieved = hop_bytes / (hop_ms * 1e-3) / 1e9 if hop_ms > 0 else 0.0
+    best = res["fp32_nn"]
+    out = {
+        "metric": METRIC,
+        "value": best["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": best["seconds"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "multi-boson local action on a 64^4 lattice (links exp(0.2 i H) seed 5101, kappa 0.1365): "
+                        "4096 blocks Omega of 8^4 with inner Lambda_0 of 6^4 (1040 boundary sites), 12 fields "
+                        "(N = 24, c = 0.5), chi on dLambda_0 and xi on Omega Gaussian (seeds 5102, 5103); 49 152 "
+                        "block solves to FP64 true relative residual 1e-10 per evaluation; value: FP32 inner "
+                        "BiCGStab right-preconditioned by a network trained on this lattice (BF16 inference)",
+            "training_s": t_train,
+            "train_loss": [round(v, 5) for v in tl],
+            "solvers": res,
+            "speedup_fp32_nn_over_fp64": best["solves_per_s"] / max(res["fp64"]["solves_per_s"], 1e-30),
+            "speedup_fp32_over_fp64": res["fp32"]["solves_per_s"] / max(res["fp64"]["solves_per_s"], 1e-30),
+        },
+        "roofline": {
+            "kernel": "k_hop (FP32, fields of one solve group) in the FP32 evaluation",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "launches": hop_n,
+            "avg_launch_us": hop_ms * 1e3 / max(hop_n, 1),
+        },
+    }
+    print(json.dumps(out), flush=True)
+    net.close()
+    g.close()
+    blk.close()
+    ctx.close()
+
+
 PROFILE = os.path.join(ROOT, "profiles", "k_hop_f32_c2_32x4_12rhs.md")
 
 
@@ -135,7 +382,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--inner", default=None, choices=["f32", "bf16", "f64"],
                     help="inner precision (default: FP32 for c2, BF16 links for c3)")
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["c4", "c5"])
+    ap.add_argument("--epochs", type=int, default=4, help="c4: training epochs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (4 times), to calibrate HBM byte counters")
     args = ap.parse_args()
@@ -153,6 +401,13 @@ def main():
         print("bench.py measures one GPU only: the block solves need no communication and this build has no "
               "multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "c4":
+        run_c4(args)
+        return
+    if args.workload == "c5":
+        run_c5(args)
+        return
 
     import torch
 

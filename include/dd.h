@@ -178,9 +178,11 @@ typedef struct {
     int32_t check_every; /* BiCGStab: inner iterations between convergence polls (<= 0: default 8) */
     int32_t use_graph;   /* replay inner iterations (BiCGStab) or the persistent inner launch
                             (GMRES) from a captured hipGraph */
-    const dd_nn *precond; /* GMRES only (NULL: none): flexible GMRES whose first direction of
-                             a restart cycle is z = N(r) for the cycle's starting residual r;
-                             needs every block to have the network's extent */
+    const dd_nn *precond; /* network preconditioner (NULL: none); every block must have the
+                             network's extent.  DD_GMRES: flexible GMRES whose first direction
+                             of a restart cycle is z = N(r) for the cycle's starting residual r.
+                             DD_BICGSTAB: right preconditioning, Dhat N u = f with x = N u
+                             (needs a DD_NN_LINEAR network) */
     int32_t precond_cycles; /* with precond: restart cycles between network applications
                                (<= 0: the network is applied once per inner solve) */
 } dd_solve_params;
@@ -211,6 +213,13 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *blocks, const dd_gauge *g
 
 /* ------------------------------------------------- multi-boson action */
 
+/* The field parameters of Section 4: u_k = 1 - z_k for the N/2 zeros z_k of
+ * the Chebyshev remainder R_{N+1} taken one per complex-conjugate pair
+ * (k = 1 .. N/2), u_k = cos(2 pi k / (N + 1)) + i sqrt(1 - c^2) sin(2 pi k / (N + 1)).
+ * u_host: [N/2][2] (re, im).  DD_EINVAL unless N is even and 0 < c < 1.
+ * Host only. */
+dd_status dd_mb_roots(int32_t N, double c, double *u_host);
+
 /* Block-local multi-boson action of eq. (localMB), Section 4, for
  * field k taken at z = u_k:
  *   S^a = sum_k sum_{x in dLambda_0^a} | u_k chi_k(x) + (D_{Omega_0^a}^{-1} xi_k^a)(x) |^2
@@ -219,7 +228,8 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *blocks, const dd_gauge *g
  * [n_fields][total_bnd_sites][4][3] complex128; xi_dev:
  * [n_fields][total_sites][4][3] complex128.  S_block_dev (may be NULL):
  * [n_blocks] FP64 device output; S_total_host (may be NULL): sum over blocks.
- * The solves use params (NULL: defaults); stats may be NULL. */
+ * The solves use params (NULL: defaults); stats may be NULL.  The fields are
+ * solved in groups (see DD_TUNE_MB_FIELDS) whose sums are added in order. */
 dd_status dd_multiboson_action(dd_ctx *ctx, const dd_blocks *blocks, const dd_gauge *gauge,
                                double kappa, int32_t n_fields, const double *u_host,
                                const void *chi_dev, const void *xi_dev,
@@ -243,13 +253,16 @@ dd_status dd_multiboson_action(dd_ctx *ctx, const dd_blocks *blocks, const dd_ga
  *                        fits.  Results depend on the threads per workgroup
  *                        only through the fixed summation order of the
  *                        workgroup's dot products. */
+/* DD_TUNE_MB_FIELDS: fields dd_multiboson_action hands to one block solve
+ * (0 = as many as fit in 60 % of the free device memory). */
 enum {
     DD_TUNE_RHS_GROUP_F64 = 0,
     DD_TUNE_RHS_GROUP_F32 = 1,
     DD_TUNE_HOP_LDS = 2,
     DD_TUNE_GMRES_THREADS = 3,
     DD_TUNE_GMRES_QUEUES = 4,
-    DD_TUNE_GMRES_WG_PER_CU = 5
+    DD_TUNE_GMRES_WG_PER_CU = 5,
+    DD_TUNE_MB_FIELDS = 6
 };
 dd_status dd_tune_set(dd_ctx *ctx, int32_t what, int32_t value);
 
@@ -337,13 +350,17 @@ dd_status dd_nn_train(dd_ctx *ctx, dd_nn *nn, const dd_blocks *blocks, const voi
  * accumulated.  The hop classes are the stencil kernel in each precision
  * (FP64; FP32; FP32 spinors with BF16 links).  Graph replay is disabled
  * while timing is on. */
-/* DD_KCLASS_GMRES is the persistent GMRES launch (time only, no byte count). */
+/* DD_KCLASS_GMRES is the persistent GMRES launch (its algorithmic bytes are
+ * counted per pair by the kernel).  DD_KCLASS_NN_BF16 is one BF16 application
+ * of the network (three matrix-core launches) inside solves; its "bytes" field
+ * counts the network's flops instead (414 720 per block site). */
 enum {
     DD_KCLASS_HOP_F64 = 0,
     DD_KCLASS_HOP_F32 = 1,
     DD_KCLASS_HOP_BF16 = 2,
     DD_KCLASS_GMRES = 3,
-    DD_KCLASS_COUNT = 4
+    DD_KCLASS_NN_BF16 = 4,
+    DD_KCLASS_COUNT = 5
 };
 dd_status dd_timer_enable(dd_ctx *ctx, int32_t on);
 dd_status dd_timer_reset(dd_ctx *ctx);

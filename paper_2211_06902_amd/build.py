@@ -30,7 +30,9 @@ DEVICE = ["-x", "hip", "--offload-arch=" + ARCH, "-Xclang", "-target-feature", "
 
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + COMMON + (DEVICE if src.endswith(".hip") else ["-D__HIP_PLATFORM_AMD__"]) + ["-c", src, "-o", obj]
+    # host sources hold no kernels; hipcc still compiles them as HIP, so name the target there too
+    host = ["-D__HIP_PLATFORM_AMD__", "--offload-arch=" + ARCH, "-Wno-unused-result"]
+    cmd = [HIPCC] + COMMON + (DEVICE if src.endswith(".hip") else host) + ["-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s\n%s" % (" ".join(cmd), r.stdout, r.stderr))

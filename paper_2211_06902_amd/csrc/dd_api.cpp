@@ -541,6 +541,11 @@ dd_status dd_tune_set(dd_ctx *ctx, int32_t what, int32_t value)
         ctx->gm_queues = value;
         return DD_OK;
     }
+    if (what == DD_TUNE_MB_FIELDS) {
+        if (value < 0 || value > kMaxRhs) return fail(ctx, DD_EINVAL, "fields per solve must be in 0..64");
+        ctx->mb_fields = value;
+        return DD_OK;
+    }
     if (what == DD_TUNE_GMRES_WG_PER_CU) {
         if (value < 0 || value > 64) return fail(ctx, DD_EINVAL, "GMRES workgroups per CU must be in 0..64");
         ctx->gm_wg_per_cu = value;

@@ -49,6 +49,7 @@ struct dd_ctx {
     int gm_threads = 0;         // persistent GMRES: threads per workgroup (0 = default)
     int gm_queues = 0;          // persistent GMRES: work queues, 1 or 8 (0 = default)
     int gm_wg_per_cu = 0;       // persistent GMRES: resident workgroups per CU (0 = all that fit)
+    int mb_fields = 0;          // multi-boson action: fields per block solve (0 = as many as fit)
 };
 
 namespace dd {
@@ -151,7 +152,7 @@ struct BlkArgs {
     const int32_t *chunk;  // sites per chunk of each block
 };
 
-enum DotMode { kDotNone = 0, kDotAuxOut = 1, kDotOutSelfOutOut = 2, kDotOutOut = 3 };
+enum DotMode { kDotNone = 0, kDotAuxOut = 1, kDotOutSelfOutOut = 2, kDotOutOut = 3, kDotOutAuxOutOut = 4 };
 
 // out = c_add*add + c_self*self + c_hop * (H in), on the sites of `parity`.
 // in lives on the other parity.  Optional fused dot products per (tile, rhs).
@@ -290,7 +291,7 @@ hipError_t launch_bicg_init(const BlkArgs &ba, dd_prec sp, const void *rhs, void
                             hipStream_t s);
 hipError_t launch_bicg_s(const BlkArgs &ba, dd_prec sp, const void *r, const void *v, void *s,
                          const PairState &ps, hipStream_t st);
-hipError_t launch_bicg_xr(const BlkArgs &ba, dd_prec sp, void *x, const void *p, const void *s,
+hipError_t launch_bicg_xr(const BlkArgs &ba, dd_prec sp, void *x, const void *p, const void *sx, const void *s,
                           const void *t, void *r, const void *rh, double *partial,
                           const PairState &ps, hipStream_t st);
 hipError_t launch_bicg_p(const BlkArgs &ba, dd_prec sp, const void *r, const void *v, void *p,
@@ -306,6 +307,6 @@ hipError_t launch_sc_beta(const BlkArgs &ba, const double *partial, const PairSt
 hipError_t launch_sc_outer(const BlkArgs &ba, const double *pe, const double *po, int first,
                            double tol, const OuterState &os, hipStream_t s);
 hipError_t launch_mb_norm(const dd_blocks *B, int n_fields, const double *u, const double *chi,
-                          const double *y, double *S, hipStream_t s);
+                          const double *y, double *S, int accumulate, hipStream_t s);
 
 }  // namespace dd

@@ -175,14 +175,16 @@ __global__ void __launch_bounds__(kTile) k_hop(BlkArgs ba, HopArgs ha)
                     const SP ov = (SP)v;
                     bstore<SP>(out_b, ov, my, so);
                     o[ri] = (double)ov;
-                    if (ha.dot_mode == kDotAuxOut) av[ri] = (double)bload<SP>(aux_b, my, so);
+                    if (ha.dot_mode == kDotAuxOut || ha.dot_mode == kDotOutAuxOutOut)
+                        av[ri] = (double)bload<SP>(aux_b, my, so);
                 }
                 if (ha.dot_mode == kDotAuxOut) {
                     dv[j][0] += av[0] * o[0] + av[1] * o[1];
                     dv[j][1] += av[0] * o[1] - av[1] * o[0];
-                } else if (ha.dot_mode == kDotOutSelfOutOut) {
-                    dv[j][0] += o[0] * sv[0] + o[1] * sv[1];
-                    dv[j][1] += o[0] * sv[1] - o[1] * sv[0];
+                } else if (ha.dot_mode == kDotOutSelfOutOut || ha.dot_mode == kDotOutAuxOutOut) {
+                    const double *q = ha.dot_mode == kDotOutAuxOutOut ? av : sv;
+                    dv[j][0] += o[0] * q[0] + o[1] * q[1];
+                    dv[j][1] += o[0] * q[1] - o[1] * q[0];
                     dv[j][2] += o[0] * o[0] + o[1] * o[1];
                 } else if (ha.dot_mode == kDotOutOut) {
                     dv[j][0] += o[0] * o[0] + o[1] * o[1];
@@ -191,7 +193,7 @@ __global__ void __launch_bounds__(kTile) k_hop(BlkArgs ba, HopArgs ha)
         }
     }
     if (ha.dot_mode != kDotNone) {
-        const int nred = ha.dot_mode == kDotAuxOut ? 2 : (ha.dot_mode == kDotOutSelfOutOut ? 3 : 1);
+        const int nred = ha.dot_mode == kDotAuxOut ? 2 : (ha.dot_mode == kDotOutSelfOutOut || ha.dot_mode == kDotOutAuxOutOut ? 3 : 1);
         tile_sum<G>(red, dv, nred, ha.partial, t.tile);
     }
 }
@@ -507,9 +509,11 @@ __global__ void __launch_bounds__(kTile) k_bicg_s(BlkArgs ba, const SP *r, const
 
 // x += alpha p + omega s;  r = s - omega t;  <rh, r>, |r|^2 per (tile, rhs)
 template <typename SP, int G>
-__global__ void __launch_bounds__(kTile) k_bicg_xr(BlkArgs ba, SP *x, const SP *p, const SP *s, const SP *tv, SP *r,
-                                                   const SP *rh, double *partial, PairState ps)
+__global__ void __launch_bounds__(kTile) k_bicg_xr(BlkArgs ba, SP *x, const SP *p, const SP *sx, const SP *s,
+                                                   const SP *tv, SP *r, const SP *rh, double *partial, PairState ps)
 {
+    // x += alpha p + omega sx (sx = s, or M s with a right preconditioner M); r = s - omega t
+    const bool own_sx = sx != s;
     __shared__ double red[G][kTile];
     const Tile t = tile_of(ba);
     double dv[G][kNRed] = {};
@@ -526,8 +530,9 @@ __global__ void __launch_bounds__(kTile) k_bicg_xr(BlkArgs ba, SP *x, const SP *
             for (int k = 0; k < 12; k++) {
                 const int64_t i0 = t.base + eoff(t, j, 2 * k), i1 = i0 + t.hb;
                 const SP pr = p[i0], pi = p[i1], sr = s[i0], si = s[i1], tr = tv[i0], ti = tv[i1];
-                x[i0] = x[i0] + (a_r * pr - a_i * pi) + (w_r * sr - w_i * si);
-                x[i1] = x[i1] + (a_r * pi + a_i * pr) + (w_r * si + w_i * sr);
+                const SP xr = own_sx ? sx[i0] : sr, xi = own_sx ? sx[i1] : si;
+                x[i0] = x[i0] + (a_r * pr - a_i * pi) + (w_r * xr - w_i * xi);
+                x[i1] = x[i1] + (a_r * pi + a_i * pr) + (w_r * xi + w_i * xr);
                 const SP nr_ = sr - (w_r * tr - w_i * ti);
                 const SP ni_ = si - (w_r * ti + w_i * tr);
                 r[i0] = nr_;
@@ -587,11 +592,11 @@ static void launch_s_t(const BlkArgs &ba, const void *r, const void *v, void *s,
                        (SP *)s, ps);
 }
 template <typename SP, int G>
-static void launch_xr_t(const BlkArgs &ba, void *x, const void *p, const void *s, const void *t, void *r,
-                        const void *rh, double *partial, const PairState &ps, hipStream_t st)
+static void launch_xr_t(const BlkArgs &ba, void *x, const void *p, const void *sx, const void *s, const void *t,
+                        void *r, const void *rh, double *partial, const PairState &ps, hipStream_t st)
 {
     hipLaunchKernelGGL((k_bicg_xr<SP, G>), dim3(ba.ntiles), dim3(kTile), 0, st, ba, (SP *)x, (const SP *)p,
-                       (const SP *)s, (const SP *)t, (SP *)r, (const SP *)rh, partial, ps);
+                       (const SP *)sx, (const SP *)s, (const SP *)t, (SP *)r, (const SP *)rh, partial, ps);
 }
 template <typename SP, int G>
 static void launch_p_t(const BlkArgs &ba, const void *r, const void *v, void *p, const PairState &ps, hipStream_t st)
@@ -632,10 +637,10 @@ hipError_t launch_bicg_s(const BlkArgs &ba, dd_prec sp, const void *r, const voi
     DD_DISPATCH(launch_s_t, sp, ba, r, v, s, ps, st);
 }
 
-hipError_t launch_bicg_xr(const BlkArgs &ba, dd_prec sp, void *x, const void *p, const void *s, const void *tv,
-                          void *r, const void *rh, double *partial, const PairState &ps, hipStream_t st)
+hipError_t launch_bicg_xr(const BlkArgs &ba, dd_prec sp, void *x, const void *p, const void *sx, const void *s,
+                          const void *tv, void *r, const void *rh, double *partial, const PairState &ps, hipStream_t st)
 {
-    DD_DISPATCH(launch_xr_t, sp, ba, x, p, s, tv, r, rh, partial, ps, st);
+    DD_DISPATCH(launch_xr_t, sp, ba, x, p, sx, s, tv, r, rh, partial, ps, st);
 }
 
 hipError_t launch_bicg_p(const BlkArgs &ba, dd_prec sp, const void *r, const void *v, void *p, const PairState &ps,
@@ -845,7 +850,8 @@ hipError_t launch_sc_outer(const BlkArgs &ba, const double *pe, const double *po
 // y: solutions in the boundary layout [k][q][24]; chi: [k][q_bnd][24].
 __global__ void __launch_bounds__(256) k_mb_norm(int nb, int nf, const double *u, const double *chi,
                                                  const double *y, const int64_t *soff, const int64_t *boff,
-                                                 const int32_t *bnd, int64_t total, int64_t total_bnd, double *S)
+                                                 const int32_t *bnd, int64_t total, int64_t total_bnd, double *S,
+                                                 int accumulate)
 {
     __shared__ double red[256];
     const int b = blockIdx.x;
@@ -870,15 +876,15 @@ __global__ void __launch_bounds__(256) k_mb_norm(int nb, int nf, const double *u
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) S[b] = red[0];
+    if (threadIdx.x == 0) S[b] = (accumulate ? S[b] : 0.0) + red[0];
 }
 
 hipError_t launch_mb_norm(const dd_blocks *B, int n_fields, const double *u, const double *chi, const double *y,
-                          double *S, hipStream_t s)
+                          double *S, int accumulate, hipStream_t s)
 {
     if (B->nb == 0) return hipSuccess;
     hipLaunchKernelGGL(k_mb_norm, dim3(B->nb), dim3(256), 0, s, B->nb, n_fields, u, chi, y, B->d_soff, B->d_boff,
-                       B->d_bnd, (int64_t)B->soff[B->nb], (int64_t)B->boff[B->nb], S);
+                       B->d_bnd, (int64_t)B->soff[B->nb], (int64_t)B->boff[B->nb], S, accumulate);
     return hipGetLastError();
 }
 

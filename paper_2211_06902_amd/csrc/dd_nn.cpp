@@ -74,7 +74,7 @@ hipError_t nn_apply_half(dd_ctx *ctx, dd_nn *nn, const dd_blocks *B, const void 
 {
     const int S = nn->e.S;
     const int np = n_rhs * B->nb;
-    const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(np, (int64_t(1) << 28) / ((int64_t)S * 32 * 4)));
+    const int chunk = (int)std::max<int64_t>(1, std::min<int64_t>(np, (int64_t(1) << 30) / ((int64_t)S * 32 * 4)));
     hipError_t e = hipSuccess;
     const size_t rows = (size_t)chunk * S;
     const bool bf = nn->infer_prec == DD_BF16;
@@ -91,6 +91,7 @@ hipError_t nn_apply_half(dd_ctx *ctx, dd_nn *nn, const dd_blocks *B, const void 
         const int64_t nrows = (int64_t)hr.npairs * S;
         if (bf) {
             e = launch_half_rows_bf16(v, (uint16_t *)X, sp, hr, ctx->stream);
+            TimedLaunch tl(ctx, DD_KCLASS_NN_BF16, 2.0 * 81 * (24 * 32 + 32 * 32 + 32 * 24) * (double)nrows);
             if (e == hipSuccess) e = nn_forward_bf16(ctx, nn, (uint16_t *)X, (uint16_t *)Z1, (uint16_t *)Z2, O, nrows);
         } else {
             e = launch_half_rows(v, (float *)X, nullptr, sp, hr, 0, ctx->stream);

@@ -49,20 +49,29 @@ struct Inner {
     const void *links;
     dd_prec ip, sp;
     double kappa, tol;
+    dd_nn *nn;     // right preconditioner M (linear network) or null
+    void *ph, *sh;  // M p, M s
+    int n_rhs;
 };
 
-// one BiCGStab iteration on all pairs (10 launches)
+// one BiCGStab iteration on all pairs (10 launches; with a right
+// preconditioner M, Dhat is applied to M p and M s, x is updated with them)
 hipError_t bicg_iteration(const Inner &in)
 {
     Ws &w = *in.w;
     const double k2 = in.kappa * in.kappa;
     hipError_t e;
     hipStream_t st = in.ctx->stream;
+    const void *pp = w.p, *ss = w.s;
+    if (in.nn) {
+        if ((e = nn_apply_half(in.ctx, in.nn, in.B, w.p, in.ph, in.n_rhs, in.sp)) != hipSuccess) return e;
+        pp = in.ph;
+    }
     // v = Dhat p
-    HopArgs h1 = hop_args(w.tmp, w.p, in.links, 1, 1.0);
+    HopArgs h1 = hop_args(w.tmp, pp, in.links, 1, 1.0);
     if ((e = run_hop(in.ctx, in.B, in.ba, h1, in.ip)) != hipSuccess) return e;
     HopArgs h2 = hop_args(w.v, w.tmp, in.links, 0, -k2);
-    h2.self = w.p;
+    h2.self = pp;
     h2.c_self = 1.0;
     h2.aux = w.rh;
     h2.dot_mode = kDotAuxOut;
@@ -70,17 +79,22 @@ hipError_t bicg_iteration(const Inner &in)
     if ((e = run_hop(in.ctx, in.B, in.ba, h2, in.ip)) != hipSuccess) return e;
     if ((e = launch_sc_alpha(in.ba, w.pA, w.ps, st)) != hipSuccess) return e;
     if ((e = launch_bicg_s(in.ba, in.sp, w.r, w.v, w.s, w.ps, st)) != hipSuccess) return e;
-    // t = Dhat s
-    HopArgs h3 = hop_args(w.tmp, w.s, in.links, 1, 1.0);
+    if (in.nn) {
+        if ((e = nn_apply_half(in.ctx, in.nn, in.B, w.s, in.sh, in.n_rhs, in.sp)) != hipSuccess) return e;
+        ss = in.sh;
+    }
+    // t = Dhat s; omega = <t, s> / <t, t>
+    HopArgs h3 = hop_args(w.tmp, ss, in.links, 1, 1.0);
     if ((e = run_hop(in.ctx, in.B, in.ba, h3, in.ip)) != hipSuccess) return e;
     HopArgs h4 = hop_args(w.t, w.tmp, in.links, 0, -k2);
-    h4.self = w.s;
+    h4.self = ss;
     h4.c_self = 1.0;
-    h4.dot_mode = kDotOutSelfOutOut;
+    h4.dot_mode = in.nn ? kDotOutAuxOutOut : kDotOutSelfOutOut;
+    h4.aux = w.s;
     h4.partial = w.pB;
     if ((e = run_hop(in.ctx, in.B, in.ba, h4, in.ip)) != hipSuccess) return e;
     if ((e = launch_sc_omega(in.ba, w.pB, w.ps, st)) != hipSuccess) return e;
-    if ((e = launch_bicg_xr(in.ba, in.sp, w.xi, w.p, w.s, w.t, w.r, w.rh, w.pC, w.ps, st)) != hipSuccess) return e;
+    if ((e = launch_bicg_xr(in.ba, in.sp, w.xi, pp, ss, w.s, w.t, w.r, w.rh, w.pC, w.ps, st)) != hipSuccess) return e;
     if ((e = launch_sc_beta(in.ba, w.pC, w.ps, in.tol, st)) != hipSuccess) return e;
     return launch_bicg_p(in.ba, in.sp, w.r, w.v, w.p, w.ps, st);
 }
@@ -183,7 +197,8 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
     if (gmres && (prm.restart < 1 || prm.restart > 16)) return fail(ctx, DD_EINVAL, "restart must be in 1..16");
     // the network keeps a lazily refreshed BF16 copy of its weights
     dd_nn *nn = const_cast<dd_nn *>(prm.precond);
-    if (nn && !gmres) return fail(ctx, DD_EINVAL, "a network preconditioner needs method DD_GMRES");
+    if (nn && !gmres && nn->act != DD_NN_LINEAR)
+        return fail(ctx, DD_EINVAL, "BiCGStab needs a linear network preconditioner (use DD_GMRES for ReLU)");
     if (nn && !nn_fits(nn, Bc)) return fail(ctx, DD_EINVAL, "every block must have the network's extent");
     const dd_prec ip = prm.inner_prec;
     const void *links = links_for(G, ip);
@@ -193,7 +208,7 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
     const int max_outer = prm.max_outer > 0 ? prm.max_outer : 30;
     const int max_inner = prm.max_inner > 0 ? prm.max_inner : 2000;
     const int check = prm.check_every > 0 ? prm.check_every : 8;
-    const bool graph = prm.use_graph && !ctx->timing && !nn;
+    const bool graph = prm.use_graph && !ctx->timing && !(nn && gmres);
 
     dd_blocks *B = const_cast<dd_blocks *>(Bc);
     HIPCHECK(ctx, enter(ctx));
@@ -241,6 +256,7 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
     double *gm_bytes = nullptr, *gm_beta0 = nullptr;
     void *gm_r = nullptr, *gm_z0 = nullptr;
     int32_t *gm_more[2] = {nullptr, nullptr};
+    void *bc_ph = nullptr, *bc_sh = nullptr;
     const QueueTable *qt = nullptr;
     const int64_t vstr = 24 * (int64_t)B->max_h;
     if (gmres) {
@@ -265,6 +281,10 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
         w.v = get("s_v", hsp);
         w.s = get("s_s", hsp);
         w.t = get("s_t", hsp);
+        if (nn) {
+            bc_ph = get("s_ph", hsp);
+            bc_sh = get("s_sh", hsp);
+        }
     }
     w.pA = (double *)get("s_pA", npart);
     w.pB = (double *)get("s_pB", npart);
@@ -297,7 +317,7 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
     HIPCHECK(ctx, hipMemsetAsync(w.xo, 0, h64, st));
     HIPCHECK(ctx, launch_pack_spinor(B, (const double *)b_dev, w.be, w.bo, DD_F64, n_rhs, st));
 
-    Inner in{ctx, B, ba, &w, links, ip, sp, kappa, inner_tol};
+    Inner in{ctx, B, ba, &w, links, ip, sp, kappa, inner_tol, gmres ? nullptr : nn, bc_ph, bc_sh, n_rhs};
     std::vector<int32_t> h_act(np);
     hipGraph_t g = nullptr;
     hipGraphExec_t gx = nullptr;
@@ -410,6 +430,8 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
         } else {
         HIPCHECK(ctx, launch_bicg_init(ba, sp, w.rhs, w.r, w.rh, w.p, w.xi, w.pA, w.os.active, st));
         HIPCHECK(ctx, launch_sc_init(ba, w.pA, w.ps, w.os.active, st));
+        // the network's workspaces and BF16 weights exist before any capture
+        if (in.nn && !gx) HIPCHECK(ctx, nn_apply_half(ctx, in.nn, B, w.p, in.ph, n_rhs, sp));
         if (graph && !gx) {
             HIPCHECK(ctx, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
             hipError_t ce = hipSuccess;
@@ -565,18 +587,60 @@ dd_status dd_multiboson_action(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *
 {
     if (!ctx || !B || !G || !u_host || !chi_dev || !xi_dev) return fail(ctx, DD_EINVAL, "null argument");
     if (n_fields < 1 || n_fields > kMaxRhs) return fail(ctx, DD_EINVAL, "n_fields must be in 1..64");
+    HIPCHECK(ctx, enter(ctx));
+    dd_solve_params prm;
+    if (params) prm = *params;
+    else dd_solve_params_default(&prm);
+    // fields per block solve: the solver's workspace grows with the rhs of a call
+    // (FP64 half fields, inner-precision Krylov vectors and the solutions), so
+    // large lattices are solved a few fields at a time
+    const int64_t total = B->soff[B->nb];
+    int fc = ctx->mb_fields;
+    if (fc <= 0) {
+        size_t fr = 0, tot = 0;
+        HIPCHECK(ctx, hipMemGetInfo(&fr, &tot));
+        const double per_field = (double)total * (192.0 + 576.0 + 132.0 * prec_bytes(prm.inner_prec == DD_F64 ? DD_F64 : DD_F32));
+        fc = (int)std::max(1.0, std::floor(0.6 * (double)fr / per_field));
+    }
+    fc = std::min<int>(fc, n_fields);
     hipError_t e = hipSuccess;
-    const size_t ybytes = (size_t)B->soff[B->nb] * 24 * n_fields * sizeof(double);
-    double *y = (double *)workspace(ctx, "mb_y", ybytes, &e);
+    double *y = (double *)workspace(ctx, "mb_y", (size_t)total * 24 * fc * sizeof(double), &e);
     double *ud = y ? (double *)workspace(ctx, "mb_u", (size_t)n_fields * 2 * sizeof(double), &e) : nullptr;
     double *S = S_block_dev;
     if (ud && !S) S = (double *)workspace(ctx, "mb_S", (size_t)std::max(B->nb, 1) * sizeof(double), &e);
     if (!y || !ud || !S) return fail(ctx, DD_ENOMEM, std::string("workspace: ") + hipGetErrorString(e));
-    const dd_status st = dd_block_solve(ctx, B, G, kappa, xi_dev, y, n_fields, params, stats);
-    if (st != DD_OK && st != DD_ENOCONV) return st;
     HIPCHECK(ctx, hipMemcpyAsync(ud, u_host, (size_t)n_fields * 2 * sizeof(double), hipMemcpyHostToDevice,
                                  ctx->stream));
-    HIPCHECK(ctx, launch_mb_norm(B, n_fields, ud, (const double *)chi_dev, y, S, ctx->stream));
+    const int64_t tb = B->boff[B->nb];
+    dd_status st_all = DD_OK;
+    double seconds = 0;
+    int32_t cycles = 0;
+    int64_t inner = 0;
+    for (int f0 = 0; f0 < n_fields; f0 += fc) {
+        const int nf = std::min(fc, n_fields - f0);
+        dd_solve_stats cs;
+        std::memset(&cs, 0, sizeof(cs));
+        if (stats) {
+            const size_t o = (size_t)f0 * B->nb;
+            cs.iters = stats->iters ? stats->iters + o : nullptr;
+            cs.true_relres = stats->true_relres ? stats->true_relres + o : nullptr;
+            cs.flags = stats->flags ? stats->flags + o : nullptr;
+        }
+        const dd_status st = dd_block_solve(ctx, B, G, kappa, (const double *)xi_dev + (size_t)f0 * total * 24, y, nf,
+                                            &prm, &cs);
+        if (st != DD_OK && st != DD_ENOCONV) return st;
+        if (st == DD_ENOCONV) st_all = DD_ENOCONV;
+        seconds += cs.seconds;
+        cycles = std::max(cycles, cs.outer_cycles);
+        inner += cs.inner_iterations;
+        HIPCHECK(ctx, launch_mb_norm(B, nf, ud + 2 * f0, (const double *)chi_dev + (size_t)f0 * tb * 24, y, S,
+                                     f0 > 0, ctx->stream));
+    }
+    if (stats) {
+        stats->seconds = seconds;
+        stats->outer_cycles = cycles;
+        stats->inner_iterations = inner;
+    }
     if (S_total_host) {
         std::vector<double> hs(B->nb);
         HIPCHECK(ctx, hipMemcpyAsync(hs.data(), S, B->nb * sizeof(double), hipMemcpyDeviceToHost, ctx->stream));
@@ -586,7 +650,23 @@ dd_status dd_multiboson_action(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *
         *S_total_host = tot;
     }
     HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
-    return st;
+    if (st_all == DD_ENOCONV) ctx->err = "some (block, field) pairs missed the tolerance";
+    return st_all;
+}
+
+dd_status dd_mb_roots(int32_t N, double c, double *u_host)
+{
+    if (!u_host || N < 2 || (N & 1) || !(c > 0.0 && c < 1.0)) return DD_EINVAL;
+    // u_k = 1 - z_k, k = 1 .. N/2, for the zeros z_k of the remainder polynomial
+    // (one of each complex-conjugate pair): angle 2 pi k / (N + 1) on the ellipse
+    // with semi-axes 1 and sqrt(1 - c^2)
+    const double s = std::sqrt(1.0 - c * c);
+    for (int k = 1; k <= N / 2; k++) {
+        const double th = 2.0 * M_PI * k / (N + 1);
+        u_host[2 * (k - 1)] = std::cos(th);
+        u_host[2 * (k - 1) + 1] = s * std::sin(th);
+    }
+    return DD_OK;
 }
 
 }  // extern "C"

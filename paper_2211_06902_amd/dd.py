@@ -22,9 +22,9 @@ LIB_PATH = os.path.join(_HERE, "libdd.so")
 DD_OK, DD_EINVAL, DD_ENOMEM, DD_EDEVICE, DD_ENOCONV, DD_EUNSUPPORTED = range(6)
 F64, F32, BF16 = 0, 1, 2
 BICGSTAB, GMRES = 0, 1
-KCLASS_HOP_F64, KCLASS_HOP_F32, KCLASS_HOP_BF16, KCLASS_GMRES = 0, 1, 2, 3
+KCLASS_HOP_F64, KCLASS_HOP_F32, KCLASS_HOP_BF16, KCLASS_GMRES, KCLASS_NN_BF16 = 0, 1, 2, 3, 4
 TUNE_RHS_GROUP_F64, TUNE_RHS_GROUP_F32, TUNE_HOP_LDS = 0, 1, 2
-TUNE_GMRES_THREADS, TUNE_GMRES_QUEUES, TUNE_GMRES_WG_PER_CU = 3, 4, 5
+TUNE_GMRES_THREADS, TUNE_GMRES_QUEUES, TUNE_GMRES_WG_PER_CU, TUNE_MB_FIELDS = 3, 4, 5, 6
 _PREC = {"f64": F64, "f32": F32, "bf16": BF16, F64: F64, F32: F32, BF16: BF16}
 
 if not os.path.exists(LIB_PATH):
@@ -136,6 +136,7 @@ _sig("dd_block_solve", _I32, [_P, _P, _P, _D, _P, _P, _I32, ctypes.POINTER(Solve
 _sig("dd_multiboson_action", _I32, [_P, _P, _P, _D, _I32, _P, _P, _P, ctypes.POINTER(SolveParams), _P, _P,
                                     ctypes.POINTER(SolveStats)])
 _sig("dd_tune_set", _I32, [_P, _I32, _I32])
+_sig("dd_mb_roots", _I32, [_I32, _D, _P])
 _sig("dd_nn_num_weights", _I64, [])
 _sig("dd_nn_create", _I32, [_P, _P, _I32, _P, _PP])
 _sig("dd_nn_free", _I32, [_P])
@@ -191,6 +192,15 @@ def nn_train_params(**kw) -> NnTrainParams:
     for k, v in kw.items():
         setattr(p, k, v)
     return p
+
+
+def mb_roots(N: int, c: float) -> np.ndarray:
+    """u_k, k = 1 .. N/2 (complex), from the library."""
+    out = np.zeros(N, dtype=np.float64)
+    st = _lib.dd_mb_roots(int(N), float(c), out.ctypes.data_as(_P))
+    if st != DD_OK:
+        raise DDError(st, "invalid N or c")
+    return out[0::2] + 1j * out[1::2]
 
 
 def nn_num_weights() -> int:

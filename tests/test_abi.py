@@ -132,3 +132,19 @@ def test_header_cites_paper_sections():
     txt = open(os.path.join(ROOT, "include", "dd.h")).read()
     for s in ["Section 2", "Section 3", "Section 4", "eq. (localMB)"]:
         assert s in txt
+
+
+def test_mb_roots_match_the_oracle():
+    """The library's host formula for the field parameters u_k against the oracle's roots."""
+    import numpy as np
+
+    from oracle import roots
+    from paper_2211_06902_amd import dd
+
+    for N, c in [(24, 0.5), (8, 0.3), (2, 0.9)]:
+        u = dd.mb_roots(N, c)
+        assert u.shape == (N // 2,)
+        assert np.max(np.abs(u - roots.mb_roots(N, c)[:N // 2])) <= 1e-15
+    for N, c in [(7, 0.5), (8, 1.0), (8, 0.0)]:
+        with pytest.raises(dd.DDError):
+            dd.mb_roots(N, c)

@@ -83,3 +83,29 @@ def test_mb_random_sources_vs_oracle(ctx, inner_prec):
     S_or, tot_or = mb.mb_local_action(L, -1, kappa, U, boxes, inner, u, chi, xi, tol=1e-12)
     assert np.max(np.abs(S.cpu().numpy() - S_or) / S_or) <= 1e-9
     assert abs(tot - tot_or) <= 1e-9 * tot_or
+
+
+@pytest.mark.parametrize("fields_per_solve", [1, 2])
+def test_mb_fields_in_groups_match_one_solve(ctx, fields_per_solve):
+    """Solving the fields a few at a time (as on large lattices) gives the same action."""
+    from paper_2211_06902_amd import dd
+
+    L = (16, 8, 8, 16)
+    kappa = 0.1365
+    nf = 5
+    U, boxes, blk, inner, bl = _setup(ctx, L, [[8, 8], [8], [8], [8, 8]], 1, nf, 81)
+    g = ctx.load_gauge(blk, _dev(U), "f32")
+    u = dd.mb_roots(2 * nf, 0.5)
+    chi = _dev(synth.gaussian_complex((nf, blk.total_bnd_sites, 4, 3), 82))
+    xi = _dev(synth.gaussian_complex((nf, blk.total_sites, 4, 3), 83))
+    S1, tot1, i1, s1 = ctx.multiboson_action(blk, g, kappa, u, chi, xi)
+    try:
+        ctx.tune_set(dd.TUNE_MB_FIELDS, fields_per_solve)
+        S2, tot2, i2, s2 = ctx.multiboson_action(blk, g, kappa, u, chi, xi)
+    finally:
+        ctx.tune_set(dd.TUNE_MB_FIELDS, 0)
+    assert s1 == dd.DD_OK and s2 == dd.DD_OK
+    assert np.all(i2["true_relres"] <= 1e-10)
+    S1, S2 = S1.cpu().numpy(), S2.cpu().numpy()
+    assert np.max(np.abs(S2 - S1) / S1) <= 1e-9
+    assert abs(tot2 - tot1) <= 1e-9 * tot1

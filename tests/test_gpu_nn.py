@@ -224,6 +224,40 @@ def test_fgmres_with_trained_network(ctx, toy, cycles):
     assert i1["iters"].mean() < i0["iters"].mean()
 
 
+def test_bicgstab_right_preconditioned_by_trained_network(ctx, toy):
+    """BiCGStab on Dhat N u = f with the linear network N: same 1e-10 solutions, fewer iterations,
+    and graph replay identical to eager launches."""
+    from oracle import geometry
+    from tests import _cfg
+
+    from paper_2211_06902_amd import dd
+
+    b = synth.spinor_field(toy["L"], 4, 62)[:, _cfg.block_sites(toy["L"], geometry.tile_boxes(toy["L"], [[4, 4]] * 4))]
+    bd = _dev(b)
+    x0, i0, s0 = ctx.block_solve(toy["blk"], toy["g"], toy["kappa"], bd, params=dd.solve_params(inner_prec="f32"))
+    x1, i1, s1 = ctx.block_solve(toy["blk"], toy["g"], toy["kappa"], bd,
+                                 params=dd.solve_params(inner_prec="f32", precond=toy["net"], use_graph=1))
+    x2, i2, s2 = ctx.block_solve(toy["blk"], toy["g"], toy["kappa"], bd,
+                                 params=dd.solve_params(inner_prec="f32", precond=toy["net"], use_graph=0))
+    print("BiCGStab iterations per pair: plain %.1f, right-preconditioned by the network %.1f" %
+          (i0["iters"].mean(), i1["iters"].mean()))
+    assert s0 == dd.DD_OK and s1 == dd.DD_OK and s2 == dd.DD_OK
+    assert np.all(i1["true_relres"] <= 1e-10)
+    assert _cfg.rel_err(x1.cpu().numpy(), x0.cpu().numpy()) <= 1e-8
+    assert np.array_equal(x1.cpu().numpy(), x2.cpu().numpy())
+    assert i1["iters"].mean() < i0["iters"].mean()
+
+
+def test_bicgstab_rejects_a_relu_network(ctx, toy):
+    from paper_2211_06902_amd import dd
+
+    net = ctx.nn_create((4, 4, 4, 4), synth.convnet_weights(74), act=dd.NN_RELU)
+    with pytest.raises(dd.DDError):
+        ctx.block_solve(toy["blk"], toy["g"], toy["kappa"], _dev(synth.gaussian_complex((1, 8**4, 4, 3), 75)),
+                        params=dd.solve_params(precond=net))
+    net.close()
+
+
 def test_fgmres_with_an_untrained_network_still_converges(ctx, toy):
     from paper_2211_06902_amd import dd
 
