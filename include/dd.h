@@ -254,7 +254,10 @@ dd_status dd_multiboson_action(dd_ctx *ctx, const dd_blocks *blocks, const dd_ga
  *                        only through the fixed summation order of the
  *                        workgroup's dot products. */
 /* DD_TUNE_MB_FIELDS: fields dd_multiboson_action hands to one block solve
- * (0 = as many as fit in 60 % of the free device memory). */
+ * (0 = as many as fit in 60 % of the free device memory).
+ * DD_TUNE_NN_KERNEL: BF16 network kernel, 1 (default) one workgroup per block
+ * with its input slices staged in LDS, 0 neighbour rows read from global
+ * memory (also used when a block's x0-slice exceeds 512 sites). */
 enum {
     DD_TUNE_RHS_GROUP_F64 = 0,
     DD_TUNE_RHS_GROUP_F32 = 1,
@@ -262,7 +265,8 @@ enum {
     DD_TUNE_GMRES_THREADS = 3,
     DD_TUNE_GMRES_QUEUES = 4,
     DD_TUNE_GMRES_WG_PER_CU = 5,
-    DD_TUNE_MB_FIELDS = 6
+    DD_TUNE_MB_FIELDS = 6,
+    DD_TUNE_NN_KERNEL = 7
 };
 dd_status dd_tune_set(dd_ctx *ctx, int32_t what, int32_t value);
 

@@ -541,6 +541,11 @@ dd_status dd_tune_set(dd_ctx *ctx, int32_t what, int32_t value)
         ctx->gm_queues = value;
         return DD_OK;
     }
+    if (what == DD_TUNE_NN_KERNEL) {
+        if (value != 0 && value != 1) return fail(ctx, DD_EINVAL, "network kernel must be 0 or 1");
+        ctx->nn_kernel = value;
+        return DD_OK;
+    }
     if (what == DD_TUNE_MB_FIELDS) {
         if (value < 0 || value > kMaxRhs) return fail(ctx, DD_EINVAL, "fields per solve must be in 0..64");
         ctx->mb_fields = value;

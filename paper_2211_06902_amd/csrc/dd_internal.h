@@ -50,6 +50,7 @@ struct dd_ctx {
     int gm_queues = 0;          // persistent GMRES: work queues, 1 or 8 (0 = default)
     int gm_wg_per_cu = 0;       // persistent GMRES: resident workgroups per CU (0 = all that fit)
     int mb_fields = 0;          // multi-boson action: fields per block solve (0 = as many as fit)
+    int nn_kernel = 1;          // BF16 network kernel: 0 global gathers, 1 LDS slices
 };
 
 namespace dd {
@@ -268,8 +269,11 @@ hipError_t launch_adam(float *w, const float *g, float *m, float *v, int64_t n, 
                        int t, hipStream_t st);
 // BF16 matrix-core inference: X [rows][32] BF16, Wt [81][32][32] BF16; Y BF16 [rows][32]
 // (act applied) or, with out_f32, FP32 [rows][24]
+// variant 0: neighbour rows gathered from global memory; 1: one workgroup per
+// block walking its x0-slices with three input slices in LDS (rows per slice <= 512)
+// (variant 1 skips blocks whose pair pair0 + block index has active[] == 0, when active is given)
 hipError_t launch_conv_mfma(const uint16_t *X, const uint16_t *Wt, void *Y, int64_t nrows, const NnExt &e, int act,
-                            bool out_f32, hipStream_t st);
+                            bool out_f32, int variant, const int32_t *active, int pair0, hipStream_t st);
 hipError_t launch_weights_bf16(const float *W, uint16_t *Wt, int cin, int cout, hipStream_t st);
 hipError_t launch_half_rows_bf16(const void *half, uint16_t *rows, dd_prec sp, const HalfRows &hr, hipStream_t st);
 hipError_t launch_rows_f32_to_bf16(const float *X, uint16_t *Xb, int64_t nrows, hipStream_t st);

@@ -55,7 +55,7 @@ hipError_t nn_forward(dd_ctx *ctx, const dd_nn *nn, const float *X, float *Z1, f
 bool nn_fits(const dd_nn *nn, const dd_blocks *B) { return same_shape(nn, B); }
 
 hipError_t nn_forward_bf16(dd_ctx *ctx, dd_nn *nn, const uint16_t *Xb, uint16_t *Zb1, uint16_t *Zb2, float *O,
-                           int64_t nrows)
+                           int64_t nrows, const int32_t *active, int pair0)
 {
     hipStream_t st = ctx->stream;
     hipError_t e = hipSuccess;
@@ -65,12 +65,17 @@ hipError_t nn_forward_bf16(dd_ctx *ctx, dd_nn *nn, const uint16_t *Xb, uint16_t 
         if (e != hipSuccess) return e;
         nn->bf16_step = nn->step;
     }
-    if ((e = launch_conv_mfma(Xb, nn->d_wbf, Zb1, nrows, nn->e, nn->act, false, st)) != hipSuccess) return e;
-    if ((e = launch_conv_mfma(Zb1, nn->d_wbf + 81 * 1024, Zb2, nrows, nn->e, nn->act, false, st)) != hipSuccess) return e;
-    return launch_conv_mfma(Zb2, nn->d_wbf + 2 * 81 * 1024, O, nrows, nn->e, 0, true, st);
+    const int v = ctx->nn_kernel;
+    if ((e = launch_conv_mfma(Xb, nn->d_wbf, Zb1, nrows, nn->e, nn->act, false, v, active, pair0, st)) != hipSuccess)
+        return e;
+    if ((e = launch_conv_mfma(Zb1, nn->d_wbf + 81 * 1024, Zb2, nrows, nn->e, nn->act, false, v, active, pair0, st)) !=
+        hipSuccess)
+        return e;
+    return launch_conv_mfma(Zb2, nn->d_wbf + 2 * 81 * 1024, O, nrows, nn->e, 0, true, v, active, pair0, st);
 }
 
-hipError_t nn_apply_half(dd_ctx *ctx, dd_nn *nn, const dd_blocks *B, const void *v, void *z, int n_rhs, dd_prec sp)
+hipError_t nn_apply_half(dd_ctx *ctx, dd_nn *nn, const dd_blocks *B, const void *v, void *z, int n_rhs, dd_prec sp,
+                         const int32_t *active)
 {
     const int S = nn->e.S;
     const int np = n_rhs * B->nb;
@@ -92,7 +97,8 @@ hipError_t nn_apply_half(dd_ctx *ctx, dd_nn *nn, const dd_blocks *B, const void 
         if (bf) {
             e = launch_half_rows_bf16(v, (uint16_t *)X, sp, hr, ctx->stream);
             TimedLaunch tl(ctx, DD_KCLASS_NN_BF16, 2.0 * 81 * (24 * 32 + 32 * 32 + 32 * 24) * (double)nrows);
-            if (e == hipSuccess) e = nn_forward_bf16(ctx, nn, (uint16_t *)X, (uint16_t *)Z1, (uint16_t *)Z2, O, nrows);
+            if (e == hipSuccess)
+                e = nn_forward_bf16(ctx, nn, (uint16_t *)X, (uint16_t *)Z1, (uint16_t *)Z2, O, nrows, active, p0);
         } else {
             e = launch_half_rows(v, (float *)X, nullptr, sp, hr, 0, ctx->stream);
             if (e == hipSuccess) e = nn_forward(ctx, nn, (float *)X, (float *)Z1, (float *)Z2, O, nrows);
@@ -284,7 +290,8 @@ dd_status dd_nn_apply(dd_ctx *ctx, dd_nn *nn, dd_prec prec, const float *x_dev, 
             HIPCHECK(ctx, nn_forward(ctx, nn, x_dev + off, (float *)Z1, (float *)Z2, y_dev + off, nrows));
         } else {
             HIPCHECK(ctx, launch_rows_f32_to_bf16(x_dev + off, (uint16_t *)Xb, nrows, ctx->stream));
-            HIPCHECK(ctx, nn_forward_bf16(ctx, nn, (uint16_t *)Xb, (uint16_t *)Z1, (uint16_t *)Z2, y_dev + off, nrows));
+            HIPCHECK(ctx, nn_forward_bf16(ctx, nn, (uint16_t *)Xb, (uint16_t *)Z1, (uint16_t *)Z2, y_dev + off, nrows,
+                                          nullptr, 0));
         }
     }
     HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));

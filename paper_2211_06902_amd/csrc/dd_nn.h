@@ -35,11 +35,14 @@ hipError_t nn_forward(dd_ctx *ctx, const dd_nn *nn, const float *X, float *Z1, f
 // z = N(v) for every (block, rhs) pair of an even half field in the library
 // layout (inner precision sp); v and z may not alias.  Blocks must all have
 // the network's extent (checked by the caller).
-hipError_t nn_apply_half(dd_ctx *ctx, dd_nn *nn, const dd_blocks *B, const void *v, void *z, int n_rhs, dd_prec sp);
+// With active (per pair, may be null) the BF16 network skips pairs whose flag is 0
+// and leaves their z unchanged.
+hipError_t nn_apply_half(dd_ctx *ctx, dd_nn *nn, const dd_blocks *B, const void *v, void *z, int n_rhs, dd_prec sp,
+                         const int32_t *active = nullptr);
 bool nn_fits(const dd_nn *nn, const dd_blocks *B);
 
 // the network in BF16 on the matrix cores: Xb [rows][32] BF16 -> O [rows][24] FP32
 hipError_t nn_forward_bf16(dd_ctx *ctx, dd_nn *nn, const uint16_t *Xb, uint16_t *Zb1, uint16_t *Zb2, float *O,
-                           int64_t nrows);
+                           int64_t nrows, const int32_t *active, int pair0);
 
 }  // namespace dd

@@ -411,6 +411,114 @@ __global__ void __launch_bounds__(256) k_conv_mfma(const uint16_t *__restrict__ 
             }
 }
 
+// The same layer with the input staged in LDS: one workgroup per block walks its
+// x0-slices, keeping the three input slices x0 - 1, x0, x0 + 1 in a ring of LDS
+// buffers (rows padded to 80 bytes against bank conflicts; slices outside the
+// block are zero), so every input row is read from HBM once per layer and the
+// 81 taps read their neighbour rows from LDS.  Wave w computes output rows
+// 64 w .. 64 w + 63 of the slice.  Needs e1 e2 e3 <= 512.
+constexpr int kSliceMax = 512;
+constexpr int kRowPad = 40;  // bf16 per LDS row (32 + 8 padding)
+
+template <int ACT, bool OUT_F32>
+__global__ void __launch_bounds__(512) k_conv_mfma_lds(const uint16_t *__restrict__ X, const uint16_t *__restrict__ Wt,
+                                                       void *__restrict__ Y, NnExt e, const int32_t *__restrict__ active,
+                                                       int pair0)
+{
+    __shared__ uint16_t ring[3][kSliceMax][kRowPad];
+    // blocks whose (block, rhs) pair is no longer iterated are skipped
+    if (active && !active[pair0 + (int)blockIdx.x]) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int kg = lane >> 4, li = lane & 15;
+    const int R = e.e[1] * e.e[2] * e.e[3];
+    const int64_t base = (int64_t)blockIdx.x * e.S;  // first row of this block
+    // output coordinates (x1, x2, x3) of this lane's row in each 16-row tile
+    int oc[4][3];
+    bool orow[4];
+#pragma unroll
+    for (int rt = 0; rt < 4; rt++) {
+        int r = wave * 64 + rt * 16 + li;
+        orow[rt] = r < R;
+        r = min(r, R - 1);
+        oc[rt][2] = r % e.e[3];
+        r /= e.e[3];
+        oc[rt][1] = r % e.e[2];
+        oc[rt][0] = r / e.e[2];
+    }
+    auto load_slice = [&](int s) {
+        uint16_t(*dst)[kRowPad] = ring[(s + 3) % 3];
+        const bool in = s >= 0 && s < e.e[0];
+        for (int k = threadIdx.x; k < R * 4; k += 512) {
+            const int r = k >> 2, q = k & 3;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (in) v = *reinterpret_cast<const uint4 *>(X + (base + (int64_t)s * R + r) * 32 + q * 8);
+            *reinterpret_cast<uint4 *>(&dst[r][q * 8]) = v;
+        }
+    };
+    load_slice(-1);
+    load_slice(0);
+    load_slice(1);
+    __syncthreads();
+    const bf16x8 zero = {};
+    for (int a = 0; a < e.e[0]; a++) {
+        f32x4 acc[4][2];
+#pragma unroll
+        for (int rt = 0; rt < 4; rt++)
+#pragma unroll
+            for (int ct = 0; ct < 2; ct++) acc[rt][ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        for (int t0 = -1; t0 <= 1; t0++) {
+            const uint16_t(*src)[kRowPad] = ring[(a + t0 + 3) % 3];
+            for (int t1 = -1; t1 <= 1; t1++)
+                for (int t2 = -1; t2 <= 1; t2++) {
+#pragma unroll
+                    for (int t3 = -1; t3 <= 1; t3++) {
+                        const int tap = ((t0 + 1) * 3 + (t1 + 1)) * 9 + (t2 + 1) * 3 + (t3 + 1);
+                        bf16x8 bv[2];
+#pragma unroll
+                        for (int ct = 0; ct < 2; ct++)
+                            bv[ct] = *reinterpret_cast<const bf16x8 *>(Wt + ((int64_t)(tap * 32 + ct * 16 + li) * 32 + kg * 8));
+                        bf16x8 av[4];
+#pragma unroll
+                        for (int rt = 0; rt < 4; rt++) {
+                            const int y1 = oc[rt][0] + t1, y2 = oc[rt][1] + t2, y3 = oc[rt][2] + t3;
+                            const bool in = orow[rt] && (unsigned)y1 < (unsigned)e.e[1] &&
+                                            (unsigned)y2 < (unsigned)e.e[2] && (unsigned)y3 < (unsigned)e.e[3];
+                            const int r = in ? (y1 * e.e[2] + y2) * e.e[3] + y3 : 0;
+                            av[rt] = in ? *reinterpret_cast<const bf16x8 *>(&src[r][kg * 8]) : zero;
+                        }
+#pragma unroll
+                        for (int rt = 0; rt < 4; rt++)
+#pragma unroll
+                            for (int ct = 0; ct < 2; ct++)
+                                acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[rt], bv[ct], acc[rt][ct], 0, 0, 0);
+                    }
+                }
+        }
+        // store this slice's output rows
+#pragma unroll
+        for (int rt = 0; rt < 4; rt++)
+#pragma unroll
+            for (int ct = 0; ct < 2; ct++)
+#pragma unroll
+                for (int i = 0; i < 4; i++) {
+                    const int r = wave * 64 + rt * 16 + 4 * kg + i;
+                    const int col = ct * 16 + li;
+                    if (r >= R) continue;
+                    const int64_t row = base + (int64_t)a * R + r;
+                    float v = acc[rt][ct][i];
+                    if constexpr (OUT_F32) {
+                        if (col < 24) reinterpret_cast<float *>(Y)[row * 24 + col] = v;
+                    } else {
+                        if (ACT) v = fmaxf(v, 0.0f);
+                        reinterpret_cast<uint16_t *>(Y)[row * 32 + col] = f2bf(v);
+                    }
+                }
+        __syncthreads();  // every wave is done with slice a - 1
+        if (a + 2 <= e.e[0]) load_slice(a + 2);
+        __syncthreads();
+    }
+}
+
 // Wt[t][o][c] = bf16(W[t][c][o]) for o < cout, c < cin; 0 elsewhere (32 x 32 per tap)
 __global__ void k_weights_bf16(const float *__restrict__ W, uint16_t *__restrict__ Wt, int cin, int cout)
 {
@@ -454,6 +562,8 @@ __global__ void k_rows_f32_to_bf16(const float *__restrict__ X, uint16_t *__rest
 }
 
 // ------------------------------------------------------------ launchers
+
+
 
 static inline dim3 g256(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
 
@@ -537,9 +647,17 @@ hipError_t launch_half_rows(const void *half, float *rows, void *half_out, dd_pr
 }
 
 hipError_t launch_conv_mfma(const uint16_t *X, const uint16_t *Wt, void *Y, int64_t nrows, const NnExt &e, int act,
-                            bool out_f32, hipStream_t st)
+                            bool out_f32, int variant, const int32_t *active, int pair0, hipStream_t st)
 {
     if (nrows <= 0) return hipSuccess;
+    const int R = e.e[1] * e.e[2] * e.e[3];
+    if (R <= kSliceMax && nrows % e.S == 0 && variant == 1) {
+        const dim3 g((unsigned)(nrows / e.S));
+        if (out_f32) hipLaunchKernelGGL((k_conv_mfma_lds<0, true>), g, dim3(512), 0, st, X, Wt, Y, e, active, pair0);
+        else if (act) hipLaunchKernelGGL((k_conv_mfma_lds<1, false>), g, dim3(512), 0, st, X, Wt, Y, e, active, pair0);
+        else hipLaunchKernelGGL((k_conv_mfma_lds<0, false>), g, dim3(512), 0, st, X, Wt, Y, e, active, pair0);
+        return hipGetLastError();
+    }
     const dim3 g((unsigned)((nrows + 255) / 256));
     if (out_f32) hipLaunchKernelGGL((k_conv_mfma<0, true>), g, dim3(256), 0, st, X, Wt, Y, nrows, e);
     else if (act) hipLaunchKernelGGL((k_conv_mfma<1, false>), g, dim3(256), 0, st, X, Wt, Y, nrows, e);

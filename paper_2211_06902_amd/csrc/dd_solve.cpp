@@ -64,7 +64,7 @@ hipError_t bicg_iteration(const Inner &in)
     hipStream_t st = in.ctx->stream;
     const void *pp = w.p, *ss = w.s;
     if (in.nn) {
-        if ((e = nn_apply_half(in.ctx, in.nn, in.B, w.p, in.ph, in.n_rhs, in.sp)) != hipSuccess) return e;
+        if ((e = nn_apply_half(in.ctx, in.nn, in.B, w.p, in.ph, in.n_rhs, in.sp, w.ps.active)) != hipSuccess) return e;
         pp = in.ph;
     }
     // v = Dhat p
@@ -80,7 +80,7 @@ hipError_t bicg_iteration(const Inner &in)
     if ((e = launch_sc_alpha(in.ba, w.pA, w.ps, st)) != hipSuccess) return e;
     if ((e = launch_bicg_s(in.ba, in.sp, w.r, w.v, w.s, w.ps, st)) != hipSuccess) return e;
     if (in.nn) {
-        if ((e = nn_apply_half(in.ctx, in.nn, in.B, w.s, in.sh, in.n_rhs, in.sp)) != hipSuccess) return e;
+        if ((e = nn_apply_half(in.ctx, in.nn, in.B, w.s, in.sh, in.n_rhs, in.sp, w.ps.active)) != hipSuccess) return e;
         ss = in.sh;
     }
     // t = Dhat s; omega = <t, s> / <t, t>

@@ -24,7 +24,7 @@ F64, F32, BF16 = 0, 1, 2
 BICGSTAB, GMRES = 0, 1
 KCLASS_HOP_F64, KCLASS_HOP_F32, KCLASS_HOP_BF16, KCLASS_GMRES, KCLASS_NN_BF16 = 0, 1, 2, 3, 4
 TUNE_RHS_GROUP_F64, TUNE_RHS_GROUP_F32, TUNE_HOP_LDS = 0, 1, 2
-TUNE_GMRES_THREADS, TUNE_GMRES_QUEUES, TUNE_GMRES_WG_PER_CU, TUNE_MB_FIELDS = 3, 4, 5, 6
+TUNE_GMRES_THREADS, TUNE_GMRES_QUEUES, TUNE_GMRES_WG_PER_CU, TUNE_MB_FIELDS, TUNE_NN_KERNEL = 3, 4, 5, 6, 7
 _PREC = {"f64": F64, "f32": F32, "bf16": BF16, F64: F64, F32: F32, BF16: BF16}
 
 if not os.path.exists(LIB_PATH):
