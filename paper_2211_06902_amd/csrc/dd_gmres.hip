@@ -96,7 +96,7 @@ __device__ __forceinline__ double wg_hop(const PairGeo &g, int p, const SP *in, 
         hop_one<2, false, SP, LK, AC, 1, false>(acc, a1.y, nullptr, hc);
         hop_one<3, true, SP, LK, AC, 1, false>(acc, a1.z, nullptr, hc);
         hop_one<3, false, SP, LK, AC, 1, false>(acc, a1.w, nullptr, hc);
-#pragma unroll 4
+#pragma unroll
         for (int c = 0; c < 24; c++) {
             const size_t o = (size_t)c * g.h + s;
             AC v = ch * acc[0][c];

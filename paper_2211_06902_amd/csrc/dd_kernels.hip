@@ -159,7 +159,8 @@ __global__ void __launch_bounds__(kTile) k_hop(BlkArgs ba, HopArgs ha)
         const AC ch = (AC)ha.c_hop, cself = (AC)ha.c_self, cadd = (AC)ha.c_add;
 #pragma unroll
         for (int j = 0; j < G; j++) {
-#pragma unroll 4
+            // fully unrolled: acc is indexed by k, and a runtime index would put it in scratch
+#pragma unroll
             for (int k = 0; k < 12; k++) {
                 double o[2], sv[2] = {0, 0}, av[2] = {0, 0};
 #pragma unroll
