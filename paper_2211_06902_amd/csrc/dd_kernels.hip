@@ -154,44 +154,60 @@ __global__ void __launch_bounds__(kTile) k_hop(BlkArgs ba, HopArgs ha)
         const Buf out_b = make_buf(reinterpret_cast<const SP *>(ha.out) + hbase, fbytes);
         const Buf self_b = make_buf(ha.self ? reinterpret_cast<const SP *>(ha.self) + hbase : nullptr, ha.self ? fbytes : 0);
         const Buf add_b = make_buf(ha.add ? reinterpret_cast<const SP *>(ha.add) + hbase : nullptr, ha.add ? fbytes : 0);
-        const Buf aux_b = make_buf(ha.aux ? reinterpret_cast<const SP *>(ha.aux) + hbase : nullptr, ha.aux ? fbytes : 0);
+        const bool need_aux = ha.dot_mode == kDotAuxOut || ha.dot_mode == kDotOutAuxOutOut;
+        const Buf aux_b = make_buf(need_aux ? reinterpret_cast<const SP *>(ha.aux) + hbase : nullptr, need_aux ? fbytes : 0);
         const bool has_self = ha.self != nullptr, has_add = ha.add != nullptr;
         const AC ch = (AC)ha.c_hop, cself = (AC)ha.c_self, cadd = (AC)ha.c_add;
+        // Two halves of 12 reals: all operand loads of a half are issued before its
+        // stores (a store to `out` could alias them, which would otherwise serialise
+        // every load behind the previous store).  An absent operand has a zero-size
+        // descriptor: its loads return 0 without touching memory, so no branch
+        // splits the batch.  Fully unrolled: acc is indexed by the component, and a
+        // runtime index would put it in scratch.
 #pragma unroll
-        for (int j = 0; j < G; j++) {
-            // fully unrolled: acc is indexed by k, and a runtime index would put it in scratch
+        for (int j = 0; j < G; j++)
 #pragma unroll
-            for (int k = 0; k < 12; k++) {
-                double o[2], sv[2] = {0, 0}, av[2] = {0, 0};
+            for (int half = 0; half < 2; half++) {
+                SP sx[12], dx[12], ax[12];
 #pragma unroll
-                for (int ri = 0; ri < 2; ri++) {
-                    const uint32_t so = (uint32_t)(j * 24 + 2 * k + ri) * hc.cstr;
-                    AC v = ch * acc[j][2 * k + ri];
-                    if (has_self) {
-                        const SP sx = bload<SP>(self_b, my, so);
-                        sv[ri] = (double)sx;
-                        v = fmad(cself, (AC)sx, v);
-                    }
-                    if (has_add) v = fmad(cadd, (AC)bload<SP>(add_b, my, so), v);
-                    const SP ov = (SP)v;
-                    bstore<SP>(out_b, ov, my, so);
-                    o[ri] = (double)ov;
-                    if (ha.dot_mode == kDotAuxOut || ha.dot_mode == kDotOutAuxOutOut)
-                        av[ri] = (double)bload<SP>(aux_b, my, so);
+                for (int q = 0; q < 12; q++) {
+                    const uint32_t so = (uint32_t)(j * 24 + 12 * half + q) * hc.cstr;
+                    sx[q] = bload<SP>(self_b, my, so);
+                    dx[q] = bload<SP>(add_b, my, so);
+                    ax[q] = bload<SP>(aux_b, my, so);
                 }
-                if (ha.dot_mode == kDotAuxOut) {
-                    dv[j][0] += av[0] * o[0] + av[1] * o[1];
-                    dv[j][1] += av[0] * o[1] - av[1] * o[0];
-                } else if (ha.dot_mode == kDotOutSelfOutOut || ha.dot_mode == kDotOutAuxOutOut) {
-                    const double *q = ha.dot_mode == kDotOutAuxOutOut ? av : sv;
-                    dv[j][0] += o[0] * q[0] + o[1] * q[1];
-                    dv[j][1] += o[0] * q[1] - o[1] * q[0];
-                    dv[j][2] += o[0] * o[0] + o[1] * o[1];
-                } else if (ha.dot_mode == kDotOutOut) {
-                    dv[j][0] += o[0] * o[0] + o[1] * o[1];
+#pragma unroll
+                for (int k = 0; k < 6; k++) {
+                    double o[2], sv[2], av[2];
+#pragma unroll
+                    for (int ri = 0; ri < 2; ri++) {
+                        const int q = 2 * k + ri;
+                        const uint32_t so = (uint32_t)(j * 24 + 12 * half + q) * hc.cstr;
+                        AC v = ch * acc[j][12 * half + q];
+                        if (has_self) v = fmad(cself, (AC)sx[q], v);
+                        if (has_add) v = fmad(cadd, (AC)dx[q], v);
+                        const SP ov = (SP)v;
+                        bstore<SP>(out_b, ov, my, so);
+                        o[ri] = (double)ov;
+                        sv[ri] = (double)sx[q];
+                        av[ri] = (double)ax[q];
+                    }
+                    if (ha.dot_mode == kDotAuxOut) {
+                        dv[j][0] += av[0] * o[0] + av[1] * o[1];
+                        dv[j][1] += av[0] * o[1] - av[1] * o[0];
+                    } else if (ha.dot_mode == kDotOutSelfOutOut) {
+                        dv[j][0] += o[0] * sv[0] + o[1] * sv[1];
+                        dv[j][1] += o[0] * sv[1] - o[1] * sv[0];
+                        dv[j][2] += o[0] * o[0] + o[1] * o[1];
+                    } else if (ha.dot_mode == kDotOutAuxOutOut) {
+                        dv[j][0] += o[0] * av[0] + o[1] * av[1];
+                        dv[j][1] += o[0] * av[1] - o[1] * av[0];
+                        dv[j][2] += o[0] * o[0] + o[1] * o[1];
+                    } else if (ha.dot_mode == kDotOutOut) {
+                        dv[j][0] += o[0] * o[0] + o[1] * o[1];
+                    }
                 }
             }
-        }
     }
     if (ha.dot_mode != kDotNone) {
         const int nred = ha.dot_mode == kDotAuxOut ? 2 : (ha.dot_mode == kDotOutSelfOutOut || ha.dot_mode == kDotOutAuxOutOut ? 3 : 1);
