@@ -126,6 +126,31 @@ def net_roofline(net, n_blocks, reps=5):
     return dt * 1e3, reps, reps * 2.0 * 81 * (24 * 32 + 32 * 32 + 32 * 24) * n_blocks * net.sites
 
 
+def run_nnapply(args):
+    """The network's BF16 application alone: 1024 blocks of 8^4 random rows (an untrained network),
+    `--steps` timed applications after one warm-up."""
+    import torch
+
+    import synth
+    from paper_2211_06902_amd import dd
+
+    ctx = dd.Context(0)
+    net = ctx.nn_create((8, 8, 8, 8), synth.convnet_weights(5))
+    ms, n, flops = net_roofline(net, 1024, reps=args.steps)
+    achieved = flops / (ms * 1e-3) / 1e12
+    print(json.dumps({
+        "metric": "network application throughput", "value": achieved, "unit": "TFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": 1, "ms_per_step": ms / n, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "24-32-32-24 3^4 conv net, BF16 matrix-core inference on 1024 blocks of 8^4 "
+                               "(414 720 flop per site), wall time around dd_nn_apply"},
+        "roofline": {"kernel": "k_conv_mfma_lds", "bound": "mfma", "achieved": achieved, "peak": 2500.0,
+                     "unit": "TFLOP/s", "frac": achieved / 2500.0, "traffic": None},
+    }), flush=True)
+    net.close()
+    ctx.close()
+
+
 def run_c4(args):
     """The learned preconditioner: train the network on ~20k (source, D^{-1} source) pairs of the
     32^4 lattice's 8^4 blocks (sources on even sites, made by the block solver), then solve fresh
@@ -397,7 +422,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--inner", default=None, choices=["f32", "bf16", "f64"],
                     help="inner precision (default: FP32 for c2, BF16 links for c3)")
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["c4", "c5"])
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["c4", "c5", "nnapply"])
     ap.add_argument("--epochs", type=int, default=4, help="c4: training epochs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (4 times), to calibrate HBM byte counters")
@@ -419,6 +444,9 @@ def main():
 
     if args.workload == "c4":
         run_c4(args)
+        return
+    if args.workload == "nnapply":
+        run_nnapply(args)
         return
     if args.workload == "c5":
         run_c5(args)

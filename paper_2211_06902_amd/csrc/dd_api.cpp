@@ -143,7 +143,9 @@ hipError_t run_hop(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const Hop
 {
     HopArgs ha = ha_in;
     ha.use_lds = ctx->hop_lds ? 1 : 0;
-    const int extra = (ha.self != nullptr) + (ha.add != nullptr) + (ha.aux != nullptr);
+    // operands the kernel reads besides `in` (aux only in the dot modes that use it)
+    const bool aux = ha.aux && (ha.dot_mode == kDotAuxOut || ha.dot_mode == kDotOutAuxOutOut);
+    const int extra = (ha.self != nullptr) + (ha.add != nullptr) + (aux ? 1 : 0);
     TimedLaunch tl(ctx, DD_KCLASS_HOP_F64 + (int)prec, hop_bytes(B, ba.n_rhs, prec, extra));
     return launch_hop(ba, ha, prec, ctx->stream);
 }

@@ -90,7 +90,7 @@ hipError_t bicg_iteration(const Inner &in)
     h4.self = ss;
     h4.c_self = 1.0;
     h4.dot_mode = in.nn ? kDotOutAuxOutOut : kDotOutSelfOutOut;
-    h4.aux = w.s;
+    h4.aux = in.nn ? w.s : nullptr;
     h4.partial = w.pB;
     if ((e = run_hop(in.ctx, in.B, in.ba, h4, in.ip)) != hipSuccess) return e;
     if ((e = launch_sc_omega(in.ba, w.pB, w.ps, st)) != hipSuccess) return e;

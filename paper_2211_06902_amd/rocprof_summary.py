@@ -29,9 +29,9 @@ KERNEL_SOURCES = [os.path.join(HERE, "csrc", "dd_kernels.hip"), os.path.join(HER
 GIB = float(1 << 30)
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(paths=None) -> str:
     h = hashlib.sha256()
-    for path in KERNEL_SOURCES:
+    for path in paths or KERNEL_SOURCES:
         with open(path, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -53,15 +53,18 @@ def _counter(path_dir: str, name: str, kernel: str):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--stats", required=True)
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
-    ap.add_argument("--copy-fetch", required=True)
-    ap.add_argument("--copy-write", required=True)
+    ap.add_argument("--fetch", help="FETCH_SIZE run (omit for a timing-only summary)")
+    ap.add_argument("--write")
+    ap.add_argument("--copy-fetch")
+    ap.add_argument("--copy-write")
     ap.add_argument("--kernel", required=True, help="substring of the kernel name")
-    ap.add_argument("--alg-bytes-per-launch", type=float, required=True)
+    ap.add_argument("--alg-bytes-per-launch", type=float, help="algorithmic bytes per launch")
+    ap.add_argument("--alg-flops-per-launch", type=float, help="algorithmic flops per launch (matrix-core kernels)")
+    ap.add_argument("--peak", type=float, default=8000.0, help="GB/s, or TFLOP/s with --alg-flops-per-launch")
     ap.add_argument("--out", required=True)
     ap.add_argument("--command", required=True)
     ap.add_argument("--title", default="")
+    ap.add_argument("--source", nargs="*", help="kernel source files to hash (default: the hop's)")
     args = ap.parse_args()
 
     stats = list(csv.DictReader(open(_one(args.stats, "*kernel_stats.csv"))))
@@ -72,33 +75,51 @@ def main():
     total_ns = sum(float(r["TotalDurationNs"]) for r in mine)
     avg_us = total_ns / calls / 1e3
 
-    copy_f = _counter(args.copy_fetch, "FETCH_SIZE", "copyBuffer") or _counter(args.copy_fetch, "FETCH_SIZE", "")
-    copy_w = _counter(args.copy_write, "WRITE_SIZE", "copyBuffer") or _counter(args.copy_write, "WRITE_SIZE", "")
-    big_f = max(copy_f)
-    big_w = max(copy_w)
-    scale_f = GIB / (big_f * 1024.0)  # bytes per reported byte
-    scale_w = GIB / (big_w * 1024.0)
-    fv = _counter(args.fetch, "FETCH_SIZE", args.kernel)
-    wv = _counter(args.write, "WRITE_SIZE", args.kernel)
-    fetch_b = sum(fv) / len(fv) * 1024.0 * scale_f
-    write_b = sum(wv) / len(wv) * 1024.0 * scale_w
-    traffic = fetch_b + write_b
-    achieved = args.alg_bytes_per_launch / (avg_us * 1e-6) / 1e9
-
     summary = {
         "kernel": args.kernel,
-        "kernel_source_sha256_16": kernel_source_hash(),
+        "kernel_source_sha256_16": kernel_source_hash(args.source),
         "launches": calls,
         "avg_duration_us": avg_us,
-        "alg_bytes_per_launch": args.alg_bytes_per_launch,
-        "achieved_alg_GBs": achieved,
-        "hbm_fetch_bytes_per_launch": fetch_b,
-        "hbm_write_bytes_per_launch": write_b,
-        "hbm_traffic_bytes_per_launch": traffic,
-        "traffic_over_alg": traffic / args.alg_bytes_per_launch,
-        "fetch_scale": scale_f,
-        "write_scale": scale_w,
     }
+    rows = [
+        "| kernel (name contains) | `%s` |" % args.kernel,
+        "| launches | %d |" % calls,
+        "| average duration | %.1f us |" % avg_us,
+    ]
+    if args.alg_bytes_per_launch:
+        achieved = args.alg_bytes_per_launch / (avg_us * 1e-6) / 1e9
+        summary.update(alg_bytes_per_launch=args.alg_bytes_per_launch, achieved_alg_GBs=achieved)
+        rows += ["| algorithmic bytes per launch | %.4g |" % args.alg_bytes_per_launch,
+                 "| achieved algorithmic bandwidth | %.0f GB/s (%.1f %% of %.0f GB/s) |"
+                 % (achieved, 100 * achieved / args.peak, args.peak)]
+    if args.alg_flops_per_launch:
+        achieved = args.alg_flops_per_launch / (avg_us * 1e-6) / 1e12
+        summary.update(alg_flops_per_launch=args.alg_flops_per_launch, achieved_TFLOPs=achieved)
+        rows += ["| algorithmic flops per launch | %.4g |" % args.alg_flops_per_launch,
+                 "| achieved | %.1f TFLOP/s (%.1f %% of %.0f TFLOP/s) |" % (achieved, 100 * achieved / args.peak, args.peak)]
+    calib = ""
+    if args.fetch:
+        copy_f = _counter(args.copy_fetch, "FETCH_SIZE", "copyBuffer") or _counter(args.copy_fetch, "FETCH_SIZE", "")
+        copy_w = _counter(args.copy_write, "WRITE_SIZE", "copyBuffer") or _counter(args.copy_write, "WRITE_SIZE", "")
+        big_f = max(copy_f)
+        big_w = max(copy_w)
+        scale_f = GIB / (big_f * 1024.0)  # bytes per reported byte
+        scale_w = GIB / (big_w * 1024.0)
+        fv = _counter(args.fetch, "FETCH_SIZE", args.kernel)
+        wv = _counter(args.write, "WRITE_SIZE", args.kernel)
+        fetch_b = sum(fv) / len(fv) * 1024.0 * scale_f
+        write_b = sum(wv) / len(wv) * 1024.0 * scale_w
+        traffic = fetch_b + write_b
+        summary.update(hbm_fetch_bytes_per_launch=fetch_b, hbm_write_bytes_per_launch=write_b,
+                       hbm_traffic_bytes_per_launch=traffic, fetch_scale=scale_f, write_scale=scale_w)
+        rows += ["| HBM fetch per launch (FETCH_SIZE x %.3f) | %.4g B |" % (scale_f, fetch_b),
+                 "| HBM write per launch (WRITE_SIZE x %.3f) | %.4g B |" % (scale_w, write_b)]
+        if args.alg_bytes_per_launch:
+            summary["traffic_over_alg"] = traffic / args.alg_bytes_per_launch
+            rows.append("| HBM traffic / algorithmic bytes | %.3f |" % (traffic / args.alg_bytes_per_launch))
+        calib = ("Calibration: a 1 GiB device copy reads FETCH_SIZE = %.0f KiB and WRITE_SIZE = %.0f KiB per copy."
+                 % (big_f, big_w))
+    rows.append("| kernel source sha256[:16] | %s |" % summary["kernel_source_sha256_16"])
     top = sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:12]
     lines = [
         "# %s" % (args.title or "rocprofv3 summary: " + args.kernel),
@@ -113,23 +134,11 @@ def main():
         "",
         "| quantity | value |",
         "|---|---|",
-        "| kernel (name contains) | `%s` |" % args.kernel,
-        "| launches | %d |" % calls,
-        "| average duration | %.1f us |" % avg_us,
-        "| algorithmic bytes per launch | %.4g |" % args.alg_bytes_per_launch,
-        "| achieved algorithmic bandwidth | %.0f GB/s (%.1f %% of 8 TB/s) |" % (achieved, achieved / 80.0),
-        "| HBM fetch per launch (FETCH_SIZE x %.3f) | %.4g B |" % (scale_f, fetch_b),
-        "| HBM write per launch (WRITE_SIZE x %.3f) | %.4g B |" % (scale_w, write_b),
-        "| HBM traffic / algorithmic bytes | %.3f |" % (traffic / args.alg_bytes_per_launch),
-        "| kernel source sha256[:16] | %s |" % summary["kernel_source_sha256_16"],
-        "",
-        "Calibration: a 1 GiB device copy reads FETCH_SIZE = %.0f KiB and WRITE_SIZE = %.0f KiB per copy." % (big_f, big_w),
-        "",
-        "## Kernel time (all kernels of the run, top 12)",
-        "",
-        "| kernel | calls | total ms | avg us | % |",
-        "|---|---|---|---|---|",
-    ]
+    ] + rows + ["", calib, "",
+                "## Kernel time (all kernels of the run, top 12)",
+                "",
+                "| kernel | calls | total ms | avg us | % |",
+                "|---|---|---|---|---|"]
     for r in top:
         lines.append("| `%s` | %s | %.2f | %.1f | %.1f |" % (r["Name"][:70], r["Calls"], float(r["TotalDurationNs"]) / 1e6,
                                                        float(r["AverageNs"]) / 1e3, float(r["Percentage"])))
