@@ -139,17 +139,19 @@ dd_status dd_blocks_tables(const dd_blocks *blocks, int32_t *boxes, int64_t *sit
  * the library's packed per-block layout: FP64 always, plus a low-precision
  * copy when low_prec is DD_F32 or DD_BF16 (rounding FP64 -> FP32 to nearest
  * even, then FP32 -> BF16 to nearest even).  U_dev is only read during the
- * call. */
+ * call.  The links must be SU(3): only their first two rows are stored. */
 dd_status dd_load_gauge(dd_ctx *ctx, const dd_blocks *blocks, const void *U_dev, dd_prec low_prec,
                         dd_gauge **out);
 dd_status dd_free_gauge(dd_gauge *gauge);
 /* Export the packed links of precision prec into dst_dev (device memory of
- * at least total_sites*4*18 elements of the precision: double, float or
+ * at least total_sites*4*12 elements of the precision: double, float or
  * uint16 BF16 bits).  Layout per block b (S_b sites, starting at element
- * 72 * site_offset(b)): [mu][k = 3*row + col][eo site][re,im] holding the
- * forward link U_mu(x) of each block site x (even sites first), multiplied
- * by -1 when it crosses the antiperiodic time edge; links that leave the
- * block are zero.  Rounding to FP32/BF16 follows the sign change (exact). */
+ * 48 * site_offset(b)): [mu][k = 3*row + col, rows 0 and 1][eo site][re,im]
+ * holding the first two rows of the forward link U_mu(x) of each block site x
+ * (even sites first), multiplied by -1 when it crosses the antiperiodic time
+ * edge; links that leave the block are zero.  Rounding to FP32/BF16 follows
+ * the sign change (exact).  The kernels rebuild row 2 as conj(row0 x row1)
+ * (with the edge sign), which is exact for SU(3) links. */
 dd_status dd_gauge_export(dd_ctx *ctx, const dd_gauge *gauge, dd_prec prec, void *dst_dev);
 
 /* ------------------------------------------------------------- operator */

@@ -136,7 +136,7 @@ double hop_bytes(const dd_blocks *B, int nr, dd_prec prec, int extra_vectors)
     const double sf = prec == DD_F64 ? 8.0 : 4.0;
     const double sl = (double)prec_bytes(prec);
     const double half_sites = (double)B->soff[B->nb] / 2.0;
-    return nr * half_sites * 24.0 * sf * (2 + extra_vectors) + (double)B->inner_links * 18.0 * sl;
+    return nr * half_sites * 24.0 * sf * (2 + extra_vectors) + (double)B->inner_links * (2.0 * kLinkK) * sl;
 }
 
 hipError_t run_hop(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const HopArgs &ha_in, dd_prec prec)
@@ -443,7 +443,7 @@ dd_status dd_load_gauge(dd_ctx *ctx, const dd_blocks *B, const void *U_dev, dd_p
     G->device = ctx->device;
     G->blocks = B;
     G->low = low_prec;
-    const size_t nl = (size_t)B->soff[B->nb] * 72;
+    const size_t nl = (size_t)B->soff[B->nb] * kLinkReals;
     hipError_t e = hipMalloc((void **)&G->d_u64, std::max<size_t>(nl * 8, 8));
     if (e == hipSuccess) e = launch_pack_gauge(B, (const double *)U_dev, DD_F64, G->d_u64, ctx->stream);
     if (e == hipSuccess && low_prec == DD_F32) {
@@ -481,7 +481,7 @@ dd_status dd_gauge_export(dd_ctx *ctx, const dd_gauge *G, dd_prec prec, void *ds
     const void *src = links_for(G, prec);
     if (!src) return fail(ctx, DD_EINVAL, "gauge holds no links of that precision");
     HIPCHECK(ctx, enter(ctx));
-    const size_t bytes = (size_t)G->blocks->soff[G->blocks->nb] * 72 * prec_bytes(prec);
+    const size_t bytes = (size_t)G->blocks->soff[G->blocks->nb] * kLinkReals * prec_bytes(prec);
     HIPCHECK(ctx, hipMemcpyAsync(dst_dev, src, bytes, hipMemcpyDeviceToDevice, ctx->stream));
     HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
     return DD_OK;

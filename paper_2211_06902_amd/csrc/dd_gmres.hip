@@ -250,7 +250,8 @@ __global__ void __launch_bounds__(NT) k_gmres(GmArgs a)
         g.h = h;
         g.nbr = a.nbr + uni64(a.nbr_off[b]);
         g.kstr = (uint32_t)(4 * h) * (uint32_t)sizeof(LK);
-        g.lk_b = make_buf(reinterpret_cast<const LK *>(a.links) + so * 72, (uint32_t)(2 * h * 72) * (uint32_t)sizeof(LK));
+        g.lk_b = make_buf(reinterpret_cast<const LK *>(a.links) + so * kLinkReals,
+                          (uint32_t)(2 * h * kLinkReals) * (uint32_t)sizeof(LK));
         const int64_t pb = (so >> 1) * 24 * a.n_rhs + (int64_t)r * 24 * h;
         const SP *f = reinterpret_cast<const SP *>(a.rhs) + pb;
         SP *x = reinterpret_cast<SP *>(a.x) + pb;
@@ -260,7 +261,7 @@ __global__ void __launch_bounds__(NT) k_gmres(GmArgs a)
         // algorithmic bytes (kept by thread 0): a vector of the pair, and one eo
         // hop's links shared by the block's n_rhs pairs
         const double vb = (double)n * sizeof(SP);
-        const double lb = (double)a.nlinks[b] * 18.0 * sizeof(LK) / a.n_rhs;
+        const double lb = (double)a.nlinks[b] * (2.0 * kLinkK) * sizeof(LK) / a.n_rhs;
         double moved;
 
         // fresh start: beta0 = |f|, x = 0, V_0 = f / beta0; resumed: V_0 = r / |r|

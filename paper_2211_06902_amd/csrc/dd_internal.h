@@ -19,6 +19,10 @@ constexpr int kTile = 256;
 constexpr int kMaxRhs = 64;
 // Reals reduced per (tile, rhs) by the fused dot products.
 constexpr int kNRed = 4;
+// Links are stored as their first two rows (6 complex entries per direction);
+// the kernels rebuild the third row of the SU(3) matrix as conj(row0 x row1).
+constexpr int kLinkK = 6;
+constexpr int kLinkReals = 4 * kLinkK * 2;  // per site: 4 directions
 // Neighbour-table entry flags: bit 30 = hop across the antiperiodic time edge.
 constexpr int32_t kNbrSign = 1 << 30;
 constexpr int32_t kNbrMask = kNbrSign - 1;

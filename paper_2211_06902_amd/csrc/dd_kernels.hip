@@ -6,8 +6,9 @@
 //     site h) at (soff[b]/2)*24*n_rhs + (r*24 + c)*h_b + h, i.e. per block and
 //     rhs a component-major structure of arrays with the site innermost.
 //     Component c = 2*(3*spin + colour) + {0: re, 1: im}.
-//   links: per block [mu][k = 3*row + col][eo site][re, im], the forward link
-//     U_mu(x) of every block site; links that leave the block are zero.
+//   links: per block [mu][k = 3*row + col, rows 0 and 1][eo site][re, im], the
+//     first two rows of the forward link U_mu(x) of every block site (row 2 is
+//     rebuilt in the kernels); links that leave the block are zero.
 //   neighbour table per block shape: [parity][h][8] int32, entries
 //     2*mu = x+mu, 2*mu+1 = x-mu as the eo index inside the other parity,
 //     -1 if the hop is dropped (Dirichlet), bit 30 set if the hop crosses
@@ -109,7 +110,8 @@ __global__ void __launch_bounds__(kTile) k_hop(BlkArgs ba, HopArgs ha)
     hc.kstr = (uint32_t)(4 * t.hb) * (uint32_t)sizeof(LK);  // S_b = 2 h_b slots, (re, im) per slot
     hc.grp_off = t.grp * G * 24 * t.hb;
     hc.in_b = make_buf(reinterpret_cast<const SP *>(ha.in) + hbase, fbytes);
-    hc.lk_b = make_buf(reinterpret_cast<const LK *>(ha.links) + soff * 72, (uint32_t)(2 * t.hb * 72) * (uint32_t)sizeof(LK));
+    hc.lk_b = make_buf(reinterpret_cast<const LK *>(ha.links) + soff * kLinkReals,
+                       (uint32_t)(2 * t.hb * kLinkReals) * (uint32_t)sizeof(LK));
     const uint32_t my = (uint32_t)(hc.grp_off + t.site) * (uint32_t)sizeof(SP);  // bytes to (group, comp 0, own site)
     if (t.live && ha.use_lds) {
 #pragma unroll 4
@@ -288,16 +290,17 @@ __global__ void __launch_bounds__(256) k_pack_gauge(PackGeom g, const double *U,
     for (int m = 0; m < 4; m++) x[m] = (g.origin[4 * b + m] + c[m]) % g.L[m];
     const int64_t n = (((int64_t)x[0] * g.L[1] + x[1]) * g.L[2] + x[2]) * g.L[3] + x[3];
     const int32_t *nb = g.nbr + g.nbr_off[b] + (int64_t)s * 8;  // slot s = p*h + site
-    LT *blk = dst + g.soff[b] * 72;
+    LT *blk = dst + g.soff[b] * kLinkReals;
     for (int mu = 0; mu < 4; mu++) {
         const int32_t e = nb[2 * mu];
         const bool in = e >= 0;
         // a link across the antiperiodic time edge is stored with the -1 of the
-        // fermion boundary condition, so both hops through it pick it up
+        // fermion boundary condition (rows 0 and 1; the rebuilt row 2 takes it
+        // from the neighbour entry's sign bit), so both hops through it pick it up
         const double sg = (in && (e & kNbrSign)) ? -1.0 : 1.0;
         const double *u = U + (n * 4 + mu) * 18;
-        for (int k = 0; k < 9; k++) {
-            LT *o = blk + (((int64_t)mu * 9 + k) * S + s) * 2;
+        for (int k = 0; k < kLinkK; k++) {
+            LT *o = blk + (((int64_t)mu * kLinkK + k) * S + s) * 2;
             o[0] = in ? cvt_link<LT>(sg * u[2 * k]) : (LT)0;
             o[1] = in ? cvt_link<LT>(sg * u[2 * k + 1]) : (LT)0;
         }

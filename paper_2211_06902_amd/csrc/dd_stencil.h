@@ -64,28 +64,51 @@ __device__ __forceinline__ void bstore<double>(const Buf &b, double v, uint32_t 
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), b.r, (int)voff, (int)soff, 0);
 }
 
-// Link layout per block: element (site slot s, mu, complex entry k = 3*row + col, re/im)
-// at soff[b]*72 + ((mu*9 + k)*S_b + s)*2 + ri.  Consecutive slots are adjacent, so a
-// wavefront reading entry k of one direction for consecutive sites touches one line.
-// load_link: voff = byte offset of the slot's pair, soff = byte offset of entry 0
-// of direction mu, kstride = bytes between entries.
+// Link layout per block: element (site slot s, mu, complex entry k = 3*row + col
+// of rows 0 and 1, re/im) at soff[b]*48 + ((mu*6 + k)*S_b + s)*2 + ri.
+// Consecutive slots are adjacent, so a wavefront reading entry k of one
+// direction for consecutive sites touches one line.  load_link: voff = byte
+// offset of the slot's pair, soff = byte offset of entry 0 of direction mu,
+// kstride = bytes between entries; neg = the hop crosses the antiperiodic
+// time edge (rows 0 and 1 are stored with that sign already).
+
+// u[12..17] = s * conj(row0 x row1): row 2 of an SU(3) matrix, with the sign s
+// of the stored rows
+template <typename AC>
+__device__ __forceinline__ void rebuild_row2(AC (&u)[18], bool neg)
+{
+    const AC sg = neg ? (AC)-1 : (AC)1;
+#pragma unroll
+    for (int c = 0; c < 3; c++) {
+        const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+        // a_{c1} b_{c2} - a_{c2} b_{c1}, a = row 0, b = row 1
+        const AC ar1 = u[2 * c1], ai1 = u[2 * c1 + 1], ar2 = u[2 * c2], ai2 = u[2 * c2 + 1];
+        const AC br1 = u[6 + 2 * c1], bi1 = u[6 + 2 * c1 + 1], br2 = u[6 + 2 * c2], bi2 = u[6 + 2 * c2 + 1];
+        const AC re = (ar1 * br2 - ai1 * bi2) - (ar2 * br1 - ai2 * bi1);
+        const AC im = (ar1 * bi2 + ai1 * br2) - (ar2 * bi1 + ai2 * br1);
+        u[12 + 2 * c] = sg * re;
+        u[12 + 2 * c + 1] = -sg * im;
+    }
+}
+
 template <typename AC>
 __device__ __forceinline__ void load_link(const Buf &b, const double *, uint32_t voff, uint32_t soff,
-                                          uint32_t kstride, AC (&u)[18])
+                                          uint32_t kstride, AC (&u)[18], bool neg)
 {
 #pragma unroll
-    for (int k = 0; k < 9; k++) {
+    for (int k = 0; k < 6; k++) {
         const auto q = __builtin_amdgcn_raw_buffer_load_b128(b.r, (int)voff, (int)(soff + k * kstride), 0);
         u[2 * k] = (AC)__builtin_bit_cast(double, __builtin_shufflevector(q, q, 0, 1));
         u[2 * k + 1] = (AC)__builtin_bit_cast(double, __builtin_shufflevector(q, q, 2, 3));
     }
+    rebuild_row2(u, neg);
 }
 template <typename AC>
 __device__ __forceinline__ void load_link(const Buf &b, const float *, uint32_t voff, uint32_t soff, uint32_t kstride,
-                                          AC (&u)[18])
+                                          AC (&u)[18], bool neg)
 {
 #pragma unroll
-    for (int k = 0; k < 9; k++) {
+    for (int k = 0; k < 6; k++) {
         // take the 8 bytes as one integer: indexing the returned vector lets
         // the compiler shrink the load to its first dword
         const uint64_t q =
@@ -93,17 +116,19 @@ __device__ __forceinline__ void load_link(const Buf &b, const float *, uint32_t 
         u[2 * k] = (AC)__uint_as_float((uint32_t)q);
         u[2 * k + 1] = (AC)__uint_as_float((uint32_t)(q >> 32));
     }
+    rebuild_row2(u, neg);
 }
 template <typename AC>
 __device__ __forceinline__ void load_link(const Buf &b, const uint16_t *, uint32_t voff, uint32_t soff,
-                                          uint32_t kstride, AC (&u)[18])
+                                          uint32_t kstride, AC (&u)[18], bool neg)
 {
 #pragma unroll
-    for (int k = 0; k < 9; k++) {
+    for (int k = 0; k < 6; k++) {
         const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(b.r, (int)voff, (int)(soff + k * kstride), 0);
         u[2 * k] = (AC)bf16_to_f32(w & 0xffffu);
         u[2 * k + 1] = (AC)bf16_to_f32(w >> 16);
     }
+    rebuild_row2(u, neg);
 }
 
 // a * b + c in one rounding
@@ -304,7 +329,8 @@ __device__ __forceinline__ void hop_one(AC (&acc)[G][24], int32_t e, const SP *s
     const int idx = e & kNbrMask;
     AC u[18];
     const int slot = FWD ? hc.slot_self : hc.other0 + idx;
-    load_link(hc.lk_b, (const LK *)nullptr, (uint32_t)slot * 2 * (uint32_t)sizeof(LK), MU * 9 * hc.kstr, hc.kstr, u);
+    load_link(hc.lk_b, (const LK *)nullptr, (uint32_t)slot * 2 * (uint32_t)sizeof(LK), MU * 6 * hc.kstr, hc.kstr, u,
+              (e & kNbrSign) != 0);
     const int lidx = idx - hc.h0;
     if (LDS && (unsigned)lidx < (unsigned)hc.tv) {
         const SrcLds<SP, G> src{stage + lidx * G};

@@ -341,10 +341,11 @@ class Gauge:
         self.low = low
 
     def export(self, prec):
-        """Packed links of precision prec as a GPU tensor (float64, float32 or int16 bits)."""
+        """Packed links (rows 0 and 1 of each link) of precision prec as a GPU tensor (float64, float32 or
+        int16 bits)."""
         import torch
 
-        n = self.blocks.total_sites * 72
+        n = self.blocks.total_sites * 48
         dt = {F64: torch.float64, F32: torch.float32, BF16: torch.int16}[_PREC[prec]]
         out = torch.empty(n, dtype=dt, device="cuda")
         self._ctx._check(_lib.dd_gauge_export(self._ctx._h, self._h, _PREC[prec], _P(out.data_ptr())))

@@ -25,15 +25,16 @@ def _dev(a):
 
 
 def _expected_links(L, U, boxes, conv):
-    """Packed layout by definition: per block [mu][k][eo site][re, im]; zero where the hop leaves the box."""
+    """Packed layout by definition: per block [mu][k of rows 0 and 1][eo site][re, im]; zero where the hop
+    leaves the box."""
     out = []
-    Uf = U.view(np.float64).reshape(U.shape[0], 4, 9, 2)
+    Uf = U.view(np.float64).reshape(U.shape[0], 4, 9, 2)[:, :, :6]
     for bx in boxes:
         o, e = bx[:4], np.asarray(bx[4:8])
         perm, _ = geometry.box_eo_order(L, o, e)
         sites = geometry.box_sites(L, o, e)
         y = np.indices(tuple(e)).reshape(4, -1).T
-        blk = np.zeros((4, 9, perm.size, 2))
+        blk = np.zeros((4, 6, perm.size, 2))
         x0 = geometry.coords(L)[sites, 0]
         for mu in range(4):
             inside = (y[:, mu] + 1 < e[mu]) | (e[mu] == L[mu])
@@ -76,9 +77,8 @@ def _check_apply(ctx, L, kappa, eps, seed_u, seed_src, segs, shift, nrhs, sample
     errs = {}
     for low in ["f32", "bf16"]:
         g = ctx.load_gauge(blk, _dev(U), low)
-        Ubf = np.empty_like(U)
-        Ubf.real = precision.round_bf16(U.real)
-        Ubf.imag = precision.round_bf16(U.imag)
+        # BF16 links: rows 0 and 1 rounded, row 2 rebuilt from them (the stored format)
+        Ubf = precision.links_two_rows(U, precision.round_bf16)
         for prec in (["f64", "f32"] if low == "f32" else ["bf16"]):
             y = ctx.apply_D_block(blk, g, kappa, prec, _dev(x)).cpu().numpy()
             Uo = Ubf if prec == "bf16" else U
@@ -141,8 +141,9 @@ def test_hop_timer_accounts_bytes(ctx):
     ctx.timer_enable(False)
     assert n == 2 and ms > 0
     # two hops, each reading in + self and writing out (3 half fields), plus the block links
+    # (two stored rows: 12 reals per link)
     V = 8**4
-    expect = 2 * (4 * (V / 2) * 24 * 4 * 3 + blk.inner_links * 18 * 4)
+    expect = 2 * (4 * (V / 2) * 24 * 4 * 3 + blk.inner_links * 12 * 4)
     assert abs(nbytes - expect) < 1e-6 * expect
 
 
