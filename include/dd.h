@@ -246,7 +246,14 @@ dd_status dd_multiboson_action(dd_ctx *ctx, const dd_blocks *blocks, const dd_ga
  * Results do not depend on it beyond rounding of the fused dot products'
  * summation order, which is fixed for a given setting. */
 /* DD_TUNE_HOP_LDS: 1 (default) stages each hop tile's chunk of the input
- * field in LDS, 0 reads every neighbour from global memory. */
+ * field in LDS, 0 reads every neighbour from global memory.
+ * DD_TUNE_HOP_WALK: the x0-walk of the hop (a workgroup streams the x0-slices
+ * of a block for one rhs, reading each input slice once), used with one rhs
+ * per thread when every block admits it (no block spans the lattice in x0,
+ * at most 512 sites per x0-slice): 0 (default) automatic, -1 never, n >= 1
+ * with each block's slices split into n segments (clamped to what the block
+ * shapes allow).  Results do not depend on it beyond the summation order of
+ * the fused dot products. */
 /* Schedule of the persistent GMRES solver (0 = default):
  * DD_TUNE_GMRES_THREADS  threads per workgroup, 256 or 512;
  * DD_TUNE_GMRES_QUEUES   work queues, 1 (one global queue) or 8 (one per XCD:
@@ -268,7 +275,8 @@ enum {
     DD_TUNE_GMRES_QUEUES = 4,
     DD_TUNE_GMRES_WG_PER_CU = 5,
     DD_TUNE_MB_FIELDS = 6,
-    DD_TUNE_NN_KERNEL = 7
+    DD_TUNE_NN_KERNEL = 7,
+    DD_TUNE_HOP_WALK = 8
 };
 dd_status dd_tune_set(dd_ctx *ctx, int32_t what, int32_t value);
 

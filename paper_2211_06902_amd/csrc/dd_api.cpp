@@ -79,6 +79,46 @@ const TileTable *tiles_for(dd_ctx *ctx, dd_blocks *B, int nr, int g, hipError_t 
     return &(B->tiles[key] = tt);
 }
 
+// Tiles of the hop's x0-walk: nr * nseg per block, ordered block, segment,
+// rhs.  nseg is clamped to the smallest number of chunk tiles of a block, so
+// that every segment owns a chunk slot of the dot-product partials.
+const TileTable *walk_for(const dd_blocks *B, int nr, int nseg, int *nseg_used, hipError_t *err)
+{
+    *err = hipSuccess;
+    int cap = 1 << 20;
+    for (int b = 0; b < B->nb; b++) {
+        const Shape &sh = B->shapes[B->shape_of[b]];
+        const int T = sh.walk_hs * (kTile / sh.walk_hs);
+        cap = std::min(cap, (sh.h + T - 1) / T);
+    }
+    nseg = std::max(1, std::min(nseg, cap));
+    *nseg_used = nseg;
+    const int key = nr * 64 + nseg;
+    auto it = B->walks.find(key);
+    if (it != B->walks.end()) return &it->second;
+    TileTable tt;
+    tt.blk_tile0.assign(B->nb + 1, 0);
+    std::vector<int32_t> tb;
+    for (int b = 0; b < B->nb; b++) {
+        tt.blk_tile0[b + 1] = tt.blk_tile0[b] + nr * nseg;
+        for (int t = 0; t < nr * nseg; t++) tb.push_back(b);
+    }
+    tt.ntiles = tt.blk_tile0[B->nb];
+    if ((*err = upload(&tt.d_tile_block, tb)) != hipSuccess) return nullptr;
+    if ((*err = upload(&tt.d_blk_tile0, tt.blk_tile0)) != hipSuccess) return nullptr;
+    return &(B->walks[key] = tt);
+}
+
+// Segments per block of the hop's x0-walk: one, unless the (block, rhs)
+// walks alone would leave the device short of workgroups.
+int walk_segments(const dd_ctx *ctx, const dd_blocks *B, int nr)
+{
+    if (ctx->hop_walk > 0) return ctx->hop_walk;
+    const int64_t walks = (int64_t)B->nb * nr;
+    const int64_t want = 2048;
+    return (int)std::min<int64_t>(8, std::max<int64_t>(1, (want + walks - 1) / walks));
+}
+
 // Right-hand sides per thread for a spinor precision (the largest power of
 // two up to the default below that divides n_rhs).  A context override
 // (dd_tune_set) takes precedence when it divides n_rhs.
@@ -147,6 +187,19 @@ hipError_t run_hop(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const Hop
     const bool aux = ha.aux && (ha.dot_mode == kDotAuxOut || ha.dot_mode == kDotOutAuxOutOut);
     const int extra = (ha.self != nullptr) + (ha.add != nullptr) + (aux ? 1 : 0);
     TimedLaunch tl(ctx, DD_KCLASS_HOP_F64 + (int)prec, hop_bytes(B, ba.n_rhs, prec, extra));
+    if (ha.use_lds && ba.g == 1 && B->walk && ctx->hop_walk >= 0) {
+        hipError_t err;
+        int nseg = 1;
+        const TileTable *wt = walk_for(B, ba.n_rhs, walk_segments(ctx, B, ba.n_rhs), &nseg, &err);
+        if (!wt) return err;
+        WalkArgs wa;
+        wa.tile_block = wt->d_tile_block;
+        wa.blk_tile0 = wt->d_blk_tile0;
+        wa.ext = B->d_ext;
+        wa.ntiles = wt->ntiles;
+        wa.nseg = nseg;
+        return launch_hop_walk(ba, wa, ha, prec, ctx->stream);
+    }
     return launch_hop(ba, ha, prec, ctx->stream);
 }
 
@@ -381,6 +434,10 @@ dd_status dd_free_blocks(dd_blocks *B)
         if (kv.second.d_blk_tile0) hipFree(kv.second.d_blk_tile0);
         if (kv.second.d_chunk) hipFree(kv.second.d_chunk);
     }
+    for (auto &kv : B->walks) {
+        if (kv.second.d_tile_block) hipFree(kv.second.d_tile_block);
+        if (kv.second.d_blk_tile0) hipFree(kv.second.d_blk_tile0);
+    }
     for (auto &kv : B->queues) {
         if (kv.second.d_queue) hipFree(kv.second.d_queue);
         if (kv.second.d_qoff) hipFree(kv.second.d_qoff);
@@ -530,6 +587,11 @@ dd_status dd_tune_set(dd_ctx *ctx, int32_t what, int32_t value)
     if (!ctx) return DD_EINVAL;
     if (what == DD_TUNE_HOP_LDS) {
         ctx->hop_lds = value != 0;
+        return DD_OK;
+    }
+    if (what == DD_TUNE_HOP_WALK) {
+        if (value < -1 || value > 64) return fail(ctx, DD_EINVAL, "hop walk must be -1 (off), 0 (automatic) or 1..64 segments");
+        ctx->hop_walk = value;
         return DD_OK;
     }
     if (what == DD_TUNE_GMRES_THREADS) {

@@ -40,6 +40,26 @@ inline void lcoords(const int e[4], int s, int y[4])
     y[0] = s;
 }
 
+// Sites per parity of an x0-slice if the hop's x0-walk applies to the shape,
+// else 0: checked on the finished table, entry by entry.  A slice holds
+// e1*e2*e3 (even) sites, half of each parity, and the eo order inside a slice
+// is the canonical one, so away from the slice ends the x0-neighbour of eo
+// site h sits at h +/- hs of the other parity.
+int walk_slice(const Shape &sh, const int32_t *tab)
+{
+    const int hs = sh.e[1] * sh.e[2] * sh.e[3] / 2;
+    if (sh.full[0] || hs > kTile || hs * sh.e[0] != sh.h) return 0;
+    for (int slot = 0; slot < sh.S; slot++) {
+        const int h = slot % sh.h, q = h / hs;
+        const int32_t *t = tab + (size_t)slot * 8;
+        const int32_t up = q + 1 < sh.e[0] ? h + hs : -1, dn = q > 0 ? h - hs : -1;
+        if ((t[0] < 0 ? -1 : (t[0] & kNbrMask)) != up || (t[1] < 0 ? -1 : (t[1] & kNbrMask)) != dn) return 0;
+        for (int k = 2; k < 8; k++)
+            if (t[k] >= 0 && (t[k] & kNbrMask) / hs != q) return 0;
+    }
+    return hs;
+}
+
 // Build the permutation and neighbour table of one shape; returns links kept.
 int64_t build_shape(Shape &sh, int tbc, std::vector<int32_t> &perm, std::vector<int32_t> &nbr)
 {
@@ -97,6 +117,7 @@ int64_t build_shape(Shape &sh, int tbc, std::vector<int32_t> &perm, std::vector<
             }
         }
     }
+    sh.walk_hs = walk_slice(sh, tab);
     return links;
 }
 
@@ -183,6 +204,8 @@ std::string build_geometry(dd_blocks *B, const int L[4], int tbc, int n, const i
         }
         B->boff[k + 1] = (int64_t)B->bnd.size();
     }
+    B->walk = n > 0;
+    for (const Shape &sh : B->shapes) B->walk = B->walk && sh.walk_hs > 0;
     return "";
 }
 

@@ -50,6 +50,7 @@ struct dd_ctx {
     dd::Timer timers[DD_KCLASS_COUNT];
     int rhs_group[2] = {0, 0};  // forced rhs per thread for FP64 / FP32 spinors (0 = automatic)
     bool hop_lds = true;        // stage the hop's chunk of the input in LDS
+    int hop_walk = 0;           // x0-walk of the hop: 0 automatic, -1 off, n >= 1 segments per block
     int gm_threads = 0;         // persistent GMRES: threads per workgroup (0 = default)
     int gm_queues = 0;          // persistent GMRES: work queues, 1 or 8 (0 = default)
     int gm_wg_per_cu = 0;       // persistent GMRES: resident workgroups per CU (0 = all that fit)
@@ -70,6 +71,11 @@ struct Shape {
     int64_t links;     // links with both ends in the block (the hops D_Lambda keeps)
     int64_t nbr_off;   // offset (entries) of this shape's table in the neighbour array
     int64_t perm_off;  // offset of the eo -> local canonical permutation
+    // Sites per parity of an x0-slice when the x0-walk of the hop applies to
+    // the shape (the eo index of a site's x0-neighbour is its own index
+    // +/- walk_hs in the other parity, hops along 1..3 stay in the slice, and
+    // the x0 hops out of the first and last slices are dropped), else 0.
+    int walk_hs = 0;
 };
 
 // Tile decomposition of the site kernels: a tile is one rhs group (g
@@ -126,6 +132,8 @@ struct dd_blocks {
     int64_t *d_boff = nullptr;      // [nb+1]
     std::map<int, dd::TileTable> tiles;  // keyed by (n_rhs, rhs per thread)
     std::map<int, dd::QueueTable> queues;  // keyed by (n_rhs, number of queues)
+    bool walk = false;                     // every shape admits the x0-walk of the hop
+    mutable std::map<int, dd::TileTable> walks;  // x0-walk tiles (a cache), keyed by (n_rhs, segments)
 };
 
 struct dd_gauge {
@@ -155,6 +163,16 @@ struct BlkArgs {
     int nb;  // number of blocks (pair = rhs * nb + block)
     int g;                 // right-hand sides per thread (1, 2 or 4; divides n_rhs)
     const int32_t *chunk;  // sites per chunk of each block
+};
+
+// Tiles of the x0-walk of the hop: tile (block, segment, rhs), rhs fastest,
+// walks the x0-slices of one of nseg equal segments of its block for one rhs.
+struct WalkArgs {
+    const int32_t *tile_block;
+    const int32_t *blk_tile0;
+    const int32_t *ext;  // [nb][4] block extents
+    int ntiles;
+    int nseg;
 };
 
 enum DotMode { kDotNone = 0, kDotAuxOut = 1, kDotOutSelfOutOut = 2, kDotOutOut = 3, kDotOutAuxOutOut = 4 };
@@ -290,6 +308,7 @@ hipError_t launch_pack_spinor(const dd_blocks *B, const double *src, void *even,
 hipError_t launch_unpack_spinor(const dd_blocks *B, const void *even, const void *odd, double *dst,
                                 dd_prec prec, int n_rhs, hipStream_t s);
 hipError_t launch_hop(const BlkArgs &ba, const HopArgs &ha, dd_prec prec, hipStream_t s);
+hipError_t launch_hop_walk(const BlkArgs &ba, const WalkArgs &wa, const HopArgs &ha, dd_prec prec, hipStream_t s);
 hipError_t launch_convert(const void *src, dd_prec sp, void *dst, dd_prec dp, int64_t n,
                           hipStream_t s);
 hipError_t launch_accum(const BlkArgs &ba, double *x, const void *e, dd_prec ep,

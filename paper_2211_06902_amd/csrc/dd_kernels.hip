@@ -88,6 +88,92 @@ __device__ __forceinline__ void tile_sum(double (*red)[kTile], const double (&dv
 // ------------------------------------------------------------- hop
 
 
+// Output operands of the hop epilogue, as block-relative buffer descriptors;
+// an absent operand gets a zero-size descriptor (its loads return 0).
+struct EpiBufs {
+    Buf out_b, self_b, add_b, aux_b;
+    bool has_self, has_add;
+};
+
+template <typename SP>
+__device__ __forceinline__ EpiBufs epi_bufs(const HopArgs &ha, int64_t hbase, uint32_t fbytes)
+{
+    EpiBufs eb;
+    eb.out_b = make_buf(reinterpret_cast<const SP *>(ha.out) + hbase, fbytes);
+    eb.self_b = make_buf(ha.self ? reinterpret_cast<const SP *>(ha.self) + hbase : nullptr, ha.self ? fbytes : 0);
+    eb.add_b = make_buf(ha.add ? reinterpret_cast<const SP *>(ha.add) + hbase : nullptr, ha.add ? fbytes : 0);
+    const bool need_aux = ha.dot_mode == kDotAuxOut || ha.dot_mode == kDotOutAuxOutOut;
+    eb.aux_b = make_buf(need_aux ? reinterpret_cast<const SP *>(ha.aux) + hbase : nullptr, need_aux ? fbytes : 0);
+    eb.has_self = ha.self != nullptr;
+    eb.has_add = ha.add != nullptr;
+    return eb;
+}
+
+// out = c_hop*acc + c_self*self + c_add*add at one site and rhs (my: byte
+// offset of its component 0, cstr: bytes between components), and the fused
+// dot products of the mode added to dv.  Two halves of 12 reals: all operand
+// loads of a half are issued before its stores (a store to `out` could alias
+// them, which would otherwise serialise every load behind the previous
+// store).  Fully unrolled: acc is indexed by the component, and a runtime
+// index would put it in scratch.
+// DM: the dot mode, or -1 to take it from ha at run time; PARTS: the
+// batches of loads (more batches, fewer registers).
+template <typename SP, typename AC, int DM, int PARTS = 2>
+__device__ __forceinline__ void hop_epilogue(const AC (&acc)[24], double (&dv)[kNRed], const HopArgs &ha,
+                                             const EpiBufs &eb, uint32_t my, uint32_t cstr)
+{
+    const int mode = DM >= 0 ? DM : ha.dot_mode;
+    const AC ch = (AC)ha.c_hop, cself = (AC)ha.c_self, cadd = (AC)ha.c_add;
+    constexpr int NQ = 24 / PARTS;
+#pragma unroll
+    for (int half = 0; half < PARTS; half++) {
+        SP sx[NQ], dx[NQ], ax[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; q++) {
+            const uint32_t so = (uint32_t)(NQ * half + q) * cstr;
+            sx[q] = bload<SP>(eb.self_b, my, so);
+            dx[q] = bload<SP>(eb.add_b, my, so);
+            ax[q] = bload<SP>(eb.aux_b, my, so);
+        }
+#pragma unroll
+        for (int k = 0; k < NQ / 2; k++) {
+            double o[2], sv[2], av[2];
+#pragma unroll
+            for (int ri = 0; ri < 2; ri++) {
+                const int q = 2 * k + ri;
+                const uint32_t so = (uint32_t)(NQ * half + q) * cstr;
+                AC v = ch * acc[NQ * half + q];
+                if (eb.has_self) v = fmad(cself, (AC)sx[q], v);
+                if (eb.has_add) v = fmad(cadd, (AC)dx[q], v);
+                const SP ov = (SP)v;
+                bstore<SP>(eb.out_b, ov, my, so);
+                o[ri] = (double)ov;
+                sv[ri] = (double)sx[q];
+                av[ri] = (double)ax[q];
+            }
+            if (mode == kDotAuxOut) {
+                dv[0] += av[0] * o[0] + av[1] * o[1];
+                dv[1] += av[0] * o[1] - av[1] * o[0];
+            } else if (mode == kDotOutSelfOutOut) {
+                dv[0] += o[0] * sv[0] + o[1] * sv[1];
+                dv[1] += o[0] * sv[1] - o[1] * sv[0];
+                dv[2] += o[0] * o[0] + o[1] * o[1];
+            } else if (mode == kDotOutAuxOutOut) {
+                dv[0] += o[0] * av[0] + o[1] * av[1];
+                dv[1] += o[0] * av[1] - o[1] * av[0];
+                dv[2] += o[0] * o[0] + o[1] * o[1];
+            } else if (mode == kDotOutOut) {
+                dv[0] += o[0] * o[0] + o[1] * o[1];
+            }
+        }
+    }
+}
+
+__host__ __device__ constexpr int dot_nred(int mode)
+{
+    return mode == kDotAuxOut ? 2 : (mode == kDotOutSelfOutOut || mode == kDotOutAuxOutOut ? 3 : (mode == kDotOutOut ? 1 : 0));
+}
+
 // out = c_add*add + c_self*self + c_hop * (H in) on the sites of one parity,
 // `in` on the other parity.  The tile first copies its chunk of `in` (its rhs
 // group) into LDS; hops that land inside the chunk read LDS, the others
@@ -153,67 +239,12 @@ __global__ void __launch_bounds__(kTile) k_hop(BlkArgs ba, HopArgs ha)
         hop_one<3, true, SP, LK, AC, G>(acc, nb[6], stage, hc);
         hop_one<3, false, SP, LK, AC, G>(acc, nb[7], stage, hc);
 
-        const Buf out_b = make_buf(reinterpret_cast<const SP *>(ha.out) + hbase, fbytes);
-        const Buf self_b = make_buf(ha.self ? reinterpret_cast<const SP *>(ha.self) + hbase : nullptr, ha.self ? fbytes : 0);
-        const Buf add_b = make_buf(ha.add ? reinterpret_cast<const SP *>(ha.add) + hbase : nullptr, ha.add ? fbytes : 0);
-        const bool need_aux = ha.dot_mode == kDotAuxOut || ha.dot_mode == kDotOutAuxOutOut;
-        const Buf aux_b = make_buf(need_aux ? reinterpret_cast<const SP *>(ha.aux) + hbase : nullptr, need_aux ? fbytes : 0);
-        const bool has_self = ha.self != nullptr, has_add = ha.add != nullptr;
-        const AC ch = (AC)ha.c_hop, cself = (AC)ha.c_self, cadd = (AC)ha.c_add;
-        // Two halves of 12 reals: all operand loads of a half are issued before its
-        // stores (a store to `out` could alias them, which would otherwise serialise
-        // every load behind the previous store).  An absent operand has a zero-size
-        // descriptor: its loads return 0 without touching memory, so no branch
-        // splits the batch.  Fully unrolled: acc is indexed by the component, and a
-        // runtime index would put it in scratch.
+        const EpiBufs eb = epi_bufs<SP>(ha, hbase, fbytes);
 #pragma unroll
-        for (int j = 0; j < G; j++)
-#pragma unroll
-            for (int half = 0; half < 2; half++) {
-                SP sx[12], dx[12], ax[12];
-#pragma unroll
-                for (int q = 0; q < 12; q++) {
-                    const uint32_t so = (uint32_t)(j * 24 + 12 * half + q) * hc.cstr;
-                    sx[q] = bload<SP>(self_b, my, so);
-                    dx[q] = bload<SP>(add_b, my, so);
-                    ax[q] = bload<SP>(aux_b, my, so);
-                }
-#pragma unroll
-                for (int k = 0; k < 6; k++) {
-                    double o[2], sv[2], av[2];
-#pragma unroll
-                    for (int ri = 0; ri < 2; ri++) {
-                        const int q = 2 * k + ri;
-                        const uint32_t so = (uint32_t)(j * 24 + 12 * half + q) * hc.cstr;
-                        AC v = ch * acc[j][12 * half + q];
-                        if (has_self) v = fmad(cself, (AC)sx[q], v);
-                        if (has_add) v = fmad(cadd, (AC)dx[q], v);
-                        const SP ov = (SP)v;
-                        bstore<SP>(out_b, ov, my, so);
-                        o[ri] = (double)ov;
-                        sv[ri] = (double)sx[q];
-                        av[ri] = (double)ax[q];
-                    }
-                    if (ha.dot_mode == kDotAuxOut) {
-                        dv[j][0] += av[0] * o[0] + av[1] * o[1];
-                        dv[j][1] += av[0] * o[1] - av[1] * o[0];
-                    } else if (ha.dot_mode == kDotOutSelfOutOut) {
-                        dv[j][0] += o[0] * sv[0] + o[1] * sv[1];
-                        dv[j][1] += o[0] * sv[1] - o[1] * sv[0];
-                        dv[j][2] += o[0] * o[0] + o[1] * o[1];
-                    } else if (ha.dot_mode == kDotOutAuxOutOut) {
-                        dv[j][0] += o[0] * av[0] + o[1] * av[1];
-                        dv[j][1] += o[0] * av[1] - o[1] * av[0];
-                        dv[j][2] += o[0] * o[0] + o[1] * o[1];
-                    } else if (ha.dot_mode == kDotOutOut) {
-                        dv[j][0] += o[0] * o[0] + o[1] * o[1];
-                    }
-                }
-            }
+        for (int j = 0; j < G; j++) hop_epilogue<SP, AC, -1>(acc[j], dv[j], ha, eb, my + (uint32_t)(j * 24) * hc.cstr, hc.cstr);
     }
     if (ha.dot_mode != kDotNone) {
-        const int nred = ha.dot_mode == kDotAuxOut ? 2 : (ha.dot_mode == kDotOutSelfOutOut || ha.dot_mode == kDotOutAuxOutOut ? 3 : 1);
-        tile_sum<G>(red, dv, nred, ha.partial, t.tile);
+        tile_sum<G>(red, dv, dot_nred(ha.dot_mode), ha.partial, t.tile);
     }
 }
 
@@ -231,6 +262,180 @@ hipError_t launch_hop(const BlkArgs &ba, const HopArgs &ha, dd_prec prec, hipStr
         hipLaunchKernelGGL((k_hop<float, uint16_t, float, 1>), g, t, 0, s, ba, ha);
     else if (prec == DD_BF16 && ba.g == 2)
         hipLaunchKernelGGL((k_hop<float, uint16_t, float, 2>), g, t, 0, s, ba, ha);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// x0-walk of the hop.  A tile of kTile threads walks the x0-slices of one
+// block segment for one rhs; thread k owns eo site k of every slice (hs sites
+// per parity and slice).  The eo order makes the x0-neighbour of a site the
+// same position k of the adjacent slice of the other parity, so each input
+// slice is read from global memory once: staged in LDS, it feeds the hops
+// along 1..3 of its own output slice (neighbours inside the slice) and the x0
+// hops of the two adjacent output slices at position k.  One accumulator
+// rides along: it holds output slice q-1 until its x0+ hop arrives with input
+// slice q, and the x0- hop of output slice q+1, computed from input slice q,
+// waits as its 12-real upper half.
+
+#ifndef DD_WALK_PARTS
+#define DD_WALK_PARTS 2
+#endif
+constexpr int kWalkParts = DD_WALK_PARTS;
+#ifndef DD_WALK_ATTR
+#define DD_WALK_ATTR
+#endif
+#ifndef DD_WALK_BF
+#define DD_WALK_BF 0
+#endif
+constexpr bool kWalkBF = DD_WALK_BF != 0;
+
+template <typename SP>
+__device__ __forceinline__ void walk_stage(SP *stage, const HopCtx &hc, int q, int hs, int k, bool live)
+{
+    if (!live) return;
+    const uint32_t vo = (uint32_t)(hc.grp_off + q * hs + k) * (uint32_t)sizeof(SP);
+    SP v[24];
+#pragma unroll
+    for (int c = 0; c < 24; c++) v[c] = bload<SP>(hc.in_b, vo, (uint32_t)c * hc.cstr);
+#pragma unroll
+    for (int c = 0; c < 24; c++) stage[c * kTile + k] = v[c];
+}
+
+struct WalkPos {
+    int p, hb, hs, k, s0, s1;
+    const int32_t *nbt;  // neighbour table of the output parity
+};
+
+// Input slice q is in LDS.  acc holds output slice q-1: it is finished and
+// written when it belongs to the segment, then restarted as output slice q
+// (carry: the upper half of its x0- hop) with the hops along 1..3; carry
+// becomes the x0- half of output slice q+1.
+template <typename SP, typename LK, typename AC, int DM>
+__device__ __forceinline__ void walk_step(AC (&acc)[1][24], AC (&carry)[1][12], double (&dv)[1][kNRed], int q,
+                                          const WalkPos &w, const SP *stage, const HopCtx &hc, const HopArgs &ha,
+                                          const EpiBufs &eb)
+{
+    if (q - 1 >= w.s0) {
+        const int h = (q - 1) * w.hs + w.k;
+        hop_at<0, true, SP, LK, AC, 1, kWalkBF>(acc, w.nbt[h * 8], stage, w.k, w.p * w.hb + h, w.k, hc);
+        hop_epilogue<SP, AC, DM, kWalkParts>(acc[0], dv[0], ha, eb, (uint32_t)(hc.grp_off + h) * (uint32_t)sizeof(SP), hc.cstr);
+    }
+    if (q >= w.s0 && q < w.s1) {
+#pragma unroll
+        for (int c = 0; c < 24; c++) acc[0][c] = 0;
+        hop_expand<0, false, AC>(acc[0], carry[0]);
+        const int h = q * w.hs + w.k, base = q * w.hs, oth = (1 - w.p) * w.hb, own = w.p * w.hb + h;
+        const int4 *t4 = reinterpret_cast<const int4 *>(w.nbt + h * 8);
+        const int4 a0 = t4[0], a1 = t4[1];
+        const int32_t nb[6] = {a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+        int li[6];
+#pragma unroll
+        for (int i = 0; i < 6; i++) li[i] = (nb[i] & kNbrMask) - base;
+        hop_at<1, true, SP, LK, AC, 1, kWalkBF>(acc, nb[0], stage, li[0], own, w.k, hc);
+        hop_at<1, false, SP, LK, AC, 1, kWalkBF>(acc, nb[1], stage, li[1], oth + base + li[1], w.k, hc);
+        hop_at<2, true, SP, LK, AC, 1, kWalkBF>(acc, nb[2], stage, li[2], own, w.k, hc);
+        hop_at<2, false, SP, LK, AC, 1, kWalkBF>(acc, nb[3], stage, li[3], oth + base + li[3], w.k, hc);
+        hop_at<3, true, SP, LK, AC, 1, kWalkBF>(acc, nb[4], stage, li[4], own, w.k, hc);
+        hop_at<3, false, SP, LK, AC, 1, kWalkBF>(acc, nb[5], stage, li[5], oth + base + li[5], w.k, hc);
+    }
+    if (q + 1 < w.s1) {
+        const int h = (q + 1) * w.hs + w.k;
+        hop_half_at<0, false, SP, LK, AC, 1, kWalkBF>(carry, w.nbt[h * 8 + 1], stage, w.k,
+                                                     (1 - w.p) * w.hb + q * w.hs + w.k, w.k, hc);
+    }
+}
+
+template <typename SP, typename LK, typename AC, int DM>
+__global__ void __launch_bounds__(kTile) DD_WALK_ATTR k_hop_walk(BlkArgs ba, WalkArgs wa, HopArgs ha)
+{
+    __shared__ SP stage[24 * kTile];
+    __shared__ double red[1][kTile];
+    const int tile = uni(xcd_tile(blockIdx.x, wa.ntiles));
+    const int b = uni(wa.tile_block[tile]);
+    const int nr = ba.n_rhs;
+    const int rel = tile - uni(wa.blk_tile0[b]);
+    const int r = rel % nr, seg = rel / nr;
+    WalkPos w;
+    w.p = ha.parity;
+    w.hb = uni(ba.h[b]);
+    const int ns = uni(wa.ext[4 * b]);  // x0-slices of the block
+    w.hs = w.hb / ns;
+    w.k = threadIdx.x;
+    w.s0 = seg * ns / wa.nseg;
+    w.s1 = (seg + 1) * ns / wa.nseg;
+    const int qa = max(w.s0 - 1, 0), qb = min(w.s1 + 1, ns);
+    const bool live = w.k < w.hs;
+    const int64_t soff = uni64(ba.soff[b]);
+    const int64_t hbase = (soff >> 1) * 24 * nr;
+    const uint32_t fbytes = (uint32_t)(nr * 24 * w.hb) * (uint32_t)sizeof(SP);
+    HopCtx hc;
+    hc.h0 = 0;
+    hc.tv = 0;
+    hc.slot_self = 0;
+    hc.other0 = 0;
+    hc.cstr = (uint32_t)w.hb * (uint32_t)sizeof(SP);
+    hc.kstr = (uint32_t)(4 * w.hb) * (uint32_t)sizeof(LK);
+    hc.grp_off = r * 24 * w.hb;
+    hc.in_b = make_buf(reinterpret_cast<const SP *>(ha.in) + hbase, fbytes);
+    hc.lk_b = make_buf(reinterpret_cast<const LK *>(ha.links) + soff * kLinkReals,
+                       (uint32_t)(2 * w.hb * kLinkReals) * (uint32_t)sizeof(LK));
+    const EpiBufs eb = epi_bufs<SP>(ha, hbase, fbytes);
+    w.nbt = ba.nbr + uni64(ba.nbr_off[b]) + (int64_t)w.p * w.hb * 8;
+    AC acc[1][24], carry[1][12];
+    double dv[1][kNRed];
+#pragma unroll
+    for (int c = 0; c < 24; c++) acc[0][c] = 0;
+#pragma unroll
+    for (int c = 0; c < 12; c++) carry[0][c] = 0;
+#pragma unroll
+    for (int i = 0; i < kNRed; i++) dv[0][i] = 0;
+    for (int q = qa; q < qb; q++) {
+        walk_stage(stage, hc, q, w.hs, w.k, live);
+        __syncthreads();
+        if (live) walk_step<SP, LK, AC, DM>(acc, carry, dv, q, w, stage, hc, ha, eb);
+        __syncthreads();
+    }
+    // The block's last slice has no x0+ neighbour: when the segment ends
+    // there, its output is finished here.
+    if (live && qb == w.s1)
+        hop_epilogue<SP, AC, DM, kWalkParts>(acc[0], dv[0], ha, eb,
+                                 (uint32_t)(hc.grp_off + (w.s1 - 1) * w.hs + w.k) * (uint32_t)sizeof(SP), hc.cstr);
+    if (DM != kDotNone) {
+        // partial sums in the chunk tiles' slots: segment seg in chunk slot seg,
+        // the block's remaining chunk slots zero
+        constexpr int nred = dot_nred(DM);
+        const int t0 = uni(ba.blk_tile0[b]), nch = (uni(ba.blk_tile0[b + 1]) - t0) / nr;
+        tile_sum<1>(red, dv, nred, ha.partial, t0 + seg * nr + r);
+        if (seg == 0)
+            for (int i = threadIdx.x; i < (nch - wa.nseg) * nred; i += kTile)
+                ha.partial[(int64_t)(t0 + (wa.nseg + i / nred) * nr + r) * kNRed + i % nred] = 0;
+    }
+}
+
+template <typename SP, typename LK, typename AC>
+static void launch_walk_t(const BlkArgs &ba, const WalkArgs &wa, const HopArgs &ha, hipStream_t s)
+{
+    dim3 g(wa.ntiles), t(kTile);
+    switch (ha.dot_mode) {
+    case kDotNone: hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, kDotNone>), g, t, 0, s, ba, wa, ha); break;
+    case kDotAuxOut: hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, kDotAuxOut>), g, t, 0, s, ba, wa, ha); break;
+    case kDotOutSelfOutOut: hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, kDotOutSelfOutOut>), g, t, 0, s, ba, wa, ha); break;
+    case kDotOutOut: hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, kDotOutOut>), g, t, 0, s, ba, wa, ha); break;
+    default: hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, kDotOutAuxOutOut>), g, t, 0, s, ba, wa, ha); break;
+    }
+}
+
+hipError_t launch_hop_walk(const BlkArgs &ba, const WalkArgs &wa, const HopArgs &ha, dd_prec prec, hipStream_t s)
+{
+    if (wa.ntiles <= 0) return hipSuccess;
+    if (ba.g != 1 || wa.nseg < 1 || ha.dot_mode < kDotNone || ha.dot_mode > kDotOutAuxOutOut) return hipErrorInvalidValue;
+    if (prec == DD_F64)
+        launch_walk_t<double, double, double>(ba, wa, ha, s);
+    else if (prec == DD_F32)
+        launch_walk_t<float, float, float>(ba, wa, ha, s);
+    else if (prec == DD_BF16)
+        launch_walk_t<float, uint16_t, float>(ba, wa, ha, s);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

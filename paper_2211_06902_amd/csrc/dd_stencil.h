@@ -232,12 +232,12 @@ struct SrcLds {
     __device__ __forceinline__ void load(int comp, SP (&v)[G]) const { ldv<SP, G>(p + comp * kTile * G, v); }
 };
 
-// acc[j] += (1 -/+ gamma_mu) W psi_j for the G rhs: project to the half
-// spinor h (2 spins x 3 colours), multiply by W = U (forward) or U^+
-// (backward), then rebuild the lower spin components from the upper ones.
-// The antiperiodic time sign is part of the stored link.
+// The upper half of the projected hop (1 -/+ gamma_mu) W psi_j for the G rhs:
+// project the neighbour's spinor to the half spinor h (2 spins x 3 colours)
+// and multiply by W = U (forward) or U^+ (backward); w[j][2*(3*s + a) + ri].
+// The antiperiodic time sign is part of the link.
 template <int MU, bool FWD, typename SP, typename AC, int G, typename SRC>
-__device__ __forceinline__ void hop_term(AC (&acc)[G][24], const SRC &src, const AC (&u)[18])
+__device__ __forceinline__ void hop_half(AC (&w)[G][12], const SRC &src, const AC (&u)[18])
 {
     using P = Proj<MU, FWD>;
     AC h[G][2][3][2];
@@ -261,9 +261,8 @@ __device__ __forceinline__ void hop_term(AC (&acc)[G][24], const SRC &src, const
     }
 #pragma unroll
     for (int j = 0; j < G; j++) {
-        // W = U h (or U^+ h) as explicit fused multiply-add chains: one
-        // multiply and five FMAs per real component
-        AC w[2][3][2];
+        // explicit fused multiply-add chains: one multiply and five FMAs per
+        // real component
 #pragma unroll
         for (int s = 0; s < 2; s++)
 #pragma unroll
@@ -290,24 +289,42 @@ __device__ __forceinline__ void hop_term(AC (&acc)[G][24], const SRC &src, const
                     re = fmad(-ui, hi, re);
                     im = fmad(ui, hr, im);
                 }
-                w[s][a][0] = re;
-                w[s][a][1] = im;
+                w[j][2 * (3 * s + a)] = re;
+                w[j][2 * (3 * s + a) + 1] = im;
             }
-#pragma unroll
-        for (int a = 0; a < 3; a++) {
-            acc[j][2 * a] += w[0][a][0];
-            acc[j][2 * a + 1] += w[0][a][1];
-            acc[j][2 * (3 + a)] += w[1][a][0];
-            acc[j][2 * (3 + a) + 1] += w[1][a][1];
-            AC re, im;
-            cmul_code<P::b0>(w[P::s0][a][0], w[P::s0][a][1], re, im);
-            acc[j][2 * (6 + a)] += re;
-            acc[j][2 * (6 + a) + 1] += im;
-            cmul_code<P::b1>(w[P::s1][a][0], w[P::s1][a][1], re, im);
-            acc[j][2 * (9 + a)] += re;
-            acc[j][2 * (9 + a) + 1] += im;
-        }
     }
+}
+
+// acc += the full spinor of a hop from its upper half w: (W_0, W_1, b_0
+// W_{sig_0}, b_1 W_{sig_1}).
+template <int MU, bool FWD, typename AC>
+__device__ __forceinline__ void hop_expand(AC (&acc)[24], const AC (&w)[12])
+{
+    using P = Proj<MU, FWD>;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        acc[2 * a] += w[2 * a];
+        acc[2 * a + 1] += w[2 * a + 1];
+        acc[2 * (3 + a)] += w[2 * (3 + a)];
+        acc[2 * (3 + a) + 1] += w[2 * (3 + a) + 1];
+        AC re, im;
+        cmul_code<P::b0>(w[2 * (3 * P::s0 + a)], w[2 * (3 * P::s0 + a) + 1], re, im);
+        acc[2 * (6 + a)] += re;
+        acc[2 * (6 + a) + 1] += im;
+        cmul_code<P::b1>(w[2 * (3 * P::s1 + a)], w[2 * (3 * P::s1 + a) + 1], re, im);
+        acc[2 * (9 + a)] += re;
+        acc[2 * (9 + a) + 1] += im;
+    }
+}
+
+// acc[j] += (1 -/+ gamma_mu) W psi_j for the G rhs.
+template <int MU, bool FWD, typename SP, typename AC, int G, typename SRC>
+__device__ __forceinline__ void hop_term(AC (&acc)[G][24], const SRC &src, const AC (&u)[18])
+{
+    AC w[G][12];
+    hop_half<MU, FWD, SP, AC, G>(w, src, u);
+#pragma unroll
+    for (int j = 0; j < G; j++) hop_expand<MU, FWD, AC>(acc[j], w[j]);
 }
 
 struct HopCtx {
@@ -339,6 +356,50 @@ __device__ __forceinline__ void hop_one(AC (&acc)[G][24], int32_t e, const SP *s
         const SrcGlobal<SP, G> src{hc.in_b, (uint32_t)(hc.grp_off + idx) * (uint32_t)sizeof(SP), hc.cstr};
         hop_term<MU, FWD, SP, AC, G>(acc, src, u);
     }
+}
+
+// Adds the hop along MU (forward or backward) with the neighbour's spinor at
+// LDS position lidx of `stage` and the link at `slot` (the site's own slot
+// forward, the neighbour's backward), when the entry e is not dropped.
+// BF: without a branch; a dropped hop then reads position `own` of the
+// stage and a link offset beyond the buffer, whose loads return 0, so it
+// adds U = 0 times a finite spinor.
+template <int MU, bool FWD, typename SP, typename LK, typename AC, int G, bool BF = false>
+__device__ __forceinline__ void hop_at(AC (&acc)[G][24], int32_t e, const SP *stage, int lidx, int slot, int own,
+                                       const HopCtx &hc)
+{
+    if constexpr (!BF) {
+        if (e < 0) return;
+    }
+    const bool drop = BF && e < 0;
+    AC u[18];
+    load_link(hc.lk_b, (const LK *)nullptr, drop ? 0x80000000u : (uint32_t)slot * 2 * (uint32_t)sizeof(LK),
+              MU * 6 * hc.kstr, hc.kstr, u, (e & kNbrSign) != 0);
+    const SrcLds<SP, G> src{stage + (drop ? own : lidx) * G};
+    hop_term<MU, FWD, SP, AC, G>(acc, src, u);
+}
+
+// The upper half (hop_half) of the hop along MU with the neighbour's spinor
+// at LDS position lidx and the link at `slot`; zero when e is dropped.
+template <int MU, bool FWD, typename SP, typename LK, typename AC, int G, bool BF = false>
+__device__ __forceinline__ void hop_half_at(AC (&w)[G][12], int32_t e, const SP *stage, int lidx, int slot, int own,
+                                            const HopCtx &hc)
+{
+    if constexpr (!BF) {
+        if (e < 0) {
+#pragma unroll
+            for (int j = 0; j < G; j++)
+#pragma unroll
+                for (int i = 0; i < 12; i++) w[j][i] = 0;
+            return;
+        }
+    }
+    const bool drop = BF && e < 0;
+    AC u[18];
+    load_link(hc.lk_b, (const LK *)nullptr, drop ? 0x80000000u : (uint32_t)slot * 2 * (uint32_t)sizeof(LK),
+              MU * 6 * hc.kstr, hc.kstr, u, (e & kNbrSign) != 0);
+    const SrcLds<SP, G> src{stage + (drop ? own : lidx) * G};
+    hop_half<MU, FWD, SP, AC, G>(w, src, u);
 }
 
 }  // namespace dd

@@ -188,3 +188,33 @@ def test_solve_with_other_rhs_groups(ctx, c1, grp):
     assert st == dd.DD_OK and np.all(info["true_relres"] <= TOL)
     assert _cfg.rel_err(x.cpu().numpy(), c1["x_lu"]) <= 1e-9
     g.close()
+
+
+@pytest.mark.parametrize("walk", [-1, 3])
+def test_solve_uneven_slabs_walk_segments(ctx, walk):
+    """BiCGStab with the fused dot products of the hop taken from the x0-walk split into 3 segments
+    per block (partials of a block's remaining chunk slots zero), or from the chunked kernel."""
+    from paper_2211_06902_amd import dd
+
+    L = (16, 8, 8, 8)
+    segs = [[6, 10], [8], [4, 4], [8]]
+    kappa = 0.13
+    U = synth.gauge_field(L, 0.4, 31)
+    boxes = geometry.tile_boxes(L, segs)
+    sites = _cfg.block_sites(L, boxes)
+    off = _cfg.site_offsets(boxes)
+    b = synth.spinor_field(L, 3, 32)[:, sites]
+    blk = ctx.make_blocks(L, -1, segs)
+    g = ctx.load_gauge(blk, _dev(U), "f32")
+    try:
+        ctx.tune_set(dd.TUNE_HOP_WALK, walk)
+        x, info, st = ctx.block_solve(blk, g, kappa, _dev(b), params=dd.solve_params())
+    finally:
+        ctx.tune_set(dd.TUNE_HOP_WALK, 0)
+    assert st == dd.DD_OK
+    x = x.cpu().numpy()
+    for k, bx in enumerate(boxes):
+        sl = slice(off[k], off[k + 1])
+        for r in range(3):
+            assert _true_relres(L, kappa, U, bx, x[r, sl], b[r, sl]) <= TOL
+    g.close()

@@ -173,3 +173,45 @@ def test_rhs_group_variants_identical(ctx):
     for grp in [2, 4]:
         for a, b, tol in zip(outs[1], outs[grp], [1e-6, 1e-6, 1e-14]):
             assert _cfg.rel_err(b, a) <= tol
+
+
+@pytest.mark.parametrize("walk", [-1, 0, 2, 3])
+def test_hop_walk_segments_vs_oracle(ctx, walk):
+    """The x0-walk of the hop (each input slice read once, -1 = chunked kernel instead) on uneven
+    slabs (128 sites per slice and parity, 6 and 10 slices), and on blocks straddling the
+    antiperiodic time edge with periodic wrap inside the slices; 2 and 3 segments per block."""
+    from paper_2211_06902_amd import dd
+
+    L = (16, 8, 8, 8)
+    cases = [([[6, 10], [8], [4, 4], [8]], (0, 0, 0, 0), 4),
+             ([[8, 8], [8], [8], [8]], (3, 0, 0, 0), 2)]
+    try:
+        ctx.tune_set(dd.TUNE_HOP_WALK, walk)
+        for segs, shift, nb in cases:
+            _check_apply(ctx, L, 0.13, 0.4, 21, 22, segs, shift, 3, range(nb), range(3))
+    finally:
+        ctx.tune_set(dd.TUNE_HOP_WALK, 0)
+
+
+def test_hop_walk_matches_chunked_kernel(ctx):
+    """Walk and chunked hop kernels agree on the full C2 geometry (FP32 and BF16 links, 12 rhs)."""
+    from paper_2211_06902_amd import dd
+
+    c = _cfg.C2
+    L = c["L"]
+    U = synth.gauge_field(L, c["eps"], c["seed_u"])
+    blk = ctx.make_blocks(L, -1, c["segs"])
+    x = _dev(synth.spinor_field(L, c["nrhs"], c["seed_src"])[:, _cfg.block_sites(L, geometry.tile_boxes(L, c["segs"]))])
+    for low in ["f32", "bf16"]:
+        g = ctx.load_gauge(blk, _dev(U), low)
+        outs = []
+        try:
+            for walk in [0, -1]:
+                ctx.tune_set(dd.TUNE_HOP_WALK, walk)
+                outs.append(ctx.apply_D_block(blk, g, c["kappa"], low, x))
+        finally:
+            ctx.tune_set(dd.TUNE_HOP_WALK, 0)
+        # same arithmetic per site; only the compiler's contraction of the sums may differ
+        assert float((outs[0] - outs[1]).abs().max()) <= 1e-5 * float(outs[1].abs().max())
+        g.close()
+        del outs
