@@ -20,6 +20,7 @@
 #include "dd_internal.h"
 #include "dd_stencil.h"
 
+
 namespace dd {
 
 namespace {
@@ -111,52 +112,64 @@ __device__ __forceinline__ double wg_hop(const PairGeo &g, int p, const SP *in, 
 }
 
 // out[2i] + i out[2i+1] = <V_i, V_iw> = sum conj(V_i) V_iw for i <= j, FP64
-// products and sums.  The basis vectors are dealt to the wavefronts
-// round-robin and every wavefront runs over all of V_iw (whose repeated reads
-// hit the cache), so each V_i is read once and each sum has one owner.  With
-// norm, out[NV - 1] = |V_iw|^2 (from the last wavefront).  Ends with a barrier.
+// products and sums.  Every thread runs over its own elements and keeps the
+// sums of a group of up to 8 basis vectors (all loads of an element issued
+// together; V_iw read once per group, each V_i once); then a butterfly inside
+// each wavefront and the wavefronts in order through LDS (red: NT / 64 * NV
+// doubles).  With norm, out[NV - 1] = |V_iw|^2.  Ends with a barrier.
 template <typename SP, int M, int NT, int NV>
-__device__ __forceinline__ void gs_dots(const Slot &sl, int iw, int h, int j, bool norm, double *out)
+__device__ __forceinline__ void gs_dots(const Slot &sl, int iw, int h, int j, bool norm, double *out, double *red)
 {
-    constexpr int NW = NT / 64, K = (M + NW) / NW;
-    const int lane = threadIdx.x & 63, wave = uni(threadIdx.x >> 6);
-    const bool do_norm = norm && wave == NW - 1;
-    double d[2 * K], nn = 0;
-#pragma unroll
-    for (int k = 0; k < 2 * K; k++) d[k] = 0;
+    constexpr int NW = NT / 64, GS = 8;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const uint32_t hb = (uint32_t)h * (uint32_t)sizeof(SP), wo = (uint32_t)iw * sl.vbytes;
 #pragma unroll 1
-    for (int cc = 0; cc < 12; cc++)
-#pragma unroll 1
-        for (int s = lane; s < h; s += 64) {
-            const uint32_t vo = (uint32_t)(2 * cc * h + s) * (uint32_t)sizeof(SP);
-            const double wr = (double)bload<SP>(sl.b, vo, wo), wi = (double)bload<SP>(sl.b, vo, wo + hb);
+    for (int i0 = 0; i0 <= j; i0 += GS) {
+        const bool do_norm = norm && i0 == 0;
+        double d[2 * GS], nn = 0;
 #pragma unroll
-            for (int k = 0; k < K; k++) {
-                const int i = wave + k * NW;
-                if (i <= j) {
-                    const uint32_t io = (uint32_t)i * sl.vbytes;
-                    const double vr = (double)bload<SP>(sl.b, vo, io), vi = (double)bload<SP>(sl.b, vo, io + hb);
-                    d[2 * k] = fma(vr, wr, fma(vi, wi, d[2 * k]));
-                    d[2 * k + 1] = fma(vr, wi, fma(-vi, wr, d[2 * k + 1]));
+        for (int k = 0; k < 2 * GS; k++) d[k] = 0;
+#pragma unroll 1
+        for (int cc = 0; cc < 12; cc++)
+#pragma unroll 1
+            for (int s = threadIdx.x; s < h; s += NT) {
+                const uint32_t vo = (uint32_t)(2 * cc * h + s) * (uint32_t)sizeof(SP);
+                const double wr = (double)bload<SP>(sl.b, vo, wo), wi = (double)bload<SP>(sl.b, vo, wo + hb);
+                // the basis offsets are recomputed here (scalar arithmetic) rather
+                // than hoisted out of the loops into scalar registers
+                uint32_t vbytes = sl.vbytes;
+                __asm__ volatile("" : "+s"(vbytes));
+#pragma unroll
+                for (int k = 0; k < GS; k++)
+                    if (i0 + k <= j) {
+                        const uint32_t io = (uint32_t)(i0 + k) * vbytes;
+                        const double vr = (double)bload<SP>(sl.b, vo, io), vi = (double)bload<SP>(sl.b, vo, io + hb);
+                        d[2 * k] = fma(vr, wr, fma(vi, wi, d[2 * k]));
+                        d[2 * k + 1] = fma(vr, wi, fma(-vi, wr, d[2 * k + 1]));
+                    }
+                if (do_norm) nn = fma(wr, wr, fma(wi, wi, nn));
+            }
+#pragma unroll
+        for (int k = 0; k < GS; k++)
+            if (i0 + k <= j) {
+                const double re = wave_sum(d[2 * k]), im = wave_sum(d[2 * k + 1]);
+                if (lane == 0) {
+                    red[wave * NV + 2 * (i0 + k)] = re;
+                    red[wave * NV + 2 * (i0 + k) + 1] = im;
                 }
             }
-            if (do_norm) nn = fma(wr, wr, fma(wi, wi, nn));
-        }
-#pragma unroll
-    for (int k = 0; k < K; k++) {
-        const int i = wave + k * NW;
-        if (i <= j) {
-            const double re = wave_sum(d[2 * k]), im = wave_sum(d[2 * k + 1]);
-            if (lane == 0) {
-                out[2 * i] = re;
-                out[2 * i + 1] = im;
-            }
+        if (do_norm) {
+            const double sn = wave_sum(nn);
+            if (lane == 0) red[wave * NV + NV - 1] = sn;
         }
     }
-    if (do_norm) {
-        const double s = wave_sum(nn);
-        if (lane == 0) out[NV - 1] = s;
+    __syncthreads();
+    const int k = threadIdx.x;
+    if (k < 2 * (j + 1) || (norm && k == NV - 1)) {
+        double t = 0;
+#pragma unroll
+        for (int w = 0; w < NW; w++) t += red[w * NV + k];
+        out[k] = t;
     }
     __syncthreads();
 }
@@ -179,10 +192,14 @@ __device__ __forceinline__ void combine(const Slot &sl, const Buf &db, uint32_t 
             __asm__ volatile("" ::: "memory");
             const uint32_t vo = (uint32_t)(2 * cc * h + s) * (uint32_t)sizeof(SP);
             double wr = (double)bload<SP>(db, vo, dso), wi = (double)bload<SP>(db, vo, dso + hb);
+            // the basis offsets are recomputed here (scalar arithmetic) rather
+            // than hoisted out of the loops into scalar registers
+            uint32_t vbytes = sl.vbytes;
+            __asm__ volatile("" : "+s"(vbytes));
 #pragma unroll
             for (int i = 0; i <= M; i++)
                 if (i >= i0 && i < n) {
-                    const uint32_t io = (uint32_t)i * sl.vbytes;
+                    const uint32_t io = (uint32_t)i * vbytes;
                     const double vr = (double)bload<SP>(sl.b, vo, io), vi = (double)bload<SP>(sl.b, vo, io + hb);
                     const double cr = sgn * c[2 * i], ci = sgn * c[2 * i + 1];
                     wr = fma(cr, vr, fma(-ci, vi, wr));
@@ -201,14 +218,16 @@ enum { kGoOn = 0, kRestart = 1, kConverged = 2, kMaxIter = 3, kNonFinite = 4, kP
 // One launch solves every pair listed in the queues whose `active` flag is set
 // and leaves e = Dhat^{-1} f (to the relative tolerance, or the last iterate)
 // in x; every workgroup leaves the loop once all queues are drained.
+// FP32 spinors: at most 168 registers, so that three wavefronts share a SIMD
 template <typename SP, typename LK, int M, int NT>
-__global__ void __launch_bounds__(NT) k_gmres(GmArgs a)
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(SP) == 4 ? 3 : 1))) k_gmres(GmArgs a)
 {
     constexpr int NW = NT / 64;
     constexpr int NV = 2 * (M + 1) + 1;
     static_assert(NV <= NT, "one thread per reduced value");
     __shared__ double red[NW];
     __shared__ double sum[NV];
+    __shared__ double red2[NW * NV];
     __shared__ double Hm[(M + 1) * M * 2];  // Hm[(i * M + j) * 2 + ri], row i, column j
     __shared__ double cs[M], sn[2 * M], gv[2 * (M + 1)], yv[2 * (M + 1)];
     __shared__ int s_pair, s_stop;
@@ -309,7 +328,7 @@ __global__ void __launch_bounds__(NT) k_gmres(GmArgs a)
                 }
                 __syncthreads();
                 // first Gram-Schmidt pass: h = V^H w, w -= V h
-                gs_dots<SP, M, NT, NV>(sl, j + 1, h, j, false, sum);
+                gs_dots<SP, M, NT, NV>(sl, j + 1, h, j, false, sum, red2);
                 if (threadIdx.x == 0)
                     for (int i = 0; i <= j; i++) {
                         Hm[(i * M + j) * 2] = sum[2 * i];
@@ -319,7 +338,7 @@ __global__ void __launch_bounds__(NT) k_gmres(GmArgs a)
                 combine<SP, M, NT>(sl, sl.b, wso, h, j + 1, sum, -1.0, 1.0);
                 __syncthreads();
                 // second pass: the corrections c = V^H w and |w|^2
-                gs_dots<SP, M, NT, NV>(sl, j + 1, h, j, true, sum);
+                gs_dots<SP, M, NT, NV>(sl, j + 1, h, j, true, sum, red2);
                 // |w - V c|^2 = |w|^2 - |c|^2 for orthonormal V; c is a rounding-level correction
                 double c2 = 0;
                 for (int i = 0; i <= j; i++) c2 += sum[2 * i] * sum[2 * i] + sum[2 * i + 1] * sum[2 * i + 1];
