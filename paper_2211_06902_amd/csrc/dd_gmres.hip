@@ -111,6 +111,61 @@ __device__ __forceinline__ double wg_hop(const PairGeo &g, int p, const SP *in, 
     return nn;
 }
 
+// wg_hop by the x0-walk (dd_stencil.h): the input slices staged in LDS one
+// after the other, each read once.  For blocks whose x0-slices hold at most
+// kTile sites per parity; all threads call it.
+template <typename SP, typename LK, int NT>
+__device__ __forceinline__ double wg_hop_walk(const PairGeo &g, int p, int ns, SP *stage, const SP *in, SP *out,
+                                              const SP *self, double c_self, double c_hop, const SP *add, double c_add)
+{
+    using AC = SP;
+    WalkPos w;
+    w.p = p;
+    w.hb = g.h;
+    w.hs = g.h / ns;
+    w.k = threadIdx.x;
+    w.s0 = 0;
+    w.s1 = ns;
+    w.nbt = g.nbr + (size_t)p * g.h * 8;
+    HopCtx hc;
+    hc.h0 = 0;
+    hc.tv = 0;
+    hc.slot_self = 0;
+    hc.other0 = 0;
+    hc.grp_off = 0;
+    hc.cstr = (uint32_t)g.h * (uint32_t)sizeof(SP);
+    hc.kstr = g.kstr;
+    hc.in_b = make_buf(in, (uint32_t)(24 * g.h) * (uint32_t)sizeof(SP));
+    hc.lk_b = g.lk_b;
+    const AC ch = (AC)c_hop, cs = (AC)c_self, ca = (AC)c_add;
+    const uint32_t vbytes = (uint32_t)(24 * g.h) * (uint32_t)sizeof(SP);
+    const Buf ob = make_buf(out, vbytes), sb = make_buf(self, self ? vbytes : 0), ab = make_buf(add, add ? vbytes : 0);
+    const bool has_self = self != nullptr, has_add = add != nullptr;
+    double nn = 0;
+    walk_run<SP, LK, AC>(w, ns, stage, hc, [&](const AC (&acc)[24], int h) {
+        const uint32_t vo = (uint32_t)h * (uint32_t)sizeof(SP);
+#pragma unroll
+        for (int half = 0; half < 2; half++) {
+            SP sv[12], av[12];
+#pragma unroll
+            for (int q = 0; q < 12; q++) {
+                sv[q] = bload<SP>(sb, vo, (uint32_t)(12 * half + q) * hc.cstr);
+                av[q] = bload<SP>(ab, vo, (uint32_t)(12 * half + q) * hc.cstr);
+            }
+#pragma unroll
+            for (int q = 0; q < 12; q++) {
+                AC v = ch * acc[12 * half + q];
+                if (has_self) v = fmad(cs, (AC)sv[q], v);
+                if (has_add) v = fmad(ca, (AC)av[q], v);
+                const SP ov = (SP)v;
+                bstore<SP>(ob, ov, vo, (uint32_t)(12 * half + q) * hc.cstr);
+                nn += (double)ov * (double)ov;
+            }
+        }
+    });
+    return nn;
+}
+
 // out[2i] + i out[2i+1] = <V_i, V_iw> = sum conj(V_i) V_iw for i <= j, FP64
 // products and sums.  Every thread runs over its own elements and keeps the
 // sums of a group of up to 8 basis vectors (all loads of an element issued
@@ -218,8 +273,9 @@ enum { kGoOn = 0, kRestart = 1, kConverged = 2, kMaxIter = 3, kNonFinite = 4, kP
 // One launch solves every pair listed in the queues whose `active` flag is set
 // and leaves e = Dhat^{-1} f (to the relative tolerance, or the last iterate)
 // in x; every workgroup leaves the loop once all queues are drained.
-// FP32 spinors: at most 168 registers, so that three wavefronts share a SIMD
-template <typename SP, typename LK, int M, int NT>
+// WALK: the hops walk the x0-slices (wg_hop_walk), else wg_hop.  FP32
+// spinors: at most 168 registers, so that three wavefronts share a SIMD.
+template <typename SP, typename LK, int M, int NT, bool WALK>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(SP) == 4 ? 3 : 1))) k_gmres(GmArgs a)
 {
     constexpr int NW = NT / 64;
@@ -228,6 +284,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
     __shared__ double red[NW];
     __shared__ double sum[NV];
     __shared__ double red2[NW * NV];
+    __shared__ SP stage[WALK ? 24 * kTile : 1];  // input slice of the walking hops
     __shared__ double Hm[(M + 1) * M * 2];  // Hm[(i * M + j) * 2 + ri], row i, column j
     __shared__ double cs[M], sn[2 * M], gv[2 * (M + 1)], yv[2 * (M + 1)];
     __shared__ int s_pair, s_stop;
@@ -264,6 +321,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
 
         const int b = pair % a.nb, r = pair / a.nb;
         const int h = uni(a.h[b]);
+        const int ns = uni(a.ext[4 * b]);  // x0-slices of the block
         const int64_t so = uni64(a.soff[b]);
         PairGeo g;
         g.h = h;
@@ -315,16 +373,19 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
             const bool use_z = z0 && cycles == 0;
             for (int j = 0; j < m && stop == kGoOn; j++) {
                 SP *vj = V + (int64_t)j * a.vstr, *w = V + (int64_t)(j + 1) * a.vstr;
-                if (j == 0 && use_z) {
-                    // flexible first direction z_0 = N(v_0) = N(r) / beta: w = Dhat z_0
-                    wg_hop<SP, LK, NT>(g, 1, z0, tmp, nullptr, 0.0, 1.0, nullptr, 0.0);
+                // w = Dhat v_j, or with the flexible first direction z_0 = N(v_0) =
+                // N(r) / beta: w = Dhat z_0
+                const bool zf = j == 0 && use_z;
+                const SP *src = zf ? z0 : vj;
+                const double cs1 = zf ? 1.0 / beta : 1.0, ch1 = zf ? -k2 / beta : -k2;
+                if constexpr (WALK) {
+                    wg_hop_walk<SP, LK, NT>(g, 1, ns, stage, src, tmp, nullptr, 0.0, 1.0, nullptr, 0.0);
                     __syncthreads();
-                    wg_hop<SP, LK, NT>(g, 0, tmp, w, z0, 1.0 / beta, -k2 / beta, nullptr, 0.0);
+                    wg_hop_walk<SP, LK, NT>(g, 0, ns, stage, tmp, w, src, cs1, ch1, nullptr, 0.0);
                 } else {
-                    // w = Dhat v_j
-                    wg_hop<SP, LK, NT>(g, 1, vj, tmp, nullptr, 0.0, 1.0, nullptr, 0.0);
+                    wg_hop<SP, LK, NT>(g, 1, src, tmp, nullptr, 0.0, 1.0, nullptr, 0.0);
                     __syncthreads();
-                    wg_hop<SP, LK, NT>(g, 0, tmp, w, vj, 1.0, -k2, nullptr, 0.0);
+                    wg_hop<SP, LK, NT>(g, 0, tmp, w, src, cs1, ch1, nullptr, 0.0);
                 }
                 __syncthreads();
                 // first Gram-Schmidt pass: h = V^H w, w -= V h
@@ -444,9 +505,16 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
             }
             if (stop != kRestart) break;
             // restart from the explicit residual V_0 = f - Dhat x
-            wg_hop<SP, LK, NT>(g, 1, x, tmp, nullptr, 0.0, 1.0, nullptr, 0.0);
-            __syncthreads();
-            const double rn = wg_hop<SP, LK, NT>(g, 0, tmp, V, x, -1.0, k2, f, 1.0);
+            double rn;
+            if constexpr (WALK) {
+                wg_hop_walk<SP, LK, NT>(g, 1, ns, stage, x, tmp, nullptr, 0.0, 1.0, nullptr, 0.0);
+                __syncthreads();
+                rn = wg_hop_walk<SP, LK, NT>(g, 0, ns, stage, tmp, V, x, -1.0, k2, f, 1.0);
+            } else {
+                wg_hop<SP, LK, NT>(g, 1, x, tmp, nullptr, 0.0, 1.0, nullptr, 0.0);
+                __syncthreads();
+                rn = wg_hop<SP, LK, NT>(g, 0, tmp, V, x, -1.0, k2, f, 1.0);
+            }
             beta = sqrt(wg_sum1<NT>(rn, red));
             est = beta;
             moved += 6.0 * vb + 2.0 * lb;
@@ -491,33 +559,39 @@ __global__ void k_fill_i32(int32_t *p, int n, int32_t v)
 
 namespace {
 
-template <typename SP, typename LK>
+template <typename SP, typename LK, bool WALK>
 struct GmKernels {
     static const void *get(int M, int nt)
     {
-        if (M == 8 && nt == 256) return (const void *)k_gmres<SP, LK, 8, 256>;
-        if (M == 8 && nt == 512) return (const void *)k_gmres<SP, LK, 8, 512>;
-        if (M == 16 && nt == 256) return (const void *)k_gmres<SP, LK, 16, 256>;
-        if (M == 16 && nt == 512) return (const void *)k_gmres<SP, LK, 16, 512>;
+        if (M == 8 && nt == 256) return (const void *)k_gmres<SP, LK, 8, 256, WALK>;
+        if (M == 8 && nt == 512) return (const void *)k_gmres<SP, LK, 8, 512, WALK>;
+        if (M == 16 && nt == 256) return (const void *)k_gmres<SP, LK, 16, 256, WALK>;
+        if (M == 16 && nt == 512) return (const void *)k_gmres<SP, LK, 16, 512, WALK>;
         return nullptr;
     }
 };
 
-const void *gmres_kernel(dd_prec prec, int M, int nt)
+template <bool WALK>
+const void *gmres_kernel_w(dd_prec prec, int M, int nt)
 {
-    if (prec == DD_F64) return GmKernels<double, double>::get(M, nt);
-    if (prec == DD_F32) return GmKernels<float, float>::get(M, nt);
-    if (prec == DD_BF16) return GmKernels<float, uint16_t>::get(M, nt);
+    if (prec == DD_F64) return GmKernels<double, double, WALK>::get(M, nt);
+    if (prec == DD_F32) return GmKernels<float, float, WALK>::get(M, nt);
+    if (prec == DD_BF16) return GmKernels<float, uint16_t, WALK>::get(M, nt);
     return nullptr;
+}
+
+const void *gmres_kernel(dd_prec prec, int M, int nt, bool walk)
+{
+    return walk ? gmres_kernel_w<true>(prec, M, nt) : gmres_kernel_w<false>(prec, M, nt);
 }
 
 }  // namespace
 
 int gmres_basis_m(int restart) { return restart <= 8 ? 8 : 16; }
 
-hipError_t gmres_occupancy(dd_prec prec, int restart, int nt, int *wgs_per_cu)
+hipError_t gmres_occupancy(dd_prec prec, int restart, int nt, bool walk, int *wgs_per_cu)
 {
-    const void *k = gmres_kernel(prec, gmres_basis_m(restart), nt);
+    const void *k = gmres_kernel(prec, gmres_basis_m(restart), nt, walk);
     if (!k) return hipErrorInvalidValue;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(wgs_per_cu, k, nt, 0);
 }
@@ -525,7 +599,7 @@ hipError_t gmres_occupancy(dd_prec prec, int restart, int nt, int *wgs_per_cu)
 hipError_t launch_gmres(const GmArgs &a, dd_prec prec, int nt, int grid, hipStream_t st)
 {
     if (a.m < 1 || a.m > 16 || grid < 1 || a.nq < 1) return hipErrorInvalidValue;
-    const void *k = gmres_kernel(prec, gmres_basis_m(a.m), nt);
+    const void *k = gmres_kernel(prec, gmres_basis_m(a.m), nt, a.walk != 0);
     if (!k) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_fill_i32, dim3((a.nq + 255) / 256), dim3(256), 0, st, a.qctr, a.nq, 0);
     const int np = a.nb * a.n_rhs;

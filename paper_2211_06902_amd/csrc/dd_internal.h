@@ -248,14 +248,18 @@ struct GmArgs {
     int32_t *iters;           // [np] += steps taken
     int32_t *flags;           // [np] |= 4 on a non-finite value
     double *relres;           // [np] last residual estimate / |f| (may be null)
+    const int32_t *ext;       // [nb][4] block extents
+    int walk;                 // 1: the hops walk the x0-slices (every block admits it)
 };
 
 // basis vectors the kernel for restart length m keeps per workgroup (its
 // compile-time bound plus one)
 int gmres_basis_m(int restart);
-hipError_t gmres_occupancy(dd_prec prec, int restart, int nt, int *wgs_per_cu);
+hipError_t gmres_occupancy(dd_prec prec, int restart, int nt, bool walk, int *wgs_per_cu);
 hipError_t launch_gmres(const GmArgs &a, dd_prec prec, int nt, int grid, hipStream_t st);
-hipError_t gmres_schedule(dd_ctx *ctx, dd_prec ip, int restart, int np, int *nt, int *nq, int *grid);
+hipError_t gmres_schedule(dd_ctx *ctx, dd_prec ip, int restart, int np, bool walk, int *nt, int *nq, int *grid);
+// whether the persistent GMRES kernel's hops take the x0-walk for these blocks
+bool gmres_walk(const dd_ctx *ctx, const dd_blocks *B);
 
 // Extent of the block the network works on (all its blocks have one shape).
 struct NnExt {

@@ -267,87 +267,10 @@ hipError_t launch_hop(const BlkArgs &ba, const HopArgs &ha, dd_prec prec, hipStr
     return hipGetLastError();
 }
 
-// x0-walk of the hop.  A tile of kTile threads walks the x0-slices of one
-// block segment for one rhs; thread k owns eo site k of every slice (hs sites
-// per parity and slice).  The eo order makes the x0-neighbour of a site the
-// same position k of the adjacent slice of the other parity, so each input
-// slice is read from global memory once: staged in LDS, it feeds the hops
-// along 1..3 of its own output slice (neighbours inside the slice) and the x0
-// hops of the two adjacent output slices at position k.  One accumulator
-// rides along: it holds output slice q-1 until its x0+ hop arrives with input
-// slice q, and the x0- hop of output slice q+1, computed from input slice q,
-// waits as its 12-real upper half.
-
-#ifndef DD_WALK_PARTS
-#define DD_WALK_PARTS 2
-#endif
-constexpr int kWalkParts = DD_WALK_PARTS;
-#ifndef DD_WALK_ATTR
-#define DD_WALK_ATTR
-#endif
-#ifndef DD_WALK_BF
-#define DD_WALK_BF 0
-#endif
-constexpr bool kWalkBF = DD_WALK_BF != 0;
-
-template <typename SP>
-__device__ __forceinline__ void walk_stage(SP *stage, const HopCtx &hc, int q, int hs, int k, bool live)
-{
-    if (!live) return;
-    const uint32_t vo = (uint32_t)(hc.grp_off + q * hs + k) * (uint32_t)sizeof(SP);
-    SP v[24];
-#pragma unroll
-    for (int c = 0; c < 24; c++) v[c] = bload<SP>(hc.in_b, vo, (uint32_t)c * hc.cstr);
-#pragma unroll
-    for (int c = 0; c < 24; c++) stage[c * kTile + k] = v[c];
-}
-
-struct WalkPos {
-    int p, hb, hs, k, s0, s1;
-    const int32_t *nbt;  // neighbour table of the output parity
-};
-
-// Input slice q is in LDS.  acc holds output slice q-1: it is finished and
-// written when it belongs to the segment, then restarted as output slice q
-// (carry: the upper half of its x0- hop) with the hops along 1..3; carry
-// becomes the x0- half of output slice q+1.
+// x0-walk of the hop (the walk itself is in dd_stencil.h): a tile walks one
+// of nseg segments of a block's x0-slices for one rhs.
 template <typename SP, typename LK, typename AC, int DM>
-__device__ __forceinline__ void walk_step(AC (&acc)[1][24], AC (&carry)[1][12], double (&dv)[1][kNRed], int q,
-                                          const WalkPos &w, const SP *stage, const HopCtx &hc, const HopArgs &ha,
-                                          const EpiBufs &eb)
-{
-    if (q - 1 >= w.s0) {
-        const int h = (q - 1) * w.hs + w.k;
-        hop_at<0, true, SP, LK, AC, 1, kWalkBF>(acc, w.nbt[h * 8], stage, w.k, w.p * w.hb + h, w.k, hc);
-        hop_epilogue<SP, AC, DM, kWalkParts>(acc[0], dv[0], ha, eb, (uint32_t)(hc.grp_off + h) * (uint32_t)sizeof(SP), hc.cstr);
-    }
-    if (q >= w.s0 && q < w.s1) {
-#pragma unroll
-        for (int c = 0; c < 24; c++) acc[0][c] = 0;
-        hop_expand<0, false, AC>(acc[0], carry[0]);
-        const int h = q * w.hs + w.k, base = q * w.hs, oth = (1 - w.p) * w.hb, own = w.p * w.hb + h;
-        const int4 *t4 = reinterpret_cast<const int4 *>(w.nbt + h * 8);
-        const int4 a0 = t4[0], a1 = t4[1];
-        const int32_t nb[6] = {a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
-        int li[6];
-#pragma unroll
-        for (int i = 0; i < 6; i++) li[i] = (nb[i] & kNbrMask) - base;
-        hop_at<1, true, SP, LK, AC, 1, kWalkBF>(acc, nb[0], stage, li[0], own, w.k, hc);
-        hop_at<1, false, SP, LK, AC, 1, kWalkBF>(acc, nb[1], stage, li[1], oth + base + li[1], w.k, hc);
-        hop_at<2, true, SP, LK, AC, 1, kWalkBF>(acc, nb[2], stage, li[2], own, w.k, hc);
-        hop_at<2, false, SP, LK, AC, 1, kWalkBF>(acc, nb[3], stage, li[3], oth + base + li[3], w.k, hc);
-        hop_at<3, true, SP, LK, AC, 1, kWalkBF>(acc, nb[4], stage, li[4], own, w.k, hc);
-        hop_at<3, false, SP, LK, AC, 1, kWalkBF>(acc, nb[5], stage, li[5], oth + base + li[5], w.k, hc);
-    }
-    if (q + 1 < w.s1) {
-        const int h = (q + 1) * w.hs + w.k;
-        hop_half_at<0, false, SP, LK, AC, 1, kWalkBF>(carry, w.nbt[h * 8 + 1], stage, w.k,
-                                                     (1 - w.p) * w.hb + q * w.hs + w.k, w.k, hc);
-    }
-}
-
-template <typename SP, typename LK, typename AC, int DM>
-__global__ void __launch_bounds__(kTile) DD_WALK_ATTR k_hop_walk(BlkArgs ba, WalkArgs wa, HopArgs ha)
+__global__ void __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(sizeof(SP) == 8 && (DM == kDotNone || DM == kDotOutOut) ? 3 : 1))) k_hop_walk(BlkArgs ba, WalkArgs wa, HopArgs ha)
 {
     __shared__ SP stage[24 * kTile];
     __shared__ double red[1][kTile];
@@ -364,8 +287,6 @@ __global__ void __launch_bounds__(kTile) DD_WALK_ATTR k_hop_walk(BlkArgs ba, Wal
     w.k = threadIdx.x;
     w.s0 = seg * ns / wa.nseg;
     w.s1 = (seg + 1) * ns / wa.nseg;
-    const int qa = max(w.s0 - 1, 0), qb = min(w.s1 + 1, ns);
-    const bool live = w.k < w.hs;
     const int64_t soff = uni64(ba.soff[b]);
     const int64_t hbase = (soff >> 1) * 24 * nr;
     const uint32_t fbytes = (uint32_t)(nr * 24 * w.hb) * (uint32_t)sizeof(SP);
@@ -382,25 +303,12 @@ __global__ void __launch_bounds__(kTile) DD_WALK_ATTR k_hop_walk(BlkArgs ba, Wal
                        (uint32_t)(2 * w.hb * kLinkReals) * (uint32_t)sizeof(LK));
     const EpiBufs eb = epi_bufs<SP>(ha, hbase, fbytes);
     w.nbt = ba.nbr + uni64(ba.nbr_off[b]) + (int64_t)w.p * w.hb * 8;
-    AC acc[1][24], carry[1][12];
     double dv[1][kNRed];
 #pragma unroll
-    for (int c = 0; c < 24; c++) acc[0][c] = 0;
-#pragma unroll
-    for (int c = 0; c < 12; c++) carry[0][c] = 0;
-#pragma unroll
     for (int i = 0; i < kNRed; i++) dv[0][i] = 0;
-    for (int q = qa; q < qb; q++) {
-        walk_stage(stage, hc, q, w.hs, w.k, live);
-        __syncthreads();
-        if (live) walk_step<SP, LK, AC, DM>(acc, carry, dv, q, w, stage, hc, ha, eb);
-        __syncthreads();
-    }
-    // The block's last slice has no x0+ neighbour: when the segment ends
-    // there, its output is finished here.
-    if (live && qb == w.s1)
-        hop_epilogue<SP, AC, DM, kWalkParts>(acc[0], dv[0], ha, eb,
-                                 (uint32_t)(hc.grp_off + (w.s1 - 1) * w.hs + w.k) * (uint32_t)sizeof(SP), hc.cstr);
+    walk_run<SP, LK, AC>(w, ns, stage, hc, [&](const AC (&acc)[24], int h) {
+        hop_epilogue<SP, AC, DM>(acc, dv[0], ha, eb, (uint32_t)(hc.grp_off + h) * (uint32_t)sizeof(SP), hc.cstr);
+    });
     if (DM != kDotNone) {
         // partial sums in the chunk tiles' slots: segment seg in chunk slot seg,
         // the block's remaining chunk slots zero

@@ -147,12 +147,14 @@ namespace dd {
 // Launch shape of the persistent GMRES kernel: threads per workgroup, number
 // of work queues and resident workgroups (grid), from the context's settings
 // (dd_tune_set, dd_autotune_gmres) or the defaults.
-hipError_t gmres_schedule(dd_ctx *ctx, dd_prec ip, int restart, int np, int *nt, int *nq, int *grid)
+bool gmres_walk(const dd_ctx *ctx, const dd_blocks *B) { return B->walk && ctx->hop_lds && ctx->hop_walk >= 0; }
+
+hipError_t gmres_schedule(dd_ctx *ctx, dd_prec ip, int restart, int np, bool walk, int *nt, int *nq, int *grid)
 {
     *nt = ctx->gm_threads > 0 ? ctx->gm_threads : 256;
     *nq = ctx->gm_queues > 0 ? ctx->gm_queues : 8;
     int occ = 0;
-    hipError_t e = gmres_occupancy(ip, restart, *nt, &occ);
+    hipError_t e = gmres_occupancy(ip, restart, *nt, walk, &occ);
     if (e != hipSuccess) return e;
     if (occ < 1) return hipErrorInvalidConfiguration;
     int ncu = 0;
@@ -260,7 +262,7 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
     const QueueTable *qt = nullptr;
     const int64_t vstr = 24 * (int64_t)B->max_h;
     if (gmres) {
-        HIPCHECK(ctx, gmres_schedule(ctx, ip, prm.restart, np, &gm_nt, &gm_nq, &gm_grid));
+        HIPCHECK(ctx, gmres_schedule(ctx, ip, prm.restart, np, gmres_walk(ctx, B), &gm_nt, &gm_nq, &gm_grid));
         qt = queues_for(B, n_rhs, gm_nq, &e);
         if (!qt) return fail(ctx, DD_EDEVICE, std::string("work queues: ") + hipGetErrorString(e));
         gm_ws = get("g_basis", (size_t)gm_grid * (gmres_basis_m(prm.restart) + 2) * vstr * prec_bytes(sp));
@@ -381,6 +383,8 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
             ga.iters = w.ps.iters;
             ga.flags = w.ps.flags;
             ga.relres = nullptr;
+            ga.ext = B->d_ext;
+            ga.walk = gmres_walk(ctx, B) ? 1 : 0;
             ga.resume = 0;
             ga.r = gm_r;
             ga.z0 = nullptr;
@@ -531,7 +535,7 @@ dd_status dd_autotune_gmres(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *G, 
     std::vector<Cand> cand;
     for (int nt : {256, 512}) {
         int occ = 0;
-        if (gmres_occupancy(p.inner_prec, p.restart, nt, &occ) != hipSuccess || occ < 1) continue;
+        if (gmres_occupancy(p.inner_prec, p.restart, nt, gmres_walk(ctx, B), &occ) != hipSuccess || occ < 1) continue;
         for (int nq : {8, 1}) {
             cand.push_back({nt, nq, occ, 0.0});
             if (occ > 1) cand.push_back({nt, nq, (occ + 1) / 2, 0.0});

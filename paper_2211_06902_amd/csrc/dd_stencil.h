@@ -361,45 +361,131 @@ __device__ __forceinline__ void hop_one(AC (&acc)[G][24], int32_t e, const SP *s
 // Adds the hop along MU (forward or backward) with the neighbour's spinor at
 // LDS position lidx of `stage` and the link at `slot` (the site's own slot
 // forward, the neighbour's backward), when the entry e is not dropped.
-// BF: without a branch; a dropped hop then reads position `own` of the
-// stage and a link offset beyond the buffer, whose loads return 0, so it
-// adds U = 0 times a finite spinor.
-template <int MU, bool FWD, typename SP, typename LK, typename AC, int G, bool BF = false>
-__device__ __forceinline__ void hop_at(AC (&acc)[G][24], int32_t e, const SP *stage, int lidx, int slot, int own,
+template <int MU, bool FWD, typename SP, typename LK, typename AC, int G>
+__device__ __forceinline__ void hop_at(AC (&acc)[G][24], int32_t e, const SP *stage, int lidx, int slot,
                                        const HopCtx &hc)
 {
-    if constexpr (!BF) {
-        if (e < 0) return;
-    }
-    const bool drop = BF && e < 0;
+    if (e < 0) return;
     AC u[18];
-    load_link(hc.lk_b, (const LK *)nullptr, drop ? 0x80000000u : (uint32_t)slot * 2 * (uint32_t)sizeof(LK),
-              MU * 6 * hc.kstr, hc.kstr, u, (e & kNbrSign) != 0);
-    const SrcLds<SP, G> src{stage + (drop ? own : lidx) * G};
+    load_link(hc.lk_b, (const LK *)nullptr, (uint32_t)slot * 2 * (uint32_t)sizeof(LK), MU * 6 * hc.kstr, hc.kstr, u,
+              (e & kNbrSign) != 0);
+    const SrcLds<SP, G> src{stage + lidx * G};
     hop_term<MU, FWD, SP, AC, G>(acc, src, u);
 }
 
 // The upper half (hop_half) of the hop along MU with the neighbour's spinor
 // at LDS position lidx and the link at `slot`; zero when e is dropped.
-template <int MU, bool FWD, typename SP, typename LK, typename AC, int G, bool BF = false>
-__device__ __forceinline__ void hop_half_at(AC (&w)[G][12], int32_t e, const SP *stage, int lidx, int slot, int own,
+template <int MU, bool FWD, typename SP, typename LK, typename AC, int G>
+__device__ __forceinline__ void hop_half_at(AC (&w)[G][12], int32_t e, const SP *stage, int lidx, int slot,
                                             const HopCtx &hc)
 {
-    if constexpr (!BF) {
-        if (e < 0) {
+    if (e < 0) {
 #pragma unroll
-            for (int j = 0; j < G; j++)
+        for (int j = 0; j < G; j++)
 #pragma unroll
-                for (int i = 0; i < 12; i++) w[j][i] = 0;
-            return;
-        }
+            for (int i = 0; i < 12; i++) w[j][i] = 0;
+        return;
     }
-    const bool drop = BF && e < 0;
     AC u[18];
-    load_link(hc.lk_b, (const LK *)nullptr, drop ? 0x80000000u : (uint32_t)slot * 2 * (uint32_t)sizeof(LK),
-              MU * 6 * hc.kstr, hc.kstr, u, (e & kNbrSign) != 0);
-    const SrcLds<SP, G> src{stage + (drop ? own : lidx) * G};
+    load_link(hc.lk_b, (const LK *)nullptr, (uint32_t)slot * 2 * (uint32_t)sizeof(LK), MU * 6 * hc.kstr, hc.kstr, u,
+              (e & kNbrSign) != 0);
+    const SrcLds<SP, G> src{stage + lidx * G};
     hop_half<MU, FWD, SP, AC, G>(w, src, u);
+}
+
+// ------------------------------------------------------------- x0-walk
+
+// x0-walk of the hop over one block and one rhs: a workgroup walks the
+// block's x0-slices; thread k owns eo site k of every slice (hs sites per
+// parity and slice).  The eo order makes the x0-neighbour of a site the same
+// position k of the adjacent slice of the other parity, so each input slice
+// is read from global memory once: staged in LDS, it feeds the hops along
+// 1..3 of its own output slice (neighbours inside the slice) and the x0 hops
+// of the two adjacent output slices at position k.  One accumulator rides
+// along: it holds output slice q-1 until its x0+ hop arrives with input
+// slice q, and the x0- hop of output slice q+1, computed from input slice q,
+// waits as its 12-real upper half.
+
+struct WalkPos {
+    int p, hb, hs, k, s0, s1;  // output parity, sites per parity, per slice; thread; output slices [s0, s1)
+    const int32_t *nbt;        // neighbour table of the output parity
+};
+
+// Copies input slice q (component-major, kTile sites per component) into the stage.
+template <typename SP>
+__device__ __forceinline__ void walk_stage(SP *stage, const HopCtx &hc, int q, int hs, int k, bool live)
+{
+    if (!live) return;
+    const uint32_t vo = (uint32_t)(hc.grp_off + q * hs + k) * (uint32_t)sizeof(SP);
+    SP v[24];
+#pragma unroll
+    for (int c = 0; c < 24; c++) v[c] = bload<SP>(hc.in_b, vo, (uint32_t)c * hc.cstr);
+#pragma unroll
+    for (int c = 0; c < 24; c++) stage[c * kTile + k] = v[c];
+}
+
+// Input slice q is in the stage.  acc holds output slice q-1: its x0+ hop is
+// added and epi(acc, h) finishes it (site h) when it belongs to [s0, s1);
+// acc then restarts as output slice q (carry: the upper half of its x0- hop)
+// with the hops along 1..3, and carry becomes the x0- half of output slice
+// q+1.
+template <typename SP, typename LK, typename AC, typename EPI>
+__device__ __forceinline__ void walk_step(AC (&acc)[1][24], AC (&carry)[1][12], int q, const WalkPos &w,
+                                          const SP *stage, const HopCtx &hc, EPI &&epi)
+{
+    if (q - 1 >= w.s0) {
+        const int h = (q - 1) * w.hs + w.k;
+        hop_at<0, true, SP, LK, AC, 1>(acc, w.nbt[h * 8], stage, w.k, w.p * w.hb + h, hc);
+        epi(acc[0], h);
+    }
+    if (q >= w.s0 && q < w.s1) {
+#pragma unroll
+        for (int c = 0; c < 24; c++) acc[0][c] = 0;
+        hop_expand<0, false, AC>(acc[0], carry[0]);
+        const int h = q * w.hs + w.k, base = q * w.hs, oth = (1 - w.p) * w.hb, own = w.p * w.hb + h;
+        const int4 *t4 = reinterpret_cast<const int4 *>(w.nbt + h * 8);
+        const int4 a0 = t4[0], a1 = t4[1];
+        const int32_t nb[6] = {a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+        int li[6];
+#pragma unroll
+        for (int i = 0; i < 6; i++) li[i] = (nb[i] & kNbrMask) - base;
+        hop_at<1, true, SP, LK, AC, 1>(acc, nb[0], stage, li[0], own, hc);
+        hop_at<1, false, SP, LK, AC, 1>(acc, nb[1], stage, li[1], oth + base + li[1], hc);
+        hop_at<2, true, SP, LK, AC, 1>(acc, nb[2], stage, li[2], own, hc);
+        hop_at<2, false, SP, LK, AC, 1>(acc, nb[3], stage, li[3], oth + base + li[3], hc);
+        hop_at<3, true, SP, LK, AC, 1>(acc, nb[4], stage, li[4], own, hc);
+        hop_at<3, false, SP, LK, AC, 1>(acc, nb[5], stage, li[5], oth + base + li[5], hc);
+    }
+    if (q + 1 < w.s1) {
+        const int h = (q + 1) * w.hs + w.k;
+        hop_half_at<0, false, SP, LK, AC, 1>(carry, w.nbt[h * 8 + 1], stage, w.k, (1 - w.p) * w.hb + q * w.hs + w.k,
+                                             hc);
+    }
+}
+
+// The whole walk over output slices [w.s0, w.s1) (input slices one beyond
+// each end when they exist).  Every thread of the workgroup calls it (it has
+// barriers); threads k >= hs only take part in those.  epi(acc, h) writes
+// output site h.
+template <typename SP, typename LK, typename AC, typename EPI>
+__device__ __forceinline__ void walk_run(const WalkPos &w, int ns, SP *stage, const HopCtx &hc, EPI &&epi)
+{
+    const int qa = max(w.s0 - 1, 0), qb = min(w.s1 + 1, ns);
+    const bool live = w.k < w.hs;
+    AC acc[1][24], carry[1][12];
+#pragma unroll
+    for (int c = 0; c < 24; c++) acc[0][c] = 0;
+#pragma unroll
+    for (int c = 0; c < 12; c++) carry[0][c] = 0;
+    for (int q = qa; q < qb; q++) {
+        walk_stage(stage, hc, q, w.hs, w.k, live);
+        __syncthreads();
+        if (live) walk_step<SP, LK, AC>(acc, carry, q, w, stage, hc, epi);
+        __syncthreads();
+    }
+    // the block's last slice has no x0+ neighbour: when the walk ends there,
+    // its output is finished here
+    if (live && qb == w.s1) epi(acc[0], (w.s1 - 1) * w.hs + w.k);
 }
 
 }  // namespace dd

@@ -135,13 +135,19 @@ def _check_uneven(u, x, info, nrhs):
             assert _cfg.rel_err(x[r, sl], xo) <= 1e-8
 
 
-@pytest.mark.parametrize("inner", ["bf16", "f32", "f64"])
-def test_uneven_blocks_gmres(ctx, uneven, inner):
+@pytest.mark.parametrize("inner,walk", [("bf16", 0), ("f32", 0), ("f64", 0), ("bf16", -1), ("f64", -1)])
+def test_uneven_blocks_gmres(ctx, uneven, inner, walk):
+    """walk 0: the kernel's hops walk the x0-slices; -1: the kernel whose hops read every neighbour
+    from global memory."""
     from paper_2211_06902_amd import dd
 
     g = ctx.load_gauge(uneven["blk"], _dev(uneven["U"]), "bf16" if inner == "bf16" else "f32")
-    x, info, st = ctx.block_solve(uneven["blk"], g, uneven["kappa"], _dev(uneven["b"]),
-                                  params=dd.solve_params(method=dd.GMRES, inner_prec=inner))
+    try:
+        ctx.tune_set(dd.TUNE_HOP_WALK, walk)
+        x, info, st = ctx.block_solve(uneven["blk"], g, uneven["kappa"], _dev(uneven["b"]),
+                                      params=dd.solve_params(method=dd.GMRES, inner_prec=inner))
+    finally:
+        ctx.tune_set(dd.TUNE_HOP_WALK, 0)
     print("uneven %s: outer %d, max steps %d" % (inner, info["outer_cycles"], info["inner_iterations"]))
     assert st == dd.DD_OK
     _check_uneven(uneven, x, info, 3)
