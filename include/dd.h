@@ -262,6 +262,11 @@ dd_status dd_multiboson_action(dd_ctx *ctx, const dd_blocks *blocks, const dd_ga
  *                        fits.  Results depend on the threads per workgroup
  *                        only through the fixed summation order of the
  *                        workgroup's dot products. */
+/* DD_TUNE_GMRES_REORTH: Gram-Schmidt of the persistent GMRES.  Each step
+ * projects w = Dhat v_j once (classical Gram-Schmidt, FP64 sums and
+ * updates) and reorthogonalizes with a second pass when |w - V h| keeps at
+ * most p percent of |w|: 0 (default) p = 10, 1..100 that p (100: always, the
+ * CGS2 scheme), -1 never. */
 /* DD_TUNE_MB_FIELDS: fields dd_multiboson_action hands to one block solve
  * (0 = as many as fit in 60 % of the free device memory).
  * DD_TUNE_NN_KERNEL: BF16 network kernel, 1 (default) one workgroup per block
@@ -276,7 +281,8 @@ enum {
     DD_TUNE_GMRES_WG_PER_CU = 5,
     DD_TUNE_MB_FIELDS = 6,
     DD_TUNE_NN_KERNEL = 7,
-    DD_TUNE_HOP_WALK = 8
+    DD_TUNE_HOP_WALK = 8,
+    DD_TUNE_GMRES_REORTH = 9
 };
 dd_status dd_tune_set(dd_ctx *ctx, int32_t what, int32_t value);
 

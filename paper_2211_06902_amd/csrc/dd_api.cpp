@@ -594,6 +594,11 @@ dd_status dd_tune_set(dd_ctx *ctx, int32_t what, int32_t value)
         ctx->hop_walk = value;
         return DD_OK;
     }
+    if (what == DD_TUNE_GMRES_REORTH) {
+        if (value < -1 || value > 100) return fail(ctx, DD_EINVAL, "reorthogonalization threshold must be -1, 0 or 1..100");
+        ctx->gm_reorth = value;
+        return DD_OK;
+    }
     if (what == DD_TUNE_GMRES_THREADS) {
         if (value != 0 && value != 256 && value != 512)
             return fail(ctx, DD_EINVAL, "GMRES threads per workgroup must be 0, 256 or 512");

@@ -388,27 +388,39 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
                     wg_hop<SP, LK, NT>(g, 0, tmp, w, src, cs1, ch1, nullptr, 0.0);
                 }
                 __syncthreads();
-                // first Gram-Schmidt pass: h = V^H w, w -= V h
-                gs_dots<SP, M, NT, NV>(sl, j + 1, h, j, false, sum, red2);
+                // Classical Gram-Schmidt with FP64 sums and updates: h = V^H w and
+                // |w|^2 in one pass; then |w - V h|^2 = |w|^2 - |h|^2 (V
+                // orthonormal).  When that keeps less than a fraction eta of |w|
+                // (cancellation), a second pass reorthogonalizes (CGS2): w -= V h,
+                // then the corrections c = V^H w and |w|^2.  The last pass writes
+                // v_{j+1} = (w - V s) / hn with s = h, or s = c after a second pass.
+                gs_dots<SP, M, NT, NV>(sl, j + 1, h, j, true, sum, red2);
                 if (threadIdx.x == 0)
                     for (int i = 0; i <= j; i++) {
                         Hm[(i * M + j) * 2] = sum[2 * i];
                         Hm[(i * M + j) * 2 + 1] = sum[2 * i + 1];
                     }
+                double s2 = 0;
+                for (int i = 0; i <= j; i++) s2 += sum[2 * i] * sum[2 * i] + sum[2 * i + 1] * sum[2 * i + 1];
+                double hh = sum[NV - 1] - s2;
                 const uint32_t wso = (uint32_t)(j + 1) * sl.vbytes;
-                combine<SP, M, NT>(sl, sl.b, wso, h, j + 1, sum, -1.0, 1.0);
-                __syncthreads();
-                // second pass: the corrections c = V^H w and |w|^2
-                gs_dots<SP, M, NT, NV>(sl, j + 1, h, j, true, sum, red2);
-                // |w - V c|^2 = |w|^2 - |c|^2 for orthonormal V; c is a rounding-level correction
-                double c2 = 0;
-                for (int i = 0; i <= j; i++) c2 += sum[2 * i] * sum[2 * i] + sum[2 * i + 1] * sum[2 * i + 1];
-                const double hn = sqrt(fmax(sum[NV - 1] - c2, 0.0));
+                const bool second = !(hh > a.reorth2 * sum[NV - 1]);
+                if (second) {
+                    combine<SP, M, NT>(sl, sl.b, wso, h, j + 1, sum, -1.0, 1.0);
+                    __syncthreads();
+                    gs_dots<SP, M, NT, NV>(sl, j + 1, h, j, true, sum, red2);
+                    s2 = 0;
+                    for (int i = 0; i <= j; i++) s2 += sum[2 * i] * sum[2 * i] + sum[2 * i + 1] * sum[2 * i + 1];
+                    hh = sum[NV - 1] - s2;
+                    if (threadIdx.x == 0)
+                        for (int i = 0; i <= j; i++) {
+                            Hm[(i * M + j) * 2] += sum[2 * i];
+                            Hm[(i * M + j) * 2 + 1] += sum[2 * i + 1];
+                        }
+                    moved += (2.0 * (j + 1) + 4.0) * vb;
+                }
+                const double hn = sqrt(fmax(hh, 0.0));
                 if (threadIdx.x == 0) {
-                    for (int i = 0; i <= j; i++) {
-                        Hm[(i * M + j) * 2] += sum[2 * i];
-                        Hm[(i * M + j) * 2 + 1] += sum[2 * i + 1];
-                    }
                     // previous rotations on column j: (a, b) <- (c a + s b, -conj(s) a + c b)
                     for (int i = 0; i < j; i++) {
                         double *pa = Hm + (i * M + j) * 2, *pb2 = Hm + ((i + 1) * M + j) * 2;
@@ -465,8 +477,9 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
                     k = j + 1;
                 }
                 it++;
-                // two hops (5 vectors, links twice) and four Gram-Schmidt passes
-                moved += (4.0 * (j + 1) + 11.0) * vb + 2.0 * lb;
+                // two hops (5 vectors, links twice) and two Gram-Schmidt passes
+                // (the second pair counted above)
+                moved += (2.0 * (j + 1) + 8.0) * vb + 2.0 * lb;
                 __syncthreads();
             }
             // x += V y with R y = g (back substitution on the rotated Hessenberg matrix)

@@ -21,6 +21,9 @@ constexpr int kMaxRhs = 64;
 constexpr int kNRed = 4;
 // Links are stored as their first two rows (6 complex entries per direction);
 // the kernels rebuild the third row of the SU(3) matrix as conj(row0 x row1).
+// GMRES: reorthogonalize (a second Gram-Schmidt pass) when |w - V h| keeps
+// at most this percentage of |w|
+constexpr int kGmReorthPercent = 10;
 constexpr int kLinkK = 6;
 constexpr int kLinkReals = 4 * kLinkK * 2;  // per site: 4 directions
 // Neighbour-table entry flags: bit 30 = hop across the antiperiodic time edge.
@@ -51,6 +54,7 @@ struct dd_ctx {
     int rhs_group[2] = {0, 0};  // forced rhs per thread for FP64 / FP32 spinors (0 = automatic)
     bool hop_lds = true;        // stage the hop's chunk of the input in LDS
     int hop_walk = 0;           // x0-walk of the hop: 0 automatic, -1 off, n >= 1 segments per block
+    int gm_reorth = 0;          // GMRES reorthogonalization threshold: 0 default, -1 never, 1..100 percent of |w|
     int gm_threads = 0;         // persistent GMRES: threads per workgroup (0 = default)
     int gm_queues = 0;          // persistent GMRES: work queues, 1 or 8 (0 = default)
     int gm_wg_per_cu = 0;       // persistent GMRES: resident workgroups per CU (0 = all that fit)
@@ -250,6 +254,7 @@ struct GmArgs {
     double *relres;           // [np] last residual estimate / |f| (may be null)
     const int32_t *ext;       // [nb][4] block extents
     int walk;                 // 1: the hops walk the x0-slices (every block admits it)
+    double reorth2;           // second Gram-Schmidt pass when |w - V h|^2 <= reorth2 |w|^2
 };
 
 // basis vectors the kernel for restart length m keeps per workgroup (its

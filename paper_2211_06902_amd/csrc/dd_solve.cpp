@@ -385,6 +385,10 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
             ga.relres = nullptr;
             ga.ext = B->d_ext;
             ga.walk = gmres_walk(ctx, B) ? 1 : 0;
+            {
+                const int pc = ctx->gm_reorth == 0 ? kGmReorthPercent : ctx->gm_reorth;
+                ga.reorth2 = pc < 0 ? -1.0 : (pc / 100.0) * (pc / 100.0);
+            }
             ga.resume = 0;
             ga.r = gm_r;
             ga.z0 = nullptr;

@@ -253,3 +253,21 @@ def test_c3_full_size_bf16_gmres(ctx):
     torch.cuda.empty_cache()
     g.close()
     blk.close()
+
+
+@pytest.mark.parametrize("reorth", [-1, 100, 40])
+def test_gmres_reorthogonalization_thresholds(ctx, uneven, reorth):
+    """Classical Gram-Schmidt once (-1), twice in every step (100) or twice when |w - V h| < 40 % of
+    |w|: every setting converges to the oracle's solution."""
+    from paper_2211_06902_amd import dd
+
+    g = ctx.load_gauge(uneven["blk"], _dev(uneven["U"]), "f32")
+    try:
+        ctx.tune_set(dd.TUNE_GMRES_REORTH, reorth)
+        x, info, st = ctx.block_solve(uneven["blk"], g, uneven["kappa"], _dev(uneven["b"]),
+                                      params=dd.solve_params(method=dd.GMRES, inner_prec="f32"))
+    finally:
+        ctx.tune_set(dd.TUNE_GMRES_REORTH, 0)
+    assert st == dd.DD_OK
+    _check_uneven(uneven, x, info, 3)
+    g.close()
