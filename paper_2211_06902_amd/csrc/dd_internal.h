@@ -302,9 +302,13 @@ hipError_t launch_adam(float *w, const float *g, float *m, float *v, int64_t n, 
 // (act applied) or, with out_f32, FP32 [rows][24]
 // variant 0: neighbour rows gathered from global memory; 1: one workgroup per
 // block walking its x0-slices with three input slices in LDS (rows per slice <= 512)
-// (variant 1 skips blocks whose pair pair0 + block index has active[] == 0, when active is given)
+// (variant 1 skips blocks whose pair pair0 + block index has active[] == 0, when active is given).
+// With origin ([nb][4] block origins; pair p is block p % nb), variant 1 uses
+// the site parity: parity_mode 1 multiplies only the taps reaching even sites
+// (the input must be zero on odd sites), 2 computes only the even output rows.
 hipError_t launch_conv_mfma(const uint16_t *X, const uint16_t *Wt, void *Y, int64_t nrows, const NnExt &e, int act,
-                            bool out_f32, int variant, const int32_t *active, int pair0, hipStream_t st);
+                            bool out_f32, int variant, const int32_t *active, int pair0, const int32_t *origin, int nb,
+                            int parity_mode, hipStream_t st);
 hipError_t launch_weights_bf16(const float *W, uint16_t *Wt, int cin, int cout, hipStream_t st);
 hipError_t launch_half_rows_bf16(const void *half, uint16_t *rows, dd_prec sp, const HalfRows &hr, hipStream_t st);
 hipError_t launch_rows_f32_to_bf16(const float *X, uint16_t *Xb, int64_t nrows, hipStream_t st);

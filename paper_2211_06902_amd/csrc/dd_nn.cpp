@@ -55,7 +55,7 @@ hipError_t nn_forward(dd_ctx *ctx, const dd_nn *nn, const float *X, float *Z1, f
 bool nn_fits(const dd_nn *nn, const dd_blocks *B) { return same_shape(nn, B); }
 
 hipError_t nn_forward_bf16(dd_ctx *ctx, dd_nn *nn, const uint16_t *Xb, uint16_t *Zb1, uint16_t *Zb2, float *O,
-                           int64_t nrows, const int32_t *active, int pair0)
+                           int64_t nrows, const int32_t *active, int pair0, const int32_t *origin, int nb)
 {
     hipStream_t st = ctx->stream;
     hipError_t e = hipSuccess;
@@ -66,12 +66,16 @@ hipError_t nn_forward_bf16(dd_ctx *ctx, dd_nn *nn, const uint16_t *Xb, uint16_t 
         nn->bf16_step = nn->step;
     }
     const int v = ctx->nn_kernel;
-    if ((e = launch_conv_mfma(Xb, nn->d_wbf, Zb1, nrows, nn->e, nn->act, false, v, active, pair0, st)) != hipSuccess)
-        return e;
-    if ((e = launch_conv_mfma(Zb1, nn->d_wbf + 81 * 1024, Zb2, nrows, nn->e, nn->act, false, v, active, pair0, st)) !=
+    // with block origins (an even half field in, its even sites out): layer 1
+    // skips the zero odd input sites, layer 3 computes the even sites only
+    if ((e = launch_conv_mfma(Xb, nn->d_wbf, Zb1, nrows, nn->e, nn->act, false, v, active, pair0, origin, nb, 1, st)) !=
         hipSuccess)
         return e;
-    return launch_conv_mfma(Zb2, nn->d_wbf + 2 * 81 * 1024, O, nrows, nn->e, 0, true, v, active, pair0, st);
+    if ((e = launch_conv_mfma(Zb1, nn->d_wbf + 81 * 1024, Zb2, nrows, nn->e, nn->act, false, v, active, pair0, origin,
+                              nb, 0, st)) != hipSuccess)
+        return e;
+    return launch_conv_mfma(Zb2, nn->d_wbf + 2 * 81 * 1024, O, nrows, nn->e, 0, true, v, active, pair0, origin, nb, 2,
+                            st);
 }
 
 hipError_t nn_apply_half(dd_ctx *ctx, dd_nn *nn, const dd_blocks *B, const void *v, void *z, int n_rhs, dd_prec sp,
@@ -98,7 +102,8 @@ hipError_t nn_apply_half(dd_ctx *ctx, dd_nn *nn, const dd_blocks *B, const void 
             e = launch_half_rows_bf16(v, (uint16_t *)X, sp, hr, ctx->stream);
             TimedLaunch tl(ctx, DD_KCLASS_NN_BF16, 2.0 * 81 * (24 * 32 + 32 * 32 + 32 * 24) * (double)nrows);
             if (e == hipSuccess)
-                e = nn_forward_bf16(ctx, nn, (uint16_t *)X, (uint16_t *)Z1, (uint16_t *)Z2, O, nrows, active, p0);
+                e = nn_forward_bf16(ctx, nn, (uint16_t *)X, (uint16_t *)Z1, (uint16_t *)Z2, O, nrows, active, p0,
+                                    B->d_origin, B->nb);
         } else {
             e = launch_half_rows(v, (float *)X, nullptr, sp, hr, 0, ctx->stream);
             if (e == hipSuccess) e = nn_forward(ctx, nn, (float *)X, (float *)Z1, (float *)Z2, O, nrows);

@@ -294,15 +294,19 @@ __global__ void k_half_to_rows(const SP *__restrict__ half, float *__restrict__ 
     const int pair = hr.pair0 + pl, b = pair % hr.nb, r = pair / hr.nb;
     const int hb = hr.h[b];
     const int s = hr.perm[hr.perm_off[b] + q];
-    float *row = rows + ((int64_t)pl * hr.S + s) * 24;
+    float v[24];
     if (q < hb) {
         const SP *src = half + (hr.soff[b] >> 1) * 24 * hr.n_rhs + (int64_t)r * 24 * hb + q;
 #pragma unroll
-        for (int c = 0; c < 24; c++) row[c] = (float)src[(int64_t)c * hb];
+        for (int c = 0; c < 24; c++) v[c] = (float)src[(int64_t)c * hb];
     } else {
 #pragma unroll
-        for (int c = 0; c < 24; c++) row[c] = 0.0f;
+        for (int c = 0; c < 24; c++) v[c] = 0.0f;
     }
+    // a row is 96 contiguous bytes: six 16-byte stores
+    float4 *row = reinterpret_cast<float4 *>(rows + ((int64_t)pl * hr.S + s) * 24);
+#pragma unroll
+    for (int i = 0; i < 6; i++) row[i] = make_float4(v[4 * i], v[4 * i + 1], v[4 * i + 2], v[4 * i + 3]);
 }
 
 // even sites of network rows back into an even half field
@@ -316,10 +320,19 @@ __global__ void k_rows_to_half(const float *__restrict__ rows, SP *__restrict__ 
     const int hb = hr.h[b];
     if (q >= hb) return;
     const int s = hr.perm[hr.perm_off[b] + q];
-    const float *row = rows + ((int64_t)pl * hr.S + s) * 24;
+    const float4 *row = reinterpret_cast<const float4 *>(rows + ((int64_t)pl * hr.S + s) * 24);
+    float v[24];
+#pragma unroll
+    for (int i = 0; i < 6; i++) {
+        const float4 t = row[i];
+        v[4 * i] = t.x;
+        v[4 * i + 1] = t.y;
+        v[4 * i + 2] = t.z;
+        v[4 * i + 3] = t.w;
+    }
     SP *dst = half + (hr.soff[b] >> 1) * 24 * hr.n_rhs + (int64_t)r * 24 * hb + q;
 #pragma unroll
-    for (int c = 0; c < 24; c++) dst[(int64_t)c * hb] = (SP)row[c];
+    for (int c = 0; c < 24; c++) dst[(int64_t)c * hb] = (SP)v[c];
 }
 
 // ------------------------------------------------- BF16 matrix-core inference
@@ -415,15 +428,25 @@ __global__ void __launch_bounds__(256) k_conv_mfma(const uint16_t *__restrict__ 
 // x0-slices, keeping the three input slices x0 - 1, x0, x0 + 1 in a ring of LDS
 // buffers (rows padded to 80 bytes against bank conflicts; slices outside the
 // block are zero), so every input row is read from HBM once per layer and the
-// 81 taps read their neighbour rows from LDS.  Wave w computes output rows
-// 64 w .. 64 w + 63 of the slice.  Needs e1 e2 e3 <= 512.
+// 81 taps read their neighbour rows from LDS.  Needs e1 e2 e3 <= 512.
+//
+// PAR = 0: wave w computes output rows 64 w .. 64 w + 63 of the slice.
+// PAR = 1, 2 (the solver's even half fields, blocks of even extents): waves
+// 0..3 take the rows with y1 + y2 + y3 even, waves 4..7 the odd ones, so that
+// the global parity of a wave's rows is one value per slice.  PAR = 1: the
+// input is zero on odd sites, so only the taps reaching even sites are
+// multiplied (41 or 40 of 81); PAR = 2: only the even output sites are
+// needed, so waves whose rows are odd in a slice skip it.  The skipped
+// products are exact zeros or unused rows: the results of the rows kept are
+// the same.  origin: the block origins [nb][4] (global parity of a site =
+// parity of origin + local coordinates).
 constexpr int kSliceMax = 512;
 constexpr int kRowPad = 40;  // bf16 per LDS row (32 + 8 padding)
 
-template <int ACT, bool OUT_F32>
+template <int ACT, bool OUT_F32, int PAR>
 __global__ void __launch_bounds__(512) k_conv_mfma_lds(const uint16_t *__restrict__ X, const uint16_t *__restrict__ Wt,
                                                        void *__restrict__ Y, NnExt e, const int32_t *__restrict__ active,
-                                                       int pair0)
+                                                       int pair0, const int32_t *__restrict__ origin, int nb)
 {
     __shared__ uint16_t ring[3][kSliceMax][kRowPad];
     // blocks whose (block, rhs) pair is no longer iterated are skipped
@@ -432,18 +455,39 @@ __global__ void __launch_bounds__(512) k_conv_mfma_lds(const uint16_t *__restric
     const int kg = lane >> 4, li = lane & 15;
     const int R = e.e[1] * e.e[2] * e.e[3];
     const int64_t base = (int64_t)blockIdx.x * e.S;  // first row of this block
-    // output coordinates (x1, x2, x3) of this lane's row in each 16-row tile
-    int oc[4][3];
+    // parity class of the wave's rows and the parity of the block origin
+    const int cls = PAR ? wave >> 2 : 0;
+    int opar = 0;
+    if constexpr (PAR != 0) {
+        const int32_t *o = origin + 4 * ((pair0 + (int)blockIdx.x) % nb);
+        opar = (o[0] + o[1] + o[2] + o[3]) & 1;
+    }
+    // output coordinates (x1, x2, x3) and slice row of this lane's row in each 16-row tile
+    int oc[4][3], orw[4];
     bool orow[4];
 #pragma unroll
     for (int rt = 0; rt < 4; rt++) {
-        int r = wave * 64 + rt * 16 + li;
-        orow[rt] = r < R;
-        r = min(r, R - 1);
-        oc[rt][2] = r % e.e[3];
-        r /= e.e[3];
-        oc[rt][1] = r % e.e[2];
-        oc[rt][0] = r / e.e[2];
+        if constexpr (PAR == 0) {
+            int r = wave * 64 + rt * 16 + li;
+            orow[rt] = r < R;
+            r = min(r, R - 1);
+            orw[rt] = r;
+            oc[rt][2] = r % e.e[3];
+            r /= e.e[3];
+            oc[rt][1] = r % e.e[2];
+            oc[rt][0] = r / e.e[2];
+        } else {
+            // j-th row of class cls: line (y1, y2), y3 = 2 m + ((cls + y1 + y2) & 1)
+            const int h3 = e.e[3] >> 1;
+            int j = (wave & 3) * 64 + rt * 16 + li;
+            orow[rt] = j < (R >> 1);
+            j = min(j, (R >> 1) - 1);
+            const int m = j % h3, line = j / h3;
+            oc[rt][1] = line % e.e[2];
+            oc[rt][0] = line / e.e[2];
+            oc[rt][2] = 2 * m + ((cls + oc[rt][0] + oc[rt][1]) & 1);
+            orw[rt] = (oc[rt][0] * e.e[2] + oc[rt][1]) * e.e[3] + oc[rt][2];
+        }
     }
     auto load_slice = [&](int s) {
         uint16_t(*dst)[kRowPad] = ring[(s + 3) % 3];
@@ -461,17 +505,23 @@ __global__ void __launch_bounds__(512) k_conv_mfma_lds(const uint16_t *__restric
     __syncthreads();
     const bf16x8 zero = {};
     for (int a = 0; a < e.e[0]; a++) {
+        // global parity of this wave's output rows in slice a
+        const int gpar = (opar + a + cls) & 1;
+        const bool work = PAR != 2 || gpar == 0;
         f32x4 acc[4][2];
 #pragma unroll
         for (int rt = 0; rt < 4; rt++)
 #pragma unroll
             for (int ct = 0; ct < 2; ct++) acc[rt][ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        if (work)
         for (int t0 = -1; t0 <= 1; t0++) {
             const uint16_t(*src)[kRowPad] = ring[(a + t0 + 3) % 3];
             for (int t1 = -1; t1 <= 1; t1++)
                 for (int t2 = -1; t2 <= 1; t2++) {
 #pragma unroll
                     for (int t3 = -1; t3 <= 1; t3++) {
+                        // PAR = 1: the tap reaches an odd (zero) input site
+                        if (PAR == 1 && ((gpar + t0 + t1 + t2 + t3) & 1)) continue;
                         const int tap = ((t0 + 1) * 3 + (t1 + 1)) * 9 + (t2 + 1) * 3 + (t3 + 1);
                         bf16x8 bv[2];
 #pragma unroll
@@ -495,15 +545,19 @@ __global__ void __launch_bounds__(512) k_conv_mfma_lds(const uint16_t *__restric
                 }
         }
         // store this slice's output rows
+        if (work)
 #pragma unroll
         for (int rt = 0; rt < 4; rt++)
 #pragma unroll
             for (int ct = 0; ct < 2; ct++)
 #pragma unroll
                 for (int i = 0; i < 4; i++) {
-                    const int r = wave * 64 + rt * 16 + 4 * kg + i;
+                    // accumulator element i of lane (kg, li) is row 4 kg + i, column li of the tile
+                    const int src_lane = 4 * kg + i;
+                    const int r = __shfl(orw[rt], src_lane, 64);
+                    const bool live = __shfl((int)orow[rt], src_lane, 64) != 0;
                     const int col = ct * 16 + li;
-                    if (r >= R) continue;
+                    if (!live) continue;
                     const int64_t row = base + (int64_t)a * R + r;
                     float v = acc[rt][ct][i];
                     if constexpr (OUT_F32) {
@@ -538,17 +592,20 @@ __global__ void k_half_to_rows_bf16(const SP *__restrict__ half, uint16_t *__res
     const int pair = hr.pair0 + pl, b = pair % hr.nb, r = pair / hr.nb;
     const int hb = hr.h[b];
     const int s = hr.perm[hr.perm_off[b] + q];
-    uint16_t *row = rows + ((int64_t)pl * hr.S + s) * 32;
+    uint32_t pk[16];  // channel pairs (2c, 2c+1), low half first
+#pragma unroll
+    for (int i = 0; i < 16; i++) pk[i] = 0;
     if (q < hb) {
         const SP *src = half + (hr.soff[b] >> 1) * 24 * hr.n_rhs + (int64_t)r * 24 * hb + q;
 #pragma unroll
-        for (int c = 0; c < 24; c++) row[c] = f2bf((float)src[(int64_t)c * hb]);
-    } else {
-#pragma unroll
-        for (int c = 0; c < 24; c++) row[c] = 0;
+        for (int c = 0; c < 12; c++)
+            pk[c] = (uint32_t)f2bf((float)src[(int64_t)(2 * c) * hb]) |
+                    ((uint32_t)f2bf((float)src[(int64_t)(2 * c + 1) * hb]) << 16);
     }
+    // a row is 64 contiguous bytes: four 16-byte stores
+    uint4 *row = reinterpret_cast<uint4 *>(rows + ((int64_t)pl * hr.S + s) * 32);
 #pragma unroll
-    for (int c = 24; c < 32; c++) row[c] = 0;
+    for (int i = 0; i < 4; i++) row[i] = make_uint4(pk[4 * i], pk[4 * i + 1], pk[4 * i + 2], pk[4 * i + 3]);
 }
 
 // FP32 rows [rows][24] -> BF16 rows [rows][32]
@@ -647,15 +704,24 @@ hipError_t launch_half_rows(const void *half, float *rows, void *half_out, dd_pr
 }
 
 hipError_t launch_conv_mfma(const uint16_t *X, const uint16_t *Wt, void *Y, int64_t nrows, const NnExt &e, int act,
-                            bool out_f32, int variant, const int32_t *active, int pair0, hipStream_t st)
+                            bool out_f32, int variant, const int32_t *active, int pair0, const int32_t *origin, int nb,
+                            int parity_mode, hipStream_t st)
 {
     if (nrows <= 0) return hipSuccess;
     const int R = e.e[1] * e.e[2] * e.e[3];
     if (R <= kSliceMax && nrows % e.S == 0 && variant == 1) {
-        const dim3 g((unsigned)(nrows / e.S));
-        if (out_f32) hipLaunchKernelGGL((k_conv_mfma_lds<0, true>), g, dim3(512), 0, st, X, Wt, Y, e, active, pair0);
-        else if (act) hipLaunchKernelGGL((k_conv_mfma_lds<1, false>), g, dim3(512), 0, st, X, Wt, Y, e, active, pair0);
-        else hipLaunchKernelGGL((k_conv_mfma_lds<0, false>), g, dim3(512), 0, st, X, Wt, Y, e, active, pair0);
+        const dim3 g((unsigned)(nrows / e.S)), t(512);
+        // the parity modes need even e3 (rows of one class per line) and the block origins
+        const int par = origin && (e.e[3] & 1) == 0 ? parity_mode : 0;
+#define CM(A, F, P) hipLaunchKernelGGL((k_conv_mfma_lds<A, F, P>), g, t, 0, st, X, Wt, Y, e, active, pair0, origin, nb)
+        if (out_f32) {
+            if (par == 2) CM(0, true, 2); else CM(0, true, 0);
+        } else if (act) {
+            if (par == 1) CM(1, false, 1); else CM(1, false, 0);
+        } else {
+            if (par == 1) CM(0, false, 1); else CM(0, false, 0);
+        }
+#undef CM
         return hipGetLastError();
     }
     const dim3 g((unsigned)((nrows + 255) / 256));

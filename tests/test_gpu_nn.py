@@ -279,3 +279,29 @@ def test_network_on_blocks_of_another_extent_is_rejected(ctx, toy):
                         params=dd.solve_params(method=dd.GMRES, precond=toy["net"]))
     g.close()
     blk.close()
+
+
+def test_network_parity_modes_change_nothing(ctx, toy):
+    """Inside the solver the BF16 network gets an even half field (odd sites zero) and only its even
+    output sites are used: the LDS kernel then skips the taps that reach the zero odd sites (layer 1)
+    and the odd output rows (layer 3).  The solve is the same as with the global-gather kernel, which
+    multiplies everything."""
+    from oracle import geometry
+    from tests import _cfg
+
+    from paper_2211_06902_amd import dd
+
+    b = synth.spinor_field(toy["L"], 4, 63)[:, _cfg.block_sites(toy["L"], geometry.tile_boxes(toy["L"], [[4, 4]] * 4))]
+    bd = _dev(b)
+    prm = dd.solve_params(inner_prec="f32", precond=toy["net"])
+    out = []
+    try:
+        for k in (0, 1):
+            ctx.tune_set(dd.TUNE_NN_KERNEL, k)
+            x, info, st = ctx.block_solve(toy["blk"], toy["g"], toy["kappa"], bd, params=prm)
+            assert st == dd.DD_OK
+            out.append((x.cpu().numpy(), info["iters"].copy()))
+    finally:
+        ctx.tune_set(dd.TUNE_NN_KERNEL, 1)
+    assert np.array_equal(out[0][1], out[1][1])
+    assert _cfg.rel_err(out[1][0], out[0][0]) <= 1e-12
