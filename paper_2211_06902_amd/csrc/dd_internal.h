@@ -306,9 +306,18 @@ hipError_t launch_adam(float *w, const float *g, float *m, float *v, int64_t n, 
 // With origin ([nb][4] block origins; pair p is block p % nb), variant 1 uses
 // the site parity: parity_mode 1 multiplies only the taps reaching even sites
 // (the input must be zero on odd sites), 2 computes only the even output rows.
+// parity_mode 3: as 1, with the input read from an even half field (FP32) instead of X.
+struct NnHalfIn {
+    const float *half;        // even half field of all pairs (library layout)
+    const int32_t *perm;      // eo position -> block-local canonical site
+    const int64_t *perm_off;  // [nb]
+    const int64_t *soff;      // [nb + 1]
+    const int32_t *h;         // [nb]
+    int n_rhs;
+};
 hipError_t launch_conv_mfma(const uint16_t *X, const uint16_t *Wt, void *Y, int64_t nrows, const NnExt &e, int act,
                             bool out_f32, int variant, const int32_t *active, int pair0, const int32_t *origin, int nb,
-                            int parity_mode, hipStream_t st);
+                            int parity_mode, hipStream_t st, const NnHalfIn *hin = nullptr);
 hipError_t launch_weights_bf16(const float *W, uint16_t *Wt, int cin, int cout, hipStream_t st);
 hipError_t launch_half_rows_bf16(const void *half, uint16_t *rows, dd_prec sp, const HalfRows &hr, hipStream_t st);
 hipError_t launch_rows_f32_to_bf16(const float *X, uint16_t *Xb, int64_t nrows, hipStream_t st);

@@ -55,7 +55,8 @@ hipError_t nn_forward(dd_ctx *ctx, const dd_nn *nn, const float *X, float *Z1, f
 bool nn_fits(const dd_nn *nn, const dd_blocks *B) { return same_shape(nn, B); }
 
 hipError_t nn_forward_bf16(dd_ctx *ctx, dd_nn *nn, const uint16_t *Xb, uint16_t *Zb1, uint16_t *Zb2, float *O,
-                           int64_t nrows, const int32_t *active, int pair0, const int32_t *origin, int nb)
+                           int64_t nrows, const int32_t *active, int pair0, const int32_t *origin, int nb,
+                           const NnHalfIn *hin)
 {
     hipStream_t st = ctx->stream;
     hipError_t e = hipSuccess;
@@ -67,15 +68,22 @@ hipError_t nn_forward_bf16(dd_ctx *ctx, dd_nn *nn, const uint16_t *Xb, uint16_t 
     }
     const int v = ctx->nn_kernel;
     // with block origins (an even half field in, its even sites out): layer 1
-    // skips the zero odd input sites, layer 3 computes the even sites only
-    if ((e = launch_conv_mfma(Xb, nn->d_wbf, Zb1, nrows, nn->e, nn->act, false, v, active, pair0, origin, nb, 1, st)) !=
-        hipSuccess)
+    // skips the zero odd input sites (reading the half field itself when hin
+    // is given), layer 3 computes the even sites only
+    if ((e = launch_conv_mfma(Xb, nn->d_wbf, Zb1, nrows, nn->e, nn->act, false, v, active, pair0, origin, nb,
+                              hin ? 3 : 1, st, hin)) != hipSuccess)
         return e;
     if ((e = launch_conv_mfma(Zb1, nn->d_wbf + 81 * 1024, Zb2, nrows, nn->e, nn->act, false, v, active, pair0, origin,
                               nb, 0, st)) != hipSuccess)
         return e;
     return launch_conv_mfma(Zb2, nn->d_wbf + 2 * 81 * 1024, O, nrows, nn->e, 0, true, v, active, pair0, origin, nb, 2,
                             st);
+}
+
+// the LDS kernel handles the block shape (x0-slices of at most 512 sites, even extents)
+static bool nn_slice_fits(const dd_nn *nn)
+{
+    return nn->e.e[1] * nn->e.e[2] * nn->e.e[3] <= 512 && (nn->e.e[3] & 1) == 0;
 }
 
 hipError_t nn_apply_half(dd_ctx *ctx, dd_nn *nn, const dd_blocks *B, const void *v, void *z, int n_rhs, dd_prec sp,
@@ -99,11 +107,14 @@ hipError_t nn_apply_half(dd_ctx *ctx, dd_nn *nn, const dd_blocks *B, const void 
         hr.npairs = std::min(chunk, np - p0);
         const int64_t nrows = (int64_t)hr.npairs * S;
         if (bf) {
-            e = launch_half_rows_bf16(v, (uint16_t *)X, sp, hr, ctx->stream);
+            // FP32 half fields feed the first layer directly (LDS kernel); else via BF16 rows
+            const bool fused = sp == DD_F32 && ctx->nn_kernel == 1 && nn_slice_fits(nn);
+            const NnHalfIn hin{(const float *)v, B->d_perm, B->d_perm_off, B->d_soff, B->d_h, n_rhs};
+            if (!fused) e = launch_half_rows_bf16(v, (uint16_t *)X, sp, hr, ctx->stream);
             TimedLaunch tl(ctx, DD_KCLASS_NN_BF16, 2.0 * 81 * (24 * 32 + 32 * 32 + 32 * 24) * (double)nrows);
             if (e == hipSuccess)
                 e = nn_forward_bf16(ctx, nn, (uint16_t *)X, (uint16_t *)Z1, (uint16_t *)Z2, O, nrows, active, p0,
-                                    B->d_origin, B->nb);
+                                    B->d_origin, B->nb, fused ? &hin : nullptr);
         } else {
             e = launch_half_rows(v, (float *)X, nullptr, sp, hr, 0, ctx->stream);
             if (e == hipSuccess) e = nn_forward(ctx, nn, (float *)X, (float *)Z1, (float *)Z2, O, nrows);

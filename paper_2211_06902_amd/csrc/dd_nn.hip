@@ -431,22 +431,24 @@ __global__ void __launch_bounds__(256) k_conv_mfma(const uint16_t *__restrict__ 
 // 81 taps read their neighbour rows from LDS.  Needs e1 e2 e3 <= 512.
 //
 // PAR = 0: wave w computes output rows 64 w .. 64 w + 63 of the slice.
-// PAR = 1, 2 (the solver's even half fields, blocks of even extents): waves
-// 0..3 take the rows with y1 + y2 + y3 even, waves 4..7 the odd ones, so that
-// the global parity of a wave's rows is one value per slice.  PAR = 1: the
-// input is zero on odd sites, so only the taps reaching even sites are
-// multiplied (41 or 40 of 81); PAR = 2: only the even output sites are
-// needed, so waves whose rows are odd in a slice skip it.  The skipped
-// products are exact zeros or unused rows: the results of the rows kept are
-// the same.  origin: the block origins [nb][4] (global parity of a site =
-// parity of origin + local coordinates).
+// PAR = 1, 2 (the solver's even half fields, blocks of even extents): rows
+// are taken by parity class (y1 + y2 + y3 even or odd), waves 0..3 the even
+// class and 4..7 the odd one, so that the global parity of a wave's rows is
+// one value per slice.  PAR = 1: the input is zero on odd sites, so only the
+// taps reaching even sites are multiplied (41 or 40 of 81).  PAR = 2: only
+// the even output sites are needed, so the waves whose class is odd in a
+// slice skip it (spreading the even rows over all waves, two tiles each, was
+// measured slower: each weight fragment then feeds half as many products).
+// The skipped products are exact zeros or unused rows: the results of the
+// rows kept are the same.  origin: the block origins [nb][4] (global parity
+// of a site = parity of origin + local coordinates).
 constexpr int kSliceMax = 512;
 constexpr int kRowPad = 40;  // bf16 per LDS row (32 + 8 padding)
 
 template <int ACT, bool OUT_F32, int PAR>
 __global__ void __launch_bounds__(512) k_conv_mfma_lds(const uint16_t *__restrict__ X, const uint16_t *__restrict__ Wt,
                                                        void *__restrict__ Y, NnExt e, const int32_t *__restrict__ active,
-                                                       int pair0, const int32_t *__restrict__ origin, int nb)
+                                                       int pair0, const int32_t *__restrict__ origin, int nb, NnHalfIn hin)
 {
     __shared__ uint16_t ring[3][kSliceMax][kRowPad];
     // blocks whose (block, rhs) pair is no longer iterated are skipped
@@ -455,6 +457,7 @@ __global__ void __launch_bounds__(512) k_conv_mfma_lds(const uint16_t *__restric
     const int kg = lane >> 4, li = lane & 15;
     const int R = e.e[1] * e.e[2] * e.e[3];
     const int64_t base = (int64_t)blockIdx.x * e.S;  // first row of this block
+    constexpr int RT = 4;  // 16-row tiles per wavefront
     // parity class of the wave's rows and the parity of the block origin
     const int cls = PAR ? wave >> 2 : 0;
     int opar = 0;
@@ -462,11 +465,13 @@ __global__ void __launch_bounds__(512) k_conv_mfma_lds(const uint16_t *__restric
         const int32_t *o = origin + 4 * ((pair0 + (int)blockIdx.x) % nb);
         opar = (o[0] + o[1] + o[2] + o[3]) & 1;
     }
-    // output coordinates (x1, x2, x3) and slice row of this lane's row in each 16-row tile
-    int oc[4][3], orw[4];
-    bool orow[4];
+    // output coordinates (x1, x2, x3) and slice row of this lane's row in each
+    // 16-row tile; for PAR != 0 the row is the j-th of its parity class (line
+    // (y1, y2), y3 = 2 m + ((class + y1 + y2) & 1)), and x3 is set per slice
+    int oc[RT][3], orw[RT], om[RT];
+    bool orow[RT];
 #pragma unroll
-    for (int rt = 0; rt < 4; rt++) {
+    for (int rt = 0; rt < RT; rt++) {
         if constexpr (PAR == 0) {
             int r = wave * 64 + rt * 16 + li;
             orow[rt] = r < R;
@@ -476,41 +481,124 @@ __global__ void __launch_bounds__(512) k_conv_mfma_lds(const uint16_t *__restric
             r /= e.e[3];
             oc[rt][1] = r % e.e[2];
             oc[rt][0] = r / e.e[2];
+            om[rt] = 0;
         } else {
-            // j-th row of class cls: line (y1, y2), y3 = 2 m + ((cls + y1 + y2) & 1)
             const int h3 = e.e[3] >> 1;
             int j = (wave & 3) * 64 + rt * 16 + li;
             orow[rt] = j < (R >> 1);
             j = min(j, (R >> 1) - 1);
-            const int m = j % h3, line = j / h3;
+            om[rt] = j % h3;
+            const int line = j / h3;
             oc[rt][1] = line % e.e[2];
             oc[rt][0] = line / e.e[2];
-            oc[rt][2] = 2 * m + ((cls + oc[rt][0] + oc[rt][1]) & 1);
-            orw[rt] = (oc[rt][0] * e.e[2] + oc[rt][1]) * e.e[3] + oc[rt][2];
+            oc[rt][2] = 0;
+            orw[rt] = 0;
         }
     }
-    auto load_slice = [&](int s) {
-        uint16_t(*dst)[kRowPad] = ring[(s + 3) % 3];
-        const bool in = s >= 0 && s < e.e[0];
-        for (int k = threadIdx.x; k < R * 4; k += 512) {
-            const int r = k >> 2, q = k & 3;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (in) v = *reinterpret_cast<const uint4 *>(X + (base + (int64_t)s * R + r) * 32 + q * 8);
-            *reinterpret_cast<uint4 *>(&dst[r][q * 8]) = v;
+    // x3 and the slice row of the class-cl rows (PAR != 0)
+    auto set_class = [&](int cl) {
+#pragma unroll
+        for (int rt = 0; rt < RT; rt++) {
+            oc[rt][2] = 2 * om[rt] + ((cl + oc[rt][0] + oc[rt][1]) & 1);
+            orw[rt] = (oc[rt][0] * e.e[2] + oc[rt][1]) * e.e[3] + oc[rt][2];
         }
     };
-    load_slice(-1);
-    load_slice(0);
-    load_slice(1);
+    if constexpr (PAR != 0) set_class(cls);
+    // slice s into registers (zero outside the block) and from there into its
+    // ring buffer.  PAR = 3: from the even half field (FP32, component-major):
+    // thread t takes even site t % 256 of the slice and components
+    // 12 (t / 256) .. + 11, converts them to BF16 into the site's row and
+    // zeroes the same channels of the odd row next to it (rows 2m, 2m + 1 of
+    // the block hold one even site each).  Else: 4 pieces of 16 bytes of the
+    // BF16 rows per thread.
+    const float *hbase = nullptr;
+    const int32_t *pm = nullptr;
+    int hbk = 0;
+    if constexpr (PAR == 3) {
+        const int pair = pair0 + (int)blockIdx.x, b = pair % nb, rr = pair / nb;
+        hbk = hin.h[b];
+        hbase = hin.half + (hin.soff[b] >> 1) * 24 * hin.n_rhs + (int64_t)rr * 24 * hbk;
+        pm = hin.perm + hin.perm_off[b];
+    }
+    struct Pre {
+        uint4 u[4];
+        float f[12];
+        int row;
+    };
+    auto fetch_slice = [&](int s, Pre &pre) {
+        const bool in = s >= 0 && s < e.e[0];
+        if constexpr (PAR == 3) {
+            const int ql = threadIdx.x & 255, g = threadIdx.x >> 8, hs = R >> 1;
+            pre.row = -1;
+#pragma unroll
+            for (int i = 0; i < 12; i++) pre.f[i] = 0.0f;
+            if (in && ql < hs) {
+                const int q = s * hs + ql;
+                pre.row = pm[q] - s * R;
+#pragma unroll
+                for (int i = 0; i < 12; i++) pre.f[i] = hbase[(int64_t)(g * 12 + i) * hbk + q];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int k = threadIdx.x + 512 * i;
+                pre.u[i] = make_uint4(0, 0, 0, 0);
+                if (in && k < R * 4)
+                    pre.u[i] = *reinterpret_cast<const uint4 *>(X + (base + (int64_t)s * R + (k >> 2)) * 32 + (k & 3) * 8);
+            }
+        }
+    };
+    auto put_slice = [&](int s, const Pre &pre) {
+        uint16_t(*dst)[kRowPad] = ring[(s + 3) % 3];
+        if constexpr (PAR == 3) {
+            const bool in = s >= 0 && s < e.e[0];
+            if (!in) {
+                for (int k = threadIdx.x; k < R * 4; k += 512)
+                    *reinterpret_cast<uint4 *>(&dst[k >> 2][(k & 3) * 8]) = make_uint4(0, 0, 0, 0);
+            } else if (pre.row >= 0) {
+                const int g = threadIdx.x >> 8;
+                uint2 *ev = reinterpret_cast<uint2 *>(&dst[pre.row][g * 12]);
+                uint2 *od = reinterpret_cast<uint2 *>(&dst[pre.row ^ 1][g * 12]);
+#pragma unroll
+                for (int i = 0; i < 3; i++) {
+                    ev[i] = make_uint2((uint32_t)f2bf(pre.f[4 * i]) | ((uint32_t)f2bf(pre.f[4 * i + 1]) << 16),
+                                       (uint32_t)f2bf(pre.f[4 * i + 2]) | ((uint32_t)f2bf(pre.f[4 * i + 3]) << 16));
+                    od[i] = make_uint2(0, 0);
+                }
+                if (g == 1) {  // padding channels 24..31 of both rows
+                    *reinterpret_cast<uint4 *>(&dst[pre.row][24]) = make_uint4(0, 0, 0, 0);
+                    *reinterpret_cast<uint4 *>(&dst[pre.row ^ 1][24]) = make_uint4(0, 0, 0, 0);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int k = threadIdx.x + 512 * i;
+                if (k < R * 4) *reinterpret_cast<uint4 *>(&dst[k >> 2][(k & 3) * 8]) = pre.u[i];
+            }
+        }
+    };
+    {
+        Pre pre;
+        fetch_slice(-1, pre);
+        put_slice(-1, pre);
+        fetch_slice(0, pre);
+        put_slice(0, pre);
+        fetch_slice(1, pre);
+        put_slice(1, pre);
+    }
     __syncthreads();
     const bf16x8 zero = {};
     for (int a = 0; a < e.e[0]; a++) {
+        // slice a + 2 is fetched during the products of slice a
+        Pre pre;
+        fetch_slice(a + 2, pre);
         // global parity of this wave's output rows in slice a
         const int gpar = (opar + a + cls) & 1;
         const bool work = PAR != 2 || gpar == 0;
-        f32x4 acc[4][2];
+        f32x4 acc[RT][2];
 #pragma unroll
-        for (int rt = 0; rt < 4; rt++)
+        for (int rt = 0; rt < RT; rt++)
 #pragma unroll
             for (int ct = 0; ct < 2; ct++) acc[rt][ct] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
         if (work)
@@ -521,15 +609,15 @@ __global__ void __launch_bounds__(512) k_conv_mfma_lds(const uint16_t *__restric
 #pragma unroll
                     for (int t3 = -1; t3 <= 1; t3++) {
                         // PAR = 1: the tap reaches an odd (zero) input site
-                        if (PAR == 1 && ((gpar + t0 + t1 + t2 + t3) & 1)) continue;
+                        if ((PAR == 1 || PAR == 3) && ((gpar + t0 + t1 + t2 + t3) & 1)) continue;
                         const int tap = ((t0 + 1) * 3 + (t1 + 1)) * 9 + (t2 + 1) * 3 + (t3 + 1);
                         bf16x8 bv[2];
 #pragma unroll
                         for (int ct = 0; ct < 2; ct++)
                             bv[ct] = *reinterpret_cast<const bf16x8 *>(Wt + ((int64_t)(tap * 32 + ct * 16 + li) * 32 + kg * 8));
-                        bf16x8 av[4];
+                        bf16x8 av[RT];
 #pragma unroll
-                        for (int rt = 0; rt < 4; rt++) {
+                        for (int rt = 0; rt < RT; rt++) {
                             const int y1 = oc[rt][0] + t1, y2 = oc[rt][1] + t2, y3 = oc[rt][2] + t3;
                             const bool in = orow[rt] && (unsigned)y1 < (unsigned)e.e[1] &&
                                             (unsigned)y2 < (unsigned)e.e[2] && (unsigned)y3 < (unsigned)e.e[3];
@@ -537,7 +625,7 @@ __global__ void __launch_bounds__(512) k_conv_mfma_lds(const uint16_t *__restric
                             av[rt] = in ? *reinterpret_cast<const bf16x8 *>(&src[r][kg * 8]) : zero;
                         }
 #pragma unroll
-                        for (int rt = 0; rt < 4; rt++)
+                        for (int rt = 0; rt < RT; rt++)
 #pragma unroll
                             for (int ct = 0; ct < 2; ct++)
                                 acc[rt][ct] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[rt], bv[ct], acc[rt][ct], 0, 0, 0);
@@ -547,7 +635,7 @@ __global__ void __launch_bounds__(512) k_conv_mfma_lds(const uint16_t *__restric
         // store this slice's output rows
         if (work)
 #pragma unroll
-        for (int rt = 0; rt < 4; rt++)
+        for (int rt = 0; rt < RT; rt++)
 #pragma unroll
             for (int ct = 0; ct < 2; ct++)
 #pragma unroll
@@ -568,7 +656,7 @@ __global__ void __launch_bounds__(512) k_conv_mfma_lds(const uint16_t *__restric
                     }
                 }
         __syncthreads();  // every wave is done with slice a - 1
-        if (a + 2 <= e.e[0]) load_slice(a + 2);
+        if (a + 2 <= e.e[0]) put_slice(a + 2, pre);
         __syncthreads();
     }
 }
@@ -586,26 +674,32 @@ __global__ void k_weights_bf16(const float *__restrict__ W, uint16_t *__restrict
 template <typename SP>
 __global__ void k_half_to_rows_bf16(const SP *__restrict__ half, uint16_t *__restrict__ rows, HalfRows hr)
 {
+    // thread k: canonical rows 2 m and 2 m + 1 of one pair's block; with even
+    // extents exactly one of them is even, and it is the m-th even site
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (k >= (int64_t)hr.npairs * hr.S) return;
-    const int pl = (int)(k / hr.S), q = (int)(k - (int64_t)pl * hr.S);
+    const int hS = hr.S >> 1;
+    if (k >= (int64_t)hr.npairs * hS) return;
+    const int pl = (int)(k / hS), m = (int)(k - (int64_t)pl * hS);
     const int pair = hr.pair0 + pl, b = pair % hr.nb, r = pair / hr.nb;
     const int hb = hr.h[b];
-    const int s = hr.perm[hr.perm_off[b] + q];
+    const int s = hr.perm[hr.perm_off[b] + m];  // 2 m or 2 m + 1
     uint32_t pk[16];  // channel pairs (2c, 2c+1), low half first
 #pragma unroll
     for (int i = 0; i < 16; i++) pk[i] = 0;
-    if (q < hb) {
-        const SP *src = half + (hr.soff[b] >> 1) * 24 * hr.n_rhs + (int64_t)r * 24 * hb + q;
+    const SP *src = half + (hr.soff[b] >> 1) * 24 * hr.n_rhs + (int64_t)r * 24 * hb + m;
 #pragma unroll
-        for (int c = 0; c < 12; c++)
-            pk[c] = (uint32_t)f2bf((float)src[(int64_t)(2 * c) * hb]) |
-                    ((uint32_t)f2bf((float)src[(int64_t)(2 * c + 1) * hb]) << 16);
+    for (int c = 0; c < 12; c++)
+        pk[c] = (uint32_t)f2bf((float)src[(int64_t)(2 * c) * hb]) | ((uint32_t)f2bf((float)src[(int64_t)(2 * c + 1) * hb]) << 16);
+    // the two rows are 128 contiguous bytes: eight 16-byte stores
+    uint4 *row = reinterpret_cast<uint4 *>(rows + ((int64_t)pl * hr.S + 2 * m) * 32);
+    const bool first = s == 2 * m;
+    const uint4 z = make_uint4(0, 0, 0, 0);
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const uint4 v = make_uint4(pk[4 * i], pk[4 * i + 1], pk[4 * i + 2], pk[4 * i + 3]);
+        row[i] = first ? v : z;
+        row[4 + i] = first ? z : v;
     }
-    // a row is 64 contiguous bytes: four 16-byte stores
-    uint4 *row = reinterpret_cast<uint4 *>(rows + ((int64_t)pl * hr.S + s) * 32);
-#pragma unroll
-    for (int i = 0; i < 4; i++) row[i] = make_uint4(pk[4 * i], pk[4 * i + 1], pk[4 * i + 2], pk[4 * i + 3]);
 }
 
 // FP32 rows [rows][24] -> BF16 rows [rows][32]
@@ -705,21 +799,23 @@ hipError_t launch_half_rows(const void *half, float *rows, void *half_out, dd_pr
 
 hipError_t launch_conv_mfma(const uint16_t *X, const uint16_t *Wt, void *Y, int64_t nrows, const NnExt &e, int act,
                             bool out_f32, int variant, const int32_t *active, int pair0, const int32_t *origin, int nb,
-                            int parity_mode, hipStream_t st)
+                            int parity_mode, hipStream_t st, const NnHalfIn *hin)
 {
     if (nrows <= 0) return hipSuccess;
     const int R = e.e[1] * e.e[2] * e.e[3];
+    // the parity modes need even e3 (rows of one class per line) and the block origins
+    const int par = origin && (e.e[3] & 1) == 0 ? parity_mode : 0;
+    if (par == 3 && (!hin || variant != 1 || out_f32 || R > kSliceMax || nrows % e.S != 0)) return hipErrorInvalidValue;
     if (R <= kSliceMax && nrows % e.S == 0 && variant == 1) {
         const dim3 g((unsigned)(nrows / e.S)), t(512);
-        // the parity modes need even e3 (rows of one class per line) and the block origins
-        const int par = origin && (e.e[3] & 1) == 0 ? parity_mode : 0;
-#define CM(A, F, P) hipLaunchKernelGGL((k_conv_mfma_lds<A, F, P>), g, t, 0, st, X, Wt, Y, e, active, pair0, origin, nb)
+        const NnHalfIn h0 = hin ? *hin : NnHalfIn{};
+#define CM(A, F, P) hipLaunchKernelGGL((k_conv_mfma_lds<A, F, P>), g, t, 0, st, X, Wt, Y, e, active, pair0, origin, nb, h0)
         if (out_f32) {
             if (par == 2) CM(0, true, 2); else CM(0, true, 0);
         } else if (act) {
-            if (par == 1) CM(1, false, 1); else CM(1, false, 0);
+            if (par == 3) CM(1, false, 3); else if (par == 1) CM(1, false, 1); else CM(1, false, 0);
         } else {
-            if (par == 1) CM(0, false, 1); else CM(0, false, 0);
+            if (par == 3) CM(0, false, 3); else if (par == 1) CM(0, false, 1); else CM(0, false, 0);
         }
 #undef CM
         return hipGetLastError();
@@ -739,7 +835,8 @@ hipError_t launch_weights_bf16(const float *W, uint16_t *Wt, int cin, int cout, 
 
 hipError_t launch_half_rows_bf16(const void *half, uint16_t *rows, dd_prec sp, const HalfRows &hr, hipStream_t st)
 {
-    const dim3 g = g256((int64_t)hr.npairs * hr.S);
+    if (hr.S & 1) return hipErrorInvalidValue;
+    const dim3 g = g256((int64_t)hr.npairs * (hr.S >> 1));
     if (sp == DD_F64) hipLaunchKernelGGL(k_half_to_rows_bf16<double>, g, dim3(256), 0, st, (const double *)half, rows, hr);
     else hipLaunchKernelGGL(k_half_to_rows_bf16<float>, g, dim3(256), 0, st, (const float *)half, rows, hr);
     return hipGetLastError();
