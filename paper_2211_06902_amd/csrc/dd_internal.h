@@ -306,9 +306,11 @@ hipError_t launch_adam(float *w, const float *g, float *m, float *v, int64_t n, 
 // With origin ([nb][4] block origins; pair p is block p % nb), variant 1 uses
 // the site parity: parity_mode 1 multiplies only the taps reaching even sites
 // (the input must be zero on odd sites), 2 computes only the even output rows.
-// parity_mode 3: as 1, with the input read from an even half field (FP32) instead of X.
+// parity_mode 3: as 1, with the input read from an even half field (FP32) instead of X;
+// 4: as 2, with the output written into the even half field out instead of Y.
 struct NnHalfIn {
     const float *half;        // even half field of all pairs (library layout)
+    float *out;               // even half field written by the last layer (mode 4)
     const int32_t *perm;      // eo position -> block-local canonical site
     const int64_t *perm_off;  // [nb]
     const int64_t *soff;      // [nb + 1]

@@ -76,8 +76,8 @@ hipError_t nn_forward_bf16(dd_ctx *ctx, dd_nn *nn, const uint16_t *Xb, uint16_t 
     if ((e = launch_conv_mfma(Zb1, nn->d_wbf + 81 * 1024, Zb2, nrows, nn->e, nn->act, false, v, active, pair0, origin,
                               nb, 0, st)) != hipSuccess)
         return e;
-    return launch_conv_mfma(Zb2, nn->d_wbf + 2 * 81 * 1024, O, nrows, nn->e, 0, true, v, active, pair0, origin, nb, 2,
-                            st);
+    return launch_conv_mfma(Zb2, nn->d_wbf + 2 * 81 * 1024, O, nrows, nn->e, 0, true, v, active, pair0, origin, nb,
+                            hin && hin->out ? 4 : 2, st, hin);
 }
 
 // the LDS kernel handles the block shape (x0-slices of at most 512 sites, even extents)
@@ -109,7 +109,7 @@ hipError_t nn_apply_half(dd_ctx *ctx, dd_nn *nn, const dd_blocks *B, const void 
         if (bf) {
             // FP32 half fields feed the first layer directly (LDS kernel); else via BF16 rows
             const bool fused = sp == DD_F32 && ctx->nn_kernel == 1 && nn_slice_fits(nn);
-            const NnHalfIn hin{(const float *)v, B->d_perm, B->d_perm_off, B->d_soff, B->d_h, n_rhs};
+            const NnHalfIn hin{(const float *)v, (float *)z, B->d_perm, B->d_perm_off, B->d_soff, B->d_h, n_rhs};
             if (!fused) e = launch_half_rows_bf16(v, (uint16_t *)X, sp, hr, ctx->stream);
             TimedLaunch tl(ctx, DD_KCLASS_NN_BF16, 2.0 * 81 * (24 * 32 + 32 * 32 + 32 * 24) * (double)nrows);
             if (e == hipSuccess)
@@ -119,7 +119,9 @@ hipError_t nn_apply_half(dd_ctx *ctx, dd_nn *nn, const dd_blocks *B, const void 
             e = launch_half_rows(v, (float *)X, nullptr, sp, hr, 0, ctx->stream);
             if (e == hipSuccess) e = nn_forward(ctx, nn, (float *)X, (float *)Z1, (float *)Z2, O, nrows);
         }
-        if (e == hipSuccess) e = launch_half_rows(nullptr, O, z, sp, hr, 1, ctx->stream);
+        // (the fused path wrote z itself)
+        if (e == hipSuccess && !(bf && sp == DD_F32 && ctx->nn_kernel == 1 && nn_slice_fits(nn)))
+            e = launch_half_rows(nullptr, O, z, sp, hr, 1, ctx->stream);
     }
     return e;
 }

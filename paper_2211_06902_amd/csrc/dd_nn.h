@@ -44,7 +44,8 @@ bool nn_fits(const dd_nn *nn, const dd_blocks *B);
 // the network in BF16 on the matrix cores: Xb [rows][32] BF16 -> O [rows][24] FP32.
 // With block origins (origin [nb][4], pair p on block p % nb) the input must
 // be zero on odd sites and only the even sites of O are written.
-// With hin as well, the input is that even half field (FP32) and Xb is unused.
+// With hin as well, the input is that even half field (FP32) and Xb is unused;
+// with hin->out, the even output sites go into that half field and O is unused.
 hipError_t nn_forward_bf16(dd_ctx *ctx, dd_nn *nn, const uint16_t *Xb, uint16_t *Zb1, uint16_t *Zb2, float *O,
                            int64_t nrows, const int32_t *active, int pair0, const int32_t *origin = nullptr,
                            int nb = 0, const NnHalfIn *hin = nullptr);

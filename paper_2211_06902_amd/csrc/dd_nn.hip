@@ -440,10 +440,15 @@ __global__ void __launch_bounds__(256) k_conv_mfma(const uint16_t *__restrict__ 
 // slice skip it (spreading the even rows over all waves, two tiles each, was
 // measured slower: each weight fragment then feeds half as many products).
 // The skipped products are exact zeros or unused rows: the results of the
-// rows kept are the same.  origin: the block origins [nb][4] (global parity
-// of a site = parity of origin + local coordinates).
+// rows kept are the same.  PAR = 3 (first layer) reads its input from the
+// FP32 even half field, PAR = 4 (last layer) writes its even output sites
+// into the FP32 even half field hin.out, both instead of network rows.
+// origin: the block origins [nb][4] (global parity of a site = parity of
+// origin + local coordinates).
 constexpr int kSliceMax = 512;
-constexpr int kRowPad = 40;  // bf16 per LDS row (32 + 8 padding)
+constexpr int kRowPad = 40;     // bf16 per LDS row (32 + 8 padding)
+constexpr int kTrStride = 257;  // floats per channel of the PAR = 4 transpose (odd: no bank conflicts)
+static_assert(24 * kTrStride * 4 <= kSliceMax * kRowPad * 2, "transpose fits a ring buffer");
 
 template <int ACT, bool OUT_F32, int PAR>
 __global__ void __launch_bounds__(512) k_conv_mfma_lds(const uint16_t *__restrict__ X, const uint16_t *__restrict__ Wt,
@@ -513,12 +518,14 @@ __global__ void __launch_bounds__(512) k_conv_mfma_lds(const uint16_t *__restric
     // BF16 rows per thread.
     const float *hbase = nullptr;
     const int32_t *pm = nullptr;
-    int hbk = 0;
-    if constexpr (PAR == 3) {
-        const int pair = pair0 + (int)blockIdx.x, b = pair % nb, rr = pair / nb;
-        hbk = hin.h[b];
-        hbase = hin.half + (hin.soff[b] >> 1) * 24 * hin.n_rhs + (int64_t)rr * 24 * hbk;
-        pm = hin.perm + hin.perm_off[b];
+    int hbk = 0, pb = 0, prhs = 0;
+    if constexpr (PAR >= 3) {
+        const int pair = pair0 + (int)blockIdx.x;
+        pb = pair % nb;
+        prhs = pair / nb;
+        hbk = hin.h[pb];
+        hbase = hin.half + (hin.soff[pb] >> 1) * 24 * hin.n_rhs + (int64_t)prhs * 24 * hbk;
+        pm = hin.perm + hin.perm_off[pb];
     }
     struct Pre {
         uint4 u[4];
@@ -595,7 +602,7 @@ __global__ void __launch_bounds__(512) k_conv_mfma_lds(const uint16_t *__restric
         fetch_slice(a + 2, pre);
         // global parity of this wave's output rows in slice a
         const int gpar = (opar + a + cls) & 1;
-        const bool work = PAR != 2 || gpar == 0;
+        const bool work = (PAR != 2 && PAR != 4) || gpar == 0;
         f32x4 acc[RT][2];
 #pragma unroll
         for (int rt = 0; rt < RT; rt++)
@@ -632,8 +639,34 @@ __global__ void __launch_bounds__(512) k_conv_mfma_lds(const uint16_t *__restric
                     }
                 }
         }
+        if constexpr (PAR == 4) {
+            // even output sites straight into the FP32 half field: the tile goes
+            // through LDS (the ring buffer slice a + 2 will fill, free now) so
+            // that the global stores run along the sites.  Even row j of the
+            // slice is its even site j.
+            __syncthreads();  // every wave is done with slice a - 1
+            float *tr = reinterpret_cast<float *>(&ring[(a + 2) % 3][0][0]);
+            if (work)
+#pragma unroll
+                for (int rt = 0; rt < RT; rt++)
+#pragma unroll
+                    for (int ct = 0; ct < 2; ct++) {
+                        const int c = ct * 16 + li;
+#pragma unroll
+                        for (int i = 0; i < 4; i++) {
+                            const int j = (wave & 3) * 64 + rt * 16 + 4 * kg + i;
+                            if (c < 24 && j < (R >> 1)) tr[c * kTrStride + j] = acc[rt][ct][i];
+                        }
+                    }
+            __syncthreads();
+            float *zb = hin.out + (hin.soff[pb] >> 1) * 24 * hin.n_rhs + (int64_t)prhs * 24 * hbk + a * (R >> 1);
+            for (int k = threadIdx.x; k < 24 * (R >> 1); k += 512) {
+                const int c = k / (R >> 1), j = k - c * (R >> 1);
+                zb[(int64_t)c * hbk + j] = tr[c * kTrStride + j];
+            }
+        }
         // store this slice's output rows
-        if (work)
+        if (PAR != 4 && work)
 #pragma unroll
         for (int rt = 0; rt < RT; rt++)
 #pragma unroll
@@ -655,7 +688,7 @@ __global__ void __launch_bounds__(512) k_conv_mfma_lds(const uint16_t *__restric
                         reinterpret_cast<uint16_t *>(Y)[row * 32 + col] = f2bf(v);
                     }
                 }
-        __syncthreads();  // every wave is done with slice a - 1
+        __syncthreads();  // every wave is done with slice a - 1 (PAR = 4: and the transpose)
         if (a + 2 <= e.e[0]) put_slice(a + 2, pre);
         __syncthreads();
     }
@@ -806,12 +839,14 @@ hipError_t launch_conv_mfma(const uint16_t *X, const uint16_t *Wt, void *Y, int6
     // the parity modes need even e3 (rows of one class per line) and the block origins
     const int par = origin && (e.e[3] & 1) == 0 ? parity_mode : 0;
     if (par == 3 && (!hin || variant != 1 || out_f32 || R > kSliceMax || nrows % e.S != 0)) return hipErrorInvalidValue;
+    if (par == 4 && (!hin || !hin->out || variant != 1 || !out_f32 || R > kSliceMax || nrows % e.S != 0))
+        return hipErrorInvalidValue;
     if (R <= kSliceMax && nrows % e.S == 0 && variant == 1) {
         const dim3 g((unsigned)(nrows / e.S)), t(512);
         const NnHalfIn h0 = hin ? *hin : NnHalfIn{};
 #define CM(A, F, P) hipLaunchKernelGGL((k_conv_mfma_lds<A, F, P>), g, t, 0, st, X, Wt, Y, e, active, pair0, origin, nb, h0)
         if (out_f32) {
-            if (par == 2) CM(0, true, 2); else CM(0, true, 0);
+            if (par == 4) CM(0, true, 4); else if (par == 2) CM(0, true, 2); else CM(0, true, 0);
         } else if (act) {
             if (par == 3) CM(1, false, 3); else if (par == 1) CM(1, false, 1); else CM(1, false, 0);
         } else {
