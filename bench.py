@@ -501,7 +501,8 @@ def main():
         kname = "k_gmres (persistent GMRES(16), FP32 spinor / %s link, whole inner solve per launch)" % inner.upper()
     else:
         kclass = {"f64": dd.KCLASS_HOP_F64, "f32": dd.KCLASS_HOP_F32, "bf16": dd.KCLASS_HOP_BF16}[inner]
-        kname = "k_hop (%s, 12 rhs)" % ("FP32 spinor / BF16 link" if inner == "bf16" else inner.upper())
+        kname = "k_hop_walk (%s, 12 rhs; the x0-walk hop, all its fused-dot variants)" % (
+            "FP32 spinor / BF16 link" if inner == "bf16" else inner.upper())
     k_ms, k_n, k_bytes = ctx.timer_read(kclass)
     ctx.timer_enable(False)
 
