@@ -242,9 +242,10 @@ dd_status dd_multiboson_action(dd_ctx *ctx, const dd_blocks *blocks, const dd_ga
 
 /* Launch-shape overrides (0 = automatic).  DD_TUNE_RHS_GROUP_F64 / _F32: the
  * number of right-hand sides one thread of the site kernels handles for
- * FP64 / FP32 spinors (1, 2 or 4; ignored when it does not divide n_rhs).
- * Results do not depend on it beyond rounding of the fused dot products'
- * summation order, which is fixed for a given setting. */
+ * FP64 / FP32 spinors (1, 2 or 4; ignored when it does not divide n_rhs;
+ * automatic: 2 for FP32 spinors with FP32 links, else 1).  Results do not
+ * depend on it beyond rounding of the fused dot products' summation order,
+ * which is fixed for a given setting. */
 /* DD_TUNE_HOP_LDS: 1 (default) stages each hop tile's chunk of the input
  * field in LDS, 0 reads every neighbour from global memory.
  * DD_TUNE_HOP_WALK: the x0-walk of the hop (a workgroup streams the x0-slices

@@ -79,10 +79,10 @@ const TileTable *tiles_for(dd_ctx *ctx, dd_blocks *B, int nr, int g, hipError_t 
     return &(B->tiles[key] = tt);
 }
 
-// Tiles of the hop's x0-walk: nr * nseg per block, ordered block, segment,
-// rhs.  nseg is clamped to the smallest number of chunk tiles of a block, so
+// Tiles of the hop's x0-walk: (nr / g) * nseg per block, ordered block,
+// segment, rhs group.  nseg is clamped to the smallest number of chunk tiles of a block, so
 // that every segment owns a chunk slot of the dot-product partials.
-const TileTable *walk_for(const dd_blocks *B, int nr, int nseg, int *nseg_used, hipError_t *err)
+const TileTable *walk_for(const dd_blocks *B, int nr, int g, int nseg, int *nseg_used, hipError_t *err)
 {
     *err = hipSuccess;
     int cap = 1 << 20;
@@ -93,15 +93,16 @@ const TileTable *walk_for(const dd_blocks *B, int nr, int nseg, int *nseg_used, 
     }
     nseg = std::max(1, std::min(nseg, cap));
     *nseg_used = nseg;
-    const int key = nr * 64 + nseg;
+    const int key = (nr * 64 + nseg) * 8 + g;
     auto it = B->walks.find(key);
     if (it != B->walks.end()) return &it->second;
     TileTable tt;
     tt.blk_tile0.assign(B->nb + 1, 0);
     std::vector<int32_t> tb;
+    const int per = (nr / g) * nseg;
     for (int b = 0; b < B->nb; b++) {
-        tt.blk_tile0[b + 1] = tt.blk_tile0[b] + nr * nseg;
-        for (int t = 0; t < nr * nseg; t++) tb.push_back(b);
+        tt.blk_tile0[b + 1] = tt.blk_tile0[b] + per;
+        for (int t = 0; t < per; t++) tb.push_back(b);
     }
     tt.ntiles = tt.blk_tile0[B->nb];
     if ((*err = upload(&tt.d_tile_block, tb)) != hipSuccess) return nullptr;
@@ -109,26 +110,26 @@ const TileTable *walk_for(const dd_blocks *B, int nr, int nseg, int *nseg_used, 
     return &(B->walks[key] = tt);
 }
 
-// Segments per block of the hop's x0-walk: one, unless the (block, rhs)
+// Segments per block of the hop's x0-walk: one, unless the (block, rhs group)
 // walks alone would leave the device short of workgroups.
 int walk_segments(const dd_ctx *ctx, const dd_blocks *B, int nr)
 {
     if (ctx->hop_walk > 0) return ctx->hop_walk;
     const int64_t walks = (int64_t)B->nb * nr;
-    const int64_t want = 2048;
+    const int64_t want = 1024;  // measured: 1536 walks of 8^4 blocks are faster whole than halved
     return (int)std::min<int64_t>(8, std::max<int64_t>(1, (want + walks - 1) / walks));
 }
 
-// Right-hand sides per thread for a spinor precision (the largest power of
-// two up to the default below that divides n_rhs).  A context override
-// (dd_tune_set) takes precedence when it divides n_rhs.
-int rhs_group(const dd_ctx *ctx, int nr, dd_prec sp)
+// Right-hand sides per thread for a spinor precision and link precision lk.
+// A context override (dd_tune_set) takes precedence when it divides n_rhs.
+// Default: two for FP32 spinors with FP32 links (the x0-walk hop then shares
+// each link load and rebuilt row between them: measured faster), else one
+// (BF16 links and FP64: measured fastest; more rhs per thread cost occupancy).
+int rhs_group(const dd_ctx *ctx, int nr, dd_prec sp, dd_prec lk)
 {
     const int forced = ctx ? ctx->rhs_group[sp == DD_F64 ? 0 : 1] : 0;
     if (forced > 0 && nr % forced == 0) return forced;
-    // One rhs per thread by default: measured fastest for FP32 and FP64 (more
-    // rhs per thread share link loads but cost occupancy).
-    const int want = 1;
+    const int want = sp == DD_F32 && lk == DD_F32 ? 2 : 1;
     for (int g = want; g > 1; g >>= 1)
         if (nr % g == 0) return g;
     return 1;
@@ -136,9 +137,9 @@ int rhs_group(const dd_ctx *ctx, int nr, dd_prec sp)
 
 // rhs per thread of the hop kernel: its LDS stage holds 256 sites x G spinors,
 // so G is at most 2 for FP32 spinors and 1 for FP64.
-int hop_group(const dd_ctx *ctx, int nr, dd_prec sp)
+int hop_group(const dd_ctx *ctx, int nr, dd_prec sp, dd_prec lk)
 {
-    const int g = rhs_group(ctx, nr, sp);
+    const int g = rhs_group(ctx, nr, sp, lk);
     const int cap = sp == DD_F64 ? 1 : 2;
     return g > cap ? cap : g;
 }
@@ -187,10 +188,10 @@ hipError_t run_hop(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const Hop
     const bool aux = ha.aux && (ha.dot_mode == kDotAuxOut || ha.dot_mode == kDotOutAuxOutOut);
     const int extra = (ha.self != nullptr) + (ha.add != nullptr) + (aux ? 1 : 0);
     TimedLaunch tl(ctx, DD_KCLASS_HOP_F64 + (int)prec, hop_bytes(B, ba.n_rhs, prec, extra));
-    if (ha.use_lds && ba.g == 1 && B->walk && ctx->hop_walk >= 0) {
+    if (ha.use_lds && (ba.g == 1 || (ba.g == 2 && prec != DD_F64)) && B->walk && ctx->hop_walk >= 0) {
         hipError_t err;
         int nseg = 1;
-        const TileTable *wt = walk_for(B, ba.n_rhs, walk_segments(ctx, B, ba.n_rhs), &nseg, &err);
+        const TileTable *wt = walk_for(B, ba.n_rhs, ba.g, walk_segments(ctx, B, ba.n_rhs / ba.g), &nseg, &err);
         if (!wt) return err;
         WalkArgs wa;
         wa.tile_block = wt->d_tile_block;
@@ -558,7 +559,7 @@ dd_status dd_apply_D_block(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, 
     HIPCHECK(ctx, enter(ctx));
     hipError_t e;
     const dd_prec sp = prec == DD_F64 ? DD_F64 : DD_F32;
-    const int g = hop_group(ctx, n_rhs, sp);
+    const int g = hop_group(ctx, n_rhs, sp, prec);
     const TileTable *tt = tiles_for(ctx, B, n_rhs, g, &e);
     if (!tt) return fail(ctx, DD_EDEVICE, std::string("tile tables: ") + hipGetErrorString(e));
     const BlkArgs ba = blk_args(B, tt, n_rhs, g);

@@ -142,7 +142,8 @@ __device__ __forceinline__ double wg_hop_walk(const PairGeo &g, int p, int ns, S
     const Buf ob = make_buf(out, vbytes), sb = make_buf(self, self ? vbytes : 0), ab = make_buf(add, add ? vbytes : 0);
     const bool has_self = self != nullptr, has_add = add != nullptr;
     double nn = 0;
-    walk_run<SP, LK, AC>(w, ns, stage, hc, [&](const AC (&acc)[24], int h) {
+    walk_run<SP, LK, AC, 1>(w, ns, stage, hc, [&](const AC (&acc1)[1][24], int h) {
+        const AC(&acc)[24] = acc1[0];
         const uint32_t vo = (uint32_t)h * (uint32_t)sizeof(SP);
 #pragma unroll
         for (int half = 0; half < 2; half++) {

@@ -16,8 +16,8 @@ void *workspace(dd_ctx *ctx, const std::string &name, size_t bytes, hipError_t *
 size_t prec_bytes(dd_prec p);
 hipError_t enter(dd_ctx *ctx);
 const TileTable *tiles_for(dd_ctx *ctx, dd_blocks *B, int nr, int g, hipError_t *err);
-int rhs_group(const dd_ctx *ctx, int nr, dd_prec sp);
-int hop_group(const dd_ctx *ctx, int nr, dd_prec sp);
+int rhs_group(const dd_ctx *ctx, int nr, dd_prec sp, dd_prec lk);
+int hop_group(const dd_ctx *ctx, int nr, dd_prec sp, dd_prec lk);
 BlkArgs blk_args(const dd_blocks *B, const TileTable *tt, int nr, int g);
 const void *links_for(const dd_gauge *G, dd_prec prec);
 double hop_bytes(const dd_blocks *B, int nr, dd_prec prec, int extra_vectors);

@@ -24,7 +24,7 @@ constexpr int kNRed = 4;
 // GMRES: reorthogonalize (a second Gram-Schmidt pass) when |w - V h| keeps
 // at most this percentage of |w|
 constexpr int kGmReorthPercent = 10;
-constexpr int kLinkK = 6;
+constexpr int kLinkK = 6;  // complex entries stored per link: rows 0 and 1 (row 2 is rebuilt)
 constexpr int kLinkReals = 4 * kLinkK * 2;  // per site: 4 directions
 // Neighbour-table entry flags: bit 30 = hop across the antiperiodic time edge.
 constexpr int32_t kNbrSign = 1 << 30;

@@ -268,17 +268,18 @@ hipError_t launch_hop(const BlkArgs &ba, const HopArgs &ha, dd_prec prec, hipStr
 }
 
 // x0-walk of the hop (the walk itself is in dd_stencil.h): a tile walks one
-// of nseg segments of a block's x0-slices for one rhs.
-template <typename SP, typename LK, typename AC, int DM>
-__global__ void __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(sizeof(SP) == 8 && (DM == kDotNone || DM == kDotOutOut) ? 3 : 1))) k_hop_walk(BlkArgs ba, WalkArgs wa, HopArgs ha)
+// of nseg segments of a block's x0-slices for one group of G rhs.
+template <typename SP, typename LK, typename AC, int G, int DM>
+__global__ void __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(sizeof(SP) == 8 && G == 1 && (DM == kDotNone || DM == kDotOutOut) ? 3 : 1)))
+k_hop_walk(BlkArgs ba, WalkArgs wa, HopArgs ha)
 {
-    __shared__ SP stage[24 * kTile];
-    __shared__ double red[1][kTile];
+    __shared__ SP stage[24 * kTile * G];
+    __shared__ double red[G][kTile];
     const int tile = uni(xcd_tile(blockIdx.x, wa.ntiles));
     const int b = uni(wa.tile_block[tile]);
-    const int nr = ba.n_rhs;
+    const int nr = ba.n_rhs, ng = nr / G;
     const int rel = tile - uni(wa.blk_tile0[b]);
-    const int r = rel % nr, seg = rel / nr;
+    const int grp = rel % ng, seg = rel / ng;
     WalkPos w;
     w.p = ha.parity;
     w.hb = uni(ba.h[b]);
@@ -297,53 +298,64 @@ __global__ void __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(size
     hc.other0 = 0;
     hc.cstr = (uint32_t)w.hb * (uint32_t)sizeof(SP);
     hc.kstr = (uint32_t)(4 * w.hb) * (uint32_t)sizeof(LK);
-    hc.grp_off = r * 24 * w.hb;
+    hc.grp_off = grp * G * 24 * w.hb;
     hc.in_b = make_buf(reinterpret_cast<const SP *>(ha.in) + hbase, fbytes);
     hc.lk_b = make_buf(reinterpret_cast<const LK *>(ha.links) + soff * kLinkReals,
                        (uint32_t)(2 * w.hb * kLinkReals) * (uint32_t)sizeof(LK));
     const EpiBufs eb = epi_bufs<SP>(ha, hbase, fbytes);
     w.nbt = ba.nbr + uni64(ba.nbr_off[b]) + (int64_t)w.p * w.hb * 8;
-    double dv[1][kNRed];
+    double dv[G][kNRed];
 #pragma unroll
-    for (int i = 0; i < kNRed; i++) dv[0][i] = 0;
-    walk_run<SP, LK, AC>(w, ns, stage, hc, [&](const AC (&acc)[24], int h) {
-        hop_epilogue<SP, AC, DM>(acc, dv[0], ha, eb, (uint32_t)(hc.grp_off + h) * (uint32_t)sizeof(SP), hc.cstr);
+    for (int j = 0; j < G; j++)
+#pragma unroll
+        for (int i = 0; i < kNRed; i++) dv[j][i] = 0;
+    walk_run<SP, LK, AC, G>(w, ns, stage, hc, [&](const AC (&acc)[G][24], int h) {
+#pragma unroll
+        for (int j = 0; j < G; j++)
+            hop_epilogue<SP, AC, DM>(acc[j], dv[j], ha, eb,
+                                     (uint32_t)(hc.grp_off + j * 24 * w.hb + h) * (uint32_t)sizeof(SP), hc.cstr);
     });
     if (DM != kDotNone) {
         // partial sums in the chunk tiles' slots: segment seg in chunk slot seg,
         // the block's remaining chunk slots zero
         constexpr int nred = dot_nred(DM);
-        const int t0 = uni(ba.blk_tile0[b]), nch = (uni(ba.blk_tile0[b + 1]) - t0) / nr;
-        tile_sum<1>(red, dv, nred, ha.partial, t0 + seg * nr + r);
+        const int t0 = uni(ba.blk_tile0[b]), nch = (uni(ba.blk_tile0[b + 1]) - t0) / ng;
+        tile_sum<G>(red, dv, nred, ha.partial, t0 + seg * ng + grp);
         if (seg == 0)
-            for (int i = threadIdx.x; i < (nch - wa.nseg) * nred; i += kTile)
-                ha.partial[(int64_t)(t0 + (wa.nseg + i / nred) * nr + r) * kNRed + i % nred] = 0;
+            for (int i = threadIdx.x; i < (nch - wa.nseg) * G * nred; i += kTile) {
+                const int ch = wa.nseg + i / (G * nred), j = (i / nred) % G, k = i % nred;
+                ha.partial[((int64_t)(t0 + ch * ng + grp) * G + j) * kNRed + k] = 0;
+            }
     }
 }
 
-template <typename SP, typename LK, typename AC>
+template <typename SP, typename LK, typename AC, int G>
 static void launch_walk_t(const BlkArgs &ba, const WalkArgs &wa, const HopArgs &ha, hipStream_t s)
 {
     dim3 g(wa.ntiles), t(kTile);
     switch (ha.dot_mode) {
-    case kDotNone: hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, kDotNone>), g, t, 0, s, ba, wa, ha); break;
-    case kDotAuxOut: hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, kDotAuxOut>), g, t, 0, s, ba, wa, ha); break;
-    case kDotOutSelfOutOut: hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, kDotOutSelfOutOut>), g, t, 0, s, ba, wa, ha); break;
-    case kDotOutOut: hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, kDotOutOut>), g, t, 0, s, ba, wa, ha); break;
-    default: hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, kDotOutAuxOutOut>), g, t, 0, s, ba, wa, ha); break;
+    case kDotNone: hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, G, kDotNone>), g, t, 0, s, ba, wa, ha); break;
+    case kDotAuxOut: hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, G, kDotAuxOut>), g, t, 0, s, ba, wa, ha); break;
+    case kDotOutSelfOutOut: hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, G, kDotOutSelfOutOut>), g, t, 0, s, ba, wa, ha); break;
+    case kDotOutOut: hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, G, kDotOutOut>), g, t, 0, s, ba, wa, ha); break;
+    default: hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, G, kDotOutAuxOutOut>), g, t, 0, s, ba, wa, ha); break;
     }
 }
 
 hipError_t launch_hop_walk(const BlkArgs &ba, const WalkArgs &wa, const HopArgs &ha, dd_prec prec, hipStream_t s)
 {
     if (wa.ntiles <= 0) return hipSuccess;
-    if (ba.g != 1 || wa.nseg < 1 || ha.dot_mode < kDotNone || ha.dot_mode > kDotOutAuxOutOut) return hipErrorInvalidValue;
-    if (prec == DD_F64)
-        launch_walk_t<double, double, double>(ba, wa, ha, s);
-    else if (prec == DD_F32)
-        launch_walk_t<float, float, float>(ba, wa, ha, s);
-    else if (prec == DD_BF16)
-        launch_walk_t<float, uint16_t, float>(ba, wa, ha, s);
+    if (wa.nseg < 1 || ha.dot_mode < kDotNone || ha.dot_mode > kDotOutAuxOutOut) return hipErrorInvalidValue;
+    if (prec == DD_F64 && ba.g == 1)
+        launch_walk_t<double, double, double, 1>(ba, wa, ha, s);
+    else if (prec == DD_F32 && ba.g == 1)
+        launch_walk_t<float, float, float, 1>(ba, wa, ha, s);
+    else if (prec == DD_F32 && ba.g == 2)
+        launch_walk_t<float, float, float, 2>(ba, wa, ha, s);
+    else if (prec == DD_BF16 && ba.g == 1)
+        launch_walk_t<float, uint16_t, float, 1>(ba, wa, ha, s);
+    else if (prec == DD_BF16 && ba.g == 2)
+        launch_walk_t<float, uint16_t, float, 2>(ba, wa, ha, s);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();

@@ -219,7 +219,7 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
     // the FP64 residual kernels and the inner-precision kernels may group rhs
     // differently; a scalar kernel reads partials with the tiling of the
     // kernel that wrote them
-    const int g64 = hop_group(ctx, n_rhs, DD_F64), gsp = hop_group(ctx, n_rhs, sp);
+    const int g64 = hop_group(ctx, n_rhs, DD_F64, DD_F64), gsp = hop_group(ctx, n_rhs, sp, ip);
     const TileTable *tt64 = tiles_for(ctx, B, n_rhs, g64, &e);
     const TileTable *ttsp = tt64 ? tiles_for(ctx, B, n_rhs, gsp, &e) : nullptr;
     if (!ttsp) return fail(ctx, DD_EDEVICE, std::string("tile tables: ") + hipGetErrorString(e));

@@ -96,19 +96,19 @@ __device__ __forceinline__ void load_link(const Buf &b, const double *, uint32_t
                                           uint32_t kstride, AC (&u)[18], bool neg)
 {
 #pragma unroll
-    for (int k = 0; k < 6; k++) {
+    for (int k = 0; k < kLinkK; k++) {
         const auto q = __builtin_amdgcn_raw_buffer_load_b128(b.r, (int)voff, (int)(soff + k * kstride), 0);
         u[2 * k] = (AC)__builtin_bit_cast(double, __builtin_shufflevector(q, q, 0, 1));
         u[2 * k + 1] = (AC)__builtin_bit_cast(double, __builtin_shufflevector(q, q, 2, 3));
     }
-    rebuild_row2(u, neg);
+    if constexpr (kLinkK == 6) rebuild_row2(u, neg);
 }
 template <typename AC>
 __device__ __forceinline__ void load_link(const Buf &b, const float *, uint32_t voff, uint32_t soff, uint32_t kstride,
                                           AC (&u)[18], bool neg)
 {
 #pragma unroll
-    for (int k = 0; k < 6; k++) {
+    for (int k = 0; k < kLinkK; k++) {
         // take the 8 bytes as one integer: indexing the returned vector lets
         // the compiler shrink the load to its first dword
         const uint64_t q =
@@ -116,19 +116,19 @@ __device__ __forceinline__ void load_link(const Buf &b, const float *, uint32_t 
         u[2 * k] = (AC)__uint_as_float((uint32_t)q);
         u[2 * k + 1] = (AC)__uint_as_float((uint32_t)(q >> 32));
     }
-    rebuild_row2(u, neg);
+    if constexpr (kLinkK == 6) rebuild_row2(u, neg);
 }
 template <typename AC>
 __device__ __forceinline__ void load_link(const Buf &b, const uint16_t *, uint32_t voff, uint32_t soff,
                                           uint32_t kstride, AC (&u)[18], bool neg)
 {
 #pragma unroll
-    for (int k = 0; k < 6; k++) {
+    for (int k = 0; k < kLinkK; k++) {
         const uint32_t w = __builtin_amdgcn_raw_buffer_load_b32(b.r, (int)voff, (int)(soff + k * kstride), 0);
         u[2 * k] = (AC)bf16_to_f32(w & 0xffffu);
         u[2 * k + 1] = (AC)bf16_to_f32(w >> 16);
     }
-    rebuild_row2(u, neg);
+    if constexpr (kLinkK == 6) rebuild_row2(u, neg);
 }
 
 // a * b + c in one rounding
@@ -346,7 +346,7 @@ __device__ __forceinline__ void hop_one(AC (&acc)[G][24], int32_t e, const SP *s
     const int idx = e & kNbrMask;
     AC u[18];
     const int slot = FWD ? hc.slot_self : hc.other0 + idx;
-    load_link(hc.lk_b, (const LK *)nullptr, (uint32_t)slot * 2 * (uint32_t)sizeof(LK), MU * 6 * hc.kstr, hc.kstr, u,
+    load_link(hc.lk_b, (const LK *)nullptr, (uint32_t)slot * 2 * (uint32_t)sizeof(LK), MU * kLinkK * hc.kstr, hc.kstr, u,
               (e & kNbrSign) != 0);
     const int lidx = idx - hc.h0;
     if (LDS && (unsigned)lidx < (unsigned)hc.tv) {
@@ -367,7 +367,7 @@ __device__ __forceinline__ void hop_at(AC (&acc)[G][24], int32_t e, const SP *st
 {
     if (e < 0) return;
     AC u[18];
-    load_link(hc.lk_b, (const LK *)nullptr, (uint32_t)slot * 2 * (uint32_t)sizeof(LK), MU * 6 * hc.kstr, hc.kstr, u,
+    load_link(hc.lk_b, (const LK *)nullptr, (uint32_t)slot * 2 * (uint32_t)sizeof(LK), MU * kLinkK * hc.kstr, hc.kstr, u,
               (e & kNbrSign) != 0);
     const SrcLds<SP, G> src{stage + lidx * G};
     hop_term<MU, FWD, SP, AC, G>(acc, src, u);
@@ -387,7 +387,7 @@ __device__ __forceinline__ void hop_half_at(AC (&w)[G][12], int32_t e, const SP 
         return;
     }
     AC u[18];
-    load_link(hc.lk_b, (const LK *)nullptr, (uint32_t)slot * 2 * (uint32_t)sizeof(LK), MU * 6 * hc.kstr, hc.kstr, u,
+    load_link(hc.lk_b, (const LK *)nullptr, (uint32_t)slot * 2 * (uint32_t)sizeof(LK), MU * kLinkK * hc.kstr, hc.kstr, u,
               (e & kNbrSign) != 0);
     const SrcLds<SP, G> src{stage + lidx * G};
     hop_half<MU, FWD, SP, AC, G>(w, src, u);
@@ -411,37 +411,43 @@ struct WalkPos {
     const int32_t *nbt;        // neighbour table of the output parity
 };
 
-// Copies input slice q (component-major, kTile sites per component) into the stage.
-template <typename SP>
+// Copies input slice q of the thread's G rhs (component-major, kTile sites
+// per component, the G rhs of a site adjacent) into the stage.
+template <typename SP, int G>
 __device__ __forceinline__ void walk_stage(SP *stage, const HopCtx &hc, int q, int hs, int k, bool live)
 {
     if (!live) return;
     const uint32_t vo = (uint32_t)(hc.grp_off + q * hs + k) * (uint32_t)sizeof(SP);
-    SP v[24];
+    SP v[24][G];
 #pragma unroll
-    for (int c = 0; c < 24; c++) v[c] = bload<SP>(hc.in_b, vo, (uint32_t)c * hc.cstr);
+    for (int j = 0; j < G; j++)
 #pragma unroll
-    for (int c = 0; c < 24; c++) stage[c * kTile + k] = v[c];
+        for (int c = 0; c < 24; c++) v[c][j] = bload<SP>(hc.in_b, vo, (uint32_t)(j * 24 + c) * hc.cstr);
+#pragma unroll
+    for (int c = 0; c < 24; c++) stv<SP, G>(stage + (c * kTile + k) * G, v[c]);
 }
 
 // Input slice q is in the stage.  acc holds output slice q-1: its x0+ hop is
 // added and epi(acc, h) finishes it (site h) when it belongs to [s0, s1);
 // acc then restarts as output slice q (carry: the upper half of its x0- hop)
 // with the hops along 1..3, and carry becomes the x0- half of output slice
-// q+1.
-template <typename SP, typename LK, typename AC, typename EPI>
-__device__ __forceinline__ void walk_step(AC (&acc)[1][24], AC (&carry)[1][12], int q, const WalkPos &w,
+// q+1.  G rhs per thread share the link loads and the rebuilt rows.
+template <typename SP, typename LK, typename AC, int G, typename EPI>
+__device__ __forceinline__ void walk_step(AC (&acc)[G][24], AC (&carry)[G][12], int q, const WalkPos &w,
                                           const SP *stage, const HopCtx &hc, EPI &&epi)
 {
     if (q - 1 >= w.s0) {
         const int h = (q - 1) * w.hs + w.k;
-        hop_at<0, true, SP, LK, AC, 1>(acc, w.nbt[h * 8], stage, w.k, w.p * w.hb + h, hc);
-        epi(acc[0], h);
+        hop_at<0, true, SP, LK, AC, G>(acc, w.nbt[h * 8], stage, w.k, w.p * w.hb + h, hc);
+        epi(acc, h);
     }
     if (q >= w.s0 && q < w.s1) {
 #pragma unroll
-        for (int c = 0; c < 24; c++) acc[0][c] = 0;
-        hop_expand<0, false, AC>(acc[0], carry[0]);
+        for (int j = 0; j < G; j++) {
+#pragma unroll
+            for (int c = 0; c < 24; c++) acc[j][c] = 0;
+            hop_expand<0, false, AC>(acc[j], carry[j]);
+        }
         const int h = q * w.hs + w.k, base = q * w.hs, oth = (1 - w.p) * w.hb, own = w.p * w.hb + h;
         const int4 *t4 = reinterpret_cast<const int4 *>(w.nbt + h * 8);
         const int4 a0 = t4[0], a1 = t4[1];
@@ -449,16 +455,16 @@ __device__ __forceinline__ void walk_step(AC (&acc)[1][24], AC (&carry)[1][12], 
         int li[6];
 #pragma unroll
         for (int i = 0; i < 6; i++) li[i] = (nb[i] & kNbrMask) - base;
-        hop_at<1, true, SP, LK, AC, 1>(acc, nb[0], stage, li[0], own, hc);
-        hop_at<1, false, SP, LK, AC, 1>(acc, nb[1], stage, li[1], oth + base + li[1], hc);
-        hop_at<2, true, SP, LK, AC, 1>(acc, nb[2], stage, li[2], own, hc);
-        hop_at<2, false, SP, LK, AC, 1>(acc, nb[3], stage, li[3], oth + base + li[3], hc);
-        hop_at<3, true, SP, LK, AC, 1>(acc, nb[4], stage, li[4], own, hc);
-        hop_at<3, false, SP, LK, AC, 1>(acc, nb[5], stage, li[5], oth + base + li[5], hc);
+        hop_at<1, true, SP, LK, AC, G>(acc, nb[0], stage, li[0], own, hc);
+        hop_at<1, false, SP, LK, AC, G>(acc, nb[1], stage, li[1], oth + base + li[1], hc);
+        hop_at<2, true, SP, LK, AC, G>(acc, nb[2], stage, li[2], own, hc);
+        hop_at<2, false, SP, LK, AC, G>(acc, nb[3], stage, li[3], oth + base + li[3], hc);
+        hop_at<3, true, SP, LK, AC, G>(acc, nb[4], stage, li[4], own, hc);
+        hop_at<3, false, SP, LK, AC, G>(acc, nb[5], stage, li[5], oth + base + li[5], hc);
     }
     if (q + 1 < w.s1) {
         const int h = (q + 1) * w.hs + w.k;
-        hop_half_at<0, false, SP, LK, AC, 1>(carry, w.nbt[h * 8 + 1], stage, w.k, (1 - w.p) * w.hb + q * w.hs + w.k,
+        hop_half_at<0, false, SP, LK, AC, G>(carry, w.nbt[h * 8 + 1], stage, w.k, (1 - w.p) * w.hb + q * w.hs + w.k,
                                              hc);
     }
 }
@@ -466,26 +472,29 @@ __device__ __forceinline__ void walk_step(AC (&acc)[1][24], AC (&carry)[1][12], 
 // The whole walk over output slices [w.s0, w.s1) (input slices one beyond
 // each end when they exist).  Every thread of the workgroup calls it (it has
 // barriers); threads k >= hs only take part in those.  epi(acc, h) writes
-// output site h.
-template <typename SP, typename LK, typename AC, typename EPI>
+// output site h of the thread's G rhs.
+template <typename SP, typename LK, typename AC, int G, typename EPI>
 __device__ __forceinline__ void walk_run(const WalkPos &w, int ns, SP *stage, const HopCtx &hc, EPI &&epi)
 {
     const int qa = max(w.s0 - 1, 0), qb = min(w.s1 + 1, ns);
     const bool live = w.k < w.hs;
-    AC acc[1][24], carry[1][12];
+    AC acc[G][24], carry[G][12];
 #pragma unroll
-    for (int c = 0; c < 24; c++) acc[0][c] = 0;
+    for (int j = 0; j < G; j++) {
 #pragma unroll
-    for (int c = 0; c < 12; c++) carry[0][c] = 0;
+        for (int c = 0; c < 24; c++) acc[j][c] = 0;
+#pragma unroll
+        for (int c = 0; c < 12; c++) carry[j][c] = 0;
+    }
     for (int q = qa; q < qb; q++) {
-        walk_stage(stage, hc, q, w.hs, w.k, live);
+        walk_stage<SP, G>(stage, hc, q, w.hs, w.k, live);
         __syncthreads();
-        if (live) walk_step<SP, LK, AC>(acc, carry, q, w, stage, hc, epi);
+        if (live) walk_step<SP, LK, AC, G>(acc, carry, q, w, stage, hc, epi);
         __syncthreads();
     }
     // the block's last slice has no x0+ neighbour: when the walk ends there,
     // its output is finished here
-    if (live && qb == w.s1) epi(acc[0], (w.s1 - 1) * w.hs + w.k);
+    if (live && qb == w.s1) epi(acc, (w.s1 - 1) * w.hs + w.k);
 }
 
 }  // namespace dd
