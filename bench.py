@@ -340,7 +340,7 @@ def run_c5(args):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         if name == "fp32":
-            hop = ctx.timer_read(dd.KCLASS_HOP_F32)
+            hop = stencil_timer(ctx, "f32")
         ctx.timer_enable(False)
         ok = st == dd.DD_OK and bool(np.all(info["true_relres"] <= TOL))
         res[name] = {"solves_per_s": blk.n_blocks * nf / dt if ok else 0.0, "seconds": dt, "all_converged": ok,
@@ -349,7 +349,7 @@ def run_c5(args):
     ref = res["fp64"]["S_total"]
     for r in res.values():
         r["S_rel_diff_vs_fp64"] = abs(r["S_total"] - ref) / abs(ref)
-    hop_ms, hop_n, hop_bytes = hop
+    hop_kname, (hop_ms, hop_n, hop_bytes) = hop
     achieved = hop_bytes / (hop_ms * 1e-3) / 1e9 if hop_ms > 0 else 0.0
     best = res["fp32_nn"]
     out = {
@@ -378,7 +378,7 @@ def run_c5(args):
             "speedup_fp32_over_fp64": res["fp32"]["solves_per_s"] / max(res["fp64"]["solves_per_s"], 1e-30),
         },
         "roofline": {
-            "kernel": "k_hop (FP32, fields of one solve group) in the FP32 evaluation",
+            "kernel": hop_kname + " in the FP32 evaluation (fields of one solve group)",
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
@@ -396,7 +396,23 @@ def run_c5(args):
     ctx.close()
 
 
-PROFILE = os.path.join(ROOT, "profiles", "k_hop_f32_c2_32x4_12rhs.md")
+PROFILE = os.path.join(ROOT, "profiles", "k_dhat_walk_f32_c2_32x4_12rhs.md")
+
+
+def stencil_timer(ctx, inner):
+    """(description, (ms, launches, bytes)) of the stencil kernel of the BiCGStab inner solves: the
+    one-kernel x0-walk of Dhat when it ran, else the hop (two launches per Dhat)."""
+    from paper_2211_06902_amd import dd
+
+    dhat = {"f32": dd.KCLASS_DHAT_F32, "bf16": dd.KCLASS_DHAT_BF16}.get(inner)
+    link = "FP32 spinor / BF16 link" if inner == "bf16" else inner.upper()
+    if dhat is not None:
+        t = ctx.timer_read(dhat)
+        if t[1] > 0:
+            return ("k_dhat_walk (%s; Dhat = 1 - kappa^2 H_eo H_oe as one x0-walk, the intermediate in LDS, "
+                    "with the fused BiCGStab updates and dots)" % link, t)
+    hop = {"f64": dd.KCLASS_HOP_F64, "f32": dd.KCLASS_HOP_F32, "bf16": dd.KCLASS_HOP_BF16}[inner]
+    return ("k_hop_walk (%s; the x0-walk hop, all its fused-dot variants)" % link, ctx.timer_read(hop))
 
 
 def profiled_traffic():
@@ -499,11 +515,9 @@ def main():
     if gmres:
         kclass = dd.KCLASS_GMRES
         kname = "k_gmres (persistent GMRES(16), FP32 spinor / %s link, whole inner solve per launch)" % inner.upper()
+        k_ms, k_n, k_bytes = ctx.timer_read(kclass)
     else:
-        kclass = {"f64": dd.KCLASS_HOP_F64, "f32": dd.KCLASS_HOP_F32, "bf16": dd.KCLASS_HOP_BF16}[inner]
-        kname = "k_hop_walk (%s, 12 rhs; the x0-walk hop, all its fused-dot variants)" % (
-            "FP32 spinor / BF16 link" if inner == "bf16" else inner.upper())
-    k_ms, k_n, k_bytes = ctx.timer_read(kclass)
+        kname, (k_ms, k_n, k_bytes) = stencil_timer(ctx, inner)
     ctx.timer_enable(False)
 
     n_solves = blk.n_blocks * w["nrhs"]

@@ -249,12 +249,24 @@ dd_status dd_multiboson_action(dd_ctx *ctx, const dd_blocks *blocks, const dd_ga
 /* DD_TUNE_HOP_LDS: 1 (default) stages each hop tile's chunk of the input
  * field in LDS, 0 reads every neighbour from global memory.
  * DD_TUNE_HOP_WALK: the x0-walk of the hop (a workgroup streams the x0-slices
- * of a block for one rhs, reading each input slice once), used with one rhs
- * per thread when every block admits it (no block spans the lattice in x0,
- * at most 512 sites per x0-slice): 0 (default) automatic, -1 never, n >= 1
- * with each block's slices split into n segments (clamped to what the block
- * shapes allow).  Results do not depend on it beyond the summation order of
- * the fused dot products. */
+ * of a block for one group of rhs, reading each input slice once), used when
+ * every block admits it (no block spans the lattice in x0, at most 512 sites
+ * per x0-slice): 0 (default) automatic, -1 never, n >= 1 with each block's
+ * slices split into n segments (clamped to what the block shapes allow).
+ * Results do not depend on it beyond the summation order of the fused dot
+ * products.
+ * DD_TUNE_BICG_FUSE: BiCGStab without a preconditioner updates its vectors
+ * s = r - alpha v and p = r + beta (p - omega v) inside the first hop of
+ * Dhat s and Dhat p, as the x0-walk stages them (p only with one walk
+ * segment per block): 0 (default) where the x0-walk runs, -1 never (separate
+ * kernels).  Results do not depend on it beyond the rounding of contracted
+ * multiply-adds.
+ * DD_TUNE_DHAT_WALK: BiCGStab applies Dhat = 1 - kappa^2 H_eo H_oe as one
+ * x0-walk kernel per product (the odd intermediate H_oe x stays in LDS, one
+ * x0-slice at a time), with FP32 spinors when every block admits the walk
+ * and one walk per (block, rhs) covers the device: 0 (default) there, -1
+ * never (two hop launches and the intermediate in global memory).  Results
+ * do not depend on it beyond the summation order of the fused dot products. */
 /* Schedule of the persistent GMRES solver (0 = default):
  * DD_TUNE_GMRES_THREADS  threads per workgroup, 256 or 512;
  * DD_TUNE_GMRES_QUEUES   work queues, 1 (one global queue) or 8 (one per XCD:
@@ -283,7 +295,9 @@ enum {
     DD_TUNE_MB_FIELDS = 6,
     DD_TUNE_NN_KERNEL = 7,
     DD_TUNE_HOP_WALK = 8,
-    DD_TUNE_GMRES_REORTH = 9
+    DD_TUNE_GMRES_REORTH = 9,
+    DD_TUNE_BICG_FUSE = 10,
+    DD_TUNE_DHAT_WALK = 11
 };
 dd_status dd_tune_set(dd_ctx *ctx, int32_t what, int32_t value);
 
@@ -374,14 +388,20 @@ dd_status dd_nn_train(dd_ctx *ctx, dd_nn *nn, const dd_blocks *blocks, const voi
 /* DD_KCLASS_GMRES is the persistent GMRES launch (its algorithmic bytes are
  * counted per pair by the kernel).  DD_KCLASS_NN_BF16 is one BF16 application
  * of the network (three matrix-core launches) inside solves; its "bytes" field
- * counts the network's flops instead (414 720 per block site). */
+ * counts the network's flops instead (414 720 per block site).
+ * DD_KCLASS_DHAT_F32 / _BF16 are the one-kernel applications of Dhat in
+ * BiCGStab (DD_TUNE_DHAT_WALK), FP32 spinors with FP32 / BF16 links: bytes
+ * are the input and output fields, the operands of the fused dots other than
+ * those two, the BiCGStab update's operands and the links once. */
 enum {
     DD_KCLASS_HOP_F64 = 0,
     DD_KCLASS_HOP_F32 = 1,
     DD_KCLASS_HOP_BF16 = 2,
     DD_KCLASS_GMRES = 3,
     DD_KCLASS_NN_BF16 = 4,
-    DD_KCLASS_COUNT = 5
+    DD_KCLASS_DHAT_F32 = 5,
+    DD_KCLASS_DHAT_BF16 = 6,
+    DD_KCLASS_COUNT = 7
 };
 dd_status dd_timer_enable(dd_ctx *ctx, int32_t on);
 dd_status dd_timer_reset(dd_ctx *ctx);

@@ -180,15 +180,31 @@ double hop_bytes(const dd_blocks *B, int nr, dd_prec prec, int extra_vectors)
     return nr * half_sites * 24.0 * sf * (2 + extra_vectors) + (double)B->inner_links * (2.0 * kLinkK) * sl;
 }
 
+static bool walk_applies(const dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, dd_prec prec)
+{
+    return ctx->hop_lds && (ba.g == 1 || (ba.g == 2 && prec != DD_F64)) && B->walk && ctx->hop_walk >= 0;
+}
+
+int hop_walk_segments(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, dd_prec prec, hipError_t *err)
+{
+    *err = hipSuccess;
+    if (!walk_applies(ctx, B, ba, prec)) return 0;
+    int nseg = 1;
+    if (!walk_for(B, ba.n_rhs, ba.g, walk_segments(ctx, B, ba.n_rhs / ba.g), &nseg, err)) return 0;
+    return nseg;
+}
+
 hipError_t run_hop(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const HopArgs &ha_in, dd_prec prec)
 {
     HopArgs ha = ha_in;
     ha.use_lds = ctx->hop_lds ? 1 : 0;
-    // operands the kernel reads besides `in` (aux only in the dot modes that use it)
+    // operands the kernel reads besides `in` (aux only in the dot modes that use
+    // it); the staging updates read r, v (and p) and write the updated input
     const bool aux = ha.aux && (ha.dot_mode == kDotAuxOut || ha.dot_mode == kDotOutAuxOutOut);
-    const int extra = (ha.self != nullptr) + (ha.add != nullptr) + (aux ? 1 : 0);
+    const int extra = (ha.self != nullptr) + (ha.add != nullptr) + (aux ? 1 : 0) +
+                      (ha.pre == kPreP ? 3 : (ha.pre == kPreS ? 2 : 0));
     TimedLaunch tl(ctx, DD_KCLASS_HOP_F64 + (int)prec, hop_bytes(B, ba.n_rhs, prec, extra));
-    if (ha.use_lds && (ba.g == 1 || (ba.g == 2 && prec != DD_F64)) && B->walk && ctx->hop_walk >= 0) {
+    if (walk_applies(ctx, B, ba, prec)) {
         hipError_t err;
         int nseg = 1;
         const TileTable *wt = walk_for(B, ba.n_rhs, ba.g, walk_segments(ctx, B, ba.n_rhs / ba.g), &nseg, &err);
@@ -202,6 +218,38 @@ hipError_t run_hop(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const Hop
         return launch_hop_walk(ba, wa, ha, prec, ctx->stream);
     }
     return launch_hop(ba, ha, prec, ctx->stream);
+}
+
+bool dhat_walk_applies(const dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, dd_prec prec)
+{
+    if (!ctx->hop_lds || !B->walk || ctx->hop_walk < 0 || ctx->dhat_walk < 0) return false;
+    if (prec != DD_F32 && prec != DD_BF16) return false;
+    return walk_segments(ctx, B, ba.n_rhs) == 1;
+}
+
+hipError_t run_dhat(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const HopArgs &ha_in, dd_prec prec)
+{
+    HopArgs ha = ha_in;
+    ha.use_lds = 1;
+    // algorithmic operands besides `in` and `out`: the self term when it is
+    // not `in` itself, aux in the dot modes that use it, and the staging
+    // update's r, v (and p) reads and its write of the updated input
+    const bool aux = ha.aux && (ha.dot_mode == kDotAuxOut || ha.dot_mode == kDotOutAuxOutOut);
+    const int extra = (ha.self != nullptr && ha.self != ha.in) + (ha.add != nullptr) + (aux ? 1 : 0) +
+                      (ha.pre == kPreP ? 3 : (ha.pre == kPreS ? 2 : 0));
+    TimedLaunch tl(ctx, prec == DD_F32 ? DD_KCLASS_DHAT_F32 : DD_KCLASS_DHAT_BF16, hop_bytes(B, ba.n_rhs, prec, extra));
+    hipError_t err;
+    int nseg = 1;
+    const TileTable *wt = walk_for(B, ba.n_rhs, 1, 1, &nseg, &err);
+    if (!wt) return err;
+    if (nseg != 1) return hipErrorInvalidValue;
+    WalkArgs wa;
+    wa.tile_block = wt->d_tile_block;
+    wa.blk_tile0 = wt->d_blk_tile0;
+    wa.ext = B->d_ext;
+    wa.ntiles = wt->ntiles;
+    wa.nseg = 1;
+    return launch_dhat_walk(ba, wa, ha, prec, ctx->stream);
 }
 
 HopArgs hop_args(void *out, const void *in, const void *links, int parity, double c_hop)
@@ -593,6 +641,16 @@ dd_status dd_tune_set(dd_ctx *ctx, int32_t what, int32_t value)
     if (what == DD_TUNE_HOP_WALK) {
         if (value < -1 || value > 64) return fail(ctx, DD_EINVAL, "hop walk must be -1 (off), 0 (automatic) or 1..64 segments");
         ctx->hop_walk = value;
+        return DD_OK;
+    }
+    if (what == DD_TUNE_DHAT_WALK) {
+        if (value != 0 && value != -1) return fail(ctx, DD_EINVAL, "Dhat walk must be 0 (where possible) or -1 (never)");
+        ctx->dhat_walk = value;
+        return DD_OK;
+    }
+    if (what == DD_TUNE_BICG_FUSE) {
+        if (value != 0 && value != -1) return fail(ctx, DD_EINVAL, "BiCGStab fusion must be 0 (where possible) or -1 (never)");
+        ctx->bicg_fuse = value;
         return DD_OK;
     }
     if (what == DD_TUNE_GMRES_REORTH) {

@@ -22,6 +22,13 @@ BlkArgs blk_args(const dd_blocks *B, const TileTable *tt, int nr, int g);
 const void *links_for(const dd_gauge *G, dd_prec prec);
 double hop_bytes(const dd_blocks *B, int nr, dd_prec prec, int extra_vectors);
 hipError_t run_hop(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const HopArgs &ha, dd_prec prec);
+// Segments per block of the x0-walk that run_hop takes for these blocks, rhs
+// group and precision; 0 when it takes the chunked kernel.
+int hop_walk_segments(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, dd_prec prec, hipError_t *err);
+// Dhat = 1 - kappa^2 H_eo H_oe as one x0-walk kernel (launch_dhat_walk): when
+// it applies to these blocks, rhs and spinor/link precision, and its launch.
+bool dhat_walk_applies(const dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, dd_prec prec);
+hipError_t run_dhat(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const HopArgs &ha, dd_prec prec);
 HopArgs hop_args(void *out, const void *in, const void *links, int parity, double c_hop);
 
 // Timing of one kernel launch of a class (events only while timing is on).

@@ -55,6 +55,8 @@ struct dd_ctx {
     bool hop_lds = true;        // stage the hop's chunk of the input in LDS
     int hop_walk = 0;           // x0-walk of the hop: 0 automatic, -1 off, n >= 1 segments per block
     int gm_reorth = 0;          // GMRES reorthogonalization threshold: 0 default, -1 never, 1..100 percent of |w|
+    int bicg_fuse = 0;          // BiCGStab updates inside the walk hop: 0 where possible, -1 never
+    int dhat_walk = 0;          // Dhat as one x0-walk kernel in BiCGStab: 0 where possible, -1 never
     int gm_threads = 0;         // persistent GMRES: threads per workgroup (0 = default)
     int gm_queues = 0;          // persistent GMRES: work queues, 1 or 8 (0 = default)
     int gm_wg_per_cu = 0;       // persistent GMRES: resident workgroups per CU (0 = all that fit)
@@ -195,7 +197,20 @@ struct HopArgs {
     int parity;
     int dot_mode;
     int use_lds;  // 0: every neighbour is read from global memory
+    // update of `in` while the x0-walk stages it (kPre*; x0-walk only)
+    int pre;
+    const void *pre_r, *pre_v;
+    const double *pre_c0, *pre_c1;  // complex per pair: kPreP beta, omega; kPreS alpha
+    const int32_t *pre_act;         // per pair: 0 keeps `in` as it is
 };
+
+// Vector updates of BiCGStab done by the first hop of Dhat as it stages its
+// input (each input site is staged by one tile):
+//   kPreP: in <- r + beta (in - omega v)   (the search direction; needs a
+//          walk of one segment per block, so that no tile reads a site that
+//          another has already overwritten)
+//   kPreS: in <- r - alpha v                (written by the slice's owner)
+enum { kPreNone = 0, kPreP = 1, kPreS = 2 };
 
 // Per-pair Krylov state (device, structure of arrays).
 struct PairState {
@@ -333,6 +348,9 @@ hipError_t launch_unpack_spinor(const dd_blocks *B, const void *even, const void
                                 dd_prec prec, int n_rhs, hipStream_t s);
 hipError_t launch_hop(const BlkArgs &ba, const HopArgs &ha, dd_prec prec, hipStream_t s);
 hipError_t launch_hop_walk(const BlkArgs &ba, const WalkArgs &wa, const HopArgs &ha, dd_prec prec, hipStream_t s);
+// Dhat = c_self self + c_hop H_eo H_oe in on the even sites (one segment per
+// block, ntiles = nb * n_rhs walk tiles); FP32 spinors with FP32 or BF16 links.
+hipError_t launch_dhat_walk(const BlkArgs &ba, const WalkArgs &wa, const HopArgs &ha, dd_prec prec, hipStream_t s);
 hipError_t launch_convert(const void *src, dd_prec sp, void *dst, dd_prec dp, int64_t n,
                           hipStream_t s);
 hipError_t launch_accum(const BlkArgs &ba, double *x, const void *e, dd_prec ep,

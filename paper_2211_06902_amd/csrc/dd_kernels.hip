@@ -250,6 +250,7 @@ __global__ void __launch_bounds__(kTile) k_hop(BlkArgs ba, HopArgs ha)
 
 hipError_t launch_hop(const BlkArgs &ba, const HopArgs &ha, dd_prec prec, hipStream_t s)
 {
+    if (ha.pre != kPreNone) return hipErrorInvalidValue;  // staging updates are x0-walk only
     if (ba.ntiles <= 0) return hipSuccess;
     dim3 g(ba.ntiles), t(kTile);
     if (prec == DD_F64 && ba.g == 1)
@@ -267,9 +268,62 @@ hipError_t launch_hop(const BlkArgs &ba, const HopArgs &ha, dd_prec prec, hipStr
     return hipGetLastError();
 }
 
+// Staging load of the walk with a BiCGStab update of the input (PRE: kPreP
+// or kPreS) for the G rhs of the thread: the updated spinors go to the stage
+// and, on the slices the tile owns, back to `in`.  Pairs that stopped keep
+// their input.  Coefficients are rounded to SP as in k_bicg_p and k_bicg_s.
+template <typename SP, int G, int PRE>
+struct PreLoad {
+    Buf in_b, r_b, v_b;
+    uint32_t cstr;
+    bool act[G], zero[G];  // zero: beta = 0, the direction restarts as r
+    SP c0r[G], c0i[G], c1r[G], c1i[G];
+
+    __device__ __forceinline__ void operator()(SP (&v)[24][G], uint32_t vo, bool own) const
+    {
+#pragma unroll
+        for (int j = 0; j < G; j++) {
+            const uint32_t jo = (uint32_t)(j * 24) * cstr;
+            if (!act[j]) {
+#pragma unroll
+                for (int c = 0; c < 24; c++) v[c][j] = bload<SP>(in_b, vo, jo + (uint32_t)c * cstr);
+                continue;
+            }
+#pragma unroll
+            for (int a = 0; a < 12; a++) {
+                const uint32_t o0 = jo + (uint32_t)(2 * a) * cstr, o1 = o0 + cstr;
+                const SP rr = bload<SP>(r_b, vo, o0), ri = bload<SP>(r_b, vo, o1);
+                SP nr, ni;
+                if (PRE == kPreS) {
+                    const SP vr = bload<SP>(v_b, vo, o0), vi = bload<SP>(v_b, vo, o1);
+                    nr = rr - (c0r[j] * vr - c0i[j] * vi);
+                    ni = ri - (c0r[j] * vi + c0i[j] * vr);
+                } else if (zero[j]) {
+                    nr = rr;
+                    ni = ri;
+                } else {
+                    const SP vr = bload<SP>(v_b, vo, o0), vi = bload<SP>(v_b, vo, o1);
+                    const SP pr = bload<SP>(in_b, vo, o0), pi = bload<SP>(in_b, vo, o1);
+                    const SP qr = pr - (c1r[j] * vr - c1i[j] * vi);
+                    const SP qi = pi - (c1r[j] * vi + c1i[j] * vr);
+                    nr = rr + (c0r[j] * qr - c0i[j] * qi);
+                    ni = ri + (c0r[j] * qi + c0i[j] * qr);
+                }
+                v[2 * a][j] = nr;
+                v[2 * a + 1][j] = ni;
+            }
+            if (own) {
+#pragma unroll
+                for (int c = 0; c < 24; c++) bstore<SP>(in_b, v[c][j], vo, jo + (uint32_t)c * cstr);
+            }
+        }
+    }
+};
+
 // x0-walk of the hop (the walk itself is in dd_stencil.h): a tile walks one
-// of nseg segments of a block's x0-slices for one group of G rhs.
-template <typename SP, typename LK, typename AC, int G, int DM>
+// of nseg segments of a block's x0-slices for one group of G rhs.  PRE: the
+// BiCGStab update of the input done while staging it (kPre*).
+template <typename SP, typename LK, typename AC, int G, int DM, int PRE = kPreNone>
 __global__ void __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(sizeof(SP) == 8 && G == 1 && (DM == kDotNone || DM == kDotOutOut) ? 3 : 1)))
 k_hop_walk(BlkArgs ba, WalkArgs wa, HopArgs ha)
 {
@@ -309,12 +363,35 @@ k_hop_walk(BlkArgs ba, WalkArgs wa, HopArgs ha)
     for (int j = 0; j < G; j++)
 #pragma unroll
         for (int i = 0; i < kNRed; i++) dv[j][i] = 0;
-    walk_run<SP, LK, AC, G>(w, ns, stage, hc, [&](const AC (&acc)[G][24], int h) {
+    auto epi = [&](const AC (&acc)[G][24], int h) {
 #pragma unroll
         for (int j = 0; j < G; j++)
             hop_epilogue<SP, AC, DM>(acc[j], dv[j], ha, eb,
                                      (uint32_t)(hc.grp_off + j * 24 * w.hb + h) * (uint32_t)sizeof(SP), hc.cstr);
-    });
+    };
+    if constexpr (PRE == kPreNone) {
+        walk_run<SP, LK, AC, G>(w, ns, stage, hc, epi);
+    } else {
+        PreLoad<SP, G, PRE> pl;
+        pl.in_b = hc.in_b;
+        pl.r_b = make_buf(reinterpret_cast<const SP *>(ha.pre_r) + hbase, fbytes);
+        pl.v_b = make_buf(reinterpret_cast<const SP *>(ha.pre_v) + hbase, fbytes);
+        pl.cstr = hc.cstr;
+#pragma unroll
+        for (int j = 0; j < G; j++) {
+            const int pr = (grp * G + j) * ba.nb + b;
+            pl.act[j] = ha.pre_act[pr] != 0;
+            const double c0r = ha.pre_c0[2 * pr], c0i = ha.pre_c0[2 * pr + 1];
+            pl.c0r[j] = (SP)c0r;
+            pl.c0i[j] = (SP)c0i;
+            pl.zero[j] = c0r == 0.0 && c0i == 0.0;
+            pl.c1r[j] = PRE == kPreP ? (SP)ha.pre_c1[2 * pr] : (SP)0;
+            pl.c1i[j] = PRE == kPreP ? (SP)ha.pre_c1[2 * pr + 1] : (SP)0;
+        }
+        walk_run<SP, LK, AC, G>(w, ns, stage, hc, epi, [&](int q, SP (&v)[24][G]) {
+            pl(v, (uint32_t)(hc.grp_off + q * w.hs + w.k) * (uint32_t)sizeof(SP), q >= w.s0 && q < w.s1);
+        });
+    }
     if (DM != kDotNone) {
         // partial sums in the chunk tiles' slots: segment seg in chunk slot seg,
         // the block's remaining chunk slots zero
@@ -333,6 +410,14 @@ template <typename SP, typename LK, typename AC, int G>
 static void launch_walk_t(const BlkArgs &ba, const WalkArgs &wa, const HopArgs &ha, hipStream_t s)
 {
     dim3 g(wa.ntiles), t(kTile);
+    if (ha.pre == kPreP) {
+        hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, G, kDotNone, kPreP>), g, t, 0, s, ba, wa, ha);
+        return;
+    }
+    if (ha.pre == kPreS) {
+        hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, G, kDotNone, kPreS>), g, t, 0, s, ba, wa, ha);
+        return;
+    }
     switch (ha.dot_mode) {
     case kDotNone: hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, G, kDotNone>), g, t, 0, s, ba, wa, ha); break;
     case kDotAuxOut: hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, G, kDotAuxOut>), g, t, 0, s, ba, wa, ha); break;
@@ -346,6 +431,12 @@ hipError_t launch_hop_walk(const BlkArgs &ba, const WalkArgs &wa, const HopArgs 
 {
     if (wa.ntiles <= 0) return hipSuccess;
     if (wa.nseg < 1 || ha.dot_mode < kDotNone || ha.dot_mode > kDotOutAuxOutOut) return hipErrorInvalidValue;
+    if (ha.pre < kPreNone || ha.pre > kPreS) return hipErrorInvalidValue;
+    // the staging updates: no fused dots; kPreP rewrites its input in place,
+    // which only one tile per site may read
+    if (ha.pre != kPreNone && (ha.dot_mode != kDotNone || !ha.pre_r || !ha.pre_v || !ha.pre_c0 || !ha.pre_act ||
+                               (ha.pre == kPreP && (wa.nseg != 1 || !ha.pre_c1))))
+        return hipErrorInvalidValue;
     if (prec == DD_F64 && ba.g == 1)
         launch_walk_t<double, double, double, 1>(ba, wa, ha, s);
     else if (prec == DD_F32 && ba.g == 1)
@@ -359,6 +450,147 @@ hipError_t launch_hop_walk(const BlkArgs &ba, const WalkArgs &wa, const HopArgs 
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
+}
+
+// Dhat on the even sites in one x0-walk per (block, rhs):
+//   out = c_self self + c_hop H_eo (H_oe in)   (+ the fused dots of DM),
+// the odd intermediate H_oe in living in LDS one x0-slice at a time and never
+// in global memory.  Step q stages input slice q (with the BiCGStab update
+// PRE), which finishes intermediate slice q-1 in the second LDS slice; the
+// second hop then takes that slice and finishes output slice q-2.  Both hops
+// are x0-walks of the same block (dd_stencil.h), the first over the odd
+// output sites, the second over the even ones.  One segment per block, one
+// rhs per thread (the two LDS slices of 24 x 256 reals keep three workgroups
+// on a compute unit).  Dot partials go to the chunk slots of the site
+// kernels' tile table (rhs group ba.g): slot 0 of the block holds the sum,
+// its other slots are zero.
+template <typename SP, typename LK, typename AC, int DM, int PRE>
+__global__ void __launch_bounds__(kTile) k_dhat_walk(BlkArgs ba, WalkArgs wa, HopArgs ha)
+{
+    __shared__ SP sa[24 * kTile];  // input slice q
+    __shared__ SP sb[24 * kTile];  // intermediate slice q-1
+    __shared__ double red[1][kTile];
+    const int tile = uni(xcd_tile(blockIdx.x, wa.ntiles));
+    const int b = uni(wa.tile_block[tile]);
+    const int nr = ba.n_rhs;
+    const int r = tile - uni(wa.blk_tile0[b]);
+    const int hb = uni(ba.h[b]);
+    const int ns = uni(wa.ext[4 * b]);
+    const int hs = hb / ns;
+    const int k = threadIdx.x;
+    const bool live = k < hs;
+    const int32_t *nbt = ba.nbr + uni64(ba.nbr_off[b]);
+    const WalkPos wodd{1, hb, hs, k, 0, ns, nbt + (int64_t)hb * 8};
+    const WalkPos weven{0, hb, hs, k, 0, ns, nbt};
+    const int64_t soff = uni64(ba.soff[b]);
+    const int64_t hbase = (soff >> 1) * 24 * nr;
+    const uint32_t fbytes = (uint32_t)(nr * 24 * hb) * (uint32_t)sizeof(SP);
+    HopCtx hc;
+    hc.h0 = 0;
+    hc.tv = 0;
+    hc.slot_self = 0;
+    hc.other0 = 0;
+    hc.cstr = (uint32_t)hb * (uint32_t)sizeof(SP);
+    hc.kstr = (uint32_t)(4 * hb) * (uint32_t)sizeof(LK);
+    hc.grp_off = r * 24 * hb;
+    hc.in_b = make_buf(reinterpret_cast<const SP *>(ha.in) + hbase, fbytes);
+    hc.lk_b = make_buf(reinterpret_cast<const LK *>(ha.links) + soff * kLinkReals,
+                       (uint32_t)(2 * hb * kLinkReals) * (uint32_t)sizeof(LK));
+    const EpiBufs eb = epi_bufs<SP>(ha, hbase, fbytes);
+    PreLoad<SP, 1, PRE> pl;
+    if constexpr (PRE != kPreNone) {
+        pl.in_b = hc.in_b;
+        pl.r_b = make_buf(reinterpret_cast<const SP *>(ha.pre_r) + hbase, fbytes);
+        pl.v_b = make_buf(reinterpret_cast<const SP *>(ha.pre_v) + hbase, fbytes);
+        pl.cstr = hc.cstr;
+        const int pr = r * ba.nb + b;
+        pl.act[0] = ha.pre_act[pr] != 0;
+        const double c0r = ha.pre_c0[2 * pr], c0i = ha.pre_c0[2 * pr + 1];
+        pl.c0r[0] = (SP)c0r;
+        pl.c0i[0] = (SP)c0i;
+        pl.zero[0] = c0r == 0.0 && c0i == 0.0;
+        pl.c1r[0] = PRE == kPreP ? (SP)ha.pre_c1[2 * pr] : (SP)0;
+        pl.c1i[0] = PRE == kPreP ? (SP)ha.pre_c1[2 * pr + 1] : (SP)0;
+    }
+    double dv[1][kNRed];
+#pragma unroll
+    for (int i = 0; i < kNRed; i++) dv[0][i] = 0;
+    AC acc1[1][24], car1[1][12], acc2[1][24], car2[1][12];
+#pragma unroll
+    for (int c = 0; c < 24; c++) acc1[0][c] = acc2[0][c] = 0;
+#pragma unroll
+    for (int c = 0; c < 12; c++) car1[0][c] = car2[0][c] = 0;
+    // the intermediate site goes to the thread's own position of sb (rounded
+    // to SP as a stored field would be)
+    auto to_sb = [&](const AC (&acc)[1][24], int) {
+#pragma unroll
+        for (int c = 0; c < 24; c++) sb[c * kTile + k] = (SP)acc[0][c];
+    };
+    auto to_out = [&](const AC (&acc)[1][24], int h) {
+        hop_epilogue<SP, AC, DM>(acc[0], dv[0], ha, eb, (uint32_t)(hc.grp_off + h) * (uint32_t)sizeof(SP), hc.cstr);
+    };
+    for (int q = 0; q <= ns; q++) {
+        if (live && q < ns) {
+            SP v[24][1];
+            const uint32_t vo = (uint32_t)(hc.grp_off + q * hs + k) * (uint32_t)sizeof(SP);
+            if constexpr (PRE == kPreNone) {
+#pragma unroll
+                for (int c = 0; c < 24; c++) v[c][0] = bload<SP>(hc.in_b, vo, (uint32_t)c * hc.cstr);
+            } else {
+                pl(v, vo, true);
+            }
+            walk_stage<SP, 1>(sa, v, k);
+        }
+        __syncthreads();
+        if (live) {
+            if (q < ns)
+                walk_step<SP, LK, AC, 1>(acc1, car1, q, wodd, sa, hc, to_sb);
+            else
+                to_sb(acc1, (ns - 1) * hs + k);  // the last slice has no x0+ neighbour
+        }
+        __syncthreads();
+        if (live && q >= 1) walk_step<SP, LK, AC, 1>(acc2, car2, q - 1, weven, sb, hc, to_out);
+    }
+    if (live) to_out(acc2, (ns - 1) * hs + k);
+    if (DM != kDotNone) {
+        constexpr int nred = dot_nred(DM);
+        const int gb = ba.g, ngb = nr / gb;
+        const int t0 = uni(ba.blk_tile0[b]), nch = (uni(ba.blk_tile0[b + 1]) - t0) / ngb;
+        tile_sum<1>(red, dv, nred, ha.partial, (t0 + r / gb) * gb + r % gb);
+        for (int i = threadIdx.x; i < (nch - 1) * nred; i += kTile) {
+            const int ch = 1 + i / nred, kk = i % nred;
+            ha.partial[((int64_t)(t0 + ch * ngb + r / gb) * gb + r % gb) * kNRed + kk] = 0;
+        }
+    }
+}
+
+template <typename SP, typename LK, typename AC>
+static hipError_t launch_dhat_t(const BlkArgs &ba, const WalkArgs &wa, const HopArgs &ha, hipStream_t s)
+{
+    dim3 g(wa.ntiles), t(kTile);
+#define DD_DHAT(DMV, PREV) hipLaunchKernelGGL((k_dhat_walk<SP, LK, AC, DMV, PREV>), g, t, 0, s, ba, wa, ha)
+    if (ha.pre == kPreP && ha.dot_mode == kDotAuxOut) DD_DHAT(kDotAuxOut, kPreP);
+    else if (ha.pre == kPreS && ha.dot_mode == kDotOutSelfOutOut) DD_DHAT(kDotOutSelfOutOut, kPreS);
+    else if (ha.pre == kPreNone && ha.dot_mode == kDotAuxOut) DD_DHAT(kDotAuxOut, kPreNone);
+    else if (ha.pre == kPreNone && ha.dot_mode == kDotOutSelfOutOut) DD_DHAT(kDotOutSelfOutOut, kPreNone);
+    else if (ha.pre == kPreNone && ha.dot_mode == kDotOutAuxOutOut) DD_DHAT(kDotOutAuxOutOut, kPreNone);
+    else if (ha.pre == kPreNone && ha.dot_mode == kDotNone) DD_DHAT(kDotNone, kPreNone);
+    else return hipErrorInvalidValue;
+#undef DD_DHAT
+    return hipGetLastError();
+}
+
+hipError_t launch_dhat_walk(const BlkArgs &ba, const WalkArgs &wa, const HopArgs &ha, dd_prec prec, hipStream_t s)
+{
+    if (wa.ntiles <= 0) return hipSuccess;
+    // one walk of a whole block per rhs; the output is the even parity
+    if (wa.nseg != 1 || ha.parity != 0 || ba.n_rhs % ba.g != 0 || wa.ntiles != ba.nb * ba.n_rhs)
+        return hipErrorInvalidValue;
+    if (ha.pre != kPreNone && (!ha.pre_r || !ha.pre_v || !ha.pre_c0 || !ha.pre_act || (ha.pre == kPreP && !ha.pre_c1)))
+        return hipErrorInvalidValue;
+    if (prec == DD_F32) return launch_dhat_t<float, float, float>(ba, wa, ha, s);
+    if (prec == DD_BF16) return launch_dhat_t<float, uint16_t, float>(ba, wa, ha, s);
+    return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------- packing
@@ -851,6 +1083,8 @@ __global__ void __launch_bounds__(256) k_sc_init(BlkArgs ba, const double *parti
     ps.rho[2 * pair + 1] = 0;
     ps.omega[2 * pair] = 1;
     ps.omega[2 * pair + 1] = 0;
+    ps.beta[2 * pair] = 0;  // a direction update before the first iteration gives p = r
+    ps.beta[2 * pair + 1] = 0;
     ps.active[pair] = (finite(bb) && bb > 0) ? 1 : 0;
     if (!finite(bb)) ps.flags[pair] |= 4;
 }

@@ -52,10 +52,16 @@ struct Inner {
     dd_nn *nn;     // right preconditioner M (linear network) or null
     void *ph, *sh;  // M p, M s
     int n_rhs;
+    // vector updates done by the first hop of Dhat as it stages its input
+    bool fuse_s, fuse_p;
+    bool dhat;  // Dhat as one x0-walk kernel (run_dhat)
 };
 
 // one BiCGStab iteration on all pairs (10 launches; with a right
-// preconditioner M, Dhat is applied to M p and M s, x is updated with them)
+// preconditioner M, Dhat is applied to M p and M s, x is updated with them).
+// With fuse_p the direction update p = r + beta (p - omega v) that ends an
+// iteration is done by the first hop of the next one (beta = 0 before the
+// first: p = r); with fuse_s the first hop of Dhat s forms s = r - alpha v.
 hipError_t bicg_iteration(const Inner &in)
 {
     Ws &w = *in.w;
@@ -67,36 +73,74 @@ hipError_t bicg_iteration(const Inner &in)
         if ((e = nn_apply_half(in.ctx, in.nn, in.B, w.p, in.ph, in.n_rhs, in.sp, w.ps.active)) != hipSuccess) return e;
         pp = in.ph;
     }
-    // v = Dhat p
+    // v = Dhat p; alpha = rho / <rh, v>
     HopArgs h1 = hop_args(w.tmp, pp, in.links, 1, 1.0);
-    if ((e = run_hop(in.ctx, in.B, in.ba, h1, in.ip)) != hipSuccess) return e;
+    if (in.fuse_p) {
+        h1.pre = kPreP;
+        h1.pre_r = w.r;
+        h1.pre_v = w.v;
+        h1.pre_c0 = w.ps.beta;
+        h1.pre_c1 = w.ps.omega;
+        h1.pre_act = w.ps.active;
+    }
     HopArgs h2 = hop_args(w.v, w.tmp, in.links, 0, -k2);
     h2.self = pp;
     h2.c_self = 1.0;
     h2.aux = w.rh;
     h2.dot_mode = kDotAuxOut;
     h2.partial = w.pA;
-    if ((e = run_hop(in.ctx, in.B, in.ba, h2, in.ip)) != hipSuccess) return e;
+    if (in.dhat) {
+        HopArgs d = h2;
+        d.in = pp;
+        d.pre = h1.pre;
+        d.pre_r = h1.pre_r;
+        d.pre_v = h1.pre_v;
+        d.pre_c0 = h1.pre_c0;
+        d.pre_c1 = h1.pre_c1;
+        d.pre_act = h1.pre_act;
+        if ((e = run_dhat(in.ctx, in.B, in.ba, d, in.ip)) != hipSuccess) return e;
+    } else {
+        if ((e = run_hop(in.ctx, in.B, in.ba, h1, in.ip)) != hipSuccess) return e;
+        if ((e = run_hop(in.ctx, in.B, in.ba, h2, in.ip)) != hipSuccess) return e;
+    }
     if ((e = launch_sc_alpha(in.ba, w.pA, w.ps, st)) != hipSuccess) return e;
-    if ((e = launch_bicg_s(in.ba, in.sp, w.r, w.v, w.s, w.ps, st)) != hipSuccess) return e;
+    if (!in.fuse_s && (e = launch_bicg_s(in.ba, in.sp, w.r, w.v, w.s, w.ps, st)) != hipSuccess) return e;
     if (in.nn) {
         if ((e = nn_apply_half(in.ctx, in.nn, in.B, w.s, in.sh, in.n_rhs, in.sp, w.ps.active)) != hipSuccess) return e;
         ss = in.sh;
     }
     // t = Dhat s; omega = <t, s> / <t, t>
     HopArgs h3 = hop_args(w.tmp, ss, in.links, 1, 1.0);
-    if ((e = run_hop(in.ctx, in.B, in.ba, h3, in.ip)) != hipSuccess) return e;
+    if (in.fuse_s) {
+        h3.pre = kPreS;
+        h3.pre_r = w.r;
+        h3.pre_v = w.v;
+        h3.pre_c0 = w.ps.alpha;
+        h3.pre_act = w.ps.active;
+    }
     HopArgs h4 = hop_args(w.t, w.tmp, in.links, 0, -k2);
     h4.self = ss;
     h4.c_self = 1.0;
     h4.dot_mode = in.nn ? kDotOutAuxOutOut : kDotOutSelfOutOut;
     h4.aux = in.nn ? w.s : nullptr;
     h4.partial = w.pB;
-    if ((e = run_hop(in.ctx, in.B, in.ba, h4, in.ip)) != hipSuccess) return e;
+    if (in.dhat) {
+        HopArgs d = h4;
+        d.in = ss;
+        d.pre = h3.pre;
+        d.pre_r = h3.pre_r;
+        d.pre_v = h3.pre_v;
+        d.pre_c0 = h3.pre_c0;
+        d.pre_act = h3.pre_act;
+        if ((e = run_dhat(in.ctx, in.B, in.ba, d, in.ip)) != hipSuccess) return e;
+    } else {
+        if ((e = run_hop(in.ctx, in.B, in.ba, h3, in.ip)) != hipSuccess) return e;
+        if ((e = run_hop(in.ctx, in.B, in.ba, h4, in.ip)) != hipSuccess) return e;
+    }
     if ((e = launch_sc_omega(in.ba, w.pB, w.ps, st)) != hipSuccess) return e;
     if ((e = launch_bicg_xr(in.ba, in.sp, w.xi, pp, ss, w.s, w.t, w.r, w.rh, w.pC, w.ps, st)) != hipSuccess) return e;
     if ((e = launch_sc_beta(in.ba, w.pC, w.ps, in.tol, st)) != hipSuccess) return e;
-    return launch_bicg_p(in.ba, in.sp, w.r, w.v, w.p, w.ps, st);
+    return in.fuse_p ? hipSuccess : launch_bicg_p(in.ba, in.sp, w.r, w.v, w.p, w.ps, st);
 }
 
 double default_inner_tol(dd_prec ip, double tol)
@@ -319,7 +363,18 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
     HIPCHECK(ctx, hipMemsetAsync(w.xo, 0, h64, st));
     HIPCHECK(ctx, launch_pack_spinor(B, (const double *)b_dev, w.be, w.bo, DD_F64, n_rhs, st));
 
-    Inner in{ctx, B, ba, &w, links, ip, sp, kappa, inner_tol, gmres ? nullptr : nn, bc_ph, bc_sh, n_rhs};
+    Inner in{ctx, B, ba, &w, links, ip, sp, kappa, inner_tol, gmres ? nullptr : nn, bc_ph, bc_sh, n_rhs,
+             false, false, false};
+    if (!gmres) {
+        in.dhat = dhat_walk_applies(ctx, B, ba, ip);
+        if (!nn && ctx->bicg_fuse == 0) {
+            hipError_t we;
+            const int nseg = in.dhat ? 1 : hop_walk_segments(ctx, B, ba, ip, &we);
+            if (!in.dhat) HIPCHECK(ctx, we);
+            in.fuse_s = nseg >= 1;
+            in.fuse_p = nseg == 1;
+        }
+    }
     std::vector<int32_t> h_act(np);
     hipGraph_t g = nullptr;
     hipGraphExec_t gx = nullptr;

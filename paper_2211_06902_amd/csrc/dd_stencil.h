@@ -411,18 +411,23 @@ struct WalkPos {
     const int32_t *nbt;        // neighbour table of the output parity
 };
 
-// Copies input slice q of the thread's G rhs (component-major, kTile sites
-// per component, the G rhs of a site adjacent) into the stage.
+// Loads input slice q of the thread's G rhs at its site (component c of rhs
+// j in v[c][j]).
 template <typename SP, int G>
-__device__ __forceinline__ void walk_stage(SP *stage, const HopCtx &hc, int q, int hs, int k, bool live)
+__device__ __forceinline__ void walk_load(SP (&v)[24][G], const HopCtx &hc, int q, int hs, int k)
 {
-    if (!live) return;
     const uint32_t vo = (uint32_t)(hc.grp_off + q * hs + k) * (uint32_t)sizeof(SP);
-    SP v[24][G];
 #pragma unroll
     for (int j = 0; j < G; j++)
 #pragma unroll
         for (int c = 0; c < 24; c++) v[c][j] = bload<SP>(hc.in_b, vo, (uint32_t)(j * 24 + c) * hc.cstr);
+}
+
+// Copies the thread's spinors v of one input slice into the stage
+// (component-major, kTile sites per component, the G rhs of a site adjacent).
+template <typename SP, int G>
+__device__ __forceinline__ void walk_stage(SP *stage, const SP (&v)[24][G], int k)
+{
 #pragma unroll
     for (int c = 0; c < 24; c++) stv<SP, G>(stage + (c * kTile + k) * G, v[c]);
 }
@@ -471,10 +476,12 @@ __device__ __forceinline__ void walk_step(AC (&acc)[G][24], AC (&carry)[G][12], 
 
 // The whole walk over output slices [w.s0, w.s1) (input slices one beyond
 // each end when they exist).  Every thread of the workgroup calls it (it has
-// barriers); threads k >= hs only take part in those.  epi(acc, h) writes
-// output site h of the thread's G rhs.
-template <typename SP, typename LK, typename AC, int G, typename EPI>
-__device__ __forceinline__ void walk_run(const WalkPos &w, int ns, SP *stage, const HopCtx &hc, EPI &&epi)
+// barriers); threads k >= hs only take part in those.  ld(q, v) produces the
+// thread's spinors of input slice q (every slice in [max(s0-1, 0),
+// min(s1+1, ns)) once, in order); epi(acc, h) writes output site h of the
+// thread's G rhs.
+template <typename SP, typename LK, typename AC, int G, typename EPI, typename LD>
+__device__ __forceinline__ void walk_run(const WalkPos &w, int ns, SP *stage, const HopCtx &hc, EPI &&epi, LD &&ld)
 {
     const int qa = max(w.s0 - 1, 0), qb = min(w.s1 + 1, ns);
     const bool live = w.k < w.hs;
@@ -487,7 +494,11 @@ __device__ __forceinline__ void walk_run(const WalkPos &w, int ns, SP *stage, co
         for (int c = 0; c < 12; c++) carry[j][c] = 0;
     }
     for (int q = qa; q < qb; q++) {
-        walk_stage<SP, G>(stage, hc, q, w.hs, w.k, live);
+        if (live) {
+            SP v[24][G];
+            ld(q, v);
+            walk_stage<SP, G>(stage, v, w.k);
+        }
         __syncthreads();
         if (live) walk_step<SP, LK, AC, G>(acc, carry, q, w, stage, hc, epi);
         __syncthreads();
@@ -495,6 +506,14 @@ __device__ __forceinline__ void walk_run(const WalkPos &w, int ns, SP *stage, co
     // the block's last slice has no x0+ neighbour: when the walk ends there,
     // its output is finished here
     if (live && qb == w.s1) epi(acc, (w.s1 - 1) * w.hs + w.k);
+}
+
+// The walk with the input slices read from hc.in_b.
+template <typename SP, typename LK, typename AC, int G, typename EPI>
+__device__ __forceinline__ void walk_run(const WalkPos &w, int ns, SP *stage, const HopCtx &hc, EPI &&epi)
+{
+    walk_run<SP, LK, AC, G>(w, ns, stage, hc, epi,
+                            [&](int q, SP (&v)[24][G]) { walk_load<SP, G>(v, hc, q, w.hs, w.k); });
 }
 
 }  // namespace dd

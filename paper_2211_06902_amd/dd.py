@@ -23,9 +23,10 @@ DD_OK, DD_EINVAL, DD_ENOMEM, DD_EDEVICE, DD_ENOCONV, DD_EUNSUPPORTED = range(6)
 F64, F32, BF16 = 0, 1, 2
 BICGSTAB, GMRES = 0, 1
 KCLASS_HOP_F64, KCLASS_HOP_F32, KCLASS_HOP_BF16, KCLASS_GMRES, KCLASS_NN_BF16 = 0, 1, 2, 3, 4
+KCLASS_DHAT_F32, KCLASS_DHAT_BF16 = 5, 6
 TUNE_RHS_GROUP_F64, TUNE_RHS_GROUP_F32, TUNE_HOP_LDS = 0, 1, 2
 TUNE_GMRES_THREADS, TUNE_GMRES_QUEUES, TUNE_GMRES_WG_PER_CU, TUNE_MB_FIELDS, TUNE_NN_KERNEL = 3, 4, 5, 6, 7
-TUNE_HOP_WALK, TUNE_GMRES_REORTH = 8, 9
+TUNE_HOP_WALK, TUNE_GMRES_REORTH, TUNE_BICG_FUSE, TUNE_DHAT_WALK = 8, 9, 10, 11
 _PREC = {"f64": F64, "f32": F32, "bf16": BF16, F64: F64, F32: F32, BF16: BF16}
 
 if not os.path.exists(LIB_PATH):
@@ -478,8 +479,9 @@ class Context:
     def tune_set(self, what, value):
         """what: TUNE_RHS_GROUP_F64 / TUNE_RHS_GROUP_F32 (value 0 = auto, 1, 2 or 4), TUNE_HOP_LDS (0/1),
         TUNE_GMRES_THREADS (0, 256, 512), TUNE_GMRES_QUEUES (0, 1, 8), TUNE_GMRES_WG_PER_CU (0 = all that fit),
-        TUNE_MB_FIELDS, TUNE_NN_KERNEL (0/1), TUNE_HOP_WALK (-1 off, 0 auto, n segments) or
-        TUNE_GMRES_REORTH (0 default, -1 never, 1..100 percent)."""
+        TUNE_MB_FIELDS, TUNE_NN_KERNEL (0/1), TUNE_HOP_WALK (-1 off, 0 auto, n segments),
+        TUNE_GMRES_REORTH (0 default, -1 never, 1..100 percent) or TUNE_BICG_FUSE (0 where possible,
+        -1 never) or TUNE_DHAT_WALK (0 where possible, -1 never)."""
         self._check(_lib.dd_tune_set(self._h, int(what), int(value)))
 
     def autotune_gmres(self, blocks: Blocks, gauge: Gauge, kappa, b, params=None, scratch=None):

@@ -305,3 +305,32 @@ def test_network_parity_modes_change_nothing(ctx, toy):
         ctx.tune_set(dd.TUNE_NN_KERNEL, 1)
     assert np.array_equal(out[0][1], out[1][1])
     assert _cfg.rel_err(out[1][0], out[0][0]) <= 1e-12
+
+
+def test_network_preconditioned_bicgstab_with_dhat_walk(ctx, toy):
+    """BiCGStab with the network as right preconditioner applies Dhat to M p and M s; with one walk
+    segment per block it takes the one-kernel x0-walk of Dhat (intermediate in LDS, the dot with rh or
+    with s fused).  Same solve as with two hop launches: every pair to tolerance, same solution, the same
+    iteration counts up to rounding at the stopping test."""
+    from oracle import geometry
+    from tests import _cfg
+
+    from paper_2211_06902_amd import dd
+
+    b = synth.spinor_field(toy["L"], 4, 64)[:, _cfg.block_sites(toy["L"], geometry.tile_boxes(toy["L"], [[4, 4]] * 4))]
+    bd = _dev(b)
+    prm = dd.solve_params(inner_prec="f32", precond=toy["net"])
+    out = []
+    try:
+        ctx.tune_set(dd.TUNE_HOP_WALK, 1)
+        for k in (0, -1):
+            ctx.tune_set(dd.TUNE_DHAT_WALK, k)
+            x, info, st = ctx.block_solve(toy["blk"], toy["g"], toy["kappa"], bd, params=prm)
+            assert st == dd.DD_OK
+            assert np.all(info["true_relres"] <= 1e-10)
+            out.append((x.cpu().numpy(), info["iters"].astype(np.int64)))
+    finally:
+        ctx.tune_set(dd.TUNE_HOP_WALK, 0)
+        ctx.tune_set(dd.TUNE_DHAT_WALK, 0)
+    assert np.max(np.abs(out[0][1] - out[1][1])) <= 2
+    assert _cfg.rel_err(out[0][0], out[1][0]) <= 1e-9

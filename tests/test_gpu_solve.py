@@ -218,3 +218,85 @@ def test_solve_uneven_slabs_walk_segments(ctx, walk):
         for r in range(3):
             assert _true_relres(L, kappa, U, bx, x[r, sl], b[r, sl]) <= TOL
     g.close()
+
+
+@pytest.mark.parametrize("inner", ["f64", "f32", "bf16"])
+def test_bicg_updates_fused_into_hop(ctx, inner):
+    """BiCGStab on every path of its inner products against the plainest one (two hop launches, the
+    intermediate in global memory, separate update kernels): Dhat as one x0-walk kernel with the updates
+    s = r - alpha v and p = r + beta (p - omega v) formed as it stages its input, or without them; the
+    updates inside the first of two hop launches (one walk segment per block: both; three: s only).
+    Every pair to tolerance (oracle residual), the same solution and, up to rounding at the stopping
+    test, the same iteration counts.  Ragged x0 extents (6 and 10 slices), 4 rhs (two per thread in the
+    hop launches for FP32)."""
+    from paper_2211_06902_amd import dd
+
+    L = (16, 8, 8, 8)
+    segs = [[6, 10], [8], [4, 4], [8]]
+    kappa = 0.13
+    U = synth.gauge_field(L, 0.4, 33)
+    boxes = geometry.tile_boxes(L, segs)
+    sites = _cfg.block_sites(L, boxes)
+    off = _cfg.site_offsets(boxes)
+    b = synth.spinor_field(L, 4, 34)[:, sites]
+    blk = ctx.make_blocks(L, -1, segs)
+    g = ctx.load_gauge(blk, _dev(U), "bf16" if inner == "bf16" else "f32")
+    out = {}
+    # (walk segments, update fusion, Dhat walk)
+    paths = [(1, -1, -1), (1, 0, 0), (1, -1, 0), (1, 0, -1), (3, 0, 0)]
+    try:
+        for walk, fuse, dhat in paths:
+            ctx.tune_set(dd.TUNE_HOP_WALK, walk)
+            ctx.tune_set(dd.TUNE_BICG_FUSE, fuse)
+            ctx.tune_set(dd.TUNE_DHAT_WALK, dhat)
+            x, info, st = ctx.block_solve(blk, g, kappa, _dev(b), params=dd.solve_params(inner_prec=inner))
+            assert st == dd.DD_OK, (walk, fuse, dhat)
+            out[(walk, fuse, dhat)] = (x.cpu().numpy(), info["iters"])
+    finally:
+        ctx.tune_set(dd.TUNE_HOP_WALK, 0)
+        ctx.tune_set(dd.TUNE_BICG_FUSE, 0)
+        ctx.tune_set(dd.TUNE_DHAT_WALK, 0)
+    x_ref, it_ref = out[paths[0]]
+    for key, (x, it) in out.items():
+        for k, bx in enumerate(boxes):
+            sl = slice(off[k], off[k + 1])
+            for r in range(4):
+                assert _true_relres(L, kappa, U, bx, x[r, sl], b[r, sl]) <= TOL, (key, k, r)
+        assert _cfg.rel_err(x, x_ref) <= 1e-8, key
+        assert np.max(np.abs(it.astype(np.int64) - it_ref)) <= 2, key
+    g.close()
+
+
+def test_bicg_fused_updates_isolate_zero_and_nan_sources(ctx):
+    """With both updates inside the walk hop, a zero source (never active) gives x = 0 and a NaN source
+    (stopped once flagged) leaves the other pairs of its block and rhs group to converge as before."""
+    from paper_2211_06902_amd import dd
+
+    L = (16, 8, 8, 8)
+    segs = [[8, 8], [8], [8], [8]]
+    kappa = 0.13
+    U = synth.gauge_field(L, 0.4, 35)
+    boxes = geometry.tile_boxes(L, segs)
+    sites = _cfg.block_sites(L, boxes)
+    off = _cfg.site_offsets(boxes)
+    b = synth.spinor_field(L, 4, 36)[:, sites]
+    b[0, off[1]:off[2]] = 0.0      # pair (rhs 0, block 1)
+    b[1, off[0] + 17, 3, 2] = np.nan  # pair (rhs 1, block 0): its rhs group partner is rhs 0
+    blk = ctx.make_blocks(L, -1, segs)
+    g = ctx.load_gauge(blk, _dev(U), "f32")
+    try:
+        ctx.tune_set(dd.TUNE_HOP_WALK, 1)
+        x, info, st = ctx.block_solve(blk, g, kappa, _dev(b), params=dd.solve_params(inner_prec="f32"))
+    finally:
+        ctx.tune_set(dd.TUNE_HOP_WALK, 0)
+    assert st == dd.DD_ENOCONV
+    x = x.cpu().numpy()
+    assert np.all(x[0, off[1]:off[2]] == 0) and info["flags"][0, 1] & 1
+    assert info["flags"][1, 0] & 4 and not info["flags"][1, 0] & 1
+    for r in range(4):
+        for k, bx in enumerate(boxes):
+            if (r, k) in [(1, 0), (0, 1)]:
+                continue
+            sl = slice(off[k], off[k + 1])
+            assert _true_relres(L, kappa, U, bx, x[r, sl], b[r, sl]) <= TOL, (r, k)
+    g.close()
