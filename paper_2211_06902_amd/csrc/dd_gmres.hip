@@ -167,6 +167,62 @@ __device__ __forceinline__ double wg_hop_walk(const PairGeo &g, int p, int ns, S
     return nn;
 }
 
+// out = c_hop H_eo (H_oe in) + c_self self + c_add add on the even sites of
+// one pair in one pass over the x0-slices (dhat_run in dd_stencil.h): the odd
+// intermediate stays in LDS (sa: input slice, sb: intermediate slice).  One
+// rhs per thread, FP32 spinors; self and add may be null.  Returns the
+// thread's share of |out|^2.  All threads call it.
+template <typename SP, typename LK, int NT>
+__device__ __forceinline__ double wg_dhat_walk(const PairGeo &g, int ns, SP *sa, SP *sb, const SP *in, SP *out,
+                                               const SP *self, double c_self, double c_hop, const SP *add,
+                                               double c_add)
+{
+    using AC = SP;
+    const int hs = g.h / ns, k = threadIdx.x;
+    const WalkPos wodd{1, g.h, hs, k, 0, ns, g.nbr + (size_t)g.h * 8};
+    const WalkPos weven{0, g.h, hs, k, 0, ns, g.nbr};
+    HopCtx hc;
+    hc.h0 = 0;
+    hc.tv = 0;
+    hc.slot_self = 0;
+    hc.other0 = 0;
+    hc.grp_off = 0;
+    hc.cstr = (uint32_t)g.h * (uint32_t)sizeof(SP);
+    hc.kstr = g.kstr;
+    hc.in_b = make_buf(in, (uint32_t)(24 * g.h) * (uint32_t)sizeof(SP));
+    hc.lk_b = g.lk_b;
+    const AC ch = (AC)c_hop, cs = (AC)c_self, ca = (AC)c_add;
+    const uint32_t vbytes = (uint32_t)(24 * g.h) * (uint32_t)sizeof(SP);
+    const Buf ob = make_buf(out, vbytes), fb = make_buf(self, self ? vbytes : 0), ab = make_buf(add, add ? vbytes : 0);
+    const bool has_self = self != nullptr, has_add = add != nullptr;
+    double nn = 0;
+    auto epi = [&](const AC (&acc1)[1][24], int h) {
+        const AC(&acc)[24] = acc1[0];
+        const uint32_t vo = (uint32_t)h * (uint32_t)sizeof(SP);
+#pragma unroll
+        for (int half = 0; half < 2; half++) {
+            SP sv[12], av[12];
+#pragma unroll
+            for (int q = 0; q < 12; q++) {
+                sv[q] = bload<SP>(fb, vo, (uint32_t)(12 * half + q) * hc.cstr);
+                av[q] = bload<SP>(ab, vo, (uint32_t)(12 * half + q) * hc.cstr);
+            }
+#pragma unroll
+            for (int q = 0; q < 12; q++) {
+                AC v = ch * acc[12 * half + q];
+                if (has_self) v = fmad(cs, (AC)sv[q], v);
+                if (has_add) v = fmad(ca, (AC)av[q], v);
+                const SP ov = (SP)v;
+                bstore<SP>(ob, ov, vo, (uint32_t)(12 * half + q) * hc.cstr);
+                nn += (double)ov * (double)ov;
+            }
+        }
+    };
+    dhat_run<SP, LK, AC>(wodd, weven, ns, sa, sb, hc,
+                         [&](int q, SP (&v)[24][1]) { walk_load<SP, 1>(v, hc, q, hs, k); }, epi);
+    return nn;
+}
+
 // out[2i] + i out[2i+1] = <V_i, V_iw> = sum conj(V_i) V_iw for i <= j, FP64
 // products and sums.  Every thread runs over its own elements and keeps the
 // sums of a group of up to 8 basis vectors (all loads of an element issued
@@ -274,20 +330,34 @@ enum { kGoOn = 0, kRestart = 1, kConverged = 2, kMaxIter = 3, kNonFinite = 4, kP
 // One launch solves every pair listed in the queues whose `active` flag is set
 // and leaves e = Dhat^{-1} f (to the relative tolerance, or the last iterate)
 // in x; every workgroup leaves the loop once all queues are drained.
-// WALK: the hops walk the x0-slices (wg_hop_walk), else wg_hop.  FP32
-// spinors: at most 168 registers, so that three wavefronts share a SIMD.
+// WALK: the hops walk the x0-slices, else wg_hop; with FP32 spinors both
+// hops of Dhat are one pass over the slices (wg_dhat_walk), with FP64 two
+// (wg_hop_walk).  FP32 spinors: at most 168 registers, so that three
+// wavefronts share a SIMD.
 template <typename SP, typename LK, int M, int NT, bool WALK>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(SP) == 4 ? 3 : 1))) k_gmres(GmArgs a)
 {
+    constexpr bool FUSED = WALK && sizeof(SP) == 4;
     constexpr int NW = NT / 64;
     constexpr int NV = 2 * (M + 1) + 1;
     static_assert(NV <= NT, "one thread per reduced value");
     __shared__ double red[NW];
-    __shared__ double sum[NV];
-    __shared__ double red2[NW * NV];
     __shared__ SP stage[WALK ? 24 * kTile : 1];  // input slice of the walking hops
-    __shared__ double Hm[(M + 1) * M * 2];  // Hm[(i * M + j) * 2 + ri], row i, column j
-    __shared__ double cs[M], sn[2 * M], gv[2 * (M + 1)], yv[2 * (M + 1)];
+    // the Gram-Schmidt sums (sum, red2) and the back substitution's y share
+    // one buffer with the intermediate slice of wg_dhat_walk: they are dead
+    // while it runs (barriers on both sides), and three workgroups of 256
+    // threads keep fitting on a compute unit
+    constexpr int NSUM = NW * NV + NV + 2 * (M + 1);
+    constexpr int NSL = FUSED ? 24 * kTile * (int)sizeof(SP) / (int)sizeof(double) : 0;
+    __shared__ double xbuf[NSL > NSUM ? NSL : NSUM];
+    double *const red2 = xbuf, *const sum = xbuf + NW * NV, *const yv = sum + NV;
+    SP *const stage2 = reinterpret_cast<SP *>(xbuf);
+    // the Hessenberg matrix's entries i <= j (the subdiagonal is folded into the
+    // rotations at once and never stored), packed by columns: H_ij at
+    // hm(i, j)[0] + i hm(i, j)[1]
+    __shared__ double Hm[M * (M + 1)];
+    auto hm = [&](int i, int j) { return Hm + (j * (j + 1) + 2 * i); };
+    __shared__ double cs[M], sn[2 * M], gv[2 * (M + 1)];
     __shared__ int s_pair, s_stop;
     __shared__ double s_est;
 
@@ -379,7 +449,9 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
                 const bool zf = j == 0 && use_z;
                 const SP *src = zf ? z0 : vj;
                 const double cs1 = zf ? 1.0 / beta : 1.0, ch1 = zf ? -k2 / beta : -k2;
-                if constexpr (WALK) {
+                if constexpr (FUSED) {
+                    wg_dhat_walk<SP, LK, NT>(g, ns, stage, stage2, src, w, src, cs1, ch1, nullptr, 0.0);
+                } else if constexpr (WALK) {
                     wg_hop_walk<SP, LK, NT>(g, 1, ns, stage, src, tmp, nullptr, 0.0, 1.0, nullptr, 0.0);
                     __syncthreads();
                     wg_hop_walk<SP, LK, NT>(g, 0, ns, stage, tmp, w, src, cs1, ch1, nullptr, 0.0);
@@ -398,8 +470,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
                 gs_dots<SP, M, NT, NV>(sl, j + 1, h, j, true, sum, red2);
                 if (threadIdx.x == 0)
                     for (int i = 0; i <= j; i++) {
-                        Hm[(i * M + j) * 2] = sum[2 * i];
-                        Hm[(i * M + j) * 2 + 1] = sum[2 * i + 1];
+                        hm(i, j)[0] = sum[2 * i];
+                        hm(i, j)[1] = sum[2 * i + 1];
                     }
                 double s2 = 0;
                 for (int i = 0; i <= j; i++) s2 += sum[2 * i] * sum[2 * i] + sum[2 * i + 1] * sum[2 * i + 1];
@@ -415,8 +487,8 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
                     hh = sum[NV - 1] - s2;
                     if (threadIdx.x == 0)
                         for (int i = 0; i <= j; i++) {
-                            Hm[(i * M + j) * 2] += sum[2 * i];
-                            Hm[(i * M + j) * 2 + 1] += sum[2 * i + 1];
+                            hm(i, j)[0] += sum[2 * i];
+                            hm(i, j)[1] += sum[2 * i + 1];
                         }
                     moved += (2.0 * (j + 1) + 4.0) * vb;
                 }
@@ -424,7 +496,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
                 if (threadIdx.x == 0) {
                     // previous rotations on column j: (a, b) <- (c a + s b, -conj(s) a + c b)
                     for (int i = 0; i < j; i++) {
-                        double *pa = Hm + (i * M + j) * 2, *pb2 = Hm + ((i + 1) * M + j) * 2;
+                        double *pa = hm(i, j), *pb2 = hm(i + 1, j);
                         const double ar = pa[0], ai = pa[1], br = pb2[0], bi = pb2[1];
                         const double sr = sn[2 * i], si = sn[2 * i + 1], cc = cs[i];
                         pa[0] = cc * ar + (sr * br - si * bi);
@@ -433,7 +505,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
                         pb2[1] = cc * bi - (sr * ai - si * ar);
                     }
                     // new rotation zeroing the real subdiagonal hn below a = Hm[j][j]
-                    double *pd = Hm + (j * M + j) * 2;
+                    double *pd = hm(j, j);
                     const double ar = pd[0], ai = pd[1];
                     const double aa = sqrt(ar * ar + ai * ai);
                     double cc, sr, si;
@@ -478,9 +550,11 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
                     k = j + 1;
                 }
                 it++;
-                // two hops (5 vectors, links twice) and two Gram-Schmidt passes
-                // (the second pair counted above)
-                moved += (2.0 * (j + 1) + 8.0) * vb + 2.0 * lb;
+                // the product: input and w, the links (with two hops: the
+                // intermediate twice, the self term, the input, once more and
+                // the links twice); two Gram-Schmidt passes: V_0..V_j and w,
+                // then again and w written (a reorthogonalizing pair counted above)
+                moved += FUSED ? (2.0 * (j + 1) + 5.0) * vb + lb : (2.0 * (j + 1) + 8.0) * vb + 2.0 * lb;
                 __syncthreads();
             }
             // x += V y with R y = g (back substitution on the rotated Hessenberg matrix)
@@ -489,11 +563,11 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
                     for (int i = k - 1; i >= 0; i--) {
                         double sr = gv[2 * i], si = gv[2 * i + 1];
                         for (int l = i + 1; l < k; l++) {
-                            const double hr = Hm[(i * M + l) * 2], hi = Hm[(i * M + l) * 2 + 1];
+                            const double hr = hm(i, l)[0], hi = hm(i, l)[1];
                             sr -= hr * yv[2 * l] - hi * yv[2 * l + 1];
                             si -= hr * yv[2 * l + 1] + hi * yv[2 * l];
                         }
-                        const double dr = Hm[(i * M + i) * 2], di = Hm[(i * M + i) * 2 + 1];
+                        const double dr = hm(i, i)[0], di = hm(i, i)[1];
                         const double den = dr * dr + di * di;
                         yv[2 * i] = (sr * dr + si * di) / den;
                         yv[2 * i + 1] = (si * dr - sr * di) / den;
@@ -520,7 +594,9 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
             if (stop != kRestart) break;
             // restart from the explicit residual V_0 = f - Dhat x
             double rn;
-            if constexpr (WALK) {
+            if constexpr (FUSED) {
+                rn = wg_dhat_walk<SP, LK, NT>(g, ns, stage, stage2, x, V, x, -1.0, k2, f, 1.0);
+            } else if constexpr (WALK) {
                 wg_hop_walk<SP, LK, NT>(g, 1, ns, stage, x, tmp, nullptr, 0.0, 1.0, nullptr, 0.0);
                 __syncthreads();
                 rn = wg_hop_walk<SP, LK, NT>(g, 0, ns, stage, tmp, V, x, -1.0, k2, f, 1.0);
@@ -531,7 +607,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
             }
             beta = sqrt(wg_sum1<NT>(rn, red));
             est = beta;
-            moved += 6.0 * vb + 2.0 * lb;
+            moved += FUSED ? 3.0 * vb + lb : 6.0 * vb + 2.0 * lb;
             if (!isfinite(beta)) {
                 stop = kNonFinite;
                 break;

@@ -478,7 +478,6 @@ __global__ void __launch_bounds__(kTile) k_dhat_walk(BlkArgs ba, WalkArgs wa, Ho
     const int ns = uni(wa.ext[4 * b]);
     const int hs = hb / ns;
     const int k = threadIdx.x;
-    const bool live = k < hs;
     const int32_t *nbt = ba.nbr + uni64(ba.nbr_off[b]);
     const WalkPos wodd{1, hb, hs, k, 0, ns, nbt + (int64_t)hb * 8};
     const WalkPos weven{0, hb, hs, k, 0, ns, nbt};
@@ -515,43 +514,19 @@ __global__ void __launch_bounds__(kTile) k_dhat_walk(BlkArgs ba, WalkArgs wa, Ho
     double dv[1][kNRed];
 #pragma unroll
     for (int i = 0; i < kNRed; i++) dv[0][i] = 0;
-    AC acc1[1][24], car1[1][12], acc2[1][24], car2[1][12];
-#pragma unroll
-    for (int c = 0; c < 24; c++) acc1[0][c] = acc2[0][c] = 0;
-#pragma unroll
-    for (int c = 0; c < 12; c++) car1[0][c] = car2[0][c] = 0;
-    // the intermediate site goes to the thread's own position of sb (rounded
-    // to SP as a stored field would be)
-    auto to_sb = [&](const AC (&acc)[1][24], int) {
-#pragma unroll
-        for (int c = 0; c < 24; c++) sb[c * kTile + k] = (SP)acc[0][c];
-    };
     auto to_out = [&](const AC (&acc)[1][24], int h) {
         hop_epilogue<SP, AC, DM>(acc[0], dv[0], ha, eb, (uint32_t)(hc.grp_off + h) * (uint32_t)sizeof(SP), hc.cstr);
     };
-    for (int q = 0; q <= ns; q++) {
-        if (live && q < ns) {
-            SP v[24][1];
-            const uint32_t vo = (uint32_t)(hc.grp_off + q * hs + k) * (uint32_t)sizeof(SP);
-            if constexpr (PRE == kPreNone) {
+    auto ld = [&](int q, SP (&v)[24][1]) {
+        const uint32_t vo = (uint32_t)(hc.grp_off + q * hs + k) * (uint32_t)sizeof(SP);
+        if constexpr (PRE == kPreNone) {
 #pragma unroll
-                for (int c = 0; c < 24; c++) v[c][0] = bload<SP>(hc.in_b, vo, (uint32_t)c * hc.cstr);
-            } else {
-                pl(v, vo, true);
-            }
-            walk_stage<SP, 1>(sa, v, k);
+            for (int c = 0; c < 24; c++) v[c][0] = bload<SP>(hc.in_b, vo, (uint32_t)c * hc.cstr);
+        } else {
+            pl(v, vo, true);
         }
-        __syncthreads();
-        if (live) {
-            if (q < ns)
-                walk_step<SP, LK, AC, 1>(acc1, car1, q, wodd, sa, hc, to_sb);
-            else
-                to_sb(acc1, (ns - 1) * hs + k);  // the last slice has no x0+ neighbour
-        }
-        __syncthreads();
-        if (live && q >= 1) walk_step<SP, LK, AC, 1>(acc2, car2, q - 1, weven, sb, hc, to_out);
-    }
-    if (live) to_out(acc2, (ns - 1) * hs + k);
+    };
+    dhat_run<SP, LK, AC>(wodd, weven, ns, sa, sb, hc, ld, to_out);
     if (DM != kDotNone) {
         constexpr int nred = dot_nred(DM);
         const int gb = ba.g, ngb = nr / gb;
@@ -874,12 +849,24 @@ __global__ void __launch_bounds__(kTile) k_bicg_s(BlkArgs ba, const SP *r, const
     for (int j = 0; j < G; j++) {
         if (!act[j]) continue;
         const SP a_r = (SP)ar[j], a_i = (SP)ai[j];
-#pragma unroll 4
-        for (int k = 0; k < 12; k++) {
-            const int64_t i0 = t.base + eoff(t, j, 2 * k), i1 = i0 + t.hb;
-            const SP vr = v[i0], vi = v[i1];
-            s[i0] = r[i0] - (a_r * vr - a_i * vi);
-            s[i1] = r[i1] - (a_r * vi + a_i * vr);
+        // all loads of a half spinor before its stores (s could alias r, v
+        // as far as the compiler knows)
+#pragma unroll
+        for (int half = 0; half < 2; half++) {
+            SP rv[12], vv[12];
+#pragma unroll
+            for (int q = 0; q < 12; q++) {
+                const int64_t i = t.base + eoff(t, j, 12 * half + q);
+                rv[q] = r[i];
+                vv[q] = v[i];
+            }
+#pragma unroll
+            for (int k = 0; k < 6; k++) {
+                const int q0 = 2 * k, q1 = q0 + 1;
+                const int64_t i0 = t.base + eoff(t, j, 12 * half + q0), i1 = i0 + t.hb;
+                s[i0] = rv[q0] - (a_r * vv[q0] - a_i * vv[q1]);
+                s[i1] = rv[q1] - (a_r * vv[q1] + a_i * vv[q0]);
+            }
         }
     }
 }
@@ -903,21 +890,38 @@ __global__ void __launch_bounds__(kTile) k_bicg_xr(BlkArgs ba, SP *x, const SP *
         for (int j = 0; j < G; j++) {
             if (!act[j]) continue;
             const SP a_r = (SP)ar[j], a_i = (SP)ai[j], w_r = (SP)wr[j], w_i = (SP)wi[j];
-#pragma unroll 2
-            for (int k = 0; k < 12; k++) {
-                const int64_t i0 = t.base + eoff(t, j, 2 * k), i1 = i0 + t.hb;
-                const SP pr = p[i0], pi = p[i1], sr = s[i0], si = s[i1], tr = tv[i0], ti = tv[i1];
-                const SP xr = own_sx ? sx[i0] : sr, xi = own_sx ? sx[i1] : si;
-                x[i0] = x[i0] + (a_r * pr - a_i * pi) + (w_r * xr - w_i * xi);
-                x[i1] = x[i1] + (a_r * pi + a_i * pr) + (w_r * xi + w_i * xr);
-                const SP nr_ = sr - (w_r * tr - w_i * ti);
-                const SP ni_ = si - (w_r * ti + w_i * tr);
-                r[i0] = nr_;
-                r[i1] = ni_;
-                const double a = (double)rh[i0], bq = (double)rh[i1], c = (double)nr_, d = (double)ni_;
-                dv[j][0] += a * c + bq * d;
-                dv[j][1] += a * d - bq * c;
-                dv[j][2] += c * c + d * d;
+            // two halves of 12 reals: every operand load of a half is issued
+            // before its stores (x and r could alias the operands as far as
+            // the compiler knows, which would otherwise order each load after
+            // the previous store)
+#pragma unroll
+            for (int half = 0; half < 2; half++) {
+                SP pv[12], sv[12], tq[12], xv[12], xo[12], hv[12];
+#pragma unroll
+                for (int q = 0; q < 12; q++) {
+                    const int64_t i = t.base + eoff(t, j, 12 * half + q);
+                    pv[q] = p[i];
+                    sv[q] = s[i];
+                    tq[q] = tv[i];
+                    xv[q] = own_sx ? sx[i] : sv[q];
+                    xo[q] = x[i];
+                    hv[q] = rh[i];
+                }
+#pragma unroll
+                for (int k = 0; k < 6; k++) {
+                    const int q0 = 2 * k, q1 = q0 + 1;
+                    const int64_t i0 = t.base + eoff(t, j, 12 * half + q0), i1 = i0 + t.hb;
+                    x[i0] = xo[q0] + (a_r * pv[q0] - a_i * pv[q1]) + (w_r * xv[q0] - w_i * xv[q1]);
+                    x[i1] = xo[q1] + (a_r * pv[q1] + a_i * pv[q0]) + (w_r * xv[q1] + w_i * xv[q0]);
+                    const SP nr_ = sv[q0] - (w_r * tq[q0] - w_i * tq[q1]);
+                    const SP ni_ = sv[q1] - (w_r * tq[q1] + w_i * tq[q0]);
+                    r[i0] = nr_;
+                    r[i1] = ni_;
+                    const double a = (double)hv[q0], bq = (double)hv[q1], c = (double)nr_, d = (double)ni_;
+                    dv[j][0] += a * c + bq * d;
+                    dv[j][1] += a * d - bq * c;
+                    dv[j][2] += c * c + d * d;
+                }
             }
         }
     }
@@ -938,14 +942,26 @@ __global__ void __launch_bounds__(kTile) k_bicg_p(BlkArgs ba, const SP *r, const
     for (int j = 0; j < G; j++) {
         if (!act[j]) continue;
         const SP b_r = (SP)br[j], b_i = (SP)bi[j], w_r = (SP)wr[j], w_i = (SP)wi[j];
-#pragma unroll 4
-        for (int k = 0; k < 12; k++) {
-            const int64_t i0 = t.base + eoff(t, j, 2 * k), i1 = i0 + t.hb;
-            const SP vr = v[i0], vi = v[i1];
-            const SP qr = p[i0] - (w_r * vr - w_i * vi);
-            const SP qi = p[i1] - (w_r * vi + w_i * vr);
-            p[i0] = r[i0] + (b_r * qr - b_i * qi);
-            p[i1] = r[i1] + (b_r * qi + b_i * qr);
+        // all loads of a half spinor before its stores (as in k_bicg_s)
+#pragma unroll
+        for (int half = 0; half < 2; half++) {
+            SP rv[12], vv[12], pv[12];
+#pragma unroll
+            for (int q = 0; q < 12; q++) {
+                const int64_t i = t.base + eoff(t, j, 12 * half + q);
+                rv[q] = r[i];
+                vv[q] = v[i];
+                pv[q] = p[i];
+            }
+#pragma unroll
+            for (int k = 0; k < 6; k++) {
+                const int q0 = 2 * k, q1 = q0 + 1;
+                const int64_t i0 = t.base + eoff(t, j, 12 * half + q0), i1 = i0 + t.hb;
+                const SP qr = pv[q0] - (w_r * vv[q0] - w_i * vv[q1]);
+                const SP qi = pv[q1] - (w_r * vv[q1] + w_i * vv[q0]);
+                p[i0] = rv[q0] + (b_r * qr - b_i * qi);
+                p[i1] = rv[q1] + (b_r * qi + b_i * qr);
+            }
         }
     }
 }

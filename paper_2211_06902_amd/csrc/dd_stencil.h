@@ -516,4 +516,48 @@ __device__ __forceinline__ void walk_run(const WalkPos &w, int ns, SP *stage, co
                             [&](int q, SP (&v)[24][G]) { walk_load<SP, G>(v, hc, q, w.hs, w.k); });
 }
 
+// Dhat-type product in one pass over a block's x0-slices, one rhs per
+// thread: out = epilogue of H_eo (H_oe in) on the even sites.  Two walks of
+// the same workgroup (wodd over the odd output sites, weven over the even
+// ones, both over all ns slices): step q stages input slice q (ld(q, v)) in
+// sa, which finishes slice q-1 of the odd intermediate; that slice goes to
+// sb (rounded to SP, as a stored field would be) and the second walk takes
+// it, finishing output slice q-2 with epi(acc, h).  The intermediate never
+// leaves LDS.  Two barriers per step: the second walk's reads of sb come
+// before the next writes of sb by the first barrier of the next step, and
+// the first walk's reads of sa before the next staging by the second.
+template <typename SP, typename LK, typename AC, typename LD, typename EPI>
+__device__ __forceinline__ void dhat_run(const WalkPos &wodd, const WalkPos &weven, int ns, SP *sa, SP *sb,
+                                         const HopCtx &hc, LD &&ld, EPI &&epi)
+{
+    const int k = wodd.k, hs = wodd.hs;
+    const bool live = k < hs;
+    AC acc1[1][24], car1[1][12], acc2[1][24], car2[1][12];
+#pragma unroll
+    for (int c = 0; c < 24; c++) acc1[0][c] = acc2[0][c] = 0;
+#pragma unroll
+    for (int c = 0; c < 12; c++) car1[0][c] = car2[0][c] = 0;
+    auto to_sb = [&](const AC (&acc)[1][24], int) {
+#pragma unroll
+        for (int c = 0; c < 24; c++) sb[c * kTile + k] = (SP)acc[0][c];
+    };
+    for (int q = 0; q <= ns; q++) {
+        if (live && q < ns) {
+            SP v[24][1];
+            ld(q, v);
+            walk_stage<SP, 1>(sa, v, k);
+        }
+        __syncthreads();
+        if (live) {
+            if (q < ns)
+                walk_step<SP, LK, AC, 1>(acc1, car1, q, wodd, sa, hc, to_sb);
+            else
+                to_sb(acc1, (ns - 1) * hs + k);  // the last slice has no x0+ neighbour
+        }
+        __syncthreads();
+        if (live && q >= 1) walk_step<SP, LK, AC, 1>(acc2, car2, q - 1, weven, sb, hc, epi);
+    }
+    if (live) epi(acc2, (ns - 1) * hs + k);
+}
+
 }  // namespace dd
