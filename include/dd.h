@@ -174,10 +174,14 @@ typedef struct {
     int32_t method;      /* DD_BICGSTAB (even-odd BiCGStab) or DD_GMRES (even-odd GMRES(restart)) */
     int32_t restart;     /* GMRES restart length, 1..16 (default 16) */
     dd_prec inner_prec;  /* stencil precision of the inner solve */
-    double inner_tol;    /* relative tolerance of each inner solve (<= 0: library default) */
+    double inner_tol;    /* relative tolerance of each inner solve (<= 0: library default:
+                            FP64 max(0.1 tol, 1e-14); FP32 max(0.3 sqrt(tol), 1e-6), two
+                            defect-correction cycles; BF16 links 2e-3) */
     int32_t max_outer;   /* defect-correction cycles (<= 0: default 30) */
     int32_t max_inner;   /* iterations per inner solve (<= 0: default 2000) */
-    int32_t check_every; /* BiCGStab: inner iterations between convergence polls (<= 0: default 8) */
+    int32_t check_every; /* BiCGStab: inner iterations between convergence polls (<= 0: default 2;
+                            pairs that converged stop updating at once, the launches
+                            stop at the next poll after the last one) */
     int32_t use_graph;   /* replay inner iterations (BiCGStab) or the persistent inner launch
                             (GMRES) from a captured hipGraph */
     const dd_nn *precond; /* network preconditioner (NULL: none); every block must have the

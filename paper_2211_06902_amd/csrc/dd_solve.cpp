@@ -143,10 +143,15 @@ hipError_t bicg_iteration(const Inner &in)
     return in.fuse_p ? hipSuccess : launch_bicg_p(in.ba, in.sp, w.r, w.v, w.p, w.ps, st);
 }
 
+// Inner tolerance by precision.  FP32: every defect-correction cycle cuts
+// the true residual by about the inner tolerance, so 0.3 sqrt(tol) reaches
+// tol in two cycles with a margin of ten; not below 1e-6, where the FP32
+// operator's rounding takes over.  BF16 links: their rounding (2^-9) bounds
+// what an inner solve can gain.
 double default_inner_tol(dd_prec ip, double tol)
 {
     if (ip == DD_F64) return std::max(0.1 * tol, 1e-14);
-    if (ip == DD_F32) return 1e-6;
+    if (ip == DD_F32) return std::max(0.3 * std::sqrt(tol), 1e-6);
     return 2e-3;
 }
 
@@ -223,7 +228,7 @@ void dd_solve_params_default(dd_solve_params *p)
     p->inner_tol = 0;
     p->max_outer = 30;
     p->max_inner = 2000;
-    p->check_every = 8;
+    p->check_every = 2;
     p->use_graph = 1;
 }
 
@@ -253,7 +258,7 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
     const double inner_tol = prm.inner_tol > 0 ? prm.inner_tol : default_inner_tol(ip, prm.tol);
     const int max_outer = prm.max_outer > 0 ? prm.max_outer : 30;
     const int max_inner = prm.max_inner > 0 ? prm.max_inner : 2000;
-    const int check = prm.check_every > 0 ? prm.check_every : 8;
+    const int check = prm.check_every > 0 ? prm.check_every : 2;
     const bool graph = prm.use_graph && !ctx->timing && !(nn && gmres);
 
     dd_blocks *B = const_cast<dd_blocks *>(Bc);
