@@ -227,6 +227,14 @@ bool dhat_walk_applies(const dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba,
     return walk_segments(ctx, B, ba.n_rhs) == 1;
 }
 
+hipError_t dhat_walk_prepare(const dd_blocks *B, const BlkArgs &ba)
+{
+    hipError_t err;
+    int nseg = 1;
+    if (!walk_for(B, ba.n_rhs, 1, 1, &nseg, &err)) return err;
+    return nseg == 1 ? hipSuccess : hipErrorInvalidValue;
+}
+
 hipError_t run_dhat(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const HopArgs &ha_in, dd_prec prec)
 {
     HopArgs ha = ha_in;
@@ -346,7 +354,11 @@ dd_status finish_blocks(dd_ctx *ctx, dd_blocks *B, dd_blocks **out)
             ext[4 * b + m] = B->box[16 * b + 4 + m];
         }
     }
+    B->iperm.assign(B->perm.size(), 0);
+    for (const Shape &sh : B->shapes)
+        for (int k = 0; k < sh.S; k++) B->iperm[sh.perm_off + B->perm[sh.perm_off + k]] = k;
     if ((e = upload(&B->d_nbr, B->nbr)) != hipSuccess || (e = upload(&B->d_perm, B->perm)) != hipSuccess ||
+        (e = upload(&B->d_iperm, B->iperm)) != hipSuccess ||
         (e = upload(&B->d_soff, B->soff)) != hipSuccess || (e = upload(&B->d_h, h)) != hipSuccess ||
         (e = upload(&B->d_nlinks, nl)) != hipSuccess ||
         (e = upload(&B->d_nbr_off, nbo)) != hipSuccess || (e = upload(&B->d_perm_off, pmo)) != hipSuccess ||
@@ -474,7 +486,7 @@ dd_status dd_free_blocks(dd_blocks *B)
 {
     if (!B) return DD_EINVAL;
     if (B->device >= 0) hipSetDevice(B->device);
-    void *ptrs[] = {B->d_nbr, B->d_perm, B->d_soff, B->d_h, B->d_nlinks, B->d_nbr_off, B->d_perm_off,
+    void *ptrs[] = {B->d_nbr, B->d_perm, B->d_iperm, B->d_soff, B->d_h, B->d_nlinks, B->d_nbr_off, B->d_perm_off,
                     B->d_origin, B->d_ext, B->d_bnd, B->d_boff};
     for (void *p : ptrs)
         if (p) hipFree(p);

@@ -28,6 +28,8 @@ int hop_walk_segments(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, dd_pre
 // Dhat = 1 - kappa^2 H_eo H_oe as one x0-walk kernel (launch_dhat_walk): when
 // it applies to these blocks, rhs and spinor/link precision, and its launch.
 bool dhat_walk_applies(const dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, dd_prec prec);
+// Builds its walk table (device memory: before any graph capture that launches it).
+hipError_t dhat_walk_prepare(const dd_blocks *B, const BlkArgs &ba);
 hipError_t run_dhat(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const HopArgs &ha, dd_prec prec);
 HopArgs hop_args(void *out, const void *in, const void *links, int parity, double c_hop);
 

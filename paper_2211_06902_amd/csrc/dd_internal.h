@@ -120,6 +120,7 @@ struct dd_blocks {
     std::vector<dd::Shape> shapes;
     std::vector<int32_t> nbr;       // all shapes: [2][h][8]
     std::vector<int32_t> perm;      // all shapes: [S] eo position -> local canonical index
+    std::vector<int32_t> iperm;     // all shapes: [S] local canonical index -> eo position
     std::vector<int32_t> bnd;       // dLambda_0 sites, box-local canonical, blocks concatenated
     std::vector<int64_t> boff;      // [nb+1] offsets into bnd
     int64_t inner_links = 0;
@@ -127,6 +128,7 @@ struct dd_blocks {
     // device copies
     int32_t *d_nbr = nullptr;
     int32_t *d_perm = nullptr;
+    int32_t *d_iperm = nullptr;
     int64_t *d_soff = nullptr;      // [nb+1]
     int32_t *d_h = nullptr;         // [nb] sites per parity
     int32_t *d_nlinks = nullptr;    // [nb] links inside the block
@@ -355,6 +357,8 @@ hipError_t launch_convert(const void *src, dd_prec sp, void *dst, dd_prec dp, in
                           hipStream_t s);
 hipError_t launch_accum(const BlkArgs &ba, double *x, const void *e, dd_prec ep,
                         const int32_t *active, hipStream_t s);
+// |a|^2 per (tile, rhs) of a half field into partial (slot 0 of kNRed)
+hipError_t launch_norm2(const BlkArgs &ba, dd_prec sp, const void *a, double *partial, hipStream_t s);
 hipError_t launch_bicg_init(const BlkArgs &ba, dd_prec sp, const void *rhs, void *r, void *rh,
                             void *p, void *x, double *partial, const int32_t *outer_active,
                             hipStream_t s);

@@ -579,6 +579,7 @@ struct PackGeom {
     const int32_t *nbr;
     const int64_t *perm_off;
     const int32_t *perm;
+    const int32_t *iperm;
     const int32_t *origin;
     const int32_t *ext;
 };
@@ -650,6 +651,7 @@ static PackGeom pack_geom(const dd_blocks *B)
     g.nbr = B->d_nbr;
     g.perm_off = B->d_perm_off;
     g.perm = B->d_perm;
+    g.iperm = B->d_iperm;
     g.origin = B->d_origin;
     g.ext = B->d_ext;
     return g;
@@ -671,9 +673,12 @@ hipError_t launch_pack_gauge(const dd_blocks *B, const double *U, dd_prec prec, 
 }
 
 // boundary layout [r][q][24] (q = block site, box-local canonical) <-> half fields.
-// Thread t -> (rhs r = t / total, eo block site q = t % total): consecutive
-// threads touch consecutive sites of one rhs in the half fields; each thread
-// moves one 192-byte spinor record of the boundary layout with 16-byte accesses.
+// Thread t -> (rhs r = t / total, block site q = t % total in the boundary
+// layout's box-local canonical order): a wavefront moves 64 consecutive
+// 192-byte spinor records of that layout (each thread one record, with
+// 16-byte accesses, so every cache line is used by the wavefront that
+// fetched it); on the half-field side consecutive threads alternate between
+// the two parities, each writing consecutive sites.
 template <typename SP, bool PACK>
 __global__ void __launch_bounds__(256) k_spinor_xfer(PackGeom g, double *ext_f, SP *even, SP *odd,
                                                     int nr, int64_t total)
@@ -681,13 +686,13 @@ __global__ void __launch_bounds__(256) k_spinor_xfer(PackGeom g, double *ext_f, 
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= total * nr) return;
     const int r = (int)(t / total);
-    const int64_t q = t - (int64_t)r * total;  // block site in eo order
+    const int64_t q = t - (int64_t)r * total;  // block site in canonical order
     const int b = find_block(g.soff, g.nb, q);
-    const int s = (int)(q - g.soff[b]);
+    const int y = (int)(q - g.soff[b]);
     const int hb = g.h[b];
+    const int s = g.iperm[g.perm_off[b] + y];  // its eo position
     const int p = s >= hb;
     const int site = s - p * hb;
-    const int y = g.perm[g.perm_off[b] + s];
     double2 *e = reinterpret_cast<double2 *>(ext_f + ((int64_t)r * total + g.soff[b] + y) * 24);
     SP *hf = (p ? odd : even) + (g.soff[b] >> 1) * 24 * nr + (int64_t)r * 24 * hb + site;
 #pragma unroll
@@ -806,6 +811,27 @@ __global__ void __launch_bounds__(kTile) k_accum(BlkArgs ba, double *x, const SE
 #pragma unroll 4
         for (int c = 0; c < 24; c++) x[eoff(t, j, c)] += (double)e[eoff(t, j, c)];
     }
+}
+
+// |a|^2 per (tile, rhs) of a half field (the partials of the hop's dot mode
+// kDotOutOut)
+template <typename SP, int G>
+__global__ void __launch_bounds__(kTile) k_norm2(BlkArgs ba, const SP *a, double *partial)
+{
+    __shared__ double red[G][kTile];
+    const Tile t = tile_of(ba);
+    double dv[G][kNRed] = {};
+    if (t.live) {
+#pragma unroll
+        for (int j = 0; j < G; j++) {
+            SP v[24];
+#pragma unroll
+            for (int c = 0; c < 24; c++) v[c] = a[t.base + eoff(t, j, c)];
+#pragma unroll
+            for (int c = 0; c < 24; c++) dv[j][0] += (double)v[c] * (double)v[c];
+        }
+    }
+    tile_sum<G>(red, dv, 1, partial, t.tile);
 }
 
 // BiCGStab start: r = rh = p = rhs, x = 0; |rhs|^2 per (tile, rhs)
@@ -972,6 +998,11 @@ static void launch_accum_t(const BlkArgs &ba, double *x, const void *e, const in
     hipLaunchKernelGGL((k_accum<SE, G>), dim3(ba.ntiles), dim3(kTile), 0, st, ba, x, (const SE *)e, active);
 }
 template <typename SP, int G>
+static void launch_norm2_t(const BlkArgs &ba, const void *a, double *partial, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_norm2<SP, G>), dim3(ba.ntiles), dim3(kTile), 0, st, ba, (const SP *)a, partial);
+}
+template <typename SP, int G>
 static void launch_init_t(const BlkArgs &ba, const void *rhs, void *r, void *rh, void *p, void *x, double *partial,
                           const int32_t *oa, hipStream_t st)
 {
@@ -1016,6 +1047,11 @@ hipError_t launch_accum(const BlkArgs &ba, double *x, const void *e, dd_prec ep,
                         hipStream_t st)
 {
     DD_DISPATCH(launch_accum_t, ep, ba, x, e, active, st);
+}
+
+hipError_t launch_norm2(const BlkArgs &ba, dd_prec sp, const void *a, double *partial, hipStream_t st)
+{
+    DD_DISPATCH(launch_norm2_t, sp, ba, a, partial, st);
 }
 
 hipError_t launch_bicg_init(const BlkArgs &ba, dd_prec sp, const void *rhs, void *r, void *rh, void *p, void *x,

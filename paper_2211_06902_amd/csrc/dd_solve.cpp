@@ -372,6 +372,7 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
              false, false, false};
     if (!gmres) {
         in.dhat = dhat_walk_applies(ctx, B, ba, ip);
+        if (in.dhat) HIPCHECK(ctx, dhat_walk_prepare(B, ba));
         if (!nn && ctx->bicg_fuse == 0) {
             hipError_t we;
             const int nseg = in.dhat ? 1 : hop_walk_segments(ctx, B, ba, ip, &we);
@@ -387,8 +388,14 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
     int64_t inner_total = 0;
     dd_status status = DD_OK;
     for (int cyc = 0;; cyc++) {
-        // FP64 true residual r_p = b_p - x_p + kappa H x_{1-p}, |r|^2 per pair
+        // FP64 true residual r_p = b_p - x_p + kappa H x_{1-p}, |r|^2 per pair;
+        // the first cycle starts from x = 0, where r = b
+        double *r_e = cyc == 0 ? w.be : w.re, *r_o = cyc == 0 ? w.bo : w.ro;
         for (int p = 0; p < 2; p++) {
+            if (cyc == 0) {
+                HIPCHECK(ctx, launch_norm2(ba64, DD_F64, p ? w.bo : w.be, p ? w.po : w.pe, st));
+                continue;
+            }
             HopArgs h = hop_args(p ? w.ro : w.re, p ? w.xe : w.xo, G->d_u64, p, kappa);
             h.self = p ? w.xo : w.xe;
             h.c_self = -1.0;
@@ -406,13 +413,17 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
         if (n_act == 0 || cyc >= max_outer) break;
         cycles++;
         // inner source rhs_e = r_e + kappa H_eo r_o in the inner precision
+        void *ri_e = w.rie, *ri_o = w.rio;
         if (sp != DD_F64) {
-            HIPCHECK(ctx, launch_convert(w.re, DD_F64, w.rie, sp, hel, st));
-            HIPCHECK(ctx, launch_convert(w.ro, DD_F64, w.rio, sp, hel, st));
+            HIPCHECK(ctx, launch_convert(r_e, DD_F64, w.rie, sp, hel, st));
+            HIPCHECK(ctx, launch_convert(r_o, DD_F64, w.rio, sp, hel, st));
+        } else {
+            ri_e = r_e;
+            ri_o = r_o;
         }
         {
-            HopArgs h = hop_args(w.rhs, w.rio, links, 0, kappa);
-            h.self = w.rie;
+            HopArgs h = hop_args(w.rhs, ri_o, links, 0, kappa);
+            h.self = ri_e;
             h.c_self = 1.0;
             HIPCHECK(ctx, run_hop(ctx, B, ba, h, ip));
         }
@@ -526,7 +537,7 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
         // e_o = r_o + kappa H_oe e_e, then x += e on the pairs above tolerance
         {
             HopArgs h = hop_args(w.tmp, w.xi, links, 1, kappa);
-            h.self = w.rio;
+            h.self = ri_o;
             h.c_self = 1.0;
             HIPCHECK(ctx, run_hop(ctx, B, ba, h, ip));
         }
