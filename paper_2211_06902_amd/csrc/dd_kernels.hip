@@ -674,35 +674,59 @@ hipError_t launch_pack_gauge(const dd_blocks *B, const double *U, dd_prec prec, 
 
 // boundary layout [r][q][24] (q = block site, box-local canonical) <-> half fields.
 // Thread t -> (rhs r = t / total, block site q = t % total in the boundary
-// layout's box-local canonical order): a wavefront moves 64 consecutive
-// 192-byte spinor records of that layout (each thread one record, with
-// 16-byte accesses, so every cache line is used by the wavefront that
-// fetched it); on the half-field side consecutive threads alternate between
-// the two parities, each writing consecutive sites.
+// layout's box-local canonical order).  The boundary layout holds thread t's
+// 192-byte spinor record at record t, so a workgroup's records are one
+// contiguous range: it is read or written with lane-contiguous 16-byte
+// accesses and transposed through LDS (records padded to 13 slots).  On the
+// half-field side consecutive threads alternate between the two parities,
+// each writing consecutive sites.
 template <typename SP, bool PACK>
 __global__ void __launch_bounds__(256) k_spinor_xfer(PackGeom g, double *ext_f, SP *even, SP *odd,
                                                     int nr, int64_t total)
 {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= total * nr) return;
-    const int r = (int)(t / total);
-    const int64_t q = t - (int64_t)r * total;  // block site in canonical order
-    const int b = find_block(g.soff, g.nb, q);
-    const int y = (int)(q - g.soff[b]);
-    const int hb = g.h[b];
-    const int s = g.iperm[g.perm_off[b] + y];  // its eo position
-    const int p = s >= hb;
-    const int site = s - p * hb;
-    double2 *e = reinterpret_cast<double2 *>(ext_f + ((int64_t)r * total + g.soff[b] + y) * 24);
-    SP *hf = (p ? odd : even) + (g.soff[b] >> 1) * 24 * nr + (int64_t)r * 24 * hb + site;
+    constexpr int kRec = 13;  // LDS slots (double2) per record: 12 used
+    __shared__ double2 tr[256 * kRec];
+    const int64_t n = total * nr;
+    const int64_t t0 = (int64_t)blockIdx.x * 256;
+    const int64_t t = t0 + threadIdx.x;
+    double2 *ext2 = reinterpret_cast<double2 *>(ext_f) + t0 * 12;  // this workgroup's records
+    const int64_t nel = (n - t0 < 256 ? n - t0 : 256) * 12;     // their 16-byte elements
+    if constexpr (PACK) {
 #pragma unroll
-    for (int k = 0; k < 12; k++) {
-        if constexpr (PACK) {
-            const double2 v = e[k];
-            hf[(int64_t)(2 * k) * hb] = (SP)v.x;
-            hf[(int64_t)(2 * k + 1) * hb] = (SP)v.y;
-        } else {
-            e[k] = make_double2((double)hf[(int64_t)(2 * k) * hb], (double)hf[(int64_t)(2 * k + 1) * hb]);
+        for (int k = 0; k < 12; k++) {
+            const int e = k * 256 + threadIdx.x;
+            if (e < nel) tr[(e / 12) * kRec + e % 12] = ext2[e];
+        }
+        __syncthreads();
+    }
+    if (t < n) {
+        const int r = (int)(t / total);
+        const int64_t q = t - (int64_t)r * total;  // block site in canonical order
+        const int b = find_block(g.soff, g.nb, q);
+        const int y = (int)(q - g.soff[b]);
+        const int hb = g.h[b];
+        const int s = g.iperm[g.perm_off[b] + y];  // its eo position
+        const int p = s >= hb;
+        const int site = s - p * hb;
+        SP *hf = (p ? odd : even) + (g.soff[b] >> 1) * 24 * nr + (int64_t)r * 24 * hb + site;
+        double2 *rec = tr + threadIdx.x * kRec;
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            if constexpr (PACK) {
+                const double2 v = rec[k];
+                hf[(int64_t)(2 * k) * hb] = (SP)v.x;
+                hf[(int64_t)(2 * k + 1) * hb] = (SP)v.y;
+            } else {
+                rec[k] = make_double2((double)hf[(int64_t)(2 * k) * hb], (double)hf[(int64_t)(2 * k + 1) * hb]);
+            }
+        }
+    }
+    if constexpr (!PACK) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 12; k++) {
+            const int e = k * 256 + threadIdx.x;
+            if (e < nel) ext2[e] = tr[(e / 12) * kRec + e % 12];
         }
     }
 }
