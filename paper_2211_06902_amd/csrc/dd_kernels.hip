@@ -832,8 +832,20 @@ __global__ void __launch_bounds__(kTile) k_accum(BlkArgs ba, double *x, const SE
 #pragma unroll
     for (int j = 0; j < G; j++) {
         if (!act[j]) continue;
-#pragma unroll 4
-        for (int c = 0; c < 24; c++) x[eoff(t, j, c)] += (double)e[eoff(t, j, c)];
+        // all loads of a half spinor before its stores (x could alias e as far
+        // as the compiler knows)
+#pragma unroll
+        for (int half = 0; half < 2; half++) {
+            double xv[12];
+            SE ev[12];
+#pragma unroll
+            for (int q = 0; q < 12; q++) {
+                xv[q] = x[eoff(t, j, 12 * half + q)];
+                ev[q] = e[eoff(t, j, 12 * half + q)];
+            }
+#pragma unroll
+            for (int q = 0; q < 12; q++) x[eoff(t, j, 12 * half + q)] = xv[q] + (double)ev[q];
+        }
     }
 }
 
@@ -858,7 +870,8 @@ __global__ void __launch_bounds__(kTile) k_norm2(BlkArgs ba, const SP *a, double
     tile_sum<G>(red, dv, 1, partial, t.tile);
 }
 
-// BiCGStab start: r = rh = p = rhs, x = 0; |rhs|^2 per (tile, rhs)
+// BiCGStab start: r = rh = p = rhs, x = 0; |rhs|^2 per (tile, rhs).  p may
+// be null (the first direction update of the iteration writes p = r).
 template <typename SP, int G>
 __global__ void __launch_bounds__(kTile) k_bicg_init(BlkArgs ba, const SP *rhs, SP *r, SP *rh, SP *p, SP *x,
                                                      double *partial, const int32_t *outer_active)
@@ -871,15 +884,20 @@ __global__ void __launch_bounds__(kTile) k_bicg_init(BlkArgs ba, const SP *rhs, 
 #pragma unroll
         for (int j = 0; j < G; j++) {
             if (!act[j]) continue;
-#pragma unroll 4
-            for (int c = 0; c < 24; c++) {
-                const int64_t i = t.base + eoff(t, j, c);
-                const SP v = rhs[i];
-                r[i] = v;
-                rh[i] = v;
-                p[i] = v;
-                x[i] = (SP)0;
-                dv[j][0] += (double)v * (double)v;
+#pragma unroll
+            for (int half = 0; half < 2; half++) {
+                SP v[12];
+#pragma unroll
+                for (int q = 0; q < 12; q++) v[q] = rhs[t.base + eoff(t, j, 12 * half + q)];
+#pragma unroll
+                for (int q = 0; q < 12; q++) {
+                    const int64_t i = t.base + eoff(t, j, 12 * half + q);
+                    r[i] = v[q];
+                    rh[i] = v[q];
+                    if (p) p[i] = v[q];
+                    x[i] = (SP)0;
+                    dv[j][0] += (double)v[q] * (double)v[q];
+                }
             }
         }
     }

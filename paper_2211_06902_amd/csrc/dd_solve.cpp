@@ -507,7 +507,7 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
                 HIPCHECK(ctx, launch_gmres(ga, ip, gm_nt, gm_grid, st));
             }
         } else {
-        HIPCHECK(ctx, launch_bicg_init(ba, sp, w.rhs, w.r, w.rh, w.p, w.xi, w.pA, w.os.active, st));
+        HIPCHECK(ctx, launch_bicg_init(ba, sp, w.rhs, w.r, w.rh, in.fuse_p ? nullptr : w.p, w.xi, w.pA, w.os.active, st));
         HIPCHECK(ctx, launch_sc_init(ba, w.pA, w.ps, w.os.active, st));
         // the network's workspaces and BF16 weights exist before any capture
         if (in.nn && !gx) HIPCHECK(ctx, nn_apply_half(ctx, in.nn, B, w.p, in.ph, n_rhs, sp));
