@@ -172,12 +172,21 @@ const void *links_for(const dd_gauge *G, dd_prec prec)
 // Algorithmic bytes of one hop launch: the half field it reads and the one it
 // writes (24 reals per site and rhs each), each extra half-field operand, and
 // every link inside the blocks once (18 reals).
-double hop_bytes(const dd_blocks *B, int nr, dd_prec prec, int extra_vectors)
+double hop_bytes(const dd_blocks *B, int nr, dd_prec prec, double extra_vectors)
 {
     const double sf = prec == DD_F64 ? 8.0 : 4.0;
     const double sl = (double)prec_bytes(prec);
     const double half_sites = (double)B->soff[B->nb] / 2.0;
     return nr * half_sites * 24.0 * sf * (2 + extra_vectors) + (double)B->inner_links * (2.0 * kLinkK) * sl;
+}
+
+// The aux operand of the fused dots in spinor-field units: the BiCGStab
+// shadow residual (mode kDotAuxOut) is BF16 with FP32 spinors, half a field.
+static double aux_vectors(const HopArgs &ha, dd_prec prec)
+{
+    if (!ha.aux) return 0.0;
+    if (ha.dot_mode == kDotAuxOut) return prec == DD_F64 ? 1.0 : 0.5;
+    return ha.dot_mode == kDotOutAuxOutOut ? 1.0 : 0.0;
 }
 
 static bool walk_applies(const dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, dd_prec prec)
@@ -200,9 +209,8 @@ hipError_t run_hop(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const Hop
     ha.use_lds = ctx->hop_lds ? 1 : 0;
     // operands the kernel reads besides `in` (aux only in the dot modes that use
     // it); the staging updates read r, v (and p) and write the updated input
-    const bool aux = ha.aux && (ha.dot_mode == kDotAuxOut || ha.dot_mode == kDotOutAuxOutOut);
-    const int extra = (ha.self != nullptr) + (ha.add != nullptr) + (aux ? 1 : 0) +
-                      (ha.pre == kPreP ? 3 : (ha.pre == kPreS ? 2 : 0));
+    const double extra = (ha.self != nullptr) + (ha.add != nullptr) + aux_vectors(ha, prec) +
+                         (ha.pre == kPreP ? 3 : (ha.pre == kPreS ? 2 : 0));
     TimedLaunch tl(ctx, DD_KCLASS_HOP_F64 + (int)prec, hop_bytes(B, ba.n_rhs, prec, extra));
     if (walk_applies(ctx, B, ba, prec)) {
         hipError_t err;
@@ -242,9 +250,8 @@ hipError_t run_dhat(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const Ho
     // algorithmic operands besides `in` and `out`: the self term when it is
     // not `in` itself, aux in the dot modes that use it, and the staging
     // update's r, v (and p) reads and its write of the updated input
-    const bool aux = ha.aux && (ha.dot_mode == kDotAuxOut || ha.dot_mode == kDotOutAuxOutOut);
-    const int extra = (ha.self != nullptr && ha.self != ha.in) + (ha.add != nullptr) + (aux ? 1 : 0) +
-                      (ha.pre == kPreP ? 3 : (ha.pre == kPreS ? 2 : 0));
+    const double extra = (ha.self != nullptr && ha.self != ha.in) + (ha.add != nullptr) + aux_vectors(ha, prec) +
+                         (ha.pre == kPreP ? 3 : (ha.pre == kPreS ? 2 : 0));
     TimedLaunch tl(ctx, prec == DD_F32 ? DD_KCLASS_DHAT_F32 : DD_KCLASS_DHAT_BF16, hop_bytes(B, ba.n_rhs, prec, extra));
     hipError_t err;
     int nseg = 1;

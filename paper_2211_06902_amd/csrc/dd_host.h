@@ -20,7 +20,7 @@ int rhs_group(const dd_ctx *ctx, int nr, dd_prec sp, dd_prec lk);
 int hop_group(const dd_ctx *ctx, int nr, dd_prec sp, dd_prec lk);
 BlkArgs blk_args(const dd_blocks *B, const TileTable *tt, int nr, int g);
 const void *links_for(const dd_gauge *G, dd_prec prec);
-double hop_bytes(const dd_blocks *B, int nr, dd_prec prec, int extra_vectors);
+double hop_bytes(const dd_blocks *B, int nr, dd_prec prec, double extra_vectors);
 hipError_t run_hop(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const HopArgs &ha, dd_prec prec);
 // Segments per block of the x0-walk that run_hop takes for these blocks, rhs
 // group and precision; 0 when it takes the chunked kernel.

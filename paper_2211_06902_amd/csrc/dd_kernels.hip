@@ -88,8 +88,25 @@ __device__ __forceinline__ void tile_sum(double (*red)[kTile], const double (&dv
 // ------------------------------------------------------------- hop
 
 
+// The BiCGStab shadow residual rh: any fixed vector with <rh, r_0> != 0
+// serves, so with FP32 spinors the solver keeps r_0 rounded to BF16 (half the
+// bytes of the two dot products per iteration that read it), with FP64 r_0.
+template <typename SP>
+struct ShadowT {
+    using T = SP;
+};
+template <>
+struct ShadowT<float> {
+    using T = uint16_t;
+};
+__device__ __forceinline__ double shadow_val(double v) { return v; }
+__device__ __forceinline__ float shadow_val(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+__device__ __forceinline__ double to_shadow(double v, double *) { return v; }
+__device__ __forceinline__ uint16_t to_shadow(float v, uint16_t *) { return f32_to_bf16_rne(v); }
+
 // Output operands of the hop epilogue, as block-relative buffer descriptors;
-// an absent operand gets a zero-size descriptor (its loads return 0).
+// an absent operand gets a zero-size descriptor (its loads return 0).  In
+// mode kDotAuxOut the aux operand is the shadow residual (ShadowT).
 struct EpiBufs {
     Buf out_b, self_b, add_b, aux_b;
     bool has_self, has_add;
@@ -98,12 +115,17 @@ struct EpiBufs {
 template <typename SP>
 __device__ __forceinline__ EpiBufs epi_bufs(const HopArgs &ha, int64_t hbase, uint32_t fbytes)
 {
+    using SH = typename ShadowT<SP>::T;
     EpiBufs eb;
     eb.out_b = make_buf(reinterpret_cast<const SP *>(ha.out) + hbase, fbytes);
     eb.self_b = make_buf(ha.self ? reinterpret_cast<const SP *>(ha.self) + hbase : nullptr, ha.self ? fbytes : 0);
     eb.add_b = make_buf(ha.add ? reinterpret_cast<const SP *>(ha.add) + hbase : nullptr, ha.add ? fbytes : 0);
-    const bool need_aux = ha.dot_mode == kDotAuxOut || ha.dot_mode == kDotOutAuxOutOut;
-    eb.aux_b = make_buf(need_aux ? reinterpret_cast<const SP *>(ha.aux) + hbase : nullptr, need_aux ? fbytes : 0);
+    if (ha.dot_mode == kDotAuxOut)
+        eb.aux_b = make_buf(reinterpret_cast<const SH *>(ha.aux) + hbase, fbytes / sizeof(SP) * sizeof(SH));
+    else if (ha.dot_mode == kDotOutAuxOutOut)
+        eb.aux_b = make_buf(reinterpret_cast<const SP *>(ha.aux) + hbase, fbytes);
+    else
+        eb.aux_b = make_buf(nullptr, 0);
     eb.has_self = ha.self != nullptr;
     eb.has_add = ha.add != nullptr;
     return eb;
@@ -133,7 +155,13 @@ __device__ __forceinline__ void hop_epilogue(const AC (&acc)[24], double (&dv)[k
             const uint32_t so = (uint32_t)(NQ * half + q) * cstr;
             sx[q] = bload<SP>(eb.self_b, my, so);
             dx[q] = bload<SP>(eb.add_b, my, so);
-            ax[q] = bload<SP>(eb.aux_b, my, so);
+            if (mode == kDotAuxOut) {
+                using SH = typename ShadowT<SP>::T;
+                constexpr uint32_t sh = sizeof(SP) / sizeof(SH);  // byte offsets scale with the element size
+                ax[q] = (SP)shadow_val(bload<SH>(eb.aux_b, my / sh, so / sh));
+            } else {
+                ax[q] = bload<SP>(eb.aux_b, my, so);
+            }
         }
 #pragma unroll
         for (int k = 0; k < NQ / 2; k++) {
@@ -870,11 +898,12 @@ __global__ void __launch_bounds__(kTile) k_norm2(BlkArgs ba, const SP *a, double
     tile_sum<G>(red, dv, 1, partial, t.tile);
 }
 
-// BiCGStab start: r = rh = p = rhs, x = 0; |rhs|^2 per (tile, rhs).  p may
-// be null (the first direction update of the iteration writes p = r).
+// BiCGStab start: r = p = rhs, rh = rhs in the shadow type (ShadowT), x = 0;
+// |rhs|^2 and <rh, rhs> per (tile, rhs).  p may be null (the first direction
+// update of the iteration writes p = r).
 template <typename SP, int G>
-__global__ void __launch_bounds__(kTile) k_bicg_init(BlkArgs ba, const SP *rhs, SP *r, SP *rh, SP *p, SP *x,
-                                                     double *partial, const int32_t *outer_active)
+__global__ void __launch_bounds__(kTile) k_bicg_init(BlkArgs ba, const SP *rhs, SP *r, typename ShadowT<SP>::T *rh,
+                                                     SP *p, SP *x, double *partial, const int32_t *outer_active)
 {
     __shared__ double red[G][kTile];
     const Tile t = tile_of(ba);
@@ -893,15 +922,24 @@ __global__ void __launch_bounds__(kTile) k_bicg_init(BlkArgs ba, const SP *rhs, 
                 for (int q = 0; q < 12; q++) {
                     const int64_t i = t.base + eoff(t, j, 12 * half + q);
                     r[i] = v[q];
-                    rh[i] = v[q];
+                    rh[i] = to_shadow(v[q], rh);
                     if (p) p[i] = v[q];
                     x[i] = (SP)0;
                     dv[j][0] += (double)v[q] * (double)v[q];
                 }
+#pragma unroll
+                for (int k = 0; k < 6; k++) {
+                    // conj(rh) rhs for one complex component
+                    const double ar = (double)shadow_val(to_shadow(v[2 * k], rh));
+                    const double ai = (double)shadow_val(to_shadow(v[2 * k + 1], rh));
+                    const double br = (double)v[2 * k], bi = (double)v[2 * k + 1];
+                    dv[j][1] += ar * br + ai * bi;
+                    dv[j][2] += ar * bi - ai * br;
+                }
             }
         }
     }
-    tile_sum<G>(red, dv, 1, partial, t.tile);
+    tile_sum<G>(red, dv, 3, partial, t.tile);
 }
 
 // s = r - alpha v
@@ -942,7 +980,8 @@ __global__ void __launch_bounds__(kTile) k_bicg_s(BlkArgs ba, const SP *r, const
 // x += alpha p + omega s;  r = s - omega t;  <rh, r>, |r|^2 per (tile, rhs)
 template <typename SP, int G>
 __global__ void __launch_bounds__(kTile) k_bicg_xr(BlkArgs ba, SP *x, const SP *p, const SP *sx, const SP *s,
-                                                   const SP *tv, SP *r, const SP *rh, double *partial, PairState ps)
+                                                   const SP *tv, SP *r, const typename ShadowT<SP>::T *rh,
+                                                   double *partial, PairState ps)
 {
     // x += alpha p + omega sx (sx = s, or M s with a right preconditioner M); r = s - omega t
     const bool own_sx = sx != s;
@@ -964,7 +1003,8 @@ __global__ void __launch_bounds__(kTile) k_bicg_xr(BlkArgs ba, SP *x, const SP *
             // the previous store)
 #pragma unroll
             for (int half = 0; half < 2; half++) {
-                SP pv[12], sv[12], tq[12], xv[12], xo[12], hv[12];
+                SP pv[12], sv[12], tq[12], xv[12], xo[12];
+                double hv[12];
 #pragma unroll
                 for (int q = 0; q < 12; q++) {
                     const int64_t i = t.base + eoff(t, j, 12 * half + q);
@@ -973,7 +1013,7 @@ __global__ void __launch_bounds__(kTile) k_bicg_xr(BlkArgs ba, SP *x, const SP *
                     tq[q] = tv[i];
                     xv[q] = own_sx ? sx[i] : sv[q];
                     xo[q] = x[i];
-                    hv[q] = rh[i];
+                    hv[q] = (double)shadow_val(rh[i]);
                 }
 #pragma unroll
                 for (int k = 0; k < 6; k++) {
@@ -985,7 +1025,7 @@ __global__ void __launch_bounds__(kTile) k_bicg_xr(BlkArgs ba, SP *x, const SP *
                     const SP ni_ = sv[q1] - (w_r * tq[q1] + w_i * tq[q0]);
                     r[i0] = nr_;
                     r[i1] = ni_;
-                    const double a = (double)hv[q0], bq = (double)hv[q1], c = (double)nr_, d = (double)ni_;
+                    const double a = hv[q0], bq = hv[q1], c = (double)nr_, d = (double)ni_;
                     dv[j][0] += a * c + bq * d;
                     dv[j][1] += a * d - bq * c;
                     dv[j][2] += c * c + d * d;
@@ -1049,7 +1089,7 @@ static void launch_init_t(const BlkArgs &ba, const void *rhs, void *r, void *rh,
                           const int32_t *oa, hipStream_t st)
 {
     hipLaunchKernelGGL((k_bicg_init<SP, G>), dim3(ba.ntiles), dim3(kTile), 0, st, ba, (const SP *)rhs, (SP *)r,
-                       (SP *)rh, (SP *)p, (SP *)x, partial, oa);
+                       (typename ShadowT<SP>::T *)rh, (SP *)p, (SP *)x, partial, oa);
 }
 template <typename SP, int G>
 static void launch_s_t(const BlkArgs &ba, const void *r, const void *v, void *s, const PairState &ps, hipStream_t st)
@@ -1062,7 +1102,8 @@ static void launch_xr_t(const BlkArgs &ba, void *x, const void *p, const void *s
                         void *r, const void *rh, double *partial, const PairState &ps, hipStream_t st)
 {
     hipLaunchKernelGGL((k_bicg_xr<SP, G>), dim3(ba.ntiles), dim3(kTile), 0, st, ba, (SP *)x, (const SP *)p,
-                       (const SP *)sx, (const SP *)s, (const SP *)t, (SP *)r, (const SP *)rh, partial, ps);
+                       (const SP *)sx, (const SP *)s, (const SP *)t, (SP *)r,
+                       (const typename ShadowT<SP>::T *)rh, partial, ps);
 }
 template <typename SP, int G>
 static void launch_p_t(const BlkArgs &ba, const void *r, const void *v, void *p, const PairState &ps, hipStream_t st)
@@ -1163,8 +1204,8 @@ __global__ void __launch_bounds__(256) k_sc_init(BlkArgs ba, const double *parti
                                                  const int32_t *outer_active)
 {
     DD_PAIR_PROLOGUE(ps.np)
-    double s[1];
-    pair_sums<1>(ba, partial, b, r, lane, s);
+    double s[3];
+    pair_sums<3>(ba, partial, b, r, lane, s);
     if (lane != 0) return;
     if (!outer_active[pair]) {
         ps.active[pair] = 0;
@@ -1173,8 +1214,8 @@ __global__ void __launch_bounds__(256) k_sc_init(BlkArgs ba, const double *parti
     const double bb = s[0];
     ps.bb[pair] = bb;
     ps.rr[pair] = bb;
-    ps.rho[2 * pair] = bb;
-    ps.rho[2 * pair + 1] = 0;
+    ps.rho[2 * pair] = s[1];  // <rh, r_0>
+    ps.rho[2 * pair + 1] = s[2];
     ps.omega[2 * pair] = 1;
     ps.omega[2 * pair + 1] = 0;
     ps.beta[2 * pair] = 0;  // a direction update before the first iteration gives p = r

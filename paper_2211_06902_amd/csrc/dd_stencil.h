@@ -50,6 +50,11 @@ __device__ __forceinline__ double bload<double>(const Buf &b, uint32_t voff, uin
 {
     return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(b.r, (int)voff, (int)soff, 0));
 }
+template <>
+__device__ __forceinline__ uint16_t bload<uint16_t>(const Buf &b, uint32_t voff, uint32_t soff)
+{
+    return __builtin_amdgcn_raw_buffer_load_b16(b.r, (int)voff, (int)soff, 0);
+}
 template <typename T>
 __device__ __forceinline__ void bstore(const Buf &b, T v, uint32_t voff, uint32_t soff);
 template <>
