@@ -1,12 +1,13 @@
 // Persistent batched GMRES(m) for the even-odd reduced block systems
 // Dhat e = f, Dhat = 1 - kappa^2 H_eo H_oe, one system per (block, rhs) pair.
 //
-// One workgroup solves one pair at a time, entirely on chip: the two eo hops
-// of Dhat, classical Gram-Schmidt applied twice (CGS2) with FP64 dot
-// products and FP64 vector updates, the Hessenberg matrix, complex Givens
-// rotations, the residual estimate and the back substitution all stay inside
-// the workgroup, so a pair needs no kernel launch per Krylov step and no
-// host round trip.  A fixed grid of workgroups (as many as fit on the chip)
+// One workgroup solves one pair at a time, entirely on chip: Dhat (with FP32
+// spinors its two eo hops in one pass over the x0-slices, the intermediate in
+// LDS), classical Gram-Schmidt with FP64 dot products and FP64 vector updates
+// and a second pass when cancellation calls for it, the Hessenberg matrix,
+// complex Givens rotations, the residual estimate and the back substitution
+// all stay inside the workgroup, so a pair needs no kernel launch per Krylov
+// step and no host round trip.  A fixed grid of workgroups (as many as fit on the chip)
 // pulls pairs from work queues with a global atomic counter until the queues
 // are empty; blocks of uneven size are balanced by the queue order (largest
 // first), and with one queue per XCD a block's right-hand sides are solved by

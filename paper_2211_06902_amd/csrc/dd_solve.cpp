@@ -57,11 +57,13 @@ struct Inner {
     bool dhat;  // Dhat as one x0-walk kernel (run_dhat)
 };
 
-// one BiCGStab iteration on all pairs (10 launches; with a right
-// preconditioner M, Dhat is applied to M p and M s, x is updated with them).
-// With fuse_p the direction update p = r + beta (p - omega v) that ends an
-// iteration is done by the first hop of the next one (beta = 0 before the
-// first: p = r); with fuse_s the first hop of Dhat s forms s = r - alpha v.
+// one BiCGStab iteration on all pairs: 6 launches with the one-kernel Dhat
+// (dhat), 8 with two hop launches per Dhat, 10 with separate update kernels
+// as well; with a right preconditioner M, Dhat is applied to M p and M s and
+// x is updated with them.  With fuse_p the direction update
+// p = r + beta (p - omega v) that ends an iteration is done by the next
+// iteration's Dhat p as it stages p (beta = 0 before the first: p = r); with
+// fuse_s Dhat s forms s = r - alpha v as it stages s.
 hipError_t bicg_iteration(const Inner &in)
 {
     Ws &w = *in.w;
