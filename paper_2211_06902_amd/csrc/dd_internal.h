@@ -225,6 +225,7 @@ struct PairState {
     int32_t *active; // [np]  inner iteration still running
     int32_t *flags;  // [np]  bit 1 breakdown, bit 2 non-finite
     int32_t *iters;  // [np]  cumulative inner iterations
+    double *tol2;    // [np]  squared relative inner tolerance of the current inner solve
     int np;
 };
 
@@ -369,14 +370,16 @@ hipError_t launch_bicg_xr(const BlkArgs &ba, dd_prec sp, void *x, const void *p,
                           const PairState &ps, hipStream_t st);
 hipError_t launch_bicg_p(const BlkArgs &ba, dd_prec sp, const void *r, const void *v, void *p,
                          const PairState &ps, hipStream_t st);
+// Inner tolerance per pair: tol_in, or with adapt at least
+// 0.3 tol_out |b| / |r| (what is left to reach the outer tolerance from the
+// current true residual; at most 0.1).
 hipError_t launch_sc_init(const BlkArgs &ba, const double *partial, const PairState &ps,
-                          const int32_t *outer_active, hipStream_t s);
+                          const OuterState &os, double tol_in, double tol_out, int adapt, hipStream_t s);
 hipError_t launch_sc_alpha(const BlkArgs &ba, const double *partial, const PairState &ps,
                            hipStream_t s);
 hipError_t launch_sc_omega(const BlkArgs &ba, const double *partial, const PairState &ps,
                            hipStream_t s);
-hipError_t launch_sc_beta(const BlkArgs &ba, const double *partial, const PairState &ps,
-                          double tol, hipStream_t s);
+hipError_t launch_sc_beta(const BlkArgs &ba, const double *partial, const PairState &ps, hipStream_t s);
 hipError_t launch_sc_outer(const BlkArgs &ba, const double *pe, const double *po, int first,
                            double tol, const OuterState &os, hipStream_t s);
 hipError_t launch_mb_norm(const dd_blocks *B, int n_fields, const double *u, const double *chi,

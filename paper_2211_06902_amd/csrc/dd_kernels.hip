@@ -1200,17 +1200,20 @@ __device__ __forceinline__ bool finite(double v) { return isfinite(v); }
     if (pair >= (NP)) return;                                                  \
     const int b = pair % ba.nb, r = pair / ba.nb;
 
-__global__ void __launch_bounds__(256) k_sc_init(BlkArgs ba, const double *partial, PairState ps,
-                                                 const int32_t *outer_active)
+__global__ void __launch_bounds__(256) k_sc_init(BlkArgs ba, const double *partial, PairState ps, OuterState os,
+                                                 double tol_in, double tol_out, int adapt)
 {
     DD_PAIR_PROLOGUE(ps.np)
     double s[3];
     pair_sums<3>(ba, partial, b, r, lane, s);
     if (lane != 0) return;
-    if (!outer_active[pair]) {
+    if (!os.active[pair]) {
         ps.active[pair] = 0;
         return;
     }
+    double t = tol_in;
+    if (adapt && os.rr[pair] > 0) t = fmax(t, fmin(0.3 * tol_out * sqrt(os.bb[pair] / os.rr[pair]), 0.1));
+    ps.tol2[pair] = t * t;
     const double bb = s[0];
     ps.bb[pair] = bb;
     ps.rr[pair] = bb;
@@ -1262,7 +1265,7 @@ __global__ void __launch_bounds__(256) k_sc_omega(BlkArgs ba, const double *part
     ps.omega[2 * pair + 1] = wi;
 }
 
-__global__ void __launch_bounds__(256) k_sc_beta(BlkArgs ba, const double *partial, PairState ps, double tol2)
+__global__ void __launch_bounds__(256) k_sc_beta(BlkArgs ba, const double *partial, PairState ps)
 {
     DD_PAIR_PROLOGUE(ps.np)
     if (!ps.active[pair]) return;
@@ -1277,7 +1280,7 @@ __global__ void __launch_bounds__(256) k_sc_beta(BlkArgs ba, const double *parti
         ps.flags[pair] |= 4;
         return;
     }
-    if (rr <= tol2 * ps.bb[pair]) {
+    if (rr <= ps.tol2[pair] * ps.bb[pair]) {
         ps.active[pair] = 0;
         return;
     }
@@ -1329,10 +1332,10 @@ __global__ void __launch_bounds__(256) k_sc_outer(BlkArgs ba, const double *pe, 
 
 static inline dim3 pair_grid(int np) { return dim3((unsigned)((np + 3) / 4)); }
 
-hipError_t launch_sc_init(const BlkArgs &ba, const double *partial, const PairState &ps, const int32_t *outer_active,
-                          hipStream_t s)
+hipError_t launch_sc_init(const BlkArgs &ba, const double *partial, const PairState &ps, const OuterState &os,
+                          double tol_in, double tol_out, int adapt, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sc_init, pair_grid(ps.np), dim3(256), 0, s, ba, partial, ps, outer_active);
+    hipLaunchKernelGGL(k_sc_init, pair_grid(ps.np), dim3(256), 0, s, ba, partial, ps, os, tol_in, tol_out, adapt);
     return hipGetLastError();
 }
 hipError_t launch_sc_alpha(const BlkArgs &ba, const double *partial, const PairState &ps, hipStream_t s)
@@ -1345,9 +1348,9 @@ hipError_t launch_sc_omega(const BlkArgs &ba, const double *partial, const PairS
     hipLaunchKernelGGL(k_sc_omega, pair_grid(ps.np), dim3(256), 0, s, ba, partial, ps);
     return hipGetLastError();
 }
-hipError_t launch_sc_beta(const BlkArgs &ba, const double *partial, const PairState &ps, double tol, hipStream_t s)
+hipError_t launch_sc_beta(const BlkArgs &ba, const double *partial, const PairState &ps, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sc_beta, pair_grid(ps.np), dim3(256), 0, s, ba, partial, ps, tol * tol);
+    hipLaunchKernelGGL(k_sc_beta, pair_grid(ps.np), dim3(256), 0, s, ba, partial, ps);
     return hipGetLastError();
 }
 hipError_t launch_sc_outer(const BlkArgs &ba, const double *pe, const double *po, int first, double tol,

@@ -141,7 +141,7 @@ hipError_t bicg_iteration(const Inner &in)
     }
     if ((e = launch_sc_omega(in.ba, w.pB, w.ps, st)) != hipSuccess) return e;
     if ((e = launch_bicg_xr(in.ba, in.sp, w.xi, pp, ss, w.s, w.t, w.r, w.rh, w.pC, w.ps, st)) != hipSuccess) return e;
-    if ((e = launch_sc_beta(in.ba, w.pC, w.ps, in.tol, st)) != hipSuccess) return e;
+    if ((e = launch_sc_beta(in.ba, w.pC, w.ps, st)) != hipSuccess) return e;
     return in.fuse_p ? hipSuccess : launch_bicg_p(in.ba, in.sp, w.r, w.v, w.p, w.ps, st);
 }
 
@@ -258,6 +258,9 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
     if (!links) return fail(ctx, DD_EINVAL, "gauge holds no links of the inner precision");
     const dd_prec sp = ip == DD_F64 ? DD_F64 : DD_F32;
     const double inner_tol = prm.inner_tol > 0 ? prm.inner_tol : default_inner_tol(ip, prm.tol);
+    // with the default inner tolerance and a low-precision inner solve, a later
+    // cycle's BiCGStab stops once it has gained what is left to reach tol
+    const bool adapt_tol = prm.inner_tol <= 0 && ip != DD_F64;
     const int max_outer = prm.max_outer > 0 ? prm.max_outer : 30;
     const int max_inner = prm.max_inner > 0 ? prm.max_inner : 2000;
     const int check = prm.check_every > 0 ? prm.check_every : 2;
@@ -344,7 +347,7 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
     w.pC = (double *)get("s_pC", npart);
     w.pe = (double *)get("s_pe", npart);
     w.po = (double *)get("s_po", npart);
-    double *pd = (double *)get("s_pair_d", (size_t)np * 12 * sizeof(double));
+    double *pd = (double *)get("s_pair_d", (size_t)np * 13 * sizeof(double));
     int32_t *pi = (int32_t *)get("s_pair_i", (size_t)np * 5 * sizeof(int32_t));
     if (e != hipSuccess) return fail(ctx, DD_ENOMEM, std::string("solver workspace: ") + hipGetErrorString(e));
     w.ps.rho = pd;
@@ -355,6 +358,7 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
     w.ps.rr = pd + 9 * np;
     w.os.bb = pd + 10 * np;
     w.os.rr = pd + 11 * np;
+    w.ps.tol2 = pd + 12 * np;
     w.ps.active = pi;
     w.ps.flags = pi + np;
     w.ps.iters = pi + 2 * np;
@@ -364,7 +368,7 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
 
     hipStream_t st = ctx->stream;
     HIPCHECK(ctx, hipMemsetAsync(pi, 0, (size_t)np * 5 * sizeof(int32_t), st));
-    HIPCHECK(ctx, hipMemsetAsync(pd, 0, (size_t)np * 12 * sizeof(double), st));
+    HIPCHECK(ctx, hipMemsetAsync(pd, 0, (size_t)np * 13 * sizeof(double), st));
     if (gm_bytes) HIPCHECK(ctx, hipMemsetAsync(gm_bytes, 0, (size_t)np * sizeof(double), st));
     HIPCHECK(ctx, hipMemsetAsync(w.xe, 0, h64, st));
     HIPCHECK(ctx, hipMemsetAsync(w.xo, 0, h64, st));
@@ -510,7 +514,7 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
             }
         } else {
         HIPCHECK(ctx, launch_bicg_init(ba, sp, w.rhs, w.r, w.rh, in.fuse_p ? nullptr : w.p, w.xi, w.pA, w.os.active, st));
-        HIPCHECK(ctx, launch_sc_init(ba, w.pA, w.ps, w.os.active, st));
+        HIPCHECK(ctx, launch_sc_init(ba, w.pA, w.ps, w.os, in.tol, prm.tol, adapt_tol ? 1 : 0, st));
         // the network's workspaces and BF16 weights exist before any capture
         if (in.nn && !gx) HIPCHECK(ctx, nn_apply_half(ctx, in.nn, B, w.p, in.ph, n_rhs, sp));
         if (graph && !gx) {
