@@ -170,8 +170,9 @@ const void *links_for(const dd_gauge *G, dd_prec prec)
 }
 
 // Algorithmic bytes of one hop launch: the half field it reads and the one it
-// writes (24 reals per site and rhs each), each extra half-field operand, and
-// every link inside the blocks once (18 reals).
+// writes (24 reals per site and rhs each), each extra half-field operand (in
+// units of such a field), and every link inside the blocks once (the two
+// stored rows, 12 reals).
 double hop_bytes(const dd_blocks *B, int nr, dd_prec prec, double extra_vectors)
 {
     const double sf = prec == DD_F64 ? 8.0 : 4.0;
