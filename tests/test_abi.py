@@ -148,3 +148,29 @@ def test_mb_roots_match_the_oracle():
     for N, c in [(7, 0.5), (8, 1.0), (8, 0.0)]:
         with pytest.raises(dd.DDError):
             dd.mb_roots(N, c)
+
+
+def test_binding_constants_match_the_header():
+    """Every DD_TUNE_* and DD_KCLASS_* value of include/dd.h has the same value in the binding."""
+    from paper_2211_06902_amd import dd
+
+    txt = open(os.path.join(ROOT, "include", "dd.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    found = re.findall(r"\bDD_((?:TUNE|KCLASS)_[A-Z0-9_]+)\s*=\s*(\d+)", txt)
+    assert len(found) >= 15
+    for name, val in found:
+        if name == "KCLASS_COUNT":
+            continue
+        assert getattr(dd, name) == int(val), name
+
+
+def test_solve_params_defaults():
+    """The header's documented defaults: tolerance 1e-10, library inner tolerance, polls every 2
+    BiCGStab iterations (host-only call, no device needed)."""
+    from paper_2211_06902_amd import dd
+
+    p = dd.solve_params()
+    assert p.tol == 1e-10
+    assert p.inner_tol <= 0
+    assert p.check_every == 2
+    assert p.restart == 16
