@@ -177,8 +177,8 @@ typedef struct {
     double inner_tol;    /* relative tolerance of each inner solve (<= 0: library default:
                             FP64 max(0.1 tol, 1e-14); FP32 max(0.3 sqrt(tol), 1e-6), two
                             defect-correction cycles; BF16 links 2e-3; with FP32 or BF16
-                            BiCGStab, per pair and cycle at least 0.3 tol |b| / |r| (what is
-                            left to reach tol from the true residual r), at most 0.1) */
+                            inner solves, per pair and cycle at least 0.3 tol |b| / |r| (what
+                            is left to reach tol from the true residual r), at most 0.1) */
     int32_t max_outer;   /* defect-correction cycles (<= 0: default 30) */
     int32_t max_inner;   /* iterations per inner solve (<= 0: default 2000) */
     int32_t check_every; /* BiCGStab: inner iterations between convergence polls (<= 0: default 2;

@@ -422,6 +422,9 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
         }
         double beta = sqrt(wg_sum1<NT>(nn, red));
         const double beta0 = a.resume ? a.beta0[pair] : beta;
+        double tolp = a.tol;
+        if (a.adapt && a.orr[pair] > 0)
+            tolp = fmax(tolp, fmin(0.3 * a.tol_out * sqrt(a.obb[pair] / a.orr[pair]), 0.1));
         const bool ok0 = isfinite(beta) && beta > 0;
         const double inv0 = ok0 ? 1.0 / beta : 0.0;
         for (int e = threadIdx.x; e < n; e += NT) {
@@ -432,7 +435,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
         if (threadIdx.x == 0 && !a.resume && a.beta0) a.beta0[pair] = beta0;
         __syncthreads();
         int it = 0, stop = ok0 ? kGoOn : (beta == 0 ? kConverged : kNonFinite);
-        if (ok0 && beta <= a.tol * beta0) stop = kConverged;
+        if (ok0 && beta <= tolp * beta0) stop = kConverged;
         double est = ok0 ? beta : 0.0;
         int cycles = 0;
         while (stop == kGoOn || stop == kRestart) {
@@ -535,7 +538,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
                     const double e2 = sqrt(gv[2 * j + 2] * gv[2 * j + 2] + gv[2 * j + 3] * gv[2 * j + 3]);
                     int st = kGoOn;
                     if (!isfinite(e2) || !isfinite(hn) || !isfinite(pd[0]) || !isfinite(pd[1])) st = kNonFinite;
-                    else if (e2 <= a.tol * beta0 || !(hn > 0.0)) st = kConverged;
+                    else if (e2 <= tolp * beta0 || !(hn > 0.0)) st = kConverged;
                     else if (it + 1 >= a.max_iter) st = kMaxIter;
                     else if (j + 1 == m) st = kRestart;
                     s_stop = st;
@@ -613,7 +616,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
                 stop = kNonFinite;
                 break;
             }
-            if (beta <= a.tol * beta0) {
+            if (beta <= tolp * beta0) {
                 stop = kConverged;
                 break;
             }

@@ -273,6 +273,11 @@ struct GmArgs {
     const int32_t *ext;       // [nb][4] block extents
     int walk;                 // 1: the hops walk the x0-slices (every block admits it)
     double reorth2;           // second Gram-Schmidt pass when |w - V h|^2 <= reorth2 |w|^2
+    // with adapt, a pair's tolerance is at least 0.3 tol_out |b| / |r| from the
+    // outer state (|b|^2 in obb, the current |r|^2 in orr; at most 0.1)
+    int adapt;
+    double tol_out;
+    const double *obb, *orr;
 };
 
 // basis vectors the kernel for restart length m keeps per workgroup (its

@@ -453,6 +453,10 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
             ga.vstr = vstr;
             ga.k2 = kappa * kappa;
             ga.tol = inner_tol;
+            ga.adapt = adapt_tol ? 1 : 0;
+            ga.tol_out = prm.tol;
+            ga.obb = w.os.bb;
+            ga.orr = w.os.rr;
             ga.m = prm.restart;
             ga.max_iter = max_inner;
             ga.nlinks = B->d_nlinks;
