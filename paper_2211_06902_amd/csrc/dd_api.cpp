@@ -253,7 +253,16 @@ hipError_t run_dhat(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const Ho
     // update's r, v (and p) reads and its write of the updated input
     const double extra = (ha.self != nullptr && ha.self != ha.in) + (ha.add != nullptr) + aux_vectors(ha, prec) +
                          (ha.pre == kPreP ? 3 : (ha.pre == kPreS ? 2 : 0));
-    TimedLaunch tl(ctx, prec == DD_F32 ? DD_KCLASS_DHAT_F32 : DD_KCLASS_DHAT_BF16, hop_bytes(B, ba.n_rhs, prec, extra));
+    const int kc = prec == DD_F32 ? DD_KCLASS_DHAT_F32 : DD_KCLASS_DHAT_BF16;
+    const double bytes = hop_bytes(B, ba.n_rhs, prec, extra);
+    // with timing on the kernel counts the bytes of the walks it does (pairs
+    // that stopped are skipped): the launch's bytes per eo site and rhs
+    const bool dev_count = ctx->timing && ctx->d_timer_bytes;
+    if (dev_count) {
+        ha.bytes_acc = ctx->d_timer_bytes + kc;
+        ha.bytes_site = bytes / ((double)ba.n_rhs * (double)(B->soff[B->nb] / 2));
+    }
+    TimedLaunch tl(ctx, kc, dev_count ? 0.0 : bytes);
     hipError_t err;
     int nseg = 1;
     const TileTable *wt = walk_for(B, ba.n_rhs, 1, 1, &nseg, &err);
@@ -715,6 +724,14 @@ dd_status dd_tune_set(dd_ctx *ctx, int32_t what, int32_t value)
 dd_status dd_timer_enable(dd_ctx *ctx, int32_t on)
 {
     if (!ctx) return DD_EINVAL;
+    if (on && !ctx->d_timer_bytes) {
+        hipError_t e;
+        const size_t nb = DD_KCLASS_COUNT * sizeof(double);
+        double *p = (double *)workspace(ctx, "timer_bytes", nb, &e);
+        if (!p) return fail(ctx, DD_ENOMEM, std::string("timer counters: ") + hipGetErrorString(e));
+        HIPCHECK(ctx, hipMemsetAsync(p, 0, nb, ctx->stream));
+        ctx->d_timer_bytes = p;
+    }
     ctx->timing = on != 0;
     return DD_OK;
 }
@@ -722,6 +739,7 @@ dd_status dd_timer_enable(dd_ctx *ctx, int32_t on)
 dd_status dd_timer_reset(dd_ctx *ctx)
 {
     if (!ctx) return DD_EINVAL;
+    if (ctx->d_timer_bytes) hipMemsetAsync(ctx->d_timer_bytes, 0, DD_KCLASS_COUNT * sizeof(double), ctx->stream);
     hipStreamSynchronize(ctx->stream);
     for (auto &t : ctx->timers) {
         t.used = 0;
@@ -742,8 +760,11 @@ dd_status dd_timer_read(dd_ctx *ctx, int32_t kclass, double *total_ms, int64_t *
         tot += ms;
     }
     if (total_ms) *total_ms = tot;
+    double dev = 0;
+    if (ctx->d_timer_bytes)
+        HIPCHECK(ctx, hipMemcpy(&dev, ctx->d_timer_bytes + kclass, sizeof(double), hipMemcpyDeviceToHost));
     if (launches) *launches = (int64_t)t.used;
-    if (alg_bytes) *alg_bytes = t.bytes;
+    if (alg_bytes) *alg_bytes = t.bytes + dev;
     return DD_OK;
 }
 

@@ -51,6 +51,7 @@ struct dd_ctx {
     std::map<std::string, dd::DevBuf> ws;  // named, grow-only workspaces
     bool timing = false;
     dd::Timer timers[DD_KCLASS_COUNT];
+    double *d_timer_bytes = nullptr;  // [DD_KCLASS_COUNT] bytes counted by kernels (timing on)
     int rhs_group[2] = {0, 0};  // forced rhs per thread for FP64 / FP32 spinors (0 = automatic)
     bool hop_lds = true;        // stage the hop's chunk of the input in LDS
     int hop_walk = 0;           // x0-walk of the hop: 0 automatic, -1 off, n >= 1 segments per block
@@ -204,6 +205,12 @@ struct HopArgs {
     const void *pre_r, *pre_v;
     const double *pre_c0, *pre_c1;  // complex per pair: kPreP beta, omega; kPreS alpha
     const int32_t *pre_act;         // per pair: 0 keeps `in` as it is
+    // one-kernel Dhat only: pairs whose flag is 0 are skipped (nothing of
+    // theirs is read again before they restart); with timing, each walk done
+    // adds hb * bytes_site algorithmic bytes to *bytes_acc
+    const int32_t *skip_act;
+    double *bytes_acc;
+    double bytes_site;
 };
 
 // Vector updates of BiCGStab done by the first hop of Dhat as it stages its

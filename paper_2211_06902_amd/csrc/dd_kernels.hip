@@ -503,6 +503,9 @@ __global__ void __launch_bounds__(kTile) k_dhat_walk(BlkArgs ba, WalkArgs wa, Ho
     const int nr = ba.n_rhs;
     const int r = tile - uni(wa.blk_tile0[b]);
     const int hb = uni(ba.h[b]);
+    // a pair that stopped iterating: the whole workgroup leaves
+    if (ha.skip_act && !ha.skip_act[r * ba.nb + b]) return;
+    if (ha.bytes_acc && threadIdx.x == 0) atomicAdd(ha.bytes_acc, ha.bytes_site * hb);
     const int ns = uni(wa.ext[4 * b]);
     const int hs = hb / ns;
     const int k = threadIdx.x;

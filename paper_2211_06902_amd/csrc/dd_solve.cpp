@@ -100,6 +100,7 @@ hipError_t bicg_iteration(const Inner &in)
         d.pre_c0 = h1.pre_c0;
         d.pre_c1 = h1.pre_c1;
         d.pre_act = h1.pre_act;
+        d.skip_act = w.ps.active;
         if ((e = run_dhat(in.ctx, in.B, in.ba, d, in.ip)) != hipSuccess) return e;
     } else {
         if ((e = run_hop(in.ctx, in.B, in.ba, h1, in.ip)) != hipSuccess) return e;
@@ -134,6 +135,7 @@ hipError_t bicg_iteration(const Inner &in)
         d.pre_v = h3.pre_v;
         d.pre_c0 = h3.pre_c0;
         d.pre_act = h3.pre_act;
+        d.skip_act = w.ps.active;
         if ((e = run_dhat(in.ctx, in.B, in.ba, d, in.ip)) != hipSuccess) return e;
     } else {
         if ((e = run_hop(in.ctx, in.B, in.ba, h3, in.ip)) != hipSuccess) return e;
