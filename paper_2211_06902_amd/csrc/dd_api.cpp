@@ -212,8 +212,18 @@ hipError_t run_hop(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const Hop
     // it); the staging updates read r, v (and p) and write the updated input
     const double extra = (ha.self != nullptr) + (ha.add != nullptr) + aux_vectors(ha, prec) +
                          (ha.pre == kPreP ? 3 : (ha.pre == kPreS ? 2 : 0));
-    TimedLaunch tl(ctx, DD_KCLASS_HOP_F64 + (int)prec, hop_bytes(B, ba.n_rhs, prec, extra));
-    if (walk_applies(ctx, B, ba, prec)) {
+    const double bytes = hop_bytes(B, ba.n_rhs, prec, extra);
+    const bool walk = walk_applies(ctx, B, ba, prec);
+    // the x0-walk skips rhs groups whose pairs all stopped (skip_act); with
+    // timing on it then counts the bytes of the tiles it does, as run_dhat
+    if (!walk) ha.skip_act = nullptr;
+    const bool dev_count = walk && ha.skip_act && ctx->timing && ctx->d_timer_bytes;
+    if (dev_count) {
+        ha.bytes_acc = ctx->d_timer_bytes + DD_KCLASS_HOP_F64 + (int)prec;
+        ha.bytes_site = bytes / ((double)ba.n_rhs * (double)(B->soff[B->nb] / 2));
+    }
+    TimedLaunch tl(ctx, DD_KCLASS_HOP_F64 + (int)prec, dev_count ? 0.0 : bytes);
+    if (walk) {
         hipError_t err;
         int nseg = 1;
         const TileTable *wt = walk_for(B, ba.n_rhs, ba.g, walk_segments(ctx, B, ba.n_rhs / ba.g), &nseg, &err);

@@ -205,9 +205,10 @@ struct HopArgs {
     const void *pre_r, *pre_v;
     const double *pre_c0, *pre_c1;  // complex per pair: kPreP beta, omega; kPreS alpha
     const int32_t *pre_act;         // per pair: 0 keeps `in` as it is
-    // one-kernel Dhat only: pairs whose flag is 0 are skipped (nothing of
-    // theirs is read again before they restart); with timing, each walk done
-    // adds hb * bytes_site algorithmic bytes to *bytes_acc
+    // x0-walk kernels only (the hop walk skips a rhs group when all its pairs
+    // have stopped): pairs whose flag is 0 are skipped (nothing of theirs is
+    // read again before they restart); with timing, each walk done adds
+    // bytes_site algorithmic bytes per eo site and rhs it covers to *bytes_acc
     const int32_t *skip_act;
     double *bytes_acc;
     double bytes_site;

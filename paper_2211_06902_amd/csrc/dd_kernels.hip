@@ -370,6 +370,14 @@ k_hop_walk(BlkArgs ba, WalkArgs wa, HopArgs ha)
     w.k = threadIdx.x;
     w.s0 = seg * ns / wa.nseg;
     w.s1 = (seg + 1) * ns / wa.nseg;
+    if (ha.skip_act) {
+        // every pair of the tile's rhs group stopped iterating: the workgroup leaves
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < G; j++) any = any || ha.skip_act[(grp * G + j) * ba.nb + b] != 0;
+        if (!any) return;
+    }
+    if (ha.bytes_acc && threadIdx.x == 0) atomicAdd(ha.bytes_acc, ha.bytes_site * (w.s1 - w.s0) * w.hs * G);
     const int64_t soff = uni64(ba.soff[b]);
     const int64_t hbase = (soff >> 1) * 24 * nr;
     const uint32_t fbytes = (uint32_t)(nr * 24 * w.hb) * (uint32_t)sizeof(SP);

@@ -103,6 +103,7 @@ hipError_t bicg_iteration(const Inner &in)
         d.skip_act = w.ps.active;
         if ((e = run_dhat(in.ctx, in.B, in.ba, d, in.ip)) != hipSuccess) return e;
     } else {
+        h1.skip_act = h2.skip_act = w.ps.active;
         if ((e = run_hop(in.ctx, in.B, in.ba, h1, in.ip)) != hipSuccess) return e;
         if ((e = run_hop(in.ctx, in.B, in.ba, h2, in.ip)) != hipSuccess) return e;
     }
@@ -138,6 +139,7 @@ hipError_t bicg_iteration(const Inner &in)
         d.skip_act = w.ps.active;
         if ((e = run_dhat(in.ctx, in.B, in.ba, d, in.ip)) != hipSuccess) return e;
     } else {
+        h3.skip_act = h4.skip_act = w.ps.active;
         if ((e = run_hop(in.ctx, in.B, in.ba, h3, in.ip)) != hipSuccess) return e;
         if ((e = run_hop(in.ctx, in.B, in.ba, h4, in.ip)) != hipSuccess) return e;
     }
