@@ -10,9 +10,8 @@
 //          e_o = r_o + kappa H_oe e_e and x += e.
 // Inner methods:
 //   BiCGStab: every launch covers all blocks and right-hand sides; per-pair
-//          scalars live on the device and pairs that converge are frozen.  Hop
-//          launches always cover every pair so that their cost per launch is
-//          fixed.
+//          scalars live on the device and pairs that converge are frozen (the
+//          x0-walk operator kernels and the vector updates skip them).
 //   GMRES(m): one persistent launch per defect-correction cycle; each
 //          workgroup solves whole pairs taken from work queues.
 #include <hip/hip_runtime.h>
