@@ -1,26 +1,29 @@
 """Benchmark: batched block solves D_Lambda^{-1} b on one MI355X.
 
-Default workload (c2): 32^4 lattice (antiperiodic time), SU(3) links
-exp(i 0.3 H) from seed 2101, kappa = 0.1355, 256 blocks of 8^4 (Dirichlet),
-12 Gaussian sources per block from seed 2102, i.e. 3072 independent block
-solves per step.  Method: FP32 even-odd BiCGStab inner solves inside FP64
-defect correction, every pair to an FP64 true relative residual <= 1e-10.
+Default workload (c5): the block-local multi-boson action of eq. (localMB) on
+a 64^4 lattice (antiperiodic time, SU(3) links exp(0.2 i H) drawn on the GPU
+from seed 5101, kappa = 0.1365): 4096 blocks Omega of 8^4 with inner
+Lambda_0 of 6^4, 12 boson fields (N = 24, c = 0.5), chi and xi Gaussian
+(seeds 5102, 5103).  One step = one dd_multiboson_action call: 49 152
+independent block solves D_Omega^{-1} xi_k to a per-pair FP64 true relative
+residual <= 1e-10, then the boundary norms.  Headline form: FP32 even-odd
+BiCGStab inner solves inside FP64 defect correction; plain FP64 solves and
+FP32 solves right-preconditioned by a network trained on this lattice are
+timed beside it.
 
---workload c3: 48^3 x 96 lattice, kappa 0.1355, links exp(i 0.3 H) from seed
-3101, 2160 uneven blocks (1296 of 8^4 and 864 of 8^3 x 12), 12 sources per
-block (25 920 solves per step) drawn on the GPU from seed 3102; persistent
-GMRES(16) inner solves with BF16 links and FP32 spinors (schedule chosen by
-the autotuner before timing) inside FP64 defect correction.
+--workload c2: 32^4 lattice, 256 blocks of 8^4, 12 sources per block (3072
+solves per step), FP32 BiCGStab inside FP64 defect correction.
+--workload c3: 48^3 x 96 lattice, 2160 uneven blocks (1296 of 8^4 and 864 of
+8^3 x 12), 12 sources per block, persistent autotuned GMRES(16) with BF16
+links.  --workload c4: the learned preconditioner's training and gain test.
 
-A step is one dd_block_solve call over the whole batch: the sources are
-already on the GPU; the step packs them into the library layout, solves all
-pairs and unpacks the solutions.  Links are packed once before timing.
+The timed steps run the library's default path (inner iterations replayed
+from captured hipGraphs, no kernel timers); one extra step with the kernel
+timers on (HIP events around every launch on the library's stream) gives the
+dominant kernel's algorithmic bandwidth for the roofline object.  Inputs are
+resident in HBM before timing; links are packed once before timing.
 
-Printed (one JSON line): solves/s, the dominant kernel's achieved
-algorithmic bandwidth against the 8 TB/s HBM peak measured with HIP events
-inside the timed steps, and the CPU oracle timed on a bounded sample.
-
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--workload c2|c3]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-nn] [--workload c5|c2|c3|c4]
 """
 from __future__ import annotations
 
@@ -104,7 +107,7 @@ def cpu_baseline(w, U, b, boxes):
     t0 = time.perf_counter()
     _, iters, rel, fails = wilson.solve_many(w["L"], -1, w["kappa"], U, sel_boxes, bh, tol=TOL, nthreads=nthr)
     dt = time.perf_counter() - t0
-    return {"value": npairs / dt, "unit": "solves/s", "cores": nthr, "kind": "oracle",
+    return {"value": npairs / dt, "unit": "solves/s", "cores": nthr, "cpu_model": cpu_model(), "kind": "oracle",
             "sample": "%d (block, rhs) pairs of the same workload (8 per thread), FP64 eo-BiCGStab with FP64 "
                       "defect correction to 1e-10 (%.1f s wall, %d failed)" % (npairs, dt, fails)}
 
@@ -278,125 +281,221 @@ def run_c4(args):
     ctx.close()
 
 
-def run_c5(args):
-    """The multi-boson action on the 64^4 lattice: 4096 blocks of 8^4 (Omega, inner Lambda_0 of
-    6^4), 12 boson fields (N = 24, c = 0.5), one D_Omega^{-1} xi_k solve per field and block,
-    evaluated with plain FP64 solves, mixed-precision (FP32 inner) solves, and mixed-precision
-    solves right-preconditioned by a network trained on this lattice's blocks."""
+C5 = dict(L=(64, 64, 64, 64), kappa=0.1365, eps=0.2, nf=12, N=24, c=0.5, seed_u=5101, seed_chi=5102, seed_xi=5103,
+          seed_nn=5104)
+
+
+def _mb_inputs(ctx, dd):
+    """The 64^4 lattice's blocks, packed links and multi-boson fields, all drawn on the GPU; the
+    canonical links are kept on the host for the oracle's sample."""
+    import synth
+
+    w = C5
+    V = 64**4
+    blk = ctx.make_blocks(w["L"], -1, [[8] * 8] * 4, inner_d=1)
+    U = synth.gauge_field_device(w["L"], w["eps"], w["seed_u"])
+    g = ctx.load_gauge(blk, U, "f32")
+    U_host = U.cpu().numpy()
+    del U
+    chi = synth.spinor_field_device(w["nf"], blk.total_bnd_sites, w["seed_chi"])
+    xi = synth.spinor_field_device(w["nf"], V, w["seed_xi"])
+    u = dd.mb_roots(w["N"], w["c"])
+    return blk, g, U_host, chi, xi, u
+
+
+def _mb_train_net(ctx, dd, blk, g, epochs):
+    """A network for this lattice: FP32 training on (even source, block solution) pairs of its blocks
+    made by the block solver (4 sources per block, 16 384 pairs)."""
     import torch
 
     import synth
+
+    w = C5
+    n_tr = 4
+    odd = torch.from_numpy(np.indices((8, 8, 8, 8)).sum(axis=0).reshape(-1) % 2 == 1).cuda()
+    src = synth.spinor_field_device(n_tr, 64**4, w["seed_nn"])
+    src.view(n_tr, 4096, 4096, 4, 3)[:, :, odd] = 0
+    sol = torch.empty_like(src)
+    _, _, st = ctx.block_solve(blk, g, w["kappa"], src, sol, params=dd.solve_params(inner_prec="f32"))
+    if st != dd.DD_OK:
+        raise SystemExit("training-pair solve did not converge")
+    net = ctx.nn_create((8, 8, 8, 8), synth.convnet_weights(w["seed_nn"]))
+    tl = []
+    for ep in range(epochs):
+        a, _ = net.train(blk, src, sol, n_tr,
+                         params=dd.nn_train_params(epochs=1, batch=32, lr=1e-3, seed=w["seed_nn"] + ep))
+        tl.append(float(a[0]))
+    del src, sol
+    torch.cuda.empty_cache()
+    return net, tl
+
+
+def mb_cpu_baseline(U_host, xi):
+    """The oracle's FP64 block solve (OpenMP over pairs) on a bounded sample of the 64^4 workload's
+    (block, field) pairs: the same xi sources, FP64 eo-BiCGStab with FP64 defect correction to 1e-10."""
+    from oracle import wilson
+
+    nthr = wilson.num_threads()
+    w = C5
+    npairs = 8 * nthr  # about 10-30 s of CPU work
+    nb, S = 4096, 4096
+    pick = [((k * 977) % nb, k % w["nf"]) for k in range(npairs)]
+    boxes = []
+    for blk, _ in pick:
+        t = [(blk >> (3 * (3 - m))) & 7 for m in range(4)]  # tile coordinates, direction 3 fastest
+        boxes.append([8 * v for v in t] + [8, 8, 8, 8])
+    bh = np.concatenate([xi[f, blk * S:(blk + 1) * S].cpu().numpy() for blk, f in pick])[None]
+    t0 = time.perf_counter()
+    _, iters, rel, fails = wilson.solve_many(w["L"], -1, w["kappa"], U_host, np.asarray(boxes), bh, tol=TOL,
+                                             nthreads=nthr)
+    dt = time.perf_counter() - t0
+    return {"value": npairs / dt, "unit": "solves/s", "cores": nthr, "cpu_model": cpu_model(), "kind": "oracle",
+            "sample": "%d (block, field) pairs of the 64^4 multi-boson workload (8 per thread; xi sources of "
+                      "%d blocks), FP64 eo-BiCGStab with FP64 defect correction to 1e-10 (%.1f s wall, "
+                      "%d failed)" % (npairs, len(set(b for b, _ in pick)), dt, fails)}
+
+
+def run_c5(args):
+    """The default workload: the block-local multi-boson action of the 64^4 lattice, 4096 blocks
+    Omega of 8^4 (inner Lambda_0 of 6^4), 12 boson fields (N = 24, c = 0.5), one D_Omega^{-1} xi_k
+    solve per field and block (49 152 solves per evaluation).  The headline is the fastest form
+    that brings every pair to 1e-10 (FP32 inner BiCGStab, FP64 defect correction); plain FP64
+    solves and FP32 solves right-preconditioned by a network trained on this lattice are
+    measured beside it."""
+    import torch
+
     from paper_2211_06902_amd import dd
 
-    L, kappa, eps, nf = (64, 64, 64, 64), 0.1365, 0.2, 12
-    V = 64**4
+    w = C5
     say = lambda m: print("c5: " + m, file=sys.stderr, flush=True)  # noqa: E731
     t0 = time.perf_counter()
     ctx = dd.Context(0)
-    blk = ctx.make_blocks(L, -1, [[8] * 8] * 4, inner_d=1)
-    U = torch.from_numpy(synth.gauge_field(L, eps, 5101)).cuda()
-    g = ctx.load_gauge(blk, U, "f32")
-    del U
-    torch.cuda.empty_cache()
-    chi = synth.spinor_field_device(nf, blk.total_bnd_sites, 5102)
-    xi = synth.spinor_field_device(nf, V, 5103)
-    u = dd.mb_roots(2 * nf, 0.5)
-    say("inputs ready (%.1f s)" % (time.perf_counter() - t0))
+    blk, g, U_host, chi, xi, u = _mb_inputs(ctx, dd)
+    t_gen = time.perf_counter() - t0
+    say("inputs ready (%.1f s)" % t_gen)
+    n_solves = blk.n_blocks * w["nf"]
+    inner = args.inner or "f32"
 
-    # network for this lattice: (even source, solution) pairs of its blocks, FP32 training
-    t0 = time.perf_counter()
-    n_tr = 4
-    odd = torch.from_numpy(np.indices((8, 8, 8, 8)).sum(axis=0).reshape(-1) % 2 == 1).cuda()
-    src = synth.spinor_field_device(n_tr, V, 5104)
-    src.view(n_tr, 4096, 4096, 4, 3)[:, :, odd] = 0
-    sol = torch.empty_like(src)
-    _, _, st = ctx.block_solve(blk, g, kappa, src, sol, params=dd.solve_params(inner_prec="f32"))
-    if st != dd.DD_OK:
-        raise SystemExit("training-pair solve did not converge")
-    net = ctx.nn_create((8, 8, 8, 8), synth.convnet_weights(5104))
-    tl = []
-    for ep in range(args.epochs):
-        a, _ = net.train(blk, src, sol, n_tr, params=dd.nn_train_params(epochs=1, batch=32, lr=1e-3, seed=5104 + ep))
-        tl.append(float(a[0]))
-        say("epoch %d train loss %.5f" % (ep, a[0]))
-    del src, sol
-    torch.cuda.empty_cache()
-    t_train = time.perf_counter() - t0
-
-    runs = {
-        "fp64": dd.solve_params(inner_prec="f64"),
-        "fp32": dd.solve_params(inner_prec="f32"),
-        "fp32_nn": dd.solve_params(inner_prec="f32", precond=net),
-    }
-    res = {}
-    hop = None
-    for name, prm in runs.items():
-        ctx.multiboson_action(blk, g, kappa, u, chi, xi, params=prm)  # warm-up (workspaces)
-        ctx.timer_enable(True)
-        ctx.timer_reset()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        S, tot, info, st = ctx.multiboson_action(blk, g, kappa, u, chi, xi, params=prm)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        if name == "fp32":
-            hop = stencil_timer(ctx, "f32")
-        ctx.timer_enable(False)
+    def evaluate(prm):
+        S, tot, info, st = ctx.multiboson_action(blk, g, w["kappa"], u, chi, xi, params=prm)
         ok = st == dd.DD_OK and bool(np.all(info["true_relres"] <= TOL))
-        res[name] = {"solves_per_s": blk.n_blocks * nf / dt if ok else 0.0, "seconds": dt, "all_converged": ok,
-                     "S_total": tot, "mean_inner_iterations_per_pair": float(info["iters"].mean())}
-        say("%s %s" % (name, res[name]))
-    ref = res["fp64"]["S_total"]
-    for r in res.values():
-        r["S_rel_diff_vs_fp64"] = abs(r["S_total"] - ref) / abs(ref)
-    hop_kname, (hop_ms, hop_n, hop_bytes) = hop
-    achieved = hop_bytes / (hop_ms * 1e-3) / 1e9 if hop_ms > 0 else 0.0
-    best = res["fp32_nn"]
+        return tot, info, ok
+
+    def timed(prm, steps, warmup):
+        """Wall time of `steps` evaluations after `warmup` untimed ones, with the library's default
+        path (inner iterations replayed from a captured graph, no kernel timers)."""
+        for _ in range(warmup):
+            evaluate(prm)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        res = [evaluate(prm) for _ in range(steps)]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        return dt, res
+
+    head = dd.solve_params(inner_prec=inner, use_graph=0 if args.no_graph else 1)
+    dt, res = timed(head, args.steps, args.warmup)
+    ok = all(r[2] for r in res)
+    S_head = res[-1][0]
+    say("%s: %.3f s per evaluation, all converged %s" % (inner, dt / args.steps, ok))
+
+    # one more evaluation with the kernel timers on (events around every launch, graph replay off):
+    # the stencil kernel's time and algorithmic bytes for the roofline
+    ctx.timer_enable(True)
+    ctx.timer_reset()
+    evaluate(head)
+    kname, (k_ms, k_n, k_bytes) = stencil_timer(ctx, inner)
+    ctx.timer_enable(False)
+    achieved = k_bytes / (k_ms * 1e-3) / 1e9 if k_ms > 0 else 0.0
+
+    forms = {}
+    side = max(1, min(args.steps, 2))
+    if inner != "f64" and not args.only_head:
+        dt64, r64 = timed(dd.solve_params(inner_prec="f64"), side, 1)
+        forms["fp64"] = {"solves_per_s": n_solves * side / dt64 if all(r[2] for r in r64) else 0.0,
+                         "s_per_evaluation": dt64 / side, "all_converged": all(r[2] for r in r64),
+                         "S_rel_diff_vs_headline": abs(r64[-1][0] - S_head) / abs(S_head)}
+        say("fp64 %s" % forms["fp64"])
+    if not args.no_nn and not args.only_head:
+        t1 = time.perf_counter()
+        net, tl = _mb_train_net(ctx, dd, blk, g, args.epochs)
+        t_train = time.perf_counter() - t1
+        dtn, rn = timed(dd.solve_params(inner_prec="f32", precond=net), side, 1)
+        forms["fp32_nn"] = {"solves_per_s": n_solves * side / dtn if all(r[2] for r in rn) else 0.0,
+                            "s_per_evaluation": dtn / side, "all_converged": all(r[2] for r in rn),
+                            "S_rel_diff_vs_headline": abs(rn[-1][0] - S_head) / abs(S_head),
+                            "training_s": t_train, "train_loss": [round(v, 5) for v in tl],
+                            "mean_inner_iterations_per_pair": float(rn[-1][1]["iters"].mean())}
+        say("fp32_nn %s" % forms["fp32_nn"])
+        net.close()
+
+    value = n_solves * args.steps / dt if ok else 0.0
     out = {
         "metric": METRIC,
-        "value": best["solves_per_s"],
+        "value": value,
         "unit": "solves/s",
         "n_gpus": 1,
-        "steps": 1,
-        "warmup": 1,
-        "ms_per_step": best["seconds"] * 1e3,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": inner,
         "data": "synthetic",
         "config": {
-            "workload": "multi-boson local action on a 64^4 lattice (links exp(0.2 i H) seed 5101, kappa 0.1365): "
-                        "4096 blocks Omega of 8^4 with inner Lambda_0 of 6^4 (1040 boundary sites), 12 fields "
-                        "(N = 24, c = 0.5), chi on dLambda_0 and xi on Omega Gaussian (seeds 5102, 5103); 49 152 "
-                        "block solves to FP64 true relative residual 1e-10 per evaluation; value: FP32 inner "
-                        "BiCGStab right-preconditioned by a network trained on this lattice (BF16 inference)",
-            "training_s": t_train,
-            "train_loss": [round(v, 5) for v in tl],
-            "solvers": res,
-            "speedup_fp32_nn_over_fp64": best["solves_per_s"] / max(res["fp64"]["solves_per_s"], 1e-30),
-            "speedup_fp32_over_fp64": res["fp32"]["solves_per_s"] / max(res["fp64"]["solves_per_s"], 1e-30),
+            "workload": "multi-boson local action (eq. localMB) on a 64^4 lattice (antiperiodic time; SU(3) links "
+                        "exp(0.2 i H) drawn on the GPU from seed 5101; kappa 0.1365): 4096 blocks Omega of 8^4 "
+                        "(Dirichlet) with inner Lambda_0 of 6^4 (1040 boundary sites), 12 boson fields (N = 24, "
+                        "c = 0.5), chi on dLambda_0 and xi on Omega Gaussian (seeds 5102, 5103); one evaluation = "
+                        "49 152 block solves to per-pair FP64 true relative residual <= 1e-10 plus the boundary "
+                        "norms; %s inner eo-BiCGStab inside FP64 defect correction" % inner.upper(),
+            "solves_per_step": n_solves,
+            "all_converged": ok,
+            "S_total": S_head,
+            "mean_inner_iterations_per_pair": float(res[-1][1]["iters"].mean()),
+            "outer_cycles": int(res[-1][1]["outer_cycles"]),
+            "graph_replay": not args.no_graph,
+            "input_generation_s": t_gen,
+            "other_forms": forms,
         },
         "roofline": {
-            "kernel": hop_kname + " in the FP32 evaluation (fields of one solve group)",
+            "kernel": kname,
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
-            "launches": hop_n,
-            "avg_launch_us": hop_ms * 1e3 / max(hop_n, 1),
+            "traffic": profiled_traffic(PROFILE_C5) if inner == "f32" else None,
+            "launches": k_n,
+            "avg_launch_us": k_ms * 1e3 / max(k_n, 1),
+            "alg_bytes_per_launch": k_bytes / max(k_n, 1),
+            "timing": "HIP events around each launch on the library stream, in one extra evaluation",
         },
     }
+    if "fp64" in forms and forms["fp64"]["solves_per_s"] > 0:
+        out["config"]["speedup_over_fp64"] = value / forms["fp64"]["solves_per_s"]
+    if not args.no_cpu:
+        out["cpu_baseline"] = mb_cpu_baseline(U_host, xi)
     print(json.dumps(out), flush=True)
-    net.close()
     g.close()
     blk.close()
     ctx.close()
 
 
-PROFILE = os.path.join(ROOT, "profiles", "k_dhat_walk_f32_c2_32x4_12rhs.md")
+PROFILE_C2 = os.path.join(ROOT, "profiles", "k_dhat_walk_f32_c2_32x4_12rhs.md")
+PROFILE_C5 = os.path.join(ROOT, "profiles", "k_dhat_walk_f32_c5_64x4_12fields.md")
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def stencil_timer(ctx, inner):
@@ -415,13 +514,13 @@ def stencil_timer(ctx, inner):
     return ("k_hop_walk (%s; the x0-walk hop, all its fused-dot variants)" % link, ctx.timer_read(hop))
 
 
-def profiled_traffic():
-    """HBM bytes per launch of the hop from the committed rocprofv3 summary, if it
-    was taken on the current kernel source (else None)."""
+def profiled_traffic(path):
+    """HBM bytes per launch of the dominant kernel from a committed rocprofv3 summary, if it was
+    taken on the current kernel source (else None)."""
     try:
         from paper_2211_06902_amd.rocprof_summary import kernel_source_hash
 
-        txt = open(PROFILE).read()
+        txt = open(path).read()
         js = json.loads(txt.split("```json", 1)[1].split("```", 1)[0])
         if js.get("kernel_source_sha256_16") != kernel_source_hash():
             return None
@@ -430,44 +529,8 @@ def profiled_traffic():
         return None
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--inner", default=None, choices=["f32", "bf16", "f64"],
-                    help="inner precision (default: FP32 for c2, BF16 links for c3)")
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["c4", "c5", "nnapply"])
-    ap.add_argument("--epochs", type=int, default=4, help="c4: training epochs")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run a plain 1 GiB device copy (4 times), to calibrate HBM byte counters")
-    args = ap.parse_args()
-    if args.copy_calibration:
-        import torch
-
-        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
-        dst = torch.empty_like(src)
-        for _ in range(4):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4, "copies": 4}))
-        return
-    if args.gpus != 1:
-        print("bench.py measures one GPU only: the block solves need no communication and this build has no "
-              "multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
-        sys.exit(2)
-
-    if args.workload == "c4":
-        run_c4(args)
-        return
-    if args.workload == "nnapply":
-        run_nnapply(args)
-        return
-    if args.workload == "c5":
-        run_c5(args)
-        return
-
+def run_solve(args):
+    """--workload c2 / c3: one dd_block_solve over all (block, rhs) pairs per step."""
     import torch
 
     from paper_2211_06902_amd import dd
@@ -487,7 +550,8 @@ def main():
     g = ctx.load_gauge(blk, U_dev, "bf16" if inner == "bf16" else "f32")
     t_pack = time.perf_counter() - t0
     del U_dev
-    params = dd.solve_params(inner_prec=inner, tol=TOL, method=dd.GMRES if gmres else dd.BICGSTAB, restart=16)
+    params = dd.solve_params(inner_prec=inner, tol=TOL, method=dd.GMRES if gmres else dd.BICGSTAB, restart=16,
+                             use_graph=0 if args.no_graph else 1)
     sched = None
     if gmres:
         tried, best = ctx.autotune_gmres(blk, g, w["kappa"], b, params=params, scratch=x)
@@ -499,8 +563,7 @@ def main():
         if st != dd.DD_OK:
             raise SystemExit("warmup solve did not converge: %s" % info["flags"])
 
-    ctx.timer_enable(True)
-    ctx.timer_reset()
+    # the timed steps run the library's default path (graph replay, no kernel timers)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ok = True
@@ -512,10 +575,13 @@ def main():
         iters.append(info["inner_iterations"])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # one more step with the kernel timers on for the roofline
+    ctx.timer_enable(True)
+    ctx.timer_reset()
+    ctx.block_solve(blk, g, w["kappa"], b, x, params=params)
     if gmres:
-        kclass = dd.KCLASS_GMRES
         kname = "k_gmres (persistent GMRES(16), FP32 spinor / %s link, whole inner solve per launch)" % inner.upper()
-        k_ms, k_n, k_bytes = ctx.timer_read(kclass)
+        k_ms, k_n, k_bytes = ctx.timer_read(dd.KCLASS_GMRES)
     else:
         kname, (k_ms, k_n, k_bytes) = stencil_timer(ctx, inner)
     ctx.timer_enable(False)
@@ -551,10 +617,11 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": profiled_traffic() if (args.workload == "c2" and inner == "f32") else None,
+            "traffic": profiled_traffic(PROFILE_C2) if (args.workload == "c2" and inner == "f32") else None,
             "launches": k_n,
             "avg_launch_us": k_ms * 1e3 / max(k_n, 1),
             "alg_bytes_per_launch": k_bytes / max(k_n, 1),
+            "timing": "HIP events around each launch on the library stream, in one extra step",
         },
     }
     if sched:
@@ -565,6 +632,39 @@ def main():
     g.close()
     blk.close()
     ctx.close()
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle's CPU baseline")
+    ap.add_argument("--no-nn", action="store_true", help="c5: skip the network-preconditioned form")
+    ap.add_argument("--only-head", action="store_true", help="c5: time the headline form only (no FP64, no network)")
+    ap.add_argument("--no-graph", action="store_true", help="launch every inner iteration from the host")
+    ap.add_argument("--inner", default=None, choices=["f32", "bf16", "f64"],
+                    help="inner precision (default: FP32; BF16 links for c3)")
+    ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS) + ["c4", "c5", "nnapply"])
+    ap.add_argument("--epochs", type=int, default=4, help="c4, c5: training epochs of the network")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (4 times), to calibrate HBM byte counters")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")  # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(4):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4, "copies": 4}))
+        return
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: the block solves need no communication and this build has no "
+              "multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    {"c4": run_c4, "c5": run_c5, "nnapply": run_nnapply}.get(args.workload, run_solve)(args)
 
 
 if __name__ == "__main__":

@@ -355,6 +355,17 @@ dd_status dd_nn_get_weights(dd_ctx *ctx, const dd_nn *nn, float *weights_host);
  * rounded to BF16 (nearest even), products on the matrix cores with FP32
  * accumulation, FP32 output. */
 dd_status dd_nn_apply(dd_ctx *ctx, dd_nn *nn, dd_prec prec, const float *x_dev, float *y_dev, int64_t n);
+/* The network as a solve applies it to an even-odd reduced system: for every
+ * (block, rhs) pair of x_dev ([n_rhs][total_sites][4][3] complex128, the
+ * dd_block_solve layout; every block must have the network's extent) the
+ * sites of even global parity are rounded to FP32, the network (in the
+ * inference precision of dd_nn_set_inference; with BF16 the kernels skip the
+ * taps that reach odd input sites and compute only even output sites) maps
+ * them with the odd sites taken as zero, and y_dev receives the even output
+ * sites widened to FP64 with its odd sites zero.  x_dev is only read;
+ * synchronizes.  DD_EINVAL on a block of another extent. */
+dd_status dd_nn_apply_blocks(dd_ctx *ctx, dd_nn *nn, const dd_blocks *blocks, const void *x_dev, void *y_dev,
+                             int32_t n_rhs);
 /* Precision of the network when a solve applies it (default DD_BF16). */
 dd_status dd_nn_set_inference(dd_ctx *ctx, dd_nn *nn, dd_prec prec);
 

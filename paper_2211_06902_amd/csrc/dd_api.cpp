@@ -171,14 +171,14 @@ const void *links_for(const dd_gauge *G, dd_prec prec)
 
 // Algorithmic bytes of one hop launch: the half field it reads and the one it
 // writes (24 reals per site and rhs each), each extra half-field operand (in
-// units of such a field), and every link inside the blocks once (the two
-// stored rows, 12 reals).
+// units of such a field), and every link inside the blocks once (a full SU(3)
+// matrix, 18 reals, although only two rows are stored).
 double hop_bytes(const dd_blocks *B, int nr, dd_prec prec, double extra_vectors)
 {
     const double sf = prec == DD_F64 ? 8.0 : 4.0;
     const double sl = (double)prec_bytes(prec);
     const double half_sites = (double)B->soff[B->nb] / 2.0;
-    return nr * half_sites * 24.0 * sf * (2 + extra_vectors) + (double)B->inner_links * (2.0 * kLinkK) * sl;
+    return nr * half_sites * 24.0 * sf * (2 + extra_vectors) + (double)B->inner_links * kLinkAlgReals * sl;
 }
 
 // The aux operand of the fused dots in spinor-field units: the BiCGStab

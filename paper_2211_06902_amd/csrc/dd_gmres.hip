@@ -410,7 +410,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
         // algorithmic bytes (kept by thread 0): a vector of the pair, and one eo
         // hop's links shared by the block's n_rhs pairs
         const double vb = (double)n * sizeof(SP);
-        const double lb = (double)a.nlinks[b] * (2.0 * kLinkK) * sizeof(LK) / a.n_rhs;
+        const double lb = (double)a.nlinks[b] * kLinkAlgReals * sizeof(LK) / a.n_rhs;
         double moved;
 
         // fresh start: beta0 = |f|, x = 0, V_0 = f / beta0; resumed: V_0 = r / |r|

@@ -26,6 +26,9 @@ constexpr int kNRed = 4;
 constexpr int kGmReorthPercent = 10;
 constexpr int kLinkK = 6;  // complex entries stored per link: rows 0 and 1 (row 2 is rebuilt)
 constexpr int kLinkReals = 4 * kLinkK * 2;  // per site: 4 directions
+// A link in the algorithmic byte counts: the full 3x3 complex matrix (18
+// reals), the amount the operator needs whatever the storage keeps of it.
+constexpr int kLinkAlgReals = 18;
 // Neighbour-table entry flags: bit 30 = hop across the antiperiodic time edge.
 constexpr int32_t kNbrSign = 1 << 30;
 constexpr int32_t kNbrMask = kNbrSign - 1;

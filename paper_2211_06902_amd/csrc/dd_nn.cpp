@@ -316,6 +316,29 @@ dd_status dd_nn_apply(dd_ctx *ctx, dd_nn *nn, dd_prec prec, const float *x_dev, 
     return DD_OK;
 }
 
+dd_status dd_nn_apply_blocks(dd_ctx *ctx, dd_nn *nn, const dd_blocks *B, const void *x_dev, void *y_dev,
+                             int32_t n_rhs)
+{
+    if (!ctx || !nn || !B || !x_dev || !y_dev) return fail(ctx, DD_EINVAL, "null argument");
+    if (n_rhs < 1 || n_rhs > kMaxRhs) return fail(ctx, DD_EINVAL, "n_rhs must be in 1..64");
+    if (B->ctx != ctx) return fail(ctx, DD_EINVAL, "blocks belong to another context (or have no device tables)");
+    if (!nn_fits(nn, B)) return fail(ctx, DD_EINVAL, "every block must have the network's extent");
+    HIPCHECK(ctx, enter(ctx));
+    hipError_t e = hipSuccess;
+    const size_t half = (size_t)(B->soff[B->nb] / 2) * 24 * n_rhs * sizeof(float);
+    void *xe = workspace(ctx, "nb_xe", half, &e);
+    void *xo = xe ? workspace(ctx, "nb_xo", half, &e) : nullptr;
+    void *ze = xo ? workspace(ctx, "nb_ze", half, &e) : nullptr;
+    if (!ze) return fail(ctx, DD_ENOMEM, std::string("workspace: ") + hipGetErrorString(e));
+    // FP32 half fields as inside a solve; the odd half is unused on input and zero on output
+    HIPCHECK(ctx, launch_pack_spinor(B, (const double *)x_dev, xe, xo, DD_F32, n_rhs, ctx->stream));
+    HIPCHECK(ctx, nn_apply_half(ctx, nn, B, xe, ze, n_rhs, DD_F32));
+    HIPCHECK(ctx, hipMemsetAsync(xo, 0, half, ctx->stream));
+    HIPCHECK(ctx, launch_unpack_spinor(B, ze, xo, (double *)y_dev, DD_F32, n_rhs, ctx->stream));
+    HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+    return DD_OK;
+}
+
 dd_status dd_nn_set_inference(dd_ctx *ctx, dd_nn *nn, dd_prec prec)
 {
     if (!ctx || !nn) return fail(ctx, DD_EINVAL, "null argument");

@@ -40,6 +40,24 @@ struct Ws {
     OuterState os;
 };
 
+// A captured graph and its executable, destroyed when the holder goes out of
+// scope (also on the early returns of the error paths).
+struct GraphHolder {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t gx = nullptr;
+    GraphHolder() = default;
+    GraphHolder(const GraphHolder &) = delete;
+    GraphHolder &operator=(const GraphHolder &) = delete;
+    void reset()
+    {
+        if (gx) hipGraphExecDestroy(gx);
+        if (g) hipGraphDestroy(g);
+        gx = nullptr;
+        g = nullptr;
+    }
+    ~GraphHolder() { reset(); }
+};
+
 struct Inner {
     dd_ctx *ctx;
     const dd_blocks *B;
@@ -272,7 +290,6 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
     dd_blocks *B = const_cast<dd_blocks *>(Bc);
     HIPCHECK(ctx, enter(ctx));
     hipError_t e;
-    // FP64 residual kernels and inner-precision kernels may group rhs differently
     // the FP64 residual kernels and the inner-precision kernels may group rhs
     // differently; a scalar kernel reads partials with the tiling of the
     // kernel that wrote them
@@ -391,8 +408,10 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
         }
     }
     std::vector<int32_t> h_act(np);
-    hipGraph_t g = nullptr;
-    hipGraphExec_t gx = nullptr;
+    // the captured inner iterations; destroyed on every return path
+    GraphHolder gh;
+    hipGraph_t &g = gh.g;
+    hipGraphExec_t &gx = gh.gx;
     int cycles = 0;
     int64_t inner_total = 0;
     dd_status status = DD_OK;
@@ -557,8 +576,7 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
         HIPCHECK(ctx, launch_accum(ba, w.xe, w.xi, sp, w.os.active, st));
         HIPCHECK(ctx, launch_accum(ba, w.xo, w.tmp, sp, w.os.active, st));
     }
-    if (gx) hipGraphExecDestroy(gx);
-    if (g) hipGraphDestroy(g);
+    gh.reset();
     HIPCHECK(ctx, launch_unpack_spinor(B, w.xe, w.xo, (double *)x_dev, DD_F64, n_rhs, st));
     std::vector<double> h_bb(np), h_rr(np);
     std::vector<int32_t> h_if(np), h_of(np), h_it(np);

@@ -145,6 +145,7 @@ _sig("dd_nn_free", _I32, [_P])
 _sig("dd_nn_get_weights", _I32, [_P, _P, _P])
 _sig("dd_nn_apply", _I32, [_P, _P, _I32, _P, _P, _I64])
 _sig("dd_nn_set_inference", _I32, [_P, _P, _I32])
+_sig("dd_nn_apply_blocks", _I32, [_P, _P, _P, _P, _P, _I32])
 _sig("dd_nn_train_params_default", None, [ctypes.POINTER(NnTrainParams)])
 _sig("dd_nn_loss_grad", _I32, [_P, _P, _P, _P, _P, _I32, _P, _I32, _I32, _P, _P])
 _sig("dd_nn_train", _I32, [_P, _P, _P, _P, _P, _I32, _P, _P, _I32, ctypes.POINTER(NnTrainParams), _P, _P])
@@ -249,6 +250,18 @@ class Net:
         n = x.numel() // (self.sites * 24)
         self._ctx._check(_lib.dd_nn_apply(self._ctx._h, self._h, _PREC[prec], _dev(x, "torch.float32"),
                                           _dev(y, "torch.float32"), n))
+        return y
+
+    def apply_blocks(self, blocks, x, n_rhs=None):
+        """The network as a solve applies it: x [n_rhs, total_sites, 4, 3] complex128 on the GPU (solver
+        layout) -> N of its even sites on the even sites (odd sites zero), same shape."""
+        import torch
+
+        if n_rhs is None:
+            n_rhs = x.numel() // (blocks.total_sites * 12)
+        y = torch.empty_like(x)
+        self._ctx._check(_lib.dd_nn_apply_blocks(self._ctx._h, self._h, blocks._h, _dev(x, "torch.complex128"),
+                                                 _dev(y, "torch.complex128"), int(n_rhs)))
         return y
 
     def set_inference(self, prec):

@@ -35,6 +35,7 @@ __all__ = [
     "volume",
     "site_index",
     "gauge_field",
+    "gauge_field_device",
     "unit_gauge",
     "spinor_field",
     "random_su3",
@@ -157,6 +158,82 @@ def gauge_field(L, eps: float, seed: int, chunk: int = 1 << 16) -> np.ndarray:
         for f in futs:
             f.result()
     return U
+
+
+def _expi_cayley_hamilton_torch(Q):
+    """exp(iQ) for traceless Hermitian Q[n,3,3] (torch complex128), the same
+    Cayley-Hamilton form as _expi_cayley_hamilton, evaluated on Q's device."""
+    import torch
+
+    d0, d1, d2 = Q[:, 0, 0].real, Q[:, 1, 1].real, Q[:, 2, 2].real
+    q01, q02, q12 = Q[:, 0, 1], Q[:, 0, 2], Q[:, 1, 2]
+    a01, a02, a12 = q01.abs() ** 2, q02.abs() ** 2, q12.abs() ** 2
+    s00 = d0 * d0 + a01 + a02
+    s11 = d1 * d1 + a01 + a12
+    s22 = d2 * d2 + a02 + a12
+    s01 = q01 * (d0 + d1) + q02 * q12.conj()
+    s02 = q02 * (d0 + d2) + q01 * q12
+    s12 = q01.conj() * q02 + q12 * (d1 + d2)
+    c1 = 0.5 * (s00 + s11 + s22)
+    c0 = d0 * d1 * d2 + 2 * (q01 * q12 * q02.conj()).real - d0 * a12 - d1 * a02 - d2 * a01
+    neg = c0 < 0
+    c0 = c0.abs()
+    c1s = torch.clamp(c1, min=1e-300)
+    c0max = 2.0 * (c1s / 3.0) ** 1.5
+    theta = torch.arccos(torch.clamp(c0 / c0max, -1.0, 1.0))
+    u = torch.sqrt(c1s / 3.0) * torch.cos(theta / 3.0)
+    w = torch.sqrt(c1s) * torch.sin(theta / 3.0)
+    w2 = w * w
+    small = w.abs() < 0.05
+    xi0 = torch.where(small, 1 - w2 / 6 * (1 - w2 / 20 * (1 - w2 / 42)),
+                      torch.sin(w) / torch.where(small, torch.ones_like(w), w))
+    e2iu = torch.exp(2j * u)
+    emiu = torch.exp(-1j * u)
+    cw = torch.cos(w)
+    u2 = u * u
+    den = 9 * u2 - w2
+    f0 = ((u2 - w2) * e2iu + emiu * (8 * u2 * cw + 2j * u * (3 * u2 + w2) * xi0)) / den
+    f1 = (2 * u * e2iu - emiu * (2 * u * cw - 1j * (3 * u2 - w2) * xi0)) / den
+    f2 = (e2iu - emiu * (cw + 3j * u * xi0)) / den
+    f0 = torch.where(neg, f0.conj(), f0)
+    f1 = torch.where(neg, -f1.conj(), f1)
+    f2 = torch.where(neg, f2.conj(), f2)
+    zero = c1 < 1e-30
+    f0 = torch.where(zero, torch.ones_like(f0), f0)
+    f1 = torch.where(zero, torch.zeros_like(f1), f1)
+    f2 = torch.where(zero, torch.zeros_like(f2), f2)
+    out = torch.empty((Q.shape[0], 3, 3), dtype=torch.complex128, device=Q.device)
+    out[:, 0, 0] = f0 + f1 * d0 + f2 * s00
+    out[:, 1, 1] = f0 + f1 * d1 + f2 * s11
+    out[:, 2, 2] = f0 + f1 * d2 + f2 * s22
+    out[:, 0, 1] = f1 * q01 + f2 * s01
+    out[:, 0, 2] = f1 * q02 + f2 * s02
+    out[:, 1, 2] = f1 * q12 + f2 * s12
+    out[:, 1, 0] = f1 * q01.conj() + f2 * s01.conj()
+    out[:, 2, 0] = f1 * q02.conj() + f2 * s02.conj()
+    out[:, 2, 1] = f1 * q12.conj() + f2 * s12.conj()
+    return out
+
+
+def gauge_field_device(L, eps: float, seed: int, device="cuda", chunk: int = 1 << 22):
+    """SU(3) link field U[V,4,3,3] = exp(i eps H) (torch complex128 on a torch
+    device), H = sum_a h_a lambda_a / 2 with h_a iid N(0,1) drawn by torch's
+    seeded generator for that device, in (site, mu, a) order chunk by chunk.
+    For lattices too large to draw on the host; the values are a function of
+    (L, eps, seed, device type) only and differ from gauge_field's."""
+    import torch
+
+    V = volume(L)
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    lam = torch.from_numpy(gell_mann().reshape(8, 9) * (0.5 * eps)).to(device)
+    U = torch.empty((V * 4, 3, 3), dtype=torch.complex128, device=device)
+    for s in range(0, V * 4, chunk):
+        e = min(s + chunk, V * 4)
+        h = torch.randn((e - s, 8), generator=g, dtype=torch.float64, device=device)
+        Q = (h.to(torch.complex128) @ lam).reshape(e - s, 3, 3)
+        U[s:e] = _expi_cayley_hamilton_torch(Q)
+    return U.reshape(V, 4, 3, 3)
 
 
 def unit_gauge(L) -> np.ndarray:
