@@ -10,11 +10,12 @@ Contents (each module cites the part of the paper it follows):
   wilson     Wilson-Dirac operator D, box restrictions D_Lambda, block solves (C, FP64)
   geometry   tilings and the domains of Section 2 (box reading)
   dense      dense-matrix determinant identities of Section 3 on tiny lattices
+  factor     the Schur-complement pieces of Section 3 (Dtilde, Dhat^d, Dhat^h, W_z) as dense matrices
   roots      polynomial P_N, remainder R_{N+1} and roots u_k of Section 4
   mb         block-local multi-boson action S_MB^a of Section 4
   precision  FP64 -> FP32 -> BF16 rounding rules
   convnet    the learned block preconditioner: 4D conv net, gradients, loss, Adam
              (not in the paper; parity pinned by independent identities)
 """
-from . import convnet, dense, geometry, mb, precision, roots, wilson  # noqa: F401
+from . import convnet, dense, factor, geometry, mb, precision, roots, wilson  # noqa: F401
 from ._clib import build  # noqa: F401

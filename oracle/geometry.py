@@ -44,6 +44,7 @@ __all__ = [
     "boundary_of",
     "exterior_boundary_of",
     "PaperDomains",
+    "BoxDomains",
 ]
 
 
@@ -216,6 +217,61 @@ class PaperDomains:
         self.phi_a = [o & ~l for o, l in zip(self.omega_a, self.lam0_a)]
         self.ext_omega_a = [exterior_boundary_of(o, self.nbr) for o in self.omega_a]
         self.ext_omega_star_a = [e & self.dPi1 for e in self.ext_omega_a]
+
+    def sites(self, mask) -> np.ndarray:
+        return np.nonzero(mask)[0].astype(np.int64)
+
+
+class BoxDomains:
+    """The sets of Section 2 for an explicit list of blocks: each block b is a
+    box Omega_0^b (origin, extent) holding an active box Lambda_0^b (an inner
+    offset and extent relative to it).  Masks over lattice sites:
+
+      lam0     union of the active boxes;  lam1 = its complement;
+      dlam0_b  sites of Lambda_0^b with a neighbour outside it;
+      dPi      sites with some coordinate on a face coordinate (first or last)
+               of an active box, in the directions where that box does not
+               span the lattice (the hyperplanes of step 2);
+      dPi1     dPi minus the active boxes;
+      omega_b  Omega_0^b;  phi_b = Omega_0^b minus Lambda_0^b (the frame);
+      ext_b    exterior boundary of Omega_0^b (outside, with a neighbour inside).
+    With the paper-mode boxes (Omega = [s - d, s + b - 1 + d]) these are the
+    sets of PaperDomains.
+    """
+
+    def __init__(self, L, boxes, inner):
+        self.L = [int(v) for v in L]
+        V = volume(self.L)
+        self.V = V
+        self.nbr = neighbours(self.L)
+        boxes = np.asarray(boxes, dtype=np.int64).reshape(-1, 8)
+        inner = np.asarray(inner, dtype=np.int64).reshape(-1, 8)
+        self.boxes, self.inner = boxes, inner
+        x = coords(self.L)
+        self.omega_a, self.lam0_a = [], []
+        faces = [set() for _ in range(4)]
+        for bx, ib in zip(boxes, inner):
+            o = bx[:4]
+            io = (o + ib[:4]) % np.asarray(self.L)
+            self.omega_a.append(box_mask(self.L, o, bx[4:8]))
+            self.lam0_a.append(box_mask(self.L, io, ib[4:8]))
+            for mu in range(4):
+                if ib[4 + mu] < self.L[mu]:
+                    faces[mu].add(int(io[mu]))
+                    faces[mu].add(int((io[mu] + ib[4 + mu] - 1) % self.L[mu]))
+        dpi = np.zeros(V, dtype=bool)
+        for mu in range(4):
+            if faces[mu]:
+                dpi |= np.isin(x[:, mu], sorted(faces[mu]))
+        self.dPi = dpi
+        self.lam0 = np.any(self.lam0_a, axis=0) if len(self.lam0_a) else np.zeros(V, dtype=bool)
+        self.lam1 = ~self.lam0
+        self.dlam0_a = [boundary_of(m, self.nbr) for m in self.lam0_a]
+        self.dlam0 = np.any(self.dlam0_a, axis=0) if len(self.dlam0_a) else np.zeros(V, dtype=bool)
+        self.lam0bar = self.lam0 & ~self.dlam0
+        self.dPi1 = self.dPi & self.lam1
+        self.phi_a = [o & ~l for o, l in zip(self.omega_a, self.lam0_a)]
+        self.ext_a = [exterior_boundary_of(o, self.nbr) for o in self.omega_a]
 
     def sites(self, mask) -> np.ndarray:
         return np.nonzero(mask)[0].astype(np.int64)

@@ -10,8 +10,12 @@ Reading used here:
     (Dhat_{dLambda_0^a} is the Schur complement of D_{Omega_0^a} onto
     dLambda_0^a, since the block bulk and the frame do not touch), so both
     operator terms are one solve with D_{Omega_0^a} restricted to dLambda_0^a;
-  * the caller supplies the source xi_k^a on Omega_0^a that collects both
-    hop-in terms (the one through Dhat^h depends on inactive links only).
+  * the source xi_k^a on Omega_0^a collects both hop-in terms.  With the
+    exact hopping term of oracle.factor, the dLambda_0^a rows of
+    D_{Omega_0^a}^{-1} applied to the frame part of the Dhat^h term equal
+    those of [Dhat_{dLambda_0^a}]^{-1} Dhat^h chi, so xi_k^a is the hop of
+    chi_k from the exterior boundary of Omega_0^a (which lies in dPi) into
+    Omega_0^a: exterior_source.  mb_local_action takes any xi.
 Hence  S^a = sum_k sum_{x in dLambda_0^a} |u_k chi_k(x) + (D_{Omega_0^a}^{-1} xi_k^a)(x)|^2.
 """
 from __future__ import annotations
@@ -20,7 +24,7 @@ import numpy as np
 
 from . import geometry, wilson
 
-__all__ = ["boundary_lists", "mb_local_action"]
+__all__ = ["boundary_lists", "mb_local_action", "exterior_source", "mb_local_action_from_chi"]
 
 
 def boundary_lists(L, boxes, inner):
@@ -62,3 +66,54 @@ def mb_local_action(L, tbc, kappa, U, boxes, inner, u, chi, xi, tol=1e-12, nthre
         soff += Sb
         boff += nbd
     return S, float(np.sum(S))
+
+
+def exterior_source(L, tbc, kappa, U, boxes, inner, chi, part="all"):
+    """The source xi^a = D_{Omega_0^a, E^a} chi of every block, on its box.
+
+    chi [n_fields, V, 4, 3] is a field on the whole lattice of which only the
+    sites of dPi are used; E^a is the exterior boundary of Omega_0^a (sites
+    outside it with a neighbour inside) restricted to
+      part = "dPi1": dPi_1, the D_{Phi_1^a, dOmega^{a*}} chi_{dPi_1} term of eq. (localMB);
+      part = "dLam0": dLambda_0 (the active boundaries of the other blocks);
+      part = "all":  both, i.e. dPi.
+    The "dLam0" part replaces [Dhat_{dLambda_0^a}]^{-1} Dhat^h chi of eq.
+    (localMB): with Dhat^h_{aa'} = -D_{dLambda_0^a, Phi_1^a} D_{Phi_1^a}^{-1}
+    P_{Phi_1^a} D_{Phi_1^{a'}, dLambda_0^{a'}} (the exact reading; see
+    oracle.factor) the dLambda_0^a rows of D_{Omega_0^a}^{-1} applied to
+    P_{Phi_1^a} sum_{a' != a} D_{Phi_1^a, dLambda_0^{a'}} chi equal those of
+    [Dhat_{dLambda_0^a}]^{-1} Dhat^h chi, since Lambda_0^a meets Phi_1^a
+    only through dLambda_0^a.
+    Computed as the restriction to Omega_0^a of D applied to chi masked to
+    E^a (the diagonal term vanishes there).  Returns [n_fields, sum_a S_a, 4, 3]
+    in box-local canonical order, blocks concatenated.
+    """
+    P = geometry.BoxDomains(L, boxes, inner)
+    sel = {"dPi1": P.dPi1, "dLam0": P.dlam0, "all": P.dPi}[part]
+    chi = np.asarray(chi, dtype=np.complex128)
+    out = []
+    for b in range(len(P.omega_a)):
+        E = P.ext_a[b] & sel
+        sites = geometry.box_sites(L, P.boxes[b][:4], P.boxes[b][4:8])
+        per_f = []
+        for f in range(chi.shape[0]):
+            psi = np.zeros_like(chi[f])
+            psi[E] = chi[f][E]
+            per_f.append(wilson.dirac_full(L, tbc, kappa, U, psi)[sites])
+        out.append(np.stack(per_f))
+    return np.concatenate(out, axis=1)
+
+
+def mb_local_action_from_chi(L, tbc, kappa, U, boxes, inner, u, chi, tol=1e-12, nthreads=0):
+    """S^a of eq. (localMB) from the multi-boson fields alone: chi [n_fields, V, 4, 3] on dPi (the
+    values elsewhere are not used); the boundary values u_k chi_k on dLambda_0^a and the source
+    xi^a = exterior_source(..., part="all")."""
+    chi = np.asarray(chi, dtype=np.complex128)
+    bl = boundary_lists(L, boxes, inner)
+    chib = []
+    for b, bx in enumerate(np.asarray(boxes).reshape(-1, 8)):
+        sites = geometry.box_sites(L, bx[:4], bx[4:8])
+        chib.append(chi[:, sites[bl[b]]])
+    chib = np.concatenate(chib, axis=1)
+    xi = exterior_source(L, tbc, kappa, U, boxes, inner, chi, "all")
+    return mb_local_action(L, tbc, kappa, U, boxes, inner, u, chib, xi, tol=tol, nthreads=nthreads)
