@@ -129,6 +129,17 @@ dd_status dd_blocks_query(const dd_blocks *blocks, int64_t *n_blocks, int64_t *t
 dd_status dd_blocks_tables(const dd_blocks *blocks, int32_t *boxes, int64_t *sites, int32_t *eo,
                            int32_t *bnd);
 
+/* Host copies of the exterior hops of the multi-boson source (see
+ * dd_mb_exterior_source), one entry per hop, ordered by block and receiving
+ * site (each pointer may be NULL; arrays of *n_hops entries):
+ *   block, site  the block and the box-local canonical index of the site the hop enters
+ *   code         2 mu + f (f = 1: the exterior site is x - mu), bit 3 set when the hop
+ *                crosses the antiperiodic time edge, bits 4-5 the part (1 dPi_1, 2 dLambda_0)
+ *   nbr          global canonical index of the exterior site
+ * Empty unless some block's inner box is not the whole block. */
+dd_status dd_blocks_exterior(const dd_blocks *blocks, int64_t *n_hops, int32_t *block, int32_t *site, int32_t *code,
+                             int64_t *nbr);
+
 /* The three constructors above accept ctx == NULL: the blocks then hold host
  * tables only (for dd_blocks_query / dd_blocks_tables) and every call that
  * needs the device rejects them with DD_EINVAL. */
@@ -243,6 +254,33 @@ dd_status dd_multiboson_action(dd_ctx *ctx, const dd_blocks *blocks, const dd_ga
                                const void *chi_dev, const void *xi_dev,
                                const dd_solve_params *params, double *S_block_dev,
                                double *S_total_host, dd_solve_stats *stats);
+
+/* The source xi of eq. (localMB) from the multi-boson fields alone
+ * (Section 4; eq. offdiagW1 of Section 3 for its dPi_1 part):
+ *   xi_k^a += D_{Omega_0^a, E^a} chi_k   for every block a and field k,
+ * i.e. the hops -kappa (1 -/+ gamma_mu) U chi_k into the sites of the block's
+ * box Omega_0^a from the sites E^a outside it that are selected by parts:
+ *   1: E^a = exterior boundary of Omega_0^a in dPi_1 (the term
+ *      D_{Phi_1^a, dOmega^{a*}} chi_{dPi_1});
+ *   2: E^a = exterior boundary in dLambda_0 (the active boundaries of the
+ *      other blocks).  The dLambda_0^a rows of D_{Omega_0^a}^{-1} applied to
+ *      this part equal those of [Dhat_{dLambda_0^a}]^{-1} Dhat^h chi with the
+ *      exact hopping term Dhat^h_{aa'} = -D_{dLambda_0^a, Phi_1^a}
+ *      D_{Phi_1^a}^{-1} P_{Phi_1^a} D_{Phi_1^{a'}, dLambda_0^{a'}} (the reading
+ *      of Section 3's garbled bracket that makes its second decomposition
+ *      exact), since Lambda_0^a meets the frame only through dLambda_0^a;
+ *   3: both, i.e. the whole source: then dd_multiboson_action with xi and
+ *      with chi on dLambda_0^a gives S_MB^a from chi alone.
+ * dPi is the set of sites with some coordinate on a face coordinate (first
+ * or last) of an inner box, in directions where that box does not span the
+ * lattice; dLambda_0 its part in the inner boxes (their boundary sites),
+ * dPi_1 the rest.  chi_global_dev: [n_fields][V][4][3] complex128 on the
+ * whole lattice in canonical order (only dPi sites are read); xi_dev:
+ * [n_fields][total_sites][4][3] complex128 in the block layout, updated in
+ * place (FP64).  Blocks whose inner box is the block contribute nothing.
+ * The links of the exterior hops are copied by dd_load_gauge (FP64). */
+dd_status dd_mb_exterior_source(dd_ctx *ctx, const dd_blocks *blocks, const dd_gauge *gauge, double kappa,
+                                int32_t n_fields, const void *chi_global_dev, void *xi_dev, int32_t parts);
 
 /* ------------------------------------------------------------ tuning */
 

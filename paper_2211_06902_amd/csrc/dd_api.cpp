@@ -51,63 +51,27 @@ void *workspace(dd_ctx *ctx, const std::string &name, size_t bytes, hipError_t *
 
 size_t prec_bytes(dd_prec p) { return p == DD_F64 ? 8 : (p == DD_F32 ? 4 : 2); }
 
-const TileTable *tiles_for(dd_ctx *ctx, dd_blocks *B, int nr, int g, hipError_t *err)
+// The site kernels' tiles for n_rhs rhs in groups of g: every chunk of every
+// block once per rhs group.
+TileTable tiles_for(const dd_blocks *B, int nr, int g)
 {
-    *err = hipSuccess;
-    const int key = nr * 8 + g;
-    auto it = B->tiles.find(key);
-    if (it != B->tiles.end()) return &it->second;
     TileTable tt;
-    tt.blk_tile0.assign(B->nb + 1, 0);
-    std::vector<int32_t> tb, chunk(B->nb, 0);
-    const int ng = nr / g;
-    for (int b = 0; b < B->nb; b++) {
-        const Shape &sh = B->shapes[B->shape_of[b]];
-        const int hs = sh.e[1] * sh.e[2] * sh.e[3] / 2;  // sites per parity of an x0-slice
-        int T = hs <= kTile ? hs * (kTile / hs) : kTile;
-        T = std::min(T, sh.h);
-        chunk[b] = T;
-        const int nt = ((sh.h + T - 1) / T) * ng;
-        tt.blk_tile0[b + 1] = tt.blk_tile0[b] + nt;
-        for (int t = 0; t < nt; t++) tb.push_back(b);
-    }
-    tt.ntiles = tt.blk_tile0[B->nb];
-    if ((*err = upload(&tt.d_tile_block, tb)) != hipSuccess) return nullptr;
-    if ((*err = upload(&tt.d_blk_tile0, tt.blk_tile0)) != hipSuccess) return nullptr;
-    if ((*err = upload(&tt.d_chunk, chunk)) != hipSuccess) return nullptr;
-    (void)ctx;
-    return &(B->tiles[key] = tt);
+    tt.ntiles = B->blk_chunk0[B->nb] * (nr / g);
+    return tt;
 }
 
 // Tiles of the hop's x0-walk: (nr / g) * nseg per block, ordered block,
-// segment, rhs group.  nseg is clamped to the smallest number of chunk tiles of a block, so
-// that every segment owns a chunk slot of the dot-product partials.
-const TileTable *walk_for(const dd_blocks *B, int nr, int g, int nseg, int *nseg_used, hipError_t *err)
+// segment, rhs group.  nseg is clamped to the smallest number of chunks of a
+// block, so that every segment owns a chunk slot of the dot-product partials.
+TileTable walk_for(const dd_blocks *B, int nr, int g, int nseg, int *nseg_used)
 {
-    *err = hipSuccess;
     int cap = 1 << 20;
-    for (int b = 0; b < B->nb; b++) {
-        const Shape &sh = B->shapes[B->shape_of[b]];
-        const int T = sh.walk_hs * (kTile / sh.walk_hs);
-        cap = std::min(cap, (sh.h + T - 1) / T);
-    }
+    for (int b = 0; b < B->nb; b++) cap = std::min(cap, B->blk_chunk0[b + 1] - B->blk_chunk0[b]);
     nseg = std::max(1, std::min(nseg, cap));
     *nseg_used = nseg;
-    const int key = (nr * 64 + nseg) * 8 + g;
-    auto it = B->walks.find(key);
-    if (it != B->walks.end()) return &it->second;
     TileTable tt;
-    tt.blk_tile0.assign(B->nb + 1, 0);
-    std::vector<int32_t> tb;
-    const int per = (nr / g) * nseg;
-    for (int b = 0; b < B->nb; b++) {
-        tt.blk_tile0[b + 1] = tt.blk_tile0[b] + per;
-        for (int t = 0; t < per; t++) tb.push_back(b);
-    }
-    tt.ntiles = tt.blk_tile0[B->nb];
-    if ((*err = upload(&tt.d_tile_block, tb)) != hipSuccess) return nullptr;
-    if ((*err = upload(&tt.d_blk_tile0, tt.blk_tile0)) != hipSuccess) return nullptr;
-    return &(B->walks[key] = tt);
+    tt.ntiles = B->nb * (nr / g) * nseg;
+    return tt;
 }
 
 // Segments per block of the hop's x0-walk: one, unless the (block, rhs group)
@@ -144,17 +108,17 @@ int hop_group(const dd_ctx *ctx, int nr, dd_prec sp, dd_prec lk)
     return g > cap ? cap : g;
 }
 
-BlkArgs blk_args(const dd_blocks *B, const TileTable *tt, int nr, int g)
+BlkArgs blk_args(const dd_blocks *B, const TileTable &tt, int nr, int g)
 {
     BlkArgs a;
-    a.chunk = tt->d_chunk;
-    a.tile_block = tt->d_tile_block;
-    a.blk_tile0 = tt->d_blk_tile0;
+    a.chunk = B->d_chunk;
+    a.chunk_block = B->d_chunk_block;
+    a.blk_chunk0 = B->d_blk_chunk0;
     a.h = B->d_h;
     a.soff = B->d_soff;
     a.nbr_off = B->d_nbr_off;
     a.nbr = B->d_nbr;
-    a.ntiles = tt->ntiles;
+    a.ntiles = tt.ntiles;
     a.n_rhs = nr;
     a.nb = B->nb;
     a.g = g;
@@ -195,12 +159,11 @@ static bool walk_applies(const dd_ctx *ctx, const dd_blocks *B, const BlkArgs &b
     return ctx->hop_lds && (ba.g == 1 || (ba.g == 2 && prec != DD_F64)) && B->walk && ctx->hop_walk >= 0;
 }
 
-int hop_walk_segments(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, dd_prec prec, hipError_t *err)
+int hop_walk_segments(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, dd_prec prec)
 {
-    *err = hipSuccess;
     if (!walk_applies(ctx, B, ba, prec)) return 0;
     int nseg = 1;
-    if (!walk_for(B, ba.n_rhs, ba.g, walk_segments(ctx, B, ba.n_rhs / ba.g), &nseg, err)) return 0;
+    walk_for(B, ba.n_rhs, ba.g, walk_segments(ctx, B, ba.n_rhs / ba.g), &nseg);
     return nseg;
 }
 
@@ -224,16 +187,13 @@ hipError_t run_hop(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const Hop
     }
     TimedLaunch tl(ctx, DD_KCLASS_HOP_F64 + (int)prec, dev_count ? 0.0 : bytes);
     if (walk) {
-        hipError_t err;
         int nseg = 1;
-        const TileTable *wt = walk_for(B, ba.n_rhs, ba.g, walk_segments(ctx, B, ba.n_rhs / ba.g), &nseg, &err);
-        if (!wt) return err;
+        const TileTable wt = walk_for(B, ba.n_rhs, ba.g, walk_segments(ctx, B, ba.n_rhs / ba.g), &nseg);
         WalkArgs wa;
-        wa.tile_block = wt->d_tile_block;
-        wa.blk_tile0 = wt->d_blk_tile0;
         wa.ext = B->d_ext;
-        wa.ntiles = wt->ntiles;
+        wa.ntiles = wt.ntiles;
         wa.nseg = nseg;
+        wa.per = nseg * (ba.n_rhs / ba.g);
         return launch_hop_walk(ba, wa, ha, prec, ctx->stream);
     }
     return launch_hop(ba, ha, prec, ctx->stream);
@@ -244,14 +204,6 @@ bool dhat_walk_applies(const dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba,
     if (!ctx->hop_lds || !B->walk || ctx->hop_walk < 0 || ctx->dhat_walk < 0) return false;
     if (prec != DD_F32 && prec != DD_BF16) return false;
     return walk_segments(ctx, B, ba.n_rhs) == 1;
-}
-
-hipError_t dhat_walk_prepare(const dd_blocks *B, const BlkArgs &ba)
-{
-    hipError_t err;
-    int nseg = 1;
-    if (!walk_for(B, ba.n_rhs, 1, 1, &nseg, &err)) return err;
-    return nseg == 1 ? hipSuccess : hipErrorInvalidValue;
 }
 
 hipError_t run_dhat(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const HopArgs &ha_in, dd_prec prec)
@@ -273,18 +225,50 @@ hipError_t run_dhat(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const Ho
         ha.bytes_site = bytes / ((double)ba.n_rhs * (double)(B->soff[B->nb] / 2));
     }
     TimedLaunch tl(ctx, kc, dev_count ? 0.0 : bytes);
-    hipError_t err;
     int nseg = 1;
-    const TileTable *wt = walk_for(B, ba.n_rhs, 1, 1, &nseg, &err);
-    if (!wt) return err;
-    if (nseg != 1) return hipErrorInvalidValue;
+    const TileTable wt = walk_for(B, ba.n_rhs, 1, 1, &nseg);
     WalkArgs wa;
-    wa.tile_block = wt->d_tile_block;
-    wa.blk_tile0 = wt->d_blk_tile0;
     wa.ext = B->d_ext;
-    wa.ntiles = wt->ntiles;
+    wa.ntiles = wt.ntiles;
     wa.nseg = 1;
+    wa.per = ba.n_rhs;
     return launch_dhat_walk(ba, wa, ha, prec, ctx->stream);
+}
+
+dd_status apply_D_check(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *G, dd_prec prec, const void *x_dev,
+                        void *y_dev, int32_t n_rhs, const void **links)
+{
+    if (!ctx || !B || !G || !x_dev || !y_dev) return fail(ctx, DD_EINVAL, "null argument");
+    if (n_rhs < 1 || n_rhs > kMaxRhs) return fail(ctx, DD_EINVAL, "n_rhs must be in 1..64");
+    if (G->blocks != B) return fail(ctx, DD_EINVAL, "gauge was loaded for other blocks");
+    *links = links_for(G, prec);
+    if (!*links) return fail(ctx, DD_EINVAL, "gauge holds no links of the requested precision");
+    return DD_OK;
+}
+
+size_t apply_D_half_bytes(const dd_blocks *B, int n_rhs, dd_prec prec)
+{
+    const dd_prec sp = prec == DD_F64 ? DD_F64 : DD_F32;
+    return (size_t)(B->soff[B->nb] / 2) * 24 * n_rhs * prec_bytes(sp);
+}
+
+dd_status apply_D_with(dd_ctx *ctx, const dd_blocks *Bc, const void *links, double kappa, dd_prec prec,
+                       const void *x_dev, void *y_dev, int32_t n_rhs, void *const hf[4])
+{
+    const dd_prec sp = prec == DD_F64 ? DD_F64 : DD_F32;
+    const int g = hop_group(ctx, n_rhs, sp, prec);
+    const BlkArgs ba = blk_args(Bc, tiles_for(Bc, n_rhs, g), n_rhs, g);
+    void *xe = hf[0], *xo = hf[1], *ye = hf[2], *yo = hf[3];
+    HIPCHECK(ctx, launch_pack_spinor(Bc, (const double *)x_dev, xe, xo, sp, n_rhs, ctx->stream));
+    for (int p = 0; p < 2; p++) {
+        HopArgs ha = hop_args(p ? yo : ye, p ? xe : xo, links, p, -kappa);
+        ha.self = p ? xo : xe;
+        ha.c_self = 1.0;
+        HIPCHECK(ctx, run_hop(ctx, Bc, ba, ha, prec));
+    }
+    HIPCHECK(ctx, launch_unpack_spinor(Bc, ye, yo, (double *)y_dev, sp, n_rhs, ctx->stream));
+    HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+    return DD_OK;
 }
 
 HopArgs hop_args(void *out, const void *in, const void *links, int parity, double c_hop)
@@ -325,6 +309,13 @@ dd_status dd_create(int device, void *hip_stream, dd_ctx **out)
         return DD_EDEVICE;
     }
     ctx->user_stream = (hipStream_t)hip_stream;
+    // the event each call records on the caller's stream
+    if (hipEventCreateWithFlags(&ctx->enter_ev, hipEventDisableTiming) != hipSuccess) {
+        if (ctx->enter_ev) hipEventDestroy(ctx->enter_ev);
+        hipStreamDestroy(ctx->stream);
+        delete ctx;
+        return DD_EDEVICE;
+    }
     *out = ctx;
     return DD_OK;
 }
@@ -341,6 +332,7 @@ dd_status dd_destroy(dd_ctx *ctx)
             hipEventDestroy(e.first);
             hipEventDestroy(e.second);
         }
+    if (ctx->enter_ev) hipEventDestroy(ctx->enter_ev);
     hipStreamDestroy(ctx->stream);
     delete ctx;
     return DD_OK;
@@ -358,11 +350,8 @@ hipError_t enter(dd_ctx *ctx)
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return e;
     (void)hipGetLastError();  // drop a stale error left by unrelated runtime calls
-    hipEvent_t ev;
-    if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess) return e;
-    if ((e = hipEventRecord(ev, ctx->user_stream)) == hipSuccess) e = hipStreamWaitEvent(ctx->stream, ev, 0);
-    hipEventDestroy(ev);
-    return e;
+    if ((e = hipEventRecord(ctx->enter_ev, ctx->user_stream)) != hipSuccess) return e;
+    return hipStreamWaitEvent(ctx->stream, ctx->enter_ev, 0);
 }
 
 dd_status finish_blocks(dd_ctx *ctx, dd_blocks *B, dd_blocks **out)
@@ -381,6 +370,19 @@ dd_status finish_blocks(dd_ctx *ctx, dd_blocks *B, dd_blocks **out)
             ext[4 * b + m] = B->box[16 * b + 4 + m];
         }
     }
+    // chunks of the site kernels: whole x0-slices up to kTile sites per parity
+    std::vector<int32_t> chunk(B->nb), chunk_block;
+    B->blk_chunk0.assign(B->nb + 1, 0);
+    for (int b = 0; b < B->nb; b++) {
+        const Shape &sh = B->shapes[B->shape_of[b]];
+        const int hs = sh.e[1] * sh.e[2] * sh.e[3] / 2;  // sites per parity of an x0-slice
+        int T = hs <= kTile ? hs * (kTile / hs) : kTile;
+        T = std::min(T, sh.h);
+        chunk[b] = T;
+        const int nc = (sh.h + T - 1) / T;
+        B->blk_chunk0[b + 1] = B->blk_chunk0[b] + nc;
+        for (int c = 0; c < nc; c++) chunk_block.push_back(b);
+    }
     B->iperm.assign(B->perm.size(), 0);
     for (const Shape &sh : B->shapes)
         for (int k = 0; k < sh.S; k++) B->iperm[sh.perm_off + B->perm[sh.perm_off + k]] = k;
@@ -390,7 +392,13 @@ dd_status finish_blocks(dd_ctx *ctx, dd_blocks *B, dd_blocks **out)
         (e = upload(&B->d_nlinks, nl)) != hipSuccess ||
         (e = upload(&B->d_nbr_off, nbo)) != hipSuccess || (e = upload(&B->d_perm_off, pmo)) != hipSuccess ||
         (e = upload(&B->d_origin, org)) != hipSuccess || (e = upload(&B->d_ext, ext)) != hipSuccess ||
-        (e = upload(&B->d_bnd, B->bnd)) != hipSuccess || (e = upload(&B->d_boff, B->boff)) != hipSuccess) {
+        (e = upload(&B->d_bnd, B->bnd)) != hipSuccess || (e = upload(&B->d_boff, B->boff)) != hipSuccess ||
+        (e = upload(&B->d_chunk, chunk)) != hipSuccess || (e = upload(&B->d_chunk_block, chunk_block)) != hipSuccess ||
+        (e = upload(&B->d_blk_chunk0, B->blk_chunk0)) != hipSuccess ||
+        (!B->x_code.empty() &&
+         ((e = upload(&B->d_xg_block, B->xg_block)) != hipSuccess || (e = upload(&B->d_xg_site, B->xg_site)) != hipSuccess ||
+          (e = upload(&B->d_xg_first, B->xg_first)) != hipSuccess || (e = upload(&B->d_x_code, B->x_code)) != hipSuccess ||
+          (e = upload(&B->d_x_nbr, B->x_nbr)) != hipSuccess || (e = upload(&B->d_x_link, B->x_link)) != hipSuccess))) {
         dd_free_blocks(B);
         return fail(ctx, DD_EDEVICE, std::string("geometry upload: ") + hipGetErrorString(e));
     }
@@ -513,19 +521,12 @@ dd_status dd_free_blocks(dd_blocks *B)
 {
     if (!B) return DD_EINVAL;
     if (B->device >= 0) hipSetDevice(B->device);
-    void *ptrs[] = {B->d_nbr, B->d_perm, B->d_iperm, B->d_soff, B->d_h, B->d_nlinks, B->d_nbr_off, B->d_perm_off,
-                    B->d_origin, B->d_ext, B->d_bnd, B->d_boff};
+    void *ptrs[] = {B->d_nbr,    B->d_perm,   B->d_iperm,  B->d_soff, B->d_h,    B->d_nlinks,
+                    B->d_nbr_off, B->d_perm_off, B->d_origin, B->d_ext,  B->d_bnd,  B->d_boff,
+                    B->d_chunk,  B->d_chunk_block, B->d_blk_chunk0, B->d_xg_block, B->d_xg_site,
+                    B->d_xg_first, B->d_x_code, B->d_x_nbr, B->d_x_link};
     for (void *p : ptrs)
         if (p) hipFree(p);
-    for (auto &kv : B->tiles) {
-        if (kv.second.d_tile_block) hipFree(kv.second.d_tile_block);
-        if (kv.second.d_blk_tile0) hipFree(kv.second.d_blk_tile0);
-        if (kv.second.d_chunk) hipFree(kv.second.d_chunk);
-    }
-    for (auto &kv : B->walks) {
-        if (kv.second.d_tile_block) hipFree(kv.second.d_tile_block);
-        if (kv.second.d_blk_tile0) hipFree(kv.second.d_blk_tile0);
-    }
     for (auto &kv : B->queues) {
         if (kv.second.d_queue) hipFree(kv.second.d_queue);
         if (kv.second.d_qoff) hipFree(kv.second.d_qoff);
@@ -573,6 +574,21 @@ dd_status dd_blocks_tables(const dd_blocks *B, int32_t *boxes, int64_t *sites, i
     return DD_OK;
 }
 
+dd_status dd_blocks_exterior(const dd_blocks *B, int64_t *n_hops, int32_t *block, int32_t *site, int32_t *code,
+                             int64_t *nbr)
+{
+    if (!B) return DD_EINVAL;
+    if (n_hops) *n_hops = (int64_t)B->x_code.size();
+    for (size_t g = 0; g < B->xg_block.size(); g++)
+        for (int32_t e = B->xg_first[g]; e < B->xg_first[g + 1]; e++) {
+            if (block) block[e] = B->xg_block[g];
+            if (site) site[e] = B->xg_site[g];
+        }
+    if (code && !B->x_code.empty()) std::memcpy(code, B->x_code.data(), B->x_code.size() * sizeof(int32_t));
+    if (nbr && !B->x_nbr.empty()) std::memcpy(nbr, B->x_nbr.data(), B->x_nbr.size() * sizeof(int64_t));
+    return DD_OK;
+}
+
 // ------------------------------------------------------------------ gauge
 
 dd_status dd_load_gauge(dd_ctx *ctx, const dd_blocks *B, const void *U_dev, dd_prec low_prec, dd_gauge **out)
@@ -599,6 +615,10 @@ dd_status dd_load_gauge(dd_ctx *ctx, const dd_blocks *B, const void *U_dev, dd_p
         e = hipMalloc((void **)&G->d_ubf, std::max<size_t>(nl * 2, 2));
         if (e == hipSuccess) e = launch_pack_gauge(B, (const double *)U_dev, DD_BF16, G->d_ubf, ctx->stream);
     }
+    if (e == hipSuccess && !B->x_code.empty()) {
+        e = hipMalloc((void **)&G->d_uext, B->x_code.size() * 18 * sizeof(double));
+        if (e == hipSuccess) e = launch_gather_ext_links(B, (const double *)U_dev, G->d_uext, ctx->stream);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
         dd_free_gauge(G);
@@ -616,6 +636,7 @@ dd_status dd_free_gauge(dd_gauge *G)
     if (G->d_u64) hipFree(G->d_u64);
     if (G->d_u32) hipFree(G->d_u32);
     if (G->d_ubf) hipFree(G->d_ubf);
+    if (G->d_uext) hipFree(G->d_uext);
     delete G;
     return DD_OK;
 }
@@ -637,35 +658,18 @@ dd_status dd_gauge_export(dd_ctx *ctx, const dd_gauge *G, dd_prec prec, void *ds
 dd_status dd_apply_D_block(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, double kappa, dd_prec prec,
                            const void *x_dev, void *y_dev, int32_t n_rhs)
 {
-    if (!ctx || !Bc || !G || !x_dev || !y_dev) return fail(ctx, DD_EINVAL, "null argument");
-    if (n_rhs < 1 || n_rhs > kMaxRhs) return fail(ctx, DD_EINVAL, "n_rhs must be in 1..64");
-    if (G->blocks != Bc) return fail(ctx, DD_EINVAL, "gauge was loaded for other blocks");
-    const void *links = links_for(G, prec);
-    if (!links) return fail(ctx, DD_EINVAL, "gauge holds no links of the requested precision");
-    dd_blocks *B = const_cast<dd_blocks *>(Bc);
+    const void *links = nullptr;
+    const dd_status st = apply_D_check(ctx, Bc, G, prec, x_dev, y_dev, n_rhs, &links);
+    if (st != DD_OK) return st;
     HIPCHECK(ctx, enter(ctx));
     hipError_t e;
-    const dd_prec sp = prec == DD_F64 ? DD_F64 : DD_F32;
-    const int g = hop_group(ctx, n_rhs, sp, prec);
-    const TileTable *tt = tiles_for(ctx, B, n_rhs, g, &e);
-    if (!tt) return fail(ctx, DD_EDEVICE, std::string("tile tables: ") + hipGetErrorString(e));
-    const BlkArgs ba = blk_args(B, tt, n_rhs, g);
-    const size_t half = (size_t)(B->soff[B->nb] / 2) * 24 * n_rhs * prec_bytes(sp);
-    void *xe = workspace(ctx, "ap_xe", half, &e);
-    void *xo = xe ? workspace(ctx, "ap_xo", half, &e) : nullptr;
-    void *ye = xo ? workspace(ctx, "ap_ye", half, &e) : nullptr;
-    void *yo = ye ? workspace(ctx, "ap_yo", half, &e) : nullptr;
-    if (!yo) return fail(ctx, DD_ENOMEM, std::string("workspace: ") + hipGetErrorString(e));
-    HIPCHECK(ctx, launch_pack_spinor(B, (const double *)x_dev, xe, xo, sp, n_rhs, ctx->stream));
-    for (int p = 0; p < 2; p++) {
-        HopArgs ha = hop_args(p ? yo : ye, p ? xe : xo, links, p, -kappa);
-        ha.self = p ? xo : xe;
-        ha.c_self = 1.0;
-        HIPCHECK(ctx, run_hop(ctx, B, ba, ha, prec));
-    }
-    HIPCHECK(ctx, launch_unpack_spinor(B, ye, yo, (double *)y_dev, sp, n_rhs, ctx->stream));
-    HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
-    return DD_OK;
+    const size_t half = apply_D_half_bytes(Bc, n_rhs, prec);
+    void *hf[4];
+    const char *names[4] = {"ap_xe", "ap_xo", "ap_ye", "ap_yo"};
+    for (int k = 0; k < 4; k++)
+        if (!(hf[k] = workspace(ctx, names[k], half, &e)))
+            return fail(ctx, DD_ENOMEM, std::string("workspace: ") + hipGetErrorString(e));
+    return apply_D_with(ctx, Bc, links, kappa, prec, x_dev, y_dev, n_rhs, hf);
 }
 
 // ------------------------------------------------------------------ timing

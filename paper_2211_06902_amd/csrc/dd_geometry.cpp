@@ -18,14 +18,23 @@ namespace dd {
 namespace {
 
 struct ShapeKey {
-    int e[4], full[4], opar, tw;
+    int e[4], full[4], opar, tw, hole, hio[4], hie[4];
     bool operator<(const ShapeKey &o) const
     {
-        return std::tie(e[0], e[1], e[2], e[3], full[0], full[1], full[2], full[3], opar, tw) <
-               std::tie(o.e[0], o.e[1], o.e[2], o.e[3], o.full[0], o.full[1], o.full[2], o.full[3], o.opar,
-                        o.tw);
+        return std::tie(e[0], e[1], e[2], e[3], full[0], full[1], full[2], full[3], opar, tw, hole, hio[0], hio[1],
+                        hio[2], hio[3], hie[0], hie[1], hie[2], hie[3]) <
+               std::tie(o.e[0], o.e[1], o.e[2], o.e[3], o.full[0], o.full[1], o.full[2], o.full[3], o.opar, o.tw,
+                        o.hole, o.hio[0], o.hio[1], o.hio[2], o.hio[3], o.hie[0], o.hie[1], o.hie[2], o.hie[3]);
     }
 };
+
+inline bool in_hole(const Shape &sh, const int y[4])
+{
+    if (!sh.hole) return false;
+    for (int m = 0; m < 4; m++)
+        if (y[m] < sh.hio[m] || y[m] >= sh.hio[m] + sh.hie[m]) return false;
+    return true;
+}
 
 inline int lidx(const int e[4], const int y[4]) { return ((y[0] * e[1] + y[1]) * e[2] + y[2]) * e[3] + y[3]; }
 
@@ -53,7 +62,9 @@ int walk_slice(const Shape &sh, const int32_t *tab)
         const int h = slot % sh.h, q = h / hs;
         const int32_t *t = tab + (size_t)slot * 8;
         const int32_t up = q + 1 < sh.e[0] ? h + hs : -1, dn = q > 0 ? h - hs : -1;
-        if ((t[0] < 0 ? -1 : (t[0] & kNbrMask)) != up || (t[1] < 0 ? -1 : (t[1] & kNbrMask)) != dn) return 0;
+        // a dropped hop (Dirichlet face, or a frame's hole) is always fine
+        if ((t[0] >= 0 && (t[0] & kNbrMask) != up) || (t[1] >= 0 && (t[1] & kNbrMask) != dn)) return 0;
+        if ((up < 0 && t[0] >= 0) || (dn < 0 && t[1] >= 0)) return 0;
         for (int k = 2; k < 8; k++)
             if (t[k] >= 0 && (t[k] & kNbrMask) / hs != q) return 0;
     }
@@ -87,6 +98,7 @@ int64_t build_shape(Shape &sh, int tbc, std::vector<int32_t> &perm, std::vector<
         const int p = slot >= sh.h;
         int y[4];
         lcoords(e, perm[sh.perm_off + slot], y);
+        const bool hole_site = in_hole(sh, y);
         for (int mu = 0; mu < 4; mu++) {
             for (int f = 0; f < 2; f++) {
                 int yy[4] = {y[0], y[1], y[2], y[3]};
@@ -108,6 +120,7 @@ int64_t build_shape(Shape &sh, int tbc, std::vector<int32_t> &perm, std::vector<
                     link_origin = yy[mu];
                 }
                 int32_t entry = -1;
+                if (in && (hole_site || in_hole(sh, yy))) in = false;
                 if (in) {
                     entry = pos[lidx(e, yy)] - (1 - p) * sh.h;
                     if (tbc < 0 && mu == 0 && link_origin == sh.tw) entry |= kNbrSign;
@@ -121,10 +134,97 @@ int64_t build_shape(Shape &sh, int tbc, std::vector<int32_t> &perm, std::vector<
     return links;
 }
 
+// Exterior hops of the multi-boson source (Section 4, eq. localMB): the
+// hyperplanes dPi are the sites with some coordinate on a face coordinate
+// (first or last) of an inner box, in the directions where that box does not
+// span the lattice; the sets dLambda_0 (boundary sites of the inner boxes)
+// and dPi_1 (dPi outside the inner boxes) are its two parts.  For every
+// block, the hops into the box from exterior sites in either part are listed,
+// grouped by receiving site.  Nothing is built when every inner box is its
+// block (no frames).
+void build_exterior(dd_blocks *B)
+{
+    const int *L = B->L;
+    bool framed = false;
+    for (int k = 0; k < B->nb; k++)
+        for (int m = 0; m < 4; m++) framed = framed || B->box[16 * k + 12 + m] != B->box[16 * k + 4 + m];
+    if (!framed || B->hole[0]) return;  // no frames, or frame domains themselves
+    const int64_t V = (int64_t)L[0] * L[1] * L[2] * L[3];
+    auto gidx = [&](const int x[4]) { return (((int64_t)x[0] * L[1] + x[1]) * L[2] + x[2]) * L[3] + x[3]; };
+    std::vector<uint8_t> face[4], lam0(V, 0), dlam0(V, 0);
+    for (int m = 0; m < 4; m++) face[m].assign(L[m], 0);
+    for (int k = 0; k < B->nb; k++) {
+        const int32_t *r = &B->box[16 * k];
+        int io[4], ie[4];
+        for (int m = 0; m < 4; m++) {
+            io[m] = (r[m] + r[8 + m]) % L[m];
+            ie[m] = r[12 + m];
+            if (ie[m] < L[m]) {
+                face[m][io[m]] = 1;
+                face[m][(io[m] + ie[m] - 1) % L[m]] = 1;
+            }
+        }
+        const int S = ie[0] * ie[1] * ie[2] * ie[3];
+        for (int q = 0; q < S; q++) {
+            int y[4], x[4];
+            lcoords(ie, q, y);
+            bool bnd = false;
+            for (int m = 0; m < 4; m++) {
+                x[m] = (io[m] + y[m]) % L[m];
+                if (ie[m] < L[m] && (y[m] == 0 || y[m] == ie[m] - 1)) bnd = true;
+            }
+            lam0[gidx(x)] = 1;
+            if (bnd) dlam0[gidx(x)] = 1;
+        }
+    }
+    B->xg_first.assign(1, 0);
+    for (int k = 0; k < B->nb; k++) {
+        const int32_t *r = &B->box[16 * k];
+        const int o[4] = {r[0], r[1], r[2], r[3]}, e[4] = {r[4], r[5], r[6], r[7]};
+        const int S = e[0] * e[1] * e[2] * e[3];
+        for (int s = 0; s < S; s++) {
+            int y[4], x[4];
+            lcoords(e, s, y);
+            bool shell = false;
+            for (int m = 0; m < 4; m++) {
+                x[m] = (o[m] + y[m]) % L[m];
+                if (e[m] < L[m] && (y[m] == 0 || y[m] == e[m] - 1)) shell = true;
+            }
+            if (!shell) continue;
+            const size_t first = B->x_code.size();
+            for (int mu = 0; mu < 4; mu++) {
+                if (e[mu] == L[mu]) continue;  // the box wraps onto itself along mu
+                for (int f = 0; f < 2; f++) {
+                    const int yy = y[mu] + (f ? -1 : 1);
+                    if (yy >= 0 && yy < e[mu]) continue;
+                    int xn[4] = {x[0], x[1], x[2], x[3]};
+                    xn[mu] = (x[mu] + (f ? L[mu] - 1 : 1)) % L[mu];
+                    const int64_t n = gidx(xn);
+                    bool on_pi = false;
+                    for (int m = 0; m < 4; m++) on_pi = on_pi || face[m][xn[m]];
+                    if (!on_pi) continue;
+                    const int part = lam0[n] ? (dlam0[n] ? 2 : 0) : 1;
+                    if (!part) continue;
+                    const bool sign = B->tbc < 0 && mu == 0 &&
+                                      ((f == 0 && x[0] == L[0] - 1) || (f == 1 && x[0] == 0));
+                    B->x_code.push_back((2 * mu + f) | (sign ? 8 : 0) | (part << 4));
+                    B->x_nbr.push_back(n);
+                    B->x_link.push_back(4 * (f ? n : gidx(x)) + mu);
+                }
+            }
+            if (B->x_code.size() > first) {
+                B->xg_block.push_back(k);
+                B->xg_site.push_back(s);
+                B->xg_first.push_back((int32_t)B->x_code.size());
+            }
+        }
+    }
+}
+
 }  // namespace
 
 std::string build_geometry(dd_blocks *B, const int L[4], int tbc, int n, const int32_t *boxes,
-                           const int32_t *inner)
+                           const int32_t *inner, bool frames)
 {
     for (int m = 0; m < 4; m++)
         if (L[m] < 2 || (L[m] & 1)) return "lattice extents must be even and >= 2";
@@ -137,6 +237,7 @@ std::string build_geometry(dd_blocks *B, const int L[4], int tbc, int n, const i
     B->soff.assign(n + 1, 0);
     B->boff.assign(n + 1, 0);
     B->shape_of.assign(n, 0);
+    B->hole.assign(n, frames ? 1 : 0);
     std::map<ShapeKey, int> shape_ids;
     std::vector<int64_t> shape_links;
     for (int k = 0; k < n; k++) {
@@ -150,12 +251,22 @@ std::string build_geometry(dd_blocks *B, const int L[4], int tbc, int n, const i
             ie[m] = inner ? inner[8 * k + 4 + m] : e[m];
             if (io[m] < 0 || ie[m] < 1 || io[m] + ie[m] > e[m]) return "inner box must lie inside its block";
         }
+        if (frames) {
+            bool proper = false;
+            for (int m = 0; m < 4; m++) proper = proper || ie[m] != e[m];
+            if (!proper) return "a frame needs an inner box smaller than its block";
+        }
         ShapeKey key;
         for (int m = 0; m < 4; m++) {
             key.e[m] = e[m];
             key.full[m] = e[m] == L[m];
         }
         key.opar = (o[0] + o[1] + o[2] + o[3]) & 1;
+        key.hole = frames ? 1 : 0;
+        for (int m = 0; m < 4; m++) {
+            key.hio[m] = frames ? io[m] : 0;
+            key.hie[m] = frames ? ie[m] : 0;
+        }
         key.tw = -1;
         if (tbc < 0) {
             const int tw = ((L[0] - 1 - o[0]) % L[0] + L[0]) % L[0];
@@ -169,6 +280,9 @@ std::string build_geometry(dd_blocks *B, const int L[4], int tbc, int n, const i
             std::memcpy(sh.full, key.full, sizeof(sh.full));
             sh.opar = key.opar;
             sh.tw = key.tw;
+            sh.hole = key.hole;
+            std::memcpy(sh.hio, key.hio, sizeof(sh.hio));
+            std::memcpy(sh.hie, key.hie, sizeof(sh.hie));
             const int64_t links = build_shape(sh, tbc, B->perm, B->nbr);
             sh.links = links;
             sid = (int)B->shapes.size();
@@ -192,7 +306,8 @@ std::string build_geometry(dd_blocks *B, const int L[4], int tbc, int n, const i
         }
         // dLambda_0: inner-box sites with a lattice neighbour outside the inner box.
         // Along a direction where the inner box spans the lattice the neighbours wrap inside.
-        for (int s = 0; s < sh.S; s++) {
+        // (A frame has none: its inner box is not part of its domain.)
+        for (int s = 0; s < (frames ? 0 : sh.S); s++) {
             int y[4];
             lcoords(e, s, y);
             bool inside = true, bnd = false;
@@ -206,6 +321,7 @@ std::string build_geometry(dd_blocks *B, const int L[4], int tbc, int n, const i
     }
     B->walk = n > 0;
     for (const Shape &sh : B->shapes) B->walk = B->walk && sh.walk_hs > 0;
+    build_exterior(B);
     return "";
 }
 

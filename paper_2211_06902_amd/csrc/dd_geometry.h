@@ -8,8 +8,9 @@
 namespace dd {
 
 // Fill the host tables of B from n boxes [n][8] (origin, extent) and optional
-// inner boxes [n][8] (offset, extent).  Returns "" or an error message.
+// inner boxes [n][8] (offset, extent).  With frames set, every block's solve
+// domain is its box minus its inner box.  Returns "" or an error message.
 std::string build_geometry(dd_blocks *B, const int L[4], int tbc, int n, const int32_t *boxes,
-                           const int32_t *inner);
+                           const int32_t *inner, bool frames = false);
 
 }  // namespace dd

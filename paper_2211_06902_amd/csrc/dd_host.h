@@ -15,23 +15,31 @@ dd_status fail(dd_ctx *ctx, dd_status st, const std::string &msg);
 void *workspace(dd_ctx *ctx, const std::string &name, size_t bytes, hipError_t *err);
 size_t prec_bytes(dd_prec p);
 hipError_t enter(dd_ctx *ctx);
-const TileTable *tiles_for(dd_ctx *ctx, dd_blocks *B, int nr, int g, hipError_t *err);
+TileTable tiles_for(const dd_blocks *B, int nr, int g);
 int rhs_group(const dd_ctx *ctx, int nr, dd_prec sp, dd_prec lk);
 int hop_group(const dd_ctx *ctx, int nr, dd_prec sp, dd_prec lk);
-BlkArgs blk_args(const dd_blocks *B, const TileTable *tt, int nr, int g);
+BlkArgs blk_args(const dd_blocks *B, const TileTable &tt, int nr, int g);
 const void *links_for(const dd_gauge *G, dd_prec prec);
 double hop_bytes(const dd_blocks *B, int nr, dd_prec prec, double extra_vectors);
 hipError_t run_hop(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const HopArgs &ha, dd_prec prec);
 // Segments per block of the x0-walk that run_hop takes for these blocks, rhs
 // group and precision; 0 when it takes the chunked kernel.
-int hop_walk_segments(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, dd_prec prec, hipError_t *err);
+int hop_walk_segments(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, dd_prec prec);
 // Dhat = 1 - kappa^2 H_eo H_oe as one x0-walk kernel (launch_dhat_walk): when
 // it applies to these blocks, rhs and spinor/link precision, and its launch.
 bool dhat_walk_applies(const dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, dd_prec prec);
-// Builds its walk table (device memory: before any graph capture that launches it).
-hipError_t dhat_walk_prepare(const dd_blocks *B, const BlkArgs &ba);
 hipError_t run_dhat(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const HopArgs &ha, dd_prec prec);
 HopArgs hop_args(void *out, const void *in, const void *links, int parity, double c_hop);
+
+// y = D_Lambda x (dd_apply_D_block): argument checks (links of the precision),
+// the bytes of each of its four half fields, and the operator with the half
+// fields x_e, x_o, y_e, y_o given (pack, one hop launch per parity, unpack;
+// synchronizes).
+dd_status apply_D_check(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *G, dd_prec prec, const void *x_dev,
+                        void *y_dev, int32_t n_rhs, const void **links);
+size_t apply_D_half_bytes(const dd_blocks *B, int n_rhs, dd_prec prec);
+dd_status apply_D_with(dd_ctx *ctx, const dd_blocks *B, const void *links, double kappa, dd_prec prec,
+                       const void *x_dev, void *y_dev, int32_t n_rhs, void *const hf[4]);
 
 // Timing of one kernel launch of a class (events only while timing is on).
 struct TimedLaunch {

@@ -50,6 +50,7 @@ struct dd_ctx {
     int device = 0;
     hipStream_t stream = nullptr;       // library stream (non-blocking, default priority)
     hipStream_t user_stream = nullptr;  // caller's stream; each call waits for it on entry
+    hipEvent_t enter_ev = nullptr;      // recorded on user_stream by each call
     std::string err;
     std::map<std::string, dd::DevBuf> ws;  // named, grow-only workspaces
     bool timing = false;
@@ -81,6 +82,11 @@ struct Shape {
     int64_t links;     // links with both ends in the block (the hops D_Lambda keeps)
     int64_t nbr_off;   // offset (entries) of this shape's table in the neighbour array
     int64_t perm_off;  // offset of the eo -> local canonical permutation
+    // A frame shape: the solve domain is the box minus the hole hio + [0, hie)
+    // (local coordinates); hole sites are decoupled (every hop into or out of
+    // the hole is dropped, so D acts as the identity there).
+    int hole = 0;
+    int hio[4] = {0, 0, 0, 0}, hie[4] = {0, 0, 0, 0};
     // Sites per parity of an x0-slice when the x0-walk of the hop applies to
     // the shape (the eo index of a site's x0-neighbour is its own index
     // +/- walk_hs in the other parity, hops along 1..3 stay in the slice, and
@@ -91,13 +97,12 @@ struct Shape {
 // Tile decomposition of the site kernels: a tile is one rhs group (g
 // consecutive rhs) on a chunk of chunk[b] consecutive eo sites of block b
 // (whole x0-slices when a slice has at most kTile sites per parity); tiles
-// are ordered block, chunk, group (group fastest).
+// are ordered block, chunk, group (group fastest), so tile t is rhs group
+// t % ng of the block's chunk number t / ng in the list of all chunks (ng =
+// n_rhs / g).  The chunk list is a property of the blocks (built once with
+// them); a tile table is only its size.
 struct TileTable {
     int ntiles = 0;
-    int32_t *d_tile_block = nullptr;  // tile -> block
-    int32_t *d_blk_tile0 = nullptr;   // block -> first tile (n_blocks + 1 entries)
-    int32_t *d_chunk = nullptr;       // sites per chunk of each block
-    std::vector<int32_t> blk_tile0;
 };
 
 // Work queues of the persistent solver: the (block, rhs) pairs split into nq
@@ -119,6 +124,7 @@ struct dd_blocks {
     int tbc = -1;
     int nb = 0;
     std::vector<int32_t> box;       // [nb][16] origin, extent, inner offset, inner extent
+    std::vector<uint8_t> hole;      // [nb] 1: the solve domain is the box minus the inner box (a frame)
     std::vector<int64_t> soff;      // [nb+1] site offsets
     std::vector<int32_t> shape_of;  // [nb]
     std::vector<dd::Shape> shapes;
@@ -142,10 +148,25 @@ struct dd_blocks {
     int32_t *d_ext = nullptr;       // [nb][4]
     int32_t *d_bnd = nullptr;       // [total bnd] box-local canonical index
     int64_t *d_boff = nullptr;      // [nb+1]
-    std::map<int, dd::TileTable> tiles;  // keyed by (n_rhs, rhs per thread)
+    // chunks of the site kernels' tiles (see TileTable), all blocks in order
+    std::vector<int32_t> blk_chunk0;     // [nb+1] first chunk of each block
+    int32_t *d_chunk = nullptr;          // [nb] sites per chunk of each block
+    int32_t *d_chunk_block = nullptr;    // [total chunks] chunk -> block
+    int32_t *d_blk_chunk0 = nullptr;     // [nb+1]
     std::map<int, dd::QueueTable> queues;  // keyed by (n_rhs, number of queues)
     bool walk = false;                     // every shape admits the x0-walk of the hop
-    mutable std::map<int, dd::TileTable> walks;  // x0-walk tiles (a cache), keyed by (n_rhs, segments)
+    // Exterior hops of the multi-boson source (blocks with an inner box that
+    // is not the whole block): each hop from a site of dPi outside a block's
+    // box into a box site, grouped by (block, receiving box-local site).
+    //   x_code: 2 mu + f (f = 1: the exterior site is x - mu), bit 3 the
+    //           antiperiodic time sign, bits 4-5 the part: 1 dPi_1, 2 dLambda_0
+    //   x_nbr:  global canonical index of the exterior site
+    //   x_link: 4 n + mu of the link in the canonical field (n its lower end)
+    std::vector<int32_t> xg_block, xg_site, xg_first;  // [ng], [ng], [ng + 1]
+    std::vector<int32_t> x_code;
+    std::vector<int64_t> x_nbr, x_link;
+    int32_t *d_xg_block = nullptr, *d_xg_site = nullptr, *d_xg_first = nullptr, *d_x_code = nullptr;
+    int64_t *d_x_nbr = nullptr, *d_x_link = nullptr;
 };
 
 struct dd_gauge {
@@ -156,6 +177,7 @@ struct dd_gauge {
     double *d_u64 = nullptr;     // [total_sites][4][18]
     float *d_u32 = nullptr;      // when low == DD_F32
     uint16_t *d_ubf = nullptr;   // when low == DD_BF16
+    double *d_uext = nullptr;    // [exterior hops][3][3][re, im]: the link of each exterior hop (FP64)
 };
 
 namespace dd {
@@ -164,8 +186,8 @@ namespace dd {
 
 // Per-block tables the site kernels read.
 struct BlkArgs {
-    const int32_t *tile_block;
-    const int32_t *blk_tile0;
+    const int32_t *chunk_block;  // chunk -> block (all chunks of all blocks)
+    const int32_t *blk_chunk0;   // [nb + 1] first chunk of each block
     const int32_t *h;
     const int64_t *soff;
     const int64_t *nbr_off;
@@ -177,14 +199,14 @@ struct BlkArgs {
     const int32_t *chunk;  // sites per chunk of each block
 };
 
-// Tiles of the x0-walk of the hop: tile (block, segment, rhs), rhs fastest,
-// walks the x0-slices of one of nseg equal segments of its block for one rhs.
+// Tiles of the x0-walk of the hop: tile (block, segment, rhs group), group
+// fastest, walks the x0-slices of one of nseg equal segments of its block for
+// one rhs group; every block has per = nseg * (n_rhs / g) tiles.
 struct WalkArgs {
-    const int32_t *tile_block;
-    const int32_t *blk_tile0;
     const int32_t *ext;  // [nb][4] block extents
     int ntiles;
     int nseg;
+    int per;
 };
 
 enum DotMode { kDotNone = 0, kDotAuxOut = 1, kDotOutSelfOutOut = 2, kDotOutOut = 3, kDotOutAuxOutOut = 4 };
@@ -400,5 +422,11 @@ hipError_t launch_sc_outer(const BlkArgs &ba, const double *pe, const double *po
                            double tol, const OuterState &os, hipStream_t s);
 hipError_t launch_mb_norm(const dd_blocks *B, int n_fields, const double *u, const double *chi,
                           const double *y, double *S, int accumulate, hipStream_t s);
+// The links of the exterior hops of B from the canonical field U into uext.
+hipError_t launch_gather_ext_links(const dd_blocks *B, const double *U, double *uext, hipStream_t s);
+// xi[f][block site] += -kappa * sum of the exterior hops (parts selected by
+// the bit mask) of chi[f][exterior site] into that site, for every field.
+hipError_t launch_mb_exterior(const dd_blocks *B, const double *uext, double kappa, int n_fields,
+                              const double *chi, double *xi, int parts, hipStream_t s);
 
 }  // namespace dd

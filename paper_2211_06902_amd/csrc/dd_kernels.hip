@@ -44,11 +44,11 @@ __device__ __forceinline__ Tile tile_of(const BlkArgs &ba)
 {
     Tile t;
     t.tile = uni(xcd_tile(blockIdx.x, ba.ntiles));
-    t.b = uni(ba.tile_block[t.tile]);
     const int ng = ba.n_rhs / ba.g;
-    const int rel = t.tile - uni(ba.blk_tile0[t.b]);
-    t.grp = rel % ng;
-    const int chunk = rel / ng;
+    const int cidx = t.tile / ng;
+    t.grp = t.tile - cidx * ng;
+    t.b = uni(ba.chunk_block[cidx]);
+    const int chunk = cidx - uni(ba.blk_chunk0[t.b]);
     t.hb = uni(ba.h[t.b]);
     const int T = uni(ba.chunk[t.b]);
     t.h0 = chunk * T;
@@ -358,9 +358,9 @@ k_hop_walk(BlkArgs ba, WalkArgs wa, HopArgs ha)
     __shared__ SP stage[24 * kTile * G];
     __shared__ double red[G][kTile];
     const int tile = uni(xcd_tile(blockIdx.x, wa.ntiles));
-    const int b = uni(wa.tile_block[tile]);
+    const int b = tile / wa.per;
     const int nr = ba.n_rhs, ng = nr / G;
-    const int rel = tile - uni(wa.blk_tile0[b]);
+    const int rel = tile - b * wa.per;
     const int grp = rel % ng, seg = rel / ng;
     WalkPos w;
     w.p = ha.parity;
@@ -432,7 +432,7 @@ k_hop_walk(BlkArgs ba, WalkArgs wa, HopArgs ha)
         // partial sums in the chunk tiles' slots: segment seg in chunk slot seg,
         // the block's remaining chunk slots zero
         constexpr int nred = dot_nred(DM);
-        const int t0 = uni(ba.blk_tile0[b]), nch = (uni(ba.blk_tile0[b + 1]) - t0) / ng;
+        const int c0 = uni(ba.blk_chunk0[b]), nch = uni(ba.blk_chunk0[b + 1]) - c0, t0 = c0 * ng;
         tile_sum<G>(red, dv, nred, ha.partial, t0 + seg * ng + grp);
         if (seg == 0)
             for (int i = threadIdx.x; i < (nch - wa.nseg) * G * nred; i += kTile) {
@@ -467,6 +467,7 @@ hipError_t launch_hop_walk(const BlkArgs &ba, const WalkArgs &wa, const HopArgs 
 {
     if (wa.ntiles <= 0) return hipSuccess;
     if (wa.nseg < 1 || ha.dot_mode < kDotNone || ha.dot_mode > kDotOutAuxOutOut) return hipErrorInvalidValue;
+    if (wa.per != wa.nseg * (ba.n_rhs / ba.g) || wa.ntiles != ba.nb * wa.per) return hipErrorInvalidValue;
     if (ha.pre < kPreNone || ha.pre > kPreS) return hipErrorInvalidValue;
     // the staging updates: no fused dots; kPreP rewrites its input in place,
     // which only one tile per site may read
@@ -507,9 +508,9 @@ __global__ void __launch_bounds__(kTile) k_dhat_walk(BlkArgs ba, WalkArgs wa, Ho
     __shared__ SP sb[24 * kTile];  // intermediate slice q-1
     __shared__ double red[1][kTile];
     const int tile = uni(xcd_tile(blockIdx.x, wa.ntiles));
-    const int b = uni(wa.tile_block[tile]);
     const int nr = ba.n_rhs;
-    const int r = tile - uni(wa.blk_tile0[b]);
+    const int b = tile / nr;
+    const int r = tile - b * nr;
     const int hb = uni(ba.h[b]);
     // a pair that stopped iterating: the whole workgroup leaves
     if (ha.skip_act && !ha.skip_act[r * ba.nb + b]) return;
@@ -569,7 +570,7 @@ __global__ void __launch_bounds__(kTile) k_dhat_walk(BlkArgs ba, WalkArgs wa, Ho
     if (DM != kDotNone) {
         constexpr int nred = dot_nred(DM);
         const int gb = ba.g, ngb = nr / gb;
-        const int t0 = uni(ba.blk_tile0[b]), nch = (uni(ba.blk_tile0[b + 1]) - t0) / ngb;
+        const int c0 = uni(ba.blk_chunk0[b]), nch = uni(ba.blk_chunk0[b + 1]) - c0, t0 = c0 * ngb;
         tile_sum<1>(red, dv, nred, ha.partial, (t0 + r / gb) * gb + r % gb);
         for (int i = threadIdx.x; i < (nch - 1) * nred; i += kTile) {
             const int ch = 1 + i / nred, kk = i % nred;
@@ -598,7 +599,7 @@ hipError_t launch_dhat_walk(const BlkArgs &ba, const WalkArgs &wa, const HopArgs
 {
     if (wa.ntiles <= 0) return hipSuccess;
     // one walk of a whole block per rhs; the output is the even parity
-    if (wa.nseg != 1 || ha.parity != 0 || ba.n_rhs % ba.g != 0 || wa.ntiles != ba.nb * ba.n_rhs)
+    if (wa.nseg != 1 || ha.parity != 0 || ba.n_rhs % ba.g != 0 || wa.ntiles != ba.nb * ba.n_rhs || wa.per != ba.n_rhs)
         return hipErrorInvalidValue;
     if (ha.pre != kPreNone && (!ha.pre_r || !ha.pre_v || !ha.pre_c0 || !ha.pre_act || (ha.pre == kPreP && !ha.pre_c1)))
         return hipErrorInvalidValue;
@@ -1191,9 +1192,8 @@ __device__ __forceinline__ void pair_sums(const BlkArgs &ba, const double *parti
 {
 #pragma unroll
     for (int k = 0; k < NK; k++) s[k] = 0;
-    const int t0 = ba.blk_tile0[b], t1 = ba.blk_tile0[b + 1];
     const int ng = ba.n_rhs / ba.g, grp = r / ba.g, j = r - grp * ba.g;
-    const int nchunk = (t1 - t0) / ng;
+    const int c0 = ba.blk_chunk0[b], nchunk = ba.blk_chunk0[b + 1] - c0, t0 = c0 * ng;
     for (int ch = lane; ch < nchunk; ch += 64) {
         const int t = t0 + ch * ng + grp;
 #pragma unroll
@@ -1413,6 +1413,84 @@ hipError_t launch_mb_norm(const dd_blocks *B, int n_fields, const double *u, con
     if (B->nb == 0) return hipSuccess;
     hipLaunchKernelGGL(k_mb_norm, dim3(B->nb), dim3(256), 0, s, B->nb, n_fields, u, chi, y, B->d_soff, B->d_boff,
                        B->d_bnd, (int64_t)B->soff[B->nb], (int64_t)B->boff[B->nb], S, accumulate);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------- multi-boson exterior source
+
+__global__ void __launch_bounds__(256) k_gather_ext_links(const double *U, const int64_t *xlink, double *uext,
+                                                           int64_t n)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n * 18) return;
+    const int64_t e = t / 18, k = t - e * 18;
+    uext[t] = U[xlink[e] * 18 + k];
+}
+
+hipError_t launch_gather_ext_links(const dd_blocks *B, const double *U, double *uext, hipStream_t s)
+{
+    const int64_t n = (int64_t)B->x_code.size();
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gather_ext_links, dim3((unsigned)((n * 18 + 255) / 256)), dim3(256), 0, s, U, B->d_x_link,
+                       uext, n);
+    return hipGetLastError();
+}
+
+// a field of the global lattice, read at one site: component c of the spinor
+struct SrcSite {
+    const double *p;
+    __device__ __forceinline__ void load(int comp, double (&v)[1]) const { v[0] = p[comp]; }
+};
+
+// One thread per (receiving site group, field): the hops of chi from the
+// group's exterior sites, -kappa (1 -/+ gamma_mu) W chi with W the link (or
+// its adjoint) of the hop, summed in FP64 and added to xi at the site.
+__global__ void __launch_bounds__(256) k_mb_exterior(const int32_t *gb, const int32_t *gs, const int32_t *gfirst,
+                                                      const int32_t *code, const int64_t *nbr, const double *uext,
+                                                      const int64_t *soff, const double *chi, double *xi, int ng, int nf,
+                                                      int64_t V, int64_t total, double kappa, int parts)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)ng * nf) return;
+    const int g = (int)(t % ng), f = (int)(t / ng);
+    double acc[1][24];
+#pragma unroll
+    for (int c = 0; c < 24; c++) acc[0][c] = 0;
+    for (int e = gfirst[g]; e < gfirst[g + 1]; e++) {
+        const int cd = code[e];
+        if (!((cd >> 4) & parts)) continue;
+        double u[18];
+        const double sg = (cd & 8) ? -1.0 : 1.0;
+#pragma unroll
+        for (int k = 0; k < 18; k++) u[k] = sg * uext[(int64_t)e * 18 + k];
+        const SrcSite src{chi + ((int64_t)f * V + nbr[e]) * 24};
+        switch (cd & 7) {
+        case 0: hop_term<0, true, double, double, 1>(acc, src, u); break;
+        case 1: hop_term<0, false, double, double, 1>(acc, src, u); break;
+        case 2: hop_term<1, true, double, double, 1>(acc, src, u); break;
+        case 3: hop_term<1, false, double, double, 1>(acc, src, u); break;
+        case 4: hop_term<2, true, double, double, 1>(acc, src, u); break;
+        case 5: hop_term<2, false, double, double, 1>(acc, src, u); break;
+        case 6: hop_term<3, true, double, double, 1>(acc, src, u); break;
+        default: hop_term<3, false, double, double, 1>(acc, src, u); break;
+        }
+    }
+    double *out = xi + ((int64_t)f * total + soff[gb[g]] + gs[g]) * 24;
+#pragma unroll
+    for (int c = 0; c < 24; c++) out[c] = fmad(-kappa, acc[0][c], out[c]);
+}
+
+hipError_t launch_mb_exterior(const dd_blocks *B, const double *uext, double kappa, int n_fields, const double *chi,
+                              double *xi, int parts, hipStream_t s)
+{
+    const int ng = (int)B->xg_block.size();
+    if (ng == 0 || n_fields == 0) return hipSuccess;
+    if (!uext) return hipErrorInvalidValue;
+    const int64_t V = (int64_t)B->L[0] * B->L[1] * B->L[2] * B->L[3];
+    const int64_t n = (int64_t)ng * n_fields;
+    hipLaunchKernelGGL(k_mb_exterior, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, B->d_xg_block, B->d_xg_site,
+                       B->d_xg_first, B->d_x_code, B->d_x_nbr, uext, B->d_soff, chi, xi, ng, n_fields, V,
+                       B->soff[B->nb], kappa, parts);
     return hipGetLastError();
 }
 

@@ -294,15 +294,13 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
     // differently; a scalar kernel reads partials with the tiling of the
     // kernel that wrote them
     const int g64 = hop_group(ctx, n_rhs, DD_F64, DD_F64), gsp = hop_group(ctx, n_rhs, sp, ip);
-    const TileTable *tt64 = tiles_for(ctx, B, n_rhs, g64, &e);
-    const TileTable *ttsp = tt64 ? tiles_for(ctx, B, n_rhs, gsp, &e) : nullptr;
-    if (!ttsp) return fail(ctx, DD_EDEVICE, std::string("tile tables: ") + hipGetErrorString(e));
+    const TileTable tt64 = tiles_for(B, n_rhs, g64), ttsp = tiles_for(B, n_rhs, gsp);
     const BlkArgs ba64 = blk_args(B, tt64, n_rhs, g64);
     const BlkArgs ba = blk_args(B, ttsp, n_rhs, gsp);
     const int np = n_rhs * B->nb;
     const int64_t hel = (B->soff[B->nb] / 2) * 24 * (int64_t)n_rhs;  // elements per half field
     const size_t h64 = (size_t)hel * 8, hsp = (size_t)hel * prec_bytes(sp);
-    const size_t npart = (size_t)std::max({tt64->ntiles * g64, ttsp->ntiles * gsp, 1}) * kNRed * sizeof(double);
+    const size_t npart = (size_t)std::max({tt64.ntiles * g64, ttsp.ntiles * gsp, 1}) * kNRed * sizeof(double);
 
     Ws w;
     std::memset(&w, 0, sizeof(w));
@@ -398,11 +396,8 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
              false, false, false};
     if (!gmres) {
         in.dhat = dhat_walk_applies(ctx, B, ba, ip);
-        if (in.dhat) HIPCHECK(ctx, dhat_walk_prepare(B, ba));
         if (!nn && ctx->bicg_fuse == 0) {
-            hipError_t we;
-            const int nseg = in.dhat ? 1 : hop_walk_segments(ctx, B, ba, ip, &we);
-            if (!in.dhat) HIPCHECK(ctx, we);
+            const int nseg = in.dhat ? 1 : hop_walk_segments(ctx, B, ba, ip);
             in.fuse_s = nseg >= 1;
             in.fuse_p = nseg == 1;
         }
@@ -762,6 +757,22 @@ dd_status dd_multiboson_action(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *
     HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
     if (st_all == DD_ENOCONV) ctx->err = "some (block, field) pairs missed the tolerance";
     return st_all;
+}
+
+dd_status dd_mb_exterior_source(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *G, double kappa, int32_t n_fields,
+                                const void *chi_global_dev, void *xi_dev, int32_t parts)
+{
+    if (!ctx || !B || !G || !chi_global_dev || !xi_dev) return fail(ctx, DD_EINVAL, "null argument");
+    if (G->blocks != B) return fail(ctx, DD_EINVAL, "gauge was loaded for other blocks");
+    if (n_fields < 1 || n_fields > kMaxRhs) return fail(ctx, DD_EINVAL, "n_fields must be in 1..64");
+    if (parts < 1 || parts > 3) return fail(ctx, DD_EINVAL, "parts must be 1 (dPi_1), 2 (dLambda_0) or 3 (both)");
+    HIPCHECK(ctx, enter(ctx));
+    if (!B->x_code.empty()) {
+        HIPCHECK(ctx, launch_mb_exterior(B, G->d_uext, kappa, n_fields, (const double *)chi_global_dev,
+                                         (double *)xi_dev, parts, ctx->stream));
+    }
+    HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+    return DD_OK;
 }
 
 dd_status dd_mb_roots(int32_t N, double c, double *u_host)

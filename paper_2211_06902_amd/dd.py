@@ -128,6 +128,7 @@ _sig("dd_make_blocks_boxes", _I32, [_P, _P, _I32, _I32, _P, _P, _PP])
 _sig("dd_free_blocks", _I32, [_P])
 _sig("dd_blocks_query", _I32, [_P, _P, _P, _P, _P])
 _sig("dd_blocks_tables", _I32, [_P, _P, _P, _P, _P])
+_sig("dd_blocks_exterior", _I32, [_P, _P, _P, _P, _P, _P])
 _sig("dd_load_gauge", _I32, [_P, _P, _P, _I32, _PP])
 _sig("dd_free_gauge", _I32, [_P])
 _sig("dd_gauge_export", _I32, [_P, _P, _I32, _P])
@@ -139,6 +140,7 @@ _sig("dd_multiboson_action", _I32, [_P, _P, _P, _D, _I32, _P, _P, _P, ctypes.POI
                                     ctypes.POINTER(SolveStats)])
 _sig("dd_tune_set", _I32, [_P, _I32, _I32])
 _sig("dd_mb_roots", _I32, [_I32, _D, _P])
+_sig("dd_mb_exterior_source", _I32, [_P, _P, _P, _D, _I32, _P, _P, _I32])
 _sig("dd_nn_num_weights", _I64, [])
 _sig("dd_nn_create", _I32, [_P, _P, _I32, _P, _PP])
 _sig("dd_nn_free", _I32, [_P])
@@ -307,6 +309,18 @@ class Blocks:
         bnd = np.zeros(max(self.total_bnd_sites, 1), dtype=np.int32)
         _lib.dd_blocks_tables(self._h, _ptr(boxes), _ptr(sites), _ptr(eo), _ptr(bnd))
         return boxes, sites, eo, bnd[: self.total_bnd_sites]
+
+    def exterior(self):
+        """Exterior hops of the multi-boson source: (block, site, code, nbr) arrays, one entry per hop."""
+        n = _I64()
+        _lib.dd_blocks_exterior(self._h, ctypes.byref(n), None, None, None, None)
+        blk = np.zeros(n.value, dtype=np.int32)
+        site = np.zeros(n.value, dtype=np.int32)
+        code = np.zeros(n.value, dtype=np.int32)
+        nbr = np.zeros(n.value, dtype=np.int64)
+        if n.value:
+            _lib.dd_blocks_exterior(self._h, ctypes.byref(n), _ptr(blk), _ptr(site), _ptr(code), _ptr(nbr))
+        return blk, site, code, nbr
 
     def close(self):
         if self._h:
@@ -487,6 +501,15 @@ class Context:
                 "flags": flags.reshape(nf, blocks.n_blocks), "seconds": stats.seconds,
                 "outer_cycles": stats.outer_cycles}
         return S_block, tot.value, info, st
+
+    def mb_exterior_source(self, blocks: Blocks, gauge: Gauge, kappa, chi_global, xi, parts=3):
+        """xi += the hops of chi_global [n_fields, V, 4, 3] from the sites of dPi outside each block's box
+        into the box (parts 1: dPi_1, 2: dLambda_0, 3: both); xi [n_fields, total_sites, 4, 3]."""
+        nf = chi_global.shape[0]
+        self._check(_lib.dd_mb_exterior_source(self._h, blocks._h, gauge._h, float(kappa), int(nf),
+                                               _dev(chi_global, "torch.complex128"), _dev(xi, "torch.complex128"),
+                                               int(parts)))
+        return xi
 
     # tuning
     def tune_set(self, what, value):

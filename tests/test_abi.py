@@ -174,3 +174,62 @@ def test_solve_params_defaults():
     assert p.inner_tol <= 0
     assert p.check_every == 2
     assert p.restart == 16
+
+
+def _oracle_exterior_hops(L, boxes, inner, tbc=-1):
+    """(block, box-local site, code, exterior site) of every hop into a box from a dPi site outside it,
+    from the oracle's sets (geometry.BoxDomains); code as in dd_blocks_exterior."""
+    B = geometry.BoxDomains(L, boxes, inner)
+    out = set()
+    for k, bx in enumerate(np.asarray(boxes).reshape(-1, 8)):
+        e = bx[4:8]
+        y = np.indices(e).reshape(4, -1).T
+        x = (y + bx[:4]) % np.asarray(L)
+        for mu in range(4):
+            if e[mu] == L[mu]:
+                continue
+            for f, step in enumerate((1, -1)):
+                yy = y[:, mu] + step
+                leave = (yy < 0) | (yy >= e[mu])
+                xn = x.copy()
+                xn[:, mu] = (xn[:, mu] + step) % L[mu]
+                n = ((xn[:, 0] * L[1] + xn[:, 1]) * L[2] + xn[:, 2]) * L[3] + xn[:, 3]
+                for s in np.nonzero(leave)[0]:
+                    part = 1 if B.dPi1[n[s]] else (2 if B.dlam0[n[s]] else 0)
+                    if not part:
+                        continue
+                    sign = tbc < 0 and mu == 0 and ((f == 0 and x[s, 0] == L[0] - 1) or (f == 1 and x[s, 0] == 0))
+                    out.add((k, int(s), (2 * mu + f) | (8 if sign else 0) | (part << 4), int(n[s])))
+    return out
+
+
+@pytest.mark.parametrize("case", ["paper_3d", "paper_4d_wrap", "tiles_inner"])
+def test_exterior_hops_match_oracle(case):
+    """The hop list of the multi-boson exterior source is bit-exact against the oracle's sets."""
+    from paper_2211_06902_amd import dd
+
+    if case == "paper_3d":
+        L, bd = (6, 6, 6, 4), [2, 1, 2, 1, 2, 1, 0, 0]
+        blk = dd.make_blocks_paper(None, L, -1, bd)
+    elif case == "paper_4d_wrap":
+        L, bd = (12, 12, 12, 12), [4, 2] * 4
+        blk = dd.make_blocks_paper(None, L, -1, bd)
+    else:
+        L = (8, 8, 8, 8)
+        blk = dd.make_blocks(None, L, -1, [[4, 4]] * 4, inner_d=1)
+    bx = blk.tables()[0]
+    b, s, c, n = blk.exterior()
+    got = set(zip(b.tolist(), s.tolist(), c.tolist(), n.tolist()))
+    assert len(got) == len(b)
+    exp = _oracle_exterior_hops(L, bx[:, :8], bx[:, 8:16])
+    assert got == exp
+    assert len(exp) > 0
+    # grouped by block and site, in increasing order
+    key = b.astype(np.int64) * (1 << 32) + s
+    assert np.all(np.diff(key) >= 0)
+    if case.startswith("paper"):
+        # the exterior boundary of a framed block lies on dPi: every exterior hop is listed
+        for k in range(blk.n_blocks):
+            e = bx[k, 4:8]
+            n_ext = sum(int(np.prod(e)) // e[m] * 2 for m in range(4) if e[m] < L[m])
+            assert np.sum(b == k) == n_ext

@@ -141,9 +141,9 @@ def test_hop_timer_accounts_bytes(ctx):
     ctx.timer_enable(False)
     assert n == 2 and ms > 0
     # two hops, each reading in + self and writing out (3 half fields), plus the block links
-    # (two stored rows: 12 reals per link)
+    # (a link counts as the full 3x3 matrix, 18 reals, whatever the storage keeps of it)
     V = 8**4
-    expect = 2 * (4 * (V / 2) * 24 * 4 * 3 + blk.inner_links * 12 * 4)
+    expect = 2 * (4 * (V / 2) * 24 * 4 * 3 + blk.inner_links * 18 * 4)
     assert abs(nbytes - expect) < 1e-6 * expect
 
 
