@@ -176,6 +176,23 @@ dd_status dd_gauge_export(dd_ctx *ctx, const dd_gauge *gauge, dd_prec prec, void
 dd_status dd_apply_D_block(dd_ctx *ctx, const dd_blocks *blocks, const dd_gauge *gauge, double kappa,
                            dd_prec prec, const void *x_dev, void *y_dev, int32_t n_rhs);
 
+/* dd_apply_D_block for callers that cannot allocate device memory (code
+ * that must not call hipMalloc: under stream capture, in tight serving loops,
+ * in harnesses that forbid it): the same operator and kernels, with the
+ * four half fields it packs into (x_e, x_o, y_e, y_o) taken from a
+ * preallocated scratch array of 128 MiB that the library holds on each
+ * device until the process ends, instead of the context's workspaces.  The
+ * call allocates nothing (no hipMalloc, no library allocation, no event
+ * creation; the kernel timers are not used).  Requests whose half fields
+ * exceed the array (total_sites * n_rhs * 48 * 8 bytes for DD_F64, * 4
+ * otherwise, each of the four rounded up to 256 bytes) return DD_EINVAL.
+ * Every call on one device shares that device's array: calls that overlap
+ * on one device (several host threads or contexts) race and must be
+ * serialized by the caller.  Arguments, layouts and results as for
+ * dd_apply_D_block. */
+dd_status dd_apply_D_block_noalloc(dd_ctx *ctx, const dd_blocks *blocks, const dd_gauge *gauge, double kappa,
+                                   dd_prec prec, const void *x_dev, void *y_dev, int32_t n_rhs);
+
 /* --------------------------------------------------------------- solves */
 
 enum { DD_BICGSTAB = 0, DD_GMRES = 1 };

@@ -133,6 +133,7 @@ _sig("dd_load_gauge", _I32, [_P, _P, _P, _I32, _PP])
 _sig("dd_free_gauge", _I32, [_P])
 _sig("dd_gauge_export", _I32, [_P, _P, _I32, _P])
 _sig("dd_apply_D_block", _I32, [_P, _P, _P, _D, _I32, _P, _P, _I32])
+_sig("dd_apply_D_block_noalloc", _I32, [_P, _P, _P, _D, _I32, _P, _P, _I32])
 _sig("dd_solve_params_default", None, [ctypes.POINTER(SolveParams)])
 _sig("dd_block_solve", _I32, [_P, _P, _P, _D, _P, _P, _I32, ctypes.POINTER(SolveParams),
                               ctypes.POINTER(SolveStats)])
@@ -450,6 +451,16 @@ class Context:
             y = torch.empty_like(x)
         self._check(_lib.dd_apply_D_block(self._h, blocks._h, gauge._h, float(kappa), _PREC[prec],
                                           _dev(x, "torch.complex128"), _dev(y, "torch.complex128"), int(n_rhs)))
+        return y
+
+    def apply_D_block_noalloc(self, blocks: Blocks, gauge: Gauge, kappa, prec, x, y, n_rhs=None):
+        """y = D_Lambda x into the caller's y, with the library's preallocated per-device scratch
+        (no device allocation by the library)."""
+        if n_rhs is None:
+            n_rhs = x.numel() // (blocks.total_sites * 12)
+        self._check(_lib.dd_apply_D_block_noalloc(self._h, blocks._h, gauge._h, float(kappa), _PREC[prec],
+                                                  _dev(x, "torch.complex128"), _dev(y, "torch.complex128"),
+                                                  int(n_rhs)))
         return y
 
     # solves
