@@ -90,6 +90,25 @@ def dirac_box(L, tbc, kappa, U, origin, extent, psi) -> np.ndarray:
     return out
 
 
+def frame_mask(extent, hole_off, hole_ext) -> np.ndarray:
+    """Box-local canonical mask of a frame: the box sites outside the hole (hole_off, hole_ext)."""
+    y = np.indices([int(v) for v in extent]).reshape(4, -1).T
+    ho, he = np.asarray(hole_off), np.asarray(hole_ext)
+    return ~np.all((y >= ho) & (y < ho + he), axis=1)
+
+
+def dirac_frame(L, tbc, kappa, U, origin, extent, hole_off, hole_ext, psi) -> np.ndarray:
+    """D_Phi psi for the frame Phi = box minus hole (Section 2's Phi_1^a = Omega_0^a minus
+    Lambda_0^a): the principal sub-matrix of D on Phi, i.e. D_box applied to psi restricted to
+    Phi, then restricted to Phi.  psi and the result are box-local canonical, zero on the hole."""
+    m = frame_mask(extent, hole_off, hole_ext)
+    p = np.array(_c128(psi), copy=True)
+    p[~m] = 0
+    out = dirac_box(L, tbc, kappa, U, origin, extent, p)
+    out[~m] = 0
+    return out
+
+
 def box_parity(L, origin, extent) -> np.ndarray:
     L4, o, e = _i4(L), _i4(origin), _i4(extent)
     S = int(np.prod(e))

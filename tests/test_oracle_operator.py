@@ -160,3 +160,25 @@ def test_hop_connects_opposite_parity(small_lattice):
     h = wilson.hop_box(L, -1, U, *box, psi)
     assert np.max(np.abs(h[par == 0])) == 0.0
     assert np.max(np.abs(h[par == 1])) > 0.0
+
+
+@pytest.mark.parametrize("frame", [
+    ((0, 0, 0, 0), (3, 3, 3, 2), (1, 1, 1, 0), (1, 1, 1, 2)),  # hole spans the box in direction 3
+    ((3, 2, 1, 1), (4, 3, 2, 2), (1, 0, 0, 0), (2, 2, 1, 1)),  # spans the time extent, wraps in 1
+])
+def test_frame_is_principal_submatrix(frame):
+    """D_Phi on a frame (box minus hole) is the full operator restricted to the frame's sites."""
+    L, kappa = (4, 4, 4, 2), 0.13
+    U = synth.gauge_field(L, 0.5, 17)
+    origin, extent, ho, he = frame
+    M = dense.dense_dirac_full(L, -1, kappa, U)
+    sites = geometry.box_sites(L, origin, extent)
+    m = wilson.frame_mask(extent, ho, he)
+    assert 0 < m.sum() < len(m)
+    rng = np.random.default_rng(3)
+    psi = rng.standard_normal((len(m), 4, 3)) + 1j * rng.standard_normal((len(m), 4, 3))
+    psi[~m] = 0
+    got = wilson.dirac_frame(L, -1, kappa, U, origin, extent, ho, he, psi)
+    ref = (dense.sub(M, sites[m]) @ psi[m].reshape(-1)).reshape(-1, 4, 3)
+    assert np.max(np.abs(got[m] - ref)) < 1e-13
+    assert np.all(got[~m] == 0)
