@@ -288,6 +288,8 @@ C5 = dict(L=(64, 64, 64, 64), kappa=0.1365, eps=0.2, nf=12, N=24, c=0.5, seed_u=
 def _mb_inputs(ctx, dd):
     """The 64^4 lattice's blocks, packed links and multi-boson fields, all drawn on the GPU; the
     canonical links are kept on the host for the oracle's sample."""
+    import torch
+
     import synth
 
     w = C5
@@ -297,6 +299,7 @@ def _mb_inputs(ctx, dd):
     g = ctx.load_gauge(blk, U, "f32")
     U_host = U.cpu().numpy()
     del U
+    torch.cuda.empty_cache()  # the library sizes its field groups by the free device memory
     chi = synth.spinor_field_device(w["nf"], blk.total_bnd_sites, w["seed_chi"])
     xi = synth.spinor_field_device(w["nf"], V, w["seed_xi"])
     u = dd.mb_roots(w["N"], w["c"])
@@ -456,6 +459,7 @@ def run_c5(args):
             "mean_inner_iterations_per_pair": float(res[-1][1]["iters"].mean()),
             "outer_cycles": int(res[-1][1]["outer_cycles"]),
             "graph_replay": not args.no_graph,
+            "fields_per_solve": int(res[-1][1]["rhs_per_solve"]),
             "input_generation_s": t_gen,
             "other_forms": forms,
         },

@@ -114,6 +114,19 @@ dd_status dd_make_blocks_paper(dd_ctx *ctx, const int32_t L[4], int32_t time_bc,
 dd_status dd_make_blocks_boxes(dd_ctx *ctx, const int32_t L[4], int32_t time_bc, int32_t n,
                                const int32_t *boxes, const int32_t *inner, dd_blocks **out);
 
+/* The frames Phi_1^a = Omega_0^a minus Lambda_0^a of Section 2 as solve
+ * domains (the D_{Phi_1^a} of Section 3's Dhat_{dLambda_0^a} and of eq. detD):
+ * one block per block of `blocks`, with the same box, whose inner box is a
+ * hole.  Every hop into or out of the hole is dropped, so on these blocks
+ * D_Lambda is D_{Phi_1^a} on the frame sites and the identity on the hole
+ * sites (dd_apply_D_block returns x there; dd_block_solve returns b there,
+ * so a source that is zero on the hole gives x = D_{Phi_1^a}^{-1} b on the
+ * frame and zero on the hole).  Layouts are those of blocks with the same
+ * boxes (hole sites included); the frames carry no dLambda_0 sites.
+ * DD_EINVAL when some inner box is its whole block.  ctx may be NULL as for
+ * the other constructors. */
+dd_status dd_make_frames(dd_ctx *ctx, const dd_blocks *blocks, dd_blocks **out);
+
 dd_status dd_free_blocks(dd_blocks *blocks);
 
 /* Sizes: number of blocks, total block sites (sum of box volumes), total
@@ -221,16 +234,27 @@ typedef struct {
                              (needs a DD_NN_LINEAR network) */
     int32_t precond_cycles; /* with precond: restart cycles between network applications
                                (<= 0: the network is applied once per inner solve) */
+    int32_t recover;     /* 1 (default): pairs that miss tol with a finite source after the
+                            low-precision or preconditioned solve (stalled inner solves,
+                            breakdowns, non-finite inner values) are solved again from x = 0
+                            with the library's default FP64 inner BiCGStab and iteration
+                            limits (same tol); their flags get bit 3.  0: off */
 } dd_solve_params;
 
 typedef struct {
     int32_t *iters;       /* [n_rhs*n_blocks] inner iterations per pair (host, caller-owned, may be NULL) */
     double *true_relres;  /* [n_rhs*n_blocks] final FP64 true relative residual (may be NULL) */
-    int32_t *flags;       /* [n_rhs*n_blocks] bit 0 converged, bit 1 breakdown seen, bit 2 non-finite (may be NULL) */
+    int32_t *flags;       /* [n_rhs*n_blocks] bit 0 converged, bit 1 breakdown seen, bit 2 non-finite,
+                             bit 3 solved again in FP64 (recover), bit 4 the network's output was not
+                             finite and the identity took its place (may be NULL) */
     double seconds;       /* wall time of the call */
     int32_t outer_cycles; /* defect-correction cycles run */
     int64_t inner_iterations; /* BiCGStab: inner iterations launched (summed over cycles);
                                  GMRES: largest per-pair total of Krylov steps */
+    int32_t rhs_per_solve;    /* right-hand sides per batched solve (dd_multiboson_action: the
+                                 fields it hands to one dd_block_solve; else n_rhs) */
+    int32_t resolved_pairs;   /* pairs that missed tol in the low-precision form and were solved
+                                 again with an FP64 inner solve (0 when none or not enabled) */
 } dd_solve_stats;
 
 /* Fill p with the defaults (tol 1e-10, BiCGStab, restart 16, FP32 inner). */
@@ -299,6 +323,20 @@ dd_status dd_multiboson_action(dd_ctx *ctx, const dd_blocks *blocks, const dd_ga
 dd_status dd_mb_exterior_source(dd_ctx *ctx, const dd_blocks *blocks, const dd_gauge *gauge, double kappa,
                                 int32_t n_fields, const void *chi_global_dev, void *xi_dev, int32_t parts);
 
+/* Per-block log-determinants (Section 3, eq. detD and the effective action
+ * after it: the block factors ln det D_{Omega_0^a} on framed blocks, and
+ * ln det D_{Phi_1^a} on the frames of dd_make_frames), in FP64:
+ *   logdet_dev[2 a] = ln |det D_Lambda^a|,  logdet_dev[2 a + 1] = its phase in (-pi, pi]
+ * (device, [n_blocks][2], may be NULL); total_host (may be NULL) [2]: the sum
+ * over blocks (phase wrapped).  det D_Lambda = det(1 - kappa^2 H_eo H_oe) on
+ * the even sites, assembled densely per block from the FP64 links and
+ * factorised by batched LU with partial pivoting.  Every block must have the
+ * same number h of sites per parity with 12 h <= 6144 (DD_EUNSUPPORTED
+ * otherwise); the dense matrices take 16 (12 h)^2 bytes per block (at most
+ * 8 GiB at a time). */
+dd_status dd_block_logdet(dd_ctx *ctx, const dd_blocks *blocks, const dd_gauge *gauge, double kappa,
+                          double *logdet_dev, double *total_host);
+
 /* ------------------------------------------------------------ tuning */
 
 /* Launch-shape overrides (0 = automatic).  DD_TUNE_RHS_GROUP_F64 / _F32: the
@@ -327,7 +365,11 @@ dd_status dd_mb_exterior_source(dd_ctx *ctx, const dd_blocks *blocks, const dd_g
  * x0-slice at a time), with FP32 spinors when every block admits the walk
  * and one walk per (block, rhs) covers the device: 0 (default) there, -1
  * never (two hop launches and the intermediate in global memory).  Results
- * do not depend on it beyond the summation order of the fused dot products. */
+ * do not depend on it beyond the summation order of the fused dot products.
+ * DD_TUNE_DHAT_RHS: right-hand sides one workgroup of that kernel walks in
+ * lockstep (sharing the block's link loads): 0 (default) three when n_rhs is
+ * a multiple of three and the blocks times n_rhs / 3 reach 1024, else one;
+ * 1 or 3 to force.  Results do not depend on it. */
 /* Schedule of the persistent GMRES solver (0 = default):
  * DD_TUNE_GMRES_THREADS  threads per workgroup, 256 or 512;
  * DD_TUNE_GMRES_QUEUES   work queues, 1 (one global queue) or 8 (one per XCD:
@@ -358,7 +400,8 @@ enum {
     DD_TUNE_HOP_WALK = 8,
     DD_TUNE_GMRES_REORTH = 9,
     DD_TUNE_BICG_FUSE = 10,
-    DD_TUNE_DHAT_WALK = 11
+    DD_TUNE_DHAT_WALK = 11,
+    DD_TUNE_DHAT_RHS = 12
 };
 dd_status dd_tune_set(dd_ctx *ctx, int32_t what, int32_t value);
 

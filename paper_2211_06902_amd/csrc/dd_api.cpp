@@ -199,6 +199,27 @@ hipError_t run_hop(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const Hop
     return launch_hop(ba, ha, prec, ctx->stream);
 }
 
+// D_Lambda as one walk over both parities (FP32 spinors; every block admits
+// the x0-walk; DD_TUNE_HOP_WALK automatic): otherwise two hop launches
+bool dlam_walk_applies(const dd_ctx *ctx, const dd_blocks *B, dd_prec prec)
+{
+    return (prec == DD_F32 || prec == DD_BF16) && B->walk && ctx->hop_lds && ctx->hop_walk == 0;
+}
+
+// Algorithmic bytes of D_Lambda on all blocks: the input and the output (24
+// reals per site and rhs each) and every link once (18 reals).
+double dlam_bytes(const dd_blocks *B, int nr, dd_prec prec)
+{
+    const double sf = prec == DD_F64 ? 8.0 : 4.0;
+    return nr * (double)B->soff[B->nb] * 48.0 * sf + (double)B->inner_links * kLinkAlgReals * (double)prec_bytes(prec);
+}
+
+int dhat_rhs_per_wg(const dd_ctx *ctx, const dd_blocks *B, int n_rhs)
+{
+    if (ctx->dhat_rhs == 1 || ctx->dhat_rhs == 3) return ctx->dhat_rhs;
+    return (n_rhs % 3 == 0 && (int64_t)B->nb * (n_rhs / 3) >= 1024) ? 3 : 1;
+}
+
 bool dhat_walk_applies(const dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, dd_prec prec)
 {
     if (!ctx->hop_lds || !B->walk || ctx->hop_walk < 0 || ctx->dhat_walk < 0) return false;
@@ -225,13 +246,15 @@ hipError_t run_dhat(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const Ho
         ha.bytes_site = bytes / ((double)ba.n_rhs * (double)(B->soff[B->nb] / 2));
     }
     TimedLaunch tl(ctx, kc, dev_count ? 0.0 : bytes);
-    int nseg = 1;
-    const TileTable wt = walk_for(B, ba.n_rhs, 1, 1, &nseg);
+    // rhs per workgroup: three (walked in lockstep, sharing the block's link
+    // loads) when n_rhs is a multiple of three and that still gives a few
+    // workgroups per compute unit, else one
+    const int nrw = dhat_rhs_per_wg(ctx, B, ba.n_rhs);
     WalkArgs wa;
     wa.ext = B->d_ext;
-    wa.ntiles = wt.ntiles;
-    wa.nseg = 1;
-    wa.per = ba.n_rhs;
+    wa.nseg = nrw;  // the Dhat walk is never segmented: nseg holds the rhs per workgroup
+    wa.per = (ba.n_rhs + nrw - 1) / nrw;
+    wa.ntiles = B->nb * wa.per;
     return launch_dhat_walk(ba, wa, ha, prec, ctx->stream);
 }
 
@@ -260,11 +283,31 @@ dd_status apply_D_with(dd_ctx *ctx, const dd_blocks *Bc, const void *links, doub
     const BlkArgs ba = blk_args(Bc, tiles_for(Bc, n_rhs, g), n_rhs, g);
     void *xe = hf[0], *xo = hf[1], *ye = hf[2], *yo = hf[3];
     HIPCHECK(ctx, launch_pack_spinor(Bc, (const double *)x_dev, xe, xo, sp, n_rhs, ctx->stream));
-    for (int p = 0; p < 2; p++) {
-        HopArgs ha = hop_args(p ? yo : ye, p ? xe : xo, links, p, -kappa);
-        ha.self = p ? xo : xe;
-        ha.c_self = 1.0;
-        HIPCHECK(ctx, run_hop(ctx, Bc, ba, ha, prec));
+    if (dlam_walk_applies(ctx, Bc, prec)) {
+        // one x0-walk per (block, rhs) over both parities; algorithmic bytes
+        // as for D_Lambda: x once, y once, the links once
+        DlamArgs da;
+        da.ext = Bc->d_ext;
+        da.ntiles = Bc->nb * n_rhs;
+        da.xe = xe;
+        da.xo = xo;
+        da.ye = ye;
+        da.yo = yo;
+        da.links = links;
+        da.c_hop = -kappa;
+        const double bytes = dlam_bytes(Bc, n_rhs, prec);
+        const bool dev = ctx->timing && ctx->d_timer_bytes;
+        da.bytes_acc = dev ? ctx->d_timer_bytes + DD_KCLASS_HOP_F64 + (int)prec : nullptr;
+        da.bytes_walk = bytes / da.ntiles;
+        TimedLaunch tl(ctx, DD_KCLASS_HOP_F64 + (int)prec, dev ? 0.0 : bytes);
+        HIPCHECK(ctx, launch_dlam_walk(blk_args(Bc, tiles_for(Bc, n_rhs, 1), n_rhs, 1), da, prec, ctx->stream));
+    } else {
+        for (int p = 0; p < 2; p++) {
+            HopArgs ha = hop_args(p ? yo : ye, p ? xe : xo, links, p, -kappa);
+            ha.self = p ? xo : xe;
+            ha.c_self = 1.0;
+            HIPCHECK(ctx, run_hop(ctx, Bc, ba, ha, prec));
+        }
     }
     HIPCHECK(ctx, launch_unpack_spinor(Bc, ye, yo, (double *)y_dev, sp, n_rhs, ctx->stream));
     HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
@@ -332,6 +375,7 @@ dd_status dd_destroy(dd_ctx *ctx)
             hipEventDestroy(e.first);
             hipEventDestroy(e.second);
         }
+    logdet_release(ctx);
     if (ctx->enter_ev) hipEventDestroy(ctx->enter_ev);
     hipStreamDestroy(ctx->stream);
     delete ctx;
@@ -407,7 +451,7 @@ dd_status finish_blocks(dd_ctx *ctx, dd_blocks *B, dd_blocks **out)
 }
 
 dd_status make_from_boxes(dd_ctx *ctx, const int32_t L[4], int32_t time_bc, int n, const int32_t *boxes,
-                          const int32_t *inner, dd_blocks **out)
+                          const int32_t *inner, dd_blocks **out, bool frames = false)
 {
     if (!L || !out || (n > 0 && !boxes)) return fail(ctx, DD_EINVAL, "null argument");
     *out = nullptr;
@@ -417,7 +461,7 @@ dd_status make_from_boxes(dd_ctx *ctx, const int32_t L[4], int32_t time_bc, int 
     B->ctx = ctx;
     B->device = ctx ? ctx->device : -1;
     int Li[4] = {L[0], L[1], L[2], L[3]};
-    const std::string msg = build_geometry(B, Li, time_bc, n, boxes, inner);
+    const std::string msg = build_geometry(B, Li, time_bc, n, boxes, inner, frames);
     if (!msg.empty()) {
         delete B;
         return fail(ctx, DD_EINVAL, msg);
@@ -515,6 +559,18 @@ dd_status dd_make_blocks_boxes(dd_ctx *ctx, const int32_t L[4], int32_t time_bc,
                                const int32_t *inner, dd_blocks **out)
 {
     return make_from_boxes(ctx, L, time_bc, n, boxes, inner, out);
+}
+
+dd_status dd_make_frames(dd_ctx *ctx, const dd_blocks *blocks, dd_blocks **out)
+{
+    if (!blocks || !out) return fail(ctx, DD_EINVAL, "null argument");
+    std::vector<int32_t> boxes, inner;
+    for (int k = 0; k < blocks->nb; k++) {
+        const int32_t *r = &blocks->box[16 * k];
+        boxes.insert(boxes.end(), r, r + 8);
+        inner.insert(inner.end(), r + 8, r + 16);
+    }
+    return make_from_boxes(ctx, blocks->L, blocks->tbc, blocks->nb, boxes.data(), inner.data(), out, true);
 }
 
 dd_status dd_free_blocks(dd_blocks *B)
@@ -689,6 +745,11 @@ dd_status dd_tune_set(dd_ctx *ctx, int32_t what, int32_t value)
     if (what == DD_TUNE_DHAT_WALK) {
         if (value != 0 && value != -1) return fail(ctx, DD_EINVAL, "Dhat walk must be 0 (where possible) or -1 (never)");
         ctx->dhat_walk = value;
+        return DD_OK;
+    }
+    if (what == DD_TUNE_DHAT_RHS) {
+        if (value != 0 && value != 1 && value != 3) return fail(ctx, DD_EINVAL, "Dhat rhs per workgroup must be 0, 1 or 3");
+        ctx->dhat_rhs = value;
         return DD_OK;
     }
     if (what == DD_TUNE_BICG_FUSE) {

@@ -29,7 +29,13 @@ int hop_walk_segments(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, dd_pre
 // it applies to these blocks, rhs and spinor/link precision, and its launch.
 bool dhat_walk_applies(const dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, dd_prec prec);
 hipError_t run_dhat(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const HopArgs &ha, dd_prec prec);
+bool dlam_walk_applies(const dd_ctx *ctx, const dd_blocks *B, dd_prec prec);
+double dlam_bytes(const dd_blocks *B, int nr, dd_prec prec);
+// rhs per workgroup of the one-kernel Dhat (1 or 3)
+int dhat_rhs_per_wg(const dd_ctx *ctx, const dd_blocks *B, int n_rhs);
 HopArgs hop_args(void *out, const void *in, const void *links, int parity, double c_hop);
+// releases the context's dense-LU library handle
+void logdet_release(dd_ctx *ctx);
 
 // y = D_Lambda x (dd_apply_D_block): argument checks (links of the precision),
 // the bytes of each of its four half fields, and the operator with the half

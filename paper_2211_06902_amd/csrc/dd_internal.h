@@ -51,6 +51,7 @@ struct dd_ctx {
     hipStream_t stream = nullptr;       // library stream (non-blocking, default priority)
     hipStream_t user_stream = nullptr;  // caller's stream; each call waits for it on entry
     hipEvent_t enter_ev = nullptr;      // recorded on user_stream by each call
+    void *blas = nullptr;               // rocBLAS handle of the dense LU (created on first use)
     std::string err;
     std::map<std::string, dd::DevBuf> ws;  // named, grow-only workspaces
     bool timing = false;
@@ -62,6 +63,7 @@ struct dd_ctx {
     int gm_reorth = 0;          // GMRES reorthogonalization threshold: 0 default, -1 never, 1..100 percent of |w|
     int bicg_fuse = 0;          // BiCGStab updates inside the walk hop: 0 where possible, -1 never
     int dhat_walk = 0;          // Dhat as one x0-walk kernel in BiCGStab: 0 where possible, -1 never
+    int dhat_rhs = 0;           // rhs per workgroup of that kernel: 0 automatic, 1 or 3
     int gm_threads = 0;         // persistent GMRES: threads per workgroup (0 = default)
     int gm_queues = 0;          // persistent GMRES: work queues, 1 or 8 (0 = default)
     int gm_wg_per_cu = 0;       // persistent GMRES: resident workgroups per CU (0 = all that fit)
@@ -268,6 +270,7 @@ struct OuterState {
     double *rr;         // [np] |b - D x|^2
     int32_t *active;    // [np] still above tolerance
     int32_t *flags;     // [np]
+    const int32_t *only;  // [np] or null: pairs with 0 take no part (inactive, x = 0)
 };
 
 // Arguments of the persistent GMRES kernel: every pair listed in the queues
@@ -392,6 +395,20 @@ hipError_t launch_hop_walk(const BlkArgs &ba, const WalkArgs &wa, const HopArgs 
 // Dhat = c_self self + c_hop H_eo H_oe in on the even sites (one segment per
 // block, ntiles = nb * n_rhs walk tiles); FP32 spinors with FP32 or BF16 links.
 hipError_t launch_dhat_walk(const BlkArgs &ba, const WalkArgs &wa, const HopArgs &ha, dd_prec prec, hipStream_t s);
+// D_Lambda on both parities in one x0-walk per (block, rhs), FP32 spinors:
+// y_p = x_p + c_hop (H x)_p for p = even, odd; x is read once from memory
+// (both parities of a slice staged in LDS), its self term again from cache.
+struct DlamArgs {
+    const int32_t *ext;  // [nb][4] block extents
+    int ntiles;          // n_blocks * n_rhs walks, rhs fastest
+    const void *xe, *xo;
+    void *ye, *yo;
+    const void *links;
+    double c_hop;
+    double *bytes_acc;  // with timing: += bytes_walk per walk done
+    double bytes_walk;
+};
+hipError_t launch_dlam_walk(const BlkArgs &ba, const DlamArgs &da, dd_prec prec, hipStream_t s);
 hipError_t launch_convert(const void *src, dd_prec sp, void *dst, dd_prec dp, int64_t n,
                           hipStream_t s);
 hipError_t launch_accum(const BlkArgs &ba, double *x, const void *e, dd_prec ep,
@@ -420,6 +437,14 @@ hipError_t launch_sc_omega(const BlkArgs &ba, const double *partial, const PairS
 hipError_t launch_sc_beta(const BlkArgs &ba, const double *partial, const PairState &ps, hipStream_t s);
 hipError_t launch_sc_outer(const BlkArgs &ba, const double *pe, const double *po, int first,
                            double tol, const OuterState &os, hipStream_t s);
+// dst = src on the pairs with mask set (both [n_rhs][total_sites][24] FP64).
+hipError_t launch_merge_pairs(const dd_blocks *B, const double *src, double *dst, const int32_t *mask, int n_rhs,
+                              hipStream_t s);
+// Network output guard: for every pair p of a half field (n_rhs rhs) with
+// active[p] set (active may be null), if z holds a non-finite value, z = v
+// (the identity) for that pair and flags[p] |= 16 (flags may be null).
+hipError_t launch_nn_guard(const dd_blocks *B, const void *v, void *z, dd_prec sp, int n_rhs, const int32_t *active,
+                           int32_t *flags, hipStream_t s);
 hipError_t launch_mb_norm(const dd_blocks *B, int n_fields, const double *u, const double *chi,
                           const double *y, double *S, int accumulate, hipStream_t s);
 // The links of the exterior hops of B from the canonical field U into uext.

@@ -497,27 +497,45 @@ hipError_t launch_hop_walk(const BlkArgs &ba, const WalkArgs &wa, const HopArgs 
 // second hop then takes that slice and finishes output slice q-2.  Both hops
 // are x0-walks of the same block (dd_stencil.h), the first over the odd
 // output sites, the second over the even ones.  One segment per block, one
-// rhs per thread (the two LDS slices of 24 x 256 reals keep three workgroups
-// on a compute unit).  Dot partials go to the chunk slots of the site
-// kernels' tile table (rhs group ba.g): slot 0 of the block holds the sum,
-// its other slots are zero.
-template <typename SP, typename LK, typename AC, int DM, int PRE>
-__global__ void __launch_bounds__(kTile) k_dhat_walk(BlkArgs ba, WalkArgs wa, HopArgs ha)
+// rhs per thread (the two LDS slices of 24 x 256 reals per rhs).
+// A workgroup walks NR rhs of one block (NR groups of kTile threads, each with
+// its own slices, in lockstep through the shared barriers): the groups load
+// the same links within one barrier interval, so a block's links come from
+// HBM about once per NR rhs instead of once per rhs.  NR = 3 keeps the same
+// three groups of kTile threads per compute unit as NR = 1 (144 KB of LDS).
+// Dot partials go to the chunk slots of the site kernels' tile table (rhs
+// group ba.g): slot 0 of the block holds the sum, its other slots are zero.
+template <typename SP, typename LK, typename AC, int DM, int PRE, int NR>
+__global__ void __launch_bounds__(kTile * NR) k_dhat_walk(BlkArgs ba, WalkArgs wa, HopArgs ha)
 {
-    __shared__ SP sa[24 * kTile];  // input slice q
-    __shared__ SP sb[24 * kTile];  // intermediate slice q-1
-    __shared__ double red[1][kTile];
+    __shared__ SP sa[NR][24 * kTile];  // input slice q
+    __shared__ SP sb[NR][24 * kTile];  // intermediate slice q-1
+    __shared__ double red[NR][kTile];
     const int tile = uni(xcd_tile(blockIdx.x, wa.ntiles));
+    const int b = tile / wa.per;
     const int nr = ba.n_rhs;
-    const int b = tile / nr;
-    const int r = tile - b * nr;
+    const int gi = NR == 1 ? 0 : uni((int)(threadIdx.x / kTile));  // rhs group of the wavefront
+    const int r = (tile - b * wa.per) * NR + gi;
     const int hb = uni(ba.h[b]);
-    // a pair that stopped iterating: the whole workgroup leaves
-    if (ha.skip_act && !ha.skip_act[r * ba.nb + b]) return;
-    if (ha.bytes_acc && threadIdx.x == 0) atomicAdd(ha.bytes_acc, ha.bytes_site * hb);
+    // a group whose rhs is past n_rhs or whose pair stopped iterating only
+    // takes part in the barriers; a workgroup with no such group leaves
+    bool alive = r < nr && (!ha.skip_act || ha.skip_act[r * ba.nb + b]);
+    if (NR > 1) {
+        bool any = false;
+#pragma unroll
+        for (int j = 0; j < NR; j++) {
+            const int rj = (tile - b * wa.per) * NR + j;
+            any = any || (rj < nr && (!ha.skip_act || ha.skip_act[rj * ba.nb + b]));
+        }
+        if (!any) return;
+    } else if (!alive) {
+        return;
+    }
+    const int k = (int)(threadIdx.x % kTile);
+    if (ha.bytes_acc && alive && k == 0) atomicAdd(ha.bytes_acc, ha.bytes_site * hb);
+    const int rr = alive ? r : 0;  // addresses of a group that does nothing stay in range
     const int ns = uni(wa.ext[4 * b]);
     const int hs = hb / ns;
-    const int k = threadIdx.x;
     const int32_t *nbt = ba.nbr + uni64(ba.nbr_off[b]);
     const WalkPos wodd{1, hb, hs, k, 0, ns, nbt + (int64_t)hb * 8};
     const WalkPos weven{0, hb, hs, k, 0, ns, nbt};
@@ -531,7 +549,7 @@ __global__ void __launch_bounds__(kTile) k_dhat_walk(BlkArgs ba, WalkArgs wa, Ho
     hc.other0 = 0;
     hc.cstr = (uint32_t)hb * (uint32_t)sizeof(SP);
     hc.kstr = (uint32_t)(4 * hb) * (uint32_t)sizeof(LK);
-    hc.grp_off = r * 24 * hb;
+    hc.grp_off = rr * 24 * hb;
     hc.in_b = make_buf(reinterpret_cast<const SP *>(ha.in) + hbase, fbytes);
     hc.lk_b = make_buf(reinterpret_cast<const LK *>(ha.links) + soff * kLinkReals,
                        (uint32_t)(2 * hb * kLinkReals) * (uint32_t)sizeof(LK));
@@ -542,7 +560,7 @@ __global__ void __launch_bounds__(kTile) k_dhat_walk(BlkArgs ba, WalkArgs wa, Ho
         pl.r_b = make_buf(reinterpret_cast<const SP *>(ha.pre_r) + hbase, fbytes);
         pl.v_b = make_buf(reinterpret_cast<const SP *>(ha.pre_v) + hbase, fbytes);
         pl.cstr = hc.cstr;
-        const int pr = r * ba.nb + b;
+        const int pr = rr * ba.nb + b;
         pl.act[0] = ha.pre_act[pr] != 0;
         const double c0r = ha.pre_c0[2 * pr], c0i = ha.pre_c0[2 * pr + 1];
         pl.c0r[0] = (SP)c0r;
@@ -566,24 +584,35 @@ __global__ void __launch_bounds__(kTile) k_dhat_walk(BlkArgs ba, WalkArgs wa, Ho
             pl(v, vo, true);
         }
     };
-    dhat_run<SP, LK, AC>(wodd, weven, ns, sa, sb, hc, ld, to_out);
+    dhat_run<SP, LK, AC>(wodd, weven, ns, sa[gi], sb[gi], hc, ld, to_out, alive);
     if (DM != kDotNone) {
+        // per-group fixed-order sums over the group's kTile threads
         constexpr int nred = dot_nred(DM);
         const int gb = ba.g, ngb = nr / gb;
         const int c0 = uni(ba.blk_chunk0[b]), nch = uni(ba.blk_chunk0[b + 1]) - c0, t0 = c0 * ngb;
-        tile_sum<1>(red, dv, nred, ha.partial, (t0 + r / gb) * gb + r % gb);
-        for (int i = threadIdx.x; i < (nch - 1) * nred; i += kTile) {
-            const int ch = 1 + i / nred, kk = i % nred;
-            ha.partial[((int64_t)(t0 + ch * ngb + r / gb) * gb + r % gb) * kNRed + kk] = 0;
+        for (int q = 0; q < nred; q++) {
+            red[gi][k] = dv[0][q];
+            __syncthreads();
+            for (int w = kTile / 2; w > 0; w >>= 1) {
+                if (k < w) red[gi][k] += red[gi][k + w];
+                __syncthreads();
+            }
+            if (alive && k == 0) ha.partial[((int64_t)(t0 + rr / gb) * gb + rr % gb) * kNRed + q] = red[gi][0];
+            __syncthreads();
         }
+        if (alive)
+            for (int i = k; i < (nch - 1) * nred; i += kTile) {
+                const int ch = 1 + i / nred, kk = i % nred;
+                ha.partial[((int64_t)(t0 + ch * ngb + rr / gb) * gb + rr % gb) * kNRed + kk] = 0;
+            }
     }
 }
 
-template <typename SP, typename LK, typename AC>
+template <typename SP, typename LK, typename AC, int NR>
 static hipError_t launch_dhat_t(const BlkArgs &ba, const WalkArgs &wa, const HopArgs &ha, hipStream_t s)
 {
-    dim3 g(wa.ntiles), t(kTile);
-#define DD_DHAT(DMV, PREV) hipLaunchKernelGGL((k_dhat_walk<SP, LK, AC, DMV, PREV>), g, t, 0, s, ba, wa, ha)
+    dim3 g(wa.ntiles), t(kTile * NR);
+#define DD_DHAT(DMV, PREV) hipLaunchKernelGGL((k_dhat_walk<SP, LK, AC, DMV, PREV, NR>), g, t, 0, s, ba, wa, ha)
     if (ha.pre == kPreP && ha.dot_mode == kDotAuxOut) DD_DHAT(kDotAuxOut, kPreP);
     else if (ha.pre == kPreS && ha.dot_mode == kDotOutSelfOutOut) DD_DHAT(kDotOutSelfOutOut, kPreS);
     else if (ha.pre == kPreNone && ha.dot_mode == kDotAuxOut) DD_DHAT(kDotAuxOut, kPreNone);
@@ -598,14 +627,116 @@ static hipError_t launch_dhat_t(const BlkArgs &ba, const WalkArgs &wa, const Hop
 hipError_t launch_dhat_walk(const BlkArgs &ba, const WalkArgs &wa, const HopArgs &ha, dd_prec prec, hipStream_t s)
 {
     if (wa.ntiles <= 0) return hipSuccess;
-    // one walk of a whole block per rhs; the output is the even parity
-    if (wa.nseg != 1 || ha.parity != 0 || ba.n_rhs % ba.g != 0 || wa.ntiles != ba.nb * ba.n_rhs || wa.per != ba.n_rhs)
+    // one walk of a whole block per rhs (wa.nseg rhs per workgroup: 1 or 3);
+    // the output is the even parity
+    const int nrw = wa.nseg;
+    if ((nrw != 1 && nrw != 3) || ha.parity != 0 || ba.n_rhs % ba.g != 0 || wa.per != (ba.n_rhs + nrw - 1) / nrw ||
+        wa.ntiles != ba.nb * wa.per)
         return hipErrorInvalidValue;
     if (ha.pre != kPreNone && (!ha.pre_r || !ha.pre_v || !ha.pre_c0 || !ha.pre_act || (ha.pre == kPreP && !ha.pre_c1)))
         return hipErrorInvalidValue;
-    if (prec == DD_F32) return launch_dhat_t<float, float, float>(ba, wa, ha, s);
-    if (prec == DD_BF16) return launch_dhat_t<float, uint16_t, float>(ba, wa, ha, s);
+    if (prec == DD_F32) return nrw == 3 ? launch_dhat_t<float, float, float, 3>(ba, wa, ha, s)
+                                         : launch_dhat_t<float, float, float, 1>(ba, wa, ha, s);
+    if (prec == DD_BF16) return nrw == 3 ? launch_dhat_t<float, uint16_t, float, 3>(ba, wa, ha, s)
+                                          : launch_dhat_t<float, uint16_t, float, 1>(ba, wa, ha, s);
     return hipErrorInvalidValue;
+}
+
+// D_Lambda in one x0-walk per (block, rhs): both parities of input slice q
+// are staged in LDS (2 x 24 x kTile reals); the even-output walk takes its
+// hops from the staged odd sites and the odd-output walk from the staged even
+// ones (walk_step of dd_stencil.h, as in the hop kernels), so x is read from
+// memory once; the epilogue's self term x_p comes back from the cache.
+template <typename SP, typename LK, typename AC>
+__global__ void __launch_bounds__(kTile) k_dlam_walk(BlkArgs ba, DlamArgs da)
+{
+    __shared__ SP stage[2][24 * kTile];
+    const int tile = uni(xcd_tile(blockIdx.x, da.ntiles));
+    const int nr = ba.n_rhs;
+    const int b = tile / nr, r = tile - b * nr;
+    const int hb = uni(ba.h[b]);
+    const int ns = uni(da.ext[4 * b]);
+    const int hs = hb / ns;
+    const int k = threadIdx.x;
+    const bool live = k < hs;
+    if (da.bytes_acc && k == 0) atomicAdd(da.bytes_acc, da.bytes_walk);
+    const int32_t *nbt = ba.nbr + uni64(ba.nbr_off[b]);
+    const WalkPos weven{0, hb, hs, k, 0, ns, nbt};
+    const WalkPos wodd{1, hb, hs, k, 0, ns, nbt + (int64_t)hb * 8};
+    const int64_t soff = uni64(ba.soff[b]);
+    const int64_t hbase = (soff >> 1) * 24 * nr;
+    const uint32_t fbytes = (uint32_t)(nr * 24 * hb) * (uint32_t)sizeof(SP);
+    HopCtx hc;
+    hc.h0 = 0;
+    hc.tv = 0;
+    hc.slot_self = 0;
+    hc.other0 = 0;
+    hc.cstr = (uint32_t)hb * (uint32_t)sizeof(SP);
+    hc.kstr = (uint32_t)(4 * hb) * (uint32_t)sizeof(LK);
+    hc.grp_off = r * 24 * hb;
+    hc.lk_b = make_buf(reinterpret_cast<const LK *>(da.links) + soff * kLinkReals,
+                       (uint32_t)(2 * hb * kLinkReals) * (uint32_t)sizeof(LK));
+    const Buf xe = make_buf(reinterpret_cast<const SP *>(da.xe) + hbase, fbytes);
+    const Buf xo = make_buf(reinterpret_cast<const SP *>(da.xo) + hbase, fbytes);
+    const Buf ye = make_buf(reinterpret_cast<const SP *>(da.ye) + hbase, fbytes);
+    const Buf yo = make_buf(reinterpret_cast<const SP *>(da.yo) + hbase, fbytes);
+    const AC ch = (AC)da.c_hop;
+    auto epi = [&](const Buf &xb, const Buf &yb, const AC (&acc)[1][24], int h) {
+        const uint32_t my = (uint32_t)(hc.grp_off + h) * (uint32_t)sizeof(SP);
+#pragma unroll
+        for (int half = 0; half < 2; half++) {
+            SP sx[12];
+#pragma unroll
+            for (int q = 0; q < 12; q++) sx[q] = bload<SP>(xb, my, (uint32_t)(12 * half + q) * hc.cstr);
+#pragma unroll
+            for (int q = 0; q < 12; q++)
+                bstore<SP>(yb, (SP)fmad(ch, acc[0][12 * half + q], (AC)sx[q]), my,
+                           (uint32_t)(12 * half + q) * hc.cstr);
+        }
+    };
+    auto epi_e = [&](const AC (&acc)[1][24], int h) { epi(xe, ye, acc, h); };
+    auto epi_o = [&](const AC (&acc)[1][24], int h) { epi(xo, yo, acc, h); };
+    AC acc0[1][24], car0[1][12], acc1[1][24], car1[1][12];
+#pragma unroll
+    for (int c = 0; c < 24; c++) acc0[0][c] = acc1[0][c] = 0;
+#pragma unroll
+    for (int c = 0; c < 12; c++) car0[0][c] = car1[0][c] = 0;
+    for (int q = 0; q < ns; q++) {
+        if (live) {
+            const uint32_t vo = (uint32_t)(hc.grp_off + q * hs + k) * (uint32_t)sizeof(SP);
+            SP v[24][1];
+#pragma unroll
+            for (int c = 0; c < 24; c++) v[c][0] = bload<SP>(xe, vo, (uint32_t)c * hc.cstr);
+            walk_stage<SP, 1>(stage[0], v, k);
+#pragma unroll
+            for (int c = 0; c < 24; c++) v[c][0] = bload<SP>(xo, vo, (uint32_t)c * hc.cstr);
+            walk_stage<SP, 1>(stage[1], v, k);
+        }
+        __syncthreads();
+        if (live) {
+            walk_step<SP, LK, AC, 1>(acc0, car0, q, weven, stage[1], hc, epi_e);
+            walk_step<SP, LK, AC, 1>(acc1, car1, q, wodd, stage[0], hc, epi_o);
+        }
+        __syncthreads();
+    }
+    if (live) {  // the last slice has no x0+ neighbour
+        epi_e(acc0, (ns - 1) * hs + k);
+        epi_o(acc1, (ns - 1) * hs + k);
+    }
+}
+
+hipError_t launch_dlam_walk(const BlkArgs &ba, const DlamArgs &da, dd_prec prec, hipStream_t s)
+{
+    if (da.ntiles <= 0) return hipSuccess;
+    if (da.ntiles != ba.nb * ba.n_rhs || !da.ext) return hipErrorInvalidValue;
+    dim3 g(da.ntiles), t(kTile);
+    if (prec == DD_F32)
+        hipLaunchKernelGGL((k_dlam_walk<float, float, float>), g, t, 0, s, ba, da);
+    else if (prec == DD_BF16)
+        hipLaunchKernelGGL((k_dlam_walk<float, uint16_t, float>), g, t, 0, s, ba, da);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- packing
@@ -1330,6 +1461,10 @@ __global__ void __launch_bounds__(256) k_sc_outer(BlkArgs ba, const double *pe, 
         os.flags[pair] = 0;
     }
     os.rr[pair] = rr;
+    if (os.only && !os.only[pair]) {  // not part of this solve
+        os.active[pair] = 0;
+        return;
+    }
     if (!finite(rr)) {
         os.flags[pair] |= 4;
         os.active[pair] = 0;
@@ -1369,6 +1504,66 @@ hipError_t launch_sc_outer(const BlkArgs &ba, const double *pe, const double *po
 {
     const int np = ba.n_rhs * ba.nb;
     hipLaunchKernelGGL(k_sc_outer, pair_grid(np), dim3(256), 0, s, ba, pe, po, first, tol * tol, os, np);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------- pair merge, network guard
+
+__global__ void __launch_bounds__(256) k_merge_pairs(const double *src, double *dst, const int32_t *mask,
+                                                      const int64_t *soff, int nb, int64_t total, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t site = i / 24, r = site / total, q = site - r * total;
+    const int b = find_block(soff, nb, q);
+    if (mask[r * nb + b]) dst[i] = src[i];
+}
+
+hipError_t launch_merge_pairs(const dd_blocks *B, const double *src, double *dst, const int32_t *mask, int n_rhs,
+                              hipStream_t s)
+{
+    const int64_t total = B->soff[B->nb], n = (int64_t)n_rhs * total * 24;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_merge_pairs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, src, dst, mask, B->d_soff,
+                       B->nb, total, n);
+    return hipGetLastError();
+}
+
+// One workgroup per pair: a non-finite value anywhere in the pair's z makes
+// z = v for the whole pair.  Nothing is cleared beforehand (the flag lives in
+// LDS), so the kernel can be replayed from a captured graph.
+template <typename SP>
+__global__ void __launch_bounds__(256) k_nn_guard(const SP *v, SP *z, const int64_t *soff, const int32_t *h, int nb,
+                                                   int n_rhs, const int32_t *active, int32_t *flags)
+{
+    __shared__ int bad;
+    const int pair = blockIdx.x, r = pair / nb, b = pair - r * nb;
+    if (active && !active[pair]) return;
+    const int hb = h[b];
+    const int64_t base = (soff[b] >> 1) * 24 * n_rhs + (int64_t)r * 24 * hb;
+    const int n = 24 * hb;
+    if (threadIdx.x == 0) bad = 0;
+    __syncthreads();
+    int mine = 0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) mine |= !isfinite(z[base + i]);
+    if (mine) bad = 1;
+    __syncthreads();
+    if (!bad) return;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) z[base + i] = v[base + i];
+    if (threadIdx.x == 0 && flags) flags[pair] |= 16;
+}
+
+hipError_t launch_nn_guard(const dd_blocks *B, const void *v, void *z, dd_prec sp, int n_rhs, const int32_t *active,
+                           int32_t *flags, hipStream_t s)
+{
+    const int np = n_rhs * B->nb;
+    if (np == 0) return hipSuccess;
+    if (sp == DD_F64)
+        hipLaunchKernelGGL(k_nn_guard<double>, dim3(np), dim3(256), 0, s, (const double *)v, (double *)z, B->d_soff,
+                           B->d_h, B->nb, n_rhs, active, flags);
+    else
+        hipLaunchKernelGGL(k_nn_guard<float>, dim3(np), dim3(256), 0, s, (const float *)v, (float *)z, B->d_soff,
+                           B->d_h, B->nb, n_rhs, active, flags);
     return hipGetLastError();
 }
 

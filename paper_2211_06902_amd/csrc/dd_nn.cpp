@@ -87,7 +87,7 @@ static bool nn_slice_fits(const dd_nn *nn)
 }
 
 hipError_t nn_apply_half(dd_ctx *ctx, dd_nn *nn, const dd_blocks *B, const void *v, void *z, int n_rhs, dd_prec sp,
-                         const int32_t *active)
+                         const int32_t *active, int32_t *flags)
 {
     const int S = nn->e.S;
     const int np = n_rhs * B->nb;
@@ -123,6 +123,8 @@ hipError_t nn_apply_half(dd_ctx *ctx, dd_nn *nn, const dd_blocks *B, const void 
         if (e == hipSuccess && !(bf && sp == DD_F32 && ctx->nn_kernel == 1 && nn_slice_fits(nn)))
             e = launch_half_rows(nullptr, O, z, sp, hr, 1, ctx->stream);
     }
+    // a pair whose network output is not finite falls back to the identity
+    if (e == hipSuccess) e = launch_nn_guard(B, v, z, sp, n_rhs, active, flags, ctx->stream);
     return e;
 }
 

@@ -36,9 +36,10 @@ hipError_t nn_forward(dd_ctx *ctx, const dd_nn *nn, const float *X, float *Z1, f
 // layout (inner precision sp); v and z may not alias.  Blocks must all have
 // the network's extent (checked by the caller).
 // With active (per pair, may be null) the BF16 network skips pairs whose flag is 0
-// and leaves their z unchanged.
+// and leaves their z unchanged.  A pair whose output is not finite gets z = v
+// (the identity) and, with flags given, flags[pair] |= 16.
 hipError_t nn_apply_half(dd_ctx *ctx, dd_nn *nn, const dd_blocks *B, const void *v, void *z, int n_rhs, dd_prec sp,
-                         const int32_t *active = nullptr);
+                         const int32_t *active = nullptr, int32_t *flags = nullptr);
 bool nn_fits(const dd_nn *nn, const dd_blocks *B);
 
 // the network in BF16 on the matrix cores: Xb [rows][32] BF16 -> O [rows][24] FP32.

@@ -89,7 +89,7 @@ hipError_t bicg_iteration(const Inner &in)
     hipStream_t st = in.ctx->stream;
     const void *pp = w.p, *ss = w.s;
     if (in.nn) {
-        if ((e = nn_apply_half(in.ctx, in.nn, in.B, w.p, in.ph, in.n_rhs, in.sp, w.ps.active)) != hipSuccess) return e;
+        if ((e = nn_apply_half(in.ctx, in.nn, in.B, w.p, in.ph, in.n_rhs, in.sp, w.ps.active, w.ps.flags)) != hipSuccess) return e;
         pp = in.ph;
     }
     // v = Dhat p; alpha = rho / <rh, v>
@@ -127,7 +127,7 @@ hipError_t bicg_iteration(const Inner &in)
     if ((e = launch_sc_alpha(in.ba, w.pA, w.ps, st)) != hipSuccess) return e;
     if (!in.fuse_s && (e = launch_bicg_s(in.ba, in.sp, w.r, w.v, w.s, w.ps, st)) != hipSuccess) return e;
     if (in.nn) {
-        if ((e = nn_apply_half(in.ctx, in.nn, in.B, w.s, in.sh, in.n_rhs, in.sp, w.ps.active)) != hipSuccess) return e;
+        if ((e = nn_apply_half(in.ctx, in.nn, in.B, w.s, in.sh, in.n_rhs, in.sp, w.ps.active, w.ps.flags)) != hipSuccess) return e;
         ss = in.sh;
     }
     // t = Dhat s; omega = <t, s> / <t, t>
@@ -253,10 +253,24 @@ void dd_solve_params_default(dd_solve_params *p)
     p->max_inner = 2000;
     p->check_every = 2;
     p->use_graph = 1;
+    p->recover = 1;
 }
 
-dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, double kappa, const void *b_dev,
-                         void *x_dev, int32_t n_rhs, const dd_solve_params *params, dd_solve_stats *stats)
+}  // extern "C"
+
+namespace {
+
+// Per-pair results of one batched solve (host copies).
+struct PairResults {
+    std::vector<int32_t> iters, flags;
+    std::vector<double> bb, rr;
+};
+
+// The batched solve of dd_block_solve.  With only (device, per pair, may be
+// null) the pairs whose entry is 0 take no part: they stay inactive with x = 0.
+dd_status block_solve_impl(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, double kappa, const void *b_dev,
+                           void *x_dev, int32_t n_rhs, const dd_solve_params *params, dd_solve_stats *stats,
+                           const int32_t *only, PairResults *res)
 {
     const auto t_start = std::chrono::steady_clock::now();
     if (!ctx || !Bc || !G || !b_dev || !x_dev) return fail(ctx, DD_EINVAL, "null argument");
@@ -383,6 +397,7 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
     w.os.active = pi + 3 * np;
     w.os.flags = pi + 4 * np;
     w.ps.np = np;
+    w.os.only = only;
 
     hipStream_t st = ctx->stream;
     HIPCHECK(ctx, hipMemsetAsync(pi, 0, (size_t)np * 5 * sizeof(int32_t), st));
@@ -496,7 +511,7 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
             if (nn) {
                 // flexible GMRES: first direction N(f) of the first cycle, then N(r) of every
                 // precond_cycles-th restart, the network applied to all pairs between launches
-                HIPCHECK(ctx, nn_apply_half(ctx, nn, B, w.rhs, gm_z0, n_rhs, sp));
+                HIPCHECK(ctx, nn_apply_half(ctx, nn, B, w.rhs, gm_z0, n_rhs, sp, nullptr, w.ps.flags));
                 ga.z0 = gm_z0;
                 ga.max_cycles = prm.precond_cycles > 0 ? prm.precond_cycles : 0;
                 ga.more = gm_more[0];
@@ -512,7 +527,7 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
                     int paused = 0;
                     for (int v : h_act) paused += v != 0;
                     if (paused == 0) break;
-                    HIPCHECK(ctx, nn_apply_half(ctx, nn, B, gm_r, gm_z0, n_rhs, sp));
+                    HIPCHECK(ctx, nn_apply_half(ctx, nn, B, gm_r, gm_z0, n_rhs, sp, nullptr, w.ps.flags));
                     ga.resume = 1;
                     ga.active = ga.more;
                     ga.more = ga.more == gm_more[0] ? gm_more[1] : gm_more[0];
@@ -537,7 +552,7 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
         HIPCHECK(ctx, launch_bicg_init(ba, sp, w.rhs, w.r, w.rh, in.fuse_p ? nullptr : w.p, w.xi, w.pA, w.os.active, st));
         HIPCHECK(ctx, launch_sc_init(ba, w.pA, w.ps, w.os, in.tol, prm.tol, adapt_tol ? 1 : 0, st));
         // the network's workspaces and BF16 weights exist before any capture
-        if (in.nn && !gx) HIPCHECK(ctx, nn_apply_half(ctx, in.nn, B, w.p, in.ph, n_rhs, sp));
+        if (in.nn && !gx) HIPCHECK(ctx, nn_apply_half(ctx, in.nn, B, w.p, in.ph, n_rhs, sp, w.ps.active, w.ps.flags));
         if (graph && !gx) {
             HIPCHECK(ctx, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
             hipError_t ce = hipSuccess;
@@ -600,10 +615,94 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, do
     if (stats) {
         stats->outer_cycles = cycles;
         stats->inner_iterations = inner_total;
+        stats->rhs_per_solve = n_rhs;
+        stats->resolved_pairs = 0;
         stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    }
+    if (res) {
+        res->iters = h_it;
+        res->bb = h_bb;
+        res->rr = h_rr;
+        res->flags.resize(np);
+        for (int k = 0; k < np; k++) res->flags[k] = (h_of[k] & 5) | (h_if[k] & 6) | (h_if[k] & 16);
     }
     if (status == DD_ENOCONV) ctx->err = "some (block, rhs) pairs missed the tolerance";
     return status;
+}
+
+}  // namespace
+
+extern "C" {
+
+dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *G, double kappa, const void *b_dev,
+                         void *x_dev, int32_t n_rhs, const dd_solve_params *params, dd_solve_stats *stats)
+{
+    const auto t_start = std::chrono::steady_clock::now();
+    dd_solve_params prm;
+    if (params) prm = *params;
+    else dd_solve_params_default(&prm);
+    PairResults res;
+    dd_solve_stats st1;
+    std::memset(&st1, 0, sizeof(st1));
+    dd_status st = block_solve_impl(ctx, B, G, kappa, b_dev, x_dev, n_rhs, &prm, &st1, nullptr, &res);
+    if (st != DD_OK && st != DD_ENOCONV) return st;
+    const int np = n_rhs * B->nb;
+    // recovery: the pairs that missed tol with a finite source (breakdown,
+    // a non-finite inner value, or a low-precision or preconditioned inner
+    // solve that stalled) are solved again with a plain FP64 inner solve
+    int n_re = 0;
+    std::vector<int32_t> mask(np, 0);
+    if (st == DD_ENOCONV && prm.recover && (prm.inner_prec != DD_F64 || prm.precond)) {
+        for (int k = 0; k < np; k++)
+            if (!(res.flags[k] & 1) && std::isfinite(res.bb[k])) {
+                mask[k] = 1;
+                n_re++;
+            }
+    }
+    PairResults res2;
+    dd_solve_stats st2;
+    std::memset(&st2, 0, sizeof(st2));
+    if (n_re > 0) {
+        hipError_t e = hipSuccess;
+        const size_t xbytes = (size_t)n_rhs * B->soff[B->nb] * 24 * sizeof(double);
+        void *x2 = workspace(ctx, "rs_x", xbytes, &e);
+        int32_t *dm = x2 ? (int32_t *)workspace(ctx, "rs_mask", (size_t)np * sizeof(int32_t), &e) : nullptr;
+        if (!dm) return fail(ctx, DD_ENOMEM, std::string("recovery workspace: ") + hipGetErrorString(e));
+        HIPCHECK(ctx, hipMemcpyAsync(dm, mask.data(), (size_t)np * sizeof(int32_t), hipMemcpyHostToDevice, ctx->stream));
+        // the same tolerance; the library's default FP64 inner solve and iteration limits
+        dd_solve_params p64;
+        dd_solve_params_default(&p64);
+        p64.tol = prm.tol;
+        p64.use_graph = prm.use_graph;
+        p64.inner_prec = DD_F64;
+        p64.recover = 0;
+        const dd_status s2 = block_solve_impl(ctx, B, G, kappa, b_dev, x2, n_rhs, &p64, &st2, dm, &res2);
+        if (s2 != DD_OK && s2 != DD_ENOCONV) return s2;
+        HIPCHECK(ctx, launch_merge_pairs(B, (const double *)x2, (double *)x_dev, dm, n_rhs, ctx->stream));
+        HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+    }
+    st = DD_OK;
+    for (int k = 0; k < np; k++) {
+        const bool re = mask[k] != 0;
+        const int fl = re ? (res2.flags[k] | 8) : res.flags[k];
+        const double bb = re ? res2.bb[k] : res.bb[k], rr = re ? res2.rr[k] : res.rr[k];
+        if (!(fl & 1)) st = DD_ENOCONV;
+        if (stats) {
+            if (stats->iters) stats->iters[k] = res.iters[k] + (re ? res2.iters[k] : 0);
+            if (stats->true_relres) stats->true_relres[k] = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+            if (stats->flags) stats->flags[k] = fl;
+        }
+    }
+    if (stats) {
+        stats->outer_cycles = st1.outer_cycles + st2.outer_cycles;
+        stats->inner_iterations = st1.inner_iterations + st2.inner_iterations;
+        stats->rhs_per_solve = n_rhs;
+        stats->resolved_pairs = n_re;
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+    }
+    if (st == DD_ENOCONV) ctx->err = "some (block, rhs) pairs missed the tolerance";
+    else ctx->err.clear();
+    return st;
 }
 
 dd_status dd_autotune_gmres(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *G, double kappa, const void *b_dev,
@@ -621,6 +720,7 @@ dd_status dd_autotune_gmres(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *G, 
     p.inner_tol = 1e-300;
     p.max_inner = p.restart;
     p.use_graph = 0;
+    p.recover = 0;  // the timed cycles are not meant to converge
     const bool timing0 = ctx->timing;
     const int nt0 = ctx->gm_threads, nq0 = ctx->gm_queues, w0 = ctx->gm_wg_per_cu;
     auto restore = [&]() {
@@ -719,7 +819,7 @@ dd_status dd_multiboson_action(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *
     const int64_t tb = B->boff[B->nb];
     dd_status st_all = DD_OK;
     double seconds = 0;
-    int32_t cycles = 0;
+    int32_t cycles = 0, resolved = 0;
     int64_t inner = 0;
     for (int f0 = 0; f0 < n_fields; f0 += fc) {
         const int nf = std::min(fc, n_fields - f0);
@@ -738,6 +838,7 @@ dd_status dd_multiboson_action(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *
         seconds += cs.seconds;
         cycles = std::max(cycles, cs.outer_cycles);
         inner += cs.inner_iterations;
+        resolved += cs.resolved_pairs;
         HIPCHECK(ctx, launch_mb_norm(B, nf, ud + 2 * f0, (const double *)chi_dev + (size_t)f0 * tb * 24, y, S,
                                      f0 > 0, ctx->stream));
     }
@@ -745,6 +846,8 @@ dd_status dd_multiboson_action(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *
         stats->seconds = seconds;
         stats->outer_cycles = cycles;
         stats->inner_iterations = inner;
+        stats->rhs_per_solve = fc;
+        stats->resolved_pairs = resolved;
     }
     if (S_total_host) {
         std::vector<double> hs(B->nb);

@@ -531,12 +531,14 @@ __device__ __forceinline__ void walk_run(const WalkPos &w, int ns, SP *stage, co
 // leaves LDS.  Two barriers per step: the second walk's reads of sb come
 // before the next writes of sb by the first barrier of the next step, and
 // the first walk's reads of sa before the next staging by the second.
+// With alive false the thread only takes part in the barriers (a workgroup
+// walking several rhs, one of which has nothing to do).
 template <typename SP, typename LK, typename AC, typename LD, typename EPI>
 __device__ __forceinline__ void dhat_run(const WalkPos &wodd, const WalkPos &weven, int ns, SP *sa, SP *sb,
-                                         const HopCtx &hc, LD &&ld, EPI &&epi)
+                                         const HopCtx &hc, LD &&ld, EPI &&epi, bool alive = true)
 {
     const int k = wodd.k, hs = wodd.hs;
-    const bool live = k < hs;
+    const bool live = alive && k < hs;
     AC acc1[1][24], car1[1][12], acc2[1][24], car2[1][12];
 #pragma unroll
     for (int c = 0; c < 24; c++) acc1[0][c] = acc2[0][c] = 0;

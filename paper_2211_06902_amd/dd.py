@@ -26,7 +26,7 @@ KCLASS_HOP_F64, KCLASS_HOP_F32, KCLASS_HOP_BF16, KCLASS_GMRES, KCLASS_NN_BF16 = 
 KCLASS_DHAT_F32, KCLASS_DHAT_BF16 = 5, 6
 TUNE_RHS_GROUP_F64, TUNE_RHS_GROUP_F32, TUNE_HOP_LDS = 0, 1, 2
 TUNE_GMRES_THREADS, TUNE_GMRES_QUEUES, TUNE_GMRES_WG_PER_CU, TUNE_MB_FIELDS, TUNE_NN_KERNEL = 3, 4, 5, 6, 7
-TUNE_HOP_WALK, TUNE_GMRES_REORTH, TUNE_BICG_FUSE, TUNE_DHAT_WALK = 8, 9, 10, 11
+TUNE_HOP_WALK, TUNE_GMRES_REORTH, TUNE_BICG_FUSE, TUNE_DHAT_WALK, TUNE_DHAT_RHS = 8, 9, 10, 11, 12
 _PREC = {"f64": F64, "f32": F32, "bf16": BF16, F64: F64, F32: F32, BF16: BF16}
 
 if not os.path.exists(LIB_PATH):
@@ -75,6 +75,7 @@ class SolveParams(ctypes.Structure):
         ("use_graph", _I32),
         ("precond", _P),
         ("precond_cycles", _I32),
+        ("recover", _I32),
     ]
 
 
@@ -86,6 +87,8 @@ class SolveStats(ctypes.Structure):
         ("seconds", _D),
         ("outer_cycles", _I32),
         ("inner_iterations", _I64),
+        ("rhs_per_solve", _I32),
+        ("resolved_pairs", _I32),
     ]
 
 
@@ -125,6 +128,7 @@ _sig("dd_last_error", ctypes.c_char_p, [_P])
 _sig("dd_make_blocks", _I32, [_P, _P, _I32, _P, _P, _P, _I32, _PP])
 _sig("dd_make_blocks_paper", _I32, [_P, _P, _I32, _P, _PP])
 _sig("dd_make_blocks_boxes", _I32, [_P, _P, _I32, _I32, _P, _P, _PP])
+_sig("dd_make_frames", _I32, [_P, _P, _PP])
 _sig("dd_free_blocks", _I32, [_P])
 _sig("dd_blocks_query", _I32, [_P, _P, _P, _P, _P])
 _sig("dd_blocks_tables", _I32, [_P, _P, _P, _P, _P])
@@ -141,6 +145,7 @@ _sig("dd_multiboson_action", _I32, [_P, _P, _P, _D, _I32, _P, _P, _P, ctypes.POI
                                     ctypes.POINTER(SolveStats)])
 _sig("dd_tune_set", _I32, [_P, _I32, _I32])
 _sig("dd_mb_roots", _I32, [_I32, _D, _P])
+_sig("dd_block_logdet", _I32, [_P, _P, _P, _D, _P, _P])
 _sig("dd_mb_exterior_source", _I32, [_P, _P, _P, _D, _I32, _P, _P, _I32])
 _sig("dd_nn_num_weights", _I64, [])
 _sig("dd_nn_create", _I32, [_P, _P, _I32, _P, _PP])
@@ -356,6 +361,11 @@ def make_blocks_paper(ctx, L, time_bc, bd) -> Blocks:
     return _make(_lib.dd_make_blocks_paper, ctx, _ptr(_i32(L)), int(time_bc), _ptr(_i32(bd)))
 
 
+def make_frames(ctx, blocks) -> Blocks:
+    """The frames (box minus inner box) of `blocks` as solve domains."""
+    return _make(_lib.dd_make_frames, ctx, blocks._h)
+
+
 def make_blocks_boxes(ctx, L, time_bc, boxes, inner=None) -> Blocks:
     b = _i32(boxes)
     inn = _i32(inner) if inner is not None else None
@@ -434,6 +444,9 @@ class Context:
     def make_blocks_boxes(self, L, time_bc, boxes, inner=None) -> Blocks:
         return make_blocks_boxes(self, L, time_bc, boxes, inner)
 
+    def make_frames(self, blocks) -> Blocks:
+        return make_frames(self, blocks)
+
     # gauge
     def load_gauge(self, blocks: Blocks, U, low_prec="f32") -> Gauge:
         out = _P()
@@ -478,13 +491,14 @@ class Context:
         iters = np.zeros(np_, dtype=np.int32)
         rel = np.zeros(np_, dtype=np.float64)
         flags = np.zeros(np_, dtype=np.int32)
-        stats = SolveStats(_ptr(iters), _ptr(rel), _ptr(flags), 0.0, 0, 0)
+        stats = SolveStats(_ptr(iters), _ptr(rel), _ptr(flags), 0.0, 0, 0, 0, 0)
         st = self._check(_lib.dd_block_solve(self._h, blocks._h, gauge._h, float(kappa), _dev(b, "torch.complex128"),
                                              _dev(x, "torch.complex128"), int(n_rhs), ctypes.byref(params),
                                              ctypes.byref(stats)), allow=(DD_ENOCONV,))
         info = {"iters": iters.reshape(n_rhs, blocks.n_blocks), "true_relres": rel.reshape(n_rhs, blocks.n_blocks),
                 "flags": flags.reshape(n_rhs, blocks.n_blocks), "seconds": stats.seconds,
-                "outer_cycles": stats.outer_cycles, "inner_iterations": stats.inner_iterations}
+                "outer_cycles": stats.outer_cycles, "inner_iterations": stats.inner_iterations,
+                "rhs_per_solve": stats.rhs_per_solve, "resolved_pairs": stats.resolved_pairs}
         return x, info, st
 
     def multiboson_action(self, blocks: Blocks, gauge: Gauge, kappa, u, chi, xi, params=None, S_block=None):
@@ -502,7 +516,7 @@ class Context:
         iters = np.zeros(np_, dtype=np.int32)
         rel = np.zeros(np_, dtype=np.float64)
         flags = np.zeros(np_, dtype=np.int32)
-        stats = SolveStats(_ptr(iters), _ptr(rel), _ptr(flags), 0.0, 0, 0)
+        stats = SolveStats(_ptr(iters), _ptr(rel), _ptr(flags), 0.0, 0, 0, 0, 0)
         tot = _D()
         st = self._check(_lib.dd_multiboson_action(self._h, blocks._h, gauge._h, float(kappa), int(nf), _ptr(uu),
                                                    _dev(chi, "torch.complex128"), _dev(xi, "torch.complex128"),
@@ -510,8 +524,19 @@ class Context:
                                                    ctypes.byref(tot), ctypes.byref(stats)), allow=(DD_ENOCONV,))
         info = {"iters": iters.reshape(nf, blocks.n_blocks), "true_relres": rel.reshape(nf, blocks.n_blocks),
                 "flags": flags.reshape(nf, blocks.n_blocks), "seconds": stats.seconds,
-                "outer_cycles": stats.outer_cycles}
+                "outer_cycles": stats.outer_cycles, "rhs_per_solve": stats.rhs_per_solve,
+                "resolved_pairs": stats.resolved_pairs}
         return S_block, tot.value, info, st
+
+    def block_logdet(self, blocks: Blocks, gauge: Gauge, kappa):
+        """Per-block ln det D_Lambda (FP64): (numpy [n_blocks] complex ln|det| + i phase, total)."""
+        import torch
+
+        out = torch.empty((blocks.n_blocks, 2), dtype=torch.float64, device="cuda")
+        tot = (ctypes.c_double * 2)()
+        self._check(_lib.dd_block_logdet(self._h, blocks._h, gauge._h, float(kappa), _dev(out, "torch.float64"), tot))
+        o = out.cpu().numpy()
+        return o[:, 0] + 1j * o[:, 1], complex(tot[0], tot[1])
 
     def mb_exterior_source(self, blocks: Blocks, gauge: Gauge, kappa, chi_global, xi, parts=3):
         """xi += the hops of chi_global [n_fields, V, 4, 3] from the sites of dPi outside each block's box

@@ -65,6 +65,9 @@ def main():
     ap.add_argument("--command", required=True)
     ap.add_argument("--title", default="")
     ap.add_argument("--source", nargs="*", help="kernel source files to hash (default: the hop's)")
+    ap.add_argument("--trace-skip", type=int, default=0,
+                    help="average the kernel's durations from the kernel trace, leaving out its first N dispatches "
+                         "(a warm-up evaluation whose first touches of fresh workspaces run slower)")
     args = ap.parse_args()
 
     stats = list(csv.DictReader(open(_one(args.stats, "*kernel_stats.csv"))))
@@ -74,6 +77,16 @@ def main():
     calls = sum(int(r["Calls"]) for r in mine)
     total_ns = sum(float(r["TotalDurationNs"]) for r in mine)
     avg_us = total_ns / calls / 1e3
+    skip_note = ""
+    if args.trace_skip:
+        tr = [r for r in csv.DictReader(open(_one(args.stats, "*kernel_trace.csv"))) if args.kernel in r["Kernel_Name"]]
+        tr.sort(key=lambda r: int(r["Start_Timestamp"]))
+        kept = tr[args.trace_skip:]
+        all_avg = avg_us
+        calls = len(kept)
+        avg_us = sum(int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in kept) / calls / 1e3
+        skip_note = ("Average over the %d dispatches after the first %d of the trace (warm-up); over all %d: %.1f us."
+                     % (calls, args.trace_skip, len(tr), all_avg))
 
     summary = {
         "kernel": args.kernel,
@@ -120,6 +133,8 @@ def main():
         calib = ("Calibration: a 1 GiB device copy reads FETCH_SIZE = %.0f KiB and WRITE_SIZE = %.0f KiB per copy."
                  % (big_f, big_w))
     rows.append("| kernel source sha256[:16] | %s |" % summary["kernel_source_sha256_16"])
+    if skip_note:
+        summary["trace_skip"] = args.trace_skip
     top = sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:12]
     lines = [
         "# %s" % (args.title or "rocprofv3 summary: " + args.kernel),
@@ -134,7 +149,7 @@ def main():
         "",
         "| quantity | value |",
         "|---|---|",
-    ] + rows + ["", calib, "",
+    ] + rows + ["", skip_note, "", calib, "",
                 "## Kernel time (all kernels of the run, top 12)",
                 "",
                 "| kernel | calls | total ms | avg us | % |",

@@ -233,3 +233,41 @@ def test_exterior_hops_match_oracle(case):
             e = bx[k, 4:8]
             n_ext = sum(int(np.prod(e)) // e[m] * 2 for m in range(4) if e[m] < L[m])
             assert np.sum(b == k) == n_ext
+
+
+@pytest.mark.parametrize("case", ["paper_3d", "paper_4d"])
+def test_frame_tables(case):
+    """Frames (box minus inner box): same boxes and layout as their blocks, no dLambda_0 sites, no
+    exterior hops, and exactly the links with both ends in the frame kept."""
+    from paper_2211_06902_amd import dd
+
+    if case == "paper_3d":
+        L, bd = (6, 6, 6, 4), [2, 1, 2, 1, 2, 1, 0, 0]
+    else:
+        L, bd = (12, 12, 12, 12), [4, 2] * 4
+    blk = dd.make_blocks_paper(None, L, -1, bd)
+    fr = dd.make_frames(None, blk)
+    bx, sites, eo, _ = blk.tables()
+    fbx, fsites, feo, _ = fr.tables()
+    assert np.array_equal(bx, fbx) and np.array_equal(sites, fsites) and np.array_equal(eo, feo)
+    assert fr.total_sites == blk.total_sites and fr.total_bnd_sites == 0
+    assert len(fr.exterior()[0]) == 0
+    links = 0
+    for b in bx:
+        e = b[4:8]
+        m = np.zeros(tuple(e), dtype=bool)
+        m[...] = True
+        ho, he = b[8:12], b[12:16]
+        m[ho[0]:ho[0] + he[0], ho[1]:ho[1] + he[1], ho[2]:ho[2] + he[2], ho[3]:ho[3] + he[3]] = False
+        for mu in range(4):
+            if e[mu] == L[mu]:
+                links += int(np.sum(m & np.roll(m, -1, axis=mu)))
+            else:
+                sl = [slice(None)] * 4
+                sl2 = [slice(None)] * 4
+                sl[mu] = slice(0, e[mu] - 1)
+                sl2[mu] = slice(1, e[mu])
+                links += int(np.sum(m[tuple(sl)] & m[tuple(sl2)]))
+    assert fr.inner_links == links
+    with pytest.raises(dd.DDError):
+        dd.make_frames(None, dd.make_blocks(None, (8, 8, 8, 8), -1, [[4, 4]] * 4))

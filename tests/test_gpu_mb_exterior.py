@@ -56,7 +56,8 @@ def test_exterior_source_matches_oracle(ctx, case):
     for parts, name in ((1, "dPi1"), (2, "dLam0"), (3, "all")):
         xi = ctx.mb_exterior_source(blk, g, kappa, chi_d, _dev(xi0), parts=parts).cpu().numpy()
         ref = mb.exterior_source(L, -1, kappa, U, bx[:, :8], bx[:, 8:16], chi, name)
-        assert np.abs(ref).max() > 0
+        # tiles with inner boxes do not overlap: no other block's dLambda_0 is outside a box
+        assert np.abs(ref).max() > 0 or (case == "tiles_inner" and name == "dLam0")
         err = np.abs((xi - xi0) - ref).max()
         assert err <= 1e-13 * np.abs(ref).max(), (parts, err)
     g.close()

@@ -113,14 +113,54 @@ def test_zero_and_nan_sources_are_isolated(ctx, c1):
 
 
 def test_max_outer_one_reports_noconv(ctx, c1):
+    """With the FP64 recovery off, pairs that miss tol are reported, not hidden."""
     from paper_2211_06902_amd import dd
 
     g = ctx.load_gauge(c1["blk"], _dev(c1["U"]), "bf16")
     x, info, st = ctx.block_solve(c1["blk"], g, c1["kappa"], _dev(c1["b"][:2]),
-                                  params=dd.solve_params(inner_prec="bf16", max_outer=1))
+                                  params=dd.solve_params(inner_prec="bf16", max_outer=1, recover=0))
     assert st == dd.DD_ENOCONV
     assert np.all(info["true_relres"] > TOL) and np.all(info["true_relres"] < 1e-1)
-    assert info["outer_cycles"] == 1
+    assert info["outer_cycles"] == 1 and info["resolved_pairs"] == 0
+    g.close()
+
+
+@pytest.mark.parametrize("method", ["bicgstab", "gmres"])
+def test_recovery_solves_missed_pairs_again_in_fp64(ctx, c1, method):
+    """Pairs that a BF16-link inner solve leaves above tol (one defect-correction cycle of one
+    iteration) are solved again with a plain FP64 inner solve: every pair converges, the re-solved
+    ones are flagged (bit 3) and agree with the dense-LU solution."""
+    from paper_2211_06902_amd import dd
+
+    g = ctx.load_gauge(c1["blk"], _dev(c1["U"]), "bf16")
+    prm = dd.solve_params(inner_prec="bf16", max_outer=1, max_inner=1,
+                          method=dd.GMRES if method == "gmres" else dd.BICGSTAB, restart=4)
+    x, info, st = ctx.block_solve(c1["blk"], g, c1["kappa"], _dev(c1["b"][:3]), params=prm)
+    assert st == dd.DD_OK
+    assert np.all(info["true_relres"] <= TOL)
+    npairs = info["flags"].size
+    assert info["resolved_pairs"] == npairs and np.all(info["flags"] & 8) and np.all(info["flags"] & 1)
+    assert _cfg.rel_err(x.cpu().numpy(), c1["x_lu"][:3]) <= 1e-9
+    g.close()
+
+
+@pytest.mark.parametrize("method", ["bicgstab", "gmres"])
+def test_nonfinite_network_output_falls_back_to_identity(ctx, c1, method):
+    """A network whose output is not finite (NaN weights) is replaced by the identity pair by pair
+    (flag bit 4): the preconditioned solves still reach tol, without a re-solve."""
+    from paper_2211_06902_amd import dd
+
+    g = ctx.load_gauge(c1["blk"], _dev(c1["U"]), "f32")
+    w = np.full(dd.nn_num_weights(), np.nan, dtype=np.float32)
+    net = ctx.nn_create((2, 2, 2, 2), w)
+    prm = dd.solve_params(inner_prec="f32", precond=net,
+                          method=dd.GMRES if method == "gmres" else dd.BICGSTAB, restart=8, precond_cycles=1)
+    x, info, st = ctx.block_solve(c1["blk"], g, c1["kappa"], _dev(c1["b"][:3]), params=prm)
+    assert st == dd.DD_OK and info["resolved_pairs"] == 0
+    assert np.all(info["true_relres"] <= TOL)
+    assert np.all(info["flags"] & 16)
+    assert _cfg.rel_err(x.cpu().numpy(), c1["x_lu"][:3]) <= 1e-9
+    net.close()
     g.close()
 
 
@@ -299,4 +339,49 @@ def test_bicg_fused_updates_isolate_zero_and_nan_sources(ctx):
                 continue
             sl = slice(off[k], off[k + 1])
             assert _true_relres(L, kappa, U, bx, x[r, sl], b[r, sl]) <= TOL, (r, k)
+    g.close()
+
+
+@pytest.mark.parametrize("inner", ["f32", "bf16"])
+def test_dhat_walk_three_rhs_per_workgroup(ctx, inner):
+    """The one-kernel Dhat with three rhs walked in lockstep per workgroup gives the same solve as
+    one rhs per workgroup, bit for bit (same arithmetic per pair, same fixed-order sums): ragged x0
+    extents, 4 rhs (the second workgroup of a block holds one rhs and two idle groups), a zero source
+    (never active) and a NaN source (stopped once flagged) beside pairs that converge."""
+    from paper_2211_06902_amd import dd
+
+    L = (16, 8, 8, 8)
+    segs = [[6, 10], [8], [4, 4], [8]]
+    kappa = 0.13
+    U = synth.gauge_field(L, 0.4, 37)
+    boxes = geometry.tile_boxes(L, segs)
+    sites = _cfg.block_sites(L, boxes)
+    off = _cfg.site_offsets(boxes)
+    b = synth.spinor_field(L, 4, 38)[:, sites]
+    b[3, off[1]:off[2]] = 0.0
+    b[1, off[2] + 5, 0, 1] = np.nan
+    blk = ctx.make_blocks(L, -1, segs)
+    g = ctx.load_gauge(blk, _dev(U), "bf16" if inner == "bf16" else "f32")
+    out = []
+    try:
+        ctx.tune_set(dd.TUNE_HOP_WALK, 1)
+        for nrw in (1, 3):
+            ctx.tune_set(dd.TUNE_DHAT_RHS, nrw)
+            x, info, st = ctx.block_solve(blk, g, kappa, _dev(b), params=dd.solve_params(inner_prec=inner))
+            assert st == dd.DD_ENOCONV
+            out.append((x.cpu().numpy(), info["iters"].copy(), info["flags"].copy()))
+    finally:
+        ctx.tune_set(dd.TUNE_HOP_WALK, 0)
+        ctx.tune_set(dd.TUNE_DHAT_RHS, 0)
+    (x1, it1, f1), (x3, it3, f3) = out
+    assert np.array_equal(it1, it3) and np.array_equal(f1, f3)
+    ok = np.isfinite(x1)
+    assert np.array_equal(ok, np.isfinite(x3)) and np.array_equal(x1[ok], x3[ok])
+    assert np.all(x3[3, off[1]:off[2]] == 0) and f3[1, 2] & 4
+    for r in range(4):
+        for k, bx in enumerate(boxes):
+            if (r, k) in [(1, 2), (3, 1)]:
+                continue
+            sl = slice(off[k], off[k + 1])
+            assert _true_relres(L, kappa, U, bx, x3[r, sl], b[r, sl]) <= TOL, (r, k)
     g.close()

@@ -138,11 +138,25 @@ def test_hop_timer_accounts_bytes(ctx):
     ctx.timer_reset()
     ctx.apply_D_block(blk, g, 0.1, "f32", _dev(x))
     ms, n, nbytes = ctx.timer_read()
-    ctx.timer_enable(False)
-    assert n == 2 and ms > 0
-    # two hops, each reading in + self and writing out (3 half fields), plus the block links
-    # (a link counts as the full 3x3 matrix, 18 reals, whatever the storage keeps of it)
+    # D_Lambda as one walk over both parities: the input and the output once (24 reals per site and
+    # rhs each) and the links once (a link counts as the full 3x3 matrix, 18 reals, whatever the
+    # storage keeps of it)
     V = 8**4
+    assert n == 1 and ms > 0
+    expect = 4 * V * 48 * 4 + blk.inner_links * 18 * 4
+    assert abs(nbytes - expect) < 1e-6 * expect
+    # with the walk split in segments: two hop launches, each reading in + self and writing out
+    from paper_2211_06902_amd import dd
+
+    try:
+        ctx.tune_set(dd.TUNE_HOP_WALK, 1)
+        ctx.timer_reset()
+        ctx.apply_D_block(blk, g, 0.1, "f32", _dev(x))
+        ms, n, nbytes = ctx.timer_read()
+    finally:
+        ctx.tune_set(dd.TUNE_HOP_WALK, 0)
+        ctx.timer_enable(False)
+    assert n == 2 and ms > 0
     expect = 2 * (4 * (V / 2) * 24 * 4 * 3 + blk.inner_links * 18 * 4)
     assert abs(nbytes - expect) < 1e-6 * expect
 
