@@ -367,9 +367,10 @@ dd_status dd_block_logdet(dd_ctx *ctx, const dd_blocks *blocks, const dd_gauge *
  * never (two hop launches and the intermediate in global memory).  Results
  * do not depend on it beyond the summation order of the fused dot products.
  * DD_TUNE_DHAT_RHS: right-hand sides one workgroup of that kernel walks in
- * lockstep (sharing the block's link loads): 0 (default) three when n_rhs is
- * a multiple of three and the blocks times n_rhs / 3 reach 1024, else one;
- * 1 or 3 to force.  Results do not depend on it. */
+ * lockstep (sharing the block's link loads): 0 (default) or 1 for one, 3 for
+ * three (fewer link re-reads, but measured slower on 8^4 blocks: the three
+ * walks share barriers and hide memory latency worse).  Results do not depend
+ * on it. */
 /* Schedule of the persistent GMRES solver (0 = default):
  * DD_TUNE_GMRES_THREADS  threads per workgroup, 256 or 512;
  * DD_TUNE_GMRES_QUEUES   work queues, 1 (one global queue) or 8 (one per XCD:

@@ -216,8 +216,11 @@ double dlam_bytes(const dd_blocks *B, int nr, dd_prec prec)
 
 int dhat_rhs_per_wg(const dd_ctx *ctx, const dd_blocks *B, int n_rhs)
 {
-    if (ctx->dhat_rhs == 1 || ctx->dhat_rhs == 3) return ctx->dhat_rhs;
-    return (n_rhs % 3 == 0 && (int64_t)B->nb * (n_rhs / 3) >= 1024) ? 3 : 1;
+    // three rhs per workgroup cut the link re-reads but hide memory latency
+    // worse (three walks behind shared barriers); one is the faster default
+    (void)B;
+    (void)n_rhs;
+    return ctx->dhat_rhs == 3 ? 3 : 1;
 }
 
 bool dhat_walk_applies(const dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, dd_prec prec)

@@ -151,8 +151,8 @@ __device__ __forceinline__ double wg_hop_walk(const PairGeo &g, int p, int ns, S
             SP sv[12], av[12];
 #pragma unroll
             for (int q = 0; q < 12; q++) {
-                sv[q] = bload<SP>(sb, vo, (uint32_t)(12 * half + q) * hc.cstr);
-                av[q] = bload<SP>(ab, vo, (uint32_t)(12 * half + q) * hc.cstr);
+                sv[q] = bload<SP, kKeep>(sb, vo, (uint32_t)(12 * half + q) * hc.cstr);
+                av[q] = bload<SP, kKeep>(ab, vo, (uint32_t)(12 * half + q) * hc.cstr);
             }
 #pragma unroll
             for (int q = 0; q < 12; q++) {
@@ -160,7 +160,7 @@ __device__ __forceinline__ double wg_hop_walk(const PairGeo &g, int p, int ns, S
                 if (has_self) v = fmad(cs, (AC)sv[q], v);
                 if (has_add) v = fmad(ca, (AC)av[q], v);
                 const SP ov = (SP)v;
-                bstore<SP>(ob, ov, vo, (uint32_t)(12 * half + q) * hc.cstr);
+                bstore<SP, kKeep>(ob, ov, vo, (uint32_t)(12 * half + q) * hc.cstr);
                 nn += (double)ov * (double)ov;
             }
         }
@@ -205,8 +205,8 @@ __device__ __forceinline__ double wg_dhat_walk(const PairGeo &g, int ns, SP *sa,
             SP sv[12], av[12];
 #pragma unroll
             for (int q = 0; q < 12; q++) {
-                sv[q] = bload<SP>(fb, vo, (uint32_t)(12 * half + q) * hc.cstr);
-                av[q] = bload<SP>(ab, vo, (uint32_t)(12 * half + q) * hc.cstr);
+                sv[q] = bload<SP, kKeep>(fb, vo, (uint32_t)(12 * half + q) * hc.cstr);
+                av[q] = bload<SP, kKeep>(ab, vo, (uint32_t)(12 * half + q) * hc.cstr);
             }
 #pragma unroll
             for (int q = 0; q < 12; q++) {
@@ -214,7 +214,7 @@ __device__ __forceinline__ double wg_dhat_walk(const PairGeo &g, int ns, SP *sa,
                 if (has_self) v = fmad(cs, (AC)sv[q], v);
                 if (has_add) v = fmad(ca, (AC)av[q], v);
                 const SP ov = (SP)v;
-                bstore<SP>(ob, ov, vo, (uint32_t)(12 * half + q) * hc.cstr);
+                bstore<SP, kKeep>(ob, ov, vo, (uint32_t)(12 * half + q) * hc.cstr);
                 nn += (double)ov * (double)ov;
             }
         }
@@ -247,7 +247,7 @@ __device__ __forceinline__ void gs_dots(const Slot &sl, int iw, int h, int j, bo
 #pragma unroll 1
             for (int s = threadIdx.x; s < h; s += NT) {
                 const uint32_t vo = (uint32_t)(2 * cc * h + s) * (uint32_t)sizeof(SP);
-                const double wr = (double)bload<SP>(sl.b, vo, wo), wi = (double)bload<SP>(sl.b, vo, wo + hb);
+                const double wr = (double)bload<SP, kKeep>(sl.b, vo, wo), wi = (double)bload<SP, kKeep>(sl.b, vo, wo + hb);
                 // the basis offsets are recomputed here (scalar arithmetic) rather
                 // than hoisted out of the loops into scalar registers
                 uint32_t vbytes = sl.vbytes;
@@ -256,7 +256,7 @@ __device__ __forceinline__ void gs_dots(const Slot &sl, int iw, int h, int j, bo
                 for (int k = 0; k < GS; k++)
                     if (i0 + k <= j) {
                         const uint32_t io = (uint32_t)(i0 + k) * vbytes;
-                        const double vr = (double)bload<SP>(sl.b, vo, io), vi = (double)bload<SP>(sl.b, vo, io + hb);
+                        const double vr = (double)bload<SP, kKeep>(sl.b, vo, io), vi = (double)bload<SP, kKeep>(sl.b, vo, io + hb);
                         d[2 * k] = fma(vr, wr, fma(vi, wi, d[2 * k]));
                         d[2 * k + 1] = fma(vr, wi, fma(-vi, wr, d[2 * k + 1]));
                     }
@@ -304,7 +304,7 @@ __device__ __forceinline__ void combine(const Slot &sl, const Buf &db, uint32_t 
             // iteration instead of being held in registers across the loop
             __asm__ volatile("" ::: "memory");
             const uint32_t vo = (uint32_t)(2 * cc * h + s) * (uint32_t)sizeof(SP);
-            double wr = (double)bload<SP>(db, vo, dso), wi = (double)bload<SP>(db, vo, dso + hb);
+            double wr = (double)bload<SP, kKeep>(db, vo, dso), wi = (double)bload<SP, kKeep>(db, vo, dso + hb);
             // the basis offsets are recomputed here (scalar arithmetic) rather
             // than hoisted out of the loops into scalar registers
             uint32_t vbytes = sl.vbytes;
@@ -313,13 +313,13 @@ __device__ __forceinline__ void combine(const Slot &sl, const Buf &db, uint32_t 
             for (int i = 0; i <= M; i++)
                 if (i >= i0 && i < n) {
                     const uint32_t io = (uint32_t)i * vbytes;
-                    const double vr = (double)bload<SP>(sl.b, vo, io), vi = (double)bload<SP>(sl.b, vo, io + hb);
+                    const double vr = (double)bload<SP, kKeep>(sl.b, vo, io), vi = (double)bload<SP, kKeep>(sl.b, vo, io + hb);
                     const double cr = sgn * c[2 * i], ci = sgn * c[2 * i + 1];
                     wr = fma(cr, vr, fma(-ci, vi, wr));
                     wi = fma(cr, vi, fma(ci, vr, wi));
                 }
-            bstore<SP>(db, (SP)(wr * scale), vo, dso);
-            bstore<SP>(db, (SP)(wi * scale), vo, dso + hb);
+            bstore<SP, kKeep>(db, (SP)(wr * scale), vo, dso);
+            bstore<SP, kKeep>(db, (SP)(wi * scale), vo, dso + hb);
         }
 }
 

@@ -441,6 +441,10 @@ dd_status block_solve_impl(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, 
             h.c_add = 1.0;
             h.dot_mode = kDotOutOut;
             h.partial = p ? w.po : w.pe;
+            // from the second residual on, only the pairs corrected in the
+            // last cycle: the others keep their residual and its partial
+            // sums, and stay converged (or flagged)
+            if (cyc >= 2) h.skip_act = w.os.active;
             HIPCHECK(ctx, run_hop(ctx, B, ba64, h, DD_F64));
         }
         HIPCHECK(ctx, launch_sc_outer(ba64, w.pe, w.po, cyc == 0, prm.tol, w.os, st));
@@ -463,6 +467,7 @@ dd_status block_solve_impl(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, 
             HopArgs h = hop_args(w.rhs, ri_o, links, 0, kappa);
             h.self = ri_e;
             h.c_self = 1.0;
+            if (cyc >= 1) h.skip_act = w.os.active;  // pairs this cycle solves
             HIPCHECK(ctx, run_hop(ctx, B, ba, h, ip));
         }
         if (gmres) {
@@ -581,6 +586,7 @@ dd_status block_solve_impl(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, 
             HopArgs h = hop_args(w.tmp, w.xi, links, 1, kappa);
             h.self = ri_o;
             h.c_self = 1.0;
+            if (cyc >= 1) h.skip_act = w.os.active;  // the accumulation masks the others
             HIPCHECK(ctx, run_hop(ctx, B, ba, h, ip));
         }
         HIPCHECK(ctx, launch_accum(ba, w.xe, w.xi, sp, w.os.active, st));
@@ -798,12 +804,15 @@ dd_status dd_multiboson_action(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *
     else dd_solve_params_default(&prm);
     // fields per block solve: the solver's workspace grows with the rhs of a call
     // (FP64 half fields, inner-precision Krylov vectors and the solutions), so
-    // large lattices are solved a few fields at a time
+    // large lattices are solved a few fields at a time.  The context's own
+    // workspaces count as free: they are reused or regrown, so the choice does
+    // not depend on what earlier calls left allocated.
     const int64_t total = B->soff[B->nb];
     int fc = ctx->mb_fields;
     if (fc <= 0) {
         size_t fr = 0, tot = 0;
         HIPCHECK(ctx, hipMemGetInfo(&fr, &tot));
+        for (const auto &kv : ctx->ws) fr += kv.second.bytes;
         const double per_field = (double)total * (192.0 + 576.0 + 132.0 * prec_bytes(prm.inner_prec == DD_F64 ? DD_F64 : DD_F32));
         fc = (int)std::max(1.0, std::floor(0.6 * (double)fr / per_field));
     }

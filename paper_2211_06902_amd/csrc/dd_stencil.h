@@ -38,35 +38,35 @@ __device__ __forceinline__ Buf make_buf(const void *p, uint32_t bytes)
 {
     return Buf{__builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, (int)bytes, 0x00020000)};
 }
-template <typename T>
-__device__ __forceinline__ T bload(const Buf &b, uint32_t voff, uint32_t soff);
-template <>
-__device__ __forceinline__ float bload<float>(const Buf &b, uint32_t voff, uint32_t soff)
+// Cache policy of a buffer access (the instruction's cache-policy bits on
+// gfx950; bit 1 = non-temporal).  kStream marks single-use spinor streams,
+// so that they do not push out of L2 and the MALL the links that every rhs
+// group of a launch reads again; kKeep (no hint) is for data that a launch
+// re-reads, such as a Krylov basis.
+enum : int { kKeep = 0, kStream = 2 };
+
+template <typename T, int CP = kStream>
+__device__ __forceinline__ T bload(const Buf &b, uint32_t voff, uint32_t soff)
 {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(b.r, (int)voff, (int)soff, 0));
+    if constexpr (sizeof(T) == 8) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b64(b.r, (int)voff, (int)soff, CP));
+    } else if constexpr (sizeof(T) == 4) {
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(b.r, (int)voff, (int)soff, CP));
+    } else {
+        static_assert(sizeof(T) == 2, "2, 4 or 8 byte elements");
+        return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b16(b.r, (int)voff, (int)soff, CP));
+    }
 }
-template <>
-__device__ __forceinline__ double bload<double>(const Buf &b, uint32_t voff, uint32_t soff)
+template <typename T, int CP = kStream>
+__device__ __forceinline__ void bstore(const Buf &b, T v, uint32_t voff, uint32_t soff)
 {
-    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(b.r, (int)voff, (int)soff, 0));
-}
-template <>
-__device__ __forceinline__ uint16_t bload<uint16_t>(const Buf &b, uint32_t voff, uint32_t soff)
-{
-    return __builtin_amdgcn_raw_buffer_load_b16(b.r, (int)voff, (int)soff, 0);
-}
-template <typename T>
-__device__ __forceinline__ void bstore(const Buf &b, T v, uint32_t voff, uint32_t soff);
-template <>
-__device__ __forceinline__ void bstore<float>(const Buf &b, float v, uint32_t voff, uint32_t soff)
-{
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), b.r, (int)voff, (int)soff, 0);
-}
-template <>
-__device__ __forceinline__ void bstore<double>(const Buf &b, double v, uint32_t voff, uint32_t soff)
-{
-    using u2 = __attribute__((ext_vector_type(2))) uint32_t;
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), b.r, (int)voff, (int)soff, 0);
+    if constexpr (sizeof(T) == 8) {
+        using u2 = __attribute__((ext_vector_type(2))) uint32_t;
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), b.r, (int)voff, (int)soff, CP);
+    } else {
+        static_assert(sizeof(T) == 4, "4 or 8 byte elements");
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), b.r, (int)voff, (int)soff, CP);
+    }
 }
 
 // Link layout per block: element (site slot s, mu, complex entry k = 3*row + col
