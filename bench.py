@@ -16,6 +16,7 @@ solves per step), FP32 BiCGStab inside FP64 defect correction.
 --workload c3: 48^3 x 96 lattice, 2160 uneven blocks (1296 of 8^4 and 864 of
 8^3 x 12), 12 sources per block, persistent autotuned GMRES(16) with BF16
 links.  --workload c4: the learned preconditioner's training and gain test.
+--workload dlam: y = D_Lambda x alone (the one-pass walk) on the 64^4 blocks, 12 rhs.
 
 The timed steps run the library's default path (inner iterations replayed
 from captured hipGraphs, no kernel timers); one extra step with the kernel
@@ -533,6 +534,58 @@ def profiled_traffic(path):
         return None
 
 
+def run_dlam(args):
+    """--workload dlam: y = D_Lambda x alone (dd_apply_D_block, FP32 arithmetic: pack to half
+    fields, the one-pass x0-walk of D_Lambda, unpack) on the 64^4 lattice's 4096 blocks of 8^4,
+    12 rhs, `--steps` timed applications after `--warmup`.  The stencil's bandwidth counts
+    n_rhs * S * 48 * 4 bytes of spinors plus every link inside the blocks once as 18 reals."""
+    import torch
+
+    import synth
+    from paper_2211_06902_amd import dd
+
+    L, nr, kappa = (64, 64, 64, 64), 12, 0.1365
+    ctx = dd.Context(0)
+    blk = ctx.make_blocks(L, -1, [[8] * 8] * 4)
+    U = synth.gauge_field_device(L, 0.2, 5101)
+    g = ctx.load_gauge(blk, U, "f32")
+    del U
+    torch.cuda.empty_cache()
+    x = synth.spinor_field_device(nr, blk.total_sites, 5103)
+    y = torch.empty_like(x)
+    for _ in range(max(args.warmup, 1)):
+        ctx.apply_D_block(blk, g, kappa, "f32", x, y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ctx.apply_D_block(blk, g, kappa, "f32", x, y)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    ctx.timer_enable(True)
+    ctx.timer_reset()
+    for _ in range(args.steps):
+        ctx.apply_D_block(blk, g, kappa, "f32", x, y)
+    k_ms, k_n, k_bytes = ctx.timer_read(dd.KCLASS_HOP_F32)
+    ctx.timer_enable(False)
+    achieved = k_bytes / (k_ms * 1e-3) / 1e9 if k_ms > 0 else 0.0
+    print(json.dumps({
+        "metric": "block D_Lambda applications (all blocks, all rhs) per second", "value": 1.0 / dt,
+        "unit": "applications/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "y = D_Lambda x on the 64^4 lattice (antiperiodic time, SU(3) links exp(0.2 i H) from "
+                               "seed 5101): 4096 blocks of 8^4 (Dirichlet), 12 rhs; FP64 in and out, FP32 arithmetic "
+                               "(pack, one-pass x0-walk, unpack)", "rhs": nr},
+        "roofline": {"kernel": "k_dlam_walk (FP32; D_Lambda in one x0-walk over both parities)", "bound": "hbm",
+                     "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": None, "launches": k_n, "avg_launch_us": k_ms * 1e3 / max(k_n, 1),
+                     "alg_bytes_per_launch": k_bytes / max(k_n, 1),
+                     "timing": "HIP events around each launch on the library stream, in extra applications"},
+    }), flush=True)
+    g.close()
+    blk.close()
+    ctx.close()
+
+
 def run_solve(args):
     """--workload c2 / c3: one dd_block_solve over all (block, rhs) pairs per step."""
     import torch
@@ -649,7 +702,7 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="launch every inner iteration from the host")
     ap.add_argument("--inner", default=None, choices=["f32", "bf16", "f64"],
                     help="inner precision (default: FP32; BF16 links for c3)")
-    ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS) + ["c4", "c5", "nnapply"])
+    ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS) + ["c4", "c5", "dlam", "nnapply"])
     ap.add_argument("--epochs", type=int, default=4, help="c4, c5: training epochs of the network")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (4 times), to calibrate HBM byte counters")
@@ -668,7 +721,7 @@ def main():
         print("bench.py measures one GPU only: the block solves need no communication and this build has no "
               "multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
-    {"c4": run_c4, "c5": run_c5, "nnapply": run_nnapply}.get(args.workload, run_solve)(args)
+    {"c4": run_c4, "c5": run_c5, "dlam": run_dlam, "nnapply": run_nnapply}.get(args.workload, run_solve)(args)
 
 
 if __name__ == "__main__":

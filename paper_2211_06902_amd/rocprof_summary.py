@@ -44,10 +44,13 @@ def _one(path_dir: str, pattern: str) -> str:
     return hits[0]
 
 
-def _counter(path_dir: str, name: str, kernel: str):
+def _counter(path_dir: str, name: str, kernel: str, skip: int = 0):
+    """Per-dispatch values of counter `name` for the kernels whose name contains `kernel`, in
+    dispatch order, leaving out the first `skip` of them."""
     rows = list(csv.DictReader(open(_one(path_dir, "*counter_collection.csv"))))
-    vals = [float(r["Counter_Value"]) for r in rows if r["Counter_Name"] == name and kernel in r["Kernel_Name"]]
-    return vals
+    hits = [r for r in rows if r["Counter_Name"] == name and kernel in r["Kernel_Name"]]
+    hits.sort(key=lambda r: int(r["Dispatch_Id"]))
+    return [float(r["Counter_Value"]) for r in hits[skip:]]
 
 
 def main():
@@ -65,6 +68,9 @@ def main():
     ap.add_argument("--command", required=True)
     ap.add_argument("--title", default="")
     ap.add_argument("--source", nargs="*", help="kernel source files to hash (default: the hop's)")
+    ap.add_argument("--counter-skip", type=int, default=0,
+                    help="average FETCH_SIZE / WRITE_SIZE leaving out the kernel's first N dispatches of each "
+                         "counter run (launches of an autotuner before the measured ones)")
     ap.add_argument("--trace-skip", type=int, default=0,
                     help="average the kernel's durations from the kernel trace, leaving out its first N dispatches "
                          "(a warm-up evaluation whose first touches of fresh workspaces run slower)")
@@ -118,8 +124,8 @@ def main():
         big_w = max(copy_w)
         scale_f = GIB / (big_f * 1024.0)  # bytes per reported byte
         scale_w = GIB / (big_w * 1024.0)
-        fv = _counter(args.fetch, "FETCH_SIZE", args.kernel)
-        wv = _counter(args.write, "WRITE_SIZE", args.kernel)
+        fv = _counter(args.fetch, "FETCH_SIZE", args.kernel, args.counter_skip)
+        wv = _counter(args.write, "WRITE_SIZE", args.kernel, args.counter_skip)
         fetch_b = sum(fv) / len(fv) * 1024.0 * scale_f
         write_b = sum(wv) / len(wv) * 1024.0 * scale_w
         traffic = fetch_b + write_b
@@ -135,6 +141,8 @@ def main():
     rows.append("| kernel source sha256[:16] | %s |" % summary["kernel_source_sha256_16"])
     if skip_note:
         summary["trace_skip"] = args.trace_skip
+    if args.counter_skip:
+        summary["counter_skip"] = args.counter_skip
     top = sorted(stats, key=lambda r: -float(r["TotalDurationNs"]))[:12]
     lines = [
         "# %s" % (args.title or "rocprofv3 summary: " + args.kernel),
