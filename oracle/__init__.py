@@ -17,5 +17,5 @@ Contents (each module cites the part of the paper it follows):
   convnet    the learned block preconditioner: 4D conv net, gradients, loss, Adam
              (not in the paper; parity pinned by independent identities)
 """
-from . import convnet, dense, factor, geometry, mb, precision, roots, wilson  # noqa: F401
+from . import clover, convnet, dense, factor, geometry, mb, precision, roots, wilson  # noqa: F401
 from ._clib import build  # noqa: F401
