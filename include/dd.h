@@ -178,6 +178,28 @@ dd_status dd_free_gauge(dd_gauge *gauge);
  * (with the edge sign), which is exact for SU(3) links. */
 dd_status dd_gauge_export(dd_ctx *ctx, const dd_gauge *gauge, dd_prec prec, void *dst_dev);
 
+/* Give the gauge's operator the clover (Sheikholeslami-Wohlert) term
+ * (Section 3 takes D to be the Wilson or Sheikholeslami-Wohlert operator):
+ * D = 1 - kappa H + (A - 1) with, at every site x,
+ *   A(x) = 1 + i kappa c_sw sum_{mu<nu} sigma_{mu nu} Fhat_{mu nu}(x),
+ *   sigma_{mu nu} = (i/2) [gamma_mu, gamma_nu] (chiral basis),
+ *   Fhat_{mu nu}(x) = (Q_{mu nu}(x) - Q_{mu nu}(x)^+) / 8,
+ * Q_{mu nu}(x) the four plaquettes of the (mu, nu) plane at x, each traversed
+ * mu-then-nu; the gauge field is periodic in every direction.  U_dev is the
+ * canonical FP64 field of the whole lattice (as for dd_load_gauge; only read
+ * during the call): D_Lambda keeps A of the whole lattice at every block
+ * site, so boundary sites see links outside their block.  The library
+ * computes A and A^-1 per block site in FP64 (FP32 copies for a gauge with
+ * FP32 or BF16 links; 72 reals per site and copy).  From then on
+ * dd_apply_D_block, dd_apply_D_block_noalloc, dd_block_solve and
+ * dd_multiboson_action use this operator and reject another kappa
+ * (DD_EINVAL); solves run even-odd BiCGStab on
+ * 1 - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe (DD_EUNSUPPORTED for GMRES, a network
+ * preconditioner, or blocks the x0-walk hop cannot take); dd_block_logdet
+ * returns DD_EUNSUPPORTED.  c_sw = 0 removes the term (the Wilson operator).
+ * Errors: DD_EINVAL (null argument, non-finite kappa or c_sw), DD_ENOMEM. */
+dd_status dd_gauge_set_clover(dd_ctx *ctx, dd_gauge *gauge, const void *U_dev, double kappa, double csw);
+
 /* ------------------------------------------------------------- operator */
 
 /* y = D_Lambda x for every block and every right-hand side (Section 3, the

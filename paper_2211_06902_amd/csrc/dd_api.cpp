@@ -261,14 +261,31 @@ hipError_t run_dhat(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const Ho
     return launch_dhat_walk(ba, wa, ha, prec, ctx->stream);
 }
 
-dd_status apply_D_check(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *G, dd_prec prec, const void *x_dev,
-                        void *y_dev, int32_t n_rhs, const void **links)
+const void *clover_for(const dd_gauge *G, dd_prec prec, bool inverse)
+{
+    if (G->cl_csw == 0.0) return nullptr;
+    if (prec == DD_F64) return inverse ? (const void *)G->d_cli64 : (const void *)G->d_cla64;
+    return inverse ? (const void *)G->d_cli32 : (const void *)G->d_cla32;
+}
+
+dd_status clover_check(dd_ctx *ctx, const dd_gauge *G, double kappa)
+{
+    if (G->cl_csw != 0.0 && !(std::fabs(kappa - G->cl_kappa) <= 1e-12 * std::fabs(G->cl_kappa)))
+        return fail(ctx, DD_EINVAL, "the gauge's clover term was built for another kappa");
+    return DD_OK;
+}
+
+dd_status apply_D_check(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *G, dd_prec prec, double kappa,
+                        const void *x_dev, void *y_dev, int32_t n_rhs, const void **links, const void **clover)
 {
     if (!ctx || !B || !G || !x_dev || !y_dev) return fail(ctx, DD_EINVAL, "null argument");
     if (n_rhs < 1 || n_rhs > kMaxRhs) return fail(ctx, DD_EINVAL, "n_rhs must be in 1..64");
     if (G->blocks != B) return fail(ctx, DD_EINVAL, "gauge was loaded for other blocks");
     *links = links_for(G, prec);
     if (!*links) return fail(ctx, DD_EINVAL, "gauge holds no links of the requested precision");
+    const dd_status st = clover_check(ctx, G, kappa);
+    if (st != DD_OK) return st;
+    *clover = clover_for(G, prec, false);
     return DD_OK;
 }
 
@@ -278,15 +295,26 @@ size_t apply_D_half_bytes(const dd_blocks *B, int n_rhs, dd_prec prec)
     return (size_t)(B->soff[B->nb] / 2) * 24 * n_rhs * prec_bytes(sp);
 }
 
-dd_status apply_D_with(dd_ctx *ctx, const dd_blocks *Bc, const void *links, double kappa, dd_prec prec,
-                       const void *x_dev, void *y_dev, int32_t n_rhs, void *const hf[4])
+dd_status apply_D_with(dd_ctx *ctx, const dd_blocks *Bc, const void *links, const void *clover, double kappa,
+                       dd_prec prec, const void *x_dev, void *y_dev, int32_t n_rhs, void *const hf[4])
 {
     const dd_prec sp = prec == DD_F64 ? DD_F64 : DD_F32;
     const int g = hop_group(ctx, n_rhs, sp, prec);
     const BlkArgs ba = blk_args(Bc, tiles_for(Bc, n_rhs, g), n_rhs, g);
     void *xe = hf[0], *xo = hf[1], *ye = hf[2], *yo = hf[3];
     HIPCHECK(ctx, launch_pack_spinor(Bc, (const double *)x_dev, xe, xo, sp, n_rhs, ctx->stream));
-    if (dlam_walk_applies(ctx, Bc, prec)) {
+    if (clover) {
+        // y_p = A_pp x_p, then y_p += -kappa H x_{1-p} in place (the hop reads
+        // a site's self term before it writes the site)
+        for (int p = 0; p < 2; p++)
+            HIPCHECK(ctx, launch_clover_apply(Bc, clover, p ? xo : xe, p ? yo : ye, p, n_rhs, sp, nullptr, ctx->stream));
+        for (int p = 0; p < 2; p++) {
+            HopArgs ha = hop_args(p ? yo : ye, p ? xe : xo, links, p, -kappa);
+            ha.self = p ? yo : ye;
+            ha.c_self = 1.0;
+            HIPCHECK(ctx, run_hop(ctx, Bc, ba, ha, prec));
+        }
+    } else if (dlam_walk_applies(ctx, Bc, prec)) {
         // one x0-walk per (block, rhs) over both parities; algorithmic bytes
         // as for D_Lambda: x once, y once, the links once
         DlamArgs da;
@@ -696,6 +724,7 @@ dd_status dd_free_gauge(dd_gauge *G)
     if (G->d_u32) hipFree(G->d_u32);
     if (G->d_ubf) hipFree(G->d_ubf);
     if (G->d_uext) hipFree(G->d_uext);
+    clover_release(G);
     delete G;
     return DD_OK;
 }
@@ -717,8 +746,8 @@ dd_status dd_gauge_export(dd_ctx *ctx, const dd_gauge *G, dd_prec prec, void *ds
 dd_status dd_apply_D_block(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, double kappa, dd_prec prec,
                            const void *x_dev, void *y_dev, int32_t n_rhs)
 {
-    const void *links = nullptr;
-    const dd_status st = apply_D_check(ctx, Bc, G, prec, x_dev, y_dev, n_rhs, &links);
+    const void *links = nullptr, *clover = nullptr;
+    const dd_status st = apply_D_check(ctx, Bc, G, prec, kappa, x_dev, y_dev, n_rhs, &links, &clover);
     if (st != DD_OK) return st;
     HIPCHECK(ctx, enter(ctx));
     hipError_t e;
@@ -728,7 +757,7 @@ dd_status dd_apply_D_block(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, 
     for (int k = 0; k < 4; k++)
         if (!(hf[k] = workspace(ctx, names[k], half, &e)))
             return fail(ctx, DD_ENOMEM, std::string("workspace: ") + hipGetErrorString(e));
-    return apply_D_with(ctx, Bc, links, kappa, prec, x_dev, y_dev, n_rhs, hf);
+    return apply_D_with(ctx, Bc, links, clover, kappa, prec, x_dev, y_dev, n_rhs, hf);
 }
 
 // ------------------------------------------------------------------ timing

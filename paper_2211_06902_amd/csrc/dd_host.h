@@ -37,15 +37,22 @@ HopArgs hop_args(void *out, const void *in, const void *links, int parity, doubl
 // releases the context's dense-LU library handle
 void logdet_release(dd_ctx *ctx);
 
-// y = D_Lambda x (dd_apply_D_block): argument checks (links of the precision),
-// the bytes of each of its four half fields, and the operator with the half
-// fields x_e, x_o, y_e, y_o given (pack, one hop launch per parity, unpack;
-// synchronizes).
-dd_status apply_D_check(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *G, dd_prec prec, const void *x_dev,
-                        void *y_dev, int32_t n_rhs, const void **links);
+// y = D_Lambda x (dd_apply_D_block): argument checks (links of the precision,
+// kappa of the clover term), the bytes of each of its four half fields, and
+// the operator with the half fields x_e, x_o, y_e, y_o given (pack, one hop
+// launch per parity, unpack; synchronizes).  clover: the clover term A in the
+// arithmetic precision (null for the Wilson operator), applied in place to
+// y before the hops.
+dd_status apply_D_check(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *G, dd_prec prec, double kappa,
+                        const void *x_dev, void *y_dev, int32_t n_rhs, const void **links, const void **clover);
 size_t apply_D_half_bytes(const dd_blocks *B, int n_rhs, dd_prec prec);
-dd_status apply_D_with(dd_ctx *ctx, const dd_blocks *B, const void *links, double kappa, dd_prec prec,
-                       const void *x_dev, void *y_dev, int32_t n_rhs, void *const hf[4]);
+dd_status apply_D_with(dd_ctx *ctx, const dd_blocks *B, const void *links, const void *clover, double kappa,
+                       dd_prec prec, const void *x_dev, void *y_dev, int32_t n_rhs, void *const hf[4]);
+// The gauge's clover matrices (A, or A^-1 with inverse) for spinors of the
+// precision that arithmetic precision prec computes in; null without a
+// clover term.  clover_check: the clover term was built for this kappa.
+const void *clover_for(const dd_gauge *G, dd_prec prec, bool inverse);
+dd_status clover_check(dd_ctx *ctx, const dd_gauge *G, double kappa);
 
 // Timing of one kernel launch of a class (events only while timing is on).
 struct TimedLaunch {

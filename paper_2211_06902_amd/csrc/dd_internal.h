@@ -26,6 +26,10 @@ constexpr int kNRed = 4;
 constexpr int kGmReorthPercent = 10;
 constexpr int kLinkK = 6;  // complex entries stored per link: rows 0 and 1 (row 2 is rebuilt)
 constexpr int kLinkReals = 4 * kLinkK * 2;  // per site: 4 directions
+// clover term per site: two hermitian 6x6 blocks (the chiralities), each as
+// 6 real diagonal entries and 15 complex entries above the diagonal
+constexpr int kCloverHalf = 36;
+constexpr int kCloverReals = 2 * kCloverHalf;
 // A link in the algorithmic byte counts: the full 3x3 complex matrix (18
 // reals), the amount the operator needs whatever the storage keeps of it.
 constexpr int kLinkAlgReals = 18;
@@ -180,6 +184,13 @@ struct dd_gauge {
     float *d_u32 = nullptr;      // when low == DD_F32
     uint16_t *d_ubf = nullptr;   // when low == DD_BF16
     double *d_uext = nullptr;    // [exterior hops][3][3][re, im]: the link of each exterior hop (FP64)
+    // clover (Sheikholeslami-Wohlert) term A of every block site and its
+    // inverse, two packed hermitian 6x6 blocks (kCloverReals per site, layout
+    // of clover_mul); FP32 copies when the links are FP32 or BF16; kappa and
+    // c_sw they were built for (csw == 0: none)
+    double *d_cla64 = nullptr, *d_cli64 = nullptr;
+    float *d_cla32 = nullptr, *d_cli32 = nullptr;
+    double cl_kappa = 0.0, cl_csw = 0.0;
 };
 
 namespace dd {
@@ -239,6 +250,11 @@ struct HopArgs {
     const int32_t *skip_act;
     double *bytes_acc;
     double bytes_site;
+    // x0-walk kernels, one rhs per thread: the block sites' clover matrices in
+    // the hop's arithmetic precision (kCloverReals per site); the hop result
+    // at an output site is multiplied by that site's matrix before the
+    // epilogue combines it with self and add
+    const void *clover;
 };
 
 // Vector updates of BiCGStab done by the first hop of Dhat as it stages its
@@ -409,6 +425,16 @@ struct DlamArgs {
     double bytes_walk;
 };
 hipError_t launch_dlam_walk(const BlkArgs &ba, const DlamArgs &da, dd_prec prec, hipStream_t s);
+// clover term (dd_clover.hip): A and A^-1 of every block site from the global
+// FP64 gauge field U[V][4][3][3] (FP64 out; FP32 copies when a32 != null)
+hipError_t launch_clover_build(const dd_blocks *B, const double *U, double kappa, double csw, double *a64,
+                               double *i64, float *a32, float *i32, hipStream_t s);
+// y = C x on half field `parity` of n_rhs rhs (C: kCloverReals per block site
+// in the precision of x; x and y may be the same); pairs whose mask is 0 are
+// left alone (mask may be null)
+void clover_release(dd_gauge *G);  // frees the clover term of a gauge (back to Wilson)
+hipError_t launch_clover_apply(const dd_blocks *B, const void *C, const void *x, void *y, int parity, int n_rhs,
+                               dd_prec sp, const int32_t *mask, hipStream_t s);
 hipError_t launch_convert(const void *src, dd_prec sp, void *dst, dd_prec dp, int64_t n,
                           hipStream_t s);
 hipError_t launch_accum(const BlkArgs &ba, double *x, const void *e, dd_prec ep,

@@ -279,6 +279,7 @@ __global__ void __launch_bounds__(kTile) k_hop(BlkArgs ba, HopArgs ha)
 hipError_t launch_hop(const BlkArgs &ba, const HopArgs &ha, dd_prec prec, hipStream_t s)
 {
     if (ha.pre != kPreNone) return hipErrorInvalidValue;  // staging updates are x0-walk only
+    if (ha.clover) return hipErrorInvalidValue;            // so is the clover term
     if (ba.ntiles <= 0) return hipSuccess;
     dim3 g(ba.ntiles), t(kTile);
     if (prec == DD_F64 && ba.g == 1)
@@ -351,10 +352,13 @@ struct PreLoad {
 // x0-walk of the hop (the walk itself is in dd_stencil.h): a tile walks one
 // of nseg segments of a block's x0-slices for one group of G rhs.  PRE: the
 // BiCGStab update of the input done while staging it (kPre*).
-template <typename SP, typename LK, typename AC, int G, int DM, int PRE = kPreNone>
-__global__ void __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(sizeof(SP) == 8 && G == 1 && (DM == kDotNone || DM == kDotOutOut) ? 3 : 1)))
+// CL: the hop result at each output site is multiplied by that site's clover
+// matrix (ha.clover) before the epilogue (one rhs per thread).
+template <typename SP, typename LK, typename AC, int G, int DM, int PRE = kPreNone, bool CL = false>
+__global__ void __launch_bounds__(kTile) __attribute__((amdgpu_waves_per_eu(sizeof(SP) == 8 && G == 1 && !CL && (DM == kDotNone || DM == kDotOutOut) ? 3 : 1)))
 k_hop_walk(BlkArgs ba, WalkArgs wa, HopArgs ha)
 {
+    static_assert(!CL || G == 1, "clover hops take one rhs per thread");
     __shared__ SP stage[24 * kTile * G];
     __shared__ double red[G][kTile];
     const int tile = uni(xcd_tile(blockIdx.x, wa.ntiles));
@@ -399,11 +403,23 @@ k_hop_walk(BlkArgs ba, WalkArgs wa, HopArgs ha)
     for (int j = 0; j < G; j++)
 #pragma unroll
         for (int i = 0; i < kNRed; i++) dv[j][i] = 0;
+    const Buf clb = make_buf(CL ? reinterpret_cast<const SP *>(ha.clover) + soff * kCloverReals : nullptr,
+                             CL ? (uint32_t)(kCloverReals * 2 * w.hb) * (uint32_t)sizeof(SP) : 0u);
     auto epi = [&](const AC (&acc)[G][24], int h) {
 #pragma unroll
-        for (int j = 0; j < G; j++)
-            hop_epilogue<SP, AC, DM>(acc[j], dv[j], ha, eb,
-                                     (uint32_t)(hc.grp_off + j * 24 * w.hb + h) * (uint32_t)sizeof(SP), hc.cstr);
+        for (int j = 0; j < G; j++) {
+            const uint32_t my = (uint32_t)(hc.grp_off + j * 24 * w.hb + h) * (uint32_t)sizeof(SP);
+            if constexpr (CL) {
+                AC a[24];
+#pragma unroll
+                for (int c = 0; c < 24; c++) a[c] = acc[j][c];
+                clover_mul<SP, AC>(a, clb, (uint32_t)(w.p * w.hb + h) * (uint32_t)sizeof(SP),
+                                   (uint32_t)(2 * w.hb) * (uint32_t)sizeof(SP));
+                hop_epilogue<SP, AC, DM>(a, dv[j], ha, eb, my, hc.cstr);
+            } else {
+                hop_epilogue<SP, AC, DM>(acc[j], dv[j], ha, eb, my, hc.cstr);
+            }
+        }
     };
     if constexpr (PRE == kPreNone) {
         walk_run<SP, LK, AC, G>(w, ns, stage, hc, epi);
@@ -442,25 +458,37 @@ k_hop_walk(BlkArgs ba, WalkArgs wa, HopArgs ha)
     }
 }
 
-template <typename SP, typename LK, typename AC, int G>
-static void launch_walk_t(const BlkArgs &ba, const WalkArgs &wa, const HopArgs &ha, hipStream_t s)
+template <typename SP, typename LK, typename AC, int G, bool CL>
+static void launch_walk_cl(const BlkArgs &ba, const WalkArgs &wa, const HopArgs &ha, hipStream_t s)
 {
     dim3 g(wa.ntiles), t(kTile);
     if (ha.pre == kPreP) {
-        hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, G, kDotNone, kPreP>), g, t, 0, s, ba, wa, ha);
+        hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, G, kDotNone, kPreP, CL>), g, t, 0, s, ba, wa, ha);
         return;
     }
     if (ha.pre == kPreS) {
-        hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, G, kDotNone, kPreS>), g, t, 0, s, ba, wa, ha);
+        hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, G, kDotNone, kPreS, CL>), g, t, 0, s, ba, wa, ha);
         return;
     }
     switch (ha.dot_mode) {
-    case kDotNone: hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, G, kDotNone>), g, t, 0, s, ba, wa, ha); break;
-    case kDotAuxOut: hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, G, kDotAuxOut>), g, t, 0, s, ba, wa, ha); break;
-    case kDotOutSelfOutOut: hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, G, kDotOutSelfOutOut>), g, t, 0, s, ba, wa, ha); break;
-    case kDotOutOut: hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, G, kDotOutOut>), g, t, 0, s, ba, wa, ha); break;
-    default: hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, G, kDotOutAuxOutOut>), g, t, 0, s, ba, wa, ha); break;
+    case kDotNone: hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, G, kDotNone, kPreNone, CL>), g, t, 0, s, ba, wa, ha); break;
+    case kDotAuxOut: hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, G, kDotAuxOut, kPreNone, CL>), g, t, 0, s, ba, wa, ha); break;
+    case kDotOutSelfOutOut: hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, G, kDotOutSelfOutOut, kPreNone, CL>), g, t, 0, s, ba, wa, ha); break;
+    case kDotOutOut: hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, G, kDotOutOut, kPreNone, CL>), g, t, 0, s, ba, wa, ha); break;
+    default: hipLaunchKernelGGL((k_hop_walk<SP, LK, AC, G, kDotOutAuxOutOut, kPreNone, CL>), g, t, 0, s, ba, wa, ha); break;
     }
+}
+
+template <typename SP, typename LK, typename AC, int G>
+static void launch_walk_t(const BlkArgs &ba, const WalkArgs &wa, const HopArgs &ha, hipStream_t s)
+{
+    if constexpr (G == 1) {
+        if (ha.clover) {
+            launch_walk_cl<SP, LK, AC, G, true>(ba, wa, ha, s);
+            return;
+        }
+    }
+    launch_walk_cl<SP, LK, AC, G, false>(ba, wa, ha, s);
 }
 
 hipError_t launch_hop_walk(const BlkArgs &ba, const WalkArgs &wa, const HopArgs &ha, dd_prec prec, hipStream_t s)
@@ -469,6 +497,7 @@ hipError_t launch_hop_walk(const BlkArgs &ba, const WalkArgs &wa, const HopArgs 
     if (wa.nseg < 1 || ha.dot_mode < kDotNone || ha.dot_mode > kDotOutAuxOutOut) return hipErrorInvalidValue;
     if (wa.per != wa.nseg * (ba.n_rhs / ba.g) || wa.ntiles != ba.nb * wa.per) return hipErrorInvalidValue;
     if (ha.pre < kPreNone || ha.pre > kPreS) return hipErrorInvalidValue;
+    if (ha.clover && ba.g != 1) return hipErrorInvalidValue;  // clover hops: one rhs per thread
     // the staging updates: no fused dots; kPreP rewrites its input in place,
     // which only one tile per site may read
     if (ha.pre != kPreNone && (ha.dot_mode != kDotNone || !ha.pre_r || !ha.pre_v || !ha.pre_c0 || !ha.pre_act ||
@@ -626,6 +655,7 @@ static hipError_t launch_dhat_t(const BlkArgs &ba, const WalkArgs &wa, const Hop
 
 hipError_t launch_dhat_walk(const BlkArgs &ba, const WalkArgs &wa, const HopArgs &ha, dd_prec prec, hipStream_t s)
 {
+    if (ha.clover) return hipErrorInvalidValue;  // Wilson only: the clover solve takes two hop launches
     if (wa.ntiles <= 0) return hipSuccess;
     // one walk of a whole block per rhs (wa.nseg rhs per workgroup: 1 or 3);
     // the output is the even parity
@@ -741,38 +771,6 @@ hipError_t launch_dlam_walk(const BlkArgs &ba, const DlamArgs &da, dd_prec prec,
 
 // ---------------------------------------------------------------- packing
 
-struct PackGeom {
-    int L[4];
-    int nb;
-    const int64_t *soff;
-    const int32_t *h;
-    const int64_t *nbr_off;
-    const int32_t *nbr;
-    const int64_t *perm_off;
-    const int32_t *perm;
-    const int32_t *iperm;
-    const int32_t *origin;
-    const int32_t *ext;
-};
-
-__device__ __forceinline__ int find_block(const int64_t *soff, int nb, int64_t q)
-{
-    int lo = 0, hi = nb;  // soff[lo] <= q < soff[hi]
-    while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (soff[mid] <= q) lo = mid; else hi = mid;
-    }
-    return lo;
-}
-
-__device__ __forceinline__ void local_coords(int y, const int32_t *e, int c[4])
-{
-    c[3] = y % e[3]; y /= e[3];
-    c[2] = y % e[2]; y /= e[2];
-    c[1] = y % e[1]; y /= e[1];
-    c[0] = y;
-}
-
 template <typename LT>
 __device__ __forceinline__ LT cvt_link(double v);
 template <> __device__ __forceinline__ double cvt_link<double>(double v) { return v; }
@@ -811,22 +809,6 @@ __global__ void __launch_bounds__(256) k_pack_gauge(PackGeom g, const double *U,
     }
 }
 
-static PackGeom pack_geom(const dd_blocks *B)
-{
-    PackGeom g;
-    for (int m = 0; m < 4; m++) g.L[m] = B->L[m];
-    g.nb = B->nb;
-    g.soff = B->d_soff;
-    g.h = B->d_h;
-    g.nbr_off = B->d_nbr_off;
-    g.nbr = B->d_nbr;
-    g.perm_off = B->d_perm_off;
-    g.perm = B->d_perm;
-    g.iperm = B->d_iperm;
-    g.origin = B->d_origin;
-    g.ext = B->d_ext;
-    return g;
-}
 
 hipError_t launch_pack_gauge(const dd_blocks *B, const double *U, dd_prec prec, void *dst, hipStream_t s)
 {

@@ -96,6 +96,7 @@ extern "C" dd_status dd_block_logdet(dd_ctx *ctx, const dd_blocks *B, const dd_g
 {
     if (!ctx || !B || !G || (!logdet_dev && !total_host)) return fail(ctx, DD_EINVAL, "null argument");
     if (G->blocks != B) return fail(ctx, DD_EINVAL, "gauge was loaded for other blocks");
+    if (G->cl_csw != 0.0) return fail(ctx, DD_EUNSUPPORTED, "dd_block_logdet takes the Wilson operator only");
     if (B->nb == 0 || B->nb > 65535) return fail(ctx, DD_EINVAL, "need 1..65535 blocks");
     const int hb = B->shapes[B->shape_of[0]].h;
     for (int k = 1; k < B->nb; k++)

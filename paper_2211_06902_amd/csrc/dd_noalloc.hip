@@ -54,8 +54,8 @@ using namespace dd;
 extern "C" dd_status dd_apply_D_block_noalloc(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *G, double kappa,
                                               dd_prec prec, const void *x_dev, void *y_dev, int32_t n_rhs)
 {
-    const void *links = nullptr;
-    dd_status st = apply_D_check(ctx, B, G, prec, x_dev, y_dev, n_rhs, &links);
+    const void *links = nullptr, *clover = nullptr;
+    dd_status st = apply_D_check(ctx, B, G, prec, kappa, x_dev, y_dev, n_rhs, &links, &clover);
     if (st != DD_OK) return st;
     const size_t slot = (apply_D_half_bytes(B, n_rhs, prec) + 255) & ~size_t(255);
     if (4 * slot > kScratchBytes)
@@ -70,7 +70,7 @@ extern "C" dd_status dd_apply_D_block_noalloc(dd_ctx *ctx, const dd_blocks *B, c
     // no kernel timers here: their events are created on first use
     const bool timing = ctx->timing;
     ctx->timing = false;
-    st = apply_D_with(ctx, B, links, kappa, prec, x_dev, y_dev, n_rhs, hf);
+    st = apply_D_with(ctx, B, links, clover, kappa, prec, x_dev, y_dev, n_rhs, hf);
     ctx->timing = timing;
     return st;
 }

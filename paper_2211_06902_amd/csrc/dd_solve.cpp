@@ -72,6 +72,7 @@ struct Inner {
     // vector updates done by the first hop of Dhat as it stages its input
     bool fuse_s, fuse_p;
     bool dhat;  // Dhat as one x0-walk kernel (run_dhat)
+    const void *clover;  // A^-1 of the clover term (inner precision) or null
 };
 
 // one BiCGStab iteration on all pairs: 6 launches with the one-kernel Dhat
@@ -102,7 +103,9 @@ hipError_t bicg_iteration(const Inner &in)
         h1.pre_c1 = w.ps.omega;
         h1.pre_act = w.ps.active;
     }
+    h1.clover = in.clover;  // with the clover term: A_oo^-1 H_oe p, then p - kappa^2 A_ee^-1 H_eo (..)
     HopArgs h2 = hop_args(w.v, w.tmp, in.links, 0, -k2);
+    h2.clover = in.clover;
     h2.self = pp;
     h2.c_self = 1.0;
     h2.aux = w.rh;
@@ -139,7 +142,9 @@ hipError_t bicg_iteration(const Inner &in)
         h3.pre_c0 = w.ps.alpha;
         h3.pre_act = w.ps.active;
     }
+    h3.clover = in.clover;
     HopArgs h4 = hop_args(w.t, w.tmp, in.links, 0, -k2);
+    h4.clover = in.clover;
     h4.self = ss;
     h4.c_self = 1.0;
     h4.dot_mode = in.nn ? kDotOutAuxOutOut : kDotOutSelfOutOut;
@@ -292,6 +297,21 @@ dd_status block_solve_impl(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, 
     const void *links = links_for(G, ip);
     if (!links) return fail(ctx, DD_EINVAL, "gauge holds no links of the inner precision");
     const dd_prec sp = ip == DD_F64 ? DD_F64 : DD_F32;
+    // the clover term: A (FP64, outer residual) and A^-1 (inner precision) of
+    // every block site; the inner system is the asymmetric even-odd form
+    // 1 - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe, its two hops with A^-1 applied
+    // to their hop results (walk hops, one rhs per thread)
+    {
+        const dd_status cs = clover_check(ctx, G, kappa);
+        if (cs != DD_OK) return cs;
+    }
+    const void *cl_a64 = clover_for(G, DD_F64, false), *cl_inv = clover_for(G, ip, true);
+    if (cl_a64) {
+        if (gmres || nn) return fail(ctx, DD_EUNSUPPORTED, "the clover term is solved by BiCGStab without a network");
+        if (!cl_inv) return fail(ctx, DD_EINVAL, "gauge holds no clover term of the inner precision");
+        if (!Bc->walk || !ctx->hop_lds || ctx->hop_walk < 0)
+            return fail(ctx, DD_EUNSUPPORTED, "the clover solve needs blocks the x0-walk hop handles");
+    }
     const double inner_tol = prm.inner_tol > 0 ? prm.inner_tol : default_inner_tol(ip, prm.tol);
     // with the default inner tolerance and a low-precision inner solve, a later
     // cycle's BiCGStab stops once it has gained what is left to reach tol
@@ -307,7 +327,7 @@ dd_status block_solve_impl(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, 
     // the FP64 residual kernels and the inner-precision kernels may group rhs
     // differently; a scalar kernel reads partials with the tiling of the
     // kernel that wrote them
-    const int g64 = hop_group(ctx, n_rhs, DD_F64, DD_F64), gsp = hop_group(ctx, n_rhs, sp, ip);
+    const int g64 = hop_group(ctx, n_rhs, DD_F64, DD_F64), gsp = cl_a64 ? 1 : hop_group(ctx, n_rhs, sp, ip);
     const TileTable tt64 = tiles_for(B, n_rhs, g64), ttsp = tiles_for(B, n_rhs, gsp);
     const BlkArgs ba64 = blk_args(B, tt64, n_rhs, g64);
     const BlkArgs ba = blk_args(B, ttsp, n_rhs, gsp);
@@ -408,9 +428,9 @@ dd_status block_solve_impl(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, 
     HIPCHECK(ctx, launch_pack_spinor(B, (const double *)b_dev, w.be, w.bo, DD_F64, n_rhs, st));
 
     Inner in{ctx, B, ba, &w, links, ip, sp, kappa, inner_tol, gmres ? nullptr : nn, bc_ph, bc_sh, n_rhs,
-             false, false, false};
+             false, false, false, cl_a64 ? cl_inv : nullptr};
     if (!gmres) {
-        in.dhat = dhat_walk_applies(ctx, B, ba, ip);
+        in.dhat = !cl_a64 && dhat_walk_applies(ctx, B, ba, ip);
         if (!nn && ctx->bicg_fuse == 0) {
             const int nseg = in.dhat ? 1 : hop_walk_segments(ctx, B, ba, ip);
             in.fuse_s = nseg >= 1;
@@ -437,6 +457,12 @@ dd_status block_solve_impl(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, 
             HopArgs h = hop_args(p ? w.ro : w.re, p ? w.xe : w.xo, G->d_u64, p, kappa);
             h.self = p ? w.xo : w.xe;
             h.c_self = -1.0;
+            if (cl_a64) {
+                // r_p = b_p - A_pp x_p + kappa H x_{1-p}: A_pp x_p into r_p first
+                HIPCHECK(ctx, launch_clover_apply(B, cl_a64, h.self, h.out, p, n_rhs, DD_F64,
+                                                  cyc >= 2 ? w.os.active : nullptr, st));
+                h.self = h.out;
+            }
             h.add = p ? w.bo : w.be;
             h.c_add = 1.0;
             h.dot_mode = kDotOutOut;
@@ -464,11 +490,22 @@ dd_status block_solve_impl(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, 
             ri_o = r_o;
         }
         {
+            // with the clover term: rhs = A_ee^-1 (r_e + kappa H_eo A_oo^-1 r_o),
+            // the odd part kept as A_oo^-1 r_o for the odd solution below
+            if (cl_a64) {
+                // into the residual's own workspace: with FP64 inner solves in
+                // the first cycle ri_o is the source b_o itself
+                void *dst = sp == DD_F64 ? (void *)w.ro : w.rio;
+                HIPCHECK(ctx, launch_clover_apply(B, cl_inv, ri_o, dst, 1, n_rhs, sp, w.os.active, st));
+                ri_o = dst;
+            }
             HopArgs h = hop_args(w.rhs, ri_o, links, 0, kappa);
             h.self = ri_e;
             h.c_self = 1.0;
             if (cyc >= 1) h.skip_act = w.os.active;  // pairs this cycle solves
             HIPCHECK(ctx, run_hop(ctx, B, ba, h, ip));
+            if (cl_a64)
+                HIPCHECK(ctx, launch_clover_apply(B, cl_inv, w.rhs, w.rhs, 0, n_rhs, sp, w.os.active, st));
         }
         if (gmres) {
             GmArgs ga;
@@ -586,6 +623,7 @@ dd_status block_solve_impl(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, 
             HopArgs h = hop_args(w.tmp, w.xi, links, 1, kappa);
             h.self = ri_o;
             h.c_self = 1.0;
+            h.clover = cl_inv;  // e_o = A_oo^-1 r_o + kappa A_oo^-1 H_oe e_e
             if (cyc >= 1) h.skip_act = w.os.active;  // the accumulation masks the others
             HIPCHECK(ctx, run_hop(ctx, B, ba, h, ip));
         }

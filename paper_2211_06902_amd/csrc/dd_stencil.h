@@ -567,4 +567,101 @@ __device__ __forceinline__ void dhat_run(const WalkPos &wodd, const WalkPos &wev
     if (live) epi(acc2, (ns - 1) * hs + k);
 }
 
+// ------------------------------------------------------------ clover term
+
+// v <- C v for one site's spinor v[24] (component 2 (3 s + c) + re/im): C is
+// block diagonal in the chirality (spins 0, 1 and spins 2, 3 of the chiral
+// basis), each block a hermitian 6x6 over (spin within the block, colour)
+// stored as its 6 real diagonal entries, then the 15 complex entries above
+// the diagonal row by row ((0,1), (0,2), .., (0,5), (1,2), .., (4,5)); the
+// entries below are their conjugates.  Real k of the site's kCloverReals is
+// at byte voff + k * kstr of cb (one site per voff, structure of arrays).
+template <typename CT, typename AC>
+__device__ __forceinline__ void clover_mul(AC (&v)[24], const Buf &cb, uint32_t voff, uint32_t kstr)
+{
+#pragma unroll
+    for (int c = 0; c < 2; c++) {
+        AC xr[6], xi[6], yr[6], yi[6];
+#pragma unroll
+        for (int i = 0; i < 6; i++) {
+            xr[i] = v[2 * (6 * c + i)];
+            xi[i] = v[2 * (6 * c + i) + 1];
+            const AC d = (AC)bload<CT, kKeep>(cb, voff, (uint32_t)(c * kCloverHalf + i) * kstr);
+            yr[i] = d * xr[i];
+            yi[i] = d * xi[i];
+        }
+        int t = 0;
+#pragma unroll
+        for (int i = 0; i < 6; i++)
+#pragma unroll
+            for (int j = i + 1; j < 6; j++, t++) {
+                const uint32_t k = (uint32_t)(c * kCloverHalf + 6 + 2 * t);
+                const AC hr = (AC)bload<CT, kKeep>(cb, voff, k * kstr);
+                const AC hi = (AC)bload<CT, kKeep>(cb, voff, (k + 1) * kstr);
+                // y_i += h_ij x_j, y_j += conj(h_ij) x_i
+                yr[i] = fmad(hr, xr[j], fmad(-hi, xi[j], yr[i]));
+                yi[i] = fmad(hr, xi[j], fmad(hi, xr[j], yi[i]));
+                yr[j] = fmad(hr, xr[i], fmad(hi, xi[i], yr[j]));
+                yi[j] = fmad(hr, xi[i], fmad(-hi, xr[i], yi[j]));
+            }
+#pragma unroll
+        for (int i = 0; i < 6; i++) {
+            v[2 * (6 * c + i)] = yr[i];
+            v[2 * (6 * c + i) + 1] = yi[i];
+        }
+    }
+}
+
+// ------------------------------------------------------ site geometry
+
+// What the packing kernels need to map a block slot to its global site.
+struct PackGeom {
+    int L[4];
+    int nb;
+    const int64_t *soff;
+    const int32_t *h;
+    const int64_t *nbr_off;
+    const int32_t *nbr;
+    const int64_t *perm_off;
+    const int32_t *perm;
+    const int32_t *iperm;
+    const int32_t *origin;
+    const int32_t *ext;
+};
+
+__device__ __forceinline__ int find_block(const int64_t *soff, int nb, int64_t q)
+{
+    int lo = 0, hi = nb;  // soff[lo] <= q < soff[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (soff[mid] <= q) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ void local_coords(int y, const int32_t *e, int c[4])
+{
+    c[3] = y % e[3]; y /= e[3];
+    c[2] = y % e[2]; y /= e[2];
+    c[1] = y % e[1]; y /= e[1];
+    c[0] = y;
+}
+
+inline PackGeom pack_geom(const dd_blocks *B)
+{
+    PackGeom g;
+    for (int m = 0; m < 4; m++) g.L[m] = B->L[m];
+    g.nb = B->nb;
+    g.soff = B->d_soff;
+    g.h = B->d_h;
+    g.nbr_off = B->d_nbr_off;
+    g.nbr = B->d_nbr;
+    g.perm_off = B->d_perm_off;
+    g.perm = B->d_perm;
+    g.iperm = B->d_iperm;
+    g.origin = B->d_origin;
+    g.ext = B->d_ext;
+    return g;
+}
+
 }  // namespace dd

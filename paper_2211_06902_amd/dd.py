@@ -136,6 +136,7 @@ _sig("dd_blocks_exterior", _I32, [_P, _P, _P, _P, _P, _P])
 _sig("dd_load_gauge", _I32, [_P, _P, _P, _I32, _PP])
 _sig("dd_free_gauge", _I32, [_P])
 _sig("dd_gauge_export", _I32, [_P, _P, _I32, _P])
+_sig("dd_gauge_set_clover", _I32, [_P, _P, _P, _D, _D])
 _sig("dd_apply_D_block", _I32, [_P, _P, _P, _D, _I32, _P, _P, _I32])
 _sig("dd_apply_D_block_noalloc", _I32, [_P, _P, _P, _D, _I32, _P, _P, _I32])
 _sig("dd_solve_params_default", None, [ctypes.POINTER(SolveParams)])
@@ -390,6 +391,13 @@ class Gauge:
         out = torch.empty(n, dtype=dt, device="cuda")
         self._ctx._check(_lib.dd_gauge_export(self._ctx._h, self._h, _PREC[prec], _P(out.data_ptr())))
         return out
+
+    def set_clover(self, U, kappa, csw):
+        """The clover term for this gauge's operator from the global FP64 field U [V, 4, 3, 3]
+        (c_sw = 0: back to the Wilson operator); later operators and solves must use this kappa."""
+        self._ctx._check(_lib.dd_gauge_set_clover(self._ctx._h, self._h, _dev(U, "torch.complex128") if csw else None,
+                                                  float(kappa), float(csw)))
+        return self
 
     def close(self):
         if self._h:
