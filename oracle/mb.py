@@ -24,7 +24,8 @@ import numpy as np
 
 from . import geometry, wilson
 
-__all__ = ["boundary_lists", "mb_local_action", "exterior_source", "mb_local_action_from_chi"]
+__all__ = ["boundary_lists", "mb_local_action", "exterior_source", "mb_local_action_from_chi", "mb_global_action",
+           "solve_masked"]
 
 
 def boundary_lists(L, boxes, inner):
@@ -117,3 +118,66 @@ def mb_local_action_from_chi(L, tbc, kappa, U, boxes, inner, u, chi, tol=1e-12, 
     chib = np.concatenate(chib, axis=1)
     xi = exterior_source(L, tbc, kappa, U, boxes, inner, chi, "all")
     return mb_local_action(L, tbc, kappa, U, boxes, inner, u, chib, xi, tol=tol, nthreads=nthreads)
+
+
+def solve_masked(L, tbc, kappa, U, mask, f, tol=1e-13, maxit=20000):
+    """y = D_X^{-1} f for the site set X = mask (Dirichlet: D_X is the principal sub-matrix of D on
+    X), by plain BiCGStab on the vectors supported on X; f [V, 4, 3] (its values outside X are not
+    used); y is zero outside X."""
+    def op(y):
+        out = wilson.dirac_full(L, tbc, kappa, U, y)
+        out[~mask] = 0.0
+        return out
+
+    b = np.zeros_like(np.asarray(f, dtype=np.complex128))
+    b[mask] = np.asarray(f)[mask]
+    bn = np.linalg.norm(b)
+    x = np.zeros_like(b)
+    if bn == 0.0:
+        return x
+    r = b.copy()
+    rh = r.copy()
+    rho = alpha = omega = 1.0 + 0j
+    v = np.zeros_like(b)
+    p = np.zeros_like(b)
+    for _ in range(maxit):
+        rho_new = np.vdot(rh, r)
+        beta = (rho_new / rho) * (alpha / omega)
+        rho = rho_new
+        p = r + beta * (p - omega * v)
+        v = op(p)
+        alpha = rho / np.vdot(rh, v)
+        s = r - alpha * v
+        t = op(s)
+        omega = np.vdot(t, s) / np.vdot(t, t)
+        x = x + alpha * p + omega * s
+        r = s - omega * t
+        if np.linalg.norm(r) <= tol * bn:
+            break
+    else:
+        raise RuntimeError("oracle masked solve did not converge")
+    true = np.linalg.norm(b - op(x)) / bn
+    if true > 100 * tol:
+        raise RuntimeError("oracle masked solve: true residual %.3g" % true)
+    return x
+
+
+def mb_global_action(L, tbc, kappa, U, boxes, inner, u, chi, tol=1e-13):
+    """S^r_MB of eq. (globalMB) per field k: |u_k chi_k + W_{dPi1,dL0} chi_k|^2 summed over dPi_1 (the
+    dPi_1 rows of W_{u_k} chi_k; field k at z = u_k as for the local term).  Reading: eliminating
+    Lambda1bar from D_{Lambda_1} (Lambda_1 = Lambda1bar u dPi_1) gives
+      W_{dPi1,dL0} chi = Dhat_{dPi1}^{-1} Dhat_{dPi1,dL0} chi = [D_{Lambda_1}^{-1} D_{Lambda_1,dL0} chi]_{dPi_1},
+    one solve on the inactive region Lambda_1 per field.  chi [n_fields, V, 4, 3] on dPi (values
+    elsewhere not used).  Returns the per-field values [n_fields]."""
+    B = geometry.BoxDomains(L, boxes, inner)
+    u = np.asarray(u, dtype=np.complex128).reshape(-1)
+    chi = np.asarray(chi, dtype=np.complex128)
+    out = np.zeros(u.size)
+    for k in range(u.size):
+        c = np.zeros_like(chi[k])
+        c[B.dlam0] = chi[k][B.dlam0]
+        f = wilson.dirac_full(L, tbc, kappa, U, c)  # D_{Lambda_1, dLambda_0} chi on Lambda_1
+        v = solve_masked(L, tbc, kappa, U, B.lam1, f, tol=tol)
+        w = u[k] * chi[k][B.dPi1] + v[B.dPi1]
+        out[k] = float(np.sum(np.abs(w) ** 2))
+    return out

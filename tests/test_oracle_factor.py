@@ -9,7 +9,9 @@ eq. (localMB) (oracle/mb.py) by dense linear algebra on tiny lattices.
   the printed bracket read with zero-extended inverses misses det W_1;
 * the sets of geometry.BoxDomains (explicit boxes) are those of geometry.PaperDomains;
 * S^a of eq. (localMB) from the dense W_z equals |u chi + D_Omega^{-1} xi| on dLambda_0^a with
-  xi the exterior source (hops from dPi into Omega_0^a), and the parts of xi add up.
+  xi the exterior source (hops from dPi into Omega_0^a), and the parts of xi add up;
+* S^r of eq. (globalMB) from one solve on Lambda_1 (mb.mb_global_action) equals the dPi_1 rows of the
+  dense W_z chi, which with the block terms make up |W_z chi|^2 (eq. MBaction).
 """
 import numpy as np
 import pytest
@@ -137,6 +139,9 @@ def test_exterior_source_reproduces_local_mb_action(geom):
     assert np.max(np.abs(S_lib - S_dense) / S_dense) <= 1e-12
     # eq. (MBaction): the block terms and the global rest make up |W_z chi|^2
     assert abs(S_dense.sum() + S_rest - np.sum(np.abs(Wc) ** 2)) <= 1e-12 * np.sum(np.abs(Wc) ** 2)
+    # eq. (globalMB) from one solve on Lambda_1 equals the dense dPi_1 rows of W_z chi
+    S_r = mb.mb_global_action(L, -1, kappa, U, boxes, inner, [z], chi)
+    assert S_rest > 0 and abs(S_r[0] - S_rest) <= 1e-10 * S_rest
 
 
 def test_exterior_source_dpi1_part_is_the_offdiagonal_term():
