@@ -127,6 +127,26 @@ dd_status dd_make_blocks_boxes(dd_ctx *ctx, const int32_t L[4], int32_t time_bc,
  * the other constructors. */
 dd_status dd_make_frames(dd_ctx *ctx, const dd_blocks *blocks, dd_blocks **out);
 
+/* The inactive region Lambda_1 of Section 2 as one solve domain (for the
+ * global rest of the multi-boson action, Section 4 eq. globalMB): a single
+ * block spanning the whole lattice (origin 0, extent L: its box-local
+ * canonical order is the global one; hops wrap, with the antiperiodic time
+ * sign) minus the union of the inner boxes of `blocks` (the active region
+ * Lambda_0), whose sites are decoupled as in a frame's hole.  Its exterior
+ * hops (dd_blocks_exterior, dd_mb_exterior_source with parts 2) are the hops
+ * from the active boxes into the domain; dd_blocks_dpi1 lists its dPi_1
+ * sites.  The domain is one block of V sites: its solves take the chunked
+ * hop kernel (a block spanning the lattice in x0 has no x0-walk) and memory
+ * for V sites per field.  DD_EINVAL when the inner boxes cover the lattice
+ * (no inactive region) or V > 2^30.  ctx may be NULL (host tables only). */
+dd_status dd_make_inactive(dd_ctx *ctx, const dd_blocks *blocks, dd_blocks **out);
+/* The dPi_1 sites of an inactive-region domain (sites of Lambda_1 with some
+ * coordinate on a face coordinate of an active box, in directions where the
+ * box does not span the lattice), ascending global canonical indices:
+ * *n_sites their number; sites (may be NULL) at least that many entries.
+ * DD_EINVAL for blocks not made by dd_make_inactive. */
+dd_status dd_blocks_dpi1(const dd_blocks *blocks, int64_t *n_sites, int64_t *sites);
+
 dd_status dd_free_blocks(dd_blocks *blocks);
 
 /* Sizes: number of blocks, total block sites (sum of box volumes), total
@@ -153,7 +173,7 @@ dd_status dd_blocks_tables(const dd_blocks *blocks, int32_t *boxes, int64_t *sit
 dd_status dd_blocks_exterior(const dd_blocks *blocks, int64_t *n_hops, int32_t *block, int32_t *site, int32_t *code,
                              int64_t *nbr);
 
-/* The three constructors above accept ctx == NULL: the blocks then hold host
+/* The constructors above accept ctx == NULL: the blocks then hold host
  * tables only (for dd_blocks_query / dd_blocks_tables) and every call that
  * needs the device rejects them with DD_EINVAL. */
 
@@ -344,6 +364,28 @@ dd_status dd_multiboson_action(dd_ctx *ctx, const dd_blocks *blocks, const dd_ga
  * The links of the exterior hops are copied by dd_load_gauge (FP64). */
 dd_status dd_mb_exterior_source(dd_ctx *ctx, const dd_blocks *blocks, const dd_gauge *gauge, double kappa,
                                 int32_t n_fields, const void *chi_global_dev, void *xi_dev, int32_t parts);
+
+/* The global rest of the multi-boson action (Section 4, eq. globalMB) for
+ * n_fields fields, field k at z = u_k (as for dd_multiboson_action):
+ *   S^r_k = sum_{x in dPi_1} | u_k chi_k(x) + (W_{dPi1,dL0} chi_k)(x) |^2,
+ * with W_{dPi1,dL0} chi = Dhat_{dPi1}^{-1} Dhat_{dPi1,dL0} chi computed as
+ * [D_{Lambda_1}^{-1} D_{Lambda_1,dLambda_0} chi] on dPi_1 (eliminating
+ * Lambda1bar from D_{Lambda_1} gives the same vector): per field, the source
+ * from the hops out of the active boxes (dd_mb_exterior_source), one
+ * dd_block_solve on the inactive region with params (as for dd_block_solve;
+ * NULL: defaults), and an FP64 fixed-order sum over dPi_1.  domain: made by
+ * dd_make_inactive; gauge: loaded for it (dd_load_gauge copies the links of
+ * its exterior hops), optionally with the clover term.  u_host: [n_fields]
+ * complex (re, im); chi_global_dev: [n_fields][V][4][3] complex128 on the
+ * whole lattice in canonical order (the values on dPi are read).  Fields are
+ * solved a few at a time as memory allows (DD_TUNE_MB_FIELDS forces the
+ * group size).  Outputs: S_field_host [n_fields] and *S_total_host (each may
+ * be NULL); stats per field (pair = field), may be NULL.  Returns DD_ENOCONV
+ * when some field's solve missed the tolerance (its value is still written). */
+dd_status dd_mb_global_action(dd_ctx *ctx, const dd_blocks *domain, const dd_gauge *gauge, double kappa,
+                              int32_t n_fields, const double *u_host, const void *chi_global_dev,
+                              const dd_solve_params *params, double *S_field_host, double *S_total_host,
+                              dd_solve_stats *stats);
 
 /* Per-block log-determinants (Section 3, eq. detD and the effective action
  * after it: the block factors ln det D_{Omega_0^a} on framed blocks, and

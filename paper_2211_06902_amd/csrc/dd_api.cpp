@@ -473,7 +473,8 @@ dd_status finish_blocks(dd_ctx *ctx, dd_blocks *B, dd_blocks **out)
         (!B->x_code.empty() &&
          ((e = upload(&B->d_xg_block, B->xg_block)) != hipSuccess || (e = upload(&B->d_xg_site, B->xg_site)) != hipSuccess ||
           (e = upload(&B->d_xg_first, B->xg_first)) != hipSuccess || (e = upload(&B->d_x_code, B->x_code)) != hipSuccess ||
-          (e = upload(&B->d_x_nbr, B->x_nbr)) != hipSuccess || (e = upload(&B->d_x_link, B->x_link)) != hipSuccess))) {
+          (e = upload(&B->d_x_nbr, B->x_nbr)) != hipSuccess || (e = upload(&B->d_x_link, B->x_link)) != hipSuccess)) ||
+        (!B->dpi1.empty() && (e = upload(&B->d_dpi1, B->dpi1)) != hipSuccess)) {
         dd_free_blocks(B);
         return fail(ctx, DD_EDEVICE, std::string("geometry upload: ") + hipGetErrorString(e));
     }
@@ -604,6 +605,27 @@ dd_status dd_make_frames(dd_ctx *ctx, const dd_blocks *blocks, dd_blocks **out)
     return make_from_boxes(ctx, blocks->L, blocks->tbc, blocks->nb, boxes.data(), inner.data(), out, true);
 }
 
+dd_status dd_make_inactive(dd_ctx *ctx, const dd_blocks *blocks, dd_blocks **out)
+{
+    if (!blocks || !out) return fail(ctx, DD_EINVAL, "null argument");
+    *out = nullptr;
+    if (ctx && enter(ctx) != hipSuccess) return fail(ctx, DD_EDEVICE, "hipSetDevice failed");
+    dd_blocks *D = new (std::nothrow) dd_blocks();
+    if (!D) return fail(ctx, DD_ENOMEM, "out of host memory");
+    D->ctx = ctx;
+    D->device = ctx ? ctx->device : -1;
+    const std::string msg = build_inactive(D, blocks);
+    if (!msg.empty()) {
+        delete D;
+        return fail(ctx, DD_EINVAL, msg);
+    }
+    if (!ctx) {  // host tables only
+        *out = D;
+        return DD_OK;
+    }
+    return finish_blocks(ctx, D, out);
+}
+
 dd_status dd_free_blocks(dd_blocks *B)
 {
     if (!B) return DD_EINVAL;
@@ -611,7 +633,7 @@ dd_status dd_free_blocks(dd_blocks *B)
     void *ptrs[] = {B->d_nbr,    B->d_perm,   B->d_iperm,  B->d_soff, B->d_h,    B->d_nlinks,
                     B->d_nbr_off, B->d_perm_off, B->d_origin, B->d_ext,  B->d_bnd,  B->d_boff,
                     B->d_chunk,  B->d_chunk_block, B->d_blk_chunk0, B->d_xg_block, B->d_xg_site,
-                    B->d_xg_first, B->d_x_code, B->d_x_nbr, B->d_x_link};
+                    B->d_xg_first, B->d_x_code, B->d_x_nbr, B->d_x_link, B->d_dpi1};
     for (void *p : ptrs)
         if (p) hipFree(p);
     for (auto &kv : B->queues) {
@@ -658,6 +680,15 @@ dd_status dd_blocks_tables(const dd_blocks *B, int32_t *boxes, int64_t *sites, i
             for (int k = 0; k < sh.S; k++) eo[s0 + B->perm[sh.perm_off + k]] = k;
     }
     if (bnd) std::memcpy(bnd, B->bnd.data(), B->bnd.size() * sizeof(int32_t));
+    return DD_OK;
+}
+
+dd_status dd_blocks_dpi1(const dd_blocks *B, int64_t *n_sites, int64_t *sites)
+{
+    if (!B || !n_sites) return DD_EINVAL;
+    if (!B->inactive) return fail(nullptr, DD_EINVAL, "not an inactive-region domain (dd_make_inactive)");
+    *n_sites = (int64_t)B->dpi1.size();
+    if (sites) std::memcpy(sites, B->dpi1.data(), B->dpi1.size() * sizeof(int64_t));
     return DD_OK;
 }
 

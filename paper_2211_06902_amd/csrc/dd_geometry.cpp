@@ -28,9 +28,12 @@ struct ShapeKey {
     }
 };
 
+inline int lidx(const int e[4], const int y[4]);
+
 inline bool in_hole(const Shape &sh, const int y[4])
 {
     if (!sh.hole) return false;
+    if (sh.hole == 2) return sh.mask[lidx(sh.e, y)] != 0;
     for (int m = 0; m < 4; m++)
         if (y[m] < sh.hio[m] || y[m] >= sh.hio[m] + sh.hie[m]) return false;
     return true;
@@ -142,16 +145,19 @@ int64_t build_shape(Shape &sh, int tbc, std::vector<int32_t> &perm, std::vector<
 // block, the hops into the box from exterior sites in either part are listed,
 // grouped by receiving site.  Nothing is built when every inner box is its
 // block (no frames).
-void build_exterior(dd_blocks *B)
+// The active sets on the lattice (global canonical index): lam0 (the union
+// of the inner boxes), dlam0 (their boundary sites: a coordinate on a face of
+// the box in a direction where it does not span the lattice), and face[m]
+// (the coordinates along m that carry a face of some inner box: dPi is the
+// sites with some coordinate among them).
+void active_sets(const dd_blocks *B, std::vector<uint8_t> &lam0, std::vector<uint8_t> &dlam0,
+                 std::vector<uint8_t> (&face)[4])
 {
     const int *L = B->L;
-    bool framed = false;
-    for (int k = 0; k < B->nb; k++)
-        for (int m = 0; m < 4; m++) framed = framed || B->box[16 * k + 12 + m] != B->box[16 * k + 4 + m];
-    if (!framed || B->hole[0]) return;  // no frames, or frame domains themselves
     const int64_t V = (int64_t)L[0] * L[1] * L[2] * L[3];
     auto gidx = [&](const int x[4]) { return (((int64_t)x[0] * L[1] + x[1]) * L[2] + x[2]) * L[3] + x[3]; };
-    std::vector<uint8_t> face[4], lam0(V, 0), dlam0(V, 0);
+    lam0.assign(V, 0);
+    dlam0.assign(V, 0);
     for (int m = 0; m < 4; m++) face[m].assign(L[m], 0);
     for (int k = 0; k < B->nb; k++) {
         const int32_t *r = &B->box[16 * k];
@@ -177,6 +183,18 @@ void build_exterior(dd_blocks *B)
             if (bnd) dlam0[gidx(x)] = 1;
         }
     }
+}
+
+void build_exterior(dd_blocks *B)
+{
+    const int *L = B->L;
+    bool framed = false;
+    for (int k = 0; k < B->nb; k++)
+        for (int m = 0; m < 4; m++) framed = framed || B->box[16 * k + 12 + m] != B->box[16 * k + 4 + m];
+    if (!framed || B->hole[0]) return;  // no frames, or frame domains themselves
+    auto gidx = [&](const int x[4]) { return (((int64_t)x[0] * L[1] + x[1]) * L[2] + x[2]) * L[3] + x[3]; };
+    std::vector<uint8_t> face[4], lam0, dlam0;
+    active_sets(B, lam0, dlam0, face);
     B->xg_first.assign(1, 0);
     for (int k = 0; k < B->nb; k++) {
         const int32_t *r = &B->box[16 * k];
@@ -322,6 +340,76 @@ std::string build_geometry(dd_blocks *B, const int L[4], int tbc, int n, const i
     B->walk = n > 0;
     for (const Shape &sh : B->shapes) B->walk = B->walk && sh.walk_hs > 0;
     build_exterior(B);
+    return "";
+}
+
+std::string build_inactive(dd_blocks *D, const dd_blocks *B)
+{
+    const int *L = B->L;
+    const int64_t V = (int64_t)L[0] * L[1] * L[2] * L[3];
+    if (V > ((int64_t)1 << 30)) return "lattice too large for one inactive-region domain";
+    auto gidx = [&](const int x[4]) { return (((int64_t)x[0] * L[1] + x[1]) * L[2] + x[2]) * L[3] + x[3]; };
+    std::vector<uint8_t> face[4], lam0, dlam0;
+    active_sets(B, lam0, dlam0, face);
+    int64_t n_in = 0;
+    for (int64_t n = 0; n < V; n++) n_in += lam0[n] == 0;
+    if (n_in == 0) return "the active boxes cover the lattice: no inactive region";
+    const int32_t box[8] = {0, 0, 0, 0, L[0], L[1], L[2], L[3]};
+    const std::string msg = build_geometry(D, L, B->tbc, 1, box, box, false);
+    if (!msg.empty()) return msg;
+    // the active boxes become the shape's excluded sites (its local canonical
+    // index is the global one: origin 0, extent L)
+    Shape &sh = D->shapes[0];
+    sh.hole = 2;
+    sh.mask = lam0;
+    D->perm.clear();
+    D->nbr.clear();
+    sh.links = build_shape(sh, B->tbc, D->perm, D->nbr);
+    D->inner_links = sh.links;
+    D->walk = sh.walk_hs > 0;
+    D->hole.assign(1, 2);
+    D->inactive = true;
+    // hops from the active boxes into the domain, grouped by receiving site
+    D->xg_block.clear();
+    D->xg_site.clear();
+    D->x_code.clear();
+    D->x_nbr.clear();
+    D->x_link.clear();
+    D->xg_first.assign(1, 0);
+    D->dpi1.clear();
+    for (int64_t n = 0; n < V; n++) {
+        if (lam0[n]) continue;
+        int x[4];
+        {
+            int64_t t = n;
+            x[3] = (int)(t % L[3]);
+            t /= L[3];
+            x[2] = (int)(t % L[2]);
+            t /= L[2];
+            x[1] = (int)(t % L[1]);
+            x[0] = (int)(t / L[1]);
+        }
+        bool on_pi = false;
+        for (int m = 0; m < 4; m++) on_pi = on_pi || face[m][x[m]];
+        if (on_pi) D->dpi1.push_back(n);
+        const size_t first = D->x_code.size();
+        for (int mu = 0; mu < 4; mu++)
+            for (int f = 0; f < 2; f++) {
+                int xn[4] = {x[0], x[1], x[2], x[3]};
+                xn[mu] = (x[mu] + (f ? L[mu] - 1 : 1)) % L[mu];
+                const int64_t nn = gidx(xn);
+                if (!lam0[nn]) continue;
+                const bool sign = B->tbc < 0 && mu == 0 && ((f == 0 && x[0] == L[0] - 1) || (f == 1 && x[0] == 0));
+                D->x_code.push_back((2 * mu + f) | (sign ? 8 : 0) | (2 << 4));
+                D->x_nbr.push_back(nn);
+                D->x_link.push_back(4 * (f ? nn : n) + mu);
+            }
+        if (D->x_code.size() > first) {
+            D->xg_block.push_back(0);
+            D->xg_site.push_back((int32_t)n);
+            D->xg_first.push_back((int32_t)D->x_code.size());
+        }
+    }
     return "";
 }
 

@@ -13,4 +13,10 @@ namespace dd {
 std::string build_geometry(dd_blocks *B, const int L[4], int tbc, int n, const int32_t *boxes,
                            const int32_t *inner, bool frames = false);
 
+// Fill the host tables of D as the inactive-region domain of B: one block,
+// the whole lattice minus the union of B's inner boxes (their sites
+// decoupled), the hops from those boxes into it as exterior hops, and the
+// dPi_1 site list.  Returns "" or an error message.
+std::string build_inactive(dd_blocks *D, const dd_blocks *B);
+
 }  // namespace dd

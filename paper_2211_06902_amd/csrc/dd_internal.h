@@ -91,8 +91,11 @@ struct Shape {
     // A frame shape: the solve domain is the box minus the hole hio + [0, hie)
     // (local coordinates); hole sites are decoupled (every hop into or out of
     // the hole is dropped, so D acts as the identity there).
+    // hole == 2: the excluded sites are those of mask (local canonical index),
+    // e.g. every active box of an inactive-region domain
     int hole = 0;
     int hio[4] = {0, 0, 0, 0}, hie[4] = {0, 0, 0, 0};
+    std::vector<uint8_t> mask;
     // Sites per parity of an x0-slice when the x0-walk of the hop applies to
     // the shape (the eo index of a site's x0-neighbour is its own index
     // +/- walk_hs in the other parity, hops along 1..3 stay in the slice, and
@@ -173,6 +176,13 @@ struct dd_blocks {
     std::vector<int64_t> x_nbr, x_link;
     int32_t *d_xg_block = nullptr, *d_xg_site = nullptr, *d_xg_first = nullptr, *d_x_code = nullptr;
     int64_t *d_x_nbr = nullptr, *d_x_link = nullptr;
+    // An inactive-region domain (dd_make_inactive): one block, the whole
+    // lattice minus the active boxes of the blocks it was made from; its
+    // exterior hops are those from the active boxes into the domain (part 2),
+    // and dpi1 lists the global canonical index of every site of dPi_1.
+    bool inactive = false;
+    std::vector<int64_t> dpi1;
+    int64_t *d_dpi1 = nullptr;
 };
 
 struct dd_gauge {

@@ -129,6 +129,8 @@ _sig("dd_make_blocks", _I32, [_P, _P, _I32, _P, _P, _P, _I32, _PP])
 _sig("dd_make_blocks_paper", _I32, [_P, _P, _I32, _P, _PP])
 _sig("dd_make_blocks_boxes", _I32, [_P, _P, _I32, _I32, _P, _P, _PP])
 _sig("dd_make_frames", _I32, [_P, _P, _PP])
+_sig("dd_make_inactive", _I32, [_P, _P, _PP])
+_sig("dd_blocks_dpi1", _I32, [_P, _P, _P])
 _sig("dd_free_blocks", _I32, [_P])
 _sig("dd_blocks_query", _I32, [_P, _P, _P, _P, _P])
 _sig("dd_blocks_tables", _I32, [_P, _P, _P, _P, _P])
@@ -148,6 +150,8 @@ _sig("dd_tune_set", _I32, [_P, _I32, _I32])
 _sig("dd_mb_roots", _I32, [_I32, _D, _P])
 _sig("dd_block_logdet", _I32, [_P, _P, _P, _D, _P, _P])
 _sig("dd_mb_exterior_source", _I32, [_P, _P, _P, _D, _I32, _P, _P, _I32])
+_sig("dd_mb_global_action", _I32, [_P, _P, _P, _D, _I32, _P, _P, ctypes.POINTER(SolveParams), _P, _P,
+                                 ctypes.POINTER(SolveStats)])
 _sig("dd_nn_num_weights", _I64, [])
 _sig("dd_nn_create", _I32, [_P, _P, _I32, _P, _PP])
 _sig("dd_nn_free", _I32, [_P])
@@ -329,6 +333,17 @@ class Blocks:
             _lib.dd_blocks_exterior(self._h, ctypes.byref(n), _ptr(blk), _ptr(site), _ptr(code), _ptr(nbr))
         return blk, site, code, nbr
 
+    def dpi1(self):
+        """dPi_1 sites of an inactive-region domain (global canonical indices, ascending)."""
+        n = _I64()
+        st = _lib.dd_blocks_dpi1(self._h, ctypes.byref(n), None)
+        if st != DD_OK:
+            raise DDError(st, _lib.dd_last_error(None).decode())
+        out = np.zeros(n.value, dtype=np.int64)
+        if n.value:
+            _lib.dd_blocks_dpi1(self._h, ctypes.byref(n), _ptr(out))
+        return out
+
     def close(self):
         if self._h:
             _lib.dd_free_blocks(self._h)
@@ -365,6 +380,11 @@ def make_blocks_paper(ctx, L, time_bc, bd) -> Blocks:
 def make_frames(ctx, blocks) -> Blocks:
     """The frames (box minus inner box) of `blocks` as solve domains."""
     return _make(_lib.dd_make_frames, ctx, blocks._h)
+
+
+def make_inactive(ctx, blocks) -> Blocks:
+    """The inactive region (the lattice minus the inner boxes of `blocks`) as one solve domain."""
+    return _make(_lib.dd_make_inactive, ctx, blocks._h)
 
 
 def make_blocks_boxes(ctx, L, time_bc, boxes, inner=None) -> Blocks:
@@ -454,6 +474,9 @@ class Context:
 
     def make_frames(self, blocks) -> Blocks:
         return make_frames(self, blocks)
+
+    def make_inactive(self, blocks) -> Blocks:
+        return make_inactive(self, blocks)
 
     # gauge
     def load_gauge(self, blocks: Blocks, U, low_prec="f32") -> Gauge:
@@ -545,6 +568,28 @@ class Context:
         self._check(_lib.dd_block_logdet(self._h, blocks._h, gauge._h, float(kappa), _dev(out, "torch.float64"), tot))
         o = out.cpu().numpy()
         return o[:, 0] + 1j * o[:, 1], complex(tot[0], tot[1])
+
+    def mb_global_action(self, domain: Blocks, gauge: Gauge, kappa, u, chi_global, params=None):
+        """Global rest S^r_MB per field on an inactive-region domain: (S per field [n_fields] numpy, total,
+        stats dict, status).  chi_global [n_fields, V, 4, 3] complex128 on the GPU."""
+        u = np.ascontiguousarray(np.asarray(u, dtype=np.complex128).reshape(-1))
+        nf = u.size
+        uu = np.ascontiguousarray(np.stack([u.real, u.imag], axis=1).reshape(-1))
+        if params is None:
+            params = solve_params()
+        iters = np.zeros(nf, dtype=np.int32)
+        rel = np.zeros(nf, dtype=np.float64)
+        flags = np.zeros(nf, dtype=np.int32)
+        stats = SolveStats(_ptr(iters), _ptr(rel), _ptr(flags), 0.0, 0, 0, 0, 0)
+        Sf = np.zeros(nf, dtype=np.float64)
+        tot = _D()
+        st = self._check(_lib.dd_mb_global_action(self._h, domain._h, gauge._h, float(kappa), int(nf), _ptr(uu),
+                                                   _dev(chi_global, "torch.complex128"), ctypes.byref(params),
+                                                   _ptr(Sf), ctypes.byref(tot), ctypes.byref(stats)),
+                         allow=(DD_ENOCONV,))
+        info = {"iters": iters, "true_relres": rel, "flags": flags, "seconds": stats.seconds,
+                "outer_cycles": stats.outer_cycles, "rhs_per_solve": stats.rhs_per_solve}
+        return Sf, tot.value, info, st
 
     def mb_exterior_source(self, blocks: Blocks, gauge: Gauge, kappa, chi_global, xi, parts=3):
         """xi += the hops of chi_global [n_fields, V, 4, 3] from the sites of dPi outside each block's box

@@ -271,3 +271,45 @@ def test_frame_tables(case):
     assert fr.inner_links == links
     with pytest.raises(dd.DDError):
         dd.make_frames(None, dd.make_blocks(None, (8, 8, 8, 8), -1, [[4, 4]] * 4))
+
+
+@pytest.mark.parametrize("case", ["tiles_inner", "paper_3d"])
+def test_inactive_domain_tables(case):
+    """The inactive-region domain (dd_make_inactive): one block spanning the lattice; its dPi_1 list is
+    the oracle's set; its exterior hops are exactly the hops from the active boxes into Lambda_1 (part
+    dLambda_0, antiperiodic sign on the time edge); it keeps exactly the links with both ends in
+    Lambda_1."""
+    from oracle import geometry
+    from paper_2211_06902_amd import dd
+
+    if case == "paper_3d":
+        L, bd = (6, 6, 6, 4), [2, 1, 2, 1, 2, 1, 0, 0]
+        blk = dd.make_blocks_paper(None, L, -1, bd)
+    else:
+        L = (8, 8, 8, 8)
+        blk = dd.make_blocks(None, L, -1, [[4, 4]] * 4, inner_d=1)
+    bx = blk.tables()[0]
+    D = dd.make_inactive(None, blk)
+    V = int(np.prod(L))
+    assert D.n_blocks == 1 and D.total_sites == V
+    dbx = D.tables()[0][0]
+    assert list(dbx[:4]) == [0, 0, 0, 0] and list(dbx[4:8]) == list(L)
+    P = geometry.BoxDomains(L, bx[:, :8], bx[:, 8:16])
+    assert np.array_equal(D.dpi1(), np.nonzero(P.dPi1)[0])
+    nb = geometry.neighbours(L)
+    x0 = geometry.coords(L)[:, 0]
+    exp = set()
+    for n in np.nonzero(P.lam1)[0]:
+        for mu in range(4):
+            for f in range(2):
+                m = nb[n, 2 * mu + f]
+                if P.lam0[m]:
+                    sign = mu == 0 and ((f == 0 and x0[n] == L[0] - 1) or (f == 1 and x0[n] == 0))
+                    exp.add((0, int(n), (2 * mu + f) | (8 if sign else 0) | (2 << 4), int(m)))
+    b, s, c, nbr = D.exterior()
+    got = set(zip(b.tolist(), s.tolist(), c.tolist(), nbr.tolist()))
+    assert len(got) == len(b) and got == exp and len(exp) > 0
+    links = sum(1 for n in np.nonzero(P.lam1)[0] for mu in range(4) if P.lam1[nb[n, 2 * mu]])
+    assert D.inner_links == links
+    D.close()
+    blk.close()
