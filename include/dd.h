@@ -138,7 +138,9 @@ dd_status dd_make_frames(dd_ctx *ctx, const dd_blocks *blocks, dd_blocks **out);
  * sites.  The domain is one block of V sites: its solves take the chunked
  * hop kernel (a block spanning the lattice in x0 has no x0-walk) and memory
  * for V sites per field.  DD_EINVAL when the inner boxes cover the lattice
- * (no inactive region) or V > 2^30.  ctx may be NULL (host tables only). */
+ * (no inactive region) or the lattice exceeds the block size limit of the
+ * constructors (11 184 810 sites, e.g. 56^4; 64^4 is refused).  ctx may be
+ * NULL (host tables only). */
 dd_status dd_make_inactive(dd_ctx *ctx, const dd_blocks *blocks, dd_blocks **out);
 /* The dPi_1 sites of an inactive-region domain (sites of Lambda_1 with some
  * coordinate on a face coordinate of an active box, in directions where the
@@ -173,7 +175,12 @@ dd_status dd_blocks_tables(const dd_blocks *blocks, int32_t *boxes, int64_t *sit
 dd_status dd_blocks_exterior(const dd_blocks *blocks, int64_t *n_hops, int32_t *block, int32_t *site, int32_t *code,
                              int64_t *nbr);
 
-/* The constructors above accept ctx == NULL: the blocks then hold host
+/* Size limit of every constructor: the kernels address a block's buffers
+ * with 32-bit byte offsets from its base, so a block holds at most
+ * 11 184 810 sites (its FP64 links below 4 GiB; DD_EINVAL beyond), and calls
+ * with n_rhs rhs need n_rhs * (sites of the largest block) * 96 < 2^32
+ * (DD_EUNSUPPORTED beyond; never reached by blocks of up to 10^4 sites).
+ * The constructors above accept ctx == NULL: the blocks then hold host
  * tables only (for dd_blocks_query / dd_blocks_tables) and every call that
  * needs the device rejects them with DD_EINVAL. */
 

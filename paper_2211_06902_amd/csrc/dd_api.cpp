@@ -261,6 +261,11 @@ hipError_t run_dhat(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const Ho
     return launch_dhat_walk(ba, wa, ha, prec, ctx->stream);
 }
 
+bool rhs_fit(const dd_blocks *B, int n_rhs)
+{
+    return (int64_t)n_rhs * B->max_h * 24 * 8 < ((int64_t)1 << 32);
+}
+
 const void *clover_for(const dd_gauge *G, dd_prec prec, bool inverse)
 {
     if (G->cl_csw == 0.0) return nullptr;
@@ -281,6 +286,8 @@ dd_status apply_D_check(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *G, dd_p
     if (!ctx || !B || !G || !x_dev || !y_dev) return fail(ctx, DD_EINVAL, "null argument");
     if (n_rhs < 1 || n_rhs > kMaxRhs) return fail(ctx, DD_EINVAL, "n_rhs must be in 1..64");
     if (G->blocks != B) return fail(ctx, DD_EINVAL, "gauge was loaded for other blocks");
+    if (!rhs_fit(B, n_rhs))
+        return fail(ctx, DD_EUNSUPPORTED, "too many rhs for the block size (32-bit offsets of the half fields)");
     *links = links_for(G, prec);
     if (!*links) return fail(ctx, DD_EINVAL, "gauge holds no links of the requested precision");
     const dd_status st = clover_check(ctx, G, kappa);

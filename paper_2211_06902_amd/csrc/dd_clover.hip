@@ -398,6 +398,8 @@ extern "C" dd_status dd_gauge_set_clover(dd_ctx *ctx, dd_gauge *G, const void *U
     if (csw == 0.0) return DD_OK;
     if (!U_dev) return fail(ctx, DD_EINVAL, "null gauge field");
     const dd_blocks *B = G->blocks;
+    if ((int64_t)2 * B->max_h * kCloverReals * 8 >= ((int64_t)1 << 32))
+        return fail(ctx, DD_EUNSUPPORTED, "block too large for the clover term's 32-bit offsets");
     const size_t n = (size_t)B->soff[B->nb] * kCloverReals;
     hipError_t e = hipMalloc(&G->d_cla64, std::max<size_t>(n, 1) * sizeof(double));
     if (e == hipSuccess) e = hipMalloc(&G->d_cli64, std::max<size_t>(n, 1) * sizeof(double));

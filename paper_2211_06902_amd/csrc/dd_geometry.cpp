@@ -312,6 +312,11 @@ std::string build_geometry(dd_blocks *B, const int L[4], int tbc, int n, const i
         }
         B->shape_of[k] = sid;
         const Shape &sh = B->shapes[sid];
+        // the kernels address a block's buffers with 32-bit byte offsets from
+        // its base: its FP64 links (4 directions x 6 complex entries) must stay
+        // below 4 GiB
+        if ((int64_t)sh.S * kLinkReals * 8 >= ((int64_t)1 << 32))
+            return "block too large for the kernels' 32-bit offsets (a block holds at most 11184810 sites)";
         B->soff[k + 1] = B->soff[k] + sh.S;
         B->inner_links += shape_links[sid];
         B->max_h = std::max(B->max_h, sh.h);

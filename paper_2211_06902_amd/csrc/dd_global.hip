@@ -90,6 +90,7 @@ extern "C" dd_status dd_mb_global_action(dd_ctx *ctx, const dd_blocks *D, const 
         fc = (int)std::max(1.0, std::floor(0.6 * (double)fr / per_field));
     }
     fc = std::min<int>(fc, n_fields);
+    while (fc > 1 && !rhs_fit(D, fc)) fc--;  // 32-bit offsets of the domain's half fields
     hipError_t e = hipSuccess;
     const size_t fbytes = (size_t)V * 24 * fc * sizeof(double);
     double *f = (double *)workspace(ctx, "mg_f", fbytes, &e);

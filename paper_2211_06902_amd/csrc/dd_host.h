@@ -52,6 +52,9 @@ dd_status apply_D_with(dd_ctx *ctx, const dd_blocks *B, const void *links, const
 // precision that arithmetic precision prec computes in; null without a
 // clover term.  clover_check: the clover term was built for this kappa.
 const void *clover_for(const dd_gauge *G, dd_prec prec, bool inverse);
+// The kernels address a block's half fields of n_rhs rhs with 32-bit byte
+// offsets: true when the largest block's FP64 half fields fit.
+bool rhs_fit(const dd_blocks *B, int n_rhs);
 dd_status clover_check(dd_ctx *ctx, const dd_gauge *G, double kappa);
 
 // Timing of one kernel launch of a class (events only while timing is on).

@@ -281,6 +281,8 @@ dd_status block_solve_impl(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, 
     if (!ctx || !Bc || !G || !b_dev || !x_dev) return fail(ctx, DD_EINVAL, "null argument");
     if (n_rhs < 1 || n_rhs > kMaxRhs) return fail(ctx, DD_EINVAL, "n_rhs must be in 1..64");
     if (G->blocks != Bc) return fail(ctx, DD_EINVAL, "gauge was loaded for other blocks");
+    if (!rhs_fit(Bc, n_rhs))
+        return fail(ctx, DD_EUNSUPPORTED, "too many rhs for the block size (32-bit offsets of the half fields)");
     dd_solve_params prm;
     if (params) prm = *params;
     else dd_solve_params_default(&prm);

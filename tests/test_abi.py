@@ -313,3 +313,19 @@ def test_inactive_domain_tables(case):
     assert D.inner_links == links
     D.close()
     blk.close()
+
+
+def test_block_size_limit_of_32bit_offsets():
+    """A block whose FP64 links would reach 4 GiB is refused (the kernels address a block's buffers with
+    32-bit byte offsets): the inactive region of 64^4 is one such block; 48^4 is accepted."""
+    from paper_2211_06902_amd import dd
+
+    blk = dd.make_blocks(None, (64, 64, 64, 64), -1, [[8] * 8] * 4, inner_d=1)
+    with pytest.raises(dd.DDError):
+        dd.make_inactive(None, blk)
+    blk.close()
+    blk = dd.make_blocks(None, (48, 48, 48, 48), -1, [[8] * 6] * 4, inner_d=1)
+    D = dd.make_inactive(None, blk)
+    assert D.total_sites == 48**4 and D.total_sites * 48 * 8 < 2**32
+    D.close()
+    blk.close()
