@@ -12,7 +12,10 @@ Contents (each module cites the part of the paper it follows):
   dense      dense-matrix determinant identities of Section 3 on tiny lattices
   factor     the Schur-complement pieces of Section 3 (Dtilde, Dhat^d, Dhat^h, W_z) as dense matrices
   roots      polynomial P_N, remainder R_{N+1} and roots u_k of Section 4
-  mb         block-local multi-boson action S_MB^a of Section 4
+  mb         multi-boson action of Section 4 (block-local S_MB^a, global rest S^r_MB), W_z chi as a
+             vector, field generation chi = W_u^{-1} eta, the remainder R_{N+1}(W_1) and the
+             stochastic estimate of ln W_N (eq. rw)
+  clover     the Sheikholeslami-Wohlert term named in Section 3
   precision  FP64 -> FP32 -> BF16 rounding rules
   convnet    the learned block preconditioner: 4D conv net, gradients, loss, Adam
              (not in the paper; parity pinned by independent identities)

@@ -22,10 +22,10 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import geometry, wilson
+from . import geometry, roots, wilson
 
 __all__ = ["boundary_lists", "mb_local_action", "exterior_source", "mb_local_action_from_chi", "mb_global_action",
-           "solve_masked"]
+           "solve_masked", "apply_w", "generate", "apply_remainder", "log_reweight_estimate"]
 
 
 def boundary_lists(L, boxes, inner):
@@ -180,4 +180,127 @@ def mb_global_action(L, tbc, kappa, U, boxes, inner, u, chi, tol=1e-13):
         v = solve_masked(L, tbc, kappa, U, B.lam1, f, tol=tol)
         w = u[k] * chi[k][B.dPi1] + v[B.dPi1]
         out[k] = float(np.sum(np.abs(w) ** 2))
+    return out
+
+
+def apply_w(L, tbc, kappa, U, boxes, inner, z, chi, tol=1e-13):
+    """W_z chi of eq. (MBaction) as a vector on dPi, one z per field: z [n_fields] complex, chi
+    [n_fields, V, 4, 3] (only its dPi values are used).  Rows on dLambda_0^a are the vector whose norm
+    is S_MB^a (eq. localMB): z chi + (D_{Omega_0^a}^{-1} xi^a) with xi^a the hops of chi from dPi
+    into Omega_0^a (exterior_source); rows on dPi_1 are those whose norm is S^r_MB (eq. globalMB):
+    z chi + [D_{Lambda_1}^{-1} D_{Lambda_1, dLambda_0} chi] (as in mb_global_action).  Zero off dPi.
+    At z = 0 it is the off-diagonal part W_1 - 1 of W_1."""
+    boxes = np.asarray(boxes, dtype=np.int32).reshape(-1, 8)
+    B = geometry.BoxDomains(L, boxes, inner)
+    z = np.asarray(z, dtype=np.complex128).reshape(-1)
+    c = np.zeros_like(np.asarray(chi, dtype=np.complex128))
+    c[:, B.dPi] = np.asarray(chi)[:, B.dPi]
+    out = np.zeros_like(c)
+    xi = exterior_source(L, tbc, kappa, U, boxes, inner, c, "all")
+    y, _, _, fails = wilson.solve_many(L, tbc, kappa, U, boxes, xi, tol=tol)
+    if fails:
+        raise RuntimeError("oracle block solve did not converge")
+    bl = boundary_lists(L, boxes, inner)
+    off = 0
+    for b, bx in enumerate(boxes):
+        sites = geometry.box_sites(L, bx[:4], bx[4:8])
+        g = sites[bl[b]]
+        for k in range(z.size):
+            out[k][g] = z[k] * c[k][g] + y[k, off + bl[b]]
+        off += sites.size
+    for k in range(z.size):
+        d = np.zeros_like(c[k])
+        d[B.dlam0] = c[k][B.dlam0]
+        v = solve_masked(L, tbc, kappa, U, B.lam1, wilson.dirac_full(L, tbc, kappa, U, d), tol=tol)
+        out[k][B.dPi1] = z[k] * c[k][B.dPi1] + v[B.dPi1]
+    return out
+
+
+def generate(L, tbc, kappa, U, boxes, inner, u, eta, tol=1e-11, inner_tol=1e-13, maxit=200):
+    """The multi-boson fields of Section 4 from Gaussian noise: chi_k = W_{u_k}^{-1} eta_k on dPi
+    (then chi_k has the density exp(-|W_{u_k} chi_k|^2) when eta_k has exp(-|eta_k|^2)).  This is
+    the one global inversion of the method, on a vector of dPi (Conclusions).  u [n_fields] complex;
+    eta [n_fields, V, 4, 3] (values off dPi are not used).  Plain BiCGStab per field on the vectors
+    supported on dPi with apply_w as the operator, stopped at |eta - W chi| <= tol |eta|.  Returns
+    (chi [n_fields, V, 4, 3], zero off dPi; iterations per field)."""
+    B = geometry.BoxDomains(L, boxes, inner)
+    u = np.asarray(u, dtype=np.complex128).reshape(-1)
+    eta = np.asarray(eta, dtype=np.complex128)
+    chi = np.zeros_like(eta)
+    its = np.zeros(u.size, dtype=np.int64)
+
+    def op(k, y):
+        return apply_w(L, tbc, kappa, U, boxes, inner, [u[k]], y[None], tol=inner_tol)[0]
+
+    for k in range(u.size):
+        b = np.zeros_like(eta[k])
+        b[B.dPi] = eta[k][B.dPi]
+        bn = np.linalg.norm(b)
+        if bn == 0.0:
+            continue
+        x = np.zeros_like(b)
+        r = b.copy()
+        rh = r.copy()
+        rho = alpha = omega = 1.0 + 0j
+        v = np.zeros_like(b)
+        p = np.zeros_like(b)
+        for it in range(1, maxit + 1):
+            rho_new = np.vdot(rh, r)
+            beta = (rho_new / rho) * (alpha / omega)
+            rho = rho_new
+            p = r + beta * (p - omega * v)
+            v = op(k, p)
+            alpha = rho / np.vdot(rh, v)
+            s = r - alpha * v
+            t = op(k, s)
+            omega = np.vdot(t, s) / np.vdot(t, t)
+            x = x + alpha * p + omega * s
+            r = s - omega * t
+            if np.linalg.norm(r) <= tol * bn:
+                break
+        else:
+            raise RuntimeError("oracle field generation did not converge")
+        chi[k] = x
+        its[k] = it
+    return chi, its
+
+
+def apply_remainder(L, tbc, kappa, U, boxes, inner, N, c, y, tol=1e-13):
+    """R_{N+1}(W_1) y on dPi for y [n_vec, V, 4, 3], with the remainder in its Chebyshev form
+    R_{N+1}(z) = T_{N+1}((1 - z)/c) / T_{N+1}(1/c) (oracle.roots; it has the printed roots).  Its
+    argument (1 - W_1)/c is -(W_1 - 1)/c = -W_0/c, so the three-term recurrence
+    T_0 y = y, T_1 y = X y, T_{j+1} y = 2 X T_j y - T_{j-1} y applies X = -apply_w(z = 0)/c alone and
+    never forms 1 - W_1 P_N(W_1), whose entries cancel to the size of R."""
+    B = geometry.BoxDomains(L, boxes, inner)
+    y = np.asarray(y, dtype=np.complex128)
+    t0 = np.zeros_like(y)
+    t0[:, B.dPi] = y[:, B.dPi]
+    zero = np.zeros(y.shape[0])
+
+    def X(v):
+        return -apply_w(L, tbc, kappa, U, boxes, inner, zero, v, tol=tol) / c
+
+    t1 = X(t0)
+    for _ in range(N):
+        t0, t1 = t1, 2 * X(t1) - t0
+    return t1 / float(np.real(roots.chebyshev_T(N + 1, np.asarray(1.0 / c))))
+
+
+def log_reweight_estimate(L, tbc, kappa, U, boxes, inner, N, c, eta, order, tol=1e-13):
+    """Stochastic estimate of ln W_N, W_N = det{1 - R_{N+1}(W_1)} of eq. (rw), by
+    ln det(1 - R) = Tr ln(1 - R) = -sum_{m >= 1} Tr(R^m)/m truncated after `order` terms, each trace
+    by the noise vectors eta [n_vec, V, 4, 3] (values on dPi; any noise with E[eta eta^+] = 1, or the
+    unit vectors of dPi, for which the sum is the exact trace): per vector
+    e_j = -sum_{m=1}^{order} eta_j^+ R^m eta_j / m.  Returns the per-vector terms e [n_vec] complex;
+    their mean estimates ln W_N.  The paper defines W_N only; this estimator is a reading."""
+    B = geometry.BoxDomains(L, boxes, inner)
+    eta = np.asarray(eta, dtype=np.complex128)
+    e0 = np.zeros_like(eta)
+    e0[:, B.dPi] = eta[:, B.dPi]
+    out = np.zeros(eta.shape[0], dtype=np.complex128)
+    w = e0
+    for m in range(1, order + 1):
+        w = apply_remainder(L, tbc, kappa, U, boxes, inner, N, c, w, tol=tol)
+        for j in range(eta.shape[0]):
+            out[j] -= np.vdot(e0[j], w[j]) / m
     return out
