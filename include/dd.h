@@ -323,7 +323,7 @@ dd_status dd_block_solve(dd_ctx *ctx, const dd_blocks *blocks, const dd_gauge *g
 /* ------------------------------------------------- multi-boson action */
 
 /* The field parameters of Section 4: u_k = 1 - z_k for the N/2 zeros z_k of
- * the Chebyshev remainder R_{N+1} taken one per complex-conjugate pair
+ * P_N(z) = (1 - R_{N+1}(z))/z taken one per complex-conjugate pair
  * (k = 1 .. N/2), u_k = cos(2 pi k / (N + 1)) + i sqrt(1 - c^2) sin(2 pi k / (N + 1)).
  * u_host: [N/2][2] (re, im).  DD_EINVAL unless N is even and 0 < c < 1.
  * Host only. */
@@ -393,6 +393,72 @@ dd_status dd_mb_global_action(dd_ctx *ctx, const dd_blocks *domain, const dd_gau
                               int32_t n_fields, const double *u_host, const void *chi_global_dev,
                               const dd_solve_params *params, double *S_field_host, double *S_total_host,
                               dd_solve_stats *stats);
+
+/* W_z chi of eq. (MBaction), Section 4, as a vector on dPi, one z per field:
+ * the rows on dLambda_0^a are the vector whose norm is S_MB^a (eq. localMB),
+ *   z chi + D_{Omega_0^a}^{-1} xi^a,  xi^a = the hops of chi from dPi into
+ *   Omega_0^a (dd_mb_exterior_source with parts 3), one dd_block_solve on blocks;
+ * the rows on dPi_1 are those whose norm is S^r_MB (eq. globalMB),
+ *   z chi + [D_{Lambda_1}^{-1} D_{Lambda_1,dLambda_0} chi],  one dd_block_solve on
+ *   domain.  At z = 0 this is W_1 - 1, the off-diagonal part of W_1.
+ * blocks/gauge: blocks with inner boxes and their gauge; domain/domain_gauge:
+ * dd_make_inactive of these blocks and its gauge (the same links; DD_EINVAL
+ * for a domain made from other blocks).  The clover term is refused
+ * (DD_EUNSUPPORTED).  z_host: [n_fields][2] (re, im).  chi_global_dev,
+ * out_global_dev: [n_fields][V][4][3] complex128 on the lattice in canonical
+ * order, distinct buffers; chi is read on dPi only, out is written everywhere
+ * (zero off dPi).  params: the inner solves (NULL: defaults; their tolerance
+ * bounds the error of W_z chi).  stats (may be NULL): seconds, outer cycles,
+ * inner iterations and fields per group (rhs_per_solve); the per-pair arrays
+ * are not written.  Fields are processed in groups as memory allows
+ * (DD_TUNE_MB_FIELDS forces the size).  DD_ENOCONV when an inner solve missed
+ * its tolerance (out is still written). */
+dd_status dd_mb_apply_W(dd_ctx *ctx, const dd_blocks *blocks, const dd_gauge *gauge, const dd_blocks *domain,
+                        const dd_gauge *domain_gauge, double kappa, int32_t n_fields, const double *z_host,
+                        const void *chi_global_dev, void *out_global_dev, const dd_solve_params *params,
+                        dd_solve_stats *stats);
+
+/* Multi-boson field generation (Section 4; the one global inversion of the
+ * method, on a vector of dPi, Conclusions): chi_k = W_{u_k}^{-1} eta_k, so that
+ * chi_k has the density exp(-|W_{u_k} chi_k|^2) when eta_k has exp(-|eta_k|^2)
+ * (each complex component with real and imaginary parts N(0, 1/2)).  The
+ * random numbers are the caller's: eta_global_dev [n_fields][V][4][3]
+ * complex128 (read on dPi only).  chi_global_dev: same layout, output (zero off
+ * dPi).  Arguments as for dd_mb_apply_W; u_host [n_fields][2].  Method: FP64
+ * BiCGStab per field over the vectors on dPi, the fields of a group in one
+ * batch (each application of W is dd_mb_apply_W's two batched solves), a
+ * field stopping when |r| <= tol |eta|; then one more application gives the
+ * true residual |eta - W chi| / |eta|.  iters_host, relres_host [n_fields]
+ * (may be NULL): iterations and true relative residual per field.
+ * params: the inner solves, whose tolerance should be well below tol.
+ * DD_ENOCONV when a field's true residual is above 10 tol, it broke down, or
+ * an inner solve missed its tolerance (chi is still written). */
+dd_status dd_mb_generate(dd_ctx *ctx, const dd_blocks *blocks, const dd_gauge *gauge, const dd_blocks *domain,
+                         const dd_gauge *domain_gauge, double kappa, int32_t n_fields, const double *u_host,
+                         const void *eta_global_dev, void *chi_global_dev, double tol, int32_t maxit,
+                         const dd_solve_params *params, int32_t *iters_host, double *relres_host,
+                         dd_solve_stats *stats);
+
+/* Stochastic estimate of ln W_N, W_N = det{1 - R_{N+1}(W_1)} the reweighting
+ * factor of eq. (rw), Section 4.  The remainder is R_{N+1}(z) =
+ * T_{N+1}((1 - z)/c) / T_{N+1}(1/c) (the Chebyshev form whose zeros of
+ * 1 - R_{N+1} are the roots of dd_mb_roots), applied to a vector by the
+ * three-term recurrence in X = (1 - W_1)/c = -W_0/c, N + 1 applications of
+ * W_0 (dd_mb_apply_W at z = 0); 1 - W_1 P_N(W_1) is never formed.  Then
+ *   ln W_N = Tr ln(1 - R) = -sum_{m >= 1} Tr(R^m) / m,
+ * truncated after `order` terms, each trace by the caller's noise vectors:
+ *   term_j = -sum_{m=1}^{order} eta_j^+ R^m eta_j / m   (eta_j on dPi).
+ * Any noise with E[eta eta^+] = 1 on dPi gives an unbiased estimate of the
+ * truncated series; the unit vectors of dPi give it exactly.  N even >= 2,
+ * 0 < c < 1 (as for dd_mb_roots), 1 <= order <= 64, 1 <= n_vec <= 64.
+ * eta_global_dev: [n_vec][V][4][3] complex128 (read on dPi).  terms_host
+ * [n_vec][2] and estimate_host [2] (their mean), each may be NULL.  Other
+ * arguments as for dd_mb_apply_W.  Cost: order (N + 1) applications of W.
+ * DD_ENOCONV when an inner solve missed its tolerance. */
+dd_status dd_mb_log_reweight(dd_ctx *ctx, const dd_blocks *blocks, const dd_gauge *gauge, const dd_blocks *domain,
+                             const dd_gauge *domain_gauge, double kappa, int32_t N, double c, int32_t order,
+                             int32_t n_vec, const void *eta_global_dev, const dd_solve_params *params,
+                             double *terms_host, double *estimate_host, dd_solve_stats *stats);
 
 /* Per-block log-determinants (Section 3, eq. detD and the effective action
  * after it: the block factors ln det D_{Omega_0^a} on framed blocks, and

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -22,6 +23,12 @@ thread_local std::string g_err;  // message of calls made without a context
 }  // namespace
 
 namespace dd {
+
+uint64_t next_blocks_serial()
+{
+    static std::atomic<uint64_t> n{0};
+    return ++n;
+}
 
 dd_status fail(dd_ctx *ctx, dd_status st, const std::string &msg)
 {
@@ -621,6 +628,7 @@ dd_status dd_make_inactive(dd_ctx *ctx, const dd_blocks *blocks, dd_blocks **out
     if (!D) return fail(ctx, DD_ENOMEM, "out of host memory");
     D->ctx = ctx;
     D->device = ctx ? ctx->device : -1;
+    D->parent = blocks->serial;
     const std::string msg = build_inactive(D, blocks);
     if (!msg.empty()) {
         delete D;

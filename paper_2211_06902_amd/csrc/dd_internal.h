@@ -124,10 +124,15 @@ struct QueueTable {
     int32_t *d_qctr = nullptr;   // [nq] counters (cleared by every launch)
 };
 
+// a process-wide number for every dd_blocks made (never reused)
+uint64_t next_blocks_serial();
+
 }  // namespace dd
 
 struct dd_blocks {
     dd_ctx *ctx = nullptr;  // creating context (identity only; may be destroyed first)
+    uint64_t serial = dd::next_blocks_serial();
+    uint64_t parent = 0;    // inactive-region domain: serial of the blocks it was made from
     int device = -1;        // device holding the tables (-1: host tables only)
     int L[4] = {0, 0, 0, 0};
     int tbc = -1;

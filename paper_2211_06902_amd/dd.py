@@ -152,6 +152,12 @@ _sig("dd_block_logdet", _I32, [_P, _P, _P, _D, _P, _P])
 _sig("dd_mb_exterior_source", _I32, [_P, _P, _P, _D, _I32, _P, _P, _I32])
 _sig("dd_mb_global_action", _I32, [_P, _P, _P, _D, _I32, _P, _P, ctypes.POINTER(SolveParams), _P, _P,
                                  ctypes.POINTER(SolveStats)])
+_sig("dd_mb_apply_W", _I32, [_P, _P, _P, _P, _P, _D, _I32, _P, _P, _P, ctypes.POINTER(SolveParams),
+                           ctypes.POINTER(SolveStats)])
+_sig("dd_mb_generate", _I32, [_P, _P, _P, _P, _P, _D, _I32, _P, _P, _P, _D, _I32, ctypes.POINTER(SolveParams),
+                            _P, _P, ctypes.POINTER(SolveStats)])
+_sig("dd_mb_log_reweight", _I32, [_P, _P, _P, _P, _P, _D, _I32, _D, _I32, _I32, _P, ctypes.POINTER(SolveParams),
+                                _P, _P, ctypes.POINTER(SolveStats)])
 _sig("dd_nn_num_weights", _I64, [])
 _sig("dd_nn_create", _I32, [_P, _P, _I32, _P, _PP])
 _sig("dd_nn_free", _I32, [_P])
@@ -590,6 +596,72 @@ class Context:
         info = {"iters": iters, "true_relres": rel, "flags": flags, "seconds": stats.seconds,
                 "outer_cycles": stats.outer_cycles, "rhs_per_solve": stats.rhs_per_solve}
         return Sf, tot.value, info, st
+
+    @staticmethod
+    def _cplx_pairs(z):
+        z = np.ascontiguousarray(np.asarray(z, dtype=np.complex128).reshape(-1))
+        return z.size, np.ascontiguousarray(np.stack([z.real, z.imag], axis=1).reshape(-1))
+
+    @staticmethod
+    def _wstats(stats):
+        return {"seconds": stats.seconds, "outer_cycles": stats.outer_cycles,
+                "inner_iterations": stats.inner_iterations, "rhs_per_solve": stats.rhs_per_solve}
+
+    def mb_apply_W(self, blocks: Blocks, gauge: Gauge, domain: Blocks, domain_gauge: Gauge, kappa, z, chi_global,
+                   out=None, params=None):
+        """W_z chi on dPi (eq. MBaction), one z per field: (out [n_fields, V, 4, 3] complex128 on the GPU,
+        info, status).  domain = make_inactive(blocks), domain_gauge its gauge (same links)."""
+        import torch
+
+        nf, zz = self._cplx_pairs(z)
+        if out is None:
+            out = torch.empty_like(chi_global)
+        if params is None:
+            params = solve_params()
+        stats = SolveStats(None, None, None, 0.0, 0, 0, 0, 0)
+        st = self._check(_lib.dd_mb_apply_W(self._h, blocks._h, gauge._h, domain._h, domain_gauge._h, float(kappa),
+                                            int(nf), _ptr(zz), _dev(chi_global, "torch.complex128"),
+                                            _dev(out, "torch.complex128"), ctypes.byref(params),
+                                            ctypes.byref(stats)), allow=(DD_ENOCONV,))
+        return out, self._wstats(stats), st
+
+    def mb_generate(self, blocks: Blocks, gauge: Gauge, domain: Blocks, domain_gauge: Gauge, kappa, u, eta_global,
+                    tol=1e-10, maxit=100, params=None, chi=None):
+        """chi_k = W_{u_k}^{-1} eta_k on dPi (the multi-boson fields from the caller's Gaussian noise):
+        (chi [n_fields, V, 4, 3] on the GPU, iterations [n_fields], true relres [n_fields], info, status)."""
+        import torch
+
+        nf, uu = self._cplx_pairs(u)
+        if chi is None:
+            chi = torch.empty_like(eta_global)
+        if params is None:
+            params = solve_params(tol=min(1e-12, tol * 1e-2))
+        its = np.zeros(nf, dtype=np.int32)
+        rel = np.zeros(nf, dtype=np.float64)
+        stats = SolveStats(None, None, None, 0.0, 0, 0, 0, 0)
+        st = self._check(_lib.dd_mb_generate(self._h, blocks._h, gauge._h, domain._h, domain_gauge._h, float(kappa),
+                                             int(nf), _ptr(uu), _dev(eta_global, "torch.complex128"),
+                                             _dev(chi, "torch.complex128"), float(tol), int(maxit),
+                                             ctypes.byref(params), _ptr(its), _ptr(rel), ctypes.byref(stats)),
+                         allow=(DD_ENOCONV,))
+        return chi, its, rel, self._wstats(stats), st
+
+    def mb_log_reweight(self, blocks: Blocks, gauge: Gauge, domain: Blocks, domain_gauge: Gauge, kappa, N, c,
+                        order, eta_global, params=None):
+        """Stochastic estimate of ln W_N (eq. rw) with the caller's noise eta [n_vec, V, 4, 3]: (per-vector
+        terms [n_vec] complex, their mean, info, status)."""
+        nv = eta_global.shape[0]
+        if params is None:
+            params = solve_params(tol=1e-12)
+        terms = np.zeros(2 * nv, dtype=np.float64)
+        est = np.zeros(2, dtype=np.float64)
+        stats = SolveStats(None, None, None, 0.0, 0, 0, 0, 0)
+        st = self._check(_lib.dd_mb_log_reweight(self._h, blocks._h, gauge._h, domain._h, domain_gauge._h,
+                                                 float(kappa), int(N), float(c), int(order), int(nv),
+                                                 _dev(eta_global, "torch.complex128"), ctypes.byref(params),
+                                                 _ptr(terms), _ptr(est), ctypes.byref(stats)),
+                         allow=(DD_ENOCONV,))
+        return terms[0::2] + 1j * terms[1::2], complex(est[0], est[1]), self._wstats(stats), st
 
     def mb_exterior_source(self, blocks: Blocks, gauge: Gauge, kappa, chi_global, xi, parts=3):
         """xi += the hops of chi_global [n_fields, V, 4, 3] from the sites of dPi outside each block's box

@@ -1,0 +1,145 @@
+"""GPU parity of the global pieces of Section 4 built on W_z (dd_mb_apply_W, dd_mb_generate,
+dd_mb_log_reweight) against the oracle (oracle.mb.apply_w / log_reweight_estimate, pinned against the
+dense W_z in test_oracle_global.py).
+
+* W_z chi on dPi, element by element (<= 1e-9 of the largest entry, <= 1e-10 per field in norm), on
+  4^4 tiles of 8^4 with 2^4 active boxes and on paper-mode b = 2, d = 1 in three directions of
+  6 x 6 x 6 x 4, at three z including 0 (the off-diagonal part W_1 - 1); zero off dPi; the field
+  grouping does not change the values beyond 1e-12.
+* Field generation: the oracle's W applied to the library's chi gives back eta within 1e-9 (the
+  solution is unique, so this pins chi to within cond(W) 1e-9); zero off dPi.
+* Reweighting estimate: per noise vector, the terms -sum_m eta^+ R^m eta / m equal the oracle's (same
+  noise, Chebyshev recurrence of R_{N+1}) within 1e-8 of the largest.
+* Refusals: a domain made from other blocks, out aliasing chi, a clover gauge, odd N.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import geometry, mb, roots
+
+pytestmark = pytest.mark.gpu
+
+KAPPA = 0.1355
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2211_06902_amd import dd
+
+    c = dd.Context(0)
+    yield c
+    c.close()
+
+
+def _dev(a):
+    import torch
+
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _setup(ctx, case, seed):
+    if case == "paper_3d":
+        L = (6, 6, 6, 4)
+        blk = ctx.make_blocks_paper(L, -1, [2, 1, 2, 1, 2, 1, 0, 0])
+    else:
+        L = (8, 8, 8, 8)
+        blk = ctx.make_blocks(L, -1, [[4, 4]] * 4, inner_d=1)
+    U = synth.gauge_field(L, 0.3, seed)
+    D = ctx.make_inactive(blk)
+    g = ctx.load_gauge(blk, _dev(U), "f32")
+    gd = ctx.load_gauge(D, _dev(U), "f32")
+    bx = blk.tables()[0]
+    return L, U, blk, D, g, gd, bx[:, :8], bx[:, 8:16]
+
+
+def _close(*hs):
+    for h in hs:
+        h.close()
+
+
+@pytest.mark.parametrize("case", ["tiles_inner", "paper_3d"])
+def test_apply_w_matches_oracle(ctx, case):
+    from paper_2211_06902_amd import dd
+
+    L, U, blk, D, g, gd, boxes, inner = _setup(ctx, case, 6611)
+    V = int(np.prod(L))
+    z = [0.5 + 0.2j, 0.0, 1j]
+    chi = synth.gaussian_complex((3, V, 4, 3), 6612)
+    prm = dd.solve_params(tol=1e-12)
+    out, info, st = ctx.mb_apply_W(blk, g, D, gd, KAPPA, z, _dev(chi), params=prm)
+    assert st == dd.DD_OK
+    got = out.cpu().numpy()
+    ref = mb.apply_w(L, -1, KAPPA, U, boxes, inner, z, chi)
+    dpi = geometry.BoxDomains(L, boxes, inner).dPi
+    for k in range(3):
+        assert np.linalg.norm(got[k] - ref[k]) <= 1e-10 * np.linalg.norm(ref[k]), k
+        assert np.abs(got[k] - ref[k]).max() <= 1e-9 * np.abs(ref[k]).max(), k
+        assert np.all(got[k][~dpi] == 0)
+    # one field per group
+    try:
+        ctx.tune_set(dd.TUNE_MB_FIELDS, 1)
+        out1, info1, st1 = ctx.mb_apply_W(blk, g, D, gd, KAPPA, z, _dev(chi), params=prm)
+    finally:
+        ctx.tune_set(dd.TUNE_MB_FIELDS, 0)
+    assert st1 == dd.DD_OK and info1["rhs_per_solve"] == 1
+    got1 = out1.cpu().numpy()
+    assert np.abs(got1 - got).max() <= 1e-12 * np.abs(got).max()
+    _close(gd, g, D, blk)
+
+
+@pytest.mark.parametrize("case", ["tiles_inner", "paper_3d"])
+def test_generate_solves_the_oracle_equation(ctx, case):
+    from paper_2211_06902_amd import dd
+
+    L, U, blk, D, g, gd, boxes, inner = _setup(ctx, case, 6621)
+    V = int(np.prod(L))
+    u = roots.mb_roots(6, 0.5)[:3]
+    eta = synth.gaussian_complex((3, V, 4, 3), 6622) / np.sqrt(2)
+    chi, its, rel, info, st = ctx.mb_generate(blk, g, D, gd, KAPPA, u, _dev(eta), tol=1e-10,
+                                              params=dd.solve_params(tol=1e-12))
+    assert st == dd.DD_OK and np.all(rel <= 1e-9) and np.all(its > 0), (its, rel)
+    chi = chi.cpu().numpy()
+    dpi = geometry.BoxDomains(L, boxes, inner).dPi
+    W = mb.apply_w(L, -1, KAPPA, U, boxes, inner, u, chi)
+    for k in range(3):
+        assert np.all(chi[k][~dpi] == 0)
+        e = np.where(dpi[:, None, None], eta[k], 0)
+        assert np.linalg.norm(W[k] - e) <= 1e-9 * np.linalg.norm(e), k
+    _close(gd, g, D, blk)
+
+
+@pytest.mark.parametrize("case,N,c,order,nv", [("paper_3d", 2, 0.9, 2, 2), ("tiles_inner", 4, 0.8, 1, 1)])
+def test_log_reweight_matches_oracle(ctx, case, N, c, order, nv):
+    from paper_2211_06902_amd import dd
+
+    L, U, blk, D, g, gd, boxes, inner = _setup(ctx, case, 6631)
+    V = int(np.prod(L))
+    eta = synth.gaussian_complex((nv, V, 4, 3), 6632) / np.sqrt(2)
+    terms, est, info, st = ctx.mb_log_reweight(blk, g, D, gd, KAPPA, N, c, order, _dev(eta),
+                                               params=dd.solve_params(tol=1e-12))
+    assert st == dd.DD_OK
+    ref = mb.log_reweight_estimate(L, -1, KAPPA, U, boxes, inner, N, c, eta, order)
+    assert np.abs(terms - ref).max() <= 1e-8 * np.abs(ref).max(), (terms, ref)
+    assert abs(est - terms.mean()) <= 1e-14 * abs(terms).max()
+    _close(gd, g, D, blk)
+
+
+def test_global_pieces_refusals(ctx):
+    from paper_2211_06902_amd import dd
+
+    L, U, blk, D, g, gd, boxes, inner = _setup(ctx, "paper_3d", 6641)
+    V = int(np.prod(L))
+    chi = _dev(synth.gaussian_complex((1, V, 4, 3), 6642))
+    other = ctx.make_blocks_paper(L, -1, [2, 1, 2, 1, 2, 1, 0, 0])
+    g_other = ctx.load_gauge(other, _dev(U), "f32")
+    with pytest.raises(dd.DDError):  # domain made from other blocks
+        ctx.mb_apply_W(other, g_other, D, gd, KAPPA, [0.5], chi)
+    with pytest.raises(dd.DDError):  # out aliasing chi
+        ctx.mb_apply_W(blk, g, D, gd, KAPPA, [0.5], chi, out=chi)
+    with pytest.raises(dd.DDError):  # odd N
+        ctx.mb_log_reweight(blk, g, D, gd, KAPPA, 3, 0.9, 1, chi)
+    g.set_clover(_dev(U), KAPPA, 1.0)
+    with pytest.raises(dd.DDError):
+        ctx.mb_apply_W(blk, g, D, gd, KAPPA, [0.5], chi)
+    _close(g_other, other, gd, g, D, blk)
