@@ -55,9 +55,10 @@ def test_inner_boundary_of_8x4_tile():
 T1 = ((4, 4, 4, 4), [(1, 1)] * 4)
 T2 = ((8, 2, 2, 2), [(3, 1), None, None, None])
 T3 = ((8, 8, 2, 2), [(3, 1), (3, 1), None, None])
+T4 = ((8, 4, 4, 4), [(3, 1), (1, 1), (1, 1), (1, 1)])
 
 
-@pytest.mark.parametrize("geom", [T1, T2, T3], ids=["T1", "T2", "T3"])
+@pytest.mark.parametrize("geom", [T1, T2, T3, T4], ids=["T1", "T2", "T3", "T4"])
 def test_domain_set_properties(geom):
     L, spec = geom
     P = geometry.PaperDomains(L, spec)
@@ -86,6 +87,16 @@ def test_T1_counts():
     # dPi: some coordinate even -> 256 - 2^4 sites; dPi1 removes the 16 blocks
     assert P.dPi.sum() == 240 and P.dPi1.sum() == 224
     assert all(o.sum() == 81 for o in P.omega_a) and all(f.sum() == 80 for f in P.phi_a)
+
+
+def test_T4_counts():
+    """8 x 4^3 with b = 3, d = 1 in time and b = d = 1 in space: 2 x 2^3 = 16 blocks of 3 x 1^3 sites
+    (all on dLambda_0), 5 x 3^3 framed boxes; the inactive region is the rest of the 512 sites."""
+    P = geometry.PaperDomains(*T4)
+    assert len(P.blocks) == 16
+    assert P.lam0.sum() == 48 and P.dlam0.sum() == 48 and P.lam0bar.sum() == 0
+    assert P.lam1.sum() == 464 and P.dPi1.sum() == 432 and (P.lam1 & ~P.dPi1).sum() == 32
+    assert all(o.sum() == 135 for o in P.omega_a) and all(f.sum() == 132 for f in P.phi_a)
 
 
 def test_1d_frames_cover_lambda1_twice():
@@ -154,6 +165,11 @@ def _logdet_identities(L, spec, kappa, eps, seed):
 @pytest.mark.slow
 def test_factorisation_T1():
     _logdet_identities(*T1, kappa=0.12, eps=0.5, seed=1101)
+
+
+@pytest.mark.slow
+def test_factorisation_T4():
+    _logdet_identities(*T4, kappa=0.12, eps=0.5, seed=41)
 
 
 def test_factorisation_T3_corners():
