@@ -22,7 +22,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import geometry, roots, wilson
+from . import clover, geometry, roots, wilson
 
 __all__ = ["boundary_lists", "mb_local_action", "exterior_source", "mb_local_action_from_chi", "mb_global_action",
            "solve_masked", "apply_w", "generate", "apply_remainder", "log_reweight_estimate"]
@@ -120,12 +120,19 @@ def mb_local_action_from_chi(L, tbc, kappa, U, boxes, inner, u, chi, tol=1e-12, 
     return mb_local_action(L, tbc, kappa, U, boxes, inner, u, chib, xi, tol=tol, nthreads=nthreads)
 
 
-def solve_masked(L, tbc, kappa, U, mask, f, tol=1e-13, maxit=20000):
+def solve_masked(L, tbc, kappa, U, mask, f, tol=1e-13, maxit=20000, csw=0.0, A=None):
     """y = D_X^{-1} f for the site set X = mask (Dirichlet: D_X is the principal sub-matrix of D on
     X), by plain BiCGStab on the vectors supported on X; f [V, 4, 3] (its values outside X are not
-    used); y is zero outside X."""
+    used); y is zero outside X.  With csw != 0, D is the Sheikholeslami-Wohlert operator
+    (oracle.clover; A its clover matrices, computed when not given)."""
+    if csw != 0.0 and A is None:
+        A = clover.clover_matrix(L, U, kappa, csw)
+
     def op(y):
-        out = wilson.dirac_full(L, tbc, kappa, U, y)
+        if csw != 0.0:
+            out = clover.dirac_clover_full(L, tbc, kappa, csw, U, y, A=A)
+        else:
+            out = wilson.dirac_full(L, tbc, kappa, U, y)
         out[~mask] = 0.0
         return out
 
@@ -162,22 +169,25 @@ def solve_masked(L, tbc, kappa, U, mask, f, tol=1e-13, maxit=20000):
     return x
 
 
-def mb_global_action(L, tbc, kappa, U, boxes, inner, u, chi, tol=1e-13):
+def mb_global_action(L, tbc, kappa, U, boxes, inner, u, chi, tol=1e-13, csw=0.0):
     """S^r_MB of eq. (globalMB) per field k: |u_k chi_k + W_{dPi1,dL0} chi_k|^2 summed over dPi_1 (the
     dPi_1 rows of W_{u_k} chi_k; field k at z = u_k as for the local term).  Reading: eliminating
     Lambda1bar from D_{Lambda_1} (Lambda_1 = Lambda1bar u dPi_1) gives
       W_{dPi1,dL0} chi = Dhat_{dPi1}^{-1} Dhat_{dPi1,dL0} chi = [D_{Lambda_1}^{-1} D_{Lambda_1,dL0} chi]_{dPi_1},
     one solve on the inactive region Lambda_1 per field.  chi [n_fields, V, 4, 3] on dPi (values
-    elsewhere not used).  Returns the per-field values [n_fields]."""
+    elsewhere not used).  With csw != 0 the operator is the Sheikholeslami-Wohlert one (its clover
+    term is site-diagonal, so the hops D_{Lambda_1, dLambda_0} are those of the Wilson operator).
+    Returns the per-field values [n_fields]."""
     B = geometry.BoxDomains(L, boxes, inner)
     u = np.asarray(u, dtype=np.complex128).reshape(-1)
     chi = np.asarray(chi, dtype=np.complex128)
     out = np.zeros(u.size)
+    A = clover.clover_matrix(L, U, kappa, csw) if csw != 0.0 else None
     for k in range(u.size):
         c = np.zeros_like(chi[k])
         c[B.dlam0] = chi[k][B.dlam0]
         f = wilson.dirac_full(L, tbc, kappa, U, c)  # D_{Lambda_1, dLambda_0} chi on Lambda_1
-        v = solve_masked(L, tbc, kappa, U, B.lam1, f, tol=tol)
+        v = solve_masked(L, tbc, kappa, U, B.lam1, f, tol=tol, csw=csw, A=A)
         w = u[k] * chi[k][B.dPi1] + v[B.dPi1]
         out[k] = float(np.sum(np.abs(w) ** 2))
     return out

@@ -148,3 +148,35 @@ def test_reweight_estimator_is_unbiased_in_the_mean():
     e = mb.log_reweight_estimate(L, -1, KAPPA, U, boxes, inner, N, c, eta, order)
     se = e.real.std(ddof=1) / np.sqrt(e.size)
     assert abs(e.real.mean() - exact.real) <= 4 * se
+
+
+def test_global_action_with_clover_matches_dense():
+    """S^r_MB with the Sheikholeslami-Wohlert operator (one masked solve on Lambda_1 with the clover
+    term) equals the dPi_1 rows of the dense W_z built from the dense clover matrix (T3)."""
+    from oracle import clover
+
+    L, spec, seed = T3
+    kappa, csw = 0.12, 1.4
+    P = geometry.PaperDomains(L, spec)
+    U = synth.gauge_field(L, 0.5, seed)
+    A = clover.clover_matrix(L, U, kappa, csw)
+    n = 12 * P.V
+    M = np.empty((n, n), dtype=complex)
+    e = np.zeros((P.V, 4, 3), dtype=complex)
+    ef = e.reshape(-1)
+    for j in range(n):
+        ef[j] = 1.0
+        M[:, j] = clover.dirac_clover_full(L, -1, kappa, csw, U, e, A=A).reshape(-1)
+        ef[j] = 0.0
+    pc = factor.pieces(M, P)
+    boxes, inner = _box_lists(P)
+    z = complex(0.3, 0.7)
+    chi = synth.gaussian_complex((1, P.V, 4, 3), seed + 21)
+    Wc = factor.w_z(pc, z) @ _vec(pc, chi[0])
+    n0 = pc["Dd"].shape[0]
+    S_rest = float(np.sum(np.abs(Wc[n0:]) ** 2))
+    S_r = mb.mb_global_action(L, -1, kappa, U, boxes, inner, [z], chi, csw=csw)
+    assert S_rest > 0 and abs(S_r[0] - S_rest) <= 1e-10 * S_rest
+    # and the term matters
+    S_w = mb.mb_global_action(L, -1, kappa, U, boxes, inner, [z], chi)
+    assert abs(S_w[0] - S_r[0]) > 1e-3 * S_rest
