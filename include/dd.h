@@ -221,8 +221,9 @@ dd_status dd_gauge_export(dd_ctx *ctx, const dd_gauge *gauge, dd_prec prec, void
  * dd_apply_D_block, dd_apply_D_block_noalloc, dd_block_solve and
  * dd_multiboson_action use this operator and reject another kappa
  * (DD_EINVAL); solves run even-odd BiCGStab on
- * 1 - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe (DD_EUNSUPPORTED for GMRES, a network
- * preconditioner, or blocks the x0-walk hop cannot take); dd_block_logdet
+ * 1 - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe (DD_EUNSUPPORTED for GMRES or a network
+ * preconditioner; the hops of blocks the x0-walk cannot take, such as an
+ * inactive region, run in the chunked hop kernel); dd_block_logdet
  * returns DD_EUNSUPPORTED.  c_sw = 0 removes the term (the Wilson operator).
  * Errors: DD_EINVAL (null argument, non-finite kappa or c_sw), DD_ENOMEM. */
 dd_status dd_gauge_set_clover(dd_ctx *ctx, dd_gauge *gauge, const void *U_dev, double kappa, double csw);

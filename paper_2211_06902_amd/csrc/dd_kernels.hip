@@ -205,10 +205,13 @@ __host__ __device__ constexpr int dot_nred(int mode)
 // out = c_add*add + c_self*self + c_hop * (H in) on the sites of one parity,
 // `in` on the other parity.  The tile first copies its chunk of `in` (its rhs
 // group) into LDS; hops that land inside the chunk read LDS, the others
-// (direction 0 across the chunk edge) read global memory.
-template <typename SP, typename LK, typename AC, int G>
+// (direction 0 across the chunk edge) read global memory.  CL: the hop result
+// at each output site is multiplied by that site's clover matrix (ha.clover)
+// before the epilogue, as in the walk hop (one rhs per thread).
+template <typename SP, typename LK, typename AC, int G, bool CL = false>
 __global__ void __launch_bounds__(kTile) k_hop(BlkArgs ba, HopArgs ha)
 {
+    static_assert(!CL || G == 1, "clover hops take one rhs per thread");
     __shared__ SP stage[24 * kTile * G];
     __shared__ double red[G][kTile];
     const Tile t = tile_of(ba);
@@ -268,6 +271,12 @@ __global__ void __launch_bounds__(kTile) k_hop(BlkArgs ba, HopArgs ha)
         hop_one<3, false, SP, LK, AC, G>(acc, nb[7], stage, hc);
 
         const EpiBufs eb = epi_bufs<SP>(ha, hbase, fbytes);
+        if constexpr (CL) {
+            const Buf clb = make_buf(reinterpret_cast<const SP *>(ha.clover) + soff * kCloverReals,
+                                     (uint32_t)(kCloverReals * 2 * t.hb) * (uint32_t)sizeof(SP));
+            clover_mul<SP, AC>(acc[0], clb, (uint32_t)hc.slot_self * (uint32_t)sizeof(SP),
+                               (uint32_t)(2 * t.hb) * (uint32_t)sizeof(SP));
+        }
 #pragma unroll
         for (int j = 0; j < G; j++) hop_epilogue<SP, AC, -1>(acc[j], dv[j], ha, eb, my + (uint32_t)(j * 24) * hc.cstr, hc.cstr);
     }
@@ -279,9 +288,20 @@ __global__ void __launch_bounds__(kTile) k_hop(BlkArgs ba, HopArgs ha)
 hipError_t launch_hop(const BlkArgs &ba, const HopArgs &ha, dd_prec prec, hipStream_t s)
 {
     if (ha.pre != kPreNone) return hipErrorInvalidValue;  // staging updates are x0-walk only
-    if (ha.clover) return hipErrorInvalidValue;            // so is the clover term
     if (ba.ntiles <= 0) return hipSuccess;
     dim3 g(ba.ntiles), t(kTile);
+    if (ha.clover) {  // clover hops: one rhs per thread
+        if (ba.g != 1) return hipErrorInvalidValue;
+        if (prec == DD_F64)
+            hipLaunchKernelGGL((k_hop<double, double, double, 1, true>), g, t, 0, s, ba, ha);
+        else if (prec == DD_F32)
+            hipLaunchKernelGGL((k_hop<float, float, float, 1, true>), g, t, 0, s, ba, ha);
+        else if (prec == DD_BF16)
+            hipLaunchKernelGGL((k_hop<float, uint16_t, float, 1, true>), g, t, 0, s, ba, ha);
+        else
+            return hipErrorInvalidValue;
+        return hipGetLastError();
+    }
     if (prec == DD_F64 && ba.g == 1)
         hipLaunchKernelGGL((k_hop<double, double, double, 1>), g, t, 0, s, ba, ha);
     else if (prec == DD_F32 && ba.g == 1)

@@ -302,7 +302,7 @@ dd_status block_solve_impl(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, 
     // the clover term: A (FP64, outer residual) and A^-1 (inner precision) of
     // every block site; the inner system is the asymmetric even-odd form
     // 1 - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe, its two hops with A^-1 applied
-    // to their hop results (walk hops, one rhs per thread)
+    // to their hop results (walk or chunked hops, one rhs per thread)
     {
         const dd_status cs = clover_check(ctx, G, kappa);
         if (cs != DD_OK) return cs;
@@ -311,8 +311,6 @@ dd_status block_solve_impl(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, 
     if (cl_a64) {
         if (gmres || nn) return fail(ctx, DD_EUNSUPPORTED, "the clover term is solved by BiCGStab without a network");
         if (!cl_inv) return fail(ctx, DD_EINVAL, "gauge holds no clover term of the inner precision");
-        if (!Bc->walk || !ctx->hop_lds || ctx->hop_walk < 0)
-            return fail(ctx, DD_EUNSUPPORTED, "the clover solve needs blocks the x0-walk hop handles");
     }
     const double inner_tol = prm.inner_tol > 0 ? prm.inner_tol : default_inner_tol(ip, prm.tol);
     // with the default inner tolerance and a low-precision inner solve, a later

@@ -37,3 +37,9 @@ def site_offsets(boxes):
 
 def rel_err(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(np.asarray(b)), 1e-300))
+
+
+def max_err(a, b):
+    """Largest element-wise difference relative to the largest element of b (complex modulus)."""
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.max(np.abs(a - b), initial=0.0) / max(np.max(np.abs(b), initial=0.0), 1e-300))

@@ -5,8 +5,8 @@
   tiles of an 8^4 lattice and on the same tiling shifted by one site (blocks that wrap, including the
   antiperiodic time edge): A(x) of the whole lattice at every block site.
 * Block solves (FP64 and FP32 inner even-odd BiCGStab on 1 - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe inside
-  FP64 defect correction): every pair's true residual with the oracle's clover operator <= 1e-10, and
-  two blocks' solutions against dense LU.
+  FP64 defect correction), with the x0-walk hops and with the chunked hop kernel: every pair's true
+  residual with the oracle's clover operator <= 1e-10, and two blocks' solutions against dense LU.
 * c_sw = 0 gives back the Wilson operator bit for bit; a kappa other than the clover term's, GMRES and
   the log-determinants are refused.
 """
@@ -99,8 +99,9 @@ def _relres(U, A, b, x, box):
     return np.linalg.norm(r) / np.linalg.norm(b)
 
 
+@pytest.mark.parametrize("walk", [True, False], ids=["walk", "chunked"])
 @pytest.mark.parametrize("inner", ["f64", "f32"])
-def test_clover_solves_match_oracle(ctx, field, inner):
+def test_clover_solves_match_oracle(ctx, field, inner, walk):
     from paper_2211_06902_amd import dd
 
     U, A = field
@@ -110,7 +111,12 @@ def test_clover_solves_match_oracle(ctx, field, inner):
     g = ctx.load_gauge(blk, _dev(U), "f32").set_clover(_dev(U), KAPPA, CSW)
     n_rhs = 3
     b = synth.gaussian_complex((n_rhs, blk.total_sites, 4, 3), 4404)
-    x, info, st = ctx.block_solve(blk, g, KAPPA, _dev(b), params=dd.solve_params(inner_prec=inner))
+    try:
+        # walk off: every hop, the clover ones included, runs in the chunked kernel
+        ctx.tune_set(dd.TUNE_HOP_WALK, 0 if walk else -1)
+        x, info, st = ctx.block_solve(blk, g, KAPPA, _dev(b), params=dd.solve_params(inner_prec=inner))
+    finally:
+        ctx.tune_set(dd.TUNE_HOP_WALK, 0)
     assert st == dd.DD_OK and np.all(info["true_relres"] <= 1e-10)
     x = x.cpu().numpy()
     for k, bx in enumerate(boxes):

@@ -82,3 +82,28 @@ def test_global_action_refuses_ordinary_blocks(ctx):
         ctx.mb_global_action(blk, g, 0.13, [0.5], chi)
     g.close()
     blk.close()
+
+
+@pytest.mark.parametrize("inner", ["f64", "f32"])
+def test_global_action_with_clover_matches_oracle(ctx, inner):
+    """The inactive-region solve with the Sheikholeslami-Wohlert term (dd_gauge_set_clover on the
+    domain's gauge) against the oracle's clover S^r_MB (pinned by the dense clover W_z)."""
+    from paper_2211_06902_amd import dd
+
+    L, blk = _blocks(ctx, "tiles_inner")
+    kappa, csw = 0.13, 1.6
+    U = synth.gauge_field(L, 0.3, 5511)
+    bx = blk.tables()[0]
+    D = ctx.make_inactive(blk)
+    g = ctx.load_gauge(D, _dev(U), "f32").set_clover(_dev(U), kappa, csw)
+    V = int(np.prod(L))
+    u = dd.mb_roots(4, 0.5)
+    chi = synth.gaussian_complex((2, V, 4, 3), 5512)
+    S, tot, info, st = ctx.mb_global_action(D, g, kappa, u, _dev(chi),
+                                            params=dd.solve_params(inner_prec=inner, tol=1e-12))
+    assert st == dd.DD_OK and np.all(info["true_relres"] <= 1e-12)
+    ref = mb.mb_global_action(L, -1, kappa, U, bx[:, :8], bx[:, 8:16], u, chi, csw=csw)
+    assert np.max(np.abs(S - ref) / ref) <= 1e-9, (S, ref)
+    g.close()
+    D.close()
+    blk.close()

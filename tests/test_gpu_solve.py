@@ -67,6 +67,8 @@ def test_c1_overlapping_blocks_vs_dense_lu(ctx, c1, inner):
         for r in range(x.shape[0]):
             sl = slice(16 * k, 16 * (k + 1))
             assert _true_relres(c1["L"], c1["kappa"], c1["U"], bx, x[r, sl], c1["b"][r, sl]) <= TOL
+            # every element of every pair against dense LU (relative to the pair's largest)
+            assert _cfg.max_err(x[r, sl], c1["x_lu"][r, sl]) <= 1e-8, (k, r)
     assert _cfg.rel_err(x, c1["x_lu"]) <= 1e-9
     g.close()
 
