@@ -565,6 +565,34 @@ dd_status dd_autotune_gmres(dd_ctx *ctx, const dd_blocks *blocks, const dd_gauge
                             const void *b_dev, void *x_dev, int32_t n_rhs, const dd_solve_params *params,
                             dd_tune_result *results, int32_t max_results, int32_t *n_results);
 
+/* One timed configuration of the BiCGStab path (the dd_tune_set knobs it sets). */
+typedef struct {
+    int32_t rhs_group;  /* DD_TUNE_RHS_GROUP_F32 (or _F64 for an FP64 inner solve): 1 or 2 */
+    int32_t dhat_walk;  /* DD_TUNE_DHAT_WALK: 0 (the one-kernel Dhat) or -1 (two walk hops) */
+    int32_t dhat_rhs;   /* DD_TUNE_DHAT_RHS: 1 or 3 with the one-kernel Dhat, else 0 */
+    int32_t bicg_fuse;  /* DD_TUNE_BICG_FUSE: 0 or -1 (with two walk hops) */
+    double ms;          /* wall time of one full dd_block_solve of b */
+} dd_bicg_tune_result;
+
+/* Autotuner of the BiCGStab path for these blocks, n_rhs and
+ * params->inner_prec (plain BiCGStab; DD_EINVAL otherwise): after one
+ * warm-up solve, times one full dd_block_solve of b under each candidate (rhs
+ * per thread 1, or 2 when it divides n_rhs; with an FP32 or BF16 inner solve
+ * the one-kernel Dhat with 1 or 3 rhs per workgroup, or two walk hops with
+ * and without the fused staging updates; FP64: the two walk hops) and keeps
+ * the fastest in the context, as dd_tune_set would.  x_dev (the size of b) is
+ * scratch.  cache_path (may be NULL): a JSON file (an object, one entry per
+ * line) keyed by device, lattice, block shapes, n_rhs and inner precision;
+ * when it holds this key nothing is timed, the stored configuration is
+ * applied and *from_cache is 1; otherwise the winner is added to the file
+ * (rewritten through a temporary file; DD_EINVAL if it cannot be written).
+ * results (may be NULL): up to max_results timings in candidate order (on a
+ * cache hit, the stored entry); n_results, from_cache may be NULL. */
+dd_status dd_autotune_bicgstab(dd_ctx *ctx, const dd_blocks *blocks, const dd_gauge *gauge, double kappa,
+                               const void *b_dev, void *x_dev, int32_t n_rhs, const dd_solve_params *params,
+                               const char *cache_path, dd_bicg_tune_result *results, int32_t max_results,
+                               int32_t *n_results, int32_t *from_cache);
+
 /* ---------------------------------------------- learned preconditioner */
 
 /* A small 4D convolutional network that approximates the block inverse on

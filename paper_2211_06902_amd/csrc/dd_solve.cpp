@@ -19,6 +19,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -825,6 +826,165 @@ dd_status dd_autotune_gmres(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *G, 
     const int nr = std::min<int>((int)cand.size(), std::max(max_results, 0));
     for (int i = 0; results && i < nr; i++) results[i] = {cand[i].nt, cand[i].nq, cand[i].wpc, cand[i].ms};
     if (n_results) *n_results = (int32_t)cand.size();
+    ctx->err.clear();
+    return DD_OK;
+}
+
+// ------------------------------------------------- BiCGStab autotuner
+
+namespace {
+
+// Cache key of a tuning problem: device, lattice, block shapes, n_rhs, inner
+// precision.  No quotes or backslashes (it is written as a JSON string).
+std::string bicg_tune_key(const dd_ctx *ctx, const dd_blocks *B, int n_rhs, dd_prec ip)
+{
+    hipDeviceProp_t prop;
+    std::string dev = "unknown";
+    if (hipGetDeviceProperties(&prop, ctx->device) == hipSuccess)
+        dev = std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount) + "cu";
+    std::string k = dev + "|L=" + std::to_string(B->L[0]) + "x" + std::to_string(B->L[1]) + "x" +
+                    std::to_string(B->L[2]) + "x" + std::to_string(B->L[3]) + "|tbc=" + std::to_string(B->tbc) +
+                    "|nb=" + std::to_string(B->nb) + "|shapes=";
+    std::vector<int> count(B->shapes.size(), 0);
+    for (int b = 0; b < B->nb; b++) count[B->shape_of[b]]++;
+    for (size_t i = 0; i < B->shapes.size(); i++) {
+        const dd::Shape &sh = B->shapes[i];
+        k += std::to_string(sh.e[0]) + "x" + std::to_string(sh.e[1]) + "x" + std::to_string(sh.e[2]) + "x" +
+             std::to_string(sh.e[3]) + "h" + std::to_string(sh.hole) + "*" + std::to_string(count[i]) + ";";
+    }
+    k += "|rhs=" + std::to_string(n_rhs) + "|inner=" + (ip == DD_F64 ? "f64" : ip == DD_F32 ? "f32" : "bf16");
+    for (char &c : k)
+        if (c == '"' || c == '\\' || (unsigned char)c < 32) c = '_';
+    return k;
+}
+
+// The cache file: a JSON object with one entry per line,
+//   "key": {"rhs_group": g, "dhat_walk": w, "dhat_rhs": r, "bicg_fuse": f, "ms": t},
+// read and written by the two functions below (lines that do not parse are
+// dropped when the file is rewritten).
+bool bicg_cache_read(const char *path, std::vector<std::pair<std::string, dd_bicg_tune_result>> &out)
+{
+    out.clear();
+    FILE *f = std::fopen(path, "r");
+    if (!f) return false;
+    char line[4096];
+    while (std::fgets(line, sizeof(line), f)) {
+        const char *q0 = std::strchr(line, '"');
+        const char *q1 = q0 ? std::strchr(q0 + 1, '"') : nullptr;
+        const char *br = q1 ? std::strchr(q1, '{') : nullptr;
+        if (!br) continue;
+        dd_bicg_tune_result r{};
+        if (std::sscanf(br, "{\"rhs_group\": %d, \"dhat_walk\": %d, \"dhat_rhs\": %d, \"bicg_fuse\": %d, \"ms\": %lf",
+                        &r.rhs_group, &r.dhat_walk, &r.dhat_rhs, &r.bicg_fuse, &r.ms) == 5)
+            out.emplace_back(std::string(q0 + 1, q1), r);
+    }
+    std::fclose(f);
+    return true;
+}
+
+bool bicg_cache_write(const char *path, const std::vector<std::pair<std::string, dd_bicg_tune_result>> &ent)
+{
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return false;
+    std::fprintf(f, "{\n");
+    for (size_t i = 0; i < ent.size(); i++) {
+        const dd_bicg_tune_result &r = ent[i].second;
+        std::fprintf(f, "\"%s\": {\"rhs_group\": %d, \"dhat_walk\": %d, \"dhat_rhs\": %d, \"bicg_fuse\": %d, \"ms\": %.6f}%s\n",
+                     ent[i].first.c_str(), r.rhs_group, r.dhat_walk, r.dhat_rhs, r.bicg_fuse, r.ms,
+                     i + 1 < ent.size() ? "," : "");
+    }
+    std::fprintf(f, "}\n");
+    const bool ok = std::fclose(f) == 0;
+    return ok && std::rename(tmp.c_str(), path) == 0;
+}
+
+}  // namespace
+
+dd_status dd_autotune_bicgstab(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *G, double kappa, const void *b_dev,
+                               void *x_dev, int32_t n_rhs, const dd_solve_params *params, const char *cache_path,
+                               dd_bicg_tune_result *results, int32_t max_results, int32_t *n_results,
+                               int32_t *from_cache)
+{
+    if (!ctx || !B || !G || !b_dev || !x_dev) return fail(ctx, DD_EINVAL, "null argument");
+    if (n_rhs < 1 || n_rhs > kMaxRhs) return fail(ctx, DD_EINVAL, "n_rhs must be in 1..64");
+    dd_solve_params p;
+    if (params) p = *params;
+    else dd_solve_params_default(&p);
+    if (p.method != DD_BICGSTAB || p.precond) return fail(ctx, DD_EINVAL, "the BiCGStab autotuner takes plain BiCGStab");
+    const dd_prec ip = p.inner_prec;
+    const bool f64 = ip == DD_F64;
+    int *rg = &ctx->rhs_group[f64 ? DD_TUNE_RHS_GROUP_F64 : DD_TUNE_RHS_GROUP_F32];
+    const int rg0 = *rg, dw0 = ctx->dhat_walk, dr0 = ctx->dhat_rhs, bf0 = ctx->bicg_fuse;
+    auto apply = [&](const dd_bicg_tune_result &c) {
+        *rg = c.rhs_group;
+        ctx->dhat_walk = c.dhat_walk;
+        ctx->dhat_rhs = c.dhat_rhs;
+        ctx->bicg_fuse = c.bicg_fuse;
+    };
+    auto restore = [&]() {
+        *rg = rg0;
+        ctx->dhat_walk = dw0;
+        ctx->dhat_rhs = dr0;
+        ctx->bicg_fuse = bf0;
+    };
+    if (from_cache) *from_cache = 0;
+    if (n_results) *n_results = 0;
+    const std::string key = bicg_tune_key(ctx, B, n_rhs, ip);
+    std::vector<std::pair<std::string, dd_bicg_tune_result>> ent;
+    if (cache_path && bicg_cache_read(cache_path, ent))
+        for (const auto &e : ent)
+            if (e.first == key) {
+                apply(e.second);
+                if (results && max_results > 0) results[0] = e.second;
+                if (n_results) *n_results = 1;
+                if (from_cache) *from_cache = 1;
+                return DD_OK;
+            }
+    // candidates: rhs per thread of the site kernels (1, or 2 when it divides
+    // n_rhs); with a low-precision inner solve the one-kernel Dhat (one or
+    // three rhs per workgroup) or two walk hops (with or without the fused
+    // staging updates); FP64: the two walk hops only
+    std::vector<dd_bicg_tune_result> cand;
+    std::vector<int> groups = {1};
+    if (n_rhs % 2 == 0) groups.push_back(2);
+    for (int g : groups) {
+        if (!f64) {
+            cand.push_back({g, 0, 1, 0, 0.0});
+            cand.push_back({g, 0, 3, 0, 0.0});
+        }
+        cand.push_back({g, -1, 0, 0, 0.0});
+        cand.push_back({g, -1, 0, -1, 0.0});
+    }
+    p.recover = 0;
+    apply(cand[0]);
+    dd_status st = dd_block_solve(ctx, B, G, kappa, b_dev, x_dev, n_rhs, &p, nullptr);  // warm-up
+    if (st != DD_OK && st != DD_ENOCONV) {
+        restore();
+        return st;
+    }
+    for (dd_bicg_tune_result &c : cand) {
+        apply(c);
+        HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
+        const auto t0 = std::chrono::steady_clock::now();
+        st = dd_block_solve(ctx, B, G, kappa, b_dev, x_dev, n_rhs, &p, nullptr);
+        if (st != DD_OK && st != DD_ENOCONV) {
+            restore();
+            return st;
+        }
+        c.ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    const dd_bicg_tune_result *best = &cand[0];
+    for (const dd_bicg_tune_result &c : cand)
+        if (c.ms < best->ms) best = &c;
+    apply(*best);
+    const int nr = std::min<int>((int)cand.size(), std::max(max_results, 0));
+    for (int i = 0; results && i < nr; i++) results[i] = cand[i];
+    if (n_results) *n_results = (int32_t)cand.size();
+    if (cache_path) {
+        ent.emplace_back(key, *best);
+        if (!bicg_cache_write(cache_path, ent)) return fail(ctx, DD_EINVAL, std::string("cannot write ") + cache_path);
+    }
     ctx->err.clear();
     return DD_OK;
 }

@@ -79,6 +79,10 @@ class SolveParams(ctypes.Structure):
     ]
 
 
+class BicgTuneResult(ctypes.Structure):
+    _fields_ = [("rhs_group", _I32), ("dhat_walk", _I32), ("dhat_rhs", _I32), ("bicg_fuse", _I32), ("ms", _D)]
+
+
 class SolveStats(ctypes.Structure):
     _fields_ = [
         ("iters", _P),
@@ -170,6 +174,8 @@ _sig("dd_nn_loss_grad", _I32, [_P, _P, _P, _P, _P, _I32, _P, _I32, _I32, _P, _P]
 _sig("dd_nn_train", _I32, [_P, _P, _P, _P, _P, _I32, _P, _P, _I32, ctypes.POINTER(NnTrainParams), _P, _P])
 _sig("dd_autotune_gmres", _I32, [_P, _P, _P, _D, _P, _P, _I32, ctypes.POINTER(SolveParams),
                                  ctypes.POINTER(TuneResult), _I32, _P])
+_sig("dd_autotune_bicgstab", _I32, [_P, _P, _P, _D, _P, _P, _I32, ctypes.POINTER(SolveParams), ctypes.c_char_p,
+                                   _P, _I32, _P, _P])
 _sig("dd_timer_enable", _I32, [_P, _I32])
 _sig("dd_timer_reset", _I32, [_P])
 _sig("dd_timer_read", _I32, [_P, _I32, _P, _P, _P])
@@ -680,6 +686,26 @@ class Context:
         TUNE_GMRES_REORTH (0 default, -1 never, 1..100 percent) or TUNE_BICG_FUSE (0 where possible,
         -1 never) or TUNE_DHAT_WALK (0 where possible, -1 never)."""
         self._check(_lib.dd_tune_set(self._h, int(what), int(value)))
+
+    def autotune_bicgstab(self, blocks: Blocks, gauge: Gauge, kappa, b, params=None, cache=None, scratch=None):
+        """Times the BiCGStab configurations on full solves of b and keeps the fastest (cache: a JSON file
+        path; a stored entry for this problem is applied without timing).  Returns (list of (rhs_group,
+        dhat_walk, dhat_rhs, bicg_fuse, ms), from_cache)."""
+        import torch
+
+        n_rhs = b.numel() // (blocks.total_sites * 12)
+        if params is None:
+            params = solve_params()
+        x = scratch if scratch is not None else torch.empty_like(b)
+        buf = (BicgTuneResult * 16)()
+        n = _I32()
+        hit = _I32()
+        self._check(_lib.dd_autotune_bicgstab(self._h, blocks._h, gauge._h, float(kappa),
+                                              _dev(b, "torch.complex128"), _dev(x, "torch.complex128"), int(n_rhs),
+                                              ctypes.byref(params), cache.encode() if cache else None, buf, 16,
+                                              ctypes.byref(n), ctypes.byref(hit)))
+        out = [(r.rhs_group, r.dhat_walk, r.dhat_rhs, r.bicg_fuse, r.ms) for r in buf[:n.value]]
+        return out, bool(hit.value)
 
     def autotune_gmres(self, blocks: Blocks, gauge: Gauge, kappa, b, params=None, scratch=None):
         """Times the persistent GMRES schedules on b's first inner solve and keeps the fastest.
