@@ -193,40 +193,53 @@ def mb_global_action(L, tbc, kappa, U, boxes, inner, u, chi, tol=1e-13, csw=0.0)
     return out
 
 
-def apply_w(L, tbc, kappa, U, boxes, inner, z, chi, tol=1e-13):
+def apply_w(L, tbc, kappa, U, boxes, inner, z, chi, tol=1e-13, csw=0.0):
     """W_z chi of eq. (MBaction) as a vector on dPi, one z per field: z [n_fields] complex, chi
     [n_fields, V, 4, 3] (only its dPi values are used).  Rows on dLambda_0^a are the vector whose norm
     is S_MB^a (eq. localMB): z chi + (D_{Omega_0^a}^{-1} xi^a) with xi^a the hops of chi from dPi
     into Omega_0^a (exterior_source); rows on dPi_1 are those whose norm is S^r_MB (eq. globalMB):
     z chi + [D_{Lambda_1}^{-1} D_{Lambda_1, dLambda_0} chi] (as in mb_global_action).  Zero off dPi.
-    At z = 0 it is the off-diagonal part W_1 - 1 of W_1."""
+    At z = 0 it is the off-diagonal part W_1 - 1 of W_1.  With csw != 0 the operator is the
+    Sheikholeslami-Wohlert one: its clover term is site-diagonal, so the hops (the sources) are
+    unchanged and the block and inactive-region solves take it (masked solves on each box's sites;
+    the boxes must not wrap onto themselves)."""
     boxes = np.asarray(boxes, dtype=np.int32).reshape(-1, 8)
     B = geometry.BoxDomains(L, boxes, inner)
     z = np.asarray(z, dtype=np.complex128).reshape(-1)
     c = np.zeros_like(np.asarray(chi, dtype=np.complex128))
     c[:, B.dPi] = np.asarray(chi)[:, B.dPi]
     out = np.zeros_like(c)
+    A = clover.clover_matrix(L, U, kappa, csw) if csw != 0.0 else None
     xi = exterior_source(L, tbc, kappa, U, boxes, inner, c, "all")
-    y, _, _, fails = wilson.solve_many(L, tbc, kappa, U, boxes, xi, tol=tol)
-    if fails:
-        raise RuntimeError("oracle block solve did not converge")
+    if A is None:
+        y, _, _, fails = wilson.solve_many(L, tbc, kappa, U, boxes, xi, tol=tol)
+        if fails:
+            raise RuntimeError("oracle block solve did not converge")
     bl = boundary_lists(L, boxes, inner)
     off = 0
     for b, bx in enumerate(boxes):
         sites = geometry.box_sites(L, bx[:4], bx[4:8])
         g = sites[bl[b]]
         for k in range(z.size):
-            out[k][g] = z[k] * c[k][g] + y[k, off + bl[b]]
+            if A is None:
+                yb = y[k, off + bl[b]]
+            else:
+                mask = np.zeros(c.shape[1], dtype=bool)
+                mask[sites] = True
+                f = np.zeros_like(c[k])
+                f[sites] = xi[k, off:off + sites.size]
+                yb = solve_masked(L, tbc, kappa, U, mask, f, tol=tol, csw=csw, A=A)[g]
+            out[k][g] = z[k] * c[k][g] + yb
         off += sites.size
     for k in range(z.size):
         d = np.zeros_like(c[k])
         d[B.dlam0] = c[k][B.dlam0]
-        v = solve_masked(L, tbc, kappa, U, B.lam1, wilson.dirac_full(L, tbc, kappa, U, d), tol=tol)
+        v = solve_masked(L, tbc, kappa, U, B.lam1, wilson.dirac_full(L, tbc, kappa, U, d), tol=tol, csw=csw, A=A)
         out[k][B.dPi1] = z[k] * c[k][B.dPi1] + v[B.dPi1]
     return out
 
 
-def generate(L, tbc, kappa, U, boxes, inner, u, eta, tol=1e-11, inner_tol=1e-13, maxit=200):
+def generate(L, tbc, kappa, U, boxes, inner, u, eta, tol=1e-11, inner_tol=1e-13, maxit=200, csw=0.0):
     """The multi-boson fields of Section 4 from Gaussian noise: chi_k = W_{u_k}^{-1} eta_k on dPi
     (then chi_k has the density exp(-|W_{u_k} chi_k|^2) when eta_k has exp(-|eta_k|^2)).  This is
     the one global inversion of the method, on a vector of dPi (Conclusions).  u [n_fields] complex;
@@ -240,7 +253,7 @@ def generate(L, tbc, kappa, U, boxes, inner, u, eta, tol=1e-11, inner_tol=1e-13,
     its = np.zeros(u.size, dtype=np.int64)
 
     def op(k, y):
-        return apply_w(L, tbc, kappa, U, boxes, inner, [u[k]], y[None], tol=inner_tol)[0]
+        return apply_w(L, tbc, kappa, U, boxes, inner, [u[k]], y[None], tol=inner_tol, csw=csw)[0]
 
     for k in range(u.size):
         b = np.zeros_like(eta[k])
@@ -275,7 +288,7 @@ def generate(L, tbc, kappa, U, boxes, inner, u, eta, tol=1e-11, inner_tol=1e-13,
     return chi, its
 
 
-def apply_remainder(L, tbc, kappa, U, boxes, inner, N, c, y, tol=1e-13):
+def apply_remainder(L, tbc, kappa, U, boxes, inner, N, c, y, tol=1e-13, csw=0.0):
     """R_{N+1}(W_1) y on dPi for y [n_vec, V, 4, 3], with the remainder in its Chebyshev form
     R_{N+1}(z) = T_{N+1}((1 - z)/c) / T_{N+1}(1/c) (oracle.roots; it has the printed roots).  Its
     argument (1 - W_1)/c is -(W_1 - 1)/c = -W_0/c, so the three-term recurrence
@@ -288,7 +301,7 @@ def apply_remainder(L, tbc, kappa, U, boxes, inner, N, c, y, tol=1e-13):
     zero = np.zeros(y.shape[0])
 
     def X(v):
-        return -apply_w(L, tbc, kappa, U, boxes, inner, zero, v, tol=tol) / c
+        return -apply_w(L, tbc, kappa, U, boxes, inner, zero, v, tol=tol, csw=csw) / c
 
     t1 = X(t0)
     for _ in range(N):
@@ -296,7 +309,7 @@ def apply_remainder(L, tbc, kappa, U, boxes, inner, N, c, y, tol=1e-13):
     return t1 / float(np.real(roots.chebyshev_T(N + 1, np.asarray(1.0 / c))))
 
 
-def log_reweight_estimate(L, tbc, kappa, U, boxes, inner, N, c, eta, order, tol=1e-13):
+def log_reweight_estimate(L, tbc, kappa, U, boxes, inner, N, c, eta, order, tol=1e-13, csw=0.0):
     """Stochastic estimate of ln W_N, W_N = det{1 - R_{N+1}(W_1)} of eq. (rw), by
     ln det(1 - R) = Tr ln(1 - R) = -sum_{m >= 1} Tr(R^m)/m truncated after `order` terms, each trace
     by the noise vectors eta [n_vec, V, 4, 3] (values on dPi; any noise with E[eta eta^+] = 1, or the
@@ -310,7 +323,7 @@ def log_reweight_estimate(L, tbc, kappa, U, boxes, inner, N, c, eta, order, tol=
     out = np.zeros(eta.shape[0], dtype=np.complex128)
     w = e0
     for m in range(1, order + 1):
-        w = apply_remainder(L, tbc, kappa, U, boxes, inner, N, c, w, tol=tol)
+        w = apply_remainder(L, tbc, kappa, U, boxes, inner, N, c, w, tol=tol, csw=csw)
         for j in range(eta.shape[0]):
             out[j] -= np.vdot(e0[j], w[j]) / m
     return out

@@ -150,13 +150,11 @@ def test_reweight_estimator_is_unbiased_in_the_mean():
     assert abs(e.real.mean() - exact.real) <= 4 * se
 
 
-def test_global_action_with_clover_matches_dense():
-    """S^r_MB with the Sheikholeslami-Wohlert operator (one masked solve on Lambda_1 with the clover
-    term) equals the dPi_1 rows of the dense W_z built from the dense clover matrix (T3)."""
+def _clover_setup(kappa, csw):
+    """T3 with the Sheikholeslami-Wohlert operator: domains, links, and the pieces of its dense matrix."""
     from oracle import clover
 
     L, spec, seed = T3
-    kappa, csw = 0.12, 1.4
     P = geometry.PaperDomains(L, spec)
     U = synth.gauge_field(L, 0.5, seed)
     A = clover.clover_matrix(L, U, kappa, csw)
@@ -168,7 +166,14 @@ def test_global_action_with_clover_matches_dense():
         ef[j] = 1.0
         M[:, j] = clover.dirac_clover_full(L, -1, kappa, csw, U, e, A=A).reshape(-1)
         ef[j] = 0.0
-    pc = factor.pieces(M, P)
+    return L, seed, P, U, factor.pieces(M, P)
+
+
+def test_global_action_with_clover_matches_dense():
+    """S^r_MB with the Sheikholeslami-Wohlert operator (one masked solve on Lambda_1 with the clover
+    term) equals the dPi_1 rows of the dense W_z built from the dense clover matrix (T3)."""
+    kappa, csw = 0.12, 1.4
+    L, seed, P, U, pc = _clover_setup(kappa, csw)
     boxes, inner = _box_lists(P)
     z = complex(0.3, 0.7)
     chi = synth.gaussian_complex((1, P.V, 4, 3), seed + 21)
@@ -180,3 +185,24 @@ def test_global_action_with_clover_matches_dense():
     # and the term matters
     S_w = mb.mb_global_action(L, -1, kappa, U, boxes, inner, [z], chi)
     assert abs(S_w[0] - S_r[0]) > 1e-3 * S_rest
+
+
+def test_apply_w_and_generate_with_clover_match_dense():
+    """W_z chi and chi = W_u^{-1} eta with the Sheikholeslami-Wohlert operator against the dense W_z
+    built from the dense clover matrix (T3), row for row; and the term matters."""
+    kappa, csw = 0.12, 1.4
+    L, seed, P, U, pc = _clover_setup(kappa, csw)
+    boxes, inner = _box_lists(P)
+    z = [0.3 + 0.7j, 0.0]
+    chi = synth.gaussian_complex((2, P.V, 4, 3), seed + 31)
+    out = mb.apply_w(L, -1, kappa, U, boxes, inner, z, chi, csw=csw)
+    for k in range(2):
+        ref = factor.w_z(pc, z[k]) @ _vec(pc, chi[k])
+        assert np.linalg.norm(_vec(pc, out[k]) - ref) <= 1e-11 * np.linalg.norm(ref), k
+    wil = mb.apply_w(L, -1, kappa, U, boxes, inner, z, chi)
+    assert np.linalg.norm(wil[0] - out[0]) > 1e-3 * np.linalg.norm(out[0])
+    u = roots.mb_roots(4, 0.5)[:1]
+    eta = synth.gaussian_complex((1, P.V, 4, 3), seed + 32) / np.sqrt(2)
+    x, its = mb.generate(L, -1, kappa, U, boxes, inner, u, eta, tol=1e-12, csw=csw)
+    ref = np.linalg.solve(factor.w_z(pc, u[0]), _vec(pc, eta[0]))
+    assert np.linalg.norm(_vec(pc, x[0]) - ref) <= 1e-10 * np.linalg.norm(ref)
