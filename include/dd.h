@@ -404,8 +404,11 @@ dd_status dd_mb_global_action(dd_ctx *ctx, const dd_blocks *domain, const dd_gau
  *   domain.  At z = 0 this is W_1 - 1, the off-diagonal part of W_1.
  * blocks/gauge: blocks with inner boxes and their gauge; domain/domain_gauge:
  * dd_make_inactive of these blocks and its gauge (the same links; DD_EINVAL
- * for a domain made from other blocks).  The clover term is refused
- * (DD_EUNSUPPORTED).  z_host: [n_fields][2] (re, im).  chi_global_dev,
+ * for a domain made from other blocks).  With the clover term
+ * (dd_gauge_set_clover) on both gauges, same kappa and c_sw, the operator is
+ * the Sheikholeslami-Wohlert one (the term is site-diagonal: the exterior
+ * hops are unchanged, the solves take it); DD_EINVAL when only one gauge
+ * carries it or the two differ.  z_host: [n_fields][2] (re, im).  chi_global_dev,
  * out_global_dev: [n_fields][V][4][3] complex128 on the lattice in canonical
  * order, distinct buffers; chi is read on dPi only, out is written everywhere
  * (zero off dPi).  params: the inner solves (NULL: defaults; their tolerance

@@ -288,7 +288,10 @@ dd_status wop_check(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *G, const dd
     if (!D->inactive || D->parent != B->serial)
         return fail(ctx, DD_EINVAL, "domain must be dd_make_inactive of these blocks");
     if (G->blocks != B || GD->blocks != D) return fail(ctx, DD_EINVAL, "a gauge was loaded for other blocks");
-    if (G->d_cla64 || GD->d_cla64) return fail(ctx, DD_EUNSUPPORTED, "the clover term is not supported here");
+    // the clover term: both solves must see the same operator
+    if ((G->d_cla64 != nullptr) != (GD->d_cla64 != nullptr) ||
+        (G->d_cla64 && (G->cl_csw != GD->cl_csw || G->cl_kappa != GD->cl_kappa)))
+        return fail(ctx, DD_EINVAL, "the two gauges must carry the same clover term (or none)");
     if (B->x_code.empty() || B->bnd.empty())
         return fail(ctx, DD_EINVAL, "the blocks have no inner boxes (dLambda_0 is empty)");
     return DD_OK;

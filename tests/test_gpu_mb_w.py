@@ -10,7 +10,8 @@ dense W_z in test_oracle_global.py).
   solution is unique, so this pins chi to within cond(W) 1e-9); zero off dPi.
 * Reweighting estimate: per noise vector, the terms -sum_m eta^+ R^m eta / m equal the oracle's (same
   noise, Chebyshev recurrence of R_{N+1}) within 1e-8 of the largest.
-* Refusals: a domain made from other blocks, out aliasing chi, a clover gauge, odd N.
+* The same three with the Sheikholeslami-Wohlert term on both gauges (against the oracle's clover W_z).
+* Refusals: a domain made from other blocks, out aliasing chi, a clover term on one gauge only, odd N.
 """
 import numpy as np
 import pytest
@@ -143,3 +144,42 @@ def test_global_pieces_refusals(ctx):
     with pytest.raises(dd.DDError):
         ctx.mb_apply_W(blk, g, D, gd, KAPPA, [0.5], chi)
     _close(g_other, other, gd, g, D, blk)
+
+
+@pytest.mark.parametrize("case", ["tiles_inner", "paper_3d"])
+def test_global_pieces_with_clover_match_oracle(ctx, case):
+    """W_z chi (two z), the generated fields and the reweighting terms with the Sheikholeslami-Wohlert
+    term on both gauges, against the oracle's clover W_z (pinned by the dense clover matrix)."""
+    from paper_2211_06902_amd import dd
+
+    kappa, csw = 0.13, 1.6
+    L, U, blk, D, g, gd, boxes, inner = _setup(ctx, case, 6651)
+    g.set_clover(_dev(U), kappa, csw)
+    gd.set_clover(_dev(U), kappa, csw)
+    V = int(np.prod(L))
+    prm = dd.solve_params(tol=1e-12)
+    z = [0.5 + 0.2j, 0.0] if case == "paper_3d" else [0.5 + 0.2j]  # the oracle's clover box solves are slow
+    chi = synth.gaussian_complex((len(z), V, 4, 3), 6652)
+    out, info, st = ctx.mb_apply_W(blk, g, D, gd, kappa, z, _dev(chi), params=prm)
+    assert st == dd.DD_OK
+    got = out.cpu().numpy()
+    ref = mb.apply_w(L, -1, kappa, U, boxes, inner, z, chi, csw=csw)
+    for k in range(len(z)):
+        assert np.linalg.norm(got[k] - ref[k]) <= 1e-10 * np.linalg.norm(ref[k]), k
+        assert np.abs(got[k] - ref[k]).max() <= 1e-9 * np.abs(ref[k]).max(), k
+    if case == "paper_3d":
+        u = roots.mb_roots(4, 0.5)[:2]
+        eta = synth.gaussian_complex((2, V, 4, 3), 6653) / np.sqrt(2)
+        x, its, rel, info, st = ctx.mb_generate(blk, g, D, gd, kappa, u, _dev(eta), tol=1e-10, params=prm)
+        assert st == dd.DD_OK and np.all(rel <= 1e-9)
+        x = x.cpu().numpy()
+        W = mb.apply_w(L, -1, kappa, U, boxes, inner, u, x, csw=csw)
+        dpi = geometry.BoxDomains(L, boxes, inner).dPi
+        for k in range(2):
+            e = np.where(dpi[:, None, None], eta[k], 0)
+            assert np.linalg.norm(W[k] - e) <= 1e-9 * np.linalg.norm(e), k
+        terms, est, info, st = ctx.mb_log_reweight(blk, g, D, gd, kappa, 2, 0.9, 1, _dev(eta[:1]), params=prm)
+        assert st == dd.DD_OK
+        ref_t = mb.log_reweight_estimate(L, -1, kappa, U, boxes, inner, 2, 0.9, eta[:1], 1, csw=csw)
+        assert np.abs(terms - ref_t).max() <= 1e-8 * np.abs(ref_t).max()
+    _close(gd, g, D, blk)
