@@ -289,6 +289,13 @@ typedef struct {
                             breakdowns, non-finite inner values) are solved again from x = 0
                             with the library's default FP64 inner BiCGStab and iteration
                             limits (same tol); their flags get bit 3.  0: off */
+    int32_t x0;          /* 1: x_dev holds an initial guess on entry (read, then overwritten with
+                            the solution; it must not be b_dev): the first cycle takes the FP64
+                            residual b - D_Lambda x0 (the tolerance stays relative to |b|), and
+                            pairs whose guess already meets tol are not iterated.  0 (default):
+                            x_dev is output only and every pair starts from x = 0.  Pairs that
+                            recover solves again start from 0.  The multi-boson and global
+                            entry points ignore it (their solutions are internal). */
 } dd_solve_params;
 
 typedef struct {
@@ -312,7 +319,8 @@ void dd_solve_params_default(dd_solve_params *p);
 
 /* x = D_Lambda^{-1} b for every (block, rhs) pair, all blocks in one batch
  * (Section 3: the D_{Omega_0^a}^{-1} of eq. offdiagW1 and eq. localMB).
- * b_dev, x_dev: [n_rhs][total_sites][4][3] complex128; x_dev is output only.
+ * b_dev, x_dev: [n_rhs][total_sites][4][3] complex128; x_dev is output only
+ * unless params->x0 asks for a warm start.
  * Method: FP64 defect correction on the true residual around an even-odd
  * Krylov solve of Dhat = 1 - kappa^2 H_eo H_oe in inner_prec.  Pair arrays
  * are ordered pair = rhs * n_blocks + block.  Returns DD_ENOCONV (stats

@@ -76,6 +76,7 @@ extern "C" dd_status dd_mb_global_action(dd_ctx *ctx, const dd_blocks *D, const 
     dd_solve_params prm;
     if (params) prm = *params;
     else dd_solve_params_default(&prm);
+    prm.x0 = 0;  // the solutions are internal workspaces
     const int64_t V = D->soff[1];
     const int64_t n = (int64_t)D->dpi1.size();
     const int nchunk = (int)std::max<int64_t>(1, (n + kGlobChunk - 1) / kGlobChunk);
@@ -329,6 +330,7 @@ dd_status wop_init(WOp &w, dd_ctx *ctx, const dd_blocks *B, const dd_gauge *G, c
     w.kappa = kappa;
     if (params) w.prm = *params;
     else dd_solve_params_default(&w.prm);
+    w.prm.x0 = 0;  // the solutions are internal workspaces
     w.fc = fc;
     w.V = D->soff[1];
     w.totalB = B->soff[B->nb];

@@ -288,6 +288,7 @@ dd_status block_solve_impl(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, 
     if (params) prm = *params;
     else dd_solve_params_default(&prm);
     if (!(prm.tol > 0)) return fail(ctx, DD_EINVAL, "tol must be positive");
+    if (prm.x0 && x_dev == b_dev) return fail(ctx, DD_EINVAL, "a warm start needs x distinct from b");
     if (prm.method != DD_BICGSTAB && prm.method != DD_GMRES) return fail(ctx, DD_EINVAL, "unknown method");
     const bool gmres = prm.method == DD_GMRES;
     if (gmres && (prm.restart < 1 || prm.restart > 16)) return fail(ctx, DD_EINVAL, "restart must be in 1..16");
@@ -424,8 +425,14 @@ dd_status block_solve_impl(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, 
     HIPCHECK(ctx, hipMemsetAsync(pi, 0, (size_t)np * 5 * sizeof(int32_t), st));
     HIPCHECK(ctx, hipMemsetAsync(pd, 0, (size_t)np * 13 * sizeof(double), st));
     if (gm_bytes) HIPCHECK(ctx, hipMemsetAsync(gm_bytes, 0, (size_t)np * sizeof(double), st));
-    HIPCHECK(ctx, hipMemsetAsync(w.xe, 0, h64, st));
-    HIPCHECK(ctx, hipMemsetAsync(w.xo, 0, h64, st));
+    // a warm start packs the caller's guess; otherwise every pair starts from x = 0
+    const bool warm = prm.x0 != 0;
+    if (warm) {
+        HIPCHECK(ctx, launch_pack_spinor(B, (const double *)x_dev, w.xe, w.xo, DD_F64, n_rhs, st));
+    } else {
+        HIPCHECK(ctx, hipMemsetAsync(w.xe, 0, h64, st));
+        HIPCHECK(ctx, hipMemsetAsync(w.xo, 0, h64, st));
+    }
     HIPCHECK(ctx, launch_pack_spinor(B, (const double *)b_dev, w.be, w.bo, DD_F64, n_rhs, st));
 
     Inner in{ctx, B, ba, &w, links, ip, sp, kappa, inner_tol, gmres ? nullptr : nn, bc_ph, bc_sh, n_rhs,
@@ -448,10 +455,18 @@ dd_status block_solve_impl(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, 
     dd_status status = DD_OK;
     for (int cyc = 0;; cyc++) {
         // FP64 true residual r_p = b_p - x_p + kappa H x_{1-p}, |r|^2 per pair;
-        // the first cycle starts from x = 0, where r = b
-        double *r_e = cyc == 0 ? w.be : w.re, *r_o = cyc == 0 ? w.bo : w.ro;
+        // the first cycle starts from x = 0, where r = b, unless a warm start
+        // gave x: then |b|^2 is taken first (the reference of tol) and the
+        // residual of the guess after it
+        const bool from_zero = cyc == 0 && !warm;
+        double *r_e = from_zero ? w.be : w.re, *r_o = from_zero ? w.bo : w.ro;
+        if (cyc == 0 && warm) {
+            HIPCHECK(ctx, launch_norm2(ba64, DD_F64, w.be, w.pe, st));
+            HIPCHECK(ctx, launch_norm2(ba64, DD_F64, w.bo, w.po, st));
+            HIPCHECK(ctx, launch_sc_outer(ba64, w.pe, w.po, 1, prm.tol, w.os, st));
+        }
         for (int p = 0; p < 2; p++) {
-            if (cyc == 0) {
+            if (from_zero) {
                 HIPCHECK(ctx, launch_norm2(ba64, DD_F64, p ? w.bo : w.be, p ? w.po : w.pe, st));
                 continue;
             }
@@ -474,7 +489,7 @@ dd_status block_solve_impl(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, 
             if (cyc >= 2) h.skip_act = w.os.active;
             HIPCHECK(ctx, run_hop(ctx, B, ba64, h, DD_F64));
         }
-        HIPCHECK(ctx, launch_sc_outer(ba64, w.pe, w.po, cyc == 0, prm.tol, w.os, st));
+        HIPCHECK(ctx, launch_sc_outer(ba64, w.pe, w.po, from_zero, prm.tol, w.os, st));
         HIPCHECK(ctx, hipMemcpyAsync(h_act.data(), w.os.active, np * sizeof(int32_t), hipMemcpyDeviceToHost, st));
         HIPCHECK(ctx, hipStreamSynchronize(st));
         int n_act = 0;
@@ -760,6 +775,7 @@ dd_status dd_autotune_gmres(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *G, 
     else dd_solve_params_default(&p);
     if (p.restart < 1 || p.restart > 16) return fail(ctx, DD_EINVAL, "restart must be in 1..16");
     // one outer cycle whose inner solve runs exactly `restart` steps per pair
+    p.x0 = 0;
     p.method = DD_GMRES;
     p.max_outer = 1;
     p.inner_tol = 1e-300;
@@ -957,6 +973,7 @@ dd_status dd_autotune_bicgstab(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *
         cand.push_back({g, -1, 0, -1, 0.0});
     }
     p.recover = 0;
+    p.x0 = 0;
     apply(cand[0]);
     dd_status st = dd_block_solve(ctx, B, G, kappa, b_dev, x_dev, n_rhs, &p, nullptr);  // warm-up
     if (st != DD_OK && st != DD_ENOCONV) {
@@ -1000,6 +1017,7 @@ dd_status dd_multiboson_action(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *
     dd_solve_params prm;
     if (params) prm = *params;
     else dd_solve_params_default(&prm);
+    prm.x0 = 0;  // the solutions are internal workspaces
     // fields per block solve: the solver's workspace grows with the rhs of a call
     // (FP64 half fields, inner-precision Krylov vectors and the solutions), so
     // large lattices are solved a few fields at a time.  The context's own

@@ -76,6 +76,7 @@ class SolveParams(ctypes.Structure):
         ("precond", _P),
         ("precond_cycles", _I32),
         ("recover", _I32),
+        ("x0", _I32),
     ]
 
 

@@ -387,3 +387,45 @@ def test_dhat_walk_three_rhs_per_workgroup(ctx, inner):
             sl = slice(off[k], off[k + 1])
             assert _true_relres(L, kappa, U, bx, x3[r, sl], b[r, sl]) <= TOL, (r, k)
     g.close()
+
+
+@pytest.mark.parametrize("inner", ["f32", "f64"])
+def test_warm_start(ctx, inner):
+    """params.x0: from the converged solution nothing is iterated and x comes back unchanged; from a
+    perturbed one the solve takes fewer iterations and meets the tolerance (the oracle's residual);
+    x aliasing b is refused."""
+    import torch
+
+    from paper_2211_06902_amd import dd
+
+    L = (16, 16, 16, 16)
+    kappa = 0.1355
+    U = synth.gauge_field(L, 0.2, 7301)
+    blk = ctx.make_blocks(L, -1, [[8, 8]] * 4)
+    g = ctx.load_gauge(blk, _dev(U), "f32")
+    b_np = synth.gaussian_complex((3, blk.total_sites, 4, 3), 7302)
+    b = _dev(b_np)
+    x_cold, info_c, st = ctx.block_solve(blk, g, kappa, b, params=dd.solve_params(inner_prec=inner))
+    assert st == dd.DD_OK
+    warm = dd.solve_params(inner_prec=inner, x0=1)
+    x = x_cold.clone()
+    x, info_w, st = ctx.block_solve(blk, g, kappa, b, x=x, params=warm)
+    assert st == dd.DD_OK and info_w["outer_cycles"] == 0 and np.all(info_w["iters"] == 0)
+    assert torch.equal(x, x_cold)
+    noise = _dev(synth.gaussian_complex((3, blk.total_sites, 4, 3), 7303))
+    xp = x_cold + 1e-6 * noise * (x_cold.abs().max() / noise.abs().max())
+    xp, info_p, st = ctx.block_solve(blk, g, kappa, b, x=xp, params=warm)
+    assert st == dd.DD_OK and np.all(info_p["true_relres"] <= TOL)
+    assert info_p["iters"].sum() < info_c["iters"].sum()
+    xc, xw = x_cold.cpu().numpy(), xp.cpu().numpy()
+    assert np.linalg.norm(xw - xc) <= 1e-8 * np.linalg.norm(xc)
+    boxes = blk.tables()[0]
+    off = _cfg.site_offsets(boxes[:, :8])
+    for k in (0, len(boxes) - 1):
+        sl = slice(off[k], off[k + 1])
+        for r in range(3):
+            assert _true_relres(L, kappa, U, boxes[k], xw[r, sl], b_np[r, sl]) <= TOL, (k, r)
+    with pytest.raises(dd.DDError):
+        ctx.block_solve(blk, g, kappa, b, x=b, params=warm)
+    g.close()
+    blk.close()
