@@ -223,8 +223,9 @@ dd_status dd_gauge_export(dd_ctx *ctx, const dd_gauge *gauge, dd_prec prec, void
  * (DD_EINVAL); solves run even-odd BiCGStab on
  * 1 - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe (DD_EUNSUPPORTED for GMRES or a network
  * preconditioner; the hops of blocks the x0-walk cannot take, such as an
- * inactive region, run in the chunked hop kernel); dd_block_logdet
- * returns DD_EUNSUPPORTED.  c_sw = 0 removes the term (the Wilson operator).
+ * inactive region, run in the chunked hop kernel); dd_block_logdet takes
+ * det A_ee det A_oo det(that operator).  c_sw = 0 removes the term (the
+ * Wilson operator).
  * Errors: DD_EINVAL (null argument, non-finite kappa or c_sw), DD_ENOMEM. */
 dd_status dd_gauge_set_clover(dd_ctx *ctx, dd_gauge *gauge, const void *U_dev, double kappa, double csw);
 
@@ -479,7 +480,11 @@ dd_status dd_mb_log_reweight(dd_ctx *ctx, const dd_blocks *blocks, const dd_gaug
  * (device, [n_blocks][2], may be NULL); total_host (may be NULL) [2]: the sum
  * over blocks (phase wrapped).  det D_Lambda = det(1 - kappa^2 H_eo H_oe) on
  * the even sites, assembled densely per block from the FP64 links and
- * factorised by batched LU with partial pivoting.  Every block must have the
+ * factorised by batched LU with partial pivoting.  With the clover term
+ * (dd_gauge_set_clover, same kappa; DD_EINVAL otherwise) det D_Lambda =
+ * det A_ee det A_oo det(1 - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe), the last
+ * assembled the same way with A^-1 in the hops, ln det A(x) of every block
+ * site by LU of its two 6x6 chirality blocks.  Every block must have the
  * same number h of sites per parity with 12 h <= 6144 (DD_EUNSUPPORTED
  * otherwise); the dense matrices take 16 (12 h)^2 bytes per block (at most
  * 8 GiB at a time). */

@@ -23,6 +23,7 @@
 #include <complex>
 #include <string>
 
+#include "dd_geometry.h"
 #include "dd_host.h"
 #include "dd_internal.h"
 #include "dd_stencil.h"
@@ -204,11 +205,15 @@ __device__ __forceinline__ void store_packed(T *blk, int64_t S, int s, int k0, c
 
 // One thread per block site: A and A^-1 (Gauss-Jordan with partial pivoting,
 // FP64, the row exchanges as selects so that every register index is static).
+// Sites in a block's hole (hole[q] != 0; hole may be null) get A = 1, so the
+// operator stays the identity there as it is for the Wilson operator.
 __global__ void __launch_bounds__(64) k_clover_build(PackGeom g, const double *U, Sigmas sg, double kc, double *a64,
-                                                     double *i64, float *a32, float *i32, int64_t total)
+                                                     double *i64, float *a32, float *i32, int64_t total,
+                                                     const uint8_t *hole)
 {
     const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= total) return;
+    const bool in_hole = hole && hole[q] != 0;
     const int b = find_block(g.soff, g.nb, q);
     const int s = (int)(q - g.soff[b]);
     const int64_t S = 2 * (int64_t)g.h[b];
@@ -231,7 +236,7 @@ __global__ void __launch_bounds__(64) k_clover_build(PackGeom g, const double *U
                 ai[i][j] = 0.0;
             }
 #pragma unroll 1
-        for (int p = 0; p < 6; p++) {
+        for (int p = 0; p < (in_hole ? 0 : 6); p++) {
             M3 F;
             field_strength(U, lat, x, kPlaneMu[p], kPlaneNu[p], F);
             // A += i kc (s_p (x) F): entry (3a + ci, 3b + di) += i kc s[a][b] F[ci][di]
@@ -343,18 +348,126 @@ __global__ void __launch_bounds__(256) k_clover_apply(const int64_t *soff, const
     for (int c = 0; c < 24; c++) y[base + (int64_t)c * hb] = v[c];
 }
 
+// ln det A(x) of every block site from the stored FP64 packed hermitian
+// chirality blocks: LU with partial pivoting per block (row exchanges as
+// selects, so that every register index is static); out[2 q] = sum of
+// ln |U_ii| over both blocks, out[2 q + 1] = the sum of their phases plus pi
+// per exchange (A is hermitian, so the phase is a multiple of pi up to
+// rounding).
+__global__ void __launch_bounds__(64) k_clover_logdet(const int64_t *soff, int nb, const double *a64, double *out,
+                                                      int64_t total)
+{
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= total) return;
+    const int b = find_block(soff, nb, q);
+    const int64_t S = soff[b + 1] - soff[b], s = q - soff[b];
+    const double *blk = a64 + soff[b] * kCloverReals;
+    double lr = 0, ph = 0;
+    for (int ch = 0; ch < 2; ch++) {
+        const int k0 = ch * kCloverHalf;
+        double mr[6][6], mi[6][6];
+#pragma unroll
+        for (int i = 0; i < 6; i++) {
+            mr[i][i] = blk[(int64_t)(k0 + i) * S + s];
+            mi[i][i] = 0.0;
+        }
+        int t = 0;
+#pragma unroll
+        for (int i = 0; i < 6; i++)
+#pragma unroll
+            for (int j = i + 1; j < 6; j++, t++) {
+                const double hr = blk[(int64_t)(k0 + 6 + 2 * t) * S + s], hi = blk[(int64_t)(k0 + 7 + 2 * t) * S + s];
+                mr[i][j] = hr;
+                mi[i][j] = hi;
+                mr[j][i] = hr;
+                mi[j][i] = -hi;
+            }
+#pragma unroll
+        for (int p = 0; p < 6; p++) {
+            int piv = p;
+            double best = mr[p][p] * mr[p][p] + mi[p][p] * mi[p][p];
+#pragma unroll
+            for (int r = p + 1; r < 6; r++) {
+                const double m2 = mr[r][p] * mr[r][p] + mi[r][p] * mi[r][p];
+                if (m2 > best) {
+                    best = m2;
+                    piv = r;
+                }
+            }
+#pragma unroll
+            for (int r = p + 1; r < 6; r++) {
+                const bool sw = r == piv;
+#pragma unroll
+                for (int j = 0; j < 6; j++) {
+                    const double xr = mr[p][j], xi = mi[p][j], yr = mr[r][j], yi = mi[r][j];
+                    mr[p][j] = sw ? yr : xr;
+                    mi[p][j] = sw ? yi : xi;
+                    mr[r][j] = sw ? xr : yr;
+                    mi[r][j] = sw ? xi : yi;
+                }
+            }
+            if (piv != p) ph += M_PI;
+            const double dr = mr[p][p], di = mi[p][p], d2 = dr * dr + di * di;
+            lr += 0.5 * log(d2);
+            ph += atan2(di, dr);
+#pragma unroll
+            for (int r = p + 1; r < 6; r++) {
+                // f = m[r][p] / d
+                const double fr = (mr[r][p] * dr + mi[r][p] * di) / d2, fi = (mi[r][p] * dr - mr[r][p] * di) / d2;
+#pragma unroll
+                for (int j = p + 1; j < 6; j++) {
+                    mr[r][j] -= fr * mr[p][j] - fi * mi[p][j];
+                    mi[r][j] -= fr * mi[p][j] + fi * mr[p][j];
+                }
+            }
+        }
+    }
+    out[2 * q] = lr;
+    out[2 * q + 1] = ph;
+}
+
+// ld[2 b] += sum of the block's site values, ld[2 b + 1] += their phases
+// (wrapped into (-pi, pi]); fixed-order sums, one workgroup per block.
+__global__ void __launch_bounds__(256) k_clover_logdet_add(const double *site, const int64_t *soff, double *ld)
+{
+    __shared__ double sre[256], sim[256];
+    const int b = blockIdx.x;
+    double re = 0, im = 0;
+    for (int64_t q = soff[b] + threadIdx.x; q < soff[b + 1]; q += 256) {
+        re += site[2 * q];
+        im += site[2 * q + 1];
+    }
+    sre[threadIdx.x] = re;
+    sim[threadIdx.x] = im;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            sre[threadIdx.x] += sre[threadIdx.x + w];
+            sim[threadIdx.x] += sim[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        ld[2 * b] += sre[0];
+        double p = fmod(ld[2 * b + 1] + sim[0], 2 * M_PI);
+        if (p > M_PI) p -= 2 * M_PI;
+        if (p <= -M_PI) p += 2 * M_PI;
+        ld[2 * b + 1] = p;
+    }
+}
+
 }  // namespace
 
 namespace dd {
 
 hipError_t launch_clover_build(const dd_blocks *B, const double *U, double kappa, double csw, double *a64,
-                               double *i64, float *a32, float *i32, hipStream_t s)
+                               double *i64, float *a32, float *i32, const uint8_t *hole, hipStream_t s)
 {
     const int64_t total = B->soff[B->nb];
     if (total == 0) return hipSuccess;
     const PackGeom g = pack_geom(B);
     hipLaunchKernelGGL(k_clover_build, dim3((unsigned)((total + 63) / 64)), dim3(64), 0, s, g, U, make_sigmas(),
-                       kappa * csw, a64, i64, a32, i32, total);
+                       kappa * csw, a64, i64, a32, i32, total, hole);
     return hipGetLastError();
 }
 
@@ -372,6 +485,18 @@ hipError_t launch_clover_apply(const dd_blocks *B, const void *C, const void *x,
                            (const float *)x, (float *)y, parity, n_rhs, half, mask);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_clover_logdet_add(const dd_blocks *B, const double *a64, double *site, double *ld, hipStream_t s)
+{
+    const int64_t total = B->soff[B->nb];
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_clover_logdet, dim3((unsigned)((total + 63) / 64)), dim3(64), 0, s, B->d_soff, B->nb, a64,
+                       site, total);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_clover_logdet_add, dim3(B->nb), dim3(256), 0, s, site, B->d_soff, ld);
     return hipGetLastError();
 }
 
@@ -409,8 +534,16 @@ extern "C" dd_status dd_gauge_set_clover(dd_ctx *ctx, dd_gauge *G, const void *U
         clover_release(G);
         return fail(ctx, DD_ENOMEM, std::string("clover term: ") + hipGetErrorString(e));
     }
-    e = launch_clover_build(B, (const double *)U_dev, kappa, csw, G->d_cla64, G->d_cli64, G->d_cla32, G->d_cli32,
-                            ctx->stream);
+    // hole sites (frames, inactive regions) keep the identity
+    const std::vector<uint8_t> hs = hole_slots(B);
+    uint8_t *hole = nullptr;
+    if (e == hipSuccess && !hs.empty()) {
+        hole = (uint8_t *)workspace(ctx, "cl_hole", hs.size(), &e);
+        if (hole) e = hipMemcpyAsync(hole, hs.data(), hs.size(), hipMemcpyHostToDevice, ctx->stream);
+    }
+    if (e == hipSuccess)
+        e = launch_clover_build(B, (const double *)U_dev, kappa, csw, G->d_cla64, G->d_cli64, G->d_cla32,
+                                G->d_cli32, hole, ctx->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
         clover_release(G);

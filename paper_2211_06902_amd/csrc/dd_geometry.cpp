@@ -418,4 +418,22 @@ std::string build_inactive(dd_blocks *D, const dd_blocks *B)
     return "";
 }
 
+std::vector<uint8_t> hole_slots(const dd_blocks *B)
+{
+    bool any = false;
+    for (const Shape &sh : B->shapes) any = any || sh.hole != 0;
+    if (!any) return {};
+    std::vector<uint8_t> out((size_t)B->soff[B->nb], 0);
+    for (int b = 0; b < B->nb; b++) {
+        const Shape &sh = B->shapes[B->shape_of[b]];
+        if (!sh.hole) continue;
+        for (int s = 0; s < sh.S; s++) {
+            int y[4];
+            lcoords(sh.e, B->perm[sh.perm_off + s], y);
+            out[(size_t)B->soff[b] + s] = in_hole(sh, y) ? 1 : 0;
+        }
+    }
+    return out;
+}
+
 }  // namespace dd

@@ -1,7 +1,9 @@
 // Host geometry builder of libdd.
 #pragma once
 
+#include <cstdint>
 #include <string>
+#include <vector>
 
 #include "dd_internal.h"
 
@@ -18,5 +20,10 @@ std::string build_geometry(dd_blocks *B, const int L[4], int tbc, int n, const i
 // decoupled), the hops from those boxes into it as exterior hops, and the
 // dPi_1 site list.  Returns "" or an error message.
 std::string build_inactive(dd_blocks *D, const dd_blocks *B);
+
+// 1 for every block site (block layout: blocks in order, eo slots within a
+// block) that lies in its block's hole (a frame's inner box, or a masked
+// site of an inactive-region domain), else 0; empty when no block has a hole.
+std::vector<uint8_t> hole_slots(const dd_blocks *B);
 
 }  // namespace dd

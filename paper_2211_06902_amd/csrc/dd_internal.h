@@ -441,13 +441,17 @@ struct DlamArgs {
 };
 hipError_t launch_dlam_walk(const BlkArgs &ba, const DlamArgs &da, dd_prec prec, hipStream_t s);
 // clover term (dd_clover.hip): A and A^-1 of every block site from the global
-// FP64 gauge field U[V][4][3][3] (FP64 out; FP32 copies when a32 != null)
+// FP64 gauge field U[V][4][3][3] (FP64 out; FP32 copies when a32 != null);
+// sites with hole[slot] != 0 (hole may be null) get the identity
 hipError_t launch_clover_build(const dd_blocks *B, const double *U, double kappa, double csw, double *a64,
-                               double *i64, float *a32, float *i32, hipStream_t s);
+                               double *i64, float *a32, float *i32, const uint8_t *hole, hipStream_t s);
 // y = C x on half field `parity` of n_rhs rhs (C: kCloverReals per block site
 // in the precision of x; x and y may be the same); pairs whose mask is 0 are
 // left alone (mask may be null)
 void clover_release(dd_gauge *G);  // frees the clover term of a gauge (back to Wilson)
+// ld[2 b], ld[2 b + 1] += ln |det A| and arg det A summed over block b's sites
+// (site: scratch of 2 doubles per block site)
+hipError_t launch_clover_logdet_add(const dd_blocks *B, const double *a64, double *site, double *ld, hipStream_t s);
 hipError_t launch_clover_apply(const dd_blocks *B, const void *C, const void *x, void *y, int parity, int n_rhs,
                                dd_prec sp, const int32_t *mask, hipStream_t s);
 hipError_t launch_convert(const void *src, dd_prec sp, void *dst, dd_prec dp, int64_t n,

@@ -3,7 +3,10 @@
 // ln det D_{Phi_1^a} on frames).
 //
 // det D_Lambda = det Dhat with Dhat = 1 - kappa^2 H_eo H_oe on the even sites
-// (the odd-odd and even-even blocks of D_Lambda are the identity).  Dhat is
+// (the odd-odd and even-even blocks of D_Lambda are the identity).  With the
+// clover term, det D_Lambda = det A_ee det A_oo det Dhat' with
+// Dhat' = 1 - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe (A^-1 applied in the hops) and
+// ln det A(x) per site by LU of its two 6x6 chirality blocks.  Dhat is
 // assembled as a dense n x n complex matrix per block (n = 12 h, h the sites
 // of one parity), column batches of 64 unit vectors at a time through the
 // FP64 hop kernels; the matrices are LU-factorised with partial pivoting by
@@ -96,7 +99,11 @@ extern "C" dd_status dd_block_logdet(dd_ctx *ctx, const dd_blocks *B, const dd_g
 {
     if (!ctx || !B || !G || (!logdet_dev && !total_host)) return fail(ctx, DD_EINVAL, "null argument");
     if (G->blocks != B) return fail(ctx, DD_EINVAL, "gauge was loaded for other blocks");
-    if (G->cl_csw != 0.0) return fail(ctx, DD_EUNSUPPORTED, "dd_block_logdet takes the Wilson operator only");
+    const bool cl = G->d_cla64 != nullptr;
+    if (cl) {
+        const dd_status cs = clover_check(ctx, G, kappa);
+        if (cs != DD_OK) return cs;
+    }
     if (B->nb == 0 || B->nb > 65535) return fail(ctx, DD_EINVAL, "need 1..65535 blocks");
     const int hb = B->shapes[B->shape_of[0]].h;
     for (int k = 1; k < B->nb; k++)
@@ -137,12 +144,15 @@ extern "C" dd_status dd_block_logdet(dd_ctx *ctx, const dd_blocks *B, const dd_g
             hipLaunchKernelGGL(k_unit_batch, dim3((unsigned)((per + 255) / 256), B->nb), dim3(256), 0, st, fe,
                                B->d_soff, hb, j0, per);
             if ((e = hipGetLastError()) != hipSuccess) break;
-            // fo = H_oe e, then fy = e - kappa^2 H_eo fo
+            // fo = H_oe e, then fy = e - kappa^2 H_eo fo; with the clover term
+            // each hop result is multiplied by A^-1 of its output site
             HopArgs h1 = hop_args(fo, fe, G->d_u64, 1, 1.0);
+            h1.clover = cl ? G->d_cli64 : nullptr;
             if ((e = run_hop(ctx, B, ba, h1, DD_F64)) != hipSuccess) break;
             HopArgs h2 = hop_args(fy, fo, G->d_u64, 0, -k2);
             h2.self = fe;
             h2.c_self = 1.0;
+            h2.clover = cl ? G->d_cli64 : nullptr;
             if ((e = run_hop(ctx, B, ba, h2, DD_F64)) != hipSuccess) break;
             const int64_t cols = (int64_t)kCols * n;
             hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)((cols + 255) / 256), nc), dim3(256), 0, st, fy,
@@ -161,6 +171,12 @@ extern "C" dd_status dd_block_logdet(dd_ctx *ctx, const dd_blocks *B, const dd_g
     }
     ctx->timing = timing;
     HIPCHECK(ctx, e);
+    if (cl) {
+        // det D_Lambda = det A_ee det A_oo det(1 - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe)
+        double *site = (double *)workspace(ctx, "ld_clsite", (size_t)B->soff[B->nb] * 2 * sizeof(double), &e);
+        if (!site) return fail(ctx, DD_ENOMEM, std::string("logdet workspace: ") + hipGetErrorString(e));
+        HIPCHECK(ctx, launch_clover_logdet_add(B, G->d_cla64, site, ld, st));
+    }
     if (logdet_dev)
         HIPCHECK(ctx, hipMemcpyAsync(logdet_dev, ld, (size_t)B->nb * 2 * sizeof(double), hipMemcpyDeviceToDevice, st));
     if (total_host) {

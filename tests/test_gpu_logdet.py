@@ -91,3 +91,82 @@ def test_logdet_rejects_mixed_sizes(ctx):
         ctx.block_logdet(blk, g, 0.12)
     g.close()
     blk.close()
+
+
+def _dense_clover_box(L, kappa, csw, U, A, b):
+    """Dense D_Lambda of the box b with the clover term: the Wilson box matrix plus A(x) - 1 on the
+    site-diagonal blocks (A of the whole lattice at the box sites), checked against the oracle's
+    clover operator on one vector."""
+    from oracle import clover
+
+    M = dense.dense_dirac_box(L, -1, kappa, U, b[:4], b[4:8]).copy()
+    sites = geometry.box_sites(L, b[:4], b[4:8])
+    for i, s in enumerate(sites):
+        M[12 * i:12 * i + 12, 12 * i:12 * i + 12] += A[s] - np.eye(12)
+    v = synth.gaussian_complex((sites.size, 4, 3), 977)
+    ref = clover.dirac_clover_box(L, -1, kappa, csw, U, b[:4], b[4:8], v, A=A).reshape(-1)
+    assert np.linalg.norm(M @ v.reshape(-1) - ref) <= 1e-13 * np.linalg.norm(ref)
+    return M
+
+
+def test_logdet_clover_tiles_vs_dense_lu(ctx):
+    """With the clover term: det D_Lambda = det A_ee det A_oo det(1 - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe)
+    on overlapping 2^4 tiles of 4^4 (wrapping blocks, time sign), against dense LU of the clover box."""
+    from oracle import clover
+
+    from paper_2211_06902_amd import dd
+
+    L, kappa, csw = (4, 4, 4, 4), 0.13, 1.6
+    U = synth.gauge_field(L, 0.5, 1111)
+    A = clover.clover_matrix(L, U, kappa, csw)
+    boxes = np.concatenate([geometry.tile_boxes(L, [[2, 2]] * 4),
+                            geometry.tile_boxes(L, [[2, 2]] * 4, shift=(1, 1, 1, 1))])
+    blk = ctx.make_blocks_boxes(L, -1, boxes)
+    g = ctx.load_gauge(blk, _dev(U), "f32").set_clover(_dev(U), kappa, csw)
+    ld, tot = ctx.block_logdet(blk, g, kappa)
+    ref = np.array([dense.logdet(_dense_clover_box(L, kappa, csw, U, A, b)) for b in boxes])
+    wil = np.array([dense.logdet(dense.dense_dirac_box(L, -1, kappa, U, b[:4], b[4:8])) for b in boxes])
+    for k in range(len(boxes)):
+        assert _close(ld[k], ref[k]), (k, ld[k], ref[k])
+    assert np.max(np.abs(ref.real - wil.real)) > 1e-2  # the term matters
+    assert abs(tot.real - ref.real.sum()) <= 1e-8
+    with pytest.raises(dd.DDError):  # another kappa than the clover term's
+        ctx.block_logdet(blk, g, kappa + 0.01)
+    g.close()
+    blk.close()
+
+
+def test_logdet_clover_framed_blocks_and_frames(ctx):
+    """Paper-mode b = 2, d = 1 on 6^4 with the clover term: ln det D_{Omega_0^a} and ln det D_{Phi_1^a}
+    against dense LU (the frame: the principal sub-matrix of the clover box on the frame sites), and
+    the clover D_Lambda of a frame acting as the identity on its hole."""
+    from oracle import clover
+
+    L, kappa, csw = (6, 6, 6, 6), 0.13, 1.4
+    U = synth.gauge_field(L, 0.3, 973)
+    A = clover.clover_matrix(L, U, kappa, csw)
+    blk = ctx.make_blocks_paper(L, -1, [2, 1] * 4)
+    fr = ctx.make_frames(blk)
+    g = ctx.load_gauge(blk, _dev(U), "f32").set_clover(_dev(U), kappa, csw)
+    gf = ctx.load_gauge(fr, _dev(U), "f32").set_clover(_dev(U), kappa, csw)
+    ld_om, _ = ctx.block_logdet(blk, g, kappa)
+    ld_phi, _ = ctx.block_logdet(fr, gf, kappa)
+    bx = blk.tables()[0]
+    S = int(np.prod(bx[0, 4:8]))
+    x = synth.gaussian_complex((1, fr.total_sites, 4, 3), 974)
+    y = ctx.apply_D_block(fr, gf, kappa, "f64", _dev(x)).cpu().numpy()
+    for k in (0, 15):
+        b = bx[k]
+        Mb = _dense_clover_box(L, kappa, csw, U, A, b)
+        assert _close(ld_om[k], dense.logdet(Mb)), k
+        m = wilson.frame_mask(b[4:8], b[8:12], b[12:16])
+        fi = dense.dof(np.nonzero(m)[0])
+        assert _close(ld_phi[k], dense.logdet(Mb[np.ix_(fi, fi)])), k
+        xb, yb = x[0, k * S:(k + 1) * S], y[0, k * S:(k + 1) * S]
+        assert np.array_equal(yb[~m], xb[~m])  # identity on the hole
+        ref = (Mb[np.ix_(fi, fi)] @ xb[m].reshape(-1)).reshape(-1, 4, 3)
+        assert np.linalg.norm(yb[m] - ref) <= 1e-12 * np.linalg.norm(ref)
+    g.close()
+    gf.close()
+    fr.close()
+    blk.close()
