@@ -10,6 +10,7 @@ dense W_z in test_oracle_global.py).
   solution is unique, so this pins chi to within cond(W) 1e-9); zero off dPi.
 * Reweighting estimate: per noise vector, the terms -sum_m eta^+ R^m eta / m equal the oracle's (same
   noise, Chebyshev recurrence of R_{N+1}) within 1e-8 of the largest.
+* Generation and the estimate give the same values when the fields or vectors are split into groups.
 * The same three with the Sheikholeslami-Wohlert term on both gauges (against the oracle's clover W_z).
 * Refusals: a domain made from other blocks, out aliasing chi, a clover term on one gauge only, odd N.
 """
@@ -107,6 +108,17 @@ def test_generate_solves_the_oracle_equation(ctx, case):
         assert np.all(chi[k][~dpi] == 0)
         e = np.where(dpi[:, None, None], eta[k], 0)
         assert np.linalg.norm(W[k] - e) <= 1e-9 * np.linalg.norm(e), k
+    # two fields per group (groups of 2 and 1): the same fields within the solver's tolerance
+    try:
+        ctx.tune_set(dd.TUNE_MB_FIELDS, 2)
+        chi2, its2, rel2, info2, st2 = ctx.mb_generate(blk, g, D, gd, KAPPA, u, _dev(eta), tol=1e-10,
+                                                       params=dd.solve_params(tol=1e-12))
+    finally:
+        ctx.tune_set(dd.TUNE_MB_FIELDS, 0)
+    assert st2 == dd.DD_OK and info2["rhs_per_solve"] == 2 and np.all(rel2 <= 1e-9)
+    chi2 = chi2.cpu().numpy()
+    for k in range(3):
+        assert np.linalg.norm(chi2[k] - chi[k]) <= 1e-8 * np.linalg.norm(chi[k]), k
     _close(gd, g, D, blk)
 
 
@@ -123,6 +135,15 @@ def test_log_reweight_matches_oracle(ctx, case, N, c, order, nv):
     ref = mb.log_reweight_estimate(L, -1, KAPPA, U, boxes, inner, N, c, eta, order)
     assert np.abs(terms - ref).max() <= 1e-8 * np.abs(ref).max(), (terms, ref)
     assert abs(est - terms.mean()) <= 1e-14 * abs(terms).max()
+    if nv > 1:  # one noise vector per group
+        try:
+            ctx.tune_set(dd.TUNE_MB_FIELDS, 1)
+            t1, _, info1, st1 = ctx.mb_log_reweight(blk, g, D, gd, KAPPA, N, c, order, _dev(eta),
+                                                    params=dd.solve_params(tol=1e-12))
+        finally:
+            ctx.tune_set(dd.TUNE_MB_FIELDS, 0)
+        assert st1 == dd.DD_OK and info1["rhs_per_solve"] == 1
+        assert np.abs(t1 - terms).max() <= 1e-9 * np.abs(terms).max()
     _close(gd, g, D, blk)
 
 

@@ -429,3 +429,48 @@ def test_warm_start(ctx, inner):
         ctx.block_solve(blk, g, kappa, b, x=b, params=warm)
     g.close()
     blk.close()
+
+
+def test_warm_start_gmres_and_clover(ctx):
+    """The warm start with persistent GMRES (BF16 links) and with the clover term: from a perturbed
+    converged solution, fewer iterations than from zero and the tolerance met on the oracle's
+    operator (Wilson for GMRES, the clover operator for the clover gauge)."""
+    from oracle import clover
+
+    from paper_2211_06902_amd import dd
+
+    L = (16, 16, 16, 16)
+    kappa, csw = 0.13, 1.4
+    U = synth.gauge_field(L, 0.2, 7311)
+    blk = ctx.make_blocks(L, -1, [[8, 8]] * 4)
+    boxes = blk.tables()[0]
+    off = _cfg.site_offsets(boxes[:, :8])
+    b_np = synth.gaussian_complex((2, blk.total_sites, 4, 3), 7312)
+    b = _dev(b_np)
+    noise = _dev(synth.gaussian_complex((2, blk.total_sites, 4, 3), 7313))
+    A = clover.clover_matrix(L, U, kappa, csw)
+    for name, low, prm in (("gmres", "bf16", dd.solve_params(method=dd.GMRES, inner_prec="bf16")),
+                           ("clover", "f32", dd.solve_params(inner_prec="f32"))):
+        g = ctx.load_gauge(blk, _dev(U), low)
+        if name == "clover":
+            g.set_clover(_dev(U), kappa, csw)
+        x0, info0, st = ctx.block_solve(blk, g, kappa, b, params=prm)
+        assert st == dd.DD_OK, name
+        xp = x0 + 1e-6 * noise * (x0.abs().max() / noise.abs().max())
+        warm = dd.solve_params(**{k: getattr(prm, k) for k in ("method", "inner_prec")}, x0=1)
+        xw, infow, st = ctx.block_solve(blk, g, kappa, b, x=xp, params=warm)
+        assert st == dd.DD_OK and np.all(infow["true_relres"] <= TOL), name
+        assert infow["iters"].sum() < info0["iters"].sum(), name
+        xw = xw.cpu().numpy()
+        for k in (0, len(boxes) - 1):
+            bx = boxes[k]
+            sl = slice(off[k], off[k + 1])
+            for r in range(2):
+                if name == "clover":
+                    Dx = clover.dirac_clover_box(L, -1, kappa, csw, U, bx[:4], bx[4:8], xw[r, sl], A=A)
+                else:
+                    Dx = wilson.dirac_box(L, -1, kappa, U, bx[:4], bx[4:8], xw[r, sl])
+                rel = np.linalg.norm(b_np[r, sl] - Dx) / np.linalg.norm(b_np[r, sl])
+                assert rel <= TOL, (name, k, r, rel)
+        g.close()
+    blk.close()
