@@ -259,7 +259,7 @@ hipError_t run_dhat(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const Ho
     // rhs per workgroup: three (walked in lockstep, sharing the block's link
     // loads) when n_rhs is a multiple of three and that still gives a few
     // workgroups per compute unit, else one
-    const int nrw = dhat_rhs_per_wg(ctx, B, ba.n_rhs);
+    const int nrw = ha.clover ? 1 : dhat_rhs_per_wg(ctx, B, ba.n_rhs);
     WalkArgs wa;
     wa.ext = B->d_ext;
     wa.nseg = nrw;  // the Dhat walk is never segmented: nseg holds the rhs per workgroup

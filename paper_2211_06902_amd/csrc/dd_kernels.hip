@@ -554,9 +554,14 @@ hipError_t launch_hop_walk(const BlkArgs &ba, const WalkArgs &wa, const HopArgs 
 // three groups of kTile threads per compute unit as NR = 1 (144 KB of LDS).
 // Dot partials go to the chunk slots of the site kernels' tile table (rhs
 // group ba.g): slot 0 of the block holds the sum, its other slots are zero.
-template <typename SP, typename LK, typename AC, int DM, int PRE, int NR>
+// CL: the clover term's asymmetric form 1 - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe,
+// A_oo^-1 (ha.clover) applied to each intermediate site before it goes to
+// LDS and A_ee^-1 to each output site before the epilogue (one rhs per
+// workgroup).
+template <typename SP, typename LK, typename AC, int DM, int PRE, int NR, bool CL = false>
 __global__ void __launch_bounds__(kTile * NR) k_dhat_walk(BlkArgs ba, WalkArgs wa, HopArgs ha)
 {
+    static_assert(!CL || NR == 1, "the clover Dhat walk takes one rhs per workgroup");
     __shared__ SP sa[NR][24 * kTile];  // input slice q
     __shared__ SP sb[NR][24 * kTile];  // intermediate slice q-1
     __shared__ double red[NR][kTile];
@@ -621,8 +626,23 @@ __global__ void __launch_bounds__(kTile * NR) k_dhat_walk(BlkArgs ba, WalkArgs w
     double dv[1][kNRed];
 #pragma unroll
     for (int i = 0; i < kNRed; i++) dv[0][i] = 0;
+    const Buf clb = make_buf(CL ? reinterpret_cast<const SP *>(ha.clover) + soff * kCloverReals : nullptr,
+                             CL ? (uint32_t)(kCloverReals * 2 * hb) * (uint32_t)sizeof(SP) : 0u);
+    const uint32_t clk = (uint32_t)(2 * hb) * (uint32_t)sizeof(SP);
     auto to_out = [&](const AC (&acc)[1][24], int h) {
-        hop_epilogue<SP, AC, DM>(acc[0], dv[0], ha, eb, (uint32_t)(hc.grp_off + h) * (uint32_t)sizeof(SP), hc.cstr);
+        if constexpr (CL) {
+            AC a[24];
+#pragma unroll
+            for (int c = 0; c < 24; c++) a[c] = acc[0][c];
+            clover_mul<SP, AC>(a, clb, (uint32_t)h * (uint32_t)sizeof(SP), clk);  // A_ee^-1, even slot h
+            hop_epilogue<SP, AC, DM>(a, dv[0], ha, eb, (uint32_t)(hc.grp_off + h) * (uint32_t)sizeof(SP), hc.cstr);
+        } else {
+            hop_epilogue<SP, AC, DM>(acc[0], dv[0], ha, eb, (uint32_t)(hc.grp_off + h) * (uint32_t)sizeof(SP),
+                                     hc.cstr);
+        }
+    };
+    auto to_sb = [&](AC (&a)[24], int h) {
+        if constexpr (CL) clover_mul<SP, AC>(a, clb, (uint32_t)(hb + h) * (uint32_t)sizeof(SP), clk);  // A_oo^-1
     };
     auto ld = [&](int q, SP (&v)[24][1]) {
         const uint32_t vo = (uint32_t)(hc.grp_off + q * hs + k) * (uint32_t)sizeof(SP);
@@ -633,7 +653,7 @@ __global__ void __launch_bounds__(kTile * NR) k_dhat_walk(BlkArgs ba, WalkArgs w
             pl(v, vo, true);
         }
     };
-    dhat_run<SP, LK, AC>(wodd, weven, ns, sa[gi], sb[gi], hc, ld, to_out, alive);
+    dhat_run<SP, LK, AC>(wodd, weven, ns, sa[gi], sb[gi], hc, ld, to_out, alive, to_sb);
     if (DM != kDotNone) {
         // per-group fixed-order sums over the group's kTile threads
         constexpr int nred = dot_nred(DM);
@@ -657,11 +677,11 @@ __global__ void __launch_bounds__(kTile * NR) k_dhat_walk(BlkArgs ba, WalkArgs w
     }
 }
 
-template <typename SP, typename LK, typename AC, int NR>
+template <typename SP, typename LK, typename AC, int NR, bool CL = false>
 static hipError_t launch_dhat_t(const BlkArgs &ba, const WalkArgs &wa, const HopArgs &ha, hipStream_t s)
 {
     dim3 g(wa.ntiles), t(kTile * NR);
-#define DD_DHAT(DMV, PREV) hipLaunchKernelGGL((k_dhat_walk<SP, LK, AC, DMV, PREV, NR>), g, t, 0, s, ba, wa, ha)
+#define DD_DHAT(DMV, PREV) hipLaunchKernelGGL((k_dhat_walk<SP, LK, AC, DMV, PREV, NR, CL>), g, t, 0, s, ba, wa, ha)
     if (ha.pre == kPreP && ha.dot_mode == kDotAuxOut) DD_DHAT(kDotAuxOut, kPreP);
     else if (ha.pre == kPreS && ha.dot_mode == kDotOutSelfOutOut) DD_DHAT(kDotOutSelfOutOut, kPreS);
     else if (ha.pre == kPreNone && ha.dot_mode == kDotAuxOut) DD_DHAT(kDotAuxOut, kPreNone);
@@ -675,7 +695,7 @@ static hipError_t launch_dhat_t(const BlkArgs &ba, const WalkArgs &wa, const Hop
 
 hipError_t launch_dhat_walk(const BlkArgs &ba, const WalkArgs &wa, const HopArgs &ha, dd_prec prec, hipStream_t s)
 {
-    if (ha.clover) return hipErrorInvalidValue;  // Wilson only: the clover solve takes two hop launches
+    if (ha.clover && wa.nseg != 1) return hipErrorInvalidValue;  // clover: one rhs per workgroup
     if (wa.ntiles <= 0) return hipSuccess;
     // one walk of a whole block per rhs (wa.nseg rhs per workgroup: 1 or 3);
     // the output is the even parity
@@ -685,6 +705,11 @@ hipError_t launch_dhat_walk(const BlkArgs &ba, const WalkArgs &wa, const HopArgs
         return hipErrorInvalidValue;
     if (ha.pre != kPreNone && (!ha.pre_r || !ha.pre_v || !ha.pre_c0 || !ha.pre_act || (ha.pre == kPreP && !ha.pre_c1)))
         return hipErrorInvalidValue;
+    if (ha.clover) {
+        if (prec == DD_F32) return launch_dhat_t<float, float, float, 1, true>(ba, wa, ha, s);
+        if (prec == DD_BF16) return launch_dhat_t<float, uint16_t, float, 1, true>(ba, wa, ha, s);
+        return hipErrorInvalidValue;
+    }
     if (prec == DD_F32) return nrw == 3 ? launch_dhat_t<float, float, float, 3>(ba, wa, ha, s)
                                          : launch_dhat_t<float, float, float, 1>(ba, wa, ha, s);
     if (prec == DD_BF16) return nrw == 3 ? launch_dhat_t<float, uint16_t, float, 3>(ba, wa, ha, s)

@@ -438,7 +438,7 @@ dd_status block_solve_impl(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, 
     Inner in{ctx, B, ba, &w, links, ip, sp, kappa, inner_tol, gmres ? nullptr : nn, bc_ph, bc_sh, n_rhs,
              false, false, false, cl_a64 ? cl_inv : nullptr};
     if (!gmres) {
-        in.dhat = !cl_a64 && dhat_walk_applies(ctx, B, ba, ip);
+        in.dhat = dhat_walk_applies(ctx, B, ba, ip);
         if (!nn && ctx->bicg_fuse == 0) {
             const int nseg = in.dhat ? 1 : hop_walk_segments(ctx, B, ba, ip);
             in.fuse_s = nseg >= 1;

@@ -533,9 +533,11 @@ __device__ __forceinline__ void walk_run(const WalkPos &w, int ns, SP *stage, co
 // the first walk's reads of sa before the next staging by the second.
 // With alive false the thread only takes part in the barriers (a workgroup
 // walking several rhs, one of which has nothing to do).
-template <typename SP, typename LK, typename AC, typename LD, typename EPI>
+// xf(a, h) transforms each finished intermediate site h (odd parity) before it
+// is stored (the clover term's A_oo^-1); the overload without it stores as is.
+template <typename SP, typename LK, typename AC, typename LD, typename EPI, typename XF>
 __device__ __forceinline__ void dhat_run(const WalkPos &wodd, const WalkPos &weven, int ns, SP *sa, SP *sb,
-                                         const HopCtx &hc, LD &&ld, EPI &&epi, bool alive = true)
+                                         const HopCtx &hc, LD &&ld, EPI &&epi, bool alive, XF &&xf)
 {
     const int k = wodd.k, hs = wodd.hs;
     const bool live = alive && k < hs;
@@ -544,9 +546,13 @@ __device__ __forceinline__ void dhat_run(const WalkPos &wodd, const WalkPos &wev
     for (int c = 0; c < 24; c++) acc1[0][c] = acc2[0][c] = 0;
 #pragma unroll
     for (int c = 0; c < 12; c++) car1[0][c] = car2[0][c] = 0;
-    auto to_sb = [&](const AC (&acc)[1][24], int) {
+    auto to_sb = [&](const AC (&acc)[1][24], int h) {
+        AC a[24];
 #pragma unroll
-        for (int c = 0; c < 24; c++) sb[c * kTile + k] = (SP)acc[0][c];
+        for (int c = 0; c < 24; c++) a[c] = acc[0][c];
+        xf(a, h);
+#pragma unroll
+        for (int c = 0; c < 24; c++) sb[c * kTile + k] = (SP)a[c];
     };
     for (int q = 0; q <= ns; q++) {
         if (live && q < ns) {
@@ -565,6 +571,13 @@ __device__ __forceinline__ void dhat_run(const WalkPos &wodd, const WalkPos &wev
         if (live && q >= 1) walk_step<SP, LK, AC, 1>(acc2, car2, q - 1, weven, sb, hc, epi);
     }
     if (live) epi(acc2, (ns - 1) * hs + k);
+}
+
+template <typename SP, typename LK, typename AC, typename LD, typename EPI>
+__device__ __forceinline__ void dhat_run(const WalkPos &wodd, const WalkPos &weven, int ns, SP *sa, SP *sb,
+                                         const HopCtx &hc, LD &&ld, EPI &&epi, bool alive = true)
+{
+    dhat_run<SP, LK, AC>(wodd, weven, ns, sa, sb, hc, ld, epi, alive, [](AC (&)[24], int) {});
 }
 
 // ------------------------------------------------------------ clover term

@@ -5,7 +5,8 @@
   tiles of an 8^4 lattice and on the same tiling shifted by one site (blocks that wrap, including the
   antiperiodic time edge): A(x) of the whole lattice at every block site.
 * Block solves (FP64 and FP32 inner even-odd BiCGStab on 1 - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe inside
-  FP64 defect correction), with the x0-walk hops and with the chunked hop kernel: every pair's true
+  FP64 defect correction), with the one-kernel Dhat walk (FP32 inner: A_oo^-1 on the intermediate in
+  LDS, A_ee^-1 in the epilogue), two x0-walk hops, and the chunked hop kernel: every pair's true
   residual with the oracle's clover operator <= 1e-10, and two blocks' solutions against dense LU.
 * c_sw = 0 gives back the Wilson operator bit for bit; a kappa other than the clover term's and GMRES
   are refused (the log-determinants with the term are compared in test_gpu_logdet.py).
@@ -99,9 +100,9 @@ def _relres(U, A, b, x, box):
     return np.linalg.norm(r) / np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("walk", [True, False], ids=["walk", "chunked"])
+@pytest.mark.parametrize("mode", ["dhat", "twohop", "chunked"])
 @pytest.mark.parametrize("inner", ["f64", "f32"])
-def test_clover_solves_match_oracle(ctx, field, inner, walk):
+def test_clover_solves_match_oracle(ctx, field, inner, mode):
     from paper_2211_06902_amd import dd
 
     U, A = field
@@ -112,11 +113,14 @@ def test_clover_solves_match_oracle(ctx, field, inner, walk):
     n_rhs = 3
     b = synth.gaussian_complex((n_rhs, blk.total_sites, 4, 3), 4404)
     try:
-        # walk off: every hop, the clover ones included, runs in the chunked kernel
-        ctx.tune_set(dd.TUNE_HOP_WALK, 0 if walk else -1)
+        # dhat: the one-kernel Dhat walk (FP32 inner); twohop: two walk hops per Dhat; chunked: the
+        # walk off, every hop (the clover ones included) in the chunked kernel
+        ctx.tune_set(dd.TUNE_DHAT_WALK, -1 if mode == "twohop" else 0)
+        ctx.tune_set(dd.TUNE_HOP_WALK, -1 if mode == "chunked" else 0)
         x, info, st = ctx.block_solve(blk, g, KAPPA, _dev(b), params=dd.solve_params(inner_prec=inner))
     finally:
         ctx.tune_set(dd.TUNE_HOP_WALK, 0)
+        ctx.tune_set(dd.TUNE_DHAT_WALK, 0)
     assert st == dd.DD_OK and np.all(info["true_relres"] <= 1e-10)
     x = x.cpu().numpy()
     for k, bx in enumerate(boxes):
