@@ -189,18 +189,41 @@ def test_global_pieces_with_clover_match_oracle(ctx, case):
         assert np.linalg.norm(got[k] - ref[k]) <= 1e-10 * np.linalg.norm(ref[k]), k
         assert np.abs(got[k] - ref[k]).max() <= 1e-9 * np.abs(ref[k]).max(), k
     if case == "paper_3d":
-        u = roots.mb_roots(4, 0.5)[:2]
-        eta = synth.gaussian_complex((2, V, 4, 3), 6653) / np.sqrt(2)
+        u = roots.mb_roots(4, 0.5)[:1]  # one field: the oracle's clover solves are slow
+        eta = synth.gaussian_complex((1, V, 4, 3), 6653) / np.sqrt(2)
         x, its, rel, info, st = ctx.mb_generate(blk, g, D, gd, kappa, u, _dev(eta), tol=1e-10, params=prm)
         assert st == dd.DD_OK and np.all(rel <= 1e-9)
         x = x.cpu().numpy()
         W = mb.apply_w(L, -1, kappa, U, boxes, inner, u, x, csw=csw)
         dpi = geometry.BoxDomains(L, boxes, inner).dPi
-        for k in range(2):
-            e = np.where(dpi[:, None, None], eta[k], 0)
-            assert np.linalg.norm(W[k] - e) <= 1e-9 * np.linalg.norm(e), k
+        e = np.where(dpi[:, None, None], eta[0], 0)
+        assert np.linalg.norm(W[0] - e) <= 1e-9 * np.linalg.norm(e)
         terms, est, info, st = ctx.mb_log_reweight(blk, g, D, gd, kappa, 2, 0.9, 1, _dev(eta[:1]), params=prm)
         assert st == dd.DD_OK
         ref_t = mb.log_reweight_estimate(L, -1, kappa, U, boxes, inner, 2, 0.9, eta[:1], 1, csw=csw)
         assert np.abs(terms - ref_t).max() <= 1e-8 * np.abs(ref_t).max()
+    _close(gd, g, D, blk)
+
+
+def test_apply_w_at_the_c5_tile_shape(ctx):
+    """W_z chi with the blocks of the 64^4 workload (8^4 tiles, 6^4 active boxes, kappa 0.1365) on a
+    16^4 lattice (16 tiles, the inactive region a connected lattice of 44 800 dPi sites): element by
+    element against the oracle."""
+    from paper_2211_06902_amd import dd
+
+    L, kappa = (16, 16, 16, 16), 0.1365
+    blk = ctx.make_blocks(L, -1, [[8, 8]] * 4, inner_d=1)
+    U = synth.gauge_field(L, 0.2, 6661)
+    D = ctx.make_inactive(blk)
+    g = ctx.load_gauge(blk, _dev(U), "f32")
+    gd = ctx.load_gauge(D, _dev(U), "f32")
+    bx = blk.tables()[0]
+    z = [0.5 + 0.2j]
+    chi = synth.gaussian_complex((1, 16**4, 4, 3), 6662)
+    out, info, st = ctx.mb_apply_W(blk, g, D, gd, kappa, z, _dev(chi), params=dd.solve_params(tol=1e-12))
+    assert st == dd.DD_OK
+    got = out.cpu().numpy()
+    ref = mb.apply_w(L, -1, kappa, U, bx[:, :8], bx[:, 8:16], z, chi)
+    assert np.linalg.norm(got[0] - ref[0]) <= 1e-10 * np.linalg.norm(ref[0])
+    assert np.abs(got[0] - ref[0]).max() <= 1e-9 * np.abs(ref[0]).max()
     _close(gd, g, D, blk)
