@@ -297,7 +297,11 @@ def _mb_inputs(ctx, dd):
     V = 64**4
     blk = ctx.make_blocks(w["L"], -1, [[8] * 8] * 4, inner_d=1)
     U = synth.gauge_field_device(w["L"], w["eps"], w["seed_u"])
-    g = ctx.load_gauge(blk, U, "f32")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    g = ctx.load_gauge(blk, U, "f32")  # packing: FP64 and FP32 link records of every block
+    torch.cuda.synchronize()
+    _mb_inputs.pack_s = time.perf_counter() - t
     U_host = U.cpu().numpy()
     del U
     torch.cuda.empty_cache()  # the library sizes its field groups by the free device memory
@@ -462,6 +466,7 @@ def run_c5(args):
             "graph_replay": not args.no_graph,
             "fields_per_solve": int(res[-1][1]["rhs_per_solve"]),
             "input_generation_s": t_gen,
+            "gauge_pack_s": getattr(_mb_inputs, "pack_s", None),
             "other_forms": forms,
         },
         "roofline": {
