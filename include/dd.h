@@ -594,8 +594,9 @@ typedef struct {
  * params->inner_prec (plain BiCGStab; DD_EINVAL otherwise): after one
  * warm-up solve, times one full dd_block_solve of b under each candidate (rhs
  * per thread 1, or 2 when it divides n_rhs; with an FP32 or BF16 inner solve
- * the one-kernel Dhat with 1 or 3 rhs per workgroup, or two walk hops with
- * and without the fused staging updates; FP64: the two walk hops) and keeps
+ * the one-kernel Dhat with 1 or 3 rhs per workgroup (1 also with separate
+ * update kernels), or two walk hops with and without the fused staging
+ * updates; FP64: the two walk hops) and keeps
  * the fastest in the context, as dd_tune_set would.  x_dev (the size of b) is
  * scratch.  cache_path (may be NULL): a JSON file (an object, one entry per
  * line) keyed by device, lattice, block shapes, n_rhs and inner precision;

@@ -959,8 +959,9 @@ dd_status dd_autotune_bicgstab(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *
             }
     // candidates: rhs per thread of the site kernels (1, or 2 when it divides
     // n_rhs); with a low-precision inner solve the one-kernel Dhat (one or
-    // three rhs per workgroup) or two walk hops (with or without the fused
-    // staging updates); FP64: the two walk hops only
+    // three rhs per workgroup; one also with separate update kernels) or two
+    // walk hops (with or without the fused staging updates); FP64: the two
+    // walk hops only
     std::vector<dd_bicg_tune_result> cand;
     std::vector<int> groups = {1};
     if (n_rhs % 2 == 0) groups.push_back(2);
@@ -968,6 +969,7 @@ dd_status dd_autotune_bicgstab(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *
         if (!f64) {
             cand.push_back({g, 0, 1, 0, 0.0});
             cand.push_back({g, 0, 3, 0, 0.0});
+            cand.push_back({g, 0, 1, -1, 0.0});
         }
         cand.push_back({g, -1, 0, 0, 0.0});
         cand.push_back({g, -1, 0, -1, 0.0});

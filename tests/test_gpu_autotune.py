@@ -29,7 +29,7 @@ def _dev(a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-@pytest.mark.parametrize("inner,ncand", [("f32", 8), ("f64", 4)])
+@pytest.mark.parametrize("inner,ncand", [("f32", 10), ("f64", 4)])
 def test_bicgstab_autotuner_and_cache(ctx, tmp_path, inner, ncand):
     from paper_2211_06902_amd import dd
 
