@@ -329,3 +329,22 @@ def test_block_size_limit_of_32bit_offsets():
     assert D.total_sites == 48**4 and D.total_sites * 48 * 8 < 2**32
     D.close()
     blk.close()
+
+
+def test_null_arguments_are_refused_without_a_device():
+    """Every entry point of the global pieces, the BiCGStab autotuner and the inactive-region builder
+    checks its handles before it touches a device: all-null calls return DD_EINVAL (no GPU here)."""
+    import ctypes
+
+    from paper_2211_06902_amd import dd
+
+    L = dd._lib
+    N = None
+    assert L.dd_mb_global_action(N, N, N, 0.1, 1, N, N, N, N, N, N) == dd.DD_EINVAL
+    assert L.dd_mb_apply_W(N, N, N, N, N, 0.1, 1, N, N, N, N, N) == dd.DD_EINVAL
+    assert L.dd_mb_generate(N, N, N, N, N, 0.1, 1, N, N, N, 1e-10, 10, N, N, N, N) == dd.DD_EINVAL
+    assert L.dd_mb_log_reweight(N, N, N, N, N, 0.1, 2, 0.5, 1, 1, N, N, N, N, N) == dd.DD_EINVAL
+    assert L.dd_autotune_bicgstab(N, N, N, 0.1, N, N, 1, N, N, N, 0, N, N) == dd.DD_EINVAL
+    out = ctypes.c_void_p()
+    assert L.dd_make_inactive(N, N, ctypes.byref(out)) == dd.DD_EINVAL
+    assert L.dd_make_inactive(N, N, N) == dd.DD_EINVAL
