@@ -221,8 +221,8 @@ dd_status dd_gauge_export(dd_ctx *ctx, const dd_gauge *gauge, dd_prec prec, void
  * dd_apply_D_block, dd_apply_D_block_noalloc, dd_block_solve and
  * dd_multiboson_action use this operator and reject another kappa
  * (DD_EINVAL); solves run even-odd BiCGStab on
- * 1 - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe (DD_EUNSUPPORTED for GMRES or a network
- * preconditioner; the hops of blocks the x0-walk cannot take, such as an
+ * 1 - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe, optionally right-preconditioned by a
+ * network (DD_EUNSUPPORTED for GMRES; the hops of blocks the x0-walk cannot take, such as an
  * inactive region, run in the chunked hop kernel); dd_block_logdet takes
  * det A_ee det A_oo det(that operator).  c_sw = 0 removes the term (the
  * Wilson operator).

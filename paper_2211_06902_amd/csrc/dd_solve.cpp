@@ -311,7 +311,7 @@ dd_status block_solve_impl(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, 
     }
     const void *cl_a64 = clover_for(G, DD_F64, false), *cl_inv = clover_for(G, ip, true);
     if (cl_a64) {
-        if (gmres || nn) return fail(ctx, DD_EUNSUPPORTED, "the clover term is solved by BiCGStab without a network");
+        if (gmres) return fail(ctx, DD_EUNSUPPORTED, "the clover term is solved by BiCGStab (GMRES takes the Wilson operator)");
         if (!cl_inv) return fail(ctx, DD_EINVAL, "gauge holds no clover term of the inner precision");
     }
     const double inner_tol = prm.inner_tol > 0 ? prm.inner_tol : default_inner_tol(ip, prm.tol);

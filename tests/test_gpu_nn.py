@@ -334,3 +334,43 @@ def test_network_preconditioned_bicgstab_with_dhat_walk(ctx, toy):
         ctx.tune_set(dd.TUNE_DHAT_WALK, 0)
     assert np.max(np.abs(out[0][1] - out[1][1])) <= 2
     assert _cfg.rel_err(out[0][0], out[1][0]) <= 1e-9
+
+
+def test_network_preconditioned_bicgstab_with_clover(ctx, toy):
+    """BiCGStab right-preconditioned by the network on the clover operator (the network trained on
+    Wilson pairs is a perturbation away from the clover inverse, which right preconditioning allows):
+    every pair to tolerance with the one-kernel Dhat and with two hop launches, the same solution, and
+    the true residual of two blocks on the oracle's clover operator."""
+    from oracle import clover, geometry
+    from tests import _cfg
+
+    from paper_2211_06902_amd import dd
+
+    L, kappa, csw = toy["L"], toy["kappa"], 1.4
+    g = ctx.load_gauge(toy["blk"], _dev(toy["U"]), "f32").set_clover(_dev(toy["U"]), kappa, csw)
+    boxes = geometry.tile_boxes(L, [[4, 4]] * 4)
+    b = synth.spinor_field(L, 3, 65)[:, _cfg.block_sites(L, boxes)]
+    bd = _dev(b)
+    prm = dd.solve_params(inner_prec="f32", precond=toy["net"])
+    out = []
+    try:
+        ctx.tune_set(dd.TUNE_HOP_WALK, 1)
+        for k in (0, -1):
+            ctx.tune_set(dd.TUNE_DHAT_WALK, k)
+            x, info, st = ctx.block_solve(toy["blk"], g, kappa, bd, params=prm)
+            assert st == dd.DD_OK and np.all(info["true_relres"] <= 1e-10), k
+            out.append(x.cpu().numpy())
+    finally:
+        ctx.tune_set(dd.TUNE_HOP_WALK, 0)
+        ctx.tune_set(dd.TUNE_DHAT_WALK, 0)
+    assert _cfg.rel_err(out[0], out[1]) <= 1e-9
+    A = clover.clover_matrix(L, toy["U"], kappa, csw)
+    off = _cfg.site_offsets(boxes)
+    for k in (0, len(boxes) - 1):
+        sl = slice(off[k], off[k + 1])
+        for r in range(3):
+            Dx = clover.dirac_clover_box(L, -1, kappa, csw, toy["U"], boxes[k][:4], boxes[k][4:8], out[0][r, sl], A=A)
+            assert np.linalg.norm(b[r, sl] - Dx) <= 1e-10 * np.linalg.norm(b[r, sl]), (k, r)
+    with pytest.raises(dd.DDError):  # GMRES takes the Wilson operator only
+        ctx.block_solve(toy["blk"], g, kappa, bd, params=dd.solve_params(method=dd.GMRES, inner_prec="f32"))
+    g.close()
