@@ -723,8 +723,8 @@ def main():
         print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4, "copies": 4}))
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the block solves need no communication and this build has no "
-              "multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU only: the block solves need no communication and the library has "
+              "no multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     {"c4": run_c4, "c5": run_c5, "dlam": run_dlam, "nnapply": run_nnapply}.get(args.workload, run_solve)(args)
 

@@ -63,7 +63,7 @@ typedef enum {
     DD_ENOMEM = 2,        /* device or host allocation failed */
     DD_EDEVICE = 3,       /* a HIP call failed */
     DD_ENOCONV = 4,       /* some (block, rhs) pair missed the tolerance; stats are filled */
-    DD_EUNSUPPORTED = 5   /* valid request this build does not implement */
+    DD_EUNSUPPORTED = 5   /* valid request the library does not implement */
 } dd_status;
 
 typedef enum { DD_F64 = 0, DD_F32 = 1, DD_BF16 = 2 } dd_prec;
