@@ -61,6 +61,8 @@ struct PairGeo {
     const int32_t *nbr;  // the block shape's neighbour table [parity][h][8]
     Buf lk_b;            // the block's links
     uint32_t kstr;       // bytes between link entries
+    Buf cl_b;            // the block's A^-1 of the clover term (walk hops with CL)
+    uint32_t cl_kstr;    // bytes between its reals
 };
 
 // out = c_hop (H in) + c_self self + c_add add on the sites of parity p of
@@ -114,8 +116,9 @@ __device__ __forceinline__ double wg_hop(const PairGeo &g, int p, const SP *in, 
 
 // wg_hop by the x0-walk (dd_stencil.h): the input slices staged in LDS one
 // after the other, each read once.  For blocks whose x0-slices hold at most
-// kTile sites per parity; all threads call it.
-template <typename SP, typename LK, int NT>
+// kTile sites per parity; all threads call it.  CL: the hop result at each
+// output site is multiplied by its A^-1 (g.cl_b) before the combination.
+template <typename SP, typename LK, int NT, bool CL = false>
 __device__ __forceinline__ double wg_hop_walk(const PairGeo &g, int p, int ns, SP *stage, const SP *in, SP *out,
                                               const SP *self, double c_self, double c_hop, const SP *add, double c_add)
 {
@@ -144,7 +147,10 @@ __device__ __forceinline__ double wg_hop_walk(const PairGeo &g, int p, int ns, S
     const bool has_self = self != nullptr, has_add = add != nullptr;
     double nn = 0;
     walk_run<SP, LK, AC, 1>(w, ns, stage, hc, [&](const AC (&acc1)[1][24], int h) {
-        const AC(&acc)[24] = acc1[0];
+        AC acc[24];
+#pragma unroll
+        for (int c = 0; c < 24; c++) acc[c] = acc1[0][c];
+        if constexpr (CL) clover_mul<SP, AC>(acc, g.cl_b, (uint32_t)(p * g.h + h) * (uint32_t)sizeof(SP), g.cl_kstr);
         const uint32_t vo = (uint32_t)h * (uint32_t)sizeof(SP);
 #pragma unroll
         for (int half = 0; half < 2; half++) {
@@ -172,8 +178,10 @@ __device__ __forceinline__ double wg_hop_walk(const PairGeo &g, int p, int ns, S
 // one pair in one pass over the x0-slices (dhat_run in dd_stencil.h): the odd
 // intermediate stays in LDS (sa: input slice, sb: intermediate slice).  One
 // rhs per thread, FP32 spinors; self and add may be null.  Returns the
-// thread's share of |out|^2.  All threads call it.
-template <typename SP, typename LK, int NT>
+// thread's share of |out|^2.  All threads call it.  CL: the clover term's
+// A_oo^-1 on each intermediate site before it goes to LDS and A_ee^-1 on the
+// hop result at each output site (out = c_hop A_ee^-1 H_eo A_oo^-1 H_oe in + ..).
+template <typename SP, typename LK, int NT, bool CL = false>
 __device__ __forceinline__ double wg_dhat_walk(const PairGeo &g, int ns, SP *sa, SP *sb, const SP *in, SP *out,
                                                const SP *self, double c_self, double c_hop, const SP *add,
                                                double c_add)
@@ -198,7 +206,10 @@ __device__ __forceinline__ double wg_dhat_walk(const PairGeo &g, int ns, SP *sa,
     const bool has_self = self != nullptr, has_add = add != nullptr;
     double nn = 0;
     auto epi = [&](const AC (&acc1)[1][24], int h) {
-        const AC(&acc)[24] = acc1[0];
+        AC acc[24];
+#pragma unroll
+        for (int c = 0; c < 24; c++) acc[c] = acc1[0][c];
+        if constexpr (CL) clover_mul<SP, AC>(acc, g.cl_b, (uint32_t)h * (uint32_t)sizeof(SP), g.cl_kstr);  // A_ee^-1
         const uint32_t vo = (uint32_t)h * (uint32_t)sizeof(SP);
 #pragma unroll
         for (int half = 0; half < 2; half++) {
@@ -219,8 +230,11 @@ __device__ __forceinline__ double wg_dhat_walk(const PairGeo &g, int ns, SP *sa,
             }
         }
     };
-    dhat_run<SP, LK, AC>(wodd, weven, ns, sa, sb, hc,
-                         [&](int q, SP (&v)[24][1]) { walk_load<SP, 1>(v, hc, q, hs, k); }, epi);
+    dhat_run<SP, LK, AC>(
+        wodd, weven, ns, sa, sb, hc, [&](int q, SP (&v)[24][1]) { walk_load<SP, 1>(v, hc, q, hs, k); }, epi, true,
+        [&](AC (&a)[24], int h) {
+            if constexpr (CL) clover_mul<SP, AC>(a, g.cl_b, (uint32_t)(g.h + h) * (uint32_t)sizeof(SP), g.cl_kstr);
+        });
     return nn;
 }
 
@@ -335,9 +349,10 @@ enum { kGoOn = 0, kRestart = 1, kConverged = 2, kMaxIter = 3, kNonFinite = 4, kP
 // hops of Dhat are one pass over the slices (wg_dhat_walk), with FP64 two
 // (wg_hop_walk).  FP32 spinors: at most 168 registers, so that three
 // wavefronts share a SIMD.
-template <typename SP, typename LK, int M, int NT, bool WALK>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(SP) == 4 ? 3 : 1))) k_gmres(GmArgs a)
+template <typename SP, typename LK, int M, int NT, bool WALK, bool CL = false>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(SP) == 4 && !CL ? 3 : 1))) k_gmres(GmArgs a)
 {
+    static_assert(!CL || WALK, "the clover term takes the walking hops");
     constexpr bool FUSED = WALK && sizeof(SP) == 4;
     constexpr int NW = NT / 64;
     constexpr int NV = 2 * (M + 1) + 1;
@@ -401,6 +416,9 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
         g.kstr = (uint32_t)(4 * h) * (uint32_t)sizeof(LK);
         g.lk_b = make_buf(reinterpret_cast<const LK *>(a.links) + so * kLinkReals,
                           (uint32_t)(2 * h * kLinkReals) * (uint32_t)sizeof(LK));
+        g.cl_b = make_buf(CL ? reinterpret_cast<const SP *>(a.clover) + so * kCloverReals : nullptr,
+                          CL ? (uint32_t)(kCloverReals * 2 * h) * (uint32_t)sizeof(SP) : 0u);
+        g.cl_kstr = (uint32_t)(2 * h) * (uint32_t)sizeof(SP);
         const int64_t pb = (so >> 1) * 24 * a.n_rhs + (int64_t)r * 24 * h;
         const SP *f = reinterpret_cast<const SP *>(a.rhs) + pb;
         SP *x = reinterpret_cast<SP *>(a.x) + pb;
@@ -454,11 +472,11 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
                 const SP *src = zf ? z0 : vj;
                 const double cs1 = zf ? 1.0 / beta : 1.0, ch1 = zf ? -k2 / beta : -k2;
                 if constexpr (FUSED) {
-                    wg_dhat_walk<SP, LK, NT>(g, ns, stage, stage2, src, w, src, cs1, ch1, nullptr, 0.0);
+                    wg_dhat_walk<SP, LK, NT, CL>(g, ns, stage, stage2, src, w, src, cs1, ch1, nullptr, 0.0);
                 } else if constexpr (WALK) {
-                    wg_hop_walk<SP, LK, NT>(g, 1, ns, stage, src, tmp, nullptr, 0.0, 1.0, nullptr, 0.0);
+                    wg_hop_walk<SP, LK, NT, CL>(g, 1, ns, stage, src, tmp, nullptr, 0.0, 1.0, nullptr, 0.0);
                     __syncthreads();
-                    wg_hop_walk<SP, LK, NT>(g, 0, ns, stage, tmp, w, src, cs1, ch1, nullptr, 0.0);
+                    wg_hop_walk<SP, LK, NT, CL>(g, 0, ns, stage, tmp, w, src, cs1, ch1, nullptr, 0.0);
                 } else {
                     wg_hop<SP, LK, NT>(g, 1, src, tmp, nullptr, 0.0, 1.0, nullptr, 0.0);
                     __syncthreads();
@@ -599,11 +617,11 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(sizeof(
             // restart from the explicit residual V_0 = f - Dhat x
             double rn;
             if constexpr (FUSED) {
-                rn = wg_dhat_walk<SP, LK, NT>(g, ns, stage, stage2, x, V, x, -1.0, k2, f, 1.0);
+                rn = wg_dhat_walk<SP, LK, NT, CL>(g, ns, stage, stage2, x, V, x, -1.0, k2, f, 1.0);
             } else if constexpr (WALK) {
-                wg_hop_walk<SP, LK, NT>(g, 1, ns, stage, x, tmp, nullptr, 0.0, 1.0, nullptr, 0.0);
+                wg_hop_walk<SP, LK, NT, CL>(g, 1, ns, stage, x, tmp, nullptr, 0.0, 1.0, nullptr, 0.0);
                 __syncthreads();
-                rn = wg_hop_walk<SP, LK, NT>(g, 0, ns, stage, tmp, V, x, -1.0, k2, f, 1.0);
+                rn = wg_hop_walk<SP, LK, NT, CL>(g, 0, ns, stage, tmp, V, x, -1.0, k2, f, 1.0);
             } else {
                 wg_hop<SP, LK, NT>(g, 1, x, tmp, nullptr, 0.0, 1.0, nullptr, 0.0);
                 __syncthreads();
@@ -653,39 +671,41 @@ __global__ void k_fill_i32(int32_t *p, int n, int32_t v)
 
 namespace {
 
-template <typename SP, typename LK, bool WALK>
+template <typename SP, typename LK, bool WALK, bool CL>
 struct GmKernels {
     static const void *get(int M, int nt)
     {
-        if (M == 8 && nt == 256) return (const void *)k_gmres<SP, LK, 8, 256, WALK>;
-        if (M == 8 && nt == 512) return (const void *)k_gmres<SP, LK, 8, 512, WALK>;
-        if (M == 16 && nt == 256) return (const void *)k_gmres<SP, LK, 16, 256, WALK>;
-        if (M == 16 && nt == 512) return (const void *)k_gmres<SP, LK, 16, 512, WALK>;
+        if (M == 8 && nt == 256) return (const void *)k_gmres<SP, LK, 8, 256, WALK, CL>;
+        if (M == 8 && nt == 512) return (const void *)k_gmres<SP, LK, 8, 512, WALK, CL>;
+        if (M == 16 && nt == 256) return (const void *)k_gmres<SP, LK, 16, 256, WALK, CL>;
+        if (M == 16 && nt == 512) return (const void *)k_gmres<SP, LK, 16, 512, WALK, CL>;
         return nullptr;
     }
 };
 
-template <bool WALK>
+template <bool WALK, bool CL>
 const void *gmres_kernel_w(dd_prec prec, int M, int nt)
 {
-    if (prec == DD_F64) return GmKernels<double, double, WALK>::get(M, nt);
-    if (prec == DD_F32) return GmKernels<float, float, WALK>::get(M, nt);
-    if (prec == DD_BF16) return GmKernels<float, uint16_t, WALK>::get(M, nt);
+    if (prec == DD_F64) return GmKernels<double, double, WALK, CL>::get(M, nt);
+    if (prec == DD_F32) return GmKernels<float, float, WALK, CL>::get(M, nt);
+    if (prec == DD_BF16) return GmKernels<float, uint16_t, WALK, CL>::get(M, nt);
     return nullptr;
 }
 
-const void *gmres_kernel(dd_prec prec, int M, int nt, bool walk)
+// the clover term takes the walking hops only (null otherwise)
+const void *gmres_kernel(dd_prec prec, int M, int nt, bool walk, bool cl)
 {
-    return walk ? gmres_kernel_w<true>(prec, M, nt) : gmres_kernel_w<false>(prec, M, nt);
+    if (cl) return walk ? gmres_kernel_w<true, true>(prec, M, nt) : nullptr;
+    return walk ? gmres_kernel_w<true, false>(prec, M, nt) : gmres_kernel_w<false, false>(prec, M, nt);
 }
 
 }  // namespace
 
 int gmres_basis_m(int restart) { return restart <= 8 ? 8 : 16; }
 
-hipError_t gmres_occupancy(dd_prec prec, int restart, int nt, bool walk, int *wgs_per_cu)
+hipError_t gmres_occupancy(dd_prec prec, int restart, int nt, bool walk, bool cl, int *wgs_per_cu)
 {
-    const void *k = gmres_kernel(prec, gmres_basis_m(restart), nt, walk);
+    const void *k = gmres_kernel(prec, gmres_basis_m(restart), nt, walk, cl);
     if (!k) return hipErrorInvalidValue;
     return hipOccupancyMaxActiveBlocksPerMultiprocessor(wgs_per_cu, k, nt, 0);
 }
@@ -693,7 +713,7 @@ hipError_t gmres_occupancy(dd_prec prec, int restart, int nt, bool walk, int *wg
 hipError_t launch_gmres(const GmArgs &a, dd_prec prec, int nt, int grid, hipStream_t st)
 {
     if (a.m < 1 || a.m > 16 || grid < 1 || a.nq < 1) return hipErrorInvalidValue;
-    const void *k = gmres_kernel(prec, gmres_basis_m(a.m), nt, a.walk != 0);
+    const void *k = gmres_kernel(prec, gmres_basis_m(a.m), nt, a.walk != 0, a.clover != nullptr);
     if (!k) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_fill_i32, dim3((a.nq + 255) / 256), dim3(256), 0, st, a.qctr, a.nq, 0);
     const int np = a.nb * a.n_rhs;

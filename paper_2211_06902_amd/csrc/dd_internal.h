@@ -345,12 +345,13 @@ struct GmArgs {
     int adapt;
     double tol_out;
     const double *obb, *orr;
+    const void *clover;       // A^-1 of the clover term (SP, block layout) or null; walking hops only
 };
 
 // basis vectors the kernel for restart length m keeps per workgroup (its
 // compile-time bound plus one)
 int gmres_basis_m(int restart);
-hipError_t gmres_occupancy(dd_prec prec, int restart, int nt, bool walk, int *wgs_per_cu);
+hipError_t gmres_occupancy(dd_prec prec, int restart, int nt, bool walk, bool cl, int *wgs_per_cu);
 hipError_t launch_gmres(const GmArgs &a, dd_prec prec, int nt, int grid, hipStream_t st);
 hipError_t gmres_schedule(dd_ctx *ctx, dd_prec ip, int restart, int np, bool walk, int *nt, int *nq, int *grid);
 // whether the persistent GMRES kernel's hops take the x0-walk for these blocks

@@ -227,12 +227,13 @@ namespace dd {
 // (dd_tune_set, dd_autotune_gmres) or the defaults.
 bool gmres_walk(const dd_ctx *ctx, const dd_blocks *B) { return B->walk && ctx->hop_lds && ctx->hop_walk >= 0; }
 
-hipError_t gmres_schedule(dd_ctx *ctx, dd_prec ip, int restart, int np, bool walk, int *nt, int *nq, int *grid)
+hipError_t gmres_schedule(dd_ctx *ctx, dd_prec ip, int restart, int np, bool walk, bool cl, int *nt, int *nq,
+                          int *grid)
 {
     *nt = ctx->gm_threads > 0 ? ctx->gm_threads : 256;
     *nq = ctx->gm_queues > 0 ? ctx->gm_queues : 8;
     int occ = 0;
-    hipError_t e = gmres_occupancy(ip, restart, *nt, walk, &occ);
+    hipError_t e = gmres_occupancy(ip, restart, *nt, walk, cl, &occ);
     if (e != hipSuccess) return e;
     if (occ < 1) return hipErrorInvalidConfiguration;
     int ncu = 0;
@@ -311,7 +312,8 @@ dd_status block_solve_impl(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, 
     }
     const void *cl_a64 = clover_for(G, DD_F64, false), *cl_inv = clover_for(G, ip, true);
     if (cl_a64) {
-        if (gmres) return fail(ctx, DD_EUNSUPPORTED, "the clover term is solved by BiCGStab (GMRES takes the Wilson operator)");
+        if (gmres && !gmres_walk(ctx, Bc))
+            return fail(ctx, DD_EUNSUPPORTED, "the clover term in GMRES needs blocks the x0-walk hop takes");
         if (!cl_inv) return fail(ctx, DD_EINVAL, "gauge holds no clover term of the inner precision");
     }
     const double inner_tol = prm.inner_tol > 0 ? prm.inner_tol : default_inner_tol(ip, prm.tol);
@@ -370,7 +372,8 @@ dd_status block_solve_impl(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, 
     const QueueTable *qt = nullptr;
     const int64_t vstr = 24 * (int64_t)B->max_h;
     if (gmres) {
-        HIPCHECK(ctx, gmres_schedule(ctx, ip, prm.restart, np, gmres_walk(ctx, B), &gm_nt, &gm_nq, &gm_grid));
+        HIPCHECK(ctx, gmres_schedule(ctx, ip, prm.restart, np, gmres_walk(ctx, B), cl_a64 != nullptr, &gm_nt, &gm_nq,
+                                     &gm_grid));
         qt = queues_for(B, n_rhs, gm_nq, &e);
         if (!qt) return fail(ctx, DD_EDEVICE, std::string("work queues: ") + hipGetErrorString(e));
         gm_ws = get("g_basis", (size_t)gm_grid * (gmres_basis_m(prm.restart) + 2) * vstr * prec_bytes(sp));
@@ -556,6 +559,7 @@ dd_status block_solve_impl(dd_ctx *ctx, const dd_blocks *Bc, const dd_gauge *G, 
             ga.relres = nullptr;
             ga.ext = B->d_ext;
             ga.walk = gmres_walk(ctx, B) ? 1 : 0;
+            ga.clover = cl_a64 ? cl_inv : nullptr;
             {
                 const int pc = ctx->gm_reorth == 0 ? kGmReorthPercent : ctx->gm_reorth;
                 ga.reorth2 = pc < 0 ? -1.0 : (pc / 100.0) * (pc / 100.0);
@@ -797,7 +801,10 @@ dd_status dd_autotune_gmres(dd_ctx *ctx, const dd_blocks *B, const dd_gauge *G, 
     std::vector<Cand> cand;
     for (int nt : {256, 512}) {
         int occ = 0;
-        if (gmres_occupancy(p.inner_prec, p.restart, nt, gmres_walk(ctx, B), &occ) != hipSuccess || occ < 1) continue;
+        if (gmres_occupancy(p.inner_prec, p.restart, nt, gmres_walk(ctx, B), G->d_cla64 != nullptr, &occ) !=
+                hipSuccess ||
+            occ < 1)
+            continue;
         for (int nq : {8, 1}) {
             cand.push_back({nt, nq, occ, 0.0});
             if (occ > 1) cand.push_back({nt, nq, (occ + 1) / 2, 0.0});

@@ -8,8 +8,10 @@
   FP64 defect correction), with the one-kernel Dhat walk (FP32 inner: A_oo^-1 on the intermediate in
   LDS, A_ee^-1 in the epilogue), two x0-walk hops, and the chunked hop kernel: every pair's true
   residual with the oracle's clover operator <= 1e-10, and two blocks' solutions against dense LU.
-* c_sw = 0 gives back the Wilson operator bit for bit; a kappa other than the clover term's and GMRES
-  are refused (the log-determinants with the term are compared in test_gpu_logdet.py).
+* Persistent GMRES with the term (FP64, FP32, BF16-link inner) against the same references.
+* c_sw = 0 gives back the Wilson operator bit for bit; a kappa other than the clover term's, and GMRES
+  without the walking hops, are refused (the log-determinants with the term are compared in
+  test_gpu_logdet.py).
 """
 import numpy as np
 import pytest
@@ -157,7 +159,48 @@ def test_clover_refusals(ctx, field):
     x = _dev(synth.gaussian_complex((1, blk.total_sites, 4, 3), 4405))
     with pytest.raises(dd.DDError):
         ctx.apply_D_block(blk, g, KAPPA + 0.01, "f64", x)
-    with pytest.raises(dd.DDError):
-        ctx.block_solve(blk, g, KAPPA, x, params=dd.solve_params(method=dd.GMRES, inner_prec="f32"))
+    try:  # GMRES takes the clover term only with the walking hops
+        ctx.tune_set(dd.TUNE_HOP_WALK, -1)
+        with pytest.raises(dd.DDError):
+            ctx.block_solve(blk, g, KAPPA, x, params=dd.solve_params(method=dd.GMRES, inner_prec="f32"))
+    finally:
+        ctx.tune_set(dd.TUNE_HOP_WALK, 0)
+    g.close()
+    blk.close()
+
+
+@pytest.mark.parametrize("inner", ["f64", "f32", "bf16"])
+def test_clover_gmres_solves_match_oracle(ctx, field, inner):
+    """Persistent GMRES(16) on 1 - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe (A^-1 inside its walking hops; FP32
+    spinors: the one-pass Dhat with A_oo^-1 on the intermediate), FP64 defect correction: every pair's
+    true residual on the oracle's clover operator <= 1e-10, one block against dense LU."""
+    from paper_2211_06902_amd import dd
+
+    U, A = field
+    boxes = _boxes(True)
+    off = _offsets(boxes)
+    blk = ctx.make_blocks_boxes(L, -1, boxes)
+    g = ctx.load_gauge(blk, _dev(U), "bf16" if inner == "bf16" else "f32").set_clover(_dev(U), KAPPA, CSW)
+    n_rhs = 2
+    b = synth.gaussian_complex((n_rhs, blk.total_sites, 4, 3), 4406)
+    x, info, st = ctx.block_solve(blk, g, KAPPA, _dev(b), params=dd.solve_params(method=dd.GMRES, inner_prec=inner))
+    assert st == dd.DD_OK and np.all(info["true_relres"] <= 1e-10)
+    x = x.cpu().numpy()
+    for k, bx in enumerate(boxes):
+        sl = slice(off[k], off[k + 1])
+        for r in range(n_rhs):
+            assert _relres(U, A, b[r, sl], x[r, sl], bx) <= 1e-10, (k, r)
+    bx = boxes[0]
+    S = int(np.prod(bx[4:8]))
+    M = np.empty((12 * S, 12 * S), dtype=complex)
+    e = np.zeros((S, 4, 3), dtype=complex)
+    ef = e.reshape(-1)
+    for j in range(12 * S):
+        ef[j] = 1.0
+        M[:, j] = clover.dirac_clover_box(L, -1, KAPPA, CSW, U, bx[:4], bx[4:8], e, A=A).reshape(-1)
+        ef[j] = 0.0
+    for r in range(n_rhs):
+        ref = np.linalg.solve(M, b[r, off[0]:off[1]].reshape(-1))
+        assert np.linalg.norm(x[r, off[0]:off[1]].reshape(-1) - ref) <= 1e-8 * np.linalg.norm(ref), r
     g.close()
     blk.close()
