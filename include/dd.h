@@ -220,12 +220,12 @@ dd_status dd_gauge_export(dd_ctx *ctx, const dd_gauge *gauge, dd_prec prec, void
  * FP32 or BF16 links; 72 reals per site and copy).  From then on
  * dd_apply_D_block, dd_apply_D_block_noalloc, dd_block_solve and
  * dd_multiboson_action use this operator and reject another kappa
- * (DD_EINVAL); solves run even-odd BiCGStab on
- * 1 - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe, optionally right-preconditioned by a
- * network (DD_EUNSUPPORTED for GMRES; the hops of blocks the x0-walk cannot take, such as an
- * inactive region, run in the chunked hop kernel); dd_block_logdet takes
- * det A_ee det A_oo det(that operator).  c_sw = 0 removes the term (the
- * Wilson operator).
+ * (DD_EINVAL); solves run on 1 - kappa^2 A_ee^-1 H_eo A_oo^-1 H_oe: BiCGStab,
+ * optionally right-preconditioned by a network (the hops of blocks the
+ * x0-walk cannot take, such as an inactive region, run in the chunked hop
+ * kernel), or persistent GMRES (DD_EUNSUPPORTED for blocks the x0-walk cannot
+ * take); dd_block_logdet takes det A_ee det A_oo det(that operator).  c_sw = 0
+ * removes the term (the Wilson operator).
  * Errors: DD_EINVAL (null argument, non-finite kappa or c_sw), DD_ENOMEM. */
 dd_status dd_gauge_set_clover(dd_ctx *ctx, dd_gauge *gauge, const void *U_dev, double kappa, double csw);
 
