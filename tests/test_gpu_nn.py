@@ -340,7 +340,8 @@ def test_network_preconditioned_bicgstab_with_clover(ctx, toy):
     """BiCGStab right-preconditioned by the network on the clover operator (the network trained on
     Wilson pairs is a perturbation away from the clover inverse, which right preconditioning allows):
     every pair to tolerance with the one-kernel Dhat and with two hop launches, the same solution, and
-    the true residual of two blocks on the oracle's clover operator."""
+    the true residual of two blocks on the oracle's clover operator; flexible GMRES with the network
+    gives the same solution."""
     from oracle import clover, geometry
     from tests import _cfg
 
@@ -371,6 +372,9 @@ def test_network_preconditioned_bicgstab_with_clover(ctx, toy):
         for r in range(3):
             Dx = clover.dirac_clover_box(L, -1, kappa, csw, toy["U"], boxes[k][:4], boxes[k][4:8], out[0][r, sl], A=A)
             assert np.linalg.norm(b[r, sl] - Dx) <= 1e-10 * np.linalg.norm(b[r, sl]), (k, r)
-    with pytest.raises(dd.DDError):  # GMRES takes the Wilson operator only
-        ctx.block_solve(toy["blk"], g, kappa, bd, params=dd.solve_params(method=dd.GMRES, inner_prec="f32"))
+    # flexible GMRES with the network's first directions on the same operator
+    xg, infog, st = ctx.block_solve(toy["blk"], g, kappa, bd,
+                                    params=dd.solve_params(method=dd.GMRES, inner_prec="f32", precond=toy["net"]))
+    assert st == dd.DD_OK and np.all(infog["true_relres"] <= 1e-10)
+    assert _cfg.rel_err(xg.cpu().numpy(), out[0]) <= 1e-9
     g.close()
