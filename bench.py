@@ -286,6 +286,9 @@ C5 = dict(L=(64, 64, 64, 64), kappa=0.1365, eps=0.2, nf=12, N=24, c=0.5, seed_u=
           seed_nn=5104)
 
 
+CLOVER_CSW = 1.6  # c_sw of the clover form timed beside the headline
+
+
 def _mb_inputs(ctx, dd):
     """The 64^4 lattice's blocks, packed links and multi-boson fields, all drawn on the GPU; the
     canonical links are kept on the host for the oracle's sample."""
@@ -368,8 +371,8 @@ def run_c5(args):
     Omega of 8^4 (inner Lambda_0 of 6^4), 12 boson fields (N = 24, c = 0.5), one D_Omega^{-1} xi_k
     solve per field and block (49 152 solves per evaluation).  The headline is the fastest form
     that brings every pair to 1e-10 (FP32 inner BiCGStab, FP64 defect correction); plain FP64
-    solves and FP32 solves right-preconditioned by a network trained on this lattice are
-    measured beside it."""
+    solves, FP32 solves right-preconditioned by a network trained on this lattice, and the same
+    workload with the clover term are measured beside it."""
     import torch
 
     from paper_2211_06902_amd import dd
@@ -436,6 +439,25 @@ def run_c5(args):
                             "mean_inner_iterations_per_pair": float(rn[-1][1]["iters"].mean())}
         say("fp32_nn %s" % forms["fp32_nn"])
         net.close()
+    if inner != "f64" and not args.only_head:
+        # the same workload with the Sheikholeslami-Wohlert term (c_sw = 1.6): another operator, so its
+        # action is not the headline's; the term is removed again afterwards
+        U_dev = torch.from_numpy(U_host).cuda()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        g.set_clover(U_dev, w["kappa"], CLOVER_CSW)
+        torch.cuda.synchronize()
+        t_cl = time.perf_counter() - t1
+        del U_dev
+        torch.cuda.empty_cache()
+        dtc, rcl = timed(dd.solve_params(inner_prec=inner), side, 1)
+        forms["clover"] = {"c_sw": CLOVER_CSW,
+                           "solves_per_s": n_solves * side / dtc if all(r[2] for r in rcl) else 0.0,
+                           "s_per_evaluation": dtc / side, "all_converged": all(r[2] for r in rcl),
+                           "clover_build_s": t_cl, "outer_cycles": int(rcl[-1][1]["outer_cycles"]),
+                           "mean_inner_iterations_per_pair": float(rcl[-1][1]["iters"].mean())}
+        say("clover %s" % forms["clover"])
+        g.set_clover(None, w["kappa"], 0.0)
 
     value = n_solves * args.steps / dt if ok else 0.0
     out = {
