@@ -17,6 +17,10 @@ solves per step), FP32 BiCGStab inside FP64 defect correction.
 8^3 x 12), 12 sources per block, persistent autotuned GMRES(16) with BF16
 links.  --workload c4: the learned preconditioner's training and gain test.
 --workload dlam: y = D_Lambda x alone (the one-pass walk) on the 64^4 blocks, 12 rhs.
+--workload nnapply: the network preconditioner's forward pass alone.
+--workload global: the global pieces of Section 4 on a 48^4 lattice (the rest
+S^r_MB, W_z chi on dPi, the field generation chi = W_u^{-1} eta, the ln W_N
+estimate), 4 fields, kappa 0.12.
 
 The timed steps run the library's default path (inner iterations replayed
 from captured hipGraphs, no kernel timers); one extra step with the kernel
@@ -24,7 +28,7 @@ timers on (HIP events around every launch on the library's stream) gives the
 dominant kernel's algorithmic bandwidth for the roofline object.  Inputs are
 resident in HBM before timing; links are packed once before timing.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-nn] [--workload c5|c2|c3|c4]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-nn] [--workload c5|c2|c3|c4|dlam|nnapply|global]
 """
 from __future__ import annotations
 
@@ -613,6 +617,89 @@ def run_dlam(args):
     ctx.close()
 
 
+def run_global(args):
+    """--workload global: the global pieces of Section 4 on a 48^4 lattice of 8^4 tiles with 4^4
+    active boxes (kappa 0.12, links exp(0.2 i H)), 4 fields at the u_k of N = 8, c = 0.5: the global
+    rest S^r_MB (one batched solve on the inactive region), W_z chi on dPi (the block solves and the
+    inactive-region solve), the field generation chi = W_u^{-1} eta (FP64 BiCGStab over dPi to 1e-10,
+    inner solves to 1e-12) and the ln W_N estimate (order 1, 4 noise vectors).  `value` = generated
+    fields per second; the other timings are in config."""
+    import torch
+
+    import synth
+    from paper_2211_06902_amd import dd
+
+    L, kappa, nf = (48, 48, 48, 48), 0.12, 4
+    ctx = dd.Context(0)
+    blk = ctx.make_blocks(L, -1, [[8] * 6] * 4, inner_d=2)
+    D = ctx.make_inactive(blk)
+    U = synth.gauge_field_device(L, 0.2, 7001)
+    g = ctx.load_gauge(blk, U, "f32")
+    gd = ctx.load_gauge(D, U, "f32")
+    del U
+    torch.cuda.empty_cache()
+    eta = synth.spinor_field_device(nf, 48**4, 7002) / np.sqrt(2)
+    u = dd.mb_roots(2 * nf, 0.5)
+    prm = dd.solve_params(tol=1e-12)
+    steps = max(1, min(args.steps, 2))
+
+    def wall(fn, what):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        print(f"# global: {what} {dt:.3f} s, status {r[-1]}", file=sys.stderr, flush=True)
+        return dt, r
+
+    ctx.mb_global_action(D, gd, kappa, u, eta, params=prm)  # workspaces
+    ctx.mb_apply_W(blk, g, D, gd, kappa, u, eta, params=prm)
+    t_sr, (Sr, _, info_sr, st_sr) = wall(lambda: ctx.mb_global_action(D, gd, kappa, u, eta, params=prm), "S^r")
+    t_w, (_, info_w, st_w) = wall(lambda: ctx.mb_apply_W(blk, g, D, gd, kappa, u, eta, params=prm), "W_z chi")
+    t_gen = 0.0
+    for _ in range(steps):
+        dt, (chi, its, rel, info_g, st_g) = wall(lambda: ctx.mb_generate(blk, g, D, gd, kappa, u, eta, tol=1e-10,
+                                                                           maxit=60, params=prm), "generation")
+        t_gen += dt
+    t_gen /= steps
+    t_rw, (terms, est, info_rw, st_rw) = wall(lambda: ctx.mb_log_reweight(blk, g, D, gd, kappa, 2 * nf, 0.5, 1, eta,
+                                                                             params=prm), "ln W_N")
+    ok = all(st == dd.DD_OK for st in (st_sr, st_w, st_g, st_rw)) and bool(np.all(rel <= 1e-9))
+    # one more W_z chi with the kernel timers on: the kernel classes of its two batched solves
+    ctx.timer_enable(True)
+    ctx.timer_reset()
+    wall(lambda: ctx.mb_apply_W(blk, g, D, gd, kappa, u, eta, params=prm), "W_z chi, kernel timers on")
+    names = {dd.KCLASS_HOP_F64: "k_hop (FP64; the defect-correction residuals)",
+             dd.KCLASS_HOP_F32: "k_hop (FP32; the hop of the inner solves on blocks or the inactive region)",
+             dd.KCLASS_DHAT_F32: "k_dhat_walk (FP32; the one-kernel Dhat of the inner solves)"}
+    per = {k: ctx.timer_read(k) for k in names}
+    ctx.timer_enable(False)
+    top = max(per, key=lambda k: per[k][0])
+    k_ms, k_n, k_bytes = per[top]
+    achieved = k_bytes / (k_ms * 1e-3) / 1e9 if k_ms > 0 else 0.0
+    print(json.dumps({
+        "metric": "multi-boson field generations (chi = W_u^{-1} eta on dPi) per second", "value": nf / t_gen if ok else 0.0,
+        "unit": "fields/s", "n_gpus": 1, "steps": steps, "warmup": 1, "ms_per_step": t_gen * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "global pieces of the multi-boson action on a 48^4 lattice (antiperiodic time, SU(3) "
+                               "links exp(0.2 i H) from seed 7001, kappa 0.12): 1296 tiles of 8^4 with 4^4 active "
+                               "boxes, the inactive region one solve domain; 4 fields (N = 8, c = 0.5), eta Gaussian "
+                               "(seed 7002); FP32 inner solves to 1e-12, generation to 1e-10",
+                   "all_ok": ok, "global_rest_s": t_sr, "S_r": [float(v) for v in Sr],
+                   "apply_W_s": t_w, "generation_s": t_gen, "generation_iterations": [int(v) for v in its],
+                   "generation_true_relres_max": float(rel.max()), "log_reweight_s": t_rw,
+                   "log_reweight_estimate": [est.real, est.imag],
+                   "apply_W_kernel_ms": {"hop_f64": per[dd.KCLASS_HOP_F64][0], "hop_f32": per[dd.KCLASS_HOP_F32][0],
+                                         "dhat_walk_f32": per[dd.KCLASS_DHAT_F32][0]}},
+        "roofline": {"kernel": names[top], "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "launches": k_n,
+                     "ms_per_launch": k_ms / max(k_n, 1), "scope": "one W_z chi"},
+    }), flush=True)
+    for h in (gd, g, D, blk):
+        h.close()
+    ctx.close()
+
+
 def run_solve(args):
     """--workload c2 / c3: one dd_block_solve over all (block, rhs) pairs per step."""
     import torch
@@ -729,7 +816,8 @@ def main():
     ap.add_argument("--no-graph", action="store_true", help="launch every inner iteration from the host")
     ap.add_argument("--inner", default=None, choices=["f32", "bf16", "f64"],
                     help="inner precision (default: FP32; BF16 links for c3)")
-    ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS) + ["c4", "c5", "dlam", "nnapply"])
+    ap.add_argument("--workload", default="c5",
+                    choices=sorted(WORKLOADS) + ["c4", "c5", "dlam", "global", "nnapply"])
     ap.add_argument("--epochs", type=int, default=4, help="c4, c5: training epochs of the network")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (4 times), to calibrate HBM byte counters")
@@ -748,7 +836,8 @@ def main():
         print("bench.py measures one GPU only: the block solves need no communication and the library has "
               "no multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
-    {"c4": run_c4, "c5": run_c5, "dlam": run_dlam, "nnapply": run_nnapply}.get(args.workload, run_solve)(args)
+    {"c4": run_c4, "c5": run_c5, "dlam": run_dlam, "nnapply": run_nnapply, "global": run_global}.get(
+        args.workload, run_solve)(args)
 
 
 if __name__ == "__main__":
