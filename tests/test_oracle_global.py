@@ -206,3 +206,24 @@ def test_apply_w_and_generate_with_clover_match_dense():
     x, its = mb.generate(L, -1, kappa, U, boxes, inner, u, eta, tol=1e-12, csw=csw)
     ref = np.linalg.solve(factor.w_z(pc, u[0]), _vec(pc, eta[0]))
     assert np.linalg.norm(_vec(pc, x[0]) - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_exterior_source_of_one_block_alone():
+    """The hops of chi from dPi into one block are the same whether dPi is built from that block alone
+    or from all blocks (8^4 tiles with 4^4 active boxes on 16^4: every tile's active-box faces lie on
+    the same hyperplanes, and the exterior shell's own perpendicular coordinate is on none of them),
+    for every block.  This is what lets a full-size test compare sampled blocks with the oracle."""
+    L, kappa = (16, 16, 16, 16), 0.12
+    boxes = np.asarray(geometry.tile_boxes(L, [[8, 8]] * 4))
+    inner = np.tile(np.array([2, 2, 2, 2, 4, 4, 4, 4]), (len(boxes), 1))
+    U = synth.gauge_field(L, 0.2, 41)
+    P = geometry.BoxDomains(L, boxes, inner)
+    chi = synth.gaussian_complex((1, P.V, 4, 3), 42)
+    chi[:, ~P.dPi] = 0
+    xa = mb.exterior_source(L, -1, kappa, U, boxes, inner, chi, "all")
+    S = 8**4
+    for a in range(len(boxes)):
+        box, inn = boxes[a:a + 1], inner[a:a + 1]
+        Pa = geometry.BoxDomains(L, box, inn)
+        assert np.array_equal(Pa.ext_a[0] & Pa.dPi, P.ext_a[a] & P.dPi), a
+        assert np.array_equal(mb.exterior_source(L, -1, kappa, U, box, inn, chi, "all"), xa[:, a * S:(a + 1) * S]), a
