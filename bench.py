@@ -521,6 +521,7 @@ def run_c5(args):
 
 PROFILE_C2 = os.path.join(ROOT, "profiles", "k_dhat_walk_f32_c2_32x4_12rhs.md")
 PROFILE_C5 = os.path.join(ROOT, "profiles", "k_dhat_walk_f32_c5_64x4_12fields.md")
+PROFILE_GLOBAL = os.path.join(ROOT, "profiles", "k_hop_f32_inactive_48x4_4fields.md")
 
 
 def cpu_model() -> str:
@@ -692,8 +693,9 @@ def run_global(args):
                    "apply_W_kernel_ms": {"hop_f64": per[dd.KCLASS_HOP_F64][0], "hop_f32": per[dd.KCLASS_HOP_F32][0],
                                          "dhat_walk_f32": per[dd.KCLASS_DHAT_F32][0]}},
         "roofline": {"kernel": names[top], "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "launches": k_n,
-                     "ms_per_launch": k_ms / max(k_n, 1), "scope": "one W_z chi"},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": profiled_traffic(PROFILE_GLOBAL) if top == dd.KCLASS_HOP_F32 else None,
+                     "launches": k_n, "ms_per_launch": k_ms / max(k_n, 1), "scope": "one W_z chi"},
     }), flush=True)
     for h in (gd, g, D, blk):
         h.close()
