@@ -441,8 +441,14 @@ dd_status dd_mb_apply_W(dd_ctx *ctx, const dd_blocks *blocks, const dd_gauge *ga
  * BiCGStab per field over the vectors on dPi, the fields of a group in one
  * batch (each application of W is dd_mb_apply_W's two batched solves), a
  * field stopping when |r| <= tol |eta|; then one more application gives the
- * true residual |eta - W chi| / |eta|.  iters_host, relres_host [n_fields]
- * (may be NULL): iterations and true relative residual per field.
+ * true residual |eta - W chi| / |eta|.  Inside the iteration the inner solves
+ * of W stop at max(params tol, min(1e-6, 0.1 tol / rho)), rho the largest
+ * relative residual |r| / |eta| of the fields still iterating (an inexact
+ * Krylov method tolerates operator errors that grow as its residual falls);
+ * the true residual takes the params tolerance, and fields whose true residual
+ * is above tol restart from their current chi (at most twice, within maxit
+ * iterations in all).  iters_host, relres_host [n_fields] (may be NULL):
+ * iterations and true relative residual per field.
  * params: the inner solves, whose tolerance should be well below tol.
  * DD_ENOCONV when a field's true residual is above 10 tol, it broke down, or
  * an inner solve missed its tolerance (chi is still written). */

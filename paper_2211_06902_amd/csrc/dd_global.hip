@@ -560,6 +560,14 @@ extern "C" dd_status dd_mb_generate(dd_ctx *ctx, const dd_blocks *B, const dd_ga
     for (int k = 0; k < kMaxRhs; k++) hone[2 * k] = 1.0;
     HIPCHECK(ctx, hipMemcpyAsync(ud, u_host, (size_t)n_fields * 2 * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
     HIPCHECK(ctx, hipMemcpyAsync(one, hone.data(), hone.size() * sizeof(double), hipMemcpyHostToDevice, ctx->stream));
+    // Inner tolerance of the W applications inside the iteration: the error a
+    // Krylov method tolerates in its operator grows as its residual falls, so
+    // with relative residual rho the inner solves need only reach
+    // 0.1 tol / rho (at most 1e-6, never below the requested inner tolerance).  The
+    // true residual is taken with the requested one, and a field left above
+    // tol restarts from its current solution (at most twice).
+    const double tol_req = w.prm.tol;
+    auto relaxed = [&](double rho) { return std::max(tol_req, std::min(1e-6, 0.1 * tol / std::max(rho, 1e-300))); };
     bool all_ok = true;
     for (int f0 = 0; f0 < n_fields; f0 += fc) {
         const int nf = std::min(fc, n_fields - f0);
@@ -568,122 +576,144 @@ extern "C" dd_status dd_mb_generate(dd_ctx *ctx, const dd_blocks *B, const dd_ga
         double *x = (double *)chi_global_dev + o;
         const double *zu = ud + 2 * f0;
         const size_t bytes = (size_t)nf * w.V * 24 * sizeof(double);
-        // r = b = eta on dPi; x = 0; rh = r; p = v = 0
+        // r = b = eta on dPi; x = 0
         if ((st = wop_restrict(w, nf, one, eta, r)) != DD_OK) return st;
         HIPCHECK(ctx, hipMemsetAsync(x, 0, bytes, ctx->stream));
-        HIPCHECK(ctx, hipMemcpyAsync(rh, r, bytes, hipMemcpyDeviceToDevice, ctx->stream));
-        HIPCHECK(ctx, hipMemsetAsync(p, 0, bytes, ctx->stream));
-        HIPCHECK(ctx, hipMemsetAsync(v, 0, bytes, ctx->stream));
         std::vector<cplx> d;
         {
             const double *a[1] = {r}, *b[1] = {r};
             if ((st = wop_dots(w, nf, 1, a, b, d)) != DD_OK) return st;
         }
-        std::vector<double> bn(nf);
-        std::vector<cplx> rho(nf, 1.0), alpha(nf, 1.0), omega(nf, 1.0);
+        std::vector<double> bn(nf), rr(nf, 1.0), rel(nf, 0.0);
         std::vector<int> live(nf), its(nf, 0), broke(nf, 0);
         for (int k = 0; k < nf; k++) {
             bn[k] = std::sqrt(d[k].real());
             live[k] = bn[k] > 0;
         }
         std::vector<cplx> cp(3 * nf), cs(3 * nf), cx(3 * nf), cr(3 * nf);
-        for (int it = 1; it <= maxit; it++) {
-            int nlive = 0;
-            for (int k = 0; k < nf; k++) nlive += live[k];
-            if (!nlive) break;
-            {
-                const double *a[1] = {rh}, *b[1] = {r};
-                if ((st = wop_dots(w, nf, 1, a, b, d)) != DD_OK) return st;
-            }
-            for (int k = 0; k < nf; k++) {
-                cplx beta = 0;
-                if (live[k]) {
-                    if (d[k] == 0.0) {
-                        live[k] = 0;
-                        broke[k] = 1;
-                    } else {
-                        beta = (d[k] / rho[k]) * (alpha[k] / omega[k]);
-                        rho[k] = d[k];
+        int it = 0;
+        for (int pass = 0; pass < 3; pass++) {
+            // rh = r; p = v = 0
+            HIPCHECK(ctx, hipMemcpyAsync(rh, r, bytes, hipMemcpyDeviceToDevice, ctx->stream));
+            HIPCHECK(ctx, hipMemsetAsync(p, 0, bytes, ctx->stream));
+            HIPCHECK(ctx, hipMemsetAsync(v, 0, bytes, ctx->stream));
+            std::vector<cplx> rho(nf, 1.0), alpha(nf, 1.0), omega(nf, 1.0);
+            while (it < maxit) {
+                int nlive = 0;
+                double rmax = 0;
+                for (int k = 0; k < nf; k++)
+                    if (live[k]) {
+                        nlive++;
+                        rmax = std::max(rmax, rr[k]);
+                    }
+                if (!nlive) break;
+                it++;
+                w.prm.tol = relaxed(rmax);
+                {
+                    const double *a[1] = {rh}, *b[1] = {r};
+                    if ((st = wop_dots(w, nf, 1, a, b, d)) != DD_OK) return st;
+                }
+                for (int k = 0; k < nf; k++) {
+                    cplx beta = 0;
+                    if (live[k]) {
+                        if (d[k] == 0.0) {
+                            live[k] = 0;
+                            broke[k] = 1;
+                        } else {
+                            beta = (d[k] / rho[k]) * (alpha[k] / omega[k]);
+                            rho[k] = d[k];
+                        }
+                    }
+                    // p = r + beta (p - omega v); a stopped field gets p = 0
+                    cp[3 * k] = live[k] ? 1.0 : 0.0;
+                    cp[3 * k + 1] = live[k] ? beta : 0.0;
+                    cp[3 * k + 2] = live[k] ? -beta * omega[k] : 0.0;
+                }
+                if ((st = wop_lincomb(w, 0, nf, cp, r, p, v, p)) != DD_OK) return st;
+                if ((st = wop_apply(w, nf, zu, p, v)) != DD_OK) return st;
+                {
+                    const double *a[1] = {rh}, *b[1] = {v};
+                    if ((st = wop_dots(w, nf, 1, a, b, d)) != DD_OK) return st;
+                }
+                for (int k = 0; k < nf; k++) {
+                    if (live[k]) {
+                        if (d[k] == 0.0) {
+                            live[k] = 0;
+                            broke[k] = 1;
+                        } else {
+                            alpha[k] = rho[k] / d[k];
+                        }
+                    }
+                    // s = r - alpha v (0 for a stopped field)
+                    cs[3 * k] = live[k] ? 1.0 : 0.0;
+                    cs[3 * k + 1] = live[k] ? -alpha[k] : 0.0;
+                    cs[3 * k + 2] = 0.0;
+                }
+                if ((st = wop_lincomb(w, 1, nf, cs, r, v, nullptr, s)) != DD_OK) return st;
+                if ((st = wop_apply(w, nf, zu, s, t)) != DD_OK) return st;
+                {
+                    const double *a[2] = {t, t}, *b[2] = {s, t};
+                    if ((st = wop_dots(w, nf, 2, a, b, d)) != DD_OK) return st;
+                }
+                for (int k = 0; k < nf; k++) {
+                    const cplx ts = d[2 * k], tt = d[2 * k + 1];
+                    cplx om = 0;
+                    if (live[k] && tt.real() > 0) om = ts / tt;
+                    // x += alpha p + omega s;  r = s - omega t  (stopped fields keep both)
+                    cx[3 * k] = 1.0;
+                    cx[3 * k + 1] = live[k] ? alpha[k] : 0.0;
+                    cx[3 * k + 2] = live[k] ? om : 0.0;
+                    cr[3 * k] = live[k] ? 1.0 : 0.0;
+                    cr[3 * k + 1] = live[k] ? -om : 0.0;
+                    cr[3 * k + 2] = live[k] ? 0.0 : 1.0;
+                    if (live[k]) {
+                        if (om == 0.0 && tt.real() > 0) broke[k] = 1;
+                        omega[k] = om;
                     }
                 }
-                // p = r + beta (p - omega v); a stopped field gets p = 0
-                cp[3 * k] = live[k] ? 1.0 : 0.0;
-                cp[3 * k + 1] = live[k] ? beta : 0.0;
-                cp[3 * k + 2] = live[k] ? -beta * omega[k] : 0.0;
-            }
-            if ((st = wop_lincomb(w, 0, nf, cp, r, p, v, p)) != DD_OK) return st;
-            if ((st = wop_apply(w, nf, zu, p, v)) != DD_OK) return st;
-            {
-                const double *a[1] = {rh}, *b[1] = {v};
-                if ((st = wop_dots(w, nf, 1, a, b, d)) != DD_OK) return st;
-            }
-            for (int k = 0; k < nf; k++) {
-                if (live[k]) {
-                    if (d[k] == 0.0) {
-                        live[k] = 0;
-                        broke[k] = 1;
-                    } else {
-                        alpha[k] = rho[k] / d[k];
-                    }
+                if ((st = wop_lincomb(w, 2, nf, cx, x, p, s, x)) != DD_OK) return st;
+                if ((st = wop_lincomb(w, 3, nf, cr, s, t, r, r)) != DD_OK) return st;
+                {
+                    const double *a[1] = {r}, *b[1] = {r};
+                    if ((st = wop_dots(w, nf, 1, a, b, d)) != DD_OK) return st;
                 }
-                // s = r - alpha v (0 for a stopped field)
-                cs[3 * k] = live[k] ? 1.0 : 0.0;
-                cs[3 * k + 1] = live[k] ? -alpha[k] : 0.0;
-                cs[3 * k + 2] = 0.0;
-            }
-            if ((st = wop_lincomb(w, 1, nf, cs, r, v, nullptr, s)) != DD_OK) return st;
-            if ((st = wop_apply(w, nf, zu, s, t)) != DD_OK) return st;
-            {
-                const double *a[2] = {t, t}, *b[2] = {s, t};
-                if ((st = wop_dots(w, nf, 2, a, b, d)) != DD_OK) return st;
-            }
-            for (int k = 0; k < nf; k++) {
-                const cplx ts = d[2 * k], tt = d[2 * k + 1];
-                cplx om = 0;
-                if (live[k] && tt.real() > 0) om = ts / tt;
-                // x += alpha p + omega s;  r = s - omega t  (stopped fields keep both)
-                cx[3 * k] = 1.0;
-                cx[3 * k + 1] = live[k] ? alpha[k] : 0.0;
-                cx[3 * k + 2] = live[k] ? om : 0.0;
-                cr[3 * k] = live[k] ? 1.0 : 0.0;
-                cr[3 * k + 1] = live[k] ? -om : 0.0;
-                cr[3 * k + 2] = live[k] ? 0.0 : 1.0;
-                if (live[k]) {
-                    if (om == 0.0 && tt.real() > 0) broke[k] = 1;
-                    omega[k] = om;
+                for (int k = 0; k < nf; k++) {
+                    if (!live[k]) continue;
+                    its[k] = it;
+                    rr[k] = std::sqrt(std::max(d[k].real(), 0.0)) / bn[k];
+                    if (rr[k] <= tol || omega[k] == 0.0) live[k] = 0;
                 }
             }
-            if ((st = wop_lincomb(w, 2, nf, cx, x, p, s, x)) != DD_OK) return st;
-            if ((st = wop_lincomb(w, 3, nf, cr, s, t, r, r)) != DD_OK) return st;
+            // true residual eta - W x on dPi, with the requested inner tolerance
+            w.prm.tol = tol_req;
+            if ((st = wop_restrict(w, nf, one, eta, s)) != DD_OK) return st;
+            if ((st = wop_apply(w, nf, zu, x, t)) != DD_OK) return st;
+            std::vector<cplx> c1(3 * nf);
+            for (int k = 0; k < nf; k++) {
+                c1[3 * k] = 1.0;
+                c1[3 * k + 1] = -1.0;
+                c1[3 * k + 2] = 0.0;
+            }
+            if ((st = wop_lincomb(w, 4, nf, c1, s, t, nullptr, s)) != DD_OK) return st;
             {
-                const double *a[1] = {r}, *b[1] = {r};
+                const double *a[1] = {s}, *b[1] = {s};
                 if ((st = wop_dots(w, nf, 1, a, b, d)) != DD_OK) return st;
             }
+            bool again = false;
             for (int k = 0; k < nf; k++) {
-                if (!live[k]) continue;
-                its[k] = it;
-                if (std::sqrt(std::max(d[k].real(), 0.0)) <= tol * bn[k] || omega[k] == 0.0) live[k] = 0;
+                rel[k] = bn[k] > 0 ? std::sqrt(std::max(d[k].real(), 0.0)) / bn[k] : 0.0;
+                live[k] = bn[k] > 0 && !broke[k] && rel[k] > tol;
+                rr[k] = rel[k];
+                again = again || live[k];
             }
-        }
-        // true residual |eta - W x| / |eta| on dPi
-        if ((st = wop_restrict(w, nf, one, eta, s)) != DD_OK) return st;
-        if ((st = wop_apply(w, nf, zu, x, t)) != DD_OK) return st;
-        std::vector<cplx> c1(3 * nf);
-        for (int k = 0; k < nf; k++) {
-            c1[3 * k] = 1.0;
-            c1[3 * k + 1] = -1.0;
-            c1[3 * k + 2] = 0.0;
-        }
-        if ((st = wop_lincomb(w, 4, nf, c1, s, t, nullptr, s)) != DD_OK) return st;
-        {
-            const double *a[1] = {s}, *b[1] = {s};
-            if ((st = wop_dots(w, nf, 1, a, b, d)) != DD_OK) return st;
+            if (!again || it >= maxit) break;
+            // restart the fields above tol from the true residual
+            HIPCHECK(ctx, hipMemcpyAsync(r, s, bytes, hipMemcpyDeviceToDevice, ctx->stream));
         }
         for (int k = 0; k < nf; k++) {
-            const double rel = bn[k] > 0 ? std::sqrt(std::max(d[k].real(), 0.0)) / bn[k] : 0.0;
             if (iters_host) iters_host[f0 + k] = its[k];
-            if (relres_host) relres_host[f0 + k] = rel;
-            if (!(rel <= 10 * tol) || broke[k]) all_ok = false;
+            if (relres_host) relres_host[f0 + k] = rel[k];
+            if (!(rel[k] <= 10 * tol) || broke[k]) all_ok = false;
         }
     }
     HIPCHECK(ctx, hipStreamSynchronize(ctx->stream));
