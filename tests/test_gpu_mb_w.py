@@ -7,7 +7,8 @@ dense W_z in test_oracle_global.py).
   6 x 6 x 6 x 4, at three z including 0 (the off-diagonal part W_1 - 1); zero off dPi; the field
   grouping does not change the values beyond 1e-12.
 * Field generation: the oracle's W applied to the library's chi gives back eta within 1e-9 (the
-  solution is unique, so this pins chi to within cond(W) 1e-9); zero off dPi.
+  solution is unique, so this pins chi to within cond(W) 1e-9); zero off dPi.  With inner solves too
+  loose for the requested tolerance it restarts, then reports DD_ENOCONV with the true residual.
 * Reweighting estimate: per noise vector, the terms -sum_m eta^+ R^m eta / m equal the oracle's (same
   noise, Chebyshev recurrence of R_{N+1}) within 1e-8 of the largest.
 * Generation and the estimate give the same values when the fields or vectors are split into groups.
@@ -126,6 +127,30 @@ def test_generate_solves_the_oracle_equation(ctx, case):
     chi2 = chi2.cpu().numpy()
     for k in live:
         assert np.linalg.norm(chi2[k] - chi[k]) <= 1e-8 * np.linalg.norm(chi[k]), k
+    _close(gd, g, D, blk)
+
+
+def test_generation_restarts_then_reports(ctx):
+    """Inner solves stopped at 1e-5 cannot give a true residual of 1e-10: the generation restarts from
+    its chi (more iterations than a converging run), reports the true residual per field and returns
+    DD_ENOCONV with chi written, a chi that still agrees with the converged one to the inner level."""
+    from paper_2211_06902_amd import dd
+
+    L, U, blk, D, g, gd, boxes, inner = _setup(ctx, "tiles_inner", 6651)
+    V = int(np.prod(L))
+    u = roots.mb_roots(4, 0.5)[:2]
+    eta = synth.gaussian_complex((2, V, 4, 3), 6652) / np.sqrt(2)
+    chi1, its1, rel1, _, st1 = ctx.mb_generate(blk, g, D, gd, KAPPA, u, _dev(eta), tol=1e-10,
+                                               params=dd.solve_params(tol=1e-12))
+    assert st1 == dd.DD_OK and np.all(rel1 <= 1e-9)
+    chi, its, rel, info, st = ctx.mb_generate(blk, g, D, gd, KAPPA, u, _dev(eta), tol=1e-10, maxit=100,
+                                              params=dd.solve_params(tol=1e-5))
+    assert st == dd.DD_ENOCONV, (its, rel)
+    assert np.all(its > its1) and np.all(its <= 100), (its, its1)
+    assert np.all(rel > 1e-10) and np.all(rel < 1e-3), rel
+    chi, chi1 = chi.cpu().numpy(), chi1.cpu().numpy()
+    for k in range(2):
+        assert np.linalg.norm(chi[k] - chi1[k]) <= 1e-3 * np.linalg.norm(chi1[k]), k
     _close(gd, g, D, blk)
 
 
