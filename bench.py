@@ -370,6 +370,26 @@ def mb_cpu_baseline(U_host, xi):
                       "%d failed)" % (npairs, len(set(b for b, _ in pick)), dt, fails)}
 
 
+def solve_byte_model(blk, info, inner, seconds):
+    """The evaluation against the byte model of eo-BiCGStab: per pair and iteration two Dhat, each
+    two eo hops (S 24 s_f spinor bytes, every link inside the block once at 18 s_l, the links shared
+    by the pairs of one launch) and an axpy (S 12 s_f), plus 14 half-field passes of vector updates
+    (S 12 s_f each), i.e. S 288 s_f + 72 L_in s_l / (pairs per launch) bytes per pair and iteration,
+    summed over every pair's iterations; the FP64 defect-correction passes are left out.  The
+    library fuses several of the 14 passes into the Dhat walks, so the effective bandwidth can
+    exceed the stencil kernel's own."""
+    sf = 8.0 if inner == "f64" else 4.0
+    sl = {"f64": 8.0, "f32": 4.0, "bf16": 2.0}[inner]
+    S = blk.total_sites / blk.n_blocks
+    L_in = blk.inner_links / blk.n_blocks
+    pair_its = float(np.sum(info["iters"]))
+    per = S * 288.0 * sf + 72.0 * L_in * sl / max(int(info["rhs_per_solve"]), 1)
+    total = pair_its * per
+    eff = total / seconds / 1e9
+    return {"pair_iterations": pair_its, "bytes_per_pair_iteration": per, "bytes_per_evaluation": total,
+            "t_min_s": total / (HBM_PEAK_GBS * 1e9), "effective_GBs": eff, "frac_of_peak": eff / HBM_PEAK_GBS}
+
+
 def run_c5(args):
     """The default workload: the block-local multi-boson action of the 64^4 lattice, 4096 blocks
     Omega of 8^4 (inner Lambda_0 of 6^4), 12 boson fields (N = 24, c = 0.5), one D_Omega^{-1} xi_k
@@ -509,6 +529,7 @@ def run_c5(args):
             "timing": "HIP events around each launch on the library stream, in one extra evaluation",
         },
     }
+    out["config"]["solve_byte_model"] = solve_byte_model(blk, res[-1][1], inner, dt / args.steps)
     if "fp64" in forms and forms["fp64"]["solves_per_s"] > 0:
         out["config"]["speedup_over_fp64"] = value / forms["fp64"]["solves_per_s"]
     if not args.no_cpu:
