@@ -364,10 +364,23 @@ def mb_cpu_baseline(U_host, xi):
     _, iters, rel, fails = wilson.solve_many(w["L"], -1, w["kappa"], U_host, np.asarray(boxes), bh, tol=TOL,
                                              nthreads=nthr)
     dt = time.perf_counter() - t0
+    # context: the oracle's D_Lambda on one 8^4 block (one thread, FP64, one rhs) for about a second,
+    # with the algorithmic bytes S 48 s_f + L_in 18 s_l per application
+    o, e = np.asarray(boxes[0][:4]), np.asarray(boxes[0][4:])
+    psi = bh[0, :S]
+    napp, t1 = 0, time.perf_counter()
+    while napp == 0 or time.perf_counter() - t1 < 1.0:
+        wilson.dirac_box(w["L"], -1, w["kappa"], U_host, o, e, psi)
+        napp += 1
+    dt1 = time.perf_counter() - t1
+    dslash = napp * (S * 48 * 8 + 4 * 8**3 * 7 * 18 * 8) / dt1 / 1e9
     return {"value": npairs / dt, "unit": "solves/s", "cores": nthr, "cpu_model": cpu_model(), "kind": "oracle",
             "sample": "%d (block, field) pairs of the 64^4 multi-boson workload (8 per thread; xi sources of "
                       "%d blocks), FP64 eo-BiCGStab with FP64 defect correction to 1e-10 (%.1f s wall, "
-                      "%d failed)" % (npairs, len(set(b for b, _ in pick)), dt, fails)}
+                      "%d failed)" % (npairs, len(set(b for b, _ in pick)), dt, fails),
+            "dslash_GBs_one_thread": dslash,
+            "dslash_sample": "%d applications of D_Lambda (FP64, one rhs) on one 8^4 block in %.2f s, one thread"
+                             % (napp, dt1)}
 
 
 def solve_byte_model(blk, info, inner, seconds):
