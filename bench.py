@@ -21,6 +21,8 @@ links.  --workload c4: the learned preconditioner's training and gain test.
 --workload global: the global pieces of Section 4 on a 48^4 lattice (the rest
 S^r_MB, W_z chi on dPi, the field generation chi = W_u^{-1} eta, the ln W_N
 estimate), 4 fields, kappa 0.12.
+--workload exterior: the exact sources xi from chi (exterior hops) on the 64^4 blocks.
+--workload logdet: per-block log-determinants of 4096 blocks of 4^4.
 
 The timed steps run the library's default path (inner iterations replayed
 from captured hipGraphs, no kernel timers); one extra step with the kernel
@@ -28,7 +30,7 @@ timers on (HIP events around every launch on the library's stream) gives the
 dominant kernel's algorithmic bandwidth for the roofline object.  Inputs are
 resident in HBM before timing; links are packed once before timing.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-nn] [--workload c5|c2|c3|c4|dlam|nnapply|global]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-nn] [--workload c5|c2|c3|c4|dlam|nnapply|global|exterior|logdet]
 """
 from __future__ import annotations
 
@@ -736,6 +738,101 @@ def run_global(args):
     ctx.close()
 
 
+def run_exterior(args):
+    """--workload exterior: the exact source of eq. (localMB) from chi alone, xi^a += the hops of chi
+    from the sites of dPi outside each block into it (dd_mb_exterior_source, both parts), for the
+    64^4 lattice's 4096 blocks of 8^4 (inner 6^4) and 12 fields, `--steps` timed calls after one.
+    Algorithmic bytes per call: every exterior hop reads the field's neighbour spinor (24 doubles
+    per field) and its link once (18 doubles), every receiving site reads and writes its xi entry
+    (2 x 24 doubles per field)."""
+    import torch
+
+    import synth
+    from paper_2211_06902_amd import dd
+
+    w = C5
+    ctx = dd.Context(0)
+    blk = ctx.make_blocks(w["L"], -1, [[8] * 8] * 4, inner_d=1)
+    U = synth.gauge_field_device(w["L"], w["eps"], w["seed_u"])
+    g = ctx.load_gauge(blk, U, "f32")
+    del U
+    torch.cuda.empty_cache()
+    chi = synth.spinor_field_device(w["nf"], 64**4, w["seed_chi"])
+    xi = torch.zeros((w["nf"], blk.total_sites, 4, 3), dtype=torch.complex128, device="cuda")
+    b, site, _, _ = blk.exterior()
+    n_hops = int(b.size)
+    n_recv = int(np.unique(b.astype(np.int64) * blk.total_sites + site).size)
+    alg = n_hops * (24 * 8 * w["nf"] + 18 * 8) + n_recv * 2 * 24 * 8 * w["nf"]
+    ctx.mb_exterior_source(blk, g, w["kappa"], chi, xi)
+    torch.cuda.synchronize()
+    steps = max(1, args.steps)
+    t = time.perf_counter()
+    for _ in range(steps):
+        ctx.mb_exterior_source(blk, g, w["kappa"], chi, xi)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / steps
+    achieved = alg / dt / 1e9
+    print(json.dumps({
+        "metric": "exact multi-boson sources xi from chi (dPi exterior hops into every block) per second",
+        "value": 1.0 / dt, "unit": "sources/s (all 4096 blocks x 12 fields)", "n_gpus": 1, "steps": steps,
+        "warmup": 1, "ms_per_step": dt * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "64^4 lattice (links exp(0.2 i H), seed 5101), 4096 blocks of 8^4 with inner 6^4, "
+                               "12 Gaussian fields chi (seed 5102) on the whole lattice (read on dPi)",
+                   "exterior_hops": n_hops, "receiving_sites": n_recv},
+        "roofline": {"kernel": "k_mb_exterior", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "alg_bytes_per_launch": alg, "timing": "wall time of the synchronising call"},
+    }), flush=True)
+    g.close()
+    blk.close()
+    ctx.close()
+
+
+def run_logdet(args):
+    """--workload logdet: per-block ln det D_Lambda (dd_block_logdet, FP64) of 4096 blocks of 4^4 on a
+    32^4 lattice (the largest blocks the dense route takes have 12 h <= 6144; 4^4 gives 12 h = 1536),
+    `--steps` timed calls after one.  The work is dominated by the batched complex LU: (8/3) n^3 real
+    flops per block with n = 12 h, set against the FP64 peak."""
+    import torch
+
+    import synth
+    from paper_2211_06902_amd import dd
+
+    L, kappa = (32, 32, 32, 32), 0.1365
+    ctx = dd.Context(0)
+    blk = ctx.make_blocks(L, -1, [[4] * 8] * 4)
+    U = synth.gauge_field_device(L, 0.2, 6101)
+    g = ctx.load_gauge(blk, U, "f32")
+    del U
+    ld, tot = ctx.block_logdet(blk, g, kappa)
+    torch.cuda.synchronize()
+    steps = max(1, min(args.steps, 3))
+    t = time.perf_counter()
+    for _ in range(steps):
+        ld2, tot2 = ctx.block_logdet(blk, g, kappa)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t) / steps
+    n = 12 * (blk.total_sites // blk.n_blocks) // 2
+    flops = blk.n_blocks * (8.0 / 3.0) * n**3
+    achieved = flops / dt / 1e12
+    print(json.dumps({
+        "metric": "per-block log-determinants ln det D_Lambda per second", "value": blk.n_blocks / dt,
+        "unit": "blocks/s", "n_gpus": 1, "steps": steps, "warmup": 1, "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "32^4 lattice (links exp(0.2 i H), seed 6101, kappa 0.1365), 4096 blocks of 4^4; "
+                               "det D_Lambda = det(1 - kappa^2 H_eo H_oe) assembled densely (n = 1536) and "
+                               "factorised by batched LU",
+                   "total_logdet": [tot.real, tot.imag], "repeatable": bool(np.array_equal(ld, ld2))},
+        "roofline": {"kernel": "dd_block_logdet (assembly and batched LU)", "bound": "mfma", "achieved": achieved,
+                     "peak": 78.6, "unit": "TFLOP/s", "frac": achieved / 78.6, "traffic": None,
+                     "alg_flops_per_launch": flops, "timing": "wall time of the synchronising call"},
+    }), flush=True)
+    g.close()
+    blk.close()
+    ctx.close()
+
+
 def run_solve(args):
     """--workload c2 / c3: one dd_block_solve over all (block, rhs) pairs per step."""
     import torch
@@ -853,7 +950,7 @@ def main():
     ap.add_argument("--inner", default=None, choices=["f32", "bf16", "f64"],
                     help="inner precision (default: FP32; BF16 links for c3)")
     ap.add_argument("--workload", default="c5",
-                    choices=sorted(WORKLOADS) + ["c4", "c5", "dlam", "global", "nnapply"])
+                    choices=sorted(WORKLOADS) + ["c4", "c5", "dlam", "exterior", "global", "logdet", "nnapply"])
     ap.add_argument("--epochs", type=int, default=4, help="c4, c5: training epochs of the network")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (4 times), to calibrate HBM byte counters")
@@ -872,8 +969,8 @@ def main():
         print("bench.py measures one GPU only: the block solves need no communication and the library has "
               "no multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
-    {"c4": run_c4, "c5": run_c5, "dlam": run_dlam, "nnapply": run_nnapply, "global": run_global}.get(
-        args.workload, run_solve)(args)
+    {"c4": run_c4, "c5": run_c5, "dlam": run_dlam, "nnapply": run_nnapply, "global": run_global,
+     "exterior": run_exterior, "logdet": run_logdet}.get(args.workload, run_solve)(args)
 
 
 if __name__ == "__main__":
