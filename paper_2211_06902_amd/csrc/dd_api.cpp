@@ -201,6 +201,11 @@ hipError_t run_hop(dd_ctx *ctx, const dd_blocks *B, const BlkArgs &ba, const Hop
         wa.ntiles = wt.ntiles;
         wa.nseg = nseg;
         wa.per = nseg * (ba.n_rhs / ba.g);
+        if (ha.b_hi > ha.b_lo) {  // tiles are block-major: the range's tiles are contiguous
+            if (ha.b_lo < 0 || ha.b_hi > B->nb) return hipErrorInvalidValue;
+            wa.tile0 = ha.b_lo * wa.per;
+            wa.ntiles = (ha.b_hi - ha.b_lo) * wa.per;
+        }
         return launch_hop_walk(ba, wa, ha, prec, ctx->stream);
     }
     return launch_hop(ba, ha, prec, ctx->stream);

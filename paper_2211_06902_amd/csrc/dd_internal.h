@@ -235,6 +235,7 @@ struct WalkArgs {
     int ntiles;
     int nseg;
     int per;
+    int tile0 = 0;  // first tile of the launch (the hop walk may cover a range of blocks)
 };
 
 enum DotMode { kDotNone = 0, kDotAuxOut = 1, kDotOutSelfOutOut = 2, kDotOutOut = 3, kDotOutAuxOutOut = 4 };
@@ -270,6 +271,9 @@ struct HopArgs {
     // at an output site is multiplied by that site's matrix before the
     // epilogue combines it with self and add
     const void *clover;
+    // blocks [b_lo, b_hi) only, when b_hi > b_lo (run_hop's x0-walk launches
+    // just their tiles; the chunked hop does every block): others untouched
+    int b_lo, b_hi;
 };
 
 // Vector updates of BiCGStab done by the first hop of Dhat as it stages its

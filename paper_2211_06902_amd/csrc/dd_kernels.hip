@@ -381,7 +381,7 @@ k_hop_walk(BlkArgs ba, WalkArgs wa, HopArgs ha)
     static_assert(!CL || G == 1, "clover hops take one rhs per thread");
     __shared__ SP stage[24 * kTile * G];
     __shared__ double red[G][kTile];
-    const int tile = uni(xcd_tile(blockIdx.x, wa.ntiles));
+    const int tile = uni(wa.tile0 + xcd_tile(blockIdx.x, wa.ntiles));
     const int b = tile / wa.per;
     const int nr = ba.n_rhs, ng = nr / G;
     const int rel = tile - b * wa.per;
@@ -515,7 +515,10 @@ hipError_t launch_hop_walk(const BlkArgs &ba, const WalkArgs &wa, const HopArgs 
 {
     if (wa.ntiles <= 0) return hipSuccess;
     if (wa.nseg < 1 || ha.dot_mode < kDotNone || ha.dot_mode > kDotOutAuxOutOut) return hipErrorInvalidValue;
-    if (wa.per != wa.nseg * (ba.n_rhs / ba.g) || wa.ntiles != ba.nb * wa.per) return hipErrorInvalidValue;
+    // the launch covers whole blocks of the tile grid: [tile0, tile0 + ntiles) within nb * per
+    if (wa.per != wa.nseg * (ba.n_rhs / ba.g) || wa.tile0 < 0 || wa.tile0 % wa.per || wa.ntiles % wa.per ||
+        (int64_t)wa.tile0 + wa.ntiles > (int64_t)ba.nb * wa.per)
+        return hipErrorInvalidValue;
     if (ha.pre < kPreNone || ha.pre > kPreS) return hipErrorInvalidValue;
     if (ha.clover && ba.g != 1) return hipErrorInvalidValue;  // clover hops: one rhs per thread
     // the staging updates: no fused dots; kPreP rewrites its input in place,

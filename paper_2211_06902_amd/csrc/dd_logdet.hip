@@ -46,16 +46,6 @@ __global__ void __launch_bounds__(256) k_unit_batch(double *e, const int64_t *so
     e[(soff[b] >> 1) * 24 * kCols + t] = v;
 }
 
-// Pair flags of the hop walks: rhs r of block b is live when b0 <= b < b0 + nc,
-// so that the walks skip the blocks of other groups.
-__global__ void __launch_bounds__(256) k_group_mask(int32_t *act, int nb, int b0, int nc)
-{
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= (int64_t)kCols * nb) return;
-    const int b = (int)(t % nb);
-    act[t] = b >= b0 && b < b0 + nc;
-}
-
 // A[b][j][i] (column-major n x n, complex) = (Dhat e_j)_i for the batch's columns j < n.
 __global__ void __launch_bounds__(256) k_gather_cols(const double *out, const int64_t *soff, int hb, int j0, int n,
                                                       double2 *A, int b0)
@@ -136,8 +126,7 @@ extern "C" dd_status dd_block_logdet(dd_ctx *ctx, const dd_blocks *B, const dd_g
     double2 *A = ld ? (double2 *)workspace(ctx, "ld_A", mat * chunk, &e) : nullptr;
     int32_t *ipiv = A ? (int32_t *)workspace(ctx, "ld_piv", (size_t)chunk * n * sizeof(int32_t), &e) : nullptr;
     int32_t *info = ipiv ? (int32_t *)workspace(ctx, "ld_info", (size_t)chunk * sizeof(int32_t), &e) : nullptr;
-    int32_t *act = info ? (int32_t *)workspace(ctx, "ld_act", (size_t)kCols * B->nb * sizeof(int32_t), &e) : nullptr;
-    if (!act) return fail(ctx, DD_ENOMEM, std::string("logdet workspace: ") + hipGetErrorString(e));
+    if (!info) return fail(ctx, DD_ENOMEM, std::string("logdet workspace: ") + hipGetErrorString(e));
     if (!ctx->blas) {
         if (rocblas_create_handle(reinterpret_cast<rocblas_handle *>(&ctx->blas)) != rocblas_status_success)
             return fail(ctx, DD_EDEVICE, "rocblas_create_handle failed");
@@ -151,11 +140,8 @@ extern "C" dd_status dd_block_logdet(dd_ctx *ctx, const dd_blocks *B, const dd_g
     ctx->timing = false;
     for (int b0 = 0; b0 < B->nb && e == hipSuccess; b0 += chunk) {
         const int nc = std::min(chunk, B->nb - b0);
-        // the hop walks do the blocks of this group only (the chunked hop,
-        // which has no pair flags, does them all; the others are not read)
-        hipLaunchKernelGGL(k_group_mask, dim3((unsigned)(((int64_t)kCols * B->nb + 255) / 256)), dim3(256), 0, st, act,
-                           B->nb, b0, nc);
-        if ((e = hipGetLastError()) != hipSuccess) break;
+        // the hop walks launch this group's blocks only (the chunked hop does
+        // every block; the others' results are not read)
         for (int j0 = 0; j0 < n; j0 += kCols) {
             const int64_t per = (int64_t)kCols * 24 * hb;
             hipLaunchKernelGGL(k_unit_batch, dim3((unsigned)((per + 255) / 256), nc), dim3(256), 0, st, fe,
@@ -165,13 +151,15 @@ extern "C" dd_status dd_block_logdet(dd_ctx *ctx, const dd_blocks *B, const dd_g
             // each hop result is multiplied by A^-1 of its output site
             HopArgs h1 = hop_args(fo, fe, G->d_u64, 1, 1.0);
             h1.clover = cl ? G->d_cli64 : nullptr;
-            h1.skip_act = act;
+            h1.b_lo = b0;
+            h1.b_hi = b0 + nc;
             if ((e = run_hop(ctx, B, ba, h1, DD_F64)) != hipSuccess) break;
             HopArgs h2 = hop_args(fy, fo, G->d_u64, 0, -k2);
             h2.self = fe;
             h2.c_self = 1.0;
             h2.clover = cl ? G->d_cli64 : nullptr;
-            h2.skip_act = act;
+            h2.b_lo = b0;
+            h2.b_hi = b0 + nc;
             if ((e = run_hop(ctx, B, ba, h2, DD_F64)) != hipSuccess) break;
             const int64_t cols = (int64_t)kCols * n;
             hipLaunchKernelGGL(k_gather_cols, dim3((unsigned)((cols + 255) / 256), nc), dim3(256), 0, st, fy,

@@ -170,3 +170,22 @@ def test_logdet_clover_framed_blocks_and_frames(ctx):
     gf.close()
     fr.close()
     blk.close()
+
+
+def test_logdet_in_two_groups_of_blocks(ctx):
+    """256 blocks of 4^4 on 16^4 (n = 12 h = 1536): their dense matrices exceed 8 GiB, so the library
+    assembles and factorises them in two groups (227 + 29 blocks), each group's hops launched over its
+    own blocks only.  Sampled blocks on both sides of the group boundary and the last one against the
+    oracle's dense LU."""
+    L, kappa = (16, 16, 16, 16), 0.1365
+    U = synth.gauge_field(L, 0.2, 6171)
+    blk = ctx.make_blocks(L, -1, [[4] * 4] * 4)
+    g = ctx.load_gauge(blk, _dev(U), "f32")
+    ld, tot = ctx.block_logdet(blk, g, kappa)
+    assert ld.shape == (256,) and np.all(np.isfinite(ld))
+    boxes = blk.tables()[0][:, :8]
+    for b in (0, 226, 227, 255):
+        ref = dense.logdet(dense.dense_dirac_box(L, -1, kappa, U, boxes[b, :4], boxes[b, 4:8]))
+        assert _close(ld[b], ref), (b, ld[b], ref)
+    g.close()
+    blk.close()
