@@ -1675,9 +1675,11 @@ __global__ void __launch_bounds__(256) k_mb_exterior(const int32_t *gb, const in
                                                       const int64_t *soff, const double *chi, double *xi, int ng, int nf,
                                                       int64_t V, int64_t total, double kappa, int parts)
 {
+    // one thread per (receiving site, field), the fields of a site in adjacent
+    // lanes: their link loads are one address, served once per wavefront
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= (int64_t)ng * nf) return;
-    const int g = (int)(t % ng), f = (int)(t / ng);
+    const int g = (int)(t / nf), f = (int)(t % nf);
     double acc[1][24];
 #pragma unroll
     for (int c = 0; c < 24; c++) acc[0][c] = 0;
