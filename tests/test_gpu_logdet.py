@@ -1,7 +1,8 @@
 """GPU parity of the per-block log-determinants (dd_block_logdet: FP64 eo-reduced dense
 assembly, batched LU) against the oracle's dense LU of the principal sub-matrix of D
 (oracle.dense): ln det D_Lambda on tiles, ln det D_{Omega_0^a} on paper-mode framed blocks and
-ln det D_{Phi_1^a} on their frames (the block factors of eq. detD).
+ln det D_{Phi_1^a} on their frames (the block factors of eq. detD); with the clover term; and 256
+blocks whose dense matrices the library assembles and factorises in two groups.
 
 ln|det| and the phase are compared to 1e-9 (absolute; |ln det| is of order the dimension)."""
 import numpy as np
